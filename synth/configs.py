@@ -1,0 +1,37 @@
+"""Workload definitions (sizes and seeds only).
+
+c1/c2/c3 are the plain method at three sizes; c4 is the batching form over the
+c3 shapes; c5 is the learned-sigmoid form over the c3 shapes.  Every workload
+uses RNS primes of the listed bit sizes, dnum-digit key switching, scale
+2^log2_scale and the row-major m x g block layout of the paper (section 2.2).
+"""
+import copy
+
+_BASE = {
+    "c1": dict(
+        name="c1-tiny", log2N=12, q_bits=[50, 40, 40, 40, 40], n_p=2, p_bits=60, dnum=3, log2_scale=40,
+        m=256, g=8, n_train=128, n_features=7, n_valid=256, seed=1, iters=3, batch_rows=None,
+        sigmoid_degree=3, target_pos=None,
+    ),
+    "c2": dict(
+        name="c2-mid", log2N=15, q_bits=[40] * 14, n_p=5, p_bits=60, dnum=3, log2_scale=40,
+        m=256, g=64, n_train=16384, n_features=63, n_valid=32768, seed=2, iters=10, batch_rows=1024,
+        sigmoid_degree=3, target_pos=None,
+    ),
+    "c3": dict(
+        name="c3-paper-scale", log2N=16, q_bits=[60] + [40] * 23, n_p=6, p_bits=60, dnum=4, log2_scale=40,
+        m=128, g=256, n_train=422108, n_features=200, n_valid=844217, seed=3, iters=10, batch_rows=1024,
+        sigmoid_degree=3, target_pos=0.2, standardise=True,
+    ),
+}
+_BASE["c4"] = dict(_BASE["c3"], name="c4-batching-form")
+_BASE["c5"] = dict(_BASE["c3"], name="c5-learned-sigmoid", sigmoid_degree=(5, 7))
+
+CONFIGS = _BASE
+
+
+def get_config(key):
+    cfg = copy.deepcopy(_BASE[key])
+    cfg["key_seed"] = cfg["seed"] + 100
+    cfg["enc_seed"] = cfg["seed"] + 200
+    return cfg

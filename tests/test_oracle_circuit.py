@@ -1,0 +1,106 @@
+"""Pins for the oracle's encrypted QG-NAG iteration: its decryptions must follow
+the FP64 plaintext trainer (same sigma~, same schedule) within the stated
+tolerance, and its intermediates must decrypt to the plaintext quantities."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import circuit, trainer
+from oracle.ckks import Oracle
+from oracle.encode import encode
+
+TOL_W = 1e-3
+
+
+def setup_run(cfgkey, degree_coeffs=trainer.G8, n_rows=None, batch=None, **over):
+    cfg = synth.get_config(cfgkey)
+    cfg.update(over)
+    d = synth.make_dataset(cfg)
+    X, y = d["X"], d["y"]
+    if n_rows:
+        X, y = X[:n_rows], y[:n_rows]
+    o = Oracle.from_config(cfg)
+    N, m, g = o.N, cfg["m"], cfg["g"]
+    o.keygen(cfg["key_seed"], circuit.rot_steps(m, g))
+    Z = trainer.build_Z(X, y, g)
+    blocks = circuit.pack_blocks(Z, m, g, N)
+    L = o.top_level
+    Zc = [o.encrypt(encode(blocks[b], N, o.delta), L, o.delta, cfg["enc_seed"], b) for b in range(len(blocks))]
+    B = trainer.bbar(X, g)
+    sB = 2.0 ** 50 / B.max()
+    Bc = o.encrypt(encode(circuit.replicate_row(B, m, g), N, sB), L, sB, cfg["enc_seed"], 1 << 20)
+    W = o.encrypt(np.zeros(N, np.int64), L, o.delta, cfg["enc_seed"], (1 << 20) + 1)
+    V = o.encrypt(np.zeros(N, np.int64), L, o.delta, cfg["enc_seed"], (1 << 20) + 2)
+    masks = circuit.make_masks(o, m, g, degree_coeffs, L, o.delta)
+    return cfg, o, X, y, Zc, Bc, W, V, masks
+
+
+def test_c1_three_iterations_match_fp64():
+    cfg, o, X, y, Zc, Bc, W, V, masks = setup_run("c1")
+    m, g, L = cfg["m"], cfg["g"], o.top_level
+    ref = trainer.train(X, y, g, cfg["iters"])
+    st = circuit.new_state(refresh_seed=7)
+    for it in range(cfg["iters"]):
+        trace = []
+        W, V, st = circuit.nag_qg_step(o, Zc, Bc, W, V, st, masks, m, g, trace=trace)
+        # depth: 4 levels on c1, so the gradient ciphertext is refreshed mid-iteration
+        assert st["refreshed_gr"]
+        W = o.refresh(W, L, 99, 2 * it)
+        V = o.refresh(V, L, 99, 2 * it + 1)
+        w = o.decrypt_values(W, g).real
+        v = o.decrypt_values(V, g).real
+        assert np.abs(w - ref["history"][it]["W"]).max() < TOL_W
+        if it == cfg["iters"] - 1:
+            assert np.abs(v - ref["V"]).max() < TOL_W
+    # weights are replicated in every row of the slots
+    full = o.decrypt_values(W).real.reshape(m, g)
+    assert np.abs(full - full[0]).max() < 1e-6
+
+
+def test_c1_intermediates_decrypt_to_plaintext_quantities():
+    cfg, o, X, y, Zc, Bc, W, V, masks = setup_run("c1")
+    m, g = cfg["m"], cfg["g"]
+    # one step from a nonzero W: encrypt a W vector replicated across rows
+    rng = np.random.default_rng(3)
+    w = np.zeros(g)
+    w[: X.shape[1] + 1] = rng.normal(size=X.shape[1] + 1) * 0.5
+    Wc = o.encrypt(encode(circuit.replicate_row(w, m, g), o.N, o.delta), o.top_level, o.delta, 9, 9)
+    trace = []
+    circuit.nag_qg_step(o, Zc, Bc, Wc, Wc, circuit.new_state(7), masks, m, g, trace=trace)
+    tr = dict(trace)
+    Z = trainer.build_Z(X, y, g)
+    Zp = np.zeros((m, g))
+    Zp[: Z.shape[0]] = Z
+    margins = Zp @ w
+    u = o.decrypt_values(tr["u0"]).real.reshape(m, g)
+    assert np.abs(u[:, 0] - margins).max() < 1e-6
+    p = o.decrypt_values(tr["p0"]).real.reshape(m, g)
+    p_ref = 1 - trainer.sigma_tilde(margins, trainer.G8)
+    assert np.abs(p - p_ref[:, None]).max() < 1e-6
+    gr = o.decrypt_values(tr["gr"]).real.reshape(m, g)
+    assert np.abs(gr - (Zp.T @ p_ref)[None, :]).max() < 1e-5
+
+
+@pytest.mark.parametrize("degree", [5, 7])
+def test_learned_degree_circuits_match_fp64(degree):
+    # odd polynomials 1/2 + sum c_k (m/8)^k: the depth-3 mask-folded evaluation
+    base = {5: [0.19129, -4.5951e-3, 4.2214e-5], 7: [0.21689, -8.1934e-3, 1.6588e-4, -1.1959e-6]}[degree]
+    coeffs = {2 * i + 1: c for i, c in enumerate(base)}
+    # c1 shapes with a deeper chain (8 primes): degree 5/7 needs 6 levels per iteration
+    cfg, o, X, y, Zc, Bc, W, V, masks = setup_run("c1", degree_coeffs=coeffs, q_bits=[50] + [40] * 7, n_p=3)
+    m, g = cfg["m"], cfg["g"]
+    ref = trainer.train(X, y, g, 2, coeffs=coeffs)
+    st = circuit.new_state(refresh_seed=7)
+    for it in range(2):
+        W, V, st = circuit.nag_qg_step(o, Zc, Bc, W, V, st, masks, m, g, degree=degree)
+        W = o.refresh(W, o.top_level, 99, 2 * it)
+        V = o.refresh(V, o.top_level, 99, 2 * it + 1)
+        assert np.abs(o.decrypt_values(W, g).real - ref["history"][it]["W"]).max() < TOL_W
+
+
+def test_scale_mismatch_is_an_error():
+    cfg, o, X, y, Zc, Bc, W, V, masks = setup_run("c1")
+    bad = W.copy()
+    bad.scale *= 1.001
+    with pytest.raises(ValueError):
+        o.add(W, bad)
