@@ -1,0 +1,339 @@
+/*
+ * heqg.h -- C ABI of the MI355X (gfx950) library for encrypted
+ * quadratic-gradient NAG logistic-regression training (RNS-CKKS).
+ *
+ * Paper: "Privacy-Preserving Logistic Regression Training on Large Datasets"
+ * (arXiv 2406.13221).  The operations below are the homomorphic operations
+ * the paper lists (section 2.1: Enc, Dec, Add, cAdd, Mul, cMul, rotation,
+ * bootstrap) and the cloud-side training step of its pipeline (section 4.3,
+ * steps 4-7: gradient, quadratic gradient B-bar*g, NAG update, refresh).
+ *
+ * Conventions for every entry point
+ *  - Return value: HEQG_OK (0) or a negative HEQG_ERR_* code; a message for
+ *    the last failure on the calling thread is in heqg_last_error().  No C++
+ *    exception crosses this boundary.
+ *  - Errors found before any work is enqueued leave every output untouched.
+ *  - The library never allocates device memory.  Context tables, keys,
+ *    ciphertexts, plaintexts and workspaces are caller-owned device buffers,
+ *    sized with the matching *_bytes() query.  Host memory it allocates is
+ *    freed by the matching destroy call.
+ *  - Device work is enqueued asynchronously on the caller's stream; results
+ *    are valid once that stream has been synchronised.  Calls that return
+ *    host data (heqg_ctx_primes, heqg_encode, heqg_decode) are synchronous.
+ *  - Polynomials are stored limb-major: a polynomial at level l is l+1 rows
+ *    of N uint64 residues, row i modulo prime i of the chain, each residue in
+ *    [0, q_i).  Ciphertexts are [n_poly][l+1][N] and always in NTT form
+ *    (row i, position k holds the evaluation at psi_i^(2*brv(k)+1)).
+ *  - Concurrent calls on one context are allowed on different streams when
+ *    their output and workspace buffers do not overlap.
+ */
+#ifndef HEQG_H
+#define HEQG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HEQG_OK = 0,
+  HEQG_ERR_ARG = -1,         /* bad pointer, size, shape or level mismatch */
+  HEQG_ERR_LEVEL = -2,       /* not enough levels left for the operation */
+  HEQG_ERR_SCALE = -3,       /* operand scales differ by more than 2^-20 relative */
+  HEQG_ERR_KEY = -4,         /* no switching key for the requested rotation */
+  HEQG_ERR_OVERFLOW = -5,    /* value does not fit (encode, constant, decode) */
+  HEQG_ERR_DEVICE = -6,      /* a HIP runtime call failed */
+  HEQG_ERR_UNSUPPORTED = -7  /* parameter outside what the kernels implement */
+};
+
+/* ------------------------------------------------------------------ */
+/* Context                                                             */
+/* ------------------------------------------------------------------ */
+
+/*
+ * RNS-CKKS parameters.  N = 2^log2N (10 <= log2N <= 16).  The ciphertext
+ * modulus chain has n_q primes of q_bits[i] bits (q_0 first, q_{n_q-1} is
+ * rescaled away first); n_p special primes of p_bits bits extend it for key
+ * switching; dnum digits of alpha = ceil(n_q/dnum) primes (n_p >= alpha is
+ * required).  Every prime is 1 mod 2N and at most 61 bits.  Scale Delta =
+ * 2^log2_scale.  Primes are chosen deterministically: for each bit size,
+ * the largest primes k*2N+1 below 2^bits, in descending order, Q chain first.
+ */
+typedef struct {
+  int log2N;
+  int n_q;
+  const int* q_bits; /* host array of n_q bit sizes */
+  int n_p;
+  int p_bits;
+  int dnum;
+  int log2_scale;
+} heqg_params;
+
+typedef struct heqg_ctx heqg_ctx;
+
+/* Thread-local message describing the last error. */
+const char* heqg_last_error(void);
+
+/* Bytes of device memory for the context tables (NTT twiddles, base-conversion constants). */
+size_t heqg_ctx_tables_bytes(const heqg_params* p);
+
+/*
+ * Builds the prime chain and all tables on the host and copies them into
+ * dev_tables (caller-owned, >= heqg_ctx_tables_bytes, must outlive the
+ * context).  Synchronous.  *out receives a host handle.
+ */
+int heqg_ctx_create(const heqg_params* p, void* dev_tables, size_t bytes, heqg_ctx** out);
+void heqg_ctx_destroy(heqg_ctx* ctx);
+
+/* Copies the n_q + n_p primes (Q chain then P) into host array out. */
+int heqg_ctx_primes(const heqg_ctx* ctx, uint64_t* out);
+
+/* N, n_q, n_p, dnum, alpha (any pointer may be NULL). */
+int heqg_ctx_info(const heqg_ctx* ctx, int* N, int* n_q, int* n_p, int* dnum, int* alpha);
+
+/* ------------------------------------------------------------------ */
+/* Ciphertexts                                                         */
+/* ------------------------------------------------------------------ */
+
+/* One ciphertext: device data [n_poly][level+1][N] (n_poly 2, or 3 after a tensor product). */
+typedef struct {
+  uint64_t* data;
+  int n_poly;
+  int level;
+  double scale;
+} heqg_ct;
+
+/*
+ * count ciphertexts of identical shape, level and scale, ciphertext b at
+ * data + b*stride (stride in uint64 words, >= n_poly*(level+1)*N).
+ */
+typedef struct {
+  uint64_t* data;
+  int64_t count;
+  int64_t stride;
+  int n_poly;
+  int level;
+  double scale;
+} heqg_ct_batch;
+
+/* ------------------------------------------------------------------ */
+/* Keys (section 4.2: the cloud holds the public and evaluation keys;    */
+/* the secret key is kept in the same buffer for decrypt and refresh)    */
+/* ------------------------------------------------------------------ */
+
+typedef struct heqg_keys heqg_keys;
+
+/* Device bytes for s, the public key, the relinearisation key and n_rot rotation keys. */
+size_t heqg_keys_bytes(const heqg_ctx* ctx, int n_rot);
+/* Device workspace bytes for heqg_keygen. */
+size_t heqg_keygen_ws_bytes(const heqg_ctx* ctx);
+
+/*
+ * Generates the secret key s (ternary), the public key (b, a) = (-a s + e, a)
+ * over the Q chain, the relinearisation key (s^2 -> s) and one rotation key
+ * (s(X^(5^r)) -> s) per distinct rotation step r in rot_steps (slot
+ * rotation to the left by r; negative r rotates right).  Randomness is the
+ * ChaCha20 stream (RFC 8439 block function) keyed by seed; every key is a
+ * deterministic function of (seed, steps).  Switching keys use dnum digits:
+ * digit j carries P*s' on the primes of digit j (P = product of the special
+ * primes).  dev_keys (>= heqg_keys_bytes) and the handle *out are owned by
+ * the caller; destroy the handle with heqg_keys_destroy.
+ */
+int heqg_keygen(heqg_ctx* ctx, uint64_t seed, const int* rot_steps, int n_rot, void* dev_keys, size_t bytes,
+                void* ws, size_t ws_bytes, heqg_keys** out, hipStream_t stream);
+void heqg_keys_destroy(heqg_keys* keys);
+/* Number of rotation keys held and their Galois elements (host array of that length, may be NULL). */
+int heqg_keys_galois(const heqg_keys* keys, uint64_t* out);
+/*
+ * Copies part of the key material to a device buffer in canonical NTT form:
+ * which = 0: s over all n_q+n_p primes; 1: public key [2][n_q][N];
+ * 2: relinearisation key [dnum][2][n_q+n_p][N]; 3: rotation key number idx
+ * (order of heqg_keys_galois).  For parity checks.
+ */
+int heqg_keys_export(const heqg_keys* keys, int which, int idx, uint64_t* dev_out, hipStream_t stream);
+
+/* ------------------------------------------------------------------ */
+/* Encode / decode (host, FP64 canonical embedding)                    */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Slot k of m(X) is m(zeta^(5^k)), zeta = exp(i*pi/N), k < N/2 (a rotation by
+ * one slot is X -> X^5).  Encodes n <= N/2 real values v (imaginary parts 0,
+ * missing slots 0) as coeffs[j] = round(scale * tau^-1(v)_j), ties away from
+ * zero.  Returns HEQG_ERR_OVERFLOW if a coefficient reaches 2^62.
+ */
+int heqg_encode(const heqg_ctx* ctx, const double* v, size_t n, double scale, int64_t* coeffs);
+/*
+ * heqg_encode for `count` vectors: v is [count][n] (row-major), coeffs is
+ * [count][N].  Rows are split over `threads` host threads (<= 0: hardware
+ * concurrency).  Fails as a whole if any row fails.
+ */
+int heqg_encode_batch(const heqg_ctx* ctx, const double* v, size_t n, int64_t count, double scale, int64_t* coeffs,
+                      int threads);
+/* Decodes N integer-valued coefficients (as doubles) into n <= N/2 real slot values / scale. */
+int heqg_decode(const heqg_ctx* ctx, const double* coeffs, double scale, double* v, size_t n);
+
+/*
+ * Centred integer lift of decrypted coefficient-form residues (host rows
+ * [level+1][N]) to doubles, from limbs 0 and 1 (limb 0 only at level 0).
+ * HEQG_ERR_OVERFLOW if any further limb disagrees (the value does not fit).
+ */
+int heqg_lift(const heqg_ctx* ctx, const uint64_t* rows, int level, double* out);
+
+/* ------------------------------------------------------------------ */
+/* Encryption (section 2.1: Enc_pk, Dec_sk)                             */
+/* ------------------------------------------------------------------ */
+
+/* Device workspace bytes for encrypting/decrypting/refreshing a batch of `count` ciphertexts. */
+size_t heqg_enc_ws_bytes(const heqg_ctx* ctx, int64_t count);
+
+/*
+ * Enc_pk(m) for a batch: message b is the N signed coefficients at
+ * dev_coeffs + b*N (device int64), encrypted at out->level with
+ * v ternary, e0, e1 centred-binomial(21) drawn from the stream
+ * (seed, purpose, object_first + b).  Output c = (v*b_pk + e0 + m, v*a_pk + e1).
+ * out->n_poly must be 2; out->scale is recorded by the caller.
+ */
+int heqg_encrypt(heqg_ctx* ctx, const heqg_keys* keys, const int64_t* dev_coeffs, uint64_t seed, uint64_t object_first,
+                 const heqg_ct_batch* out, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Dec: c0 + c1*s (+ c2*s^2), written in coefficient form to dev_rows[b][level+1][N]. */
+int heqg_decrypt(heqg_ctx* ctx, const heqg_keys* keys, const heqg_ct_batch* in, uint64_t* dev_rows, void* ws,
+                 size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Key-holder refresh (stand-in for the paper's bootstrap, section 4.3 step 7):
+ * decrypts, lifts each coefficient to the integer centred in q_0*q_1 (q_0 at
+ * level 0), and encrypts it afresh at target_level with stream
+ * (seed, object_first + b).  The scale is kept.  out may equal in only when
+ * target_level == in->level.
+ */
+int heqg_refresh(heqg_ctx* ctx, const heqg_keys* keys, const heqg_ct_batch* in, int target_level, uint64_t seed,
+                 uint64_t object_first, const heqg_ct_batch* out, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Signed coefficients (device int64 [count][N]) -> NTT-form plaintexts [count][level+1][N]. */
+int heqg_pt_load(heqg_ctx* ctx, const int64_t* dev_coeffs, int64_t count, int level, uint64_t* dev_pt,
+                 hipStream_t stream);
+
+/* ------------------------------------------------------------------ */
+/* Arithmetic (section 2.1).  Batched: one call processes every          */
+/* ciphertext of the batch.  Binary operations drop the higher-level     */
+/* operand to the lower level; outputs take that level.                  */
+/* ------------------------------------------------------------------ */
+
+/* Device workspace bytes for hmult/rotate/relin on a batch of `count` at the context's top level. */
+size_t heqg_ks_ws_bytes(const heqg_ctx* ctx, int64_t count);
+
+/* out = a + b / a - b (scales must agree to 2^-20; out keeps a's scale). */
+int heqg_add(heqg_ctx* ctx, const heqg_ct_batch* a, const heqg_ct_batch* b, const heqg_ct_batch* out, hipStream_t s);
+int heqg_sub(heqg_ctx* ctx, const heqg_ct_batch* a, const heqg_ct_batch* b, const heqg_ct_batch* out, hipStream_t s);
+/* Tensor product (a0 b0, a0 b1 + a1 b0, a1 b1); out->n_poly = 3, scale s_a*s_b. */
+int heqg_tensor(heqg_ctx* ctx, const heqg_ct_batch* a, const heqg_ct_batch* b, const heqg_ct_batch* out, hipStream_t s);
+/* Relinearise a 3-part ciphertext with the s^2 -> s key (hybrid key switching). */
+int heqg_relin(heqg_ctx* ctx, const heqg_keys* keys, const heqg_ct_batch* in, const heqg_ct_batch* out, void* ws,
+               size_t ws_bytes, hipStream_t s);
+/* Mul: tensor + relinearise (no rescale). */
+int heqg_hmult(heqg_ctx* ctx, const heqg_keys* keys, const heqg_ct_batch* a, const heqg_ct_batch* b,
+               const heqg_ct_batch* out, void* ws, size_t ws_bytes, hipStream_t s);
+/*
+ * Rotation of every slot vector left by `step`: X -> X^(5^step), then key
+ * switch back to s.  HEQG_ERR_KEY if no key for that Galois element.
+ */
+int heqg_rotate(heqg_ctx* ctx, const heqg_keys* keys, const heqg_ct_batch* in, int step, const heqg_ct_batch* out,
+                void* ws, size_t ws_bytes, hipStream_t s);
+/*
+ * Rescale by the last prime q_l: x_i <- (x_i - [x_l]_centred) * q_l^-1 mod q_i,
+ * level l -> l-1, scale / q_l.  HEQG_ERR_LEVEL at level 0.
+ */
+int heqg_rescale(heqg_ctx* ctx, const heqg_ct_batch* in, const heqg_ct_batch* out, void* ws, size_t ws_bytes,
+                 hipStream_t s);
+/* Keep limbs 0..level (out may alias in; no data moves when it does and strides match). */
+int heqg_drop(heqg_ctx* ctx, const heqg_ct_batch* in, int level, const heqg_ct_batch* out, hipStream_t s);
+/* Every part times an NTT-form plaintext (device rows, >= level+1 limbs); scale s*pt_scale. */
+int heqg_mul_pt(heqg_ctx* ctx, const heqg_ct_batch* in, const uint64_t* dev_pt, double pt_scale,
+                const heqg_ct_batch* out, hipStream_t s);
+/* c0 += plaintext (scales must agree). */
+int heqg_add_pt(heqg_ctx* ctx, const heqg_ct_batch* in, const uint64_t* dev_pt, double pt_scale,
+                const heqg_ct_batch* out, hipStream_t s);
+/*
+ * cMul with exact target scale: k = round(c * target * q_l / scale) (FP64,
+ * left to right, ties away from zero), multiply by k, rescale; the result is
+ * labelled with `target`.  HEQG_ERR_OVERFLOW if |k| >= 2^62.
+ */
+int heqg_mul_const(heqg_ctx* ctx, const heqg_ct_batch* in, double c, double target, const heqg_ct_batch* out,
+                   void* ws, size_t ws_bytes, hipStream_t s);
+
+/* ------------------------------------------------------------------ */
+/* Limb NTT (exposed for parity and throughput measurement)             */
+/* ------------------------------------------------------------------ */
+
+/*
+ * In-place forward (inverse = 0) or inverse negacyclic NTT of n_rows rows of
+ * N residues at dev_rows + r*N; row r uses prime index first_prime + (r mod period).
+ */
+int heqg_ntt(heqg_ctx* ctx, uint64_t* dev_rows, int64_t n_rows, int first_prime, int period, int inverse,
+             hipStream_t s);
+
+/* ------------------------------------------------------------------ */
+/* Training step (section 3.2 Algorithm 1; section 3.3; section 4.3)    */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Sigmoid plan: sigma~(m) = 1/2 + sum_k c_k m^k over odd k <= degree
+ * (degree 3, 5 or 7).  masks: device NTT-form plaintexts at level mask_level,
+ * [n_terms + 1][mask_level+1][N]: for each odd k ascending, encode(-c_k * F)
+ * at mask_scales[i], then encode(F / 2) at mask_scales[n_terms], where F is
+ * the column-0 filter (1 in column 0 of every row of the m x g block layout).
+ */
+typedef struct {
+  int degree;
+  const uint64_t* masks;
+  int mask_level;
+  const double* mask_scales; /* host array, n_terms + 1 entries */
+} heqg_sigmoid;
+
+/*
+ * NAG state (Algorithm 1): iteration index t (0-based), alpha0, alpha1; the
+ * learning-rate multiplier on G is F2(t) = lr_max - (lr_max - lr_min)*(t/T)^gamma.
+ * On return t is incremented and (alpha0, alpha1) advanced; eta and lr hold
+ * the values used; refreshed_gr is 1 when the gradient ciphertext had to be
+ * refreshed mid-iteration (chains too short for the whole iteration).
+ */
+typedef struct {
+  int t;
+  double alpha0, alpha1;
+  double lr_max, lr_min, T, gamma;
+  int m_rows, g_cols;
+  uint64_t refresh_seed;
+  double eta, lr;
+  int refreshed_gr;
+} heqg_nag_state;
+
+/* Device workspace bytes for heqg_nag_qg_step with `batch` blocks in flight. */
+size_t heqg_nag_ws_bytes(const heqg_ctx* ctx, int batch, int degree);
+
+/*
+ * One encrypted QG-NAG iteration over the blocks Z (all blocks: full-batch,
+ * section 3.3; the blocks of one mini-batch with that batch's B-bar:
+ * Algorithm 1).  Z, Bbar, W, V at one level with W, V at the working scale.
+ * Per block: margins u = Rescale(Relin(Z_b (x) W)), row sums by rotations,
+ * masked sigmoid p = 1 - sigma~(u) in column 0, replication across the row,
+ * accumulation of Z_b (x) p.  Then relinearise + rescale, column sums,
+ * G_v = (lr B-bar) g, G_w = (lr (1-eta) B-bar) g, and
+ * V' = W + G_v,  W' = (1-eta) W + eta V + G_w  (section 3.2, Algorithm 1).
+ * W and V are overwritten with W', V' (level lower by the depth used, scale
+ * Delta).  `batch` blocks are processed per launch (1 <= batch).
+ */
+int heqg_nag_qg_step(heqg_ctx* ctx, const heqg_keys* keys, const heqg_ct_batch* Z, const heqg_ct* Bbar,
+                     heqg_ct* W, heqg_ct* V, const heqg_sigmoid* sig, heqg_nag_state* st, int batch, void* ws,
+                     size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HEQG_H */

@@ -1,0 +1,92 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "modarith.h"
+
+#define HEQG_MAX_PRIMES 64
+
+// Rows of N residues: row (ia, ib, ii) at data + ia*sa + ib*sb + ii*N, using prime pidx[ii].
+struct RowSet {
+  uint64_t* data;
+  int64_t na, nb;
+  int ni;
+  int64_t sa, sb;
+  int pidx[HEQG_MAX_PRIMES];
+};
+
+// A batch of ciphertext-shaped arrays: element (b, p, i, c) at d + b*cs + p*ps + i*N + c.
+struct CtV {
+  uint64_t* d;
+  int64_t cs, ps;
+};
+
+// Device-side table pointers (inside the caller's table buffer).
+struct DevTables {
+  const uint64_t* tw_fwd;    // [nqp][N][2]: psi^brv(k) and its Shoup companion
+  const uint64_t* tw_inv;    // [nqp][N][2]: psi^-brv(k) and its Shoup companion
+  const PrimeConst* pc;      // [nqp]
+  const uint64_t* rescale;   // [n_q][n_q][2]: q_l^-1 mod q_i (+Shoup) at [l][i]
+  const uint64_t* rescale_q; // [n_q][n_q]: q_l mod q_i
+  const uint64_t* modup;     // [n_q][dnum][mu_stride][2]
+  const uint64_t* moddown;   // inv_hatP [n_p][2], hatP [n_q][n_p][2], Pinv [n_q][2]
+};
+
+// Geometry the kernels need.
+struct Geo {
+  int logN, N, n_q, n_p, nqp, dnum, alpha, mu_stride;
+};
+
+// ---- launchers (kernels.hip / ntt.hip) ----
+int launch_ntt(const DevTables& t, int log2N, const RowSet& rows, bool inverse, hipStream_t s);
+
+void k_add_launch(const Geo& g, const DevTables& t, CtV a, CtV b, CtV out, int64_t count, int n_poly, int nl, bool sub,
+                  hipStream_t s);
+void k_tensor_launch(const Geo& g, const DevTables& t, CtV a, CtV b, CtV out, int64_t count, int nl, bool acc,
+                     hipStream_t s);
+void k_tensor_reduce_launch(const Geo& g, const DevTables& t, CtV a, CtV b, int64_t count, CtV acc, int nl,
+                            bool accumulate, hipStream_t s);
+void k_mul_pt_launch(const Geo& g, const DevTables& t, CtV a, const uint64_t* pt, CtV out, int64_t count, int n_poly,
+                     int nl, hipStream_t s);
+void k_add_pt_launch(const Geo& g, const DevTables& t, CtV a, const uint64_t* pt, CtV out, int64_t count, int nl,
+                     hipStream_t s);
+void k_mul_scalar_launch(const Geo& g, const DevTables& t, CtV a, CtV out, int64_t count, int n_poly, int nl,
+                         const uint64_t* k_res /* host [nl][2] */, hipStream_t s);
+void k_copy_launch(const Geo& g, CtV a, CtV out, int64_t count, int n_poly, int nl, hipStream_t s);
+void k_automorph_launch(const Geo& g, CtV a, CtV out, int64_t count, int n_poly, int nl, uint64_t galois,
+                        hipStream_t s);
+void k_rescale_spread_launch(const Geo& g, const DevTables& t, const uint64_t* last, uint64_t* spread, int64_t rows,
+                             int level, hipStream_t s);
+void k_rescale_combine_launch(const Geo& g, const DevTables& t, CtV in, const uint64_t* spread, CtV out, int64_t count,
+                              int n_poly, int level, hipStream_t s);
+void k_modup_launch(const Geo& g, const DevTables& t, const uint64_t* dcoef, int64_t count, int level, int digit,
+                    uint64_t* ext, int64_t ext_cs, hipStream_t s);
+void k_ks_inner_launch(const Geo& g, const DevTables& t, CtV d, const uint64_t* ext, int64_t ext_cs, int64_t ext_ds,
+                       const uint64_t* key, uint64_t* acc, int64_t count, int level, hipStream_t s);
+void k_moddown_conv_launch(const Geo& g, const DevTables& t, const uint64_t* acc, uint64_t* conv, int64_t count,
+                           int level, hipStream_t s);
+void k_ks_combine_launch(const Geo& g, const DevTables& t, const uint64_t* acc, const uint64_t* conv, CtV base0,
+                         CtV base1, bool has_base1, CtV out, int64_t count, int level, hipStream_t s);
+
+// sampling / encryption
+enum { PUR_SK = 1, PUR_PK_A = 2, PUR_PK_E = 3, PUR_KSK_A = 4, PUR_KSK_E = 5, PUR_ENC_V = 6, PUR_ENC_E0 = 7, PUR_ENC_E1 = 8 };
+void k_sample_small_launch(uint64_t seed, uint64_t purpose, uint64_t obj_first, int64_t count, int N, int kind,
+                           int64_t* out, hipStream_t s);  // kind 0 ternary, 1 CBD(21)
+void k_small_to_rows_launch(const Geo& g, const DevTables& t, const int64_t* in, int64_t in_stride, int64_t count,
+                            uint64_t* rows, int64_t row_cs, int nrows, int p_first_q, int split, hipStream_t s);
+void k_sample_uniform_launch(const Geo& g, const DevTables& t, uint64_t seed, uint64_t purpose, uint64_t obj,
+                             uint64_t* rows, int nrows, const int* pidx_host, hipStream_t s);
+void k_pk_combine_launch(const Geo& g, const DevTables& t, const uint64_t* a, const uint64_t* e, const uint64_t* sk,
+                         uint64_t* b, int nrows, hipStream_t s);
+void k_ksk_combine_launch(const Geo& g, const DevTables& t, const uint64_t* a, const uint64_t* e, const uint64_t* sk,
+                          const uint64_t* sprime, const uint64_t* pmod_host, uint64_t* b, int digit, hipStream_t s);
+void k_enc_combine_launch(const Geo& g, const DevTables& t, const uint64_t* tmp, int64_t tmp_cs, const uint64_t* pk,
+                          CtV out, int64_t count, int nl, hipStream_t s);
+void k_dec_launch(const Geo& g, const DevTables& t, CtV ct, int n_poly, const uint64_t* sk, uint64_t* out,
+                  int64_t count, int nl, hipStream_t s);
+// lift constants: q0^-1 mod q1, its Shoup companion, (q0*q1 - 1)/2 as (lo, hi)
+void k_lift_launch(const Geo& g, const DevTables& t, const uint64_t lc[4], const uint64_t* dec, int nl_in, uint64_t* out,
+                   int64_t out_cs, int nl_out, int64_t count, hipStream_t s);
+void k_mul_rows_launch(const Geo& g, const DevTables& t, const uint64_t* a, const uint64_t* b, uint64_t* out,
+                       int nrows, hipStream_t s);

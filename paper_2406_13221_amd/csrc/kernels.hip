@@ -1,0 +1,788 @@
+// Elementwise, base-conversion, key-switching and sampling kernels (gfx950).
+//
+// All data are limb-major uint64 rows of N residues.  Elementwise kernels
+// give each thread two adjacent coefficients (one 16-byte access per
+// operand) and each workgroup of 256 threads a 512-coefficient chunk of one
+// row; the grid enumerates (ciphertext, part, limb, chunk) with the chunk
+// fastest, so consecutive workgroups stream consecutive memory.
+#include "internal.h"
+
+namespace {
+
+constexpr int EW_THREADS = 256;
+constexpr int EW_CHUNK = 512;
+
+struct __align__(16) U2 {
+  uint64_t a, b;
+};
+
+__device__ __forceinline__ U2 ld2(const uint64_t* p) { return *reinterpret_cast<const U2*>(p); }
+__device__ __forceinline__ void st2(uint64_t* p, uint64_t a, uint64_t b) { *reinterpret_cast<U2*>(p) = U2{a, b}; }
+
+struct K64 {
+  U2 v[HEQG_MAX_PRIMES];
+};
+
+inline unsigned grid_of(int64_t n) { return (unsigned)n; }
+
+// ------------------------------------------------------------------ add / sub
+__global__ void __launch_bounds__(EW_THREADS) k_add(const PrimeConst* pc, CtV a, CtV b, CtV out, int logN, int nl,
+                                                     int n_poly, int sub) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  int64_t bid = blockIdx.x;
+  int ch = (int)(bid % chunks);
+  int64_t row = bid / chunks;
+  int i = (int)(row % nl);
+  int64_t r2 = row / nl;
+  int p = (int)(r2 % n_poly);
+  int64_t ct = r2 / n_poly;
+  int64_t off = ((int64_t)i << logN) + ch * EW_CHUNK + threadIdx.x * 2;
+  const uint64_t q = pc[i].q;
+  U2 x = ld2(a.d + ct * a.cs + p * a.ps + off);
+  U2 y = ld2(b.d + ct * b.cs + p * b.ps + off);
+  uint64_t r0, r1;
+  if (sub) {
+    r0 = submod(x.a, y.a, q);
+    r1 = submod(x.b, y.b, q);
+  } else {
+    r0 = addmod(x.a, y.a, q);
+    r1 = addmod(x.b, y.b, q);
+  }
+  st2(out.d + ct * out.cs + p * out.ps + off, r0, r1);
+}
+
+// ------------------------------------------------------------------ tensor
+__device__ __forceinline__ void tensor1(uint64_t a0, uint64_t a1, uint64_t b0, uint64_t b1, const PrimeConst& pc,
+                                        uint64_t& d0, uint64_t& d1, uint64_t& d2) {
+  d0 = mulmod(a0, b0, pc);
+  d2 = mulmod(a1, b1, pc);
+  uint64_t s = mulmod(addmod(a0, a1, pc.q), addmod(b0, b1, pc.q), pc);
+  d1 = submod(submod(s, d0, pc.q), d2, pc.q);
+}
+
+__global__ void __launch_bounds__(EW_THREADS) k_tensor(const PrimeConst* pc, CtV a, CtV b, CtV out, int logN, int nl,
+                                                        int acc) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  int64_t bid = blockIdx.x;
+  int ch = (int)(bid % chunks);
+  int64_t row = bid / chunks;
+  int i = (int)(row % nl);
+  int64_t ct = row / nl;
+  int64_t off = ((int64_t)i << logN) + ch * EW_CHUNK + threadIdx.x * 2;
+  const PrimeConst P = pc[i];
+  const uint64_t* pa = a.d + ct * a.cs + off;
+  const uint64_t* pb = b.d + ct * b.cs + off;
+  U2 a0 = ld2(pa), a1 = ld2(pa + a.ps), b0 = ld2(pb), b1 = ld2(pb + b.ps);
+  uint64_t d0a, d1a, d2a, d0b, d1b, d2b;
+  tensor1(a0.a, a1.a, b0.a, b1.a, P, d0a, d1a, d2a);
+  tensor1(a0.b, a1.b, b0.b, b1.b, P, d0b, d1b, d2b);
+  uint64_t* po = out.d + ct * out.cs + off;
+  if (acc) {
+    U2 o0 = ld2(po), o1 = ld2(po + out.ps), o2 = ld2(po + 2 * out.ps);
+    d0a = addmod(d0a, o0.a, P.q); d0b = addmod(d0b, o0.b, P.q);
+    d1a = addmod(d1a, o1.a, P.q); d1b = addmod(d1b, o1.b, P.q);
+    d2a = addmod(d2a, o2.a, P.q); d2b = addmod(d2b, o2.b, P.q);
+  }
+  st2(po, d0a, d0b);
+  st2(po + out.ps, d1a, d1b);
+  st2(po + 2 * out.ps, d2a, d2b);
+}
+
+// acc (3 parts, one ciphertext) (+)= sum_b a_b (x) b_b
+__global__ void __launch_bounds__(EW_THREADS) k_tensor_reduce(const PrimeConst* pc, CtV a, CtV b, int64_t count, CtV acc,
+                                                               int logN, int nl, int accumulate) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  int64_t bid = blockIdx.x;
+  int ch = (int)(bid % chunks);
+  int i = (int)(bid / chunks);
+  int64_t off = ((int64_t)i << logN) + ch * EW_CHUNK + threadIdx.x * 2;
+  const PrimeConst P = pc[i];
+  uint64_t s0a = 0, s1a = 0, s2a = 0, s0b = 0, s1b = 0, s2b = 0;
+  uint64_t* po = acc.d + off;
+  if (accumulate) {
+    U2 o0 = ld2(po), o1 = ld2(po + acc.ps), o2 = ld2(po + 2 * acc.ps);
+    s0a = o0.a; s0b = o0.b; s1a = o1.a; s1b = o1.b; s2a = o2.a; s2b = o2.b;
+  }
+  for (int64_t ct = 0; ct < count; ++ct) {
+    const uint64_t* pa = a.d + ct * a.cs + off;
+    const uint64_t* pb = b.d + ct * b.cs + off;
+    U2 a0 = ld2(pa), a1 = ld2(pa + a.ps), b0 = ld2(pb), b1 = ld2(pb + b.ps);
+    uint64_t d0, d1, d2;
+    tensor1(a0.a, a1.a, b0.a, b1.a, P, d0, d1, d2);
+    s0a = addmod(s0a, d0, P.q); s1a = addmod(s1a, d1, P.q); s2a = addmod(s2a, d2, P.q);
+    tensor1(a0.b, a1.b, b0.b, b1.b, P, d0, d1, d2);
+    s0b = addmod(s0b, d0, P.q); s1b = addmod(s1b, d1, P.q); s2b = addmod(s2b, d2, P.q);
+  }
+  st2(po, s0a, s0b);
+  st2(po + acc.ps, s1a, s1b);
+  st2(po + 2 * acc.ps, s2a, s2b);
+}
+
+// ------------------------------------------------------------------ plaintext / scalar products
+__global__ void __launch_bounds__(EW_THREADS) k_mul_pt(const PrimeConst* pc, CtV a, const uint64_t* pt, CtV out,
+                                                        int logN, int nl, int n_poly) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  int64_t bid = blockIdx.x;
+  int ch = (int)(bid % chunks);
+  int64_t row = bid / chunks;
+  int i = (int)(row % nl);
+  int64_t r2 = row / nl;
+  int p = (int)(r2 % n_poly);
+  int64_t ct = r2 / n_poly;
+  int64_t off = ((int64_t)i << logN) + ch * EW_CHUNK + threadIdx.x * 2;
+  const PrimeConst P = pc[i];
+  U2 x = ld2(a.d + ct * a.cs + p * a.ps + off);
+  U2 w = ld2(pt + off);
+  st2(out.d + ct * out.cs + p * out.ps + off, mulmod(x.a, w.a, P), mulmod(x.b, w.b, P));
+}
+
+__global__ void __launch_bounds__(EW_THREADS) k_add_pt(const PrimeConst* pc, CtV a, const uint64_t* pt, CtV out,
+                                                        int logN, int nl) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  int64_t bid = blockIdx.x;
+  int ch = (int)(bid % chunks);
+  int64_t row = bid / chunks;
+  int i = (int)(row % nl);
+  int64_t ct = row / nl;
+  int64_t off = ((int64_t)i << logN) + ch * EW_CHUNK + threadIdx.x * 2;
+  const uint64_t q = pc[i].q;
+  U2 x = ld2(a.d + ct * a.cs + off);
+  U2 y = ld2(a.d + ct * a.cs + a.ps + off);
+  U2 w = ld2(pt + off);
+  st2(out.d + ct * out.cs + off, addmod(x.a, w.a, q), addmod(x.b, w.b, q));
+  st2(out.d + ct * out.cs + out.ps + off, y.a, y.b);
+}
+
+__global__ void __launch_bounds__(EW_THREADS) k_mul_scalar(const PrimeConst* pc, CtV a, CtV out, int logN, int nl,
+                                                            int n_poly, K64 k) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  int64_t bid = blockIdx.x;
+  int ch = (int)(bid % chunks);
+  int64_t row = bid / chunks;
+  int i = (int)(row % nl);
+  int64_t r2 = row / nl;
+  int p = (int)(r2 % n_poly);
+  int64_t ct = r2 / n_poly;
+  int64_t off = ((int64_t)i << logN) + ch * EW_CHUNK + threadIdx.x * 2;
+  const uint64_t q = pc[i].q;
+  U2 x = ld2(a.d + ct * a.cs + p * a.ps + off);
+  U2 w = k.v[i];
+  st2(out.d + ct * out.cs + p * out.ps + off, mul_shoup(x.a, w.a, w.b, q), mul_shoup(x.b, w.a, w.b, q));
+}
+
+__global__ void __launch_bounds__(EW_THREADS) k_copy(CtV a, CtV out, int logN, int nl, int n_poly) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  int64_t bid = blockIdx.x;
+  int ch = (int)(bid % chunks);
+  int64_t row = bid / chunks;
+  int i = (int)(row % nl);
+  int64_t r2 = row / nl;
+  int p = (int)(r2 % n_poly);
+  int64_t ct = r2 / n_poly;
+  int64_t off = ((int64_t)i << logN) + ch * EW_CHUNK + threadIdx.x * 2;
+  U2 x = ld2(a.d + ct * a.cs + p * a.ps + off);
+  st2(out.d + ct * out.cs + p * out.ps + off, x.a, x.b);
+}
+
+// ------------------------------------------------------------------ automorphism (NTT domain)
+// Position k holds the evaluation at psi^(2 brv(k) + 1); X -> X^t maps it to the
+// evaluation at psi^((2 brv(k) + 1) t), found at position brv(((2 brv(k)+1) t mod 2N - 1) / 2).
+__device__ __forceinline__ uint32_t brv_n(uint32_t x, int logN) { return __brev(x) >> (32 - logN); }
+
+__global__ void __launch_bounds__(EW_THREADS) k_automorph(CtV a, CtV out, int logN, int nl, int n_poly,
+                                                           uint64_t galois) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  int64_t bid = blockIdx.x;
+  int ch = (int)(bid % chunks);
+  int64_t row = bid / chunks;
+  int i = (int)(row % nl);
+  int64_t r2 = row / nl;
+  int p = (int)(r2 % n_poly);
+  int64_t ct = r2 / n_poly;
+  const uint32_t mask2n = (2u << logN) - 1;
+  const uint64_t* src = a.d + ct * a.cs + p * a.ps + ((int64_t)i << logN);
+  uint64_t* dst = out.d + ct * out.cs + p * out.ps + ((int64_t)i << logN);
+  uint32_t k0 = ch * EW_CHUNK + threadIdx.x * 2;
+  uint64_t v[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    uint32_t k = k0 + u;
+    uint32_t e = 2 * brv_n(k, logN) + 1;
+    uint32_t et = (uint32_t)(((uint64_t)e * galois) & mask2n);
+    v[u] = src[brv_n((et - 1) >> 1, logN)];
+  }
+  st2(dst + k0, v[0], v[1]);
+}
+
+// ------------------------------------------------------------------ rescale
+// spread[r][i][c] = [x]_centred mod q_i for i < level, from last[r][c] (coefficient form mod q_level)
+__global__ void __launch_bounds__(EW_THREADS) k_rescale_spread(const PrimeConst* pc, const uint64_t* rq,
+                                                                const uint64_t* last, uint64_t* spread, int logN,
+                                                                int level, int nq) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  int64_t bid = blockIdx.x;
+  int ch = (int)(bid % chunks);
+  int64_t r = bid / chunks;
+  int c = ch * EW_CHUNK + threadIdx.x * 2;
+  const uint64_t ql = pc[level].q;
+  U2 x = ld2(last + (r << logN) + c);
+  const uint64_t half = (ql - 1) >> 1;
+  for (int i = 0; i < level; ++i) {
+    const PrimeConst P = pc[i];
+    uint64_t qlm = rq[(int64_t)level * nq + i];
+    uint64_t v0 = reduce64(x.a, P), v1 = reduce64(x.b, P);
+    if (x.a > half) v0 = submod(v0, qlm, P.q);
+    if (x.b > half) v1 = submod(v1, qlm, P.q);
+    st2(spread + ((r * level + i) << logN) + c, v0, v1);
+  }
+}
+
+// out_i = (in_i - spread_i) * q_l^-1 mod q_i for i < level
+__global__ void __launch_bounds__(EW_THREADS) k_rescale_combine(const PrimeConst* pc, const uint64_t* rs, CtV in,
+                                                                 const uint64_t* spread, CtV out, int logN, int level,
+                                                                 int n_poly, int nq) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  int64_t bid = blockIdx.x;
+  int ch = (int)(bid % chunks);
+  int64_t row = bid / chunks;
+  int i = (int)(row % level);
+  int64_t r2 = row / level;  // = ct * n_poly + p
+  int p = (int)(r2 % n_poly);
+  int64_t ct = r2 / n_poly;
+  int64_t off = ((int64_t)i << logN) + ch * EW_CHUNK + threadIdx.x * 2;
+  const uint64_t q = pc[i].q;
+  const uint64_t* c2 = rs + ((int64_t)level * nq + i) * 2;
+  U2 x = ld2(in.d + ct * in.cs + p * in.ps + off);
+  U2 y = ld2(spread + ((r2 * level) << logN) + off);
+  st2(out.d + ct * out.cs + p * out.ps + off, mul_shoup(submod(x.a, y.a, q), c2[0], c2[1], q),
+      mul_shoup(submod(x.b, y.b, q), c2[0], c2[1], q));
+}
+
+// ------------------------------------------------------------------ key switching
+// ModUp of digit j at level l: d (coefficient form, rows 0..l, ct stride (l+1)N) to every
+// prime outside the digit: sum_k [x_k * (D/s_k)^-1]_{s_k} * (D/s_k) mod target.
+// ext rows: targets in order (Q rows 0..l outside the digit, then P rows).
+__global__ void __launch_bounds__(EW_THREADS) k_modup(const PrimeConst* pc, const uint64_t* mu_tab, const uint64_t* dcoef,
+                                                       uint64_t* ext, int64_t ext_cs, int logN, int level, int lo,
+                                                       int sz, int nq, int np, int alpha) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  int64_t bid = blockIdx.x;
+  int ch = (int)(bid % chunks);
+  int64_t ct = bid / chunks;
+  const int nl = level + 1;
+  int c = ch * EW_CHUNK + threadIdx.x * 2;
+  const uint64_t* src = dcoef + ((ct * nl) << logN) + c;
+  uint64_t y0[16], y1[16];
+#pragma unroll 4
+  for (int k = 0; k < sz; ++k) {
+    const uint64_t q = pc[lo + k].q;
+    U2 x = ld2(src + ((int64_t)(lo + k) << logN));
+    uint64_t w = mu_tab[2 * k], ws = mu_tab[2 * k + 1];
+    y0[k] = mul_shoup(x.a, w, ws, q);
+    y1[k] = mul_shoup(x.b, w, ws, q);
+  }
+  uint64_t* dst = ext + ct * ext_cs + c;
+  int e = 0;
+  for (int g = 0; g < nl + np; ++g) {
+    if (g >= lo && g < lo + sz) continue;
+    int gp = g < nl ? g : nq + (g - nl);
+    const uint64_t q = pc[gp].q, two_q = 2 * q;
+    const uint64_t* h = mu_tab + 2 * (alpha + gp * alpha);
+    uint64_t a0 = 0, a1 = 0;
+    for (int k = 0; k < sz; ++k) {
+      uint64_t w = h[2 * k], ws = h[2 * k + 1];
+      a0 += mul_shoup_lazy(y0[k], w, ws, q);
+      a1 += mul_shoup_lazy(y1[k], w, ws, q);
+      a0 = a0 >= two_q ? a0 - two_q : a0;
+      a1 = a1 >= two_q ? a1 - two_q : a1;
+    }
+    st2(dst + ((int64_t)e << logN), csub(a0, q), csub(a1, q));
+    ++e;
+  }
+}
+
+// acc[ct][part][x] = sum_j v_j[x] * key_j[part][prime(x)], x over Q rows 0..l then P rows;
+// v_j[x] = d[x] for x in digit j, else the ModUp row of digit j.
+__global__ void __launch_bounds__(EW_THREADS) k_ks_inner(const PrimeConst* pc, CtV d, const uint64_t* ext, int64_t ext_cs,
+                                                          int64_t ext_ds, const uint64_t* key, uint64_t* acc, int logN,
+                                                          int level, int nq, int np, int alpha) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  const int nl = level + 1, nx = nl + np, nqp = nq + np;
+  int64_t bid = blockIdx.x;
+  int ch = (int)(bid % chunks);
+  int64_t row = bid / chunks;
+  int x = (int)(row % nx);
+  int64_t ct = row / nx;
+  int c = ch * EW_CHUNK + threadIdx.x * 2;
+  int gp = x < nl ? x : nq + (x - nl);
+  const PrimeConst P = pc[gp];
+  const int nd = (nl + alpha - 1) / alpha;
+  uint64_t s0a = 0, s0b = 0, s1a = 0, s1b = 0;
+  for (int j = 0; j < nd; ++j) {
+    int lo = j * alpha, hi = min(lo + alpha, nl);
+    U2 v;
+    if (x >= lo && x < hi) {
+      v = ld2(d.d + ct * d.cs + ((int64_t)x << logN) + c);
+    } else {
+      int e = x < lo ? x : x - (hi - lo);
+      v = ld2(ext + ct * ext_cs + j * ext_ds + ((int64_t)e << logN) + c);
+    }
+    const uint64_t* kb = key + (((int64_t)j * 2 * nqp + gp) << logN) + c;
+    const uint64_t* ka = kb + ((int64_t)nqp << logN);
+    U2 b = ld2(kb), a = ld2(ka);
+    s0a = addmod(s0a, mulmod(v.a, b.a, P), P.q);
+    s0b = addmod(s0b, mulmod(v.b, b.b, P), P.q);
+    s1a = addmod(s1a, mulmod(v.a, a.a, P), P.q);
+    s1b = addmod(s1b, mulmod(v.b, a.b, P), P.q);
+  }
+  uint64_t* o = acc + ct * (int64_t)(2 * nx) * (1 << logN) + ((int64_t)x << logN) + c;
+  st2(o, s0a, s0b);
+  st2(o + ((int64_t)nx << logN), s1a, s1b);
+}
+
+// conv[ct][part][i] = sum_k [x_k * (P/p_k)^-1]_{p_k} * (P/p_k) mod q_i  (x = P rows of acc, coefficient form)
+__global__ void __launch_bounds__(EW_THREADS) k_moddown_conv(const PrimeConst* pc, const uint64_t* md, const uint64_t* acc,
+                                                              uint64_t* conv, int logN, int level, int nq, int np) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  const int nl = level + 1, nx = nl + np;
+  int64_t bid = blockIdx.x;
+  int ch = (int)(bid % chunks);
+  int64_t r = bid / chunks;  // ct*2 + part
+  int c = ch * EW_CHUNK + threadIdx.x * 2;
+  const uint64_t* src = acc + ((r * nx + nl) << logN) + c;
+  uint64_t y0[16], y1[16];
+  for (int k = 0; k < np; ++k) {
+    const uint64_t q = pc[nq + k].q;
+    U2 x = ld2(src + ((int64_t)k << logN));
+    y0[k] = mul_shoup(x.a, md[2 * k], md[2 * k + 1], q);
+    y1[k] = mul_shoup(x.b, md[2 * k], md[2 * k + 1], q);
+  }
+  const uint64_t* hat = md + 2 * np;
+  uint64_t* dst = conv + ((r * nl) << logN) + c;
+  for (int i = 0; i < nl; ++i) {
+    const uint64_t q = pc[i].q, two_q = 2 * q;
+    const uint64_t* h = hat + 2 * (int64_t)i * np;
+    uint64_t a0 = 0, a1 = 0;
+    for (int k = 0; k < np; ++k) {
+      a0 += mul_shoup_lazy(y0[k], h[2 * k], h[2 * k + 1], q);
+      a1 += mul_shoup_lazy(y1[k], h[2 * k], h[2 * k + 1], q);
+      a0 = a0 >= two_q ? a0 - two_q : a0;
+      a1 = a1 >= two_q ? a1 - two_q : a1;
+    }
+    st2(dst + ((int64_t)i << logN), csub(a0, q), csub(a1, q));
+  }
+}
+
+// out_p_i = base_p_i + (acc_p_i - conv_p_i) * P^-1 mod q_i   (base_1 may be absent)
+__global__ void __launch_bounds__(EW_THREADS) k_ks_combine(const PrimeConst* pc, const uint64_t* pinv,
+                                                            const uint64_t* acc, const uint64_t* conv, CtV base0,
+                                                            CtV base1, int has_base1, CtV out, int logN, int level,
+                                                            int np) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  const int nl = level + 1, nx = nl + np;
+  int64_t bid = blockIdx.x;
+  int ch = (int)(bid % chunks);
+  int64_t row = bid / chunks;
+  int i = (int)(row % nl);
+  int64_t r2 = row / nl;
+  int p = (int)(r2 % 2);
+  int64_t ct = r2 / 2;
+  int64_t off = ((int64_t)i << logN) + ch * EW_CHUNK + threadIdx.x * 2;
+  const uint64_t q = pc[i].q;
+  U2 x = ld2(acc + ((ct * 2 + p) * nx << logN) + off);
+  U2 y = ld2(conv + ((ct * 2 + p) * nl << logN) + off);
+  uint64_t w = pinv[2 * i], ws = pinv[2 * i + 1];
+  uint64_t r0 = mul_shoup(submod(x.a, y.a, q), w, ws, q);
+  uint64_t r1 = mul_shoup(submod(x.b, y.b, q), w, ws, q);
+  if (p == 0 || has_base1) {
+    const CtV& B = p == 0 ? base0 : base1;
+    U2 z = ld2(B.d + ct * B.cs + off);
+    r0 = addmod(r0, z.a, q);
+    r1 = addmod(r1, z.b, q);
+  }
+  st2(out.d + ct * out.cs + p * out.ps + off, r0, r1);
+}
+
+// ------------------------------------------------------------------ ChaCha20 (RFC 8439) and samplers
+__device__ __forceinline__ uint32_t rotl(uint32_t v, int n) { return (v << n) | (v >> (32 - n)); }
+#define QRD(a, b, c, d)          \
+  a += b; d ^= a; d = rotl(d, 16); \
+  c += d; b ^= c; b = rotl(b, 12); \
+  a += b; d ^= a; d = rotl(d, 8);  \
+  c += d; b ^= c; b = rotl(b, 7);
+
+// 16 output words of the block (key from seed/purpose/object, nonce (lane,0,0), counter)
+__device__ void chacha_block(uint64_t seed, uint64_t purpose, uint64_t object, uint32_t lane, uint32_t counter,
+                             uint32_t out[16]) {
+  uint32_t s[16];
+  s[0] = 0x61707865u; s[1] = 0x3320646eu; s[2] = 0x79622d32u; s[3] = 0x6b206574u;
+  s[4] = (uint32_t)seed; s[5] = (uint32_t)(seed >> 32);
+  s[6] = (uint32_t)purpose; s[7] = (uint32_t)(purpose >> 32);
+  s[8] = (uint32_t)object; s[9] = (uint32_t)(object >> 32);
+  s[10] = 0x47514548u; s[11] = 1u;
+  s[12] = counter; s[13] = lane; s[14] = 0; s[15] = 0;
+  uint32_t x[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) x[i] = s[i];
+#pragma unroll 1
+  for (int r = 0; r < 10; ++r) {
+    QRD(x[0], x[4], x[8], x[12]);
+    QRD(x[1], x[5], x[9], x[13]);
+    QRD(x[2], x[6], x[10], x[14]);
+    QRD(x[3], x[7], x[11], x[15]);
+    QRD(x[0], x[5], x[10], x[15]);
+    QRD(x[1], x[6], x[11], x[12]);
+    QRD(x[2], x[7], x[8], x[13]);
+    QRD(x[3], x[4], x[9], x[14]);
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) out[i] = x[i] + s[i];
+}
+
+// one thread per ChaCha block: 8 words -> 8 coefficients of message b
+__global__ void __launch_bounds__(EW_THREADS) k_sample_small(uint64_t seed, uint64_t purpose, uint64_t obj_first,
+                                                              int64_t count, int N, int kind, int64_t* out) {
+  int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t per = N / 8;
+  if (gid >= count * per) return;
+  int64_t b = gid / per;
+  uint32_t blk = (uint32_t)(gid % per);
+  uint32_t w[16];
+  chacha_block(seed, purpose, obj_first + (uint64_t)b, 0, blk, w);
+  int64_t* o = out + b * N + (int64_t)blk * 8;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    uint64_t v = (uint64_t)w[2 * k] | ((uint64_t)w[2 * k + 1] << 32);
+    int64_t r;
+    if (kind == 0) {
+      uint64_t m = v % 3;
+      r = m == 0 ? 0 : (m == 1 ? 1 : -1);
+    } else {
+      r = (int64_t)__popcll(v & 0x1FFFFFull) - (int64_t)__popcll((v >> 21) & 0x1FFFFFull);
+    }
+    o[k] = r;
+  }
+}
+
+// uniform rows: row r uses prime pidx[r] and lane pidx[r]; coefficient c from words 2c, 2c+1
+struct I64 {
+  int v[HEQG_MAX_PRIMES];
+};
+__global__ void __launch_bounds__(EW_THREADS) k_sample_uniform(const PrimeConst* pc, uint64_t seed, uint64_t purpose,
+                                                                uint64_t obj, uint64_t* rows, int N, int nrows, I64 pidx) {
+  int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int per = N / 4;
+  if (gid >= (int64_t)nrows * per) return;
+  int r = (int)(gid / per);
+  uint32_t blk = (uint32_t)(gid % per);
+  int g = pidx.v[r];
+  const PrimeConst P = pc[g];
+  uint32_t w[16];
+  chacha_block(seed, purpose, obj, (uint32_t)g, blk, w);
+  uint64_t* o = rows + (int64_t)r * N + (int64_t)blk * 4;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    uint64_t lo = (uint64_t)w[4 * k] | ((uint64_t)w[4 * k + 1] << 32);
+    uint64_t hi = (uint64_t)w[4 * k + 2] | ((uint64_t)w[4 * k + 3] << 32);
+    uint64_t h = mul_shoup(reduce64(hi, P), P.r64, P.r64_sh, P.q);
+    o[k] = addmod(h, reduce64(lo, P), P.q);
+  }
+}
+
+// signed coefficients -> residues on rows 0..nrows-1 (row r: prime r)
+__global__ void __launch_bounds__(EW_THREADS) k_small_to_rows(const PrimeConst* pc, const int64_t* in, int64_t in_stride,
+                                                               uint64_t* rows, int64_t row_cs, int logN, int nrows) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  int64_t bid = blockIdx.x;
+  int ch = (int)(bid % chunks);
+  int64_t row = bid / chunks;
+  int r = (int)(row % nrows);
+  int64_t b = row / nrows;
+  int c = ch * EW_CHUNK + threadIdx.x * 2;
+  const PrimeConst P = pc[r];
+  const int64_t* src = in + b * in_stride + c;
+  st2(rows + b * row_cs + ((int64_t)r << logN) + c, from_signed(src[0], P), from_signed(src[1], P));
+}
+
+// b = -a*s + e on nrows rows (row r: prime r)
+__global__ void __launch_bounds__(EW_THREADS) k_pk_combine(const PrimeConst* pc, const uint64_t* a, const uint64_t* e,
+                                                            const uint64_t* sk, uint64_t* b, int logN) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  int64_t bid = blockIdx.x;
+  int ch = (int)(bid % chunks);
+  int r = (int)(bid / chunks);
+  int64_t off = ((int64_t)r << logN) + ch * EW_CHUNK + threadIdx.x * 2;
+  const PrimeConst P = pc[r];
+  U2 av = ld2(a + off), ev = ld2(e + off), sv = ld2(sk + off);
+  st2(b + off, submod(ev.a, mulmod(av.a, sv.a, P), P.q), submod(ev.b, mulmod(av.b, sv.b, P), P.q));
+}
+
+// switching-key digit: b = -a*s + e + [r in digit] (P mod q_r) * s'_r  over all n_q+n_p rows
+__global__ void __launch_bounds__(EW_THREADS) k_ksk_combine(const PrimeConst* pc, const uint64_t* a, const uint64_t* e,
+                                                             const uint64_t* sk, const uint64_t* sp, K64 pm, uint64_t* b,
+                                                             int logN, int lo, int hi) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  int64_t bid = blockIdx.x;
+  int ch = (int)(bid % chunks);
+  int r = (int)(bid / chunks);
+  int64_t off = ((int64_t)r << logN) + ch * EW_CHUNK + threadIdx.x * 2;
+  const PrimeConst P = pc[r];
+  U2 av = ld2(a + off), ev = ld2(e + off), sv = ld2(sk + off);
+  uint64_t v0 = submod(ev.a, mulmod(av.a, sv.a, P), P.q);
+  uint64_t v1 = submod(ev.b, mulmod(av.b, sv.b, P), P.q);
+  if (r >= lo && r < hi) {
+    U2 s2 = ld2(sp + off);
+    v0 = addmod(v0, mul_shoup(s2.a, pm.v[r].a, pm.v[r].b, P.q), P.q);
+    v1 = addmod(v1, mul_shoup(s2.b, pm.v[r].a, pm.v[r].b, P.q), P.q);
+  }
+  st2(b + off, v0, v1);
+}
+
+// tmp per ciphertext: rows [v | e0 | e1 | m] x nl (NTT form); c0 = v*b + e0 + m, c1 = v*a + e1
+__global__ void __launch_bounds__(EW_THREADS) k_enc_combine(const PrimeConst* pc, const uint64_t* tmp, int64_t tmp_cs,
+                                                             const uint64_t* pk, CtV out, int logN, int nl, int nq) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  int64_t bid = blockIdx.x;
+  int ch = (int)(bid % chunks);
+  int64_t row = bid / chunks;
+  int i = (int)(row % nl);
+  int64_t ct = row / nl;
+  int64_t off = ((int64_t)i << logN) + ch * EW_CHUNK + threadIdx.x * 2;
+  const int64_t R = (int64_t)nl << logN;
+  const PrimeConst P = pc[i];
+  const uint64_t* t = tmp + ct * tmp_cs + off;
+  U2 v = ld2(t), e0 = ld2(t + R), e1 = ld2(t + 2 * R), m = ld2(t + 3 * R);
+  U2 pb = ld2(pk + off), pa = ld2(pk + ((int64_t)nq << logN) + off);
+  uint64_t* o = out.d + ct * out.cs + off;
+  st2(o, addmod(addmod(mulmod(v.a, pb.a, P), e0.a, P.q), m.a, P.q),
+      addmod(addmod(mulmod(v.b, pb.b, P), e0.b, P.q), m.b, P.q));
+  st2(o + out.ps, addmod(mulmod(v.a, pa.a, P), e1.a, P.q), addmod(mulmod(v.b, pa.b, P), e1.b, P.q));
+}
+
+// out[ct][i] = c0 + c1 s (+ c2 s^2)   (NTT domain)
+__global__ void __launch_bounds__(EW_THREADS) k_dec(const PrimeConst* pc, CtV ct, int n_poly, const uint64_t* sk,
+                                                     uint64_t* out, int logN, int nl) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  int64_t bid = blockIdx.x;
+  int ch = (int)(bid % chunks);
+  int64_t row = bid / chunks;
+  int i = (int)(row % nl);
+  int64_t b = row / nl;
+  int64_t off = ((int64_t)i << logN) + ch * EW_CHUNK + threadIdx.x * 2;
+  const PrimeConst P = pc[i];
+  const uint64_t* src = ct.d + b * ct.cs + off;
+  U2 s = ld2(sk + off);
+  U2 c0 = ld2(src), c1 = ld2(src + ct.ps);
+  uint64_t r0 = addmod(c0.a, mulmod(c1.a, s.a, P), P.q);
+  uint64_t r1 = addmod(c0.b, mulmod(c1.b, s.b, P), P.q);
+  if (n_poly == 3) {
+    U2 c2 = ld2(src + 2 * ct.ps);
+    uint64_t s2a = mulmod(s.a, s.a, P), s2b = mulmod(s.b, s.b, P);
+    r0 = addmod(r0, mulmod(c2.a, s2a, P), P.q);
+    r1 = addmod(r1, mulmod(c2.b, s2b, P), P.q);
+  }
+  st2(out + ((b * nl) << logN) + off, r0, r1);
+}
+
+// centred lift from limbs 0, 1 (limb 0 at level 0) reduced into rows 0..nl_out-1
+struct LiftC {
+  uint64_t q0inv, q0inv_sh;  // q0^-1 mod q1 and Shoup companion
+  uint64_t half_lo, half_hi; // (q0 q1 - 1) / 2 as 128 bits
+};
+__global__ void __launch_bounds__(EW_THREADS) k_lift(const PrimeConst* pc, LiftC L, const uint64_t* dec, int nl_in,
+                                                      uint64_t* out, int64_t out_cs, int nl_out, int logN) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  int64_t bid = blockIdx.x;
+  int ch = (int)(bid % chunks);
+  int64_t b = bid / chunks;
+  int c = ch * EW_CHUNK + threadIdx.x * 2;
+  const uint64_t* src = dec + ((b * nl_in) << logN) + c;
+  const uint64_t q0 = pc[0].q;
+  U2 x0 = ld2(src);
+  uint64_t xs[2] = {x0.a, x0.b}, hs[2] = {0, 0};
+  bool neg[2];
+  if (nl_in >= 2) {
+    const PrimeConst P1 = pc[1];
+    const uint64_t q1 = P1.q;
+    U2 x1 = ld2(src + ((int64_t)1 << logN));
+    uint64_t ys[2] = {x1.a, x1.b};
+    for (int u = 0; u < 2; ++u) {
+      uint64_t h = mul_shoup(submod(ys[u], reduce64(xs[u], P1), q1), L.q0inv, L.q0inv_sh, q1);
+      hs[u] = h;
+      // v = x0 + q0 h as 128 bits, compared with (q0 q1 - 1)/2
+      uint64_t lo = q0 * h, hi = mulhi64(q0, h);
+      uint64_t vlo = lo + xs[u];
+      uint64_t vhi = hi + (vlo < lo ? 1 : 0);
+      neg[u] = vhi > L.half_hi || (vhi == L.half_hi && vlo > L.half_lo);
+    }
+  } else {
+    for (int u = 0; u < 2; ++u) neg[u] = xs[u] > ((q0 - 1) >> 1);
+  }
+  for (int i = 0; i < nl_out; ++i) {
+    const PrimeConst P = pc[i];
+    uint64_t q0m = reduce64(q0, P);
+    uint64_t r[2];
+    for (int u = 0; u < 2; ++u) {
+      uint64_t v = reduce64(xs[u], P);
+      if (nl_in >= 2) {
+        uint64_t q1m = reduce64(pc[1].q, P);
+        v = addmod(v, mulmod(q0m, reduce64(hs[u], P), P), P.q);
+        if (neg[u]) v = submod(v, mulmod(q0m, q1m, P), P.q);
+      } else if (neg[u]) {
+        v = submod(v, q0m, P.q);
+      }
+      r[u] = v;
+    }
+    st2(out + b * out_cs + ((int64_t)i << logN) + c, r[0], r[1]);
+  }
+}
+
+__global__ void __launch_bounds__(EW_THREADS) k_mul_rows(const PrimeConst* pc, const uint64_t* a, const uint64_t* b,
+                                                          uint64_t* out, int logN) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  int64_t bid = blockIdx.x;
+  int ch = (int)(bid % chunks);
+  int r = (int)(bid / chunks);
+  int64_t off = ((int64_t)r << logN) + ch * EW_CHUNK + threadIdx.x * 2;
+  const PrimeConst P = pc[r];
+  U2 x = ld2(a + off), y = ld2(b + off);
+  st2(out + off, mulmod(x.a, y.a, P), mulmod(x.b, y.b, P));
+}
+
+}  // namespace
+
+// ====================================================================== launchers
+#define CHUNKS(g) ((g).N / EW_CHUNK)
+#define LAUNCH(kern, nblk, s, ...) hipLaunchKernelGGL(kern, dim3(grid_of(nblk)), dim3(EW_THREADS), 0, s, __VA_ARGS__)
+
+void k_add_launch(const Geo& g, const DevTables& t, CtV a, CtV b, CtV out, int64_t count, int n_poly, int nl, bool sub,
+                  hipStream_t s) {
+  int64_t n = count * n_poly * nl * CHUNKS(g);
+  if (n) LAUNCH(k_add, n, s, t.pc, a, b, out, g.logN, nl, n_poly, sub ? 1 : 0);
+}
+void k_tensor_launch(const Geo& g, const DevTables& t, CtV a, CtV b, CtV out, int64_t count, int nl, bool acc,
+                     hipStream_t s) {
+  int64_t n = count * nl * CHUNKS(g);
+  if (n) LAUNCH(k_tensor, n, s, t.pc, a, b, out, g.logN, nl, acc ? 1 : 0);
+}
+void k_tensor_reduce_launch(const Geo& g, const DevTables& t, CtV a, CtV b, int64_t count, CtV acc, int nl,
+                            bool accumulate, hipStream_t s) {
+  int64_t n = (int64_t)nl * CHUNKS(g);
+  LAUNCH(k_tensor_reduce, n, s, t.pc, a, b, count, acc, g.logN, nl, accumulate ? 1 : 0);
+}
+void k_mul_pt_launch(const Geo& g, const DevTables& t, CtV a, const uint64_t* pt, CtV out, int64_t count, int n_poly,
+                     int nl, hipStream_t s) {
+  int64_t n = count * n_poly * nl * CHUNKS(g);
+  if (n) LAUNCH(k_mul_pt, n, s, t.pc, a, pt, out, g.logN, nl, n_poly);
+}
+void k_add_pt_launch(const Geo& g, const DevTables& t, CtV a, const uint64_t* pt, CtV out, int64_t count, int nl,
+                     hipStream_t s) {
+  int64_t n = count * nl * CHUNKS(g);
+  if (n) LAUNCH(k_add_pt, n, s, t.pc, a, pt, out, g.logN, nl);
+}
+void k_mul_scalar_launch(const Geo& g, const DevTables& t, CtV a, CtV out, int64_t count, int n_poly, int nl,
+                         const uint64_t* k_res, hipStream_t s) {
+  K64 k;
+  for (int i = 0; i < nl; ++i) k.v[i] = U2{k_res[2 * i], k_res[2 * i + 1]};
+  int64_t n = count * n_poly * nl * CHUNKS(g);
+  if (n) LAUNCH(k_mul_scalar, n, s, t.pc, a, out, g.logN, nl, n_poly, k);
+}
+void k_copy_launch(const Geo& g, CtV a, CtV out, int64_t count, int n_poly, int nl, hipStream_t s) {
+  int64_t n = count * n_poly * nl * CHUNKS(g);
+  if (n) LAUNCH(k_copy, n, s, a, out, g.logN, nl, n_poly);
+}
+void k_automorph_launch(const Geo& g, CtV a, CtV out, int64_t count, int n_poly, int nl, uint64_t galois,
+                        hipStream_t s) {
+  int64_t n = count * n_poly * nl * CHUNKS(g);
+  if (n) LAUNCH(k_automorph, n, s, a, out, g.logN, nl, n_poly, galois);
+}
+void k_rescale_spread_launch(const Geo& g, const DevTables& t, const uint64_t* last, uint64_t* spread, int64_t rows,
+                             int level, hipStream_t s) {
+  int64_t n = rows * CHUNKS(g);
+  if (n) LAUNCH(k_rescale_spread, n, s, t.pc, t.rescale_q, last, spread, g.logN, level, g.n_q);
+}
+void k_rescale_combine_launch(const Geo& g, const DevTables& t, CtV in, const uint64_t* spread, CtV out, int64_t count,
+                              int n_poly, int level, hipStream_t s) {
+  int64_t n = count * n_poly * level * CHUNKS(g);
+  if (n) LAUNCH(k_rescale_combine, n, s, t.pc, t.rescale, in, spread, out, g.logN, level, n_poly, g.n_q);
+}
+void k_modup_launch(const Geo& g, const DevTables& t, const uint64_t* dcoef, int64_t count, int level, int digit,
+                    uint64_t* ext, int64_t ext_cs, hipStream_t s) {
+  int nl = level + 1;
+  int lo = digit * g.alpha;
+  int sz = nl - lo < g.alpha ? nl - lo : g.alpha;
+  const uint64_t* tab = t.modup + 2 * (int64_t)((level * g.dnum + digit) * g.mu_stride);
+  int64_t n = count * CHUNKS(g);
+  if (n) LAUNCH(k_modup, n, s, t.pc, tab, dcoef, ext, ext_cs, g.logN, level, lo, sz, g.n_q, g.n_p, g.alpha);
+}
+void k_ks_inner_launch(const Geo& g, const DevTables& t, CtV d, const uint64_t* ext, int64_t ext_cs, int64_t ext_ds,
+                       const uint64_t* key, uint64_t* acc, int64_t count, int level, hipStream_t s) {
+  int nx = level + 1 + g.n_p;
+  int64_t n = count * nx * CHUNKS(g);
+  if (n) LAUNCH(k_ks_inner, n, s, t.pc, d, ext, ext_cs, ext_ds, key, acc, g.logN, level, g.n_q, g.n_p, g.alpha);
+}
+void k_moddown_conv_launch(const Geo& g, const DevTables& t, const uint64_t* acc, uint64_t* conv, int64_t count,
+                           int level, hipStream_t s) {
+  int64_t n = count * 2 * CHUNKS(g);
+  if (n) LAUNCH(k_moddown_conv, n, s, t.pc, t.moddown, acc, conv, g.logN, level, g.n_q, g.n_p);
+}
+void k_ks_combine_launch(const Geo& g, const DevTables& t, const uint64_t* acc, const uint64_t* conv, CtV base0,
+                         CtV base1, bool has_base1, CtV out, int64_t count, int level, hipStream_t s) {
+  const uint64_t* pinv = t.moddown + 2 * g.n_p + 2 * (int64_t)g.n_q * g.n_p;
+  int64_t n = count * 2 * (level + 1) * CHUNKS(g);
+  if (n)
+    LAUNCH(k_ks_combine, n, s, t.pc, pinv, acc, conv, base0, base1, has_base1 ? 1 : 0, out, g.logN, level, g.n_p);
+}
+void k_sample_small_launch(uint64_t seed, uint64_t purpose, uint64_t obj_first, int64_t count, int N, int kind,
+                           int64_t* out, hipStream_t s) {
+  int64_t threads = count * (N / 8);
+  int64_t n = (threads + EW_THREADS - 1) / EW_THREADS;
+  if (n) LAUNCH(k_sample_small, n, s, seed, purpose, obj_first, count, N, kind, out);
+}
+void k_small_to_rows_launch(const Geo& g, const DevTables& t, const int64_t* in, int64_t in_stride, int64_t count,
+                            uint64_t* rows, int64_t row_cs, int nrows, int, int, hipStream_t s) {
+  int64_t n = count * nrows * CHUNKS(g);
+  if (n) LAUNCH(k_small_to_rows, n, s, t.pc, in, in_stride, rows, row_cs, g.logN, nrows);
+}
+void k_sample_uniform_launch(const Geo& g, const DevTables& t, uint64_t seed, uint64_t purpose, uint64_t obj,
+                             uint64_t* rows, int nrows, const int* pidx_host, hipStream_t s) {
+  I64 p;
+  for (int i = 0; i < nrows; ++i) p.v[i] = pidx_host[i];
+  int64_t threads = (int64_t)nrows * (g.N / 4);
+  int64_t n = (threads + EW_THREADS - 1) / EW_THREADS;
+  if (n) LAUNCH(k_sample_uniform, n, s, t.pc, seed, purpose, obj, rows, g.N, nrows, p);
+}
+void k_pk_combine_launch(const Geo& g, const DevTables& t, const uint64_t* a, const uint64_t* e, const uint64_t* sk,
+                         uint64_t* b, int nrows, hipStream_t s) {
+  int64_t n = (int64_t)nrows * CHUNKS(g);
+  if (n) LAUNCH(k_pk_combine, n, s, t.pc, a, e, sk, b, g.logN);
+}
+void k_ksk_combine_launch(const Geo& g, const DevTables& t, const uint64_t* a, const uint64_t* e, const uint64_t* sk,
+                          const uint64_t* sprime, const uint64_t* pmod_host, uint64_t* b, int digit, hipStream_t s) {
+  K64 pm;
+  for (int i = 0; i < g.n_q; ++i) pm.v[i] = U2{pmod_host[2 * i], pmod_host[2 * i + 1]};
+  int lo = digit * g.alpha, hi = lo + g.alpha < g.n_q ? lo + g.alpha : g.n_q;
+  int64_t n = (int64_t)g.nqp * CHUNKS(g);
+  LAUNCH(k_ksk_combine, n, s, t.pc, a, e, sk, sprime, pm, b, g.logN, lo, hi);
+}
+void k_enc_combine_launch(const Geo& g, const DevTables& t, const uint64_t* tmp, int64_t tmp_cs, const uint64_t* pk,
+                          CtV out, int64_t count, int nl, hipStream_t s) {
+  int64_t n = count * nl * CHUNKS(g);
+  if (n) LAUNCH(k_enc_combine, n, s, t.pc, tmp, tmp_cs, pk, out, g.logN, nl, g.n_q);
+}
+void k_dec_launch(const Geo& g, const DevTables& t, CtV ct, int n_poly, const uint64_t* sk, uint64_t* out,
+                  int64_t count, int nl, hipStream_t s) {
+  int64_t n = count * nl * CHUNKS(g);
+  if (n) LAUNCH(k_dec, n, s, t.pc, ct, n_poly, sk, out, g.logN, nl);
+}
+void k_lift_launch(const Geo& g, const DevTables& t, const uint64_t lc[4], const uint64_t* dec, int nl_in, uint64_t* out,
+                   int64_t out_cs, int nl_out, int64_t count, hipStream_t s) {
+  LiftC L{lc[0], lc[1], lc[2], lc[3]};
+  int64_t n = count * CHUNKS(g);
+  if (n) LAUNCH(k_lift, n, s, t.pc, L, dec, nl_in, out, out_cs, nl_out, g.logN);
+}
+void k_mul_rows_launch(const Geo& g, const DevTables& t, const uint64_t* a, const uint64_t* b, uint64_t* out,
+                       int nrows, hipStream_t s) {
+  int64_t n = (int64_t)nrows * CHUNKS(g);
+  if (n) LAUNCH(k_mul_rows, n, s, t.pc, a, b, out, g.logN);
+}

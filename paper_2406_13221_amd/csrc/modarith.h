@@ -1,0 +1,57 @@
+// Device modular arithmetic for primes q < 2^61 (gfx950, 64-bit VALU sequences).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+// Per-prime constants used by the kernels.
+struct PrimeConst {
+  uint64_t q;
+  uint64_t two_q;
+  uint64_t mu;        // floor(2^(2k) / q), k = bit length of q (Barrett)
+  uint64_t rdiv;      // floor(2^64 / q) (reduction of any 64-bit value)
+  uint64_t r64;       // 2^64 mod q
+  uint64_t r64_sh;    // Shoup companion of r64
+  uint64_t ninv;      // N^-1 mod q
+  uint64_t ninv_sh;
+  int k;              // bit length of q
+  int pad;
+};
+
+__device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
+
+__device__ __forceinline__ uint64_t csub(uint64_t a, uint64_t q) { return a >= q ? a - q : a; }
+
+// a * w mod q in [0, 2q) for any a < 2^64, w < q, wsh = floor(w * 2^64 / q)   (Shoup)
+__device__ __forceinline__ uint64_t mul_shoup_lazy(uint64_t a, uint64_t w, uint64_t wsh, uint64_t q) {
+  return a * w - mulhi64(a, wsh) * q;
+}
+__device__ __forceinline__ uint64_t mul_shoup(uint64_t a, uint64_t w, uint64_t wsh, uint64_t q) {
+  return csub(mul_shoup_lazy(a, w, wsh, q), q);
+}
+
+// any 64-bit value mod q
+__device__ __forceinline__ uint64_t reduce64(uint64_t a, const PrimeConst& p) {
+  return csub(a - mulhi64(a, p.rdiv) * p.q, p.q);
+}
+
+// a * b mod q for a, b < q (Barrett on the 128-bit product)
+__device__ __forceinline__ uint64_t mulmod(uint64_t a, uint64_t b, const PrimeConst& p) {
+  uint64_t lo = a * b, hi = mulhi64(a, b);
+  int k = p.k;
+  uint64_t x1 = (hi << (65 - k)) | (lo >> (k - 1));
+  uint64_t plo = x1 * p.mu, phi = mulhi64(x1, p.mu);
+  uint64_t q3 = (phi << (63 - k)) | (plo >> (k + 1));
+  uint64_t r = lo - q3 * p.q;
+  r = csub(r, p.two_q);
+  return csub(r, p.q);
+}
+
+__device__ __forceinline__ uint64_t addmod(uint64_t a, uint64_t b, uint64_t q) { return csub(a + b, q); }
+__device__ __forceinline__ uint64_t submod(uint64_t a, uint64_t b, uint64_t q) { return a >= b ? a - b : a + q - b; }
+__device__ __forceinline__ uint64_t negmod(uint64_t a, uint64_t q) { return a == 0 ? 0 : q - a; }
+
+// signed 64-bit integer -> residue
+__device__ __forceinline__ uint64_t from_signed(int64_t v, const PrimeConst& p) {
+  uint64_t m = reduce64(v < 0 ? (uint64_t)(-(v + 1)) + 1 : (uint64_t)v, p);
+  return v < 0 ? negmod(m, p.q) : m;
+}

@@ -1,0 +1,342 @@
+// One encrypted quadratic-gradient NAG iteration (paper: Algorithm 1, the
+// full-batch form of section 3.3, and steps 4-6 of the pipeline in section 4.3).
+//
+// The blocks are processed in lock-step chunks of `batch` ciphertexts, so
+// every launch covers batch x parts x limbs rows; each switching key is read
+// once per chunk instead of once per block.  The circuit is first run "dry"
+// on the host (levels, scales, key availability, constants) and only then
+// enqueued, so every error is reported before any device work starts.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "ops.h"
+
+namespace {
+
+struct Ct {
+  uint64_t* d;
+  int64_t cs, ps;
+  int n_poly, level;
+  double scale;
+  int64_t count;
+  CtV v() const { return CtV{d, count > 1 ? cs : 0, ps}; }
+};
+
+struct Fail {
+  int code;
+};
+
+struct Exec {
+  heqg_ctx* c;
+  const heqg_keys* k;
+  hipStream_t s;
+  bool dry;
+  int64_t B;          // ciphertexts per chunk
+  int nl_top;         // rows per part in a slot
+  std::vector<uint64_t*> slots;
+  size_t next = 0;
+  uint64_t* ks_ws;
+  uint64_t* rs_ws;
+
+  int N() const { return c->g.N; }
+  double q(int l) const { return (double)c->primes[l]; }
+
+  [[noreturn]] void fail(int code, const std::string& m) {
+    set_err("nag_qg_step: " + m);
+    throw Fail{code};
+  }
+
+  Ct slot(int n_poly, int level, double scale, int64_t count) {
+    if (next >= slots.size()) fail(HEQG_ERR_ARG, "internal: out of workspace slots");
+    uint64_t* d = slots[next++];
+    return Ct{d, (int64_t)3 * nl_top * N(), (int64_t)nl_top * N(), n_poly, level, scale, count};
+  }
+  void reset(size_t mark) { next = mark; }
+
+  static Ct drop(const Ct& a, int level) {
+    Ct r = a;
+    r.level = level;
+    return r;
+  }
+  void align(Ct& a, Ct& b) {
+    int lv = std::min(a.level, b.level);
+    a = drop(a, lv);
+    b = drop(b, lv);
+  }
+  void check_scale(double a, double b, const char* what) {
+    if (std::fabs(a / b - 1.0) > std::ldexp(1.0, -20)) fail(HEQG_ERR_SCALE, std::string("scale mismatch in ") + what);
+  }
+
+  Ct add(Ct a, Ct b) {
+    align(a, b);
+    check_scale(a.scale, b.scale, "add");
+    int64_t cnt = std::max(a.count, b.count);
+    Ct o = slot(a.n_poly, a.level, a.scale, cnt);
+    if (!dry) k_add_launch(c->g, c->t, a.v(), b.v(), o.v(), cnt, a.n_poly, a.level + 1, false, s);
+    return o;
+  }
+  Ct tensor(Ct a, Ct b) {
+    align(a, b);
+    int64_t cnt = std::max(a.count, b.count);
+    Ct o = slot(3, a.level, a.scale * b.scale, cnt);
+    if (!dry) k_tensor_launch(c->g, c->t, a.v(), b.v(), o.v(), cnt, a.level + 1, false, s);
+    return o;
+  }
+  Ct relin(Ct a) {
+    Ct o = slot(2, a.level, a.scale, a.count);
+    if (!dry) ops::relin(c, k, a.v(), o.v(), a.count, a.level, ks_ws, s);
+    return o;
+  }
+  Ct rescale(Ct a) {
+    if (a.level < 1) fail(HEQG_ERR_LEVEL, "level exhausted");
+    Ct o = slot(a.n_poly, a.level - 1, a.scale / q(a.level), a.count);
+    if (!dry) ops::rescale(c, a.v(), o.v(), a.count, a.n_poly, a.level, rs_ws, s);
+    return o;
+  }
+  Ct hmult_rs(Ct a, Ct b) {  // Rescale(Relin(Tensor(a, b)))
+    size_t m = next;
+    Ct t = tensor(a, b);
+    Ct r = relin(t);
+    Ct o = rescale(r);
+    // keep only the result: move it to the first freed slot
+    if (!dry) std::swap(slots[m], slots[next - 1]);
+    Ct res = o;
+    res.d = slots[m];
+    reset(m + 1);
+    return res;
+  }
+  Ct rotate(Ct a, int step) {
+    const int64_t half = N() / 2;
+    int64_t r = ((int64_t)step % half + half) % half;
+    uint64_t t = h_pow(5, (uint64_t)r, 2 * (uint64_t)N());
+    if (t != 1 && !ops::rot_key(k, t)) fail(HEQG_ERR_KEY, "no rotation key for step " + std::to_string(step));
+    Ct o = slot(2, a.level, a.scale, a.count);
+    if (!dry) {
+      int rc = ops::rotate(c, k, a.v(), o.v(), a.count, a.level, t, ks_ws, s);
+      if (rc) fail(rc, "rotate");
+    }
+    return o;
+  }
+  Ct mul_pt(Ct a, const uint64_t* pt, double pt_scale) {
+    Ct o = slot(a.n_poly, a.level, a.scale * pt_scale, a.count);
+    if (!dry) k_mul_pt_launch(c->g, c->t, a.v(), pt, o.v(), a.count, a.n_poly, a.level + 1, s);
+    return o;
+  }
+  Ct add_pt(Ct a, const uint64_t* pt, double pt_scale) {
+    check_scale(a.scale, pt_scale, "add_pt");
+    Ct o = slot(2, a.level, a.scale, a.count);
+    if (!dry) k_add_pt_launch(c->g, c->t, a.v(), pt, o.v(), a.count, a.level + 1, s);
+    return o;
+  }
+  Ct mul_const(Ct a, double cst, double target) {
+    if (a.level < 1) fail(HEQG_ERR_LEVEL, "level exhausted");
+    int64_t kint;
+    if (ops::const_int(c, cst, target, a.level, a.scale, &kint)) fail(HEQG_ERR_OVERFLOW, "constant overflow");
+    Ct o = slot(a.n_poly, a.level - 1, target, a.count);
+    if (!dry) ops::mul_const(c, a.v(), a.count, a.n_poly, a.level, a.scale, cst, target, o.v(), rs_ws, s);
+    return o;
+  }
+  // x <- x + Rot(x, step), reusing x's slot (x must be the most recent allocation)
+  Ct add_rot(Ct x, int step) {
+    size_t mk = next;
+    Ct r = rotate(x, step);
+    Ct nx = add(x, r);
+    if (!dry) std::swap(slots[mk - 1], slots[next - 1]);
+    nx.d = slots[mk - 1];
+    reset(mk);
+    return nx;
+  }
+  Ct refresh(Ct a, int target, uint64_t seed, uint64_t obj) {
+    Ct o = slot(2, target, a.scale, a.count);
+    if (!dry) ops::refresh(c, k, a.v(), a.count, a.level, target, seed, obj, o.v(), ks_ws, s);
+    return o;
+  }
+};
+
+int n_terms(int degree) { return (degree + 1) / 2; }
+
+// masked sigma~ on column 0 of u: returns p = 1 - sigma~(m) in column 0, 0 elsewhere
+Ct sigmoid_block(Exec& X, const Ct& u, const heqg_sigmoid* sg) {
+  const size_t plane = (size_t)(sg->mask_level + 1) * X.N();
+  const int nt = n_terms(sg->degree);
+  auto M = [&](int i) { return sg->masks + i * plane; };
+  if (u.level > sg->mask_level) X.fail(HEQG_ERR_ARG, "mask plaintexts below the margin level");
+  size_t mark = X.next;
+  Ct a1 = X.rescale(X.mul_pt(u, M(0), sg->mask_scales[0]));
+  Ct s = X.hmult_rs(u, u);
+  Ct s4{};
+  if (sg->degree >= 5) s4 = X.hmult_rs(s, s);
+  Ct b3 = X.rescale(X.mul_pt(u, M(1), sg->mask_scales[1]));
+  Ct t3 = X.hmult_rs(b3, s);
+  Ct p = X.add(a1, t3);
+  if (sg->degree >= 5) {
+    Ct b5 = X.rescale(X.mul_pt(u, M(2), sg->mask_scales[2]));
+    Ct t5 = X.hmult_rs(b5, s4);
+    p = X.add(p, t5);
+  }
+  if (sg->degree >= 7) {
+    Ct b7 = X.rescale(X.mul_pt(u, M(3), sg->mask_scales[3]));
+    Ct t7a = X.hmult_rs(b7, s);
+    Ct t7 = X.hmult_rs(t7a, s4);
+    p = X.add(p, t7);
+  }
+  if (p.level > sg->mask_level) X.fail(HEQG_ERR_ARG, "mask level");
+  Ct r = X.add_pt(p, M(nt), sg->mask_scales[nt]);
+  // keep r only
+  if (!X.dry) std::swap(X.slots[mark], X.slots[X.next - 1]);
+  r.d = X.slots[mark];
+  X.reset(mark + 1);
+  return r;
+}
+
+struct Io {
+  Ct Z;  // all blocks
+  Ct Bbar, W, V;
+};
+
+// the whole iteration; returns (W', V') in slots, updates st
+void circuit(Exec& X, const Io& io, const heqg_sigmoid* sg, heqg_nag_state* st, int64_t n_blocks, Ct& Wn, Ct& Vn) {
+  const int g = st->g_cols, m = st->m_rows;
+  int lg = 0, lm = 0;
+  while ((1 << lg) < g) ++lg;
+  while ((1 << lm) < m) ++lm;
+  // acc lives in slot 0 for the whole iteration
+  Ct acc{};
+  bool have_acc = false;
+  X.reset(0);
+  Ct accs = X.slot(3, 0, 0.0, 1);
+  size_t base = X.next;
+  for (int64_t b0 = 0; b0 < n_blocks; b0 += X.B) {
+    const int64_t cnt = std::min<int64_t>(X.B, n_blocks - b0);
+    X.reset(base);
+    Ct Zc = io.Z;
+    Zc.d = io.Z.d + b0 * io.Z.cs;
+    Zc.count = cnt;
+    Ct u = X.hmult_rs(Zc, io.W);
+    for (int k = 0; k < lg; ++k) u = X.add_rot(u, 1 << k);
+    Ct p = sigmoid_block(X, u, sg);
+    for (int k = 0; k < lg; ++k) p = X.add_rot(p, -(1 << k));
+    Ct Zd = Exec::drop(Zc, p.level);
+    double sc = Zd.scale * p.scale;
+    if (have_acc) {
+      if (acc.level != p.level) X.fail(HEQG_ERR_ARG, "internal: accumulator level");
+      X.check_scale(acc.scale, sc, "gradient accumulation");
+    } else {
+      acc = accs;
+      acc.level = p.level;
+      acc.scale = sc;
+      acc.n_poly = 3;
+    }
+    if (!X.dry) k_tensor_reduce_launch(X.c->g, X.c->t, Zd.v(), p.v(), cnt, acc.v(), p.level + 1, have_acc, X.s);
+    have_acc = true;
+  }
+  X.reset(base);
+  Ct gr = X.rescale(X.relin(acc));
+  for (int k = 0; k < lm; ++k) gr = X.add_rot(gr, g << k);
+  const int t = st->t;
+  st->refreshed_gr = 0;
+  if (std::min(io.Bbar.level - 1, gr.level) < 1) {
+    gr = X.refresh(gr, X.c->g.n_q - 1, st->refresh_seed, ((uint64_t)t << 4) | 2);
+    st->refreshed_gr = 1;
+  }
+  const double eta = (1.0 - st->alpha0) / st->alpha1;
+  const double lr = st->lr_max - (st->lr_max - st->lr_min) * std::pow((double)t / st->T, st->gamma);
+  const double s_g = X.c->delta;
+  const int lt = std::min(io.Bbar.level - 1, gr.level);
+  const double s_bv = s_g * X.q(lt) / gr.scale;
+  Ct Bv = X.mul_const(io.Bbar, lr, s_bv);
+  Ct Bw = X.mul_const(io.Bbar, lr * (1.0 - eta), s_bv);
+  Ct Gv = X.hmult_rs(Bv, gr);
+  Ct Gw = X.hmult_rs(Bw, gr);
+  Vn = X.add(X.mul_const(io.W, 1.0, s_g), Gv);
+  Wn = X.add(X.add(X.mul_const(io.W, 1.0 - eta, s_g), X.mul_const(io.V, eta, s_g)), Gw);
+  st->eta = eta;
+  st->lr = lr;
+}
+
+size_t slot_words(const heqg_ctx* c, int64_t B) { return (size_t)B * 3 * c->g.n_q * c->g.N; }
+const int kSlots = 28;
+
+}  // namespace
+
+extern "C" size_t heqg_nag_ws_bytes(const heqg_ctx* c, int batch, int degree) {
+  (void)degree;
+  if (!c || batch < 1) return 0;
+  const int top = c->g.n_q - 1;
+  size_t ks = std::max(ops::rot_ws_words(c, batch, top),
+                       ops::enc_ws_words(c, 1) + (size_t)c->g.n_q * c->g.N);
+  size_t rs = 2 * slot_words(c, batch);
+  return 8 * (kSlots * slot_words(c, batch) + ks + rs);
+}
+
+extern "C" int heqg_nag_qg_step(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch* Z, const heqg_ct* Bbar,
+                                heqg_ct* W, heqg_ct* V, const heqg_sigmoid* sg, heqg_nag_state* st, int batch,
+                                void* ws, size_t ws_bytes, hipStream_t s) {
+  if (!c || !k || !Z || !Bbar || !W || !V || !sg || !st || !Z->data || !Bbar->data || !W->data || !V->data ||
+      !sg->masks || !sg->mask_scales) {
+    set_err("nag_qg_step: null argument");
+    return HEQG_ERR_ARG;
+  }
+  if (batch < 1 || Z->count < 1 || Z->n_poly != 2 || Bbar->n_poly != 2 || W->n_poly != 2 || V->n_poly != 2 ||
+      (sg->degree != 3 && sg->degree != 5 && sg->degree != 7) || st->m_rows < 1 || st->g_cols < 1 ||
+      (int64_t)st->m_rows * st->g_cols != c->g.N / 2 || (st->g_cols & (st->g_cols - 1)) ||
+      (st->m_rows & (st->m_rows - 1)) || sg->mask_level < 0 || sg->mask_level >= c->g.n_q) {
+    set_err("nag_qg_step: bad shapes (m_rows*g_cols must equal N/2, powers of two; degree 3, 5 or 7)");
+    return HEQG_ERR_ARG;
+  }
+  for (int lv : {Z->level, Bbar->level, W->level, V->level})
+    if (lv < 0 || lv >= c->g.n_q) {
+      set_err("nag_qg_step: level out of range");
+      return HEQG_ERR_ARG;
+    }
+  if (Z->count > 1 && Z->stride < (int64_t)2 * (Z->level + 1) * c->g.N) {
+    set_err("nag_qg_step: Z stride too small");
+    return HEQG_ERR_ARG;
+  }
+  if (!ws || ws_bytes < heqg_nag_ws_bytes(c, batch, sg->degree)) {
+    set_err("nag_qg_step: workspace too small");
+    return HEQG_ERR_ARG;
+  }
+  const int N = c->g.N;
+  Exec X{c, k, s, true, batch, c->g.n_q};
+  uint64_t* w = static_cast<uint64_t*>(ws);
+  for (int i = 0; i < kSlots; ++i) X.slots.push_back(w + (size_t)i * slot_words(c, batch));
+  X.ks_ws = w + (size_t)kSlots * slot_words(c, batch);
+  X.rs_ws = X.ks_ws + std::max(ops::rot_ws_words(c, batch, c->g.n_q - 1),
+                               ops::enc_ws_words(c, 1) + (size_t)c->g.n_q * N);
+  Io io;
+  io.Z = Ct{Z->data, Z->stride, (int64_t)(Z->level + 1) * N, 2, Z->level, Z->scale, Z->count};
+  io.Bbar = Ct{Bbar->data, 0, (int64_t)(Bbar->level + 1) * N, 2, Bbar->level, Bbar->scale, 1};
+  io.W = Ct{W->data, 0, (int64_t)(W->level + 1) * N, 2, W->level, W->scale, 1};
+  io.V = Ct{V->data, 0, (int64_t)(V->level + 1) * N, 2, V->level, V->scale, 1};
+  heqg_nag_state st_dry = *st;
+  Ct Wn{}, Vn{};
+  try {
+    circuit(X, io, sg, &st_dry, Z->count, Wn, Vn);   // plan: validates everything, launches nothing
+    X.dry = false;
+    heqg_nag_state st_run = *st;
+    circuit(X, io, sg, &st_run, Z->count, Wn, Vn);
+    // W', V' back into the caller's buffers, compact [2][level+1][N]
+    k_copy_launch(c->g, Vn.v(), CtV{V->data, 0, (int64_t)(Vn.level + 1) * N}, 1, 2, Vn.level + 1, s);
+    k_copy_launch(c->g, Wn.v(), CtV{W->data, 0, (int64_t)(Wn.level + 1) * N}, 1, 2, Wn.level + 1, s);
+    W->level = Wn.level;
+    W->scale = Wn.scale;
+    V->level = Vn.level;
+    V->scale = Vn.scale;
+    st->eta = st_run.eta;
+    st->lr = st_run.lr;
+    st->refreshed_gr = st_run.refreshed_gr;
+    st->t += 1;
+    st->alpha0 = st_run.alpha1;
+    st->alpha1 = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * st_run.alpha1 * st_run.alpha1));
+  } catch (const Fail& f) {
+    return f.code;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_err(std::string("nag_qg_step: ") + hipGetErrorString(e));
+    return HEQG_ERR_DEVICE;
+  }
+  return HEQG_OK;
+}

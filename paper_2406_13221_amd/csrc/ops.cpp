@@ -1,0 +1,273 @@
+// Device pipelines of the scheme operations: key generation, encryption,
+// decryption, refresh, hybrid key switching, rotation, rescale, cMul.
+#include "ops.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace ops {
+
+int ntt(const heqg_ctx* c, const RowSet& rs, bool inverse, hipStream_t s) {
+  if (launch_ntt(c->t, c->g.logN, rs, inverse, s) != 0) {
+    set_err("ntt: unsupported ring degree");
+    return HEQG_ERR_UNSUPPORTED;
+  }
+  return HEQG_OK;
+}
+
+RowSet rows(uint64_t* data, int64_t na, int64_t sa, int64_t nb, int64_t sb, int ni, const int* pidx) {
+  RowSet r{};
+  r.data = data;
+  r.na = na;
+  r.sa = sa;
+  r.nb = nb;
+  r.sb = sb;
+  r.ni = ni;
+  for (int i = 0; i < ni; ++i) r.pidx[i] = pidx[i];
+  return r;
+}
+
+RowSet rows_q(uint64_t* data, int64_t na, int64_t sa, int64_t nb, int64_t sb, int ni, int first) {
+  RowSet r{};
+  r.data = data;
+  r.na = na;
+  r.sa = sa;
+  r.nb = nb;
+  r.sb = sb;
+  r.ni = ni;
+  for (int i = 0; i < ni; ++i) r.pidx[i] = first + i;
+  return r;
+}
+
+// ------------------------------------------------------------------ keys
+static void make_ksk(heqg_ctx* c, heqg_keys* k, uint64_t seed, uint64_t tag, const uint64_t* sp, uint64_t* dest,
+                     int64_t* small, uint64_t* erows, hipStream_t s) {
+  const int N = c->g.N, nqp = c->g.nqp;
+  std::vector<int> pidx(nqp);
+  for (int i = 0; i < nqp; ++i) pidx[i] = i;
+  for (int j = 0; j < c->g.dnum; ++j) {
+    uint64_t obj = (tag << 8) | (uint64_t)j;
+    k_sample_small_launch(seed, PUR_KSK_E, obj, 1, N, 1, small, s);
+    k_small_to_rows_launch(c->g, c->t, small, N, 1, erows, 0, nqp, 0, 0, s);
+    ntt(c, rows_q(erows, 1, 0, 1, 0, nqp), false, s);
+    uint64_t* b = dest + (size_t)(2 * j) * nqp * N;
+    uint64_t* a = b + (size_t)nqp * N;
+    k_sample_uniform_launch(c->g, c->t, seed, PUR_KSK_A, obj, a, nqp, pidx.data(), s);
+    k_ksk_combine_launch(c->g, c->t, a, erows, k->sk, sp, c->pmod.data(), b, j, s);
+  }
+}
+
+int keygen(heqg_ctx* c, heqg_keys* k, uint64_t seed, uint8_t* ws, hipStream_t s) {
+  const int N = c->g.N, nq = c->g.n_q, nqp = c->g.nqp;
+  int64_t* small = reinterpret_cast<int64_t*>(ws);
+  uint64_t* erows = reinterpret_cast<uint64_t*>(ws) + N;
+  uint64_t* sp = erows + (size_t)nqp * N;
+  // s: ternary, stream (seed, SK, 0), NTT over every prime
+  k_sample_small_launch(seed, PUR_SK, 0, 1, N, 0, small, s);
+  k_small_to_rows_launch(c->g, c->t, small, N, 1, k->sk, 0, nqp, 0, 0, s);
+  ntt(c, rows_q(k->sk, 1, 0, 1, 0, nqp), false, s);
+  // pk = (-a s + e, a) over Q
+  k_sample_small_launch(seed, PUR_PK_E, 0, 1, N, 1, small, s);
+  k_small_to_rows_launch(c->g, c->t, small, N, 1, erows, 0, nq, 0, 0, s);
+  ntt(c, rows_q(erows, 1, 0, 1, 0, nq), false, s);
+  std::vector<int> pidx(nqp);
+  for (int i = 0; i < nqp; ++i) pidx[i] = i;
+  uint64_t* pa = k->pk + (size_t)nq * N;
+  k_sample_uniform_launch(c->g, c->t, seed, PUR_PK_A, 0, pa, nq, pidx.data(), s);
+  k_pk_combine_launch(c->g, c->t, pa, erows, k->sk, k->pk, nq, s);
+  // relinearisation key: s' = s^2
+  k_mul_rows_launch(c->g, c->t, k->sk, k->sk, sp, nq, s);
+  make_ksk(c, k, seed, 0, sp, k->rlk, small, erows, s);
+  // rotation keys: s' = s(X^t), the NTT-domain permutation of s
+  for (size_t r = 0; r < k->galois.size(); ++r) {
+    k_automorph_launch(c->g, CtV{k->sk, 0, 0}, CtV{sp, 0, 0}, 1, 1, nq, k->galois[r], s);
+    make_ksk(c, k, seed, k->galois[r], sp, k->rot + r * k->key_words, small, erows, s);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_err(std::string("keygen: ") + hipGetErrorString(e));
+    return HEQG_ERR_DEVICE;
+  }
+  return HEQG_OK;
+}
+
+// ------------------------------------------------------------------ encryption
+size_t enc_ws_words(const heqg_ctx* c, int64_t count) {
+  return (size_t)count * (3 + 4 * (size_t)c->g.n_q) * c->g.N;
+}
+
+// ws: small [3][count][N] int64, then tmp [count][4][nl][N] (v, e0, e1, m rows).
+// When coeffs is null the caller has already written the message rows (coefficient form) to tmp part 3.
+static void enc_core(heqg_ctx* c, const heqg_keys* k, const int64_t* coeffs, uint64_t seed, uint64_t obj_first,
+                     CtV out, int64_t count, int level, uint64_t* ws, hipStream_t s) {
+  const int N = c->g.N, nl = level + 1;
+  int64_t* small = reinterpret_cast<int64_t*>(ws);
+  uint64_t* tmp = ws + 3 * (size_t)count * N;
+  const int64_t tcs = (int64_t)4 * nl * N;
+  k_sample_small_launch(seed, PUR_ENC_V, obj_first, count, N, 0, small, s);
+  k_sample_small_launch(seed, PUR_ENC_E0, obj_first, count, N, 1, small + count * N, s);
+  k_sample_small_launch(seed, PUR_ENC_E1, obj_first, count, N, 1, small + 2 * count * N, s);
+  for (int part = 0; part < 3; ++part)
+    k_small_to_rows_launch(c->g, c->t, small + part * count * N, N, count, tmp + (size_t)part * nl * N, tcs, nl, 0, 0,
+                           s);
+  if (coeffs) k_small_to_rows_launch(c->g, c->t, coeffs, N, count, tmp + (size_t)3 * nl * N, tcs, nl, 0, 0, s);
+  ntt(c, rows_q(tmp, count, tcs, 4, (int64_t)nl * N, nl), false, s);
+  k_enc_combine_launch(c->g, c->t, tmp, tcs, k->pk, out, count, nl, s);
+}
+
+int encrypt(heqg_ctx* c, const heqg_keys* k, const int64_t* coeffs, const uint64_t*, int, uint64_t seed,
+            uint64_t obj_first, CtV out, int64_t count, int level, uint64_t* ws, hipStream_t s) {
+  enc_core(c, k, coeffs, seed, obj_first, out, count, level, ws, s);
+  return HEQG_OK;
+}
+
+int decrypt(heqg_ctx* c, const heqg_keys* k, CtV in, int n_poly, int64_t count, int level, uint64_t* rows_out,
+            hipStream_t s) {
+  const int N = c->g.N, nl = level + 1;
+  k_dec_launch(c->g, c->t, in, n_poly, k->sk, rows_out, count, nl, s);
+  return ntt(c, rows_q(rows_out, count, (int64_t)nl * N, 1, 0, nl), true, s);
+}
+
+int refresh(heqg_ctx* c, const heqg_keys* k, CtV in, int64_t count, int level, int target, uint64_t seed,
+            uint64_t obj_first, CtV out, uint64_t* ws, hipStream_t s) {
+  const int N = c->g.N, nl = level + 1, nlo = target + 1;
+  uint64_t* dec = ws + enc_ws_words(c, count);
+  int rc = decrypt(c, k, in, 2, count, level, dec, s);
+  if (rc) return rc;
+  uint64_t* tmp = ws + 3 * (size_t)count * N;
+  const int64_t tcs = (int64_t)4 * nlo * N;
+  k_lift_launch(c->g, c->t, c->lift_c, dec, nl, tmp + (size_t)3 * nlo * N, tcs, nlo, count, s);
+  enc_core(c, k, nullptr, seed, obj_first, out, count, target, ws, s);
+  return HEQG_OK;
+}
+
+int pt_load(heqg_ctx* c, const int64_t* coeffs, int64_t count, int level, uint64_t* out, hipStream_t s) {
+  const int N = c->g.N, nl = level + 1;
+  k_small_to_rows_launch(c->g, c->t, coeffs, N, count, out, (int64_t)nl * N, nl, 0, 0, s);
+  return ntt(c, rows_q(out, count, (int64_t)nl * N, 1, 0, nl), false, s);
+}
+
+// ------------------------------------------------------------------ key switching
+size_t ks_ws_words(const heqg_ctx* c, int64_t count, int level) {
+  const size_t nl = level + 1, nx = nl + c->g.n_p, nd = (nl + c->g.alpha - 1) / c->g.alpha;
+  return (size_t)count * (nl + nd * nx + 2 * nx + 2 * nl) * c->g.N;
+}
+size_t rot_ws_words(const heqg_ctx* c, int64_t count, int level) {
+  return (size_t)count * 2 * (level + 1) * c->g.N + ks_ws_words(c, count, level);
+}
+size_t rescale_ws_words(const heqg_ctx* c, int64_t count, int n_poly, int level) {
+  return (size_t)count * n_poly * (1 + level) * c->g.N;
+}
+size_t mul_const_ws_words(const heqg_ctx* c, int64_t count, int n_poly, int level) {
+  return (size_t)count * n_poly * (level + 1) * c->g.N + rescale_ws_words(c, count, n_poly, level);
+}
+
+void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, CtV base0, CtV base1, bool has_base1,
+             CtV out, uint64_t* ws, hipStream_t s) {
+  const int N = c->g.N, nl = level + 1, np = c->g.n_p, nq = c->g.n_q, nx = nl + np, alpha = c->g.alpha;
+  const int nd = (nl + alpha - 1) / alpha;
+  uint64_t* dcoef = ws;
+  uint64_t* ext = dcoef + (size_t)count * nl * N;
+  uint64_t* acc = ext + (size_t)count * nd * nx * N;
+  uint64_t* conv = acc + (size_t)count * 2 * nx * N;
+  const int64_t ext_cs = (int64_t)nd * nx * N;
+  // 1. d to coefficient form
+  k_copy_launch(c->g, d, CtV{dcoef, (int64_t)nl * N, 0}, count, 1, nl, s);
+  ntt(c, rows_q(dcoef, count, (int64_t)nl * N, 1, 0, nl), true, s);
+  // 2. ModUp per digit, then NTT of the new rows
+  for (int j = 0; j < nd; ++j) {
+    int lo = j * alpha, sz = std::min(alpha, nl - lo);
+    std::vector<int> tgt;
+    for (int g = 0; g < nl; ++g)
+      if (g < lo || g >= lo + sz) tgt.push_back(g);
+    for (int kk = 0; kk < np; ++kk) tgt.push_back(nq + kk);
+    uint64_t* e = ext + (size_t)j * nx * N;
+    k_modup_launch(c->g, c->t, dcoef, count, level, j, e, ext_cs, s);
+    ntt(c, rows(e, count, ext_cs, 1, 0, (int)tgt.size(), tgt.data()), false, s);
+  }
+  // 3. inner product with the key over Q_l and P
+  k_ks_inner_launch(c->g, c->t, d, ext, ext_cs, (int64_t)nx * N, key, acc, count, level, s);
+  // 4. ModDown of both parts
+  ntt(c, rows_q(acc + (size_t)nl * N, count, (int64_t)2 * nx * N, 2, (int64_t)nx * N, np, nq), true, s);
+  k_moddown_conv_launch(c->g, c->t, acc, conv, count, level, s);
+  ntt(c, rows_q(conv, count * 2, (int64_t)nl * N, 1, 0, nl), false, s);
+  k_ks_combine_launch(c->g, c->t, acc, conv, base0, base1, has_base1, out, count, level, s);
+}
+
+int relin(heqg_ctx* c, const heqg_keys* k, CtV in3, CtV out, int64_t count, int level, uint64_t* ws, hipStream_t s) {
+  CtV d{in3.d + 2 * in3.ps, in3.cs, in3.ps};
+  CtV b0{in3.d, in3.cs, in3.ps};
+  CtV b1{in3.d + in3.ps, in3.cs, in3.ps};
+  ks_core(c, k->rlk, d, count, level, b0, b1, true, out, ws, s);
+  return HEQG_OK;
+}
+
+const uint64_t* rot_key(const heqg_keys* k, uint64_t galois) {
+  for (size_t r = 0; r < k->galois.size(); ++r)
+    if (k->galois[r] == galois) return k->rot + r * k->key_words;
+  return nullptr;
+}
+
+int rotate(heqg_ctx* c, const heqg_keys* k, CtV in, CtV out, int64_t count, int level, uint64_t galois, uint64_t* ws,
+           hipStream_t s) {
+  const int N = c->g.N, nl = level + 1;
+  if (galois == 1) {
+    k_copy_launch(c->g, in, out, count, 2, nl, s);
+    return HEQG_OK;
+  }
+  const uint64_t* key = rot_key(k, galois);
+  if (!key) {
+    set_err("rotate: no rotation key for this step");
+    return HEQG_ERR_KEY;
+  }
+  CtV t{ws, (int64_t)2 * nl * N, (int64_t)nl * N};
+  k_automorph_launch(c->g, in, t, count, 2, nl, galois, s);
+  CtV d{ws + (size_t)nl * N, t.cs, t.ps};
+  ks_core(c, key, d, count, level, t, t, false, out, ws + (size_t)count * 2 * nl * N, s);
+  return HEQG_OK;
+}
+
+void rescale(heqg_ctx* c, CtV in, CtV out, int64_t count, int n_poly, int level, uint64_t* ws, hipStream_t s) {
+  const int N = c->g.N;
+  uint64_t* last = ws;
+  uint64_t* spread = ws + (size_t)count * n_poly * N;
+  const int64_t rowsn = count * n_poly;
+  k_copy_launch(c->g, CtV{in.d + (size_t)level * N, in.cs, in.ps}, CtV{last, (int64_t)n_poly * N, N}, count, n_poly, 1,
+                s);
+  int pl[1] = {level};
+  ntt(c, rows(last, rowsn, N, 1, 0, 1, pl), true, s);
+  k_rescale_spread_launch(c->g, c->t, last, spread, rowsn, level, s);
+  ntt(c, rows_q(spread, rowsn, (int64_t)level * N, 1, 0, level), false, s);
+  k_rescale_combine_launch(c->g, c->t, in, spread, out, count, n_poly, level, s);
+}
+
+int const_int(const heqg_ctx* c, double cst, double target, int level, double in_scale, int64_t* k) {
+  double v = ((cst * target) * (double)c->primes[level]) / in_scale;
+  if (!(std::fabs(v) < 4611686018427387904.0)) {
+    set_err("mul_const: constant overflow");
+    return HEQG_ERR_OVERFLOW;
+  }
+  *k = std::llround(v);
+  return HEQG_OK;
+}
+
+int mul_const(heqg_ctx* c, CtV in, int64_t count, int n_poly, int level, double in_scale, double cst, double target,
+              CtV out, uint64_t* ws, hipStream_t s) {
+  int64_t kint;
+  int rc = const_int(c, cst, target, level, in_scale, &kint);
+  if (rc) return rc;
+  const int N = c->g.N, nl = level + 1;
+  std::vector<uint64_t> kr(2 * (size_t)nl);
+  for (int i = 0; i < nl; ++i) {
+    uint64_t q = c->primes[i];
+    uint64_t m = kint < 0 ? (q - (uint64_t)(-(__int128)kint % q)) % q : (uint64_t)kint % q;
+    kr[2 * i] = m;
+    kr[2 * i + 1] = h_shoup(m, q);
+  }
+  CtV t{ws, (int64_t)n_poly * nl * N, (int64_t)nl * N};
+  k_mul_scalar_launch(c->g, c->t, in, t, count, n_poly, nl, kr.data(), s);
+  rescale(c, t, out, count, n_poly, level, ws + (size_t)count * n_poly * nl * N, s);
+  return HEQG_OK;
+}
+
+}  // namespace ops

@@ -1,0 +1,39 @@
+// Internal operations behind the C ABI (device work enqueued on a stream).
+#pragma once
+#include "ctx.h"
+
+namespace ops {
+
+int ntt(const heqg_ctx* c, const RowSet& rs, bool inverse, hipStream_t s);
+RowSet rows(uint64_t* data, int64_t na, int64_t sa, int64_t nb, int64_t sb, int ni, const int* pidx);
+RowSet rows_q(uint64_t* data, int64_t na, int64_t sa, int64_t nb, int64_t sb, int ni, int first = 0);
+
+int keygen(heqg_ctx* c, heqg_keys* k, uint64_t seed, uint8_t* ws, hipStream_t s);
+
+size_t enc_ws_words(const heqg_ctx* c, int64_t count);
+int encrypt(heqg_ctx* c, const heqg_keys* k, const int64_t* coeffs, const uint64_t*, int, uint64_t seed,
+            uint64_t obj_first, CtV out, int64_t count, int level, uint64_t* ws, hipStream_t s);
+int decrypt(heqg_ctx* c, const heqg_keys* k, CtV in, int n_poly, int64_t count, int level, uint64_t* rows,
+            hipStream_t s);
+int refresh(heqg_ctx* c, const heqg_keys* k, CtV in, int64_t count, int level, int target, uint64_t seed,
+            uint64_t obj_first, CtV out, uint64_t* ws, hipStream_t s);
+int pt_load(heqg_ctx* c, const int64_t* coeffs, int64_t count, int level, uint64_t* out, hipStream_t s);
+
+size_t ks_ws_words(const heqg_ctx* c, int64_t count, int level);
+size_t rot_ws_words(const heqg_ctx* c, int64_t count, int level);
+size_t rescale_ws_words(const heqg_ctx* c, int64_t count, int n_poly, int level);
+size_t mul_const_ws_words(const heqg_ctx* c, int64_t count, int n_poly, int level);
+
+// key switch of d (NTT rows 0..level) with `key`; out_p = base_p + ks_p (base_1 optional)
+void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, CtV base0, CtV base1, bool has_base1,
+             CtV out, uint64_t* ws, hipStream_t s);
+int relin(heqg_ctx* c, const heqg_keys* k, CtV in3, CtV out, int64_t count, int level, uint64_t* ws, hipStream_t s);
+const uint64_t* rot_key(const heqg_keys* k, uint64_t galois);
+int rotate(heqg_ctx* c, const heqg_keys* k, CtV in, CtV out, int64_t count, int level, uint64_t galois, uint64_t* ws,
+           hipStream_t s);
+void rescale(heqg_ctx* c, CtV in, CtV out, int64_t count, int n_poly, int level, uint64_t* ws, hipStream_t s);
+int const_int(const heqg_ctx* c, double cst, double target, int level, double in_scale, int64_t* k);
+int mul_const(heqg_ctx* c, CtV in, int64_t count, int n_poly, int level, double in_scale, double cst, double target,
+              CtV out, uint64_t* ws, hipStream_t s);
+
+}  // namespace ops

@@ -1,0 +1,422 @@
+"""ctypes binding of libheqg.so (C ABI in include/heqg.h).
+
+Argument marshalling only: every step runs in the HIP library.  PyTorch
+supplies device memory (int64 tensors hold the uint64 residues bit for bit)
+and the current HIP stream.  Importing this module on a machine without the
+built library raises; there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libheqg.so")
+
+OK, ERR_ARG, ERR_LEVEL, ERR_SCALE, ERR_KEY, ERR_OVERFLOW, ERR_DEVICE, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+_NAMES = {-1: "ARG", -2: "LEVEL", -3: "SCALE", -4: "KEY", -5: "OVERFLOW", -6: "DEVICE", -7: "UNSUPPORTED"}
+
+
+class HeqgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("HEQG_ERR_%s: %s" % (_NAMES.get(code, code), msg))
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("log2N", ctypes.c_int), ("n_q", ctypes.c_int), ("q_bits", ctypes.POINTER(ctypes.c_int)),
+                ("n_p", ctypes.c_int), ("p_bits", ctypes.c_int), ("dnum", ctypes.c_int), ("log2_scale", ctypes.c_int)]
+
+
+class CtS(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("n_poly", ctypes.c_int), ("level", ctypes.c_int), ("scale", ctypes.c_double)]
+
+
+class BatchS(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("count", ctypes.c_int64), ("stride", ctypes.c_int64),
+                ("n_poly", ctypes.c_int), ("level", ctypes.c_int), ("scale", ctypes.c_double)]
+
+
+class SigmoidS(ctypes.Structure):
+    _fields_ = [("degree", ctypes.c_int), ("masks", ctypes.c_void_p), ("mask_level", ctypes.c_int),
+                ("mask_scales", ctypes.POINTER(ctypes.c_double))]
+
+
+class NagStateS(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int), ("alpha0", ctypes.c_double), ("alpha1", ctypes.c_double),
+                ("lr_max", ctypes.c_double), ("lr_min", ctypes.c_double), ("T", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("m_rows", ctypes.c_int), ("g_cols", ctypes.c_int),
+                ("refresh_seed", ctypes.c_uint64), ("eta", ctypes.c_double), ("lr", ctypes.c_double),
+                ("refreshed_gr", ctypes.c_int)]
+
+
+EXPORTS = None  # filled on load: every heqg_* function name the header declares
+_lib = None
+
+
+def lib():
+    global _lib, EXPORTS
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libheqg.so is not built (run __graft_entry__.build() or python -m "
+                           "paper_2406_13221_amd.build); there is no non-HIP fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u64, sz, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_double
+    P = ctypes.POINTER
+    sig = {
+        "heqg_last_error": (ctypes.c_char_p, []),
+        "heqg_ctx_tables_bytes": (sz, [P(Params)]),
+        "heqg_ctx_create": (i32, [P(Params), vp, sz, P(vp)]),
+        "heqg_ctx_destroy": (None, [vp]),
+        "heqg_ctx_primes": (i32, [vp, vp]),
+        "heqg_ctx_info": (i32, [vp, vp, vp, vp, vp, vp]),
+        "heqg_keys_bytes": (sz, [vp, i32]),
+        "heqg_keygen_ws_bytes": (sz, [vp]),
+        "heqg_keygen": (i32, [vp, u64, vp, i32, vp, sz, vp, sz, P(vp), vp]),
+        "heqg_keys_destroy": (None, [vp]),
+        "heqg_keys_galois": (i32, [vp, vp]),
+        "heqg_keys_export": (i32, [vp, i32, i32, vp, vp]),
+        "heqg_encode": (i32, [vp, vp, sz, dbl, vp]),
+        "heqg_encode_batch": (i32, [vp, vp, sz, i64, dbl, vp, i32]),
+        "heqg_decode": (i32, [vp, vp, dbl, vp, sz]),
+        "heqg_lift": (i32, [vp, vp, i32, vp]),
+        "heqg_enc_ws_bytes": (sz, [vp, i64]),
+        "heqg_encrypt": (i32, [vp, vp, vp, u64, u64, P(BatchS), vp, sz, vp]),
+        "heqg_decrypt": (i32, [vp, vp, P(BatchS), vp, vp, sz, vp]),
+        "heqg_refresh": (i32, [vp, vp, P(BatchS), i32, u64, u64, P(BatchS), vp, sz, vp]),
+        "heqg_pt_load": (i32, [vp, vp, i64, i32, vp, vp]),
+        "heqg_ks_ws_bytes": (sz, [vp, i64]),
+        "heqg_add": (i32, [vp, P(BatchS), P(BatchS), P(BatchS), vp]),
+        "heqg_sub": (i32, [vp, P(BatchS), P(BatchS), P(BatchS), vp]),
+        "heqg_tensor": (i32, [vp, P(BatchS), P(BatchS), P(BatchS), vp]),
+        "heqg_relin": (i32, [vp, vp, P(BatchS), P(BatchS), vp, sz, vp]),
+        "heqg_hmult": (i32, [vp, vp, P(BatchS), P(BatchS), P(BatchS), vp, sz, vp]),
+        "heqg_rotate": (i32, [vp, vp, P(BatchS), i32, P(BatchS), vp, sz, vp]),
+        "heqg_rescale": (i32, [vp, P(BatchS), P(BatchS), vp, sz, vp]),
+        "heqg_drop": (i32, [vp, P(BatchS), i32, P(BatchS), vp]),
+        "heqg_mul_pt": (i32, [vp, P(BatchS), vp, dbl, P(BatchS), vp]),
+        "heqg_add_pt": (i32, [vp, P(BatchS), vp, dbl, P(BatchS), vp]),
+        "heqg_mul_const": (i32, [vp, P(BatchS), dbl, dbl, P(BatchS), vp, sz, vp]),
+        "heqg_ntt": (i32, [vp, vp, i64, i32, i32, i32, vp]),
+        "heqg_nag_ws_bytes": (sz, [vp, i32, i32]),
+        "heqg_nag_qg_step": (i32, [vp, vp, P(BatchS), P(CtS), P(CtS), P(CtS), P(SigmoidS), P(NagStateS), i32, vp,
+                                   sz, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    EXPORTS = sorted(sig)
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc < 0:
+        raise HeqgError(rc, lib().heqg_last_error().decode())
+    return rc
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ws(nbytes):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 8), dtype=torch.uint8, device="cuda")
+
+
+class Cts:
+    """A batch of ciphertexts: int64 tensor [count, n_poly, level+1, N] on the GPU."""
+
+    def __init__(self, data, level, scale):
+        self.data = data
+        self.level = level
+        self.scale = float(scale)
+
+    @property
+    def count(self):
+        return self.data.shape[0]
+
+    @property
+    def n_poly(self):
+        return self.data.shape[1]
+
+    def batch(self):
+        d = self.data
+        return BatchS(d.data_ptr(), d.shape[0], d.stride(0), d.shape[1], self.level, self.scale)
+
+    def one(self, i=0):
+        d = self.data[i]
+        return CtS(d.data_ptr(), d.shape[0], self.level, self.scale)
+
+    def numpy(self):
+        return self.data.cpu().numpy().view(np.uint64)
+
+
+class Keys:
+    def __init__(self, ctx, handle, buf, galois):
+        self.ctx, self.handle, self.buf, self.galois = ctx, handle, buf, galois
+
+    def export(self, which, idx=0):
+        torch = _torch()
+        c = self.ctx
+        words = {0: c.nqp * c.N, 1: 2 * c.n_q * c.N}.get(which, c.dnum * 2 * c.nqp * c.N)
+        out = torch.empty(words, dtype=torch.int64, device="cuda")
+        _check(lib().heqg_keys_export(self.handle, which, idx, out.data_ptr(), _stream()))
+        return out
+
+    def __del__(self):
+        try:
+            lib().heqg_keys_destroy(self.handle)
+        except Exception:
+            pass
+
+
+class Context:
+    def __init__(self, log2N, q_bits, n_p, p_bits, dnum, log2_scale):
+        torch = _torch()
+        L = lib()
+        self._qb = (ctypes.c_int * len(q_bits))(*q_bits)
+        self.params = Params(log2N, len(q_bits), self._qb, n_p, p_bits, dnum, log2_scale)
+        nbytes = L.heqg_ctx_tables_bytes(ctypes.byref(self.params))
+        if nbytes == 0:
+            raise HeqgError(ERR_UNSUPPORTED, L.heqg_last_error().decode())
+        self.tables = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        h = ctypes.c_void_p()
+        _check(L.heqg_ctx_create(ctypes.byref(self.params), self.tables.data_ptr(), nbytes, ctypes.byref(h)))
+        self.h = h
+        self.N = 1 << log2N
+        self.n_q, self.n_p, self.dnum = len(q_bits), n_p, dnum
+        self.nqp = self.n_q + n_p
+        self.delta = float(2 ** log2_scale)
+        pr = np.zeros(self.nqp, dtype=np.uint64)
+        _check(L.heqg_ctx_primes(h, pr.ctypes.data))
+        self.primes = pr
+
+    @classmethod
+    def from_config(cls, cfg):
+        return cls(cfg["log2N"], cfg["q_bits"], cfg["n_p"], cfg["p_bits"], cfg["dnum"], cfg["log2_scale"])
+
+    def __del__(self):
+        try:
+            lib().heqg_ctx_destroy(self.h)
+        except Exception:
+            pass
+
+    @property
+    def top_level(self):
+        return self.n_q - 1
+
+    # ---------------------------------------------------------------- keys
+    def keygen(self, seed, rot_steps):
+        L = lib()
+        steps = (ctypes.c_int * max(1, len(rot_steps)))(*rot_steps)
+        nb = L.heqg_keys_bytes(self.h, len(rot_steps))
+        buf = _ws(nb)
+        ws = _ws(L.heqg_keygen_ws_bytes(self.h))
+        h = ctypes.c_void_p()
+        _check(L.heqg_keygen(self.h, seed, steps, len(rot_steps), buf.data_ptr(), nb, ws.data_ptr(), ws.numel(),
+                             ctypes.byref(h), _stream()))
+        n = _check(L.heqg_keys_galois(h, None))
+        gal = np.zeros(max(n, 1), dtype=np.uint64)
+        L.heqg_keys_galois(h, gal.ctypes.data)
+        _torch().cuda.current_stream().synchronize()
+        return Keys(self, h, buf, [int(x) for x in gal[:n]])
+
+    # ---------------------------------------------------------------- encode
+    def encode(self, values, scale):
+        v = np.ascontiguousarray(values, dtype=np.float64)
+        out = np.zeros(self.N, dtype=np.int64)
+        _check(lib().heqg_encode(self.h, v.ctypes.data, v.size, float(scale), out.ctypes.data))
+        return out
+
+    def encode_batch(self, values, scale, threads=0):
+        """values: [count, n] float64 -> int64 [count, N]."""
+        v = np.ascontiguousarray(values, dtype=np.float64)
+        if v.ndim == 1:
+            v = v[None]
+        out = np.zeros((v.shape[0], self.N), dtype=np.int64)
+        _check(lib().heqg_encode_batch(self.h, v.ctypes.data, v.shape[1], v.shape[0], float(scale), out.ctypes.data,
+                                       threads))
+        return out
+
+    def decode(self, coeffs, scale, n=None):
+        c = np.ascontiguousarray(coeffs, dtype=np.float64)
+        n = self.N // 2 if n is None else n
+        out = np.zeros(n, dtype=np.float64)
+        _check(lib().heqg_decode(self.h, c.ctypes.data, float(scale), out.ctypes.data, n))
+        return out
+
+    def lift(self, rows, level):
+        r = np.ascontiguousarray(rows, dtype=np.uint64)
+        out = np.zeros(self.N, dtype=np.float64)
+        _check(lib().heqg_lift(self.h, r.ctypes.data, level, out.ctypes.data))
+        return out
+
+    # ---------------------------------------------------------------- alloc helpers
+    def empty(self, count, n_poly, level, scale):
+        torch = _torch()
+        return Cts(torch.empty((count, n_poly, level + 1, self.N), dtype=torch.int64, device="cuda"), level, scale)
+
+    # ---------------------------------------------------------------- encryption
+    def encrypt(self, keys, coeffs, level, scale, seed, obj_first):
+        """coeffs: int64 tensor [count, N] on the GPU (or numpy, copied over)."""
+        torch = _torch()
+        if isinstance(coeffs, np.ndarray):
+            coeffs = torch.from_numpy(np.ascontiguousarray(coeffs, dtype=np.int64)).cuda()
+        coeffs = coeffs.reshape(-1, self.N).contiguous()
+        out = self.empty(coeffs.shape[0], 2, level, scale)
+        L = lib()
+        ws = _ws(L.heqg_enc_ws_bytes(self.h, out.count))
+        b = out.batch()
+        _check(L.heqg_encrypt(self.h, keys.handle, coeffs.data_ptr(), seed, obj_first, ctypes.byref(b),
+                              ws.data_ptr(), ws.numel(), _stream()))
+        return out
+
+    def decrypt(self, keys, ct):
+        torch = _torch()
+        out = torch.empty((ct.count, ct.level + 1, self.N), dtype=torch.int64, device="cuda")
+        b = ct.batch()
+        _check(lib().heqg_decrypt(self.h, keys.handle, ctypes.byref(b), out.data_ptr(), None, 0, _stream()))
+        return out
+
+    def decrypt_values(self, keys, ct, n=None, index=0):
+        rows = self.decrypt(keys, ct)[index].cpu().numpy().view(np.uint64)
+        return self.decode(self.lift(rows, ct.level), ct.scale, n)
+
+    def refresh(self, keys, ct, target_level, seed, obj_first):
+        out = self.empty(ct.count, 2, target_level, ct.scale)
+        L = lib()
+        nb = L.heqg_enc_ws_bytes(self.h, ct.count) + 8 * ct.count * (ct.level + 1) * self.N
+        ws = _ws(nb)
+        bi, bo = ct.batch(), out.batch()
+        _check(L.heqg_refresh(self.h, keys.handle, ctypes.byref(bi), target_level, seed, obj_first, ctypes.byref(bo),
+                              ws.data_ptr(), ws.numel(), _stream()))
+        return out
+
+    def pt_load(self, coeffs, level):
+        torch = _torch()
+        if isinstance(coeffs, np.ndarray):
+            coeffs = torch.from_numpy(np.ascontiguousarray(coeffs, dtype=np.int64)).cuda()
+        coeffs = coeffs.reshape(-1, self.N).contiguous()
+        out = torch.empty((coeffs.shape[0], level + 1, self.N), dtype=torch.int64, device="cuda")
+        _check(lib().heqg_pt_load(self.h, coeffs.data_ptr(), coeffs.shape[0], level, out.data_ptr(), _stream()))
+        return out
+
+    def ntt(self, rows, first_prime, period, inverse=False):
+        """In place on an int64 tensor of shape [..., N]."""
+        n = rows.numel() // self.N
+        _check(lib().heqg_ntt(self.h, rows.data_ptr(), n, first_prime, period, 1 if inverse else 0, _stream()))
+        return rows
+
+    # ---------------------------------------------------------------- arithmetic
+    def _bin(self, fn, a, b, n_poly, scale):
+        lv = min(a.level, b.level)
+        out = self.empty(a.count, n_poly, lv, scale)
+        ba, bb, bo = a.batch(), b.batch(), out.batch()
+        _check(fn(self.h, ctypes.byref(ba), ctypes.byref(bb), ctypes.byref(bo), _stream()))
+        return out
+
+    def add(self, a, b):
+        return self._bin(lib().heqg_add, a, b, a.n_poly, a.scale)
+
+    def sub(self, a, b):
+        return self._bin(lib().heqg_sub, a, b, a.n_poly, a.scale)
+
+    def tensor(self, a, b):
+        return self._bin(lib().heqg_tensor, a, b, 3, a.scale * b.scale)
+
+    def relin(self, keys, a):
+        out = self.empty(a.count, 2, a.level, a.scale)
+        L = lib()
+        ws = _ws(L.heqg_ks_ws_bytes(self.h, a.count))
+        ba, bo = a.batch(), out.batch()
+        _check(L.heqg_relin(self.h, keys.handle, ctypes.byref(ba), ctypes.byref(bo), ws.data_ptr(), ws.numel(),
+                            _stream()))
+        return out
+
+    def hmult(self, keys, a, b):
+        lv = min(a.level, b.level)
+        out = self.empty(a.count, 2, lv, a.scale * b.scale)
+        L = lib()
+        ws = _ws(L.heqg_ks_ws_bytes(self.h, a.count) + 8 * a.count * 3 * (lv + 1) * self.N)
+        ba, bb, bo = a.batch(), b.batch(), out.batch()
+        _check(L.heqg_hmult(self.h, keys.handle, ctypes.byref(ba), ctypes.byref(bb), ctypes.byref(bo), ws.data_ptr(),
+                            ws.numel(), _stream()))
+        return out
+
+    def rotate(self, keys, a, step):
+        out = self.empty(a.count, 2, a.level, a.scale)
+        L = lib()
+        ws = _ws(L.heqg_ks_ws_bytes(self.h, a.count) + 8 * a.count * 2 * (a.level + 1) * self.N)
+        ba, bo = a.batch(), out.batch()
+        _check(L.heqg_rotate(self.h, keys.handle, ctypes.byref(ba), step, ctypes.byref(bo), ws.data_ptr(), ws.numel(),
+                             _stream()))
+        return out
+
+    def rescale(self, a):
+        out = self.empty(a.count, a.n_poly, a.level - 1, a.scale / float(int(self.primes[a.level])))
+        ws = _ws(8 * a.count * a.n_poly * (a.level + 1) * self.N)
+        ba, bo = a.batch(), out.batch()
+        _check(lib().heqg_rescale(self.h, ctypes.byref(ba), ctypes.byref(bo), ws.data_ptr(), ws.numel(), _stream()))
+        return out
+
+    def drop(self, a, level):
+        out = self.empty(a.count, a.n_poly, level, a.scale)
+        ba, bo = a.batch(), out.batch()
+        _check(lib().heqg_drop(self.h, ctypes.byref(ba), level, ctypes.byref(bo), _stream()))
+        return out
+
+    def mul_pt(self, a, pt, pt_scale):
+        out = self.empty(a.count, a.n_poly, a.level, a.scale * pt_scale)
+        ba, bo = a.batch(), out.batch()
+        _check(lib().heqg_mul_pt(self.h, ctypes.byref(ba), pt.data_ptr(), float(pt_scale), ctypes.byref(bo), _stream()))
+        return out
+
+    def add_pt(self, a, pt, pt_scale):
+        out = self.empty(a.count, 2, a.level, a.scale)
+        ba, bo = a.batch(), out.batch()
+        _check(lib().heqg_add_pt(self.h, ctypes.byref(ba), pt.data_ptr(), float(pt_scale), ctypes.byref(bo), _stream()))
+        return out
+
+    # ---------------------------------------------------------------- training step
+    def nag_ws_bytes(self, batch, degree=3):
+        return lib().heqg_nag_ws_bytes(self.h, batch, degree)
+
+    def nag_qg_step(self, keys, Z, Bbar, W, V, masks, mask_level, mask_scales, degree, state, batch, ws=None,
+                    stream=None):
+        """One encrypted QG-NAG iteration; W and V (count-1 Cts) are updated in place.
+
+        masks: int64 tensor [n_terms + 1, mask_level + 1, N] (NTT form); state: NagStateS (updated)."""
+        L = lib()
+        if ws is None:
+            ws = _ws(self.nag_ws_bytes(batch, degree))
+        sc = (ctypes.c_double * len(mask_scales))(*mask_scales)
+        sig = SigmoidS(degree, masks.data_ptr(), mask_level, sc)
+        zb = Z.batch()
+        bb, wb, vb = Bbar.one(), W.one(), V.one()
+        s = _stream() if stream is None else ctypes.c_void_p(stream)
+        _check(L.heqg_nag_qg_step(self.h, keys.handle, ctypes.byref(zb), ctypes.byref(bb), ctypes.byref(wb),
+                                  ctypes.byref(vb), ctypes.byref(sig), ctypes.byref(state), batch, ws.data_ptr(),
+                                  ws.numel(), s))
+        for ct, cs in ((W, wb), (V, vb)):
+            n = 2 * (cs.level + 1) * self.N
+            ct.data = ct.data.reshape(-1)[:n].view(1, 2, cs.level + 1, self.N)
+            ct.level, ct.scale = cs.level, cs.scale
+        return state
+
+    def mul_const(self, a, c, target):
+        out = self.empty(a.count, a.n_poly, a.level - 1, target)
+        ws = _ws(16 * a.count * a.n_poly * (a.level + 1) * self.N)
+        ba, bo = a.batch(), out.batch()
+        _check(lib().heqg_mul_const(self.h, ctypes.byref(ba), float(c), float(target), ctypes.byref(bo), ws.data_ptr(),
+                                    ws.numel(), _stream()))
+        return out

@@ -1,0 +1,185 @@
+"""Encrypted QG-NAG logistic-regression training on the HIP library.
+
+Follows the pipeline of the paper (section 4.3): the client builds
+Z = y+- * [1 | X] and the diagonal B-bar from -1/4 X^T X, packs Z row by row
+into m x g blocks (section 2.2), encrypts Z, B-bar and W = V = 0; the cloud
+runs steps 4-6 (heqg_nag_qg_step) and refreshes W and V (step 7, here the
+key-holder refresh); the client decrypts W (step 8).
+
+Everything arithmetic on ciphertexts runs in libheqg.so; this module only
+prepares plaintext vectors and calls the C ABI through the binding.
+"""
+import math
+
+import numpy as np
+
+from . import heqg
+
+G8 = {1: 0.15, 3: -0.0015}   # least-squares cubic on [-8, 8] (section 4.1)
+
+
+def rot_steps(m, g):
+    """Row sums (+2^k), replication (-2^k) and column sums (+g 2^k)."""
+    lg, lm = int(math.log2(g)), int(math.log2(m))
+    return [1 << k for k in range(lg)] + [-(1 << k) for k in range(lg)] + [g << k for k in range(lm)]
+
+
+def z_matrix(X, y, g):
+    """y+- * [1 | X | 0] with labels in {0, 1} mapped to -1/+1."""
+    n, f = X.shape
+    Z = np.zeros((n, g))
+    Z[:, 0] = 1.0
+    Z[:, 1:f + 1] = X
+    return Z * (2.0 * np.asarray(y, dtype=np.float64) - 1.0)[:, None]
+
+
+def pack_rows(Z, m, g):
+    """Blocks of m rows, each flattened row-major into m*g slots (zero rows pad the last block)."""
+    n = Z.shape[0]
+    nb = -(-n // m)
+    out = np.zeros((nb, m * g))
+    flat = Z.reshape(-1)
+    for b in range(nb):
+        seg = flat[b * m * g: (b + 1) * m * g]
+        out[b, :seg.size] = seg
+    return out
+
+
+def bbar_diag(X, g, eps=1e-8):
+    """1 / (eps + sum_l |H_jl|), H = 1/4 [1|X]^T [1|X] (sections 3.1, 4.3); 0 on padding columns."""
+    n, f = X.shape
+    A = np.hstack([np.ones((n, 1)), X])
+    H = 0.25 * (A.T @ A)
+    out = np.zeros(g)
+    out[:f + 1] = 1.0 / (eps + np.abs(H).sum(axis=1))
+    return out
+
+
+def tile_row(vec, m, g):
+    row = np.zeros(g)
+    row[:len(vec)] = vec
+    return np.tile(row, m)
+
+
+def first_column(m, g):
+    F = np.zeros((m, g))
+    F[:, 0] = 1.0
+    return F.reshape(-1)
+
+
+def sigmoid_scales(primes, level, s_z, s_w, s_c, degree):
+    """Plaintext scales for the masked odd terms so every term reaches scale s_c."""
+    q = [float(int(p)) for p in primes]
+    s_u = s_z * s_w / q[level]
+    s_s = s_u * s_u / q[level - 1]
+    sc = {1: s_c * q[level - 1] / s_u, 3: s_c * q[level - 2] * q[level - 1] / (s_u * s_s)}
+    if degree >= 5:
+        s_s4 = s_s * s_s / q[level - 2]
+        sc[5] = s_c * q[level - 3] * q[level - 1] / (s_u * s_s4)
+        if degree >= 7:
+            sc[7] = s_c * q[level - 3] * q[level - 2] * q[level - 1] / (s_u * s_s * s_s4)
+    return sc
+
+
+def new_state(m, g, refresh_seed=0, lr_max=2.0, lr_min=1.0, T=81.0, gamma=2.5):
+    a0 = 0.01
+    a1 = 0.5 * (1.0 + math.sqrt(1.0 + 4.0 * a0 * a0))
+    return heqg.NagStateS(0, a0, a1, lr_max, lr_min, T, gamma, m, g, refresh_seed, 0.0, 0.0, 0)
+
+
+class EncryptedQGNAG:
+    """Client + cloud roles of the pipeline on one GPU."""
+
+    def __init__(self, cfg, X, y, coeffs=None, batch=16, rows=None, threads=0, mini_batch=False):
+        import torch
+        self.cfg = cfg
+        self.m, self.g = cfg["m"], cfg["g"]
+        self.coeffs = dict(coeffs or G8)
+        self.degree = max(self.coeffs)
+        self.batch = batch
+        self.ctx = ctx = heqg.Context.from_config(cfg)
+        self.keys = ctx.keygen(cfg["key_seed"], rot_steps(self.m, self.g))
+        L = ctx.top_level
+        self.L = L
+        Xs, ys = (X, y) if rows is None else (X[rows[0]:rows[1]], y[rows[0]:rows[1]])
+        # step 1-2: Z blocks, B-bar, W = V = 0 (client side)
+        blocks = pack_rows(z_matrix(Xs, ys, self.g), self.m, self.g)
+        nb = blocks.shape[0]
+        self.Z = heqg.Cts(torch.empty((nb, 2, L + 1, ctx.N), dtype=torch.int64, device="cuda"), L, ctx.delta)
+        chunk = 64
+        ws = heqg._ws(heqg.lib().heqg_enc_ws_bytes(ctx.h, chunk))
+        for b0 in range(0, nb, chunk):
+            b1 = min(nb, b0 + chunk)
+            coeffs_np = ctx.encode_batch(blocks[b0:b1], ctx.delta, threads)
+            dev = torch.from_numpy(coeffs_np).cuda()
+            out = heqg.Cts(self.Z.data[b0:b1], L, ctx.delta)
+            ob = out.batch()
+            heqg._check(heqg.lib().heqg_encrypt(ctx.h, self.keys.handle, dev.data_ptr(), cfg["enc_seed"], b0,
+                                                ctypes_byref(ob), ws.data_ptr(), ws.numel(), heqg._stream()))
+        # full batch: one B-bar from all rows; mini-batch (Algorithm 1): one B-bar per batch of rows
+        n = Xs.shape[0]
+        br = cfg.get("batch_rows") if mini_batch else None
+        if br and br % self.m:
+            raise ValueError("batch_rows must be a multiple of m")
+        spans = [(0, n)] if not br else [(s, min(s + br, n)) for s in range(0, n, br)]
+        self.block_spans = [(s // self.m, -(-e // self.m)) for s, e in spans]
+        self.Bbars = []
+        for i, (s, e) in enumerate(spans):
+            B = bbar_diag(Xs[s:e], self.g)
+            sB = 2.0 ** 50 / B.max()
+            self.Bbars.append(ctx.encrypt(self.keys, ctx.encode(tile_row(B, self.m, self.g), sB)[None], L, sB,
+                                          cfg["enc_seed"], (1 << 40) + 16 + i))
+        self.Bbar = self.Bbars[0]
+        zero = np.zeros((1, ctx.N), dtype=np.int64)
+        self.W = ctx.encrypt(self.keys, zero, L, ctx.delta, cfg["enc_seed"], (1 << 40) + 1)
+        self.V = ctx.encrypt(self.keys, zero, L, ctx.delta, cfg["enc_seed"], (1 << 40) + 2)
+        self.set_sigmoid(self.coeffs)
+        self.state = new_state(self.m, self.g, refresh_seed=cfg["enc_seed"] + 7)
+        self.ws = heqg._ws(ctx.nag_ws_bytes(batch, self.degree))
+        self.refresh_obj = 1 << 41
+
+    def set_sigmoid(self, coeffs):
+        """Encode -c_k F for each odd power (ascending) and F/2 at the planned scales, NTT form at level L-1."""
+        ctx = self.ctx
+        self.coeffs = dict(coeffs)
+        self.degree = max(self.coeffs)
+        lv = self.L
+        s_c = ctx.delta
+        sc = sigmoid_scales(ctx.primes, lv, ctx.delta, ctx.delta, s_c, self.degree)
+        F = first_column(self.m, self.g)
+        vals, scales = [], []
+        for k in sorted(self.coeffs):
+            vals.append(ctx.encode(-self.coeffs[k] * F, sc[k]))
+            scales.append(sc[k])
+        vals.append(ctx.encode(0.5 * F, s_c))
+        scales.append(s_c)
+        self.mask_level = lv - 1
+        self.masks = ctx.pt_load(np.stack(vals), self.mask_level)
+        self.mask_scales = scales
+
+    def step(self, refresh=True):
+        """One iteration: all blocks (full batch) or the blocks of batch t mod n_batches with its B-bar."""
+        ctx = self.ctx
+        k = self.state.t % len(self.block_spans)
+        b0, b1 = self.block_spans[k]
+        Z = heqg.Cts(self.Z.data[b0:b1], self.Z.level, self.Z.scale)
+        ctx.nag_qg_step(self.keys, Z, self.Bbars[k], self.W, self.V, self.masks, self.mask_level, self.mask_scales,
+                        self.degree, self.state, self.batch, self.ws)
+        if refresh:
+            self.refresh()
+        return self.state
+
+    def refresh(self):
+        o = self.refresh_obj
+        self.W = self.ctx.refresh(self.keys, self.W, self.L, self.cfg["enc_seed"] + 9, o)
+        self.V = self.ctx.refresh(self.keys, self.V, self.L, self.cfg["enc_seed"] + 9, o + 1)
+        self.refresh_obj += 2
+
+    def weights(self, f=None):
+        n = self.g if f is None else f
+        return self.ctx.decrypt_values(self.keys, self.W, n)
+
+
+def ctypes_byref(x):
+    import ctypes
+    return ctypes.byref(x)

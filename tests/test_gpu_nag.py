@@ -1,0 +1,153 @@
+"""GPU parity of the encrypted QG-NAG iteration (heqg_nag_qg_step) against the
+oracle's op-by-op circuit: bit-exact ciphertexts on identical inputs, and
+decrypted weights within 1e-3 of the FP64 plaintext trainer."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import circuit, trainer
+from oracle.ckks import Oracle
+from oracle.encode import encode
+from tests.gpu_common import assert_same_ct, gpu_ct
+
+pytestmark = pytest.mark.gpu
+TOL_W = 1e-3
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def oracle_setup(cfgkey, coeffs=trainer.G8, rows=None, bbar_rows=None, **over):
+    cfg = synth.get_config(cfgkey)
+    cfg.update(over)
+    d = synth.make_dataset(cfg)
+    X, y = d["X"], d["y"]
+    if rows:
+        X, y = X[rows[0]:rows[1]], y[rows[0]:rows[1]]
+    o = Oracle.from_config(cfg)
+    N, m, g = o.N, cfg["m"], cfg["g"]
+    o.keygen(cfg["key_seed"], circuit.rot_steps(m, g))
+    Z = trainer.build_Z(X, y, g)
+    blocks = circuit.pack_blocks(Z, m, g, N)
+    L = o.top_level
+    Zc = [o.encrypt(encode(blocks[b], N, o.delta), L, o.delta, cfg["enc_seed"], b) for b in range(len(blocks))]
+    XB = X if bbar_rows is None else X[bbar_rows[0]:bbar_rows[1]]
+    B = trainer.bbar(XB, g)
+    sB = 2.0 ** 50 / B.max()
+    Bc = o.encrypt(encode(circuit.replicate_row(B, m, g), N, sB), L, sB, cfg["enc_seed"], 1 << 20)
+    W = o.encrypt(np.zeros(N, np.int64), L, o.delta, cfg["enc_seed"], (1 << 20) + 1)
+    V = o.encrypt(np.zeros(N, np.int64), L, o.delta, cfg["enc_seed"], (1 << 20) + 2)
+    masks = circuit.make_masks(o, m, g, coeffs, L, o.delta)
+    return cfg, o, X, y, Zc, Bc, W, V, masks
+
+
+def gpu_side(cfg, o, Zc, Bc, W, V, masks, coeffs):
+    import torch
+    from paper_2406_13221_amd import heqg
+    ctx = heqg.Context.from_config(cfg)
+    keys = ctx.keygen(cfg["key_seed"], circuit.rot_steps(cfg["m"], cfg["g"]))
+    Z = heqg.Cts(torch.from_numpy(np.stack([z.data for z in Zc]).view(np.int64).copy()).cuda(), Zc[0].level,
+                 Zc[0].scale)
+    order = sorted(coeffs) + ["half"]
+    mk = torch.from_numpy(np.stack([masks[k][0] for k in order]).view(np.int64).copy()).cuda()
+    scales = [masks[k][1] for k in order]
+    return ctx, keys, Z, gpu_ct(ctx, Bc), gpu_ct(ctx, W), gpu_ct(ctx, V), mk, scales
+
+
+def gpu_state(ost, m, g):
+    from paper_2406_13221_amd import heqg
+    return heqg.NagStateS(ost["t"], ost["alpha0"], ost["alpha1"], 2.0, 1.0, 81.0, 2.5, m, g, ost["refresh_seed"],
+                          0.0, 0.0, 0)
+
+
+def run_parity(cfgkey, iters, batch, coeffs=trainer.G8, rows=None, bbar_rows=None, **over):
+    cfg, o, X, y, Zc, Bc, W, V, masks = oracle_setup(cfgkey, coeffs, rows, bbar_rows, **over)
+    m, g, L = cfg["m"], cfg["g"], o.top_level
+    ctx, keys, gZ, gB, gW, gV, mk, scales = gpu_side(cfg, o, Zc, Bc, W, V, masks, coeffs)
+    deg = max(coeffs)
+    ost = circuit.new_state(refresh_seed=7)
+    gst = gpu_state(ost, m, g)
+    for it in range(iters):
+        W, V, ost = circuit.nag_qg_step(o, Zc, Bc, W, V, ost, masks, m, g, degree=deg)
+        ctx.nag_qg_step(keys, gZ, gB, gW, gV, mk, L - 1, scales, deg, gst, batch)
+        assert_same_ct(gW, W, "W%d" % it)
+        assert_same_ct(gV, V, "V%d" % it)
+        assert gst.t == ost["t"] and gst.alpha1 == ost["alpha1"] and gst.eta == ost["eta"]
+        assert bool(gst.refreshed_gr) == ost["refreshed_gr"]
+        W = o.refresh(W, L, 99, 2 * it)
+        V = o.refresh(V, L, 99, 2 * it + 1)
+        gW = ctx.refresh(keys, gW, L, 99, 2 * it)
+        gV = ctx.refresh(keys, gV, L, 99, 2 * it + 1)
+        assert_same_ct(gW, W, "W%d-refreshed" % it)
+    return o, W
+
+
+def test_c1_steps_bit_exact(torch_cuda):
+    run_parity("c1", 3, batch=1)
+
+
+def test_c2_minibatch_step_bit_exact_ragged_chunks(torch_cuda):
+    # batch 0 of 1,024 rows = 4 blocks of 256 rows with its own B-bar; chunks of 3 + 1 blocks
+    run_parity("c2", 1, batch=3, rows=(0, 1024))
+
+
+@pytest.mark.parametrize("degree", [5, 7])
+def test_learned_degree_step_bit_exact(torch_cuda, degree):
+    base = {5: [0.19129, -4.5951e-3, 4.2214e-5], 7: [0.21689, -8.1934e-3, 1.6588e-4, -1.1959e-6]}[degree]
+    coeffs = {2 * i + 1: c for i, c in enumerate(base)}
+    run_parity("c1", 1, batch=1, coeffs=coeffs, q_bits=[50] + [40] * 7, n_p=3)
+
+
+def test_step_errors_before_launch(torch_cuda):
+    from paper_2406_13221_amd import heqg
+    cfg, o, X, y, Zc, Bc, W, V, masks = oracle_setup("c1")
+    ctx, keys, gZ, gB, gW, gV, mk, scales = gpu_side(cfg, o, Zc, Bc, W, V, masks, trainer.G8)
+    st = gpu_state(circuit.new_state(7), cfg["m"], cfg["g"])
+    w_before = gW.data.clone()
+    bad = list(scales)
+    bad[-1] *= 1.01      # F/2 plaintext at the wrong scale
+    with pytest.raises(heqg.HeqgError) as e:
+        ctx.nag_qg_step(keys, gZ, gB, gW, gV, mk, o.top_level - 1, bad, 3, st, 1)
+    assert e.value.code == heqg.ERR_SCALE
+    assert st.t == 0 and gW.level == o.top_level and bool((gW.data == w_before).all())
+    # a key set without the column-sum rotations
+    keys2 = ctx.keygen(cfg["key_seed"], [1, 2, 4, -1, -2, -4])
+    with pytest.raises(heqg.HeqgError) as e:
+        ctx.nag_qg_step(keys2, gZ, gB, gW, gV, mk, o.top_level - 1, scales, 3, st, 1)
+    assert e.value.code == heqg.ERR_KEY
+
+
+def _train_gpu(cfgkey, iters, mini, batch):
+    from paper_2406_13221_amd.train import EncryptedQGNAG
+    cfg = synth.get_config(cfgkey)
+    d = synth.make_dataset(cfg)
+    run = EncryptedQGNAG(cfg, d["X"], d["y"], batch=batch, mini_batch=mini)
+    ws = []
+    for _ in range(iters):
+        run.step()
+        ws.append(run.weights(cfg["g"]))
+    ref = trainer.train(d["X"], d["y"], cfg["g"], iters, batch_rows=cfg["batch_rows"] if mini else None)
+    return ws, ref, d
+
+
+def test_c1_training_matches_fp64(torch_cuda):
+    ws, ref, d = _train_gpu("c1", 3, False, 1)
+    for it, w in enumerate(ws):
+        assert np.abs(w - ref["history"][it]["W"]).max() < TOL_W
+
+
+def test_c2_minibatch_training_matches_fp64(torch_cuda):
+    ws, ref, d = _train_gpu("c2", 10, True, 4)
+    for it, w in enumerate(ws):
+        assert np.abs(w - ref["history"][it]["W"]).max() < TOL_W, it
+
+
+def test_c2_fullbatch_training_matches_fp64(torch_cuda):
+    ws, ref, d = _train_gpu("c2", 3, False, 16)
+    for it, w in enumerate(ws):
+        assert np.abs(w - ref["history"][it]["W"]).max() < TOL_W, it
