@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Throughput of encrypted quadratic-gradient NAG training on one MI355X.
+
+Workload: the paper's full-batch experiment shape (section 5.1, Table 1):
+422,108 synthetic samples x 200 features (+ bias, padded to 256 columns),
+packed 128 rows per ciphertext into 3,298 CKKS ciphertexts, N = 2^16,
+24 RNS limbs (60/40-bit), dnum = 4 hybrid key switching, scale 2^40,
+degree-3 sigmoid g8.  One step = one encrypted QG-NAG iteration over every
+block (steps 4-6 of section 4.3) plus the refresh of W and V (step 7, here
+the key-holder refresh).  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line (metric, value in seconds per iteration, the NTT
+row-pass roofline measured live with sampled HIP events, and the CPU oracle
+timed on a bounded sample of the same workload).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PMC_FILE = os.path.join(ROOT, "profiles", "ntt_rows_fwd_c3_pmc.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2406_13221_amd", "csrc", "ntt.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(cfg, data, n_blocks):
+    """The oracle timed on one block's per-iteration pipeline, extrapolated to all blocks."""
+    import numpy as np
+    from oracle import circuit, trainer
+    from oracle.ckks import Oracle
+    from oracle.encode import encode
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    o = Oracle.from_config(cfg)
+    m, g = cfg["m"], cfg["g"]
+    lg = int(np.log2(g))
+    steps = [1 << k for k in range(lg)] + [-(1 << k) for k in range(lg)]
+    o.keygen(cfg["key_seed"], steps)
+    Z = trainer.build_Z(data["X"][:m], data["y"][:m], g)
+    blk = circuit.pack_blocks(Z, m, g, o.N)[0]
+    L = o.top_level
+    Zc = o.encrypt(encode(blk, o.N, o.delta), L, o.delta, cfg["enc_seed"], 0)
+    W = o.encrypt(np.zeros(o.N, np.int64), L, o.delta, cfg["enc_seed"], 1)
+    masks = circuit.make_masks(o, m, g, trainer.G8, L, o.delta)
+    t0 = time.perf_counter()
+    u = o.rescale(o.hmult(Zc, W))
+    for k in range(lg):
+        u = o.add(u, o.rotate(u, 1 << k))
+    p = circuit.sigmoid_block(o, u, masks, 3)
+    for k in range(lg):
+        p = o.add(p, o.rotate(p, -(1 << k)))
+    o.tensor(Zc, p)
+    dt = time.perf_counter() - t0
+    return dict(value=dt * n_blocks, unit="s/iter", cores=threads, kind="oracle",
+                sample="1 of %d blocks through the per-block pipeline (3 relinearisations, 16 rotations, "
+                       "masked sigmoid, gradient tensor) at the same parameters, %.1f s, x%d; the "
+                       "once-per-iteration tail is not included" % (n_blocks, dt, n_blocks))
+
+
+def pmc_traffic(avg_rows):
+    """HBM bytes per launch of the row pass from committed rocprofv3 --pmc summaries, or None."""
+    try:
+        with open(PMC_FILE) as f:
+            pm = json.load(f)
+        with open(KERNEL_SRC, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != pm["kernel_source_sha256"]:
+                return None
+        return pm["bytes_per_row"] * avg_rows
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c3")
+    ap.add_argument("--batch", type=int, default=16, help="blocks per lock-step chunk")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--prof-every", type=int, default=16)
+    ap.add_argument("--mode", default="train", choices=["train", "ntt"],
+                    help="ntt: only the batched forward NTT (768 limbs) and a 1 GiB device copy, for counters")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (see DESIGN.md for how "
+              "the iteration would shard by row blocks)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2406_13221_amd import heqg
+    from paper_2406_13221_amd.train import EncryptedQGNAG
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    cfg = synth.get_config(args.config)
+    if args.mode == "ntt":
+        ctx = heqg.Context.from_config(cfg)
+        rows = torch.randint(0, 2 ** 39, (16 * 2, ctx.n_q, ctx.N), dtype=torch.int64, device="cuda")
+        for _ in range(3):
+            ctx.ntt(rows, 0, ctx.n_q)
+        src = torch.ones(1 << 27, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "ntt", "ntt_rows_per_launch": rows.shape[0] * rows.shape[1],
+                          "copy_bytes": src.numel() * 8}), flush=True)
+        return
+    data = synth.make_dataset(cfg)
+    t0 = time.perf_counter()
+    run = EncryptedQGNAG(cfg, data["X"], data["y"], batch=args.batch)
+    torch.cuda.synchronize()
+    log("setup %.1f s, %d blocks, %.1f GB resident" % (time.perf_counter() - t0, run.Z.count,
+                                                       torch.cuda.memory_allocated() / 1e9))
+    for i in range(args.warmup):
+        run.step()
+        torch.cuda.synchronize()
+        log("warmup step %d done" % i)
+
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    heqg.prof_start(args.prof_every)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record()
+        run.step(refresh=False)
+        ev[k][1].record()
+        run.refresh()
+        ev[k][2].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    avg_us, n_sampled, avg_rows = heqg.prof_stop()
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    upd = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps / 1000.0
+    ref = sum(e[1].elapsed_time(e[2]) for e in ev) / args.steps / 1000.0
+    log("timed %d steps: %.3f s/step (update %.3f s, refresh %.4f s)" % (args.steps, ms_per_step / 1e3, upd, ref))
+
+    # NTT throughput: forward + inverse over a batch of 768 limbs, as read once + written once per transform
+    N = run.ctx.N
+    rows = torch.randint(0, 2 ** 39, (16 * 2, run.ctx.n_q, N), dtype=torch.int64, device="cuda")
+    nrows = rows.shape[0] * rows.shape[1]
+    for _ in range(2):
+        run.ctx.ntt(rows, 0, run.ctx.n_q)
+        run.ctx.ntt(rows, 0, run.ctx.n_q, inverse=True)
+    e0, e1, e2 = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        run.ctx.ntt(rows, 0, run.ctx.n_q)
+    e1.record()
+    for _ in range(reps):
+        run.ctx.ntt(rows, 0, run.ctx.n_q, inverse=True)
+    e2.record()
+    torch.cuda.synchronize()
+    ntt_bytes = 16.0 * N * nrows
+    fwd_gbs = ntt_bytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    inv_gbs = ntt_bytes * reps / (e1.elapsed_time(e2) * 1e-3) / 1e9
+
+    w = run.weights(cfg["n_features"] + 1)
+    if not (abs(w).max() < 1e3):
+        print("decrypted weights out of range", file=sys.stderr)
+        sys.exit(1)
+
+    achieved = 16.0 * N * avg_rows / (avg_us * 1e-6) / 1e9 if avg_us > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": pmc_traffic(avg_rows),
+                "kernel": "k_ntt_rows<8,true> (forward NTT, second pass)",
+                "avg_launch_us": round(avg_us, 2), "sampled_launches": n_sampled, "avg_rows_per_launch": avg_rows}
+
+    out = {
+        "metric": "sec per encrypted QG-NAG iteration (422k x 200, N=2^16)",
+        "value": round(ms_per_step / 1000.0, 4),
+        "unit": "s/iter",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic (seeded; shapes of the paper's 422,108 x 200 workload)",
+        "config": {"workload": "%s full-batch QG-NAG iteration + W/V refresh" % cfg["name"],
+                   "n_samples": cfg["n_train"], "n_features": cfg["n_features"], "log2N": cfg["log2N"],
+                   "limbs": len(cfg["q_bits"]), "dnum": cfg["dnum"], "blocks": run.Z.count,
+                   "rows_per_block": cfg["m"], "cols": cfg["g"], "batch_blocks": args.batch},
+        "update_s": round(upd, 4),
+        "refresh_s": round(ref, 5),
+        "ntt_gbps": {"forward": round(fwd_gbs, 1), "inverse": round(inv_gbs, 1), "limbs_per_call": nrows,
+                     "frac_of_hbm_peak": round(fwd_gbs / HBM_PEAK_GBS, 4)},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(cfg, data, run.Z.count)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

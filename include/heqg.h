@@ -278,6 +278,18 @@ int heqg_mul_const(heqg_ctx* ctx, const heqg_ct_batch* in, double c, double targ
 int heqg_ntt(heqg_ctx* ctx, uint64_t* dev_rows, int64_t n_rows, int first_prime, int period, int inverse,
              hipStream_t s);
 
+/*
+ * Launch-duration sampling of the forward NTT row pass (the second of the two
+ * passes, the most time-consuming kernel of an iteration): after
+ * heqg_prof_start(every), every `every`-th launch of that kernel, on whatever
+ * stream it is enqueued, is bracketed by two hipEvents recorded on the same
+ * stream.  heqg_prof_stop synchronises those events and returns the mean
+ * duration in microseconds, the number of sampled launches and the mean
+ * number of N-word rows per sampled launch; it disables sampling.  Process-wide.
+ */
+int heqg_prof_start(int every);
+int heqg_prof_stop(double* avg_us, int64_t* launches, double* avg_rows);
+
 /* ------------------------------------------------------------------ */
 /* Training step (section 3.2 Algorithm 1; section 3.3; section 4.3)    */
 /* ------------------------------------------------------------------ */

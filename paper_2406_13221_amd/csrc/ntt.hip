@@ -15,6 +15,9 @@
 // {16*j + r} (stages with distance < T); T = S/16 threads share a
 // sub-transform of size S.  Butterflies use Shoup multiplication with lazy
 // reduction (Harvey): forward values live in [0, 4q), inverse in [0, 2q).
+#include <mutex>
+#include <vector>
+
 #include "internal.h"
 
 namespace {
@@ -229,6 +232,22 @@ __global__ void __launch_bounds__(256) k_ntt_rows(NttParams P) {
   }
 }
 
+// sampled launch timing of the forward row pass
+struct ProfState {
+  std::mutex mu;
+  int every = 0;
+  int64_t seen = 0;
+  struct Rec {
+    hipEvent_t a, b;
+    int64_t rows;
+  };
+  std::vector<Rec> recs;
+};
+ProfState& prof() {
+  static ProfState p;
+  return p;
+}
+
 template <int LA, int LB>
 void run_ntt(NttParams P, int64_t rows, bool inverse, const U2* twf, const U2* twi, hipStream_t s) {
   const int N1 = 1 << LA, N2 = 1 << LB;
@@ -239,7 +258,22 @@ void run_ntt(NttParams P, int64_t rows, bool inverse, const U2* twf, const U2* t
     P.tiles = tilesA;
     hipLaunchKernelGGL((k_ntt_cols<LA, true>), dim3((unsigned)(rows * tilesA)), dim3(256), 0, s, P);
     P.tiles = tilesB;
+    ProfState& ps = prof();
+    bool sample = false;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (ps.every > 0) {
+      std::lock_guard<std::mutex> g(ps.mu);
+      if (ps.every > 0 && (ps.seen++ % ps.every) == 0 && hipEventCreate(&ea) == hipSuccess &&
+          hipEventCreate(&eb) == hipSuccess)
+        sample = true;
+    }
+    if (sample) hipEventRecord(ea, s);
     hipLaunchKernelGGL((k_ntt_rows<LB, true>), dim3((unsigned)(rows * tilesB)), dim3(256), 0, s, P);
+    if (sample) {
+      hipEventRecord(eb, s);
+      std::lock_guard<std::mutex> g(ps.mu);
+      ps.recs.push_back({ea, eb, rows});
+    }
   } else {
     P.tw = twi;
     P.tiles = tilesB;
@@ -250,6 +284,42 @@ void run_ntt(NttParams P, int64_t rows, bool inverse, const U2* twf, const U2* t
 }
 
 }  // namespace
+
+extern "C" int heqg_prof_start(int every) {
+  ProfState& ps = prof();
+  std::lock_guard<std::mutex> g(ps.mu);
+  for (auto& r : ps.recs) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  ps.recs.clear();
+  ps.seen = 0;
+  ps.every = every > 0 ? every : 1;
+  return 0;
+}
+
+extern "C" int heqg_prof_stop(double* avg_us, int64_t* launches, double* avg_rows) {
+  ProfState& ps = prof();
+  std::lock_guard<std::mutex> g(ps.mu);
+  ps.every = 0;
+  double tot = 0.0, rows = 0.0;
+  int64_t n = 0;
+  int rc = 0;
+  for (auto& r : ps.recs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) rc = -6;
+    tot += ms;
+    rows += (double)r.rows;
+    ++n;
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  ps.recs.clear();
+  if (avg_us) *avg_us = n ? 1000.0 * tot / n : 0.0;
+  if (launches) *launches = n;
+  if (avg_rows) *avg_rows = n ? rows / n : 0.0;
+  return rc;
+}
 
 int launch_ntt(const DevTables& t, int log2N, const RowSet& rs, bool inverse, hipStream_t s) {
   NttParams P;

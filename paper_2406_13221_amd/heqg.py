@@ -99,6 +99,8 @@ def lib():
         "heqg_add_pt": (i32, [vp, P(BatchS), vp, dbl, P(BatchS), vp]),
         "heqg_mul_const": (i32, [vp, P(BatchS), dbl, dbl, P(BatchS), vp, sz, vp]),
         "heqg_ntt": (i32, [vp, vp, i64, i32, i32, i32, vp]),
+        "heqg_prof_start": (i32, [i32]),
+        "heqg_prof_stop": (i32, [P(dbl), P(i64), P(dbl)]),
         "heqg_nag_ws_bytes": (sz, [vp, i32, i32]),
         "heqg_nag_qg_step": (i32, [vp, vp, P(BatchS), P(CtS), P(CtS), P(CtS), P(SigmoidS), P(NagStateS), i32, vp,
                                    sz, vp]),
@@ -116,6 +118,17 @@ def _check(rc):
     if rc < 0:
         raise HeqgError(rc, lib().heqg_last_error().decode())
     return rc
+
+
+def prof_start(every):
+    _check(lib().heqg_prof_start(int(every)))
+
+
+def prof_stop():
+    """(mean microseconds, sampled launches, mean rows per launch) of the forward NTT row pass."""
+    a, n, r = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+    _check(lib().heqg_prof_stop(ctypes.byref(a), ctypes.byref(n), ctypes.byref(r)))
+    return a.value, n.value, r.value
 
 
 def _torch():
