@@ -290,6 +290,16 @@ int heqg_ntt(heqg_ctx* ctx, uint64_t* dev_rows, int64_t n_rows, int first_prime,
 int heqg_prof_start(int every);
 int heqg_prof_stop(double* avg_us, int64_t* launches, double* avg_rows);
 
+/*
+ * Kernel-variant switches read by the launchers (process-wide; set by the
+ * autotuner in the Python package).  which = 0: forward NTT row pass,
+ * 1: inverse NTT row pass; value 0 = 16-byte accesses in the per-thread
+ * contiguous layout, 1 = coalesced accesses through an LDS transpose.
+ * Every variant computes identical results.  Returns -1 on a bad selector.
+ */
+int heqg_tune_set(int which, int value);
+int heqg_tune_get(int which);
+
 /* ------------------------------------------------------------------ */
 /* Training step (section 3.2 Algorithm 1; section 3.3; section 4.3)    */
 /* ------------------------------------------------------------------ */

@@ -58,7 +58,7 @@ static uint32_t h_brv(uint32_t x, int bits) {
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Section offsets (bytes) in the device table buffer; returns the total size.
-size_t ctx_layout(const heqg_params* p, bool check, std::string* err, size_t offs[8]) {
+size_t ctx_layout(const heqg_params* p, bool check, std::string* err, size_t offs[10]) {
   if (!p || !p->q_bits) {
     if (err) *err = "null params";
     return 0;
@@ -90,7 +90,7 @@ size_t ctx_layout(const heqg_params* p, bool check, std::string* err, size_t off
   size_t N = (size_t)1 << p->log2N, nq = p->n_q, np = p->n_p, nqp = nq + np;
   size_t alpha = (nq + p->dnum - 1) / p->dnum;
   size_t mu_stride = alpha + nqp * alpha;
-  size_t sz[7] = {
+  size_t sz[9] = {
       nqp * N * 16,                    // tw_fwd
       nqp * N * 16,                    // tw_inv
       nqp * sizeof(PrimeConst),        // pc
@@ -98,13 +98,15 @@ size_t ctx_layout(const heqg_params* p, bool check, std::string* err, size_t off
       nq * nq * 8,                     // rescale_q
       nq * p->dnum * mu_stride * 16,   // modup
       (np + nq * np + nq) * 16,        // moddown
+      nqp * N * 8,                     // tw_fwd_f
+      nqp * N * 8,                     // tw_inv_f
   };
   size_t o = 0;
-  for (int i = 0; i < 7; ++i) {
+  for (int i = 0; i < 9; ++i) {
     if (offs) offs[i] = o;
     o = align256(o + sz[i]);
   }
-  if (offs) offs[7] = o;
+  if (offs) offs[9] = o;
   return o;
 }
 
@@ -119,11 +121,14 @@ static void fill_pc(PrimeConst& c, uint64_t q, int log2N) {
   c.ninv = h_inv((uint64_t)1 << log2N, q);
   c.ninv_sh = h_shoup(c.ninv, q);
   c.pad = 0;
+  c.qd = (double)q;
+  c.qinv = 1.0 / (double)q;
+  c.ninv_d = (double)c.ninv;
 }
 
 int ctx_build(heqg_ctx* c, void* dev, size_t bytes, std::string* err) {
   const heqg_params* p = &c->p;
-  size_t offs[8];
+  size_t offs[10];
   size_t total = ctx_layout(p, true, err, offs);
   if (!total) return HEQG_ERR_UNSUPPORTED;
   if (!dev || bytes < total) {
@@ -181,10 +186,12 @@ int ctx_build(heqg_ctx* c, void* dev, size_t bytes, std::string* err) {
       pw[0] = 1;
       for (uint64_t j = 1; j < N; ++j) pw[j] = h_mul(pw[j - 1], r, q);
       uint64_t* tw = (dir ? twi : twf) + (size_t)k * N * 2;
+      double* twd = reinterpret_cast<double*>(host.data() + offs[dir ? 8 : 7]) + (size_t)k * N;
       for (uint64_t j = 0; j < N; ++j) {
         uint64_t w = pw[h_brv((uint32_t)j, logN)];
         tw[2 * j] = w;
         tw[2 * j + 1] = h_shoup(w, q);
+        twd[j] = (double)w;
       }
     }
   }
@@ -288,6 +295,8 @@ int ctx_build(heqg_ctx* c, void* dev, size_t bytes, std::string* err) {
   c->t.rescale_q = reinterpret_cast<const uint64_t*>(d + offs[4]);
   c->t.modup = reinterpret_cast<const uint64_t*>(d + offs[5]);
   c->t.moddown = reinterpret_cast<const uint64_t*>(d + offs[6]);
+  c->t.tw_fwd_f = reinterpret_cast<const double*>(d + offs[7]);
+  c->t.tw_inv_f = reinterpret_cast<const double*>(d + offs[8]);
   return HEQG_OK;
 }
 

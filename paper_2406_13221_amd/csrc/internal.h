@@ -31,6 +31,8 @@ struct DevTables {
   const uint64_t* rescale_q; // [n_q][n_q]: q_l mod q_i
   const uint64_t* modup;     // [n_q][dnum][mu_stride][2]
   const uint64_t* moddown;   // inv_hatP [n_p][2], hatP [n_q][n_p][2], Pinv [n_q][2]
+  const double* tw_fwd_f;    // [nqp][N]: psi^brv(k) as doubles (primes of <= FP_MAX_BITS bits)
+  const double* tw_inv_f;    // [nqp][N]: psi^-brv(k) as doubles
 };
 
 // Geometry the kernels need.

@@ -15,7 +15,48 @@ struct PrimeConst {
   uint64_t ninv_sh;
   int k;              // bit length of q
   int pad;
+  double qd;          // q as a double (exact for k <= 53)
+  double qinv;        // 1/q rounded
+  double ninv_d;      // N^-1 mod q as a double
 };
+
+// ---------------------------------------------------------------------------
+// Exact modular arithmetic carried in FP64 for primes of at most FP_MAX_BITS bits.
+// Values are integers held exactly in doubles (|x| < 2^53).  a*w mod q:
+//   h = fl(a*w), l = a*w - h (exact, FMA), qt = rint(h/q), t = (h - qt*q) + l
+// where h - qt*q is exact (FMA) because it is small; t = a*w - qt*q exactly,
+// |t| < q for |a| < 2^46 and w < 2^42.
+#define FP_MAX_BITS 42
+
+__device__ __forceinline__ double fmulmod(double a, double w, double q, double qi) {
+#pragma clang fp contract(off)
+  double h = a * w;
+  double l = __fma_rn(a, w, -h);
+  double qt = __builtin_rint(h * qi);
+  return __fma_rn(-qt, q, h) + l;
+}
+
+// symmetric reduction: result in [-q/2 - 1, q/2 + 1] for |x| < 2^52
+__device__ __forceinline__ double fred(double x, double q, double qi) {
+#pragma clang fp contract(off)
+  return __fma_rn(-__builtin_rint(x * qi), q, x);
+}
+
+// canonical residue of an exact integer x (|x| < 2^52) as uint64
+__device__ __forceinline__ uint64_t fcanon(double x, double q, double qi) {
+#pragma clang fp contract(off)
+  double t = fred(x, q, qi);
+  t = t < 0.0 ? t + q : t;
+  t = t >= q ? t - q : t;
+  double hi = __builtin_floor(t * 2.3283064365386963e-10);   // 2^-32, exact
+  double lo = __fma_rn(hi, -4294967296.0, t);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
+}
+
+__device__ __forceinline__ double u64_to_f(uint64_t v) {
+#pragma clang fp contract(off)
+  return __fma_rn((double)(uint32_t)(v >> 32), 4294967296.0, (double)(uint32_t)v);
+}
 
 __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
 

@@ -13,8 +13,17 @@
 // the elements {j + T*r} of its sub-transform (stages with distance >= T),
 // then, after one exchange through LDS, the 16 consecutive elements
 // {16*j + r} (stages with distance < T); T = S/16 threads share a
-// sub-transform of size S.  Butterflies use Shoup multiplication with lazy
-// reduction (Harvey): forward values live in [0, 4q), inverse in [0, 2q).
+// sub-transform of size S.
+//
+// Two arithmetic paths, chosen per workgroup from the prime's size (uniform,
+// so no divergence):
+//  * primes of at most FP_MAX_BITS bits: residues are exact integers held in
+//    FP64; a twiddle product is an FMA two-product plus a rounded quotient
+//    (8 FP64 instructions per butterfly).  Between the passes the values are
+//    kept as doubles in the row buffer; only the final output is made canonical.
+//  * larger primes: 64-bit Shoup multiplication with lazy reduction (Harvey);
+//    forward values live in [0, 4q), inverse in [0, 2q).
+// Both paths produce the canonical residues of the same transform.
 #include <mutex>
 #include <vector>
 
@@ -33,11 +42,14 @@ struct NttParams {
   int64_t sa, sb;
   int pidx[HEQG_MAX_PRIMES];
   const U2* tw;
+  const double* twf;
   const PrimeConst* pc;
   int logN;
   int tiles;
+  int group;
 };
 
+// ------------------------------------------------------------------ integer butterflies
 __device__ __forceinline__ void ct_bfly(uint64_t& X, uint64_t& Y, U2 w, uint64_t q, uint64_t two_q) {
   uint64_t x = X >= two_q ? X - two_q : X;
   uint64_t t = mul_shoup_lazy(Y, w.a, w.b, q);
@@ -53,56 +65,59 @@ __device__ __forceinline__ void gs_bfly(uint64_t& X, uint64_t& Y, U2 w, uint64_t
   Y = mul_shoup_lazy(d, w.a, w.b, q);
 }
 
-// Forward stages on layout {j + T*r}: local stages 0..3, twiddle (base)*2^st + (r >> (4-st)).
-template <bool FWD>
-__device__ __forceinline__ void stages_strided(uint64_t (&x)[16], const U2* tw, int64_t base, uint64_t q,
-                                               uint64_t two_q, int st0) {
+// ------------------------------------------------------------------ FP64 butterflies
+__device__ __forceinline__ void ct_f(double& X, double& Y, double w, double q, double qi) {
+#pragma clang fp contract(off)
+  double t = fmulmod(Y, w, q, qi);
+  double x = X;
+  X = x + t;
+  Y = x - t;
+}
+
+__device__ __forceinline__ void gs_f(double& X, double& Y, double w, double q, double qi) {
+#pragma clang fp contract(off)
+  double s = fred(X + Y, q, qi);
+  double d = X - Y;
+  X = s;
+  Y = fmulmod(d, w, q, qi);
+}
+
+// Stages on layout {j + T*r}: local stages 0..3 (distance 8T..T), twiddle base*2^s + (r >> (4-s)).
+template <bool FWD, typename V, typename TW, typename BF>
+__device__ __forceinline__ void stages_strided(V (&x)[16], const TW* tw, int64_t base, BF bf) {
   if (FWD) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int dr = 8 >> s;
-      const int64_t m = base << (st0 + s);
+      const int64_t m = base << s;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        if ((r & dr) == 0) {
-          U2 w = tw[m + (r >> (4 - s))];
-          ct_bfly(x[r], x[r + dr], w, q, two_q);
-        }
-      }
+      for (int r = 0; r < 16; ++r)
+        if ((r & dr) == 0) bf(x[r], x[r + dr], tw[m + (r >> (4 - s))]);
     }
   } else {
 #pragma unroll
     for (int s = 3; s >= 0; --s) {
       const int dr = 8 >> s;
-      const int64_t m = base << (st0 + s);
+      const int64_t m = base << s;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        if ((r & dr) == 0) {
-          U2 w = tw[m + (r >> (4 - s))];
-          gs_bfly(x[r], x[r + dr], w, q, two_q);
-        }
-      }
+      for (int r = 0; r < 16; ++r)
+        if ((r & dr) == 0) bf(x[r], x[r + dr], tw[m + (r >> (4 - s))]);
     }
   }
 }
 
 // Stages on layout {16*j + r} (distance < T): local stage st (4 <= st < LOGS), distance 2^(LOGS-st-1),
 // group (16*j + r) >> (LOGS - st), twiddle base*2^st + group.
-template <int LOGS, bool FWD>
-__device__ __forceinline__ void stages_contig(uint64_t (&x)[16], const U2* tw, int64_t base, int j, uint64_t q,
-                                              uint64_t two_q) {
+template <int LOGS, bool FWD, typename V, typename TW, typename BF>
+__device__ __forceinline__ void stages_contig(V (&x)[16], const TW* tw, int64_t base, int j, BF bf) {
   if (FWD) {
 #pragma unroll
     for (int st = 4; st < LOGS; ++st) {
       const int d = 1 << (LOGS - st - 1);
       const int64_t m = base << st;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        if ((r & d) == 0) {
-          U2 w = tw[m + ((16 * j + r) >> (LOGS - st))];
-          ct_bfly(x[r], x[r + d], w, q, two_q);
-        }
-      }
+      for (int r = 0; r < 16; ++r)
+        if ((r & d) == 0) bf(x[r], x[r + d], tw[m + ((16 * j + r) >> (LOGS - st))]);
     }
   } else {
 #pragma unroll
@@ -110,128 +125,271 @@ __device__ __forceinline__ void stages_contig(uint64_t (&x)[16], const U2* tw, i
       const int d = 1 << (LOGS - st - 1);
       const int64_t m = base << st;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        if ((r & d) == 0) {
-          U2 w = tw[m + ((16 * j + r) >> (LOGS - st))];
-          gs_bfly(x[r], x[r + d], w, q, two_q);
-        }
-      }
+      for (int r = 0; r < 16; ++r)
+        if ((r & d) == 0) bf(x[r], x[r + d], tw[m + ((16 * j + r) >> (LOGS - st))]);
     }
   }
 }
 
-__device__ __forceinline__ uint64_t* row_ptr(const NttParams& P, int64_t rest, int& ii) {
-  int64_t nab = P.na * P.nb;
-  int64_t ab = rest % nab;
-  ii = (int)(rest / nab);
-  int64_t ia = ab / P.nb, ib = ab % P.nb;
-  return P.data + ia * P.sa + ib * P.sb + ((int64_t)ii << P.logN);
-}
+__device__ __forceinline__ double as_f(uint64_t v) { return __longlong_as_double((long long)v); }
+__device__ __forceinline__ uint64_t as_u(double v) { return (uint64_t)__double_as_longlong(v); }
 
-// Pass A: columns of the N1 x N2 view, N1 = 2^LOGS.
-template <int LOGS, bool FWD>
-__global__ void __launch_bounds__(256) k_ntt_cols(NttParams P) {
+// ------------------------------------------------------------------ pass A (columns)
+template <int LOGS, bool FWD, bool FP>
+__device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, int p, int tile, uint64_t* lds) {
   constexpr int S = 1 << LOGS, T = S / 16, C = 256 / T;
-  __shared__ uint64_t lds[4096];
   const int tid = threadIdx.x;
-  const int tile = (int)(blockIdx.x % P.tiles);
-  int ii;
-  uint64_t* row = row_ptr(P, blockIdx.x / P.tiles, ii);
-  const int p = P.pidx[ii];
-  const uint64_t q = P.pc[p].q, two_q = 2 * q;
-  const U2* tw = P.tw + ((int64_t)p << P.logN);
+  const PrimeConst pc = P.pc[p];
   const int N2 = 1 << (P.logN - LOGS);
   const int cl = tid % C, kg = tid / C;
   const int c = tile * C + cl;
-  uint64_t x[16];
-  if (FWD) {
+  if (FP) {
+    const double q = pc.qd, qi = pc.qinv;
+    const double* tw = P.twf + ((int64_t)p << P.logN);
+    auto bf = [&](double& X, double& Y, double w) {
+      if (FWD) ct_f(X, Y, w, q, qi); else gs_f(X, Y, w, q, qi);
+    };
+    double x[16];
+    if (FWD) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) x[r] = row[(int64_t)(kg + T * r) * N2 + c];
-    stages_strided<true>(x, tw, 1, q, two_q, 0);
+      for (int r = 0; r < 16; ++r) x[r] = u64_to_f(row[(int64_t)(kg + T * r) * N2 + c]);
+      stages_strided<true>(x, tw, 1, bf);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) lds[(kg + T * r) * C + cl] = x[r];
-    __syncthreads();
+      for (int r = 0; r < 16; ++r) lds[(kg + T * r) * C + cl] = as_u(x[r]);
+      __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 16; ++r) x[r] = lds[(16 * kg + r) * C + cl];
-    stages_contig<LOGS, true>(x, tw, 1, kg, q, two_q);
+      for (int r = 0; r < 16; ++r) x[r] = as_f(lds[(16 * kg + r) * C + cl]);
+      stages_contig<LOGS, true>(x, tw, 1, kg, bf);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) row[(int64_t)(16 * kg + r) * N2 + c] = x[r];
+      for (int r = 0; r < 16; ++r) row[(int64_t)(16 * kg + r) * N2 + c] = as_u(x[r]);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) x[r] = as_f(row[(int64_t)(16 * kg + r) * N2 + c]);
+      stages_contig<LOGS, false>(x, tw, 1, kg, bf);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) lds[(16 * kg + r) * C + cl] = as_u(x[r]);
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 16; ++r) x[r] = as_f(lds[(kg + T * r) * C + cl]);
+      stages_strided<false>(x, tw, 1, bf);
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        row[(int64_t)(kg + T * r) * N2 + c] = fcanon(fmulmod(x[r], pc.ninv_d, q, qi), q, qi);
+    }
   } else {
+    const uint64_t q = pc.q, two_q = 2 * q;
+    const U2* tw = P.tw + ((int64_t)p << P.logN);
+    auto bf = [&](uint64_t& X, uint64_t& Y, U2 w) {
+      if (FWD) ct_bfly(X, Y, w, q, two_q); else gs_bfly(X, Y, w, q, two_q);
+    };
+    uint64_t x[16];
+    if (FWD) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) x[r] = row[(int64_t)(16 * kg + r) * N2 + c];
-    stages_contig<LOGS, false>(x, tw, 1, kg, q, two_q);
+      for (int r = 0; r < 16; ++r) x[r] = row[(int64_t)(kg + T * r) * N2 + c];
+      stages_strided<true>(x, tw, 1, bf);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) lds[(16 * kg + r) * C + cl] = x[r];
-    __syncthreads();
+      for (int r = 0; r < 16; ++r) lds[(kg + T * r) * C + cl] = x[r];
+      __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 16; ++r) x[r] = lds[(kg + T * r) * C + cl];
-    stages_strided<false>(x, tw, 1, q, two_q, 0);
-    const PrimeConst pc = P.pc[p];
+      for (int r = 0; r < 16; ++r) x[r] = lds[(16 * kg + r) * C + cl];
+      stages_contig<LOGS, true>(x, tw, 1, kg, bf);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) row[(int64_t)(kg + T * r) * N2 + c] = mul_shoup(x[r], pc.ninv, pc.ninv_sh, q);
+      for (int r = 0; r < 16; ++r) row[(int64_t)(16 * kg + r) * N2 + c] = x[r];
+    } else {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) x[r] = row[(int64_t)(16 * kg + r) * N2 + c];
+      stages_contig<LOGS, false>(x, tw, 1, kg, bf);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) lds[(16 * kg + r) * C + cl] = x[r];
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 16; ++r) x[r] = lds[(kg + T * r) * C + cl];
+      stages_strided<false>(x, tw, 1, bf);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) row[(int64_t)(kg + T * r) * N2 + c] = mul_shoup(x[r], pc.ninv, pc.ninv_sh, q);
+    }
   }
 }
 
-// LDS position of element l of a row in pass B (XOR swizzle of the low 4 bits).
+template <int LOGS, bool FWD>
+__global__ void __launch_bounds__(256) k_ntt_cols(NttParams P) {
+  __shared__ uint64_t lds[4096];
+  const int tile = (int)(blockIdx.x % P.tiles);
+  const int64_t rest = blockIdx.x / P.tiles;
+  const int64_t nab = P.na * P.nb;
+  const int64_t ab = rest % nab;
+  const int ii = (int)(rest / nab);
+  uint64_t* row = P.data + (ab / P.nb) * P.sa + (ab % P.nb) * P.sb + ((int64_t)ii << P.logN);
+  const int p = P.pidx[ii];
+  if (P.pc[p].k <= FP_MAX_BITS)
+    cols_body<LOGS, FWD, true>(P, row, p, tile, lds);
+  else
+    cols_body<LOGS, FWD, false>(P, row, p, tile, lds);
+}
+
+// ------------------------------------------------------------------ pass B (rows)
+// LDS position of element l of a row (XOR swizzle of the low 4 bits).
 __device__ __forceinline__ int swz(int l) { return l ^ ((l >> 4) & 15); }
 
-// Pass B: N1 contiguous rows of N2 = 2^LOGS; global stages log2(N1) .. logN-1.
-template <int LOGS, bool FWD>
+// A workgroup transforms R = 256/T sub-rows: P.group rows of the same index b taken
+// from P.group limbs that share one prime (so they share all twiddles), times R/group
+// consecutive b.  COAL: accesses in the {16*j + r} layout go through an extra LDS
+// transpose so that every global load/store is coalesced.
+template <int LOGS, bool FWD, bool COAL, bool FP>
+__device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, int p, int b, uint64_t* l) {
+  constexpr int S = 1 << LOGS, T = S / 16;
+  const int j = threadIdx.x % T;
+  const PrimeConst pc = P.pc[p];
+  const int N1 = 1 << (P.logN - LOGS);
+  const int64_t base = N1 + b;
+  if (FP) {
+    const double q = pc.qd, qi = pc.qinv;
+    const double* tw = P.twf + ((int64_t)p << P.logN);
+    auto bf = [&](double& X, double& Y, double w) {
+      if (FWD) ct_f(X, Y, w, q, qi); else gs_f(X, Y, w, q, qi);
+    };
+    double x[16];
+    if (FWD) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) x[r] = as_f(src[j + T * r]);
+      stages_strided<true>(x, tw, base, bf);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) l[swz(j + T * r)] = as_u(x[r]);
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 16; ++r) x[r] = as_f(l[swz(16 * j + r)]);
+      stages_contig<LOGS, true>(x, tw, base, j, bf);
+      uint64_t y[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) y[r] = fcanon(x[r], q, qi);
+      if (COAL) {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) l[swz(16 * j + r)] = y[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) src[j + T * r] = l[swz(j + T * r)];
+      } else {
+        U2* dst = reinterpret_cast<U2*>(src + 16 * j);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) dst[r] = U2{y[2 * r], y[2 * r + 1]};
+      }
+    } else {
+      if (COAL) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) l[swz(j + T * r)] = src[j + T * r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[r] = u64_to_f(l[swz(16 * j + r)]);
+        __syncthreads();
+      } else {
+        const U2* s2 = reinterpret_cast<const U2*>(src + 16 * j);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          U2 v = s2[r];
+          x[2 * r] = u64_to_f(v.a);
+          x[2 * r + 1] = u64_to_f(v.b);
+        }
+      }
+      stages_contig<LOGS, false>(x, tw, base, j, bf);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) l[swz(16 * j + r)] = as_u(x[r]);
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 16; ++r) x[r] = as_f(l[swz(j + T * r)]);
+      stages_strided<false>(x, tw, base, bf);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) src[j + T * r] = as_u(x[r]);
+    }
+  } else {
+    const uint64_t q = pc.q, two_q = 2 * q;
+    const U2* tw = P.tw + ((int64_t)p << P.logN);
+    auto bf = [&](uint64_t& X, uint64_t& Y, U2 w) {
+      if (FWD) ct_bfly(X, Y, w, q, two_q); else gs_bfly(X, Y, w, q, two_q);
+    };
+    uint64_t x[16];
+    if (FWD) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) x[r] = src[j + T * r];
+      stages_strided<true>(x, tw, base, bf);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) l[swz(j + T * r)] = x[r];
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 16; ++r) x[r] = l[swz(16 * j + r)];
+      stages_contig<LOGS, true>(x, tw, base, j, bf);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        uint64_t v = x[r] >= two_q ? x[r] - two_q : x[r];
+        x[r] = v >= q ? v - q : v;
+      }
+      if (COAL) {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) l[swz(16 * j + r)] = x[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) src[j + T * r] = l[swz(j + T * r)];
+      } else {
+        U2* dst = reinterpret_cast<U2*>(src + 16 * j);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) dst[r] = U2{x[2 * r], x[2 * r + 1]};
+      }
+    } else {
+      if (COAL) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) l[swz(j + T * r)] = src[j + T * r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[r] = l[swz(16 * j + r)];
+        __syncthreads();
+      } else {
+        const U2* s2 = reinterpret_cast<const U2*>(src + 16 * j);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          U2 v = s2[r];
+          x[2 * r] = v.a;
+          x[2 * r + 1] = v.b;
+        }
+      }
+      stages_contig<LOGS, false>(x, tw, base, j, bf);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) l[swz(16 * j + r)] = x[r];
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 16; ++r) x[r] = l[swz(j + T * r)];
+      stages_strided<false>(x, tw, base, bf);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) src[j + T * r] = x[r];
+    }
+  }
+}
+
+template <int LOGS, bool FWD, bool COAL>
 __global__ void __launch_bounds__(256) k_ntt_rows(NttParams P) {
   constexpr int S = 1 << LOGS, T = S / 16, R = 256 / T;
   __shared__ uint64_t lds[4096];
   const int tid = threadIdx.x;
+  const int G = P.group;
   const int tile = (int)(blockIdx.x % P.tiles);
-  int ii;
-  uint64_t* row = row_ptr(P, blockIdx.x / P.tiles, ii);
+  const int64_t rest = blockIdx.x / P.tiles;
+  const int64_t nab = P.na * P.nb, ngrp = nab / G;
+  const int64_t lg = rest % ngrp;
+  const int ii = (int)(rest / ngrp);
+  const int rl = tid / T;
+  const int64_t ab = lg * G + rl % G;
+  const int b = tile * (R / G) + rl / G;
+  uint64_t* row = P.data + (ab / P.nb) * P.sa + (ab % P.nb) * P.sb + ((int64_t)ii << P.logN);
   const int p = P.pidx[ii];
-  const uint64_t q = P.pc[p].q, two_q = 2 * q;
-  const U2* tw = P.tw + ((int64_t)p << P.logN);
-  const int N1 = 1 << (P.logN - LOGS);
-  const int rl = tid / T, j = tid % T;
-  const int b = tile * R + rl;
-  const int64_t base = N1 + b;
   uint64_t* src = row + (int64_t)b * S;
   uint64_t* l = lds + rl * S;
-  uint64_t x[16];
-  if (FWD) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) x[r] = src[j + T * r];
-    stages_strided<true>(x, tw, base, q, two_q, 0);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) l[swz(j + T * r)] = x[r];
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < 16; ++r) x[r] = l[swz(16 * j + r)];
-    stages_contig<LOGS, true>(x, tw, base, j, q, two_q);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      uint64_t v = x[r] >= two_q ? x[r] - two_q : x[r];
-      x[r] = v >= q ? v - q : v;
-    }
-    U2* dst = reinterpret_cast<U2*>(src + 16 * j);
-#pragma unroll
-    for (int r = 0; r < 8; ++r) dst[r] = U2{x[2 * r], x[2 * r + 1]};
-  } else {
-    const U2* s2 = reinterpret_cast<const U2*>(src + 16 * j);
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      U2 v = s2[r];
-      x[2 * r] = v.a;
-      x[2 * r + 1] = v.b;
-    }
-    stages_contig<LOGS, false>(x, tw, base, j, q, two_q);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) l[swz(16 * j + r)] = x[r];
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < 16; ++r) x[r] = l[swz(j + T * r)];
-    stages_strided<false>(x, tw, base, q, two_q, 0);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) src[j + T * r] = x[r];
-  }
+  if (P.pc[p].k <= FP_MAX_BITS)
+    rows_body<LOGS, FWD, COAL, true>(P, src, p, b, l);
+  else
+    rows_body<LOGS, FWD, COAL, false>(P, src, p, b, l);
 }
 
+// ------------------------------------------------------------------ launch
 // sampled launch timing of the forward row pass
 struct ProfState {
   std::mutex mu;
@@ -248,13 +406,34 @@ ProfState& prof() {
   return p;
 }
 
+// Row-pass variant: 0 = 16-byte accesses in the consecutive layout, 1 = LDS-transposed
+// coalesced accesses.  Process-wide choice per direction (set by the tuner).
+int g_rows_variant[2] = {1, 1};
+
+template <int LB, bool FWD>
+void launch_rows(const NttParams& P, unsigned blocks, hipStream_t s) {
+  if (g_rows_variant[FWD ? 0 : 1])
+    hipLaunchKernelGGL((k_ntt_rows<LB, FWD, true>), dim3(blocks), dim3(256), 0, s, P);
+  else
+    hipLaunchKernelGGL((k_ntt_rows<LB, FWD, false>), dim3(blocks), dim3(256), 0, s, P);
+}
+
 template <int LA, int LB>
-void run_ntt(NttParams P, int64_t rows, bool inverse, const U2* twf, const U2* twi, hipStream_t s) {
+void run_ntt(NttParams P, int64_t rows, bool inverse, const U2* twf, const U2* twi, const double* twff,
+             const double* twif, hipStream_t s) {
   const int N1 = 1 << LA, N2 = 1 << LB;
   const int tilesA = N2 / (256 / ((1 << LA) / 16));
-  const int tilesB = N1 / (256 / ((1 << LB) / 16));
+  const int RB = 256 / ((1 << LB) / 16);
+  // same-prime limbs per workgroup in the row pass: largest power of two <= RB dividing na*nb
+  const int64_t nab = P.na * P.nb;
+  int G = 1;
+  while (G * 2 <= RB && nab % (G * 2) == 0) G *= 2;
+  P.group = G;
+  const int tilesB = N1 / (RB / G);
+  const unsigned blocksB = (unsigned)(rows / G * tilesB);
   if (!inverse) {
     P.tw = twf;
+    P.twf = twff;
     P.tiles = tilesA;
     hipLaunchKernelGGL((k_ntt_cols<LA, true>), dim3((unsigned)(rows * tilesA)), dim3(256), 0, s, P);
     P.tiles = tilesB;
@@ -268,7 +447,7 @@ void run_ntt(NttParams P, int64_t rows, bool inverse, const U2* twf, const U2* t
         sample = true;
     }
     if (sample) hipEventRecord(ea, s);
-    hipLaunchKernelGGL((k_ntt_rows<LB, true>), dim3((unsigned)(rows * tilesB)), dim3(256), 0, s, P);
+    launch_rows<LB, true>(P, blocksB, s);
     if (sample) {
       hipEventRecord(eb, s);
       std::lock_guard<std::mutex> g(ps.mu);
@@ -276,14 +455,26 @@ void run_ntt(NttParams P, int64_t rows, bool inverse, const U2* twf, const U2* t
     }
   } else {
     P.tw = twi;
+    P.twf = twif;
     P.tiles = tilesB;
-    hipLaunchKernelGGL((k_ntt_rows<LB, false>), dim3((unsigned)(rows * tilesB)), dim3(256), 0, s, P);
+    launch_rows<LB, false>(P, blocksB, s);
     P.tiles = tilesA;
     hipLaunchKernelGGL((k_ntt_cols<LA, false>), dim3((unsigned)(rows * tilesA)), dim3(256), 0, s, P);
   }
 }
 
 }  // namespace
+
+extern "C" int heqg_tune_set(int which, int value) {
+  if (which < 0 || which > 1 || value < 0 || value > 1) return -1;
+  g_rows_variant[which] = value;
+  return 0;
+}
+
+extern "C" int heqg_tune_get(int which) {
+  if (which < 0 || which > 1) return -1;
+  return g_rows_variant[which];
+}
 
 extern "C" int heqg_prof_start(int every) {
   ProfState& ps = prof();
@@ -333,17 +524,19 @@ int launch_ntt(const DevTables& t, int log2N, const RowSet& rs, bool inverse, hi
   P.pc = t.pc;
   P.logN = log2N;
   P.tw = nullptr;
+  P.twf = nullptr;
   P.tiles = 1;
+  P.group = 1;
   int64_t rows = rs.na * rs.nb * rs.ni;
   if (rows <= 0) return 0;
   const U2* twf = reinterpret_cast<const U2*>(t.tw_fwd);
   const U2* twi = reinterpret_cast<const U2*>(t.tw_inv);
   switch (log2N) {
-    case 12: run_ntt<6, 6>(P, rows, inverse, twf, twi, s); break;
-    case 13: run_ntt<6, 7>(P, rows, inverse, twf, twi, s); break;
-    case 14: run_ntt<7, 7>(P, rows, inverse, twf, twi, s); break;
-    case 15: run_ntt<7, 8>(P, rows, inverse, twf, twi, s); break;
-    case 16: run_ntt<8, 8>(P, rows, inverse, twf, twi, s); break;
+    case 12: run_ntt<6, 6>(P, rows, inverse, twf, twi, t.tw_fwd_f, t.tw_inv_f, s); break;
+    case 13: run_ntt<6, 7>(P, rows, inverse, twf, twi, t.tw_fwd_f, t.tw_inv_f, s); break;
+    case 14: run_ntt<7, 7>(P, rows, inverse, twf, twi, t.tw_fwd_f, t.tw_inv_f, s); break;
+    case 15: run_ntt<7, 8>(P, rows, inverse, twf, twi, t.tw_fwd_f, t.tw_inv_f, s); break;
+    case 16: run_ntt<8, 8>(P, rows, inverse, twf, twi, t.tw_fwd_f, t.tw_inv_f, s); break;
     default: return -1;
   }
   return 0;

@@ -99,6 +99,8 @@ def lib():
         "heqg_add_pt": (i32, [vp, P(BatchS), vp, dbl, P(BatchS), vp]),
         "heqg_mul_const": (i32, [vp, P(BatchS), dbl, dbl, P(BatchS), vp, sz, vp]),
         "heqg_ntt": (i32, [vp, vp, i64, i32, i32, i32, vp]),
+        "heqg_tune_set": (i32, [i32, i32]),
+        "heqg_tune_get": (i32, [i32]),
         "heqg_prof_start": (i32, [i32]),
         "heqg_prof_stop": (i32, [P(dbl), P(i64), P(dbl)]),
         "heqg_nag_ws_bytes": (sz, [vp, i32, i32]),
