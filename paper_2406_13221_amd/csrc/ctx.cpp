@@ -58,7 +58,7 @@ static uint32_t h_brv(uint32_t x, int bits) {
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Section offsets (bytes) in the device table buffer; returns the total size.
-size_t ctx_layout(const heqg_params* p, bool check, std::string* err, size_t offs[10]) {
+size_t ctx_layout(const heqg_params* p, bool check, std::string* err, size_t offs[12]) {
   if (!p || !p->q_bits) {
     if (err) *err = "null params";
     return 0;
@@ -68,8 +68,9 @@ size_t ctx_layout(const heqg_params* p, bool check, std::string* err, size_t off
       if (err) *err = "log2N must be in [12, 16]";
       return 0;
     }
-    if (p->n_q < 1 || p->n_p < 1 || p->n_q + p->n_p > HEQG_MAX_PRIMES || p->dnum < 1 || p->dnum > p->n_q) {
-      if (err) *err = "bad prime counts or dnum";
+    if (p->n_q < 1 || p->n_p < 1 || p->n_q + p->n_p > HEQG_MAX_PRIMES || p->dnum < 1 || p->dnum > p->n_q ||
+        p->dnum > 8) {
+      if (err) *err = "bad prime counts or dnum (1 <= dnum <= min(n_q, 8))";
       return 0;
     }
     int alpha = (p->n_q + p->dnum - 1) / p->dnum;
@@ -90,7 +91,7 @@ size_t ctx_layout(const heqg_params* p, bool check, std::string* err, size_t off
   size_t N = (size_t)1 << p->log2N, nq = p->n_q, np = p->n_p, nqp = nq + np;
   size_t alpha = (nq + p->dnum - 1) / p->dnum;
   size_t mu_stride = alpha + nqp * alpha;
-  size_t sz[9] = {
+  size_t sz[11] = {
       nqp * N * 16,                    // tw_fwd
       nqp * N * 16,                    // tw_inv
       nqp * sizeof(PrimeConst),        // pc
@@ -100,13 +101,15 @@ size_t ctx_layout(const heqg_params* p, bool check, std::string* err, size_t off
       (np + nq * np + nq) * 16,        // moddown
       nqp * N * 8,                     // tw_fwd_f
       nqp * N * 8,                     // tw_inv_f
+      nq * p->dnum * nqp * alpha * 16, // modup_f
+      nq * np * 16,                    // moddown_f
   };
   size_t o = 0;
-  for (int i = 0; i < 9; ++i) {
+  for (int i = 0; i < 11; ++i) {
     if (offs) offs[i] = o;
     o = align256(o + sz[i]);
   }
-  if (offs) offs[9] = o;
+  if (offs) offs[11] = o;
   return o;
 }
 
@@ -128,7 +131,7 @@ static void fill_pc(PrimeConst& c, uint64_t q, int log2N) {
 
 int ctx_build(heqg_ctx* c, void* dev, size_t bytes, std::string* err) {
   const heqg_params* p = &c->p;
-  size_t offs[10];
+  size_t offs[12];
   size_t total = ctx_layout(p, true, err, offs);
   if (!total) return HEQG_ERR_UNSUPPORTED;
   if (!dev || bytes < total) {
@@ -230,6 +233,10 @@ int ctx_build(heqg_ctx* c, void* dev, size_t bytes, std::string* err) {
           uint64_t* e = tab + 2 * (alpha + gi * alpha + k);
           e[0] = hat;
           e[1] = h_shoup(hat, t);
+          double* ef = reinterpret_cast<double*>(host.data() + offs[9]) +
+                       2 * ((((size_t)l * p->dnum + j) * nqp + gi) * alpha + k);
+          ef[0] = (double)hat;
+          ef[1] = (double)h_mul(hat, (uint64_t)((((hu128)1) << 32) % t), t);
         }
       }
     }
@@ -252,6 +259,9 @@ int ctx_build(heqg_ctx* c, void* dev, size_t bytes, std::string* err) {
       uint64_t* e = md + 2 * np + 2 * ((size_t)i * np + k);
       e[0] = hat;
       e[1] = h_shoup(hat, qi);
+      double* ef = reinterpret_cast<double*>(host.data() + offs[10]) + 2 * ((size_t)i * np + k);
+      ef[0] = (double)hat;
+      ef[1] = (double)h_mul(hat, (uint64_t)((((hu128)1) << 32) % qi), qi);
       P = h_mul(P, c->primes[nq + k] % qi, qi);
     }
     uint64_t pinv = h_inv(P, qi);
@@ -297,6 +307,8 @@ int ctx_build(heqg_ctx* c, void* dev, size_t bytes, std::string* err) {
   c->t.moddown = reinterpret_cast<const uint64_t*>(d + offs[6]);
   c->t.tw_fwd_f = reinterpret_cast<const double*>(d + offs[7]);
   c->t.tw_inv_f = reinterpret_cast<const double*>(d + offs[8]);
+  c->t.modup_f = reinterpret_cast<const double*>(d + offs[9]);
+  c->t.moddown_f = reinterpret_cast<const double*>(d + offs[10]);
   return HEQG_OK;
 }
 

@@ -33,6 +33,8 @@ struct DevTables {
   const uint64_t* moddown;   // inv_hatP [n_p][2], hatP [n_q][n_p][2], Pinv [n_q][2]
   const double* tw_fwd_f;    // [nqp][N]: psi^brv(k) as doubles (primes of <= FP_MAX_BITS bits)
   const double* tw_inv_f;    // [nqp][N]: psi^-brv(k) as doubles
+  const double* modup_f;     // [n_q][dnum][nqp][alpha][2]: (D/s_k mod t, 2^32 * D/s_k mod t) as doubles
+  const double* moddown_f;   // [n_q][n_p][2]: (P/p_k mod q_i, 2^32 * P/p_k mod q_i) as doubles
 };
 
 // Geometry the kernels need.

@@ -60,6 +60,16 @@ __device__ __forceinline__ void tensor1(uint64_t a0, uint64_t a1, uint64_t b0, u
   d1 = submod(submod(s, d0, pc.q), d2, pc.q);
 }
 
+// FP64 path (q <= FP_MAX_BITS bits): the three parts as exact integers of magnitude < 1.1 q
+__device__ __forceinline__ void tensor1f(uint64_t a0, uint64_t a1, uint64_t b0, uint64_t b1, double q, double qi,
+                                         double& d0, double& d1, double& d2) {
+#pragma clang fp contract(off)
+  double x0 = u64_to_f(a0), x1 = u64_to_f(a1), y0 = u64_to_f(b0), y1 = u64_to_f(b1);
+  d0 = fmulmod(x0, y0, q, qi);
+  d2 = fmulmod(x1, y1, q, qi);
+  d1 = fmulmod(x0, y1, q, qi) + fmulmod(x1, y0, q, qi);
+}
+
 __global__ void __launch_bounds__(EW_THREADS) k_tensor(const PrimeConst* pc, CtV a, CtV b, CtV out, int logN, int nl,
                                                         int acc) {
   const int chunks = (1 << logN) / EW_CHUNK;
@@ -74,8 +84,16 @@ __global__ void __launch_bounds__(EW_THREADS) k_tensor(const PrimeConst* pc, CtV
   const uint64_t* pb = b.d + ct * b.cs + off;
   U2 a0 = ld2(pa), a1 = ld2(pa + a.ps), b0 = ld2(pb), b1 = ld2(pb + b.ps);
   uint64_t d0a, d1a, d2a, d0b, d1b, d2b;
-  tensor1(a0.a, a1.a, b0.a, b1.a, P, d0a, d1a, d2a);
-  tensor1(a0.b, a1.b, b0.b, b1.b, P, d0b, d1b, d2b);
+  if (P.k <= FP_MAX_BITS) {
+    double f0, f1, f2;
+    tensor1f(a0.a, a1.a, b0.a, b1.a, P.qd, P.qinv, f0, f1, f2);
+    d0a = fcanon(f0, P.qd, P.qinv); d1a = fcanon(f1, P.qd, P.qinv); d2a = fcanon(f2, P.qd, P.qinv);
+    tensor1f(a0.b, a1.b, b0.b, b1.b, P.qd, P.qinv, f0, f1, f2);
+    d0b = fcanon(f0, P.qd, P.qinv); d1b = fcanon(f1, P.qd, P.qinv); d2b = fcanon(f2, P.qd, P.qinv);
+  } else {
+    tensor1(a0.a, a1.a, b0.a, b1.a, P, d0a, d1a, d2a);
+    tensor1(a0.b, a1.b, b0.b, b1.b, P, d0b, d1b, d2b);
+  }
   uint64_t* po = out.d + ct * out.cs + off;
   if (acc) {
     U2 o0 = ld2(po), o1 = ld2(po + out.ps), o2 = ld2(po + 2 * out.ps);
@@ -102,6 +120,31 @@ __global__ void __launch_bounds__(EW_THREADS) k_tensor_reduce(const PrimeConst* 
   if (accumulate) {
     U2 o0 = ld2(po), o1 = ld2(po + acc.ps), o2 = ld2(po + 2 * acc.ps);
     s0a = o0.a; s0b = o0.b; s1a = o1.a; s1b = o1.b; s2a = o2.a; s2b = o2.b;
+  }
+  if (P.k <= FP_MAX_BITS) {
+#pragma clang fp contract(off)
+    // exact integer sums in FP64; reduced every 16 terms so magnitudes stay below 2^46
+    const double q = P.qd, qi = P.qinv;
+    double f0a = u64_to_f(s0a), f1a = u64_to_f(s1a), f2a = u64_to_f(s2a);
+    double f0b = u64_to_f(s0b), f1b = u64_to_f(s1b), f2b = u64_to_f(s2b);
+    for (int64_t ct = 0; ct < count; ++ct) {
+      const uint64_t* pa = a.d + ct * a.cs + off;
+      const uint64_t* pb = b.d + ct * b.cs + off;
+      U2 a0 = ld2(pa), a1 = ld2(pa + a.ps), b0 = ld2(pb), b1 = ld2(pb + b.ps);
+      double d0, d1, d2;
+      tensor1f(a0.a, a1.a, b0.a, b1.a, q, qi, d0, d1, d2);
+      f0a += d0; f1a += d1; f2a += d2;
+      tensor1f(a0.b, a1.b, b0.b, b1.b, q, qi, d0, d1, d2);
+      f0b += d0; f1b += d1; f2b += d2;
+      if ((ct & 15) == 15) {
+        f0a = fred(f0a, q, qi); f1a = fred(f1a, q, qi); f2a = fred(f2a, q, qi);
+        f0b = fred(f0b, q, qi); f1b = fred(f1b, q, qi); f2b = fred(f2b, q, qi);
+      }
+    }
+    st2(po, fcanon(f0a, q, qi), fcanon(f0b, q, qi));
+    st2(po + acc.ps, fcanon(f1a, q, qi), fcanon(f1b, q, qi));
+    st2(po + 2 * acc.ps, fcanon(f2a, q, qi), fcanon(f2b, q, qi));
+    return;
   }
   for (int64_t ct = 0; ct < count; ++ct) {
     const uint64_t* pa = a.d + ct * a.cs + off;
@@ -262,9 +305,10 @@ __global__ void __launch_bounds__(EW_THREADS) k_rescale_combine(const PrimeConst
 // ModUp of digit j at level l: d (coefficient form, rows 0..l, ct stride (l+1)N) to every
 // prime outside the digit: sum_k [x_k * (D/s_k)^-1]_{s_k} * (D/s_k) mod target.
 // ext rows: targets in order (Q rows 0..l outside the digit, then P rows).
-__global__ void __launch_bounds__(EW_THREADS) k_modup(const PrimeConst* pc, const uint64_t* mu_tab, const uint64_t* dcoef,
-                                                       uint64_t* ext, int64_t ext_cs, int logN, int level, int lo,
-                                                       int sz, int nq, int np, int alpha) {
+__global__ void __launch_bounds__(EW_THREADS) k_modup(const PrimeConst* pc, const uint64_t* mu_tab,
+                                                       const double* muf, const uint64_t* dcoef, uint64_t* ext,
+                                                       int64_t ext_cs, int logN, int level, int lo, int sz, int nq,
+                                                       int np, int alpha) {
   const int chunks = (1 << logN) / EW_CHUNK;
   int64_t bid = blockIdx.x;
   int ch = (int)(bid % chunks);
@@ -273,9 +317,11 @@ __global__ void __launch_bounds__(EW_THREADS) k_modup(const PrimeConst* pc, cons
   int c = ch * EW_CHUNK + threadIdx.x * 2;
   const uint64_t* src = dcoef + ((ct * nl) << logN) + c;
   uint64_t y0[16], y1[16];
+  bool src_small = true;  // every source residue fits an exact double operand
 #pragma unroll 4
   for (int k = 0; k < sz; ++k) {
     const uint64_t q = pc[lo + k].q;
+    src_small = src_small && pc[lo + k].k <= FP_MAX_BITS;
     U2 x = ld2(src + ((int64_t)(lo + k) << logN));
     uint64_t w = mu_tab[2 * k], ws = mu_tab[2 * k + 1];
     y0[k] = mul_shoup(x.a, w, ws, q);
@@ -286,63 +332,127 @@ __global__ void __launch_bounds__(EW_THREADS) k_modup(const PrimeConst* pc, cons
   for (int g = 0; g < nl + np; ++g) {
     if (g >= lo && g < lo + sz) continue;
     int gp = g < nl ? g : nq + (g - nl);
-    const uint64_t q = pc[gp].q, two_q = 2 * q;
-    const uint64_t* h = mu_tab + 2 * (alpha + gp * alpha);
-    uint64_t a0 = 0, a1 = 0;
-    for (int k = 0; k < sz; ++k) {
-      uint64_t w = h[2 * k], ws = h[2 * k + 1];
-      a0 += mul_shoup_lazy(y0[k], w, ws, q);
-      a1 += mul_shoup_lazy(y1[k], w, ws, q);
-      a0 = a0 >= two_q ? a0 - two_q : a0;
-      a1 = a1 >= two_q ? a1 - two_q : a1;
+    const PrimeConst P = pc[gp];
+    if (P.k <= FP_MAX_BITS) {
+#pragma clang fp contract(off)
+      // y * hat = y_hi * (2^32 hat) + y_lo * hat; every product exact, |sum| < 2 sz q
+      const double* h = muf + 2 * (int64_t)gp * alpha;
+      double a0 = 0.0, a1 = 0.0;
+      for (int k = 0; k < sz; ++k) {
+        if (src_small) {
+          a0 += fmulmod(u64_to_f(y0[k]), h[2 * k], P.qd, P.qinv);
+          a1 += fmulmod(u64_to_f(y1[k]), h[2 * k], P.qd, P.qinv);
+        } else {
+          a0 += fmulmod((double)(uint32_t)(y0[k] >> 32), h[2 * k + 1], P.qd, P.qinv) +
+                fmulmod((double)(uint32_t)y0[k], h[2 * k], P.qd, P.qinv);
+          a1 += fmulmod((double)(uint32_t)(y1[k] >> 32), h[2 * k + 1], P.qd, P.qinv) +
+                fmulmod((double)(uint32_t)y1[k], h[2 * k], P.qd, P.qinv);
+        }
+      }
+      st2(dst + ((int64_t)e << logN), fcanon(a0, P.qd, P.qinv), fcanon(a1, P.qd, P.qinv));
+    } else {
+      const uint64_t q = P.q, two_q = 2 * q;
+      const uint64_t* h = mu_tab + 2 * (alpha + gp * alpha);
+      uint64_t a0 = 0, a1 = 0;
+      for (int k = 0; k < sz; ++k) {
+        uint64_t w = h[2 * k], ws = h[2 * k + 1];
+        a0 += mul_shoup_lazy(y0[k], w, ws, q);
+        a1 += mul_shoup_lazy(y1[k], w, ws, q);
+        a0 = a0 >= two_q ? a0 - two_q : a0;
+        a1 = a1 >= two_q ? a1 - two_q : a1;
+      }
+      st2(dst + ((int64_t)e << logN), csub(a0, q), csub(a1, q));
     }
-    st2(dst + ((int64_t)e << logN), csub(a0, q), csub(a1, q));
     ++e;
   }
 }
 
 // acc[ct][part][x] = sum_j v_j[x] * key_j[part][prime(x)], x over Q rows 0..l then P rows;
-// v_j[x] = d[x] for x in digit j, else the ModUp row of digit j.
+// v_j[x] = d[x] for x in digit j, else the ModUp row of digit j.  One thread owns two
+// coefficients of one extended row and loops over the ciphertexts of the batch, so
+// each key residue is read once per launch.
+constexpr int KS_MAX_DIGITS = 8;
 __global__ void __launch_bounds__(EW_THREADS) k_ks_inner(const PrimeConst* pc, CtV d, const uint64_t* ext, int64_t ext_cs,
                                                           int64_t ext_ds, const uint64_t* key, uint64_t* acc, int logN,
-                                                          int level, int nq, int np, int alpha) {
+                                                          int level, int nq, int np, int alpha, int64_t count) {
   const int chunks = (1 << logN) / EW_CHUNK;
   const int nl = level + 1, nx = nl + np, nqp = nq + np;
   int64_t bid = blockIdx.x;
   int ch = (int)(bid % chunks);
-  int64_t row = bid / chunks;
-  int x = (int)(row % nx);
-  int64_t ct = row / nx;
+  int x = (int)(bid / chunks);
   int c = ch * EW_CHUNK + threadIdx.x * 2;
   int gp = x < nl ? x : nq + (x - nl);
   const PrimeConst P = pc[gp];
   const int nd = (nl + alpha - 1) / alpha;
-  uint64_t s0a = 0, s0b = 0, s1a = 0, s1b = 0;
-  for (int j = 0; j < nd; ++j) {
-    int lo = j * alpha, hi = min(lo + alpha, nl);
-    U2 v;
-    if (x >= lo && x < hi) {
-      v = ld2(d.d + ct * d.cs + ((int64_t)x << logN) + c);
-    } else {
-      int e = x < lo ? x : x - (hi - lo);
-      v = ld2(ext + ct * ext_cs + j * ext_ds + ((int64_t)e << logN) + c);
+  U2 kb[KS_MAX_DIGITS], ka[KS_MAX_DIGITS];
+  const uint64_t* vsrc[KS_MAX_DIGITS];
+  int64_t vcs[KS_MAX_DIGITS];
+#pragma unroll
+  for (int j = 0; j < KS_MAX_DIGITS; ++j) {
+    if (j < nd) {
+      const uint64_t* kp = key + (((int64_t)j * 2 * nqp + gp) << logN) + c;
+      kb[j] = ld2(kp);
+      ka[j] = ld2(kp + ((int64_t)nqp << logN));
+      int lo = j * alpha, hi = min(lo + alpha, nl);
+      if (x >= lo && x < hi) {
+        vsrc[j] = d.d + ((int64_t)x << logN) + c;
+        vcs[j] = d.cs;
+      } else {
+        int e = x < lo ? x : x - (hi - lo);
+        vsrc[j] = ext + j * ext_ds + ((int64_t)e << logN) + c;
+        vcs[j] = ext_cs;
+      }
     }
-    const uint64_t* kb = key + (((int64_t)j * 2 * nqp + gp) << logN) + c;
-    const uint64_t* ka = kb + ((int64_t)nqp << logN);
-    U2 b = ld2(kb), a = ld2(ka);
-    s0a = addmod(s0a, mulmod(v.a, b.a, P), P.q);
-    s0b = addmod(s0b, mulmod(v.b, b.b, P), P.q);
-    s1a = addmod(s1a, mulmod(v.a, a.a, P), P.q);
-    s1b = addmod(s1b, mulmod(v.b, a.b, P), P.q);
   }
-  uint64_t* o = acc + ct * (int64_t)(2 * nx) * (1 << logN) + ((int64_t)x << logN) + c;
-  st2(o, s0a, s0b);
-  st2(o + ((int64_t)nx << logN), s1a, s1b);
+  const int64_t acs = (int64_t)(2 * nx) << logN;
+  uint64_t* o = acc + ((int64_t)x << logN) + c;
+  if (P.k <= FP_MAX_BITS) {
+#pragma clang fp contract(off)
+    const double q = P.qd, qi = P.qinv;
+    double fb0[KS_MAX_DIGITS], fb1[KS_MAX_DIGITS], fa0[KS_MAX_DIGITS], fa1[KS_MAX_DIGITS];
+#pragma unroll
+    for (int j = 0; j < KS_MAX_DIGITS; ++j)
+      if (j < nd) {
+        fb0[j] = u64_to_f(kb[j].a); fb1[j] = u64_to_f(kb[j].b);
+        fa0[j] = u64_to_f(ka[j].a); fa1[j] = u64_to_f(ka[j].b);
+      }
+    for (int64_t ct = 0; ct < count; ++ct) {
+      double s0a = 0, s0b = 0, s1a = 0, s1b = 0;
+#pragma unroll
+      for (int j = 0; j < KS_MAX_DIGITS; ++j)
+        if (j < nd) {
+          U2 v = ld2(vsrc[j] + ct * vcs[j]);
+          double va = u64_to_f(v.a), vb = u64_to_f(v.b);
+          s0a += fmulmod(va, fb0[j], q, qi);
+          s0b += fmulmod(vb, fb1[j], q, qi);
+          s1a += fmulmod(va, fa0[j], q, qi);
+          s1b += fmulmod(vb, fa1[j], q, qi);
+        }
+      st2(o + ct * acs, fcanon(s0a, q, qi), fcanon(s0b, q, qi));
+      st2(o + ct * acs + ((int64_t)nx << logN), fcanon(s1a, q, qi), fcanon(s1b, q, qi));
+    }
+    return;
+  }
+  for (int64_t ct = 0; ct < count; ++ct) {
+    uint64_t s0a = 0, s0b = 0, s1a = 0, s1b = 0;
+#pragma unroll
+    for (int j = 0; j < KS_MAX_DIGITS; ++j)
+      if (j < nd) {
+        U2 v = ld2(vsrc[j] + ct * vcs[j]);
+        s0a = addmod(s0a, mulmod(v.a, kb[j].a, P), P.q);
+        s0b = addmod(s0b, mulmod(v.b, kb[j].b, P), P.q);
+        s1a = addmod(s1a, mulmod(v.a, ka[j].a, P), P.q);
+        s1b = addmod(s1b, mulmod(v.b, ka[j].b, P), P.q);
+      }
+    st2(o + ct * acs, s0a, s0b);
+    st2(o + ct * acs + ((int64_t)nx << logN), s1a, s1b);
+  }
 }
 
 // conv[ct][part][i] = sum_k [x_k * (P/p_k)^-1]_{p_k} * (P/p_k) mod q_i  (x = P rows of acc, coefficient form)
-__global__ void __launch_bounds__(EW_THREADS) k_moddown_conv(const PrimeConst* pc, const uint64_t* md, const uint64_t* acc,
-                                                              uint64_t* conv, int logN, int level, int nq, int np) {
+__global__ void __launch_bounds__(EW_THREADS) k_moddown_conv(const PrimeConst* pc, const uint64_t* md,
+                                                              const double* mdf, const uint64_t* acc, uint64_t* conv,
+                                                              int logN, int level, int nq, int np) {
   const int chunks = (1 << logN) / EW_CHUNK;
   const int nl = level + 1, nx = nl + np;
   int64_t bid = blockIdx.x;
@@ -360,7 +470,22 @@ __global__ void __launch_bounds__(EW_THREADS) k_moddown_conv(const PrimeConst* p
   const uint64_t* hat = md + 2 * np;
   uint64_t* dst = conv + ((r * nl) << logN) + c;
   for (int i = 0; i < nl; ++i) {
-    const uint64_t q = pc[i].q, two_q = 2 * q;
+    const PrimeConst Pi = pc[i];
+    if (Pi.k <= FP_MAX_BITS) {
+#pragma clang fp contract(off)
+      // y * hat = y_hi * (2^32 hat) + y_lo * hat, exact products, |sum| < 2 np q
+      const double* h = mdf + 2 * (int64_t)i * np;
+      double a0 = 0.0, a1 = 0.0;
+      for (int k = 0; k < np; ++k) {
+        a0 += fmulmod((double)(uint32_t)(y0[k] >> 32), h[2 * k + 1], Pi.qd, Pi.qinv) +
+              fmulmod((double)(uint32_t)y0[k], h[2 * k], Pi.qd, Pi.qinv);
+        a1 += fmulmod((double)(uint32_t)(y1[k] >> 32), h[2 * k + 1], Pi.qd, Pi.qinv) +
+              fmulmod((double)(uint32_t)y1[k], h[2 * k], Pi.qd, Pi.qinv);
+      }
+      st2(dst + ((int64_t)i << logN), fcanon(a0, Pi.qd, Pi.qinv), fcanon(a1, Pi.qd, Pi.qinv));
+      continue;
+    }
+    const uint64_t q = Pi.q, two_q = 2 * q;
     const uint64_t* h = hat + 2 * (int64_t)i * np;
     uint64_t a0 = 0, a1 = 0;
     for (int k = 0; k < np; ++k) {
@@ -713,18 +838,20 @@ void k_modup_launch(const Geo& g, const DevTables& t, const uint64_t* dcoef, int
   int sz = nl - lo < g.alpha ? nl - lo : g.alpha;
   const uint64_t* tab = t.modup + 2 * (int64_t)((level * g.dnum + digit) * g.mu_stride);
   int64_t n = count * CHUNKS(g);
-  if (n) LAUNCH(k_modup, n, s, t.pc, tab, dcoef, ext, ext_cs, g.logN, level, lo, sz, g.n_q, g.n_p, g.alpha);
+  const double* tabf = t.modup_f + 2 * (int64_t)((level * g.dnum + digit) * g.nqp) * g.alpha;
+  if (n) LAUNCH(k_modup, n, s, t.pc, tab, tabf, dcoef, ext, ext_cs, g.logN, level, lo, sz, g.n_q, g.n_p, g.alpha);
 }
 void k_ks_inner_launch(const Geo& g, const DevTables& t, CtV d, const uint64_t* ext, int64_t ext_cs, int64_t ext_ds,
                        const uint64_t* key, uint64_t* acc, int64_t count, int level, hipStream_t s) {
   int nx = level + 1 + g.n_p;
-  int64_t n = count * nx * CHUNKS(g);
-  if (n) LAUNCH(k_ks_inner, n, s, t.pc, d, ext, ext_cs, ext_ds, key, acc, g.logN, level, g.n_q, g.n_p, g.alpha);
+  int64_t n = count > 0 ? (int64_t)nx * CHUNKS(g) : 0;
+  if (n)
+    LAUNCH(k_ks_inner, n, s, t.pc, d, ext, ext_cs, ext_ds, key, acc, g.logN, level, g.n_q, g.n_p, g.alpha, count);
 }
 void k_moddown_conv_launch(const Geo& g, const DevTables& t, const uint64_t* acc, uint64_t* conv, int64_t count,
                            int level, hipStream_t s) {
   int64_t n = count * 2 * CHUNKS(g);
-  if (n) LAUNCH(k_moddown_conv, n, s, t.pc, t.moddown, acc, conv, g.logN, level, g.n_q, g.n_p);
+  if (n) LAUNCH(k_moddown_conv, n, s, t.pc, t.moddown, t.moddown_f, acc, conv, g.logN, level, g.n_q, g.n_p);
 }
 void k_ks_combine_launch(const Geo& g, const DevTables& t, const uint64_t* acc, const uint64_t* conv, CtV base0,
                          CtV base1, bool has_base1, CtV out, int64_t count, int level, hipStream_t s) {
