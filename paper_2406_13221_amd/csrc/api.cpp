@@ -362,6 +362,10 @@ extern "C" int heqg_rotate(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch*
     set_err("rotate: output shape mismatch");
     return HEQG_ERR_ARG;
   }
+  if (out->data == in->data) {
+    set_err("rotate: output must not alias the input");
+    return HEQG_ERR_ARG;
+  }
   uint64_t t = galois_of(c, step);
   size_t need = ops::rot_ws_words(c, in->count, in->level);
   if (!ws || ws_bytes < 8 * need) {

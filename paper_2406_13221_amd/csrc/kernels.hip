@@ -308,11 +308,13 @@ __global__ void __launch_bounds__(EW_THREADS) k_rescale_combine(const PrimeConst
 __global__ void __launch_bounds__(EW_THREADS) k_modup(const PrimeConst* pc, const uint64_t* mu_tab,
                                                        const double* muf, const uint64_t* dcoef, uint64_t* ext,
                                                        int64_t ext_cs, int logN, int level, int lo, int sz, int nq,
-                                                       int np, int alpha) {
+                                                       int np, int alpha, int tgroup, int ngroups) {
   const int chunks = (1 << logN) / EW_CHUNK;
   int64_t bid = blockIdx.x;
   int ch = (int)(bid % chunks);
-  int64_t ct = bid / chunks;
+  int64_t rest = bid / chunks;
+  const int e_lo = (int)(rest % ngroups) * tgroup, e_hi = e_lo + tgroup;
+  int64_t ct = rest / ngroups;
   const int nl = level + 1;
   int c = ch * EW_CHUNK + threadIdx.x * 2;
   const uint64_t* src = dcoef + ((ct * nl) << logN) + c;
@@ -331,6 +333,10 @@ __global__ void __launch_bounds__(EW_THREADS) k_modup(const PrimeConst* pc, cons
   int e = 0;
   for (int g = 0; g < nl + np; ++g) {
     if (g >= lo && g < lo + sz) continue;
+    if (e < e_lo || e >= e_hi) {
+      ++e;
+      continue;
+    }
     int gp = g < nl ? g : nq + (g - nl);
     const PrimeConst P = pc[gp];
     if (P.k <= FP_MAX_BITS) {
@@ -369,24 +375,30 @@ __global__ void __launch_bounds__(EW_THREADS) k_modup(const PrimeConst* pc, cons
 
 // acc[ct][part][x] = sum_j v_j[x] * key_j[part][prime(x)], x over Q rows 0..l then P rows;
 // v_j[x] = d[x] for x in digit j, else the ModUp row of digit j.  One thread owns two
-// coefficients of one extended row and loops over the ciphertexts of the batch, so
-// each key residue is read once per launch.
+// coefficients of one extended row of one ciphertext.  The grid is XCD-aware:
+// workgroup b runs on XCD b mod 8, and the `count` workgroups that share one
+// (row, chunk) tile of the key are given consecutive slots on the same XCD, so the
+// key tile is fetched from HBM once per launch and then served by that XCD's L2.
+// With galois != 1, d is the input before the automorphism X -> X^galois and the
+// in-digit rows are gathered through it.
 constexpr int KS_MAX_DIGITS = 8;
 __global__ void __launch_bounds__(EW_THREADS) k_ks_inner(const PrimeConst* pc, CtV d, const uint64_t* ext, int64_t ext_cs,
                                                           int64_t ext_ds, const uint64_t* key, uint64_t* acc, int logN,
-                                                          int level, int nq, int np, int alpha, int64_t count) {
+                                                          int level, int nq, int np, int alpha, int64_t count,
+                                                          uint64_t galois) {
   const int chunks = (1 << logN) / EW_CHUNK;
   const int nl = level + 1, nx = nl + np, nqp = nq + np;
-  int64_t bid = blockIdx.x;
-  int ch = (int)(bid % chunks);
-  int x = (int)(bid / chunks);
-  int c = ch * EW_CHUNK + threadIdx.x * 2;
-  int gp = x < nl ? x : nq + (x - nl);
+  const int64_t bid = blockIdx.x;
+  const int64_t rest = bid >> 3;
+  const int64_t ct = rest % count;
+  const int64_t tile = (rest / count) * 8 + (bid & 7);
+  const int ch = (int)(tile % chunks);
+  const int x = (int)(tile / chunks);
+  const int c = ch * EW_CHUNK + threadIdx.x * 2;
+  const int gp = x < nl ? x : nq + (x - nl);
   const PrimeConst P = pc[gp];
   const int nd = (nl + alpha - 1) / alpha;
-  U2 kb[KS_MAX_DIGITS], ka[KS_MAX_DIGITS];
-  const uint64_t* vsrc[KS_MAX_DIGITS];
-  int64_t vcs[KS_MAX_DIGITS];
+  U2 v[KS_MAX_DIGITS], kb[KS_MAX_DIGITS], ka[KS_MAX_DIGITS];
 #pragma unroll
   for (int j = 0; j < KS_MAX_DIGITS; ++j) {
     if (j < nd) {
@@ -395,58 +407,51 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_inner(const PrimeConst* pc, C
       ka[j] = ld2(kp + ((int64_t)nqp << logN));
       int lo = j * alpha, hi = min(lo + alpha, nl);
       if (x >= lo && x < hi) {
-        vsrc[j] = d.d + ((int64_t)x << logN) + c;
-        vcs[j] = d.cs;
+        const uint64_t* row = d.d + ct * d.cs + ((int64_t)x << logN);
+        if (galois != 1) {
+          const uint32_t mask2n = (2u << logN) - 1;
+          uint32_t e0 = (uint32_t)(((uint64_t)(2 * brv_n(c, logN) + 1) * galois) & mask2n);
+          uint32_t e1 = (uint32_t)(((uint64_t)(2 * brv_n(c + 1, logN) + 1) * galois) & mask2n);
+          v[j].a = row[brv_n((e0 - 1) >> 1, logN)];
+          v[j].b = row[brv_n((e1 - 1) >> 1, logN)];
+        } else {
+          v[j] = ld2(row + c);
+        }
       } else {
         int e = x < lo ? x : x - (hi - lo);
-        vsrc[j] = ext + j * ext_ds + ((int64_t)e << logN) + c;
-        vcs[j] = ext_cs;
+        v[j] = ld2(ext + ct * ext_cs + j * ext_ds + ((int64_t)e << logN) + c);
       }
     }
   }
-  const int64_t acs = (int64_t)(2 * nx) << logN;
-  uint64_t* o = acc + ((int64_t)x << logN) + c;
+  uint64_t* o = acc + ct * ((int64_t)(2 * nx) << logN) + ((int64_t)x << logN) + c;
   if (P.k <= FP_MAX_BITS) {
 #pragma clang fp contract(off)
     const double q = P.qd, qi = P.qinv;
-    double fb0[KS_MAX_DIGITS], fb1[KS_MAX_DIGITS], fa0[KS_MAX_DIGITS], fa1[KS_MAX_DIGITS];
+    double s0a = 0, s0b = 0, s1a = 0, s1b = 0;
 #pragma unroll
     for (int j = 0; j < KS_MAX_DIGITS; ++j)
       if (j < nd) {
-        fb0[j] = u64_to_f(kb[j].a); fb1[j] = u64_to_f(kb[j].b);
-        fa0[j] = u64_to_f(ka[j].a); fa1[j] = u64_to_f(ka[j].b);
+        double va = u64_to_f(v[j].a), vb = u64_to_f(v[j].b);
+        s0a += fmulmod(va, u64_to_f(kb[j].a), q, qi);
+        s0b += fmulmod(vb, u64_to_f(kb[j].b), q, qi);
+        s1a += fmulmod(va, u64_to_f(ka[j].a), q, qi);
+        s1b += fmulmod(vb, u64_to_f(ka[j].b), q, qi);
       }
-    for (int64_t ct = 0; ct < count; ++ct) {
-      double s0a = 0, s0b = 0, s1a = 0, s1b = 0;
-#pragma unroll
-      for (int j = 0; j < KS_MAX_DIGITS; ++j)
-        if (j < nd) {
-          U2 v = ld2(vsrc[j] + ct * vcs[j]);
-          double va = u64_to_f(v.a), vb = u64_to_f(v.b);
-          s0a += fmulmod(va, fb0[j], q, qi);
-          s0b += fmulmod(vb, fb1[j], q, qi);
-          s1a += fmulmod(va, fa0[j], q, qi);
-          s1b += fmulmod(vb, fa1[j], q, qi);
-        }
-      st2(o + ct * acs, fcanon(s0a, q, qi), fcanon(s0b, q, qi));
-      st2(o + ct * acs + ((int64_t)nx << logN), fcanon(s1a, q, qi), fcanon(s1b, q, qi));
-    }
+    st2(o, fcanon(s0a, q, qi), fcanon(s0b, q, qi));
+    st2(o + ((int64_t)nx << logN), fcanon(s1a, q, qi), fcanon(s1b, q, qi));
     return;
   }
-  for (int64_t ct = 0; ct < count; ++ct) {
-    uint64_t s0a = 0, s0b = 0, s1a = 0, s1b = 0;
+  uint64_t s0a = 0, s0b = 0, s1a = 0, s1b = 0;
 #pragma unroll
-    for (int j = 0; j < KS_MAX_DIGITS; ++j)
-      if (j < nd) {
-        U2 v = ld2(vsrc[j] + ct * vcs[j]);
-        s0a = addmod(s0a, mulmod(v.a, kb[j].a, P), P.q);
-        s0b = addmod(s0b, mulmod(v.b, kb[j].b, P), P.q);
-        s1a = addmod(s1a, mulmod(v.a, ka[j].a, P), P.q);
-        s1b = addmod(s1b, mulmod(v.b, ka[j].b, P), P.q);
-      }
-    st2(o + ct * acs, s0a, s0b);
-    st2(o + ct * acs + ((int64_t)nx << logN), s1a, s1b);
-  }
+  for (int j = 0; j < KS_MAX_DIGITS; ++j)
+    if (j < nd) {
+      s0a = addmod(s0a, mulmod(v[j].a, kb[j].a, P), P.q);
+      s0b = addmod(s0b, mulmod(v[j].b, kb[j].b, P), P.q);
+      s1a = addmod(s1a, mulmod(v[j].a, ka[j].a, P), P.q);
+      s1b = addmod(s1b, mulmod(v[j].b, ka[j].b, P), P.q);
+    }
+  st2(o, s0a, s0b);
+  st2(o + ((int64_t)nx << logN), s1a, s1b);
 }
 
 // conv[ct][part][i] = sum_k [x_k * (P/p_k)^-1]_{p_k} * (P/p_k) mod q_i  (x = P rows of acc, coefficient form)
@@ -498,11 +503,12 @@ __global__ void __launch_bounds__(EW_THREADS) k_moddown_conv(const PrimeConst* p
   }
 }
 
-// out_p_i = base_p_i + (acc_p_i - conv_p_i) * P^-1 mod q_i   (base_1 may be absent)
+// out_p_i = [addend_p_i +] base_p_i + (acc_p_i - conv_p_i) * P^-1 mod q_i   (base_1 may be absent).
+// With galois != 1, base_0 is read through the automorphism X -> X^galois (NTT-domain gather).
 __global__ void __launch_bounds__(EW_THREADS) k_ks_combine(const PrimeConst* pc, const uint64_t* pinv,
                                                             const uint64_t* acc, const uint64_t* conv, CtV base0,
                                                             CtV base1, int has_base1, CtV out, int logN, int level,
-                                                            int np) {
+                                                            int np, uint64_t galois, CtV addend, int has_addend) {
   const int chunks = (1 << logN) / EW_CHUNK;
   const int nl = level + 1, nx = nl + np;
   int64_t bid = blockIdx.x;
@@ -512,7 +518,8 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_combine(const PrimeConst* pc,
   int64_t r2 = row / nl;
   int p = (int)(r2 % 2);
   int64_t ct = r2 / 2;
-  int64_t off = ((int64_t)i << logN) + ch * EW_CHUNK + threadIdx.x * 2;
+  const int k0 = ch * EW_CHUNK + threadIdx.x * 2;
+  int64_t off = ((int64_t)i << logN) + k0;
   const uint64_t q = pc[i].q;
   U2 x = ld2(acc + ((ct * 2 + p) * nx << logN) + off);
   U2 y = ld2(conv + ((ct * 2 + p) * nl << logN) + off);
@@ -521,7 +528,22 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_combine(const PrimeConst* pc,
   uint64_t r1 = mul_shoup(submod(x.b, y.b, q), w, ws, q);
   if (p == 0 || has_base1) {
     const CtV& B = p == 0 ? base0 : base1;
-    U2 z = ld2(B.d + ct * B.cs + off);
+    U2 z;
+    if (p == 0 && galois != 1) {
+      const uint64_t* src = B.d + ct * B.cs + ((int64_t)i << logN);
+      const uint32_t mask2n = (2u << logN) - 1;
+      uint32_t e0 = (uint32_t)(((uint64_t)(2 * brv_n(k0, logN) + 1) * galois) & mask2n);
+      uint32_t e1 = (uint32_t)(((uint64_t)(2 * brv_n(k0 + 1, logN) + 1) * galois) & mask2n);
+      z.a = src[brv_n((e0 - 1) >> 1, logN)];
+      z.b = src[brv_n((e1 - 1) >> 1, logN)];
+    } else {
+      z = ld2(B.d + ct * B.cs + off);
+    }
+    r0 = addmod(r0, z.a, q);
+    r1 = addmod(r1, z.b, q);
+  }
+  if (has_addend) {
+    U2 z = ld2(addend.d + ct * addend.cs + p * addend.ps + off);
     r0 = addmod(r0, z.a, q);
     r1 = addmod(r1, z.b, q);
   }
@@ -837,16 +859,22 @@ void k_modup_launch(const Geo& g, const DevTables& t, const uint64_t* dcoef, int
   int lo = digit * g.alpha;
   int sz = nl - lo < g.alpha ? nl - lo : g.alpha;
   const uint64_t* tab = t.modup + 2 * (int64_t)((level * g.dnum + digit) * g.mu_stride);
-  int64_t n = count * CHUNKS(g);
+  // targets are split over workgroups (8 per group) to keep every CU busy
+  const int nt = nl + g.n_p - sz, tgroup = 8, ngroups = (nt + tgroup - 1) / tgroup;
+  int64_t n = count * ngroups * CHUNKS(g);
   const double* tabf = t.modup_f + 2 * (int64_t)((level * g.dnum + digit) * g.nqp) * g.alpha;
-  if (n) LAUNCH(k_modup, n, s, t.pc, tab, tabf, dcoef, ext, ext_cs, g.logN, level, lo, sz, g.n_q, g.n_p, g.alpha);
+  if (n)
+    LAUNCH(k_modup, n, s, t.pc, tab, tabf, dcoef, ext, ext_cs, g.logN, level, lo, sz, g.n_q, g.n_p, g.alpha, tgroup,
+           ngroups);
 }
 void k_ks_inner_launch(const Geo& g, const DevTables& t, CtV d, const uint64_t* ext, int64_t ext_cs, int64_t ext_ds,
-                       const uint64_t* key, uint64_t* acc, int64_t count, int level, hipStream_t s) {
+                       const uint64_t* key, uint64_t* acc, int64_t count, int level, uint64_t galois, hipStream_t s) {
   int nx = level + 1 + g.n_p;
-  int64_t n = count > 0 ? (int64_t)nx * CHUNKS(g) : 0;
+  // tiles (row x chunk) are a multiple of 8 because N/512 is
+  int64_t n = count * (int64_t)nx * CHUNKS(g);
   if (n)
-    LAUNCH(k_ks_inner, n, s, t.pc, d, ext, ext_cs, ext_ds, key, acc, g.logN, level, g.n_q, g.n_p, g.alpha, count);
+    LAUNCH(k_ks_inner, n, s, t.pc, d, ext, ext_cs, ext_ds, key, acc, g.logN, level, g.n_q, g.n_p, g.alpha, count,
+           galois);
 }
 void k_moddown_conv_launch(const Geo& g, const DevTables& t, const uint64_t* acc, uint64_t* conv, int64_t count,
                            int level, hipStream_t s) {
@@ -854,11 +882,14 @@ void k_moddown_conv_launch(const Geo& g, const DevTables& t, const uint64_t* acc
   if (n) LAUNCH(k_moddown_conv, n, s, t.pc, t.moddown, t.moddown_f, acc, conv, g.logN, level, g.n_q, g.n_p);
 }
 void k_ks_combine_launch(const Geo& g, const DevTables& t, const uint64_t* acc, const uint64_t* conv, CtV base0,
-                         CtV base1, bool has_base1, CtV out, int64_t count, int level, hipStream_t s) {
+                         CtV base1, bool has_base1, CtV out, int64_t count, int level, uint64_t galois,
+                         const CtV* addend, hipStream_t s) {
   const uint64_t* pinv = t.moddown + 2 * g.n_p + 2 * (int64_t)g.n_q * g.n_p;
   int64_t n = count * 2 * (level + 1) * CHUNKS(g);
+  CtV ad = addend ? *addend : CtV{nullptr, 0, 0};
   if (n)
-    LAUNCH(k_ks_combine, n, s, t.pc, pinv, acc, conv, base0, base1, has_base1 ? 1 : 0, out, g.logN, level, g.n_p);
+    LAUNCH(k_ks_combine, n, s, t.pc, pinv, acc, conv, base0, base1, has_base1 ? 1 : 0, out, g.logN, level, g.n_p,
+           galois, ad, addend ? 1 : 0);
 }
 void k_sample_small_launch(uint64_t seed, uint64_t purpose, uint64_t obj_first, int64_t count, int N, int kind,
                            int64_t* out, hipStream_t s) {

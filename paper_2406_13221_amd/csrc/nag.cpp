@@ -137,15 +137,24 @@ struct Exec {
     if (!dry) ops::mul_const(c, a.v(), a.count, a.n_poly, a.level, a.scale, cst, target, o.v(), rs_ws, s);
     return o;
   }
-  // x <- x + Rot(x, step), reusing x's slot (x must be the most recent allocation)
+  // x <- x + Rot(x, step), reusing x's slot (x must be the most recent allocation);
+  // the addition is fused into the key switch's final kernel.
   Ct add_rot(Ct x, int step) {
+    const int64_t half = N() / 2;
+    int64_t r = ((int64_t)step % half + half) % half;
+    uint64_t t = h_pow(5, (uint64_t)r, 2 * (uint64_t)N());
+    if (t != 1 && !ops::rot_key(k, t)) fail(HEQG_ERR_KEY, "no rotation key for step " + std::to_string(step));
     size_t mk = next;
-    Ct r = rotate(x, step);
-    Ct nx = add(x, r);
-    if (!dry) std::swap(slots[mk - 1], slots[next - 1]);
-    nx.d = slots[mk - 1];
+    Ct o = slot(2, x.level, x.scale, x.count);
+    if (!dry) {
+      CtV xv = x.v();
+      int rc = ops::rotate(c, k, xv, o.v(), x.count, x.level, t, ks_ws, s, &xv);
+      if (rc) fail(rc, "rotate");
+      std::swap(slots[mk - 1], slots[next - 1]);
+    }
+    o.d = slots[mk - 1];
     reset(mk);
-    return nx;
+    return o;
   }
   Ct refresh(Ct a, int target, uint64_t seed, uint64_t obj) {
     Ct o = slot(2, target, a.scale, a.count);

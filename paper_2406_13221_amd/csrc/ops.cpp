@@ -163,7 +163,7 @@ size_t mul_const_ws_words(const heqg_ctx* c, int64_t count, int n_poly, int leve
 }
 
 void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, CtV base0, CtV base1, bool has_base1,
-             CtV out, uint64_t* ws, hipStream_t s) {
+             CtV out, uint64_t* ws, hipStream_t s, uint64_t galois, const CtV* addend) {
   const int N = c->g.N, nl = level + 1, np = c->g.n_p, nq = c->g.n_q, nx = nl + np, alpha = c->g.alpha;
   const int nd = (nl + alpha - 1) / alpha;
   uint64_t* dcoef = ws;
@@ -171,8 +171,11 @@ void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, 
   uint64_t* acc = ext + (size_t)count * nd * nx * N;
   uint64_t* conv = acc + (size_t)count * 2 * nx * N;
   const int64_t ext_cs = (int64_t)nd * nx * N;
-  // 1. d to coefficient form
-  k_copy_launch(c->g, d, CtV{dcoef, (int64_t)nl * N, 0}, count, 1, nl, s);
+  // 1. d (after the automorphism, if any) to coefficient form
+  if (galois == 1)
+    k_copy_launch(c->g, d, CtV{dcoef, (int64_t)nl * N, 0}, count, 1, nl, s);
+  else
+    k_automorph_launch(c->g, d, CtV{dcoef, (int64_t)nl * N, 0}, count, 1, nl, galois, s);
   ntt(c, rows_q(dcoef, count, (int64_t)nl * N, 1, 0, nl), true, s);
   // 2. ModUp per digit, then NTT of the new rows
   for (int j = 0; j < nd; ++j) {
@@ -186,19 +189,19 @@ void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, 
     ntt(c, rows(e, count, ext_cs, 1, 0, (int)tgt.size(), tgt.data()), false, s);
   }
   // 3. inner product with the key over Q_l and P
-  k_ks_inner_launch(c->g, c->t, d, ext, ext_cs, (int64_t)nx * N, key, acc, count, level, s);
+  k_ks_inner_launch(c->g, c->t, d, ext, ext_cs, (int64_t)nx * N, key, acc, count, level, galois, s);
   // 4. ModDown of both parts
   ntt(c, rows_q(acc + (size_t)nl * N, count, (int64_t)2 * nx * N, 2, (int64_t)nx * N, np, nq), true, s);
   k_moddown_conv_launch(c->g, c->t, acc, conv, count, level, s);
   ntt(c, rows_q(conv, count * 2, (int64_t)nl * N, 1, 0, nl), false, s);
-  k_ks_combine_launch(c->g, c->t, acc, conv, base0, base1, has_base1, out, count, level, s);
+  k_ks_combine_launch(c->g, c->t, acc, conv, base0, base1, has_base1, out, count, level, galois, addend, s);
 }
 
 int relin(heqg_ctx* c, const heqg_keys* k, CtV in3, CtV out, int64_t count, int level, uint64_t* ws, hipStream_t s) {
   CtV d{in3.d + 2 * in3.ps, in3.cs, in3.ps};
   CtV b0{in3.d, in3.cs, in3.ps};
   CtV b1{in3.d + in3.ps, in3.cs, in3.ps};
-  ks_core(c, k->rlk, d, count, level, b0, b1, true, out, ws, s);
+  ks_core(c, k->rlk, d, count, level, b0, b1, true, out, ws, s, 1, nullptr);
   return HEQG_OK;
 }
 
@@ -208,11 +211,17 @@ const uint64_t* rot_key(const heqg_keys* k, uint64_t galois) {
   return nullptr;
 }
 
+// The automorphism is folded into the key switch: the copy of c1 into coefficient
+// form, the in-digit limbs of the inner product and the final combine all read
+// through the permutation, so no permuted copy of the ciphertext is written.
 int rotate(heqg_ctx* c, const heqg_keys* k, CtV in, CtV out, int64_t count, int level, uint64_t galois, uint64_t* ws,
-           hipStream_t s) {
-  const int N = c->g.N, nl = level + 1;
+           hipStream_t s, const CtV* addend) {
+  const int nl = level + 1;
   if (galois == 1) {
-    k_copy_launch(c->g, in, out, count, 2, nl, s);
+    if (addend)
+      k_add_launch(c->g, c->t, in, *addend, out, count, 2, nl, false, s);
+    else
+      k_copy_launch(c->g, in, out, count, 2, nl, s);
     return HEQG_OK;
   }
   const uint64_t* key = rot_key(k, galois);
@@ -220,10 +229,8 @@ int rotate(heqg_ctx* c, const heqg_keys* k, CtV in, CtV out, int64_t count, int 
     set_err("rotate: no rotation key for this step");
     return HEQG_ERR_KEY;
   }
-  CtV t{ws, (int64_t)2 * nl * N, (int64_t)nl * N};
-  k_automorph_launch(c->g, in, t, count, 2, nl, galois, s);
-  CtV d{ws + (size_t)nl * N, t.cs, t.ps};
-  ks_core(c, key, d, count, level, t, t, false, out, ws + (size_t)count * 2 * nl * N, s);
+  CtV d{in.d + in.ps, in.cs, in.ps};
+  ks_core(c, key, d, count, level, in, in, false, out, ws, s, galois, addend);
   return HEQG_OK;
 }
 

@@ -25,12 +25,14 @@ size_t rescale_ws_words(const heqg_ctx* c, int64_t count, int n_poly, int level)
 size_t mul_const_ws_words(const heqg_ctx* c, int64_t count, int n_poly, int level);
 
 // key switch of d (NTT rows 0..level) with `key`; out_p = base_p + ks_p (base_1 optional)
+// galois != 1: d and base0 are read through X -> X^galois; addend (both parts) is added to the output
 void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, CtV base0, CtV base1, bool has_base1,
-             CtV out, uint64_t* ws, hipStream_t s);
+             CtV out, uint64_t* ws, hipStream_t s, uint64_t galois, const CtV* addend);
 int relin(heqg_ctx* c, const heqg_keys* k, CtV in3, CtV out, int64_t count, int level, uint64_t* ws, hipStream_t s);
 const uint64_t* rot_key(const heqg_keys* k, uint64_t galois);
+// out = Rot(in) [+ addend]; out must not alias in
 int rotate(heqg_ctx* c, const heqg_keys* k, CtV in, CtV out, int64_t count, int level, uint64_t galois, uint64_t* ws,
-           hipStream_t s);
+           hipStream_t s, const CtV* addend = nullptr);
 void rescale(heqg_ctx* c, CtV in, CtV out, int64_t count, int n_poly, int level, uint64_t* ws, hipStream_t s);
 int const_int(const heqg_ctx* c, double cst, double target, int level, double in_scale, int64_t* k);
 int mul_const(heqg_ctx* c, CtV in, int64_t count, int n_poly, int level, double in_scale, double cst, double target,
