@@ -301,6 +301,37 @@ int heqg_tune_set(int which, int value);
 int heqg_tune_get(int which);
 
 /* ------------------------------------------------------------------ */
+/* Learned sigmoid polynomial (replaces the fixed cubic of section 4.1)  */
+/* ------------------------------------------------------------------ */
+
+/*
+ * p_c(m) = 1/2 + sum_{i < n_terms} c_i (m/8)^(2i+1), n_terms <= 4 (degree <= 7),
+ * fitted to sigma(m) = 1/(1+e^-m) in mean squared error over n FP32 margins
+ * dev_m (device).  All arithmetic per margin is FP32; per-workgroup partial
+ * sums are combined in FP64 in a fixed order (deterministic).
+ *
+ * heqg_sigfit_grad: loss and gradient (2/n) sum (p_c(m) - sigma(m)) (m/8)^(2i+1)
+ * at coefficients dev_c (device, n_terms floats) into dev_grad (n_terms) and
+ * dev_loss (1 float, may be NULL).
+ * Asynchronous on the stream.
+ * heqg_sigfit_train: `steps` Adam steps (moments start at zero; learning rate
+ * lr * (1 + cos(pi t/steps))/2) updating dev_c in place; dev_loss_trace
+ * (steps floats, may be NULL) receives the loss before each step.  Adam runs
+ * in whitened coordinates a = L^T c, with L L^T = Phi^T Phi / n the Cholesky
+ * factor of the basis Gram matrix on the margins (computed on the device,
+ * factored on the host in FP64), so the loss is isotropic in a.  Synchronises
+ * the stream twice (Gram read-back, end).  HEQG_ERR_ARG when the Gram matrix is
+ * not positive definite (e.g. all margins zero).
+ * Workspace: heqg_sigfit_ws_bytes device bytes (independent of n), owned by
+ * the caller.
+ */
+size_t heqg_sigfit_ws_bytes(int64_t n, int n_terms);
+int heqg_sigfit_grad(const float* dev_m, int64_t n, const float* dev_c, int n_terms, float* dev_grad,
+                     float* dev_loss, void* ws, size_t ws_bytes, hipStream_t stream);
+int heqg_sigfit_train(const float* dev_m, int64_t n, int n_terms, float* dev_c, int steps, float lr, float beta1,
+                      float beta2, float eps, float* dev_loss_trace, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------ */
 /* Training step (section 3.2 Algorithm 1; section 3.3; section 4.3)    */
 /* ------------------------------------------------------------------ */
 

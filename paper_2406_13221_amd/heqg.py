@@ -99,6 +99,10 @@ def lib():
         "heqg_add_pt": (i32, [vp, P(BatchS), vp, dbl, P(BatchS), vp]),
         "heqg_mul_const": (i32, [vp, P(BatchS), dbl, dbl, P(BatchS), vp, sz, vp]),
         "heqg_ntt": (i32, [vp, vp, i64, i32, i32, i32, vp]),
+        "heqg_sigfit_ws_bytes": (sz, [i64, i32]),
+        "heqg_sigfit_grad": (i32, [vp, i64, vp, i32, vp, vp, vp, sz, vp]),
+        "heqg_sigfit_train": (i32, [vp, i64, i32, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float, vp, vp, sz, vp]),
         "heqg_tune_set": (i32, [i32, i32]),
         "heqg_tune_get": (i32, [i32]),
         "heqg_prof_start": (i32, [i32]),
