@@ -58,7 +58,7 @@ static uint32_t h_brv(uint32_t x, int bits) {
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Section offsets (bytes) in the device table buffer; returns the total size.
-size_t ctx_layout(const heqg_params* p, bool check, std::string* err, size_t offs[12]) {
+size_t ctx_layout(const heqg_params* p, bool check, std::string* err, size_t offs[14]) {
   if (!p || !p->q_bits) {
     if (err) *err = "null params";
     return 0;
@@ -91,7 +91,7 @@ size_t ctx_layout(const heqg_params* p, bool check, std::string* err, size_t off
   size_t N = (size_t)1 << p->log2N, nq = p->n_q, np = p->n_p, nqp = nq + np;
   size_t alpha = (nq + p->dnum - 1) / p->dnum;
   size_t mu_stride = alpha + nqp * alpha;
-  size_t sz[11] = {
+  size_t sz[13] = {
       nqp * N * 16,                    // tw_fwd
       nqp * N * 16,                    // tw_inv
       nqp * sizeof(PrimeConst),        // pc
@@ -103,13 +103,15 @@ size_t ctx_layout(const heqg_params* p, bool check, std::string* err, size_t off
       nqp * N * 8,                     // tw_inv_f
       nq * p->dnum * nqp * alpha * 16, // modup_f
       nq * np * 16,                    // moddown_f
+      nq * nqp * 16,                   // ks_scale
+      nq * nqp * 8,                    // ks_scale_f
   };
   size_t o = 0;
-  for (int i = 0; i < 11; ++i) {
+  for (int i = 0; i < 13; ++i) {
     if (offs) offs[i] = o;
     o = align256(o + sz[i]);
   }
-  if (offs) offs[11] = o;
+  if (offs) offs[13] = o;
   return o;
 }
 
@@ -131,7 +133,7 @@ static void fill_pc(PrimeConst& c, uint64_t q, int log2N) {
 
 int ctx_build(heqg_ctx* c, void* dev, size_t bytes, std::string* err) {
   const heqg_params* p = &c->p;
-  size_t offs[12];
+  size_t offs[14];
   size_t total = ctx_layout(p, true, err, offs);
   if (!total) return HEQG_ERR_UNSUPPORTED;
   if (!dev || bytes < total) {
@@ -271,6 +273,26 @@ int ctx_build(heqg_ctx* c, void* dev, size_t bytes, std::string* err) {
     c->pmod[2 * i] = P;
     c->pmod[2 * i + 1] = h_shoup(P, qi);
   }
+  // key-switch INTT output scales: N^-1 times the first factor of each base conversion
+  {
+    uint64_t* ks = reinterpret_cast<uint64_t*>(host.data() + offs[11]);
+    double* ksf = reinterpret_cast<double*>(host.data() + offs[12]);
+    for (int l = 0; l < nq; ++l)
+      for (int gi = 0; gi < nqp; ++gi) {
+        uint64_t t = c->primes[gi], v;
+        if (gi < nq) {
+          if (gi > l) continue;
+          int j = gi / alpha, lo = j * alpha;
+          v = mu[2 * (size_t)((l * p->dnum + j) * mst) + 2 * (gi - lo)];
+        } else {
+          v = md[2 * (gi - nq)];
+        }
+        uint64_t w = h_mul(v, h_inv((uint64_t)N % t, t), t);
+        ks[2 * ((size_t)l * nqp + gi)] = w;
+        ks[2 * ((size_t)l * nqp + gi) + 1] = h_shoup(w, t);
+        ksf[(size_t)l * nqp + gi] = (double)w;
+      }
+  }
   // lift constants
   std::memset(c->lift_c, 0, sizeof(c->lift_c));
   if (nq >= 2) {
@@ -309,6 +331,8 @@ int ctx_build(heqg_ctx* c, void* dev, size_t bytes, std::string* err) {
   c->t.tw_inv_f = reinterpret_cast<const double*>(d + offs[8]);
   c->t.modup_f = reinterpret_cast<const double*>(d + offs[9]);
   c->t.moddown_f = reinterpret_cast<const double*>(d + offs[10]);
+  c->t.ks_scale = reinterpret_cast<const uint64_t*>(d + offs[11]);
+  c->t.ks_scale_f = reinterpret_cast<const double*>(d + offs[12]);
   return HEQG_OK;
 }
 

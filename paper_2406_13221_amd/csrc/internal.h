@@ -22,6 +22,44 @@ struct CtV {
   int64_t cs, ps;
 };
 
+// Key-switch combine, applied where the forward NTT of the ModDown conversion stores
+// its output (rows ia = ct*2 + part, limb ii):
+//   out = (acc_Q - NTT(conv)) * P^-1 + base_part (+ addend)
+// base0 is read through X -> X^galois when galois != 1.
+struct KsEpi {
+  const uint64_t* acc;    // row (ia, ii) at acc + ia*acc_s + ii*N (NTT form)
+  int64_t acc_s;
+  const uint64_t* pinv;   // [limb][2]: P^-1 mod q_i and its Shoup companion
+  CtV base0, base1, addend, out;
+  int has_base1, has_addend;
+  uint64_t galois;
+};
+
+// Optional work fused into the passes of one NTT launch (everything off when zeroed).
+struct NttExtra {
+  // inverse, first pass: read row (ia, ib, ii) from in + ia*in_sa + ib*in_sb + ii*N (out of
+  // place), through X -> X^galois when galois > 1
+  const uint64_t* in;
+  int64_t in_sa, in_sb;
+  uint64_t galois;
+  // inverse, last pass: multiply by scale[p] (pairs w, Shoup(w)) / scalef[p] instead of N^-1
+  const uint64_t* scale;
+  const double* scalef;
+  // forward, first pass: the input of row (ia, ib, ii) is the base conversion
+  //   sum_s csrc_s * hat[p][s]  mod q_p,  csrc_s = csrc + ia*csrc_sa + ib*csrc_sb + s*N
+  // with hat pairs (w, Shoup(w)) at chat + 2*(p*cstride + s) and FP64 pairs
+  // (w, 2^32 w mod q_p) at chatf + 2*(p*cstride + s); bit s of csplit: source s may
+  // exceed FP_MAX_BITS bits, so FP64 products take it in 32-bit halves
+  const uint64_t* csrc;
+  int64_t csrc_sa, csrc_sb;
+  int ns, cstride, csplit;
+  const uint64_t* chat;
+  const double* chatf;
+  // forward, last pass: key-switch combine instead of a plain store
+  int has_epi;
+  KsEpi epi;
+};
+
 // Device-side table pointers (inside the caller's table buffer).
 struct DevTables {
   const uint64_t* tw_fwd;    // [nqp][N][2]: psi^brv(k) and its Shoup companion
@@ -35,6 +73,9 @@ struct DevTables {
   const double* tw_inv_f;    // [nqp][N]: psi^-brv(k) as doubles
   const double* modup_f;     // [n_q][dnum][nqp][alpha][2]: (D/s_k mod t, 2^32 * D/s_k mod t) as doubles
   const double* moddown_f;   // [n_q][n_p][2]: (P/p_k mod q_i, 2^32 * P/p_k mod q_i) as doubles
+  const uint64_t* ks_scale;  // [n_q][nqp][2]: at level l, N^-1 * (D/s)^-1 mod s for Q prime s in its
+                             // digit D, N^-1 * (P/p)^-1 mod p for special prime p (+Shoup)
+  const double* ks_scale_f;  // [n_q][nqp]: the same as doubles
 };
 
 // Geometry the kernels need.
@@ -44,6 +85,7 @@ struct Geo {
 
 // ---- launchers (kernels.hip / ntt.hip) ----
 int launch_ntt(const DevTables& t, int log2N, const RowSet& rows, bool inverse, hipStream_t s);
+int launch_ntt_ex(const DevTables& t, int log2N, const RowSet& rows, bool inverse, const NttExtra& x, hipStream_t s);
 
 void k_add_launch(const Geo& g, const DevTables& t, CtV a, CtV b, CtV out, int64_t count, int n_poly, int nl, bool sub,
                   hipStream_t s);

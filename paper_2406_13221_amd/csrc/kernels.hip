@@ -230,7 +230,6 @@ __global__ void __launch_bounds__(EW_THREADS) k_copy(CtV a, CtV out, int logN, i
 // ------------------------------------------------------------------ automorphism (NTT domain)
 // Position k holds the evaluation at psi^(2 brv(k) + 1); X -> X^t maps it to the
 // evaluation at psi^((2 brv(k) + 1) t), found at position brv(((2 brv(k)+1) t mod 2N - 1) / 2).
-__device__ __forceinline__ uint32_t brv_n(uint32_t x, int logN) { return __brev(x) >> (32 - logN); }
 
 __global__ void __launch_bounds__(EW_THREADS) k_automorph(CtV a, CtV out, int logN, int nl, int n_poly,
                                                            uint64_t galois) {

@@ -88,6 +88,16 @@ __device__ __forceinline__ uint64_t mulmod(uint64_t a, uint64_t b, const PrimeCo
 }
 
 __device__ __forceinline__ uint64_t addmod(uint64_t a, uint64_t b, uint64_t q) { return csub(a + b, q); }
+
+// bit reversal of the low logN bits
+__device__ __forceinline__ uint32_t brv_n(uint32_t x, int logN) { return __brev(x) >> (32 - logN); }
+
+// Slot k of an NTT-form polynomial holds the evaluation at psi^(2 brv(k) + 1).  After
+// X -> X^galois, slot k holds what slot galois_src(k) held before.
+__device__ __forceinline__ uint32_t galois_src(uint32_t k, uint64_t galois, int logN) {
+  const uint32_t e = (uint32_t)(((uint64_t)(2 * brv_n(k, logN) + 1) * galois) & ((2u << logN) - 1));
+  return brv_n((e - 1) >> 1, logN);
+}
 __device__ __forceinline__ uint64_t submod(uint64_t a, uint64_t b, uint64_t q) { return a >= b ? a - b : a + q - b; }
 __device__ __forceinline__ uint64_t negmod(uint64_t a, uint64_t q) { return a == 0 ? 0 : q - a; }
 

@@ -47,6 +47,7 @@ struct NttParams {
   int logN;
   int tiles;
   int group;
+  NttExtra X;
 };
 
 // ------------------------------------------------------------------ integer butterflies
@@ -134,9 +135,70 @@ __device__ __forceinline__ void stages_contig(V (&x)[16], const TW* tw, int64_t 
 __device__ __forceinline__ double as_f(uint64_t v) { return __longlong_as_double((long long)v); }
 __device__ __forceinline__ uint64_t as_u(double v) { return (uint64_t)__double_as_longlong(v); }
 
+// ------------------------------------------------------------------ fused prologue / epilogue helpers
+// Workgroup index -> (unit, sub), sub fastest, such that the nsub workgroups of one unit
+// run on one XCD (workgroups are dispatched round-robin over the 8 XCDs), so data they
+// share is fetched into that XCD's L2 once.  Units beyond the last multiple of 8 are
+// mapped plainly.
+__device__ __forceinline__ void xcd_map(int64_t bid, int64_t nsub, int64_t nunit, int64_t& unit, int64_t& sub) {
+  const int64_t full = nunit & ~(int64_t)7;
+  if (bid < full * nsub) {
+    const int64_t slot = bid >> 3;
+    sub = slot % nsub;
+    unit = (slot / nsub) * 8 + (bid & 7);
+  } else {
+    const int64_t r = bid - full * nsub;
+    sub = r % nsub;
+    unit = full + r / nsub;
+  }
+}
+
+__device__ __forceinline__ uint64_t ld_in(const uint64_t* in, int64_t pos, uint64_t galois, int logN) {
+  return in[galois > 1 ? (int64_t)galois_src((uint32_t)pos, galois, logN) : pos];
+}
+
+// Key-switch combine of the 16 output residues y[r] of row (ab, ii) at positions
+// pos0 + st*r.  All loads of a group of 8 are issued before any store, so the stores
+// (which the compiler must assume may alias the inputs) do not serialise them.
+__device__ __forceinline__ void ks_epi16(const KsEpi& E, int64_t ab, int ii, int p, uint64_t q, int logN, int64_t pos0,
+                                         int st, const uint64_t (&y)[16]) {
+  const int64_t ct = ab >> 1;
+  const int part = (int)(ab & 1);
+  const int64_t lo = (int64_t)ii << logN;
+  const uint64_t* acc = E.acc + ab * E.acc_s + lo;
+  const bool use_base = part == 0 || E.has_base1;
+  const CtV& B = part == 0 ? E.base0 : E.base1;
+  const uint64_t* bs = B.d + ct * B.cs + lo;
+  const bool gather = part == 0 && E.galois > 1;
+  const uint64_t* ad = E.addend.d + ct * E.addend.cs + part * E.addend.ps + lo;
+  uint64_t* out = E.out.d + ct * E.out.cs + part * E.out.ps + lo;
+  const uint64_t w = E.pinv[2 * p], wsh = E.pinv[2 * p + 1];
+#pragma unroll
+  for (int h = 0; h < 16; h += 8) {
+    uint64_t a[8], z[8], v[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) a[r] = acc[pos0 + st * (h + r)];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int64_t pos = pos0 + st * (h + r);
+      z[r] = use_base ? bs[gather ? (int64_t)galois_src((uint32_t)pos, E.galois, logN) : pos] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = E.has_addend ? ad[pos0 + st * (h + r)] : 0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      uint64_t o = mul_shoup(submod(a[r], y[h + r], q), w, wsh, q);
+      o = addmod(o, z[r], q);
+      out[pos0 + st * (h + r)] = addmod(o, v[r], q);
+    }
+  }
+}
+
 // ------------------------------------------------------------------ pass A (columns)
-template <int LOGS, bool FWD, bool FP>
-__device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, int p, int tile, uint64_t* lds) {
+// CONV (forward only): the input is the base conversion of the rows at cs.
+template <int LOGS, bool FWD, bool CONV, bool FP>
+__device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, const uint64_t* cs, int p, int tile,
+                                          uint64_t* lds) {
   constexpr int S = 1 << LOGS, T = S / 16, C = 256 / T;
   const int tid = threadIdx.x;
   const PrimeConst pc = P.pc[p];
@@ -144,6 +206,7 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, int
   const int cl = tid % C, kg = tid / C;
   const int c = tile * C + cl;
   if (FP) {
+#pragma clang fp contract(off)
     const double q = pc.qd, qi = pc.qinv;
     const double* tw = P.twf + ((int64_t)p << P.logN);
     auto bf = [&](double& X, double& Y, double w) {
@@ -151,8 +214,32 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, int
     };
     double x[16];
     if (FWD) {
+      if (CONV) {
+        // sum of at most 2*16 products, each |.| <= q/2 + 1: exact, then reduced to |x| <= q/2 + 1
+        const double* h = P.X.chatf + 2 * (int64_t)p * P.X.cstride;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) x[r] = u64_to_f(row[(int64_t)(kg + T * r) * N2 + c]);
+        for (int r = 0; r < 16; ++r) x[r] = 0.0;
+#pragma unroll 1
+        for (int s = 0; s < P.X.ns; ++s) {
+          const uint64_t* ys = cs + ((int64_t)s << P.logN) + c;
+          const double h0 = h[2 * s], h1 = h[2 * s + 1];
+          if ((P.X.csplit >> s) & 1) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const uint64_t y = ys[(int64_t)(kg + T * r) * N2];
+              x[r] += fmulmod((double)(uint32_t)(y >> 32), h1, q, qi) + fmulmod((double)(uint32_t)y, h0, q, qi);
+            }
+          } else {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) x[r] += fmulmod(u64_to_f(ys[(int64_t)(kg + T * r) * N2]), h0, q, qi);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[r] = fred(x[r], q, qi);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[r] = u64_to_f(row[(int64_t)(kg + T * r) * N2 + c]);
+      }
       stages_strided<true>(x, tw, 1, bf);
 #pragma unroll
       for (int r = 0; r < 16; ++r) lds[(kg + T * r) * C + cl] = as_u(x[r]);
@@ -172,9 +259,9 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, int
 #pragma unroll
       for (int r = 0; r < 16; ++r) x[r] = as_f(lds[(kg + T * r) * C + cl]);
       stages_strided<false>(x, tw, 1, bf);
+      const double sd = P.X.scalef ? P.X.scalef[p] : pc.ninv_d;
 #pragma unroll
-      for (int r = 0; r < 16; ++r)
-        row[(int64_t)(kg + T * r) * N2 + c] = fcanon(fmulmod(x[r], pc.ninv_d, q, qi), q, qi);
+      for (int r = 0; r < 16; ++r) row[(int64_t)(kg + T * r) * N2 + c] = fcanon(fmulmod(x[r], sd, q, qi), q, qi);
     }
   } else {
     const uint64_t q = pc.q, two_q = 2 * q;
@@ -184,8 +271,25 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, int
     };
     uint64_t x[16];
     if (FWD) {
+      if (CONV) {
+        // lazy sum kept in [0, 2q)
+        const uint64_t* h = P.X.chat + 2 * (int64_t)p * P.X.cstride;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) x[r] = row[(int64_t)(kg + T * r) * N2 + c];
+        for (int r = 0; r < 16; ++r) x[r] = 0;
+#pragma unroll 1
+        for (int s = 0; s < P.X.ns; ++s) {
+          const uint64_t* ys = cs + ((int64_t)s << P.logN) + c;
+          const uint64_t w = h[2 * s], wsh = h[2 * s + 1];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const uint64_t v = x[r] + mul_shoup_lazy(ys[(int64_t)(kg + T * r) * N2], w, wsh, q);
+            x[r] = v >= two_q ? v - two_q : v;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[r] = row[(int64_t)(kg + T * r) * N2 + c];
+      }
       stages_strided<true>(x, tw, 1, bf);
 #pragma unroll
       for (int r = 0; r < 16; ++r) lds[(kg + T * r) * C + cl] = x[r];
@@ -205,26 +309,41 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, int
 #pragma unroll
       for (int r = 0; r < 16; ++r) x[r] = lds[(kg + T * r) * C + cl];
       stages_strided<false>(x, tw, 1, bf);
+      const uint64_t sw = P.X.scale ? P.X.scale[2 * p] : pc.ninv;
+      const uint64_t ssh = P.X.scale ? P.X.scale[2 * p + 1] : pc.ninv_sh;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) row[(int64_t)(kg + T * r) * N2 + c] = mul_shoup(x[r], pc.ninv, pc.ninv_sh, q);
+      for (int r = 0; r < 16; ++r) row[(int64_t)(kg + T * r) * N2 + c] = mul_shoup(x[r], sw, ssh, q);
     }
   }
 }
 
-template <int LOGS, bool FWD>
+template <int LOGS, bool FWD, bool CONV>
 __global__ void __launch_bounds__(256) k_ntt_cols(NttParams P) {
   __shared__ uint64_t lds[4096];
-  const int tile = (int)(blockIdx.x % P.tiles);
-  const int64_t rest = blockIdx.x / P.tiles;
   const int64_t nab = P.na * P.nb;
-  const int64_t ab = rest % nab;
-  const int ii = (int)(rest / nab);
-  uint64_t* row = P.data + (ab / P.nb) * P.sa + (ab % P.nb) * P.sb + ((int64_t)ii << P.logN);
+  int64_t ab;
+  int ii, tile;
+  if (CONV) {
+    // the target rows of one (ab, tile) share their source tiles: keep them on one XCD
+    int64_t unit, sub;
+    xcd_map(blockIdx.x, P.ni, nab * P.tiles, unit, sub);
+    ii = (int)sub;
+    tile = (int)(unit % P.tiles);
+    ab = unit / P.tiles;
+  } else {
+    tile = (int)(blockIdx.x % P.tiles);
+    const int64_t rest = blockIdx.x / P.tiles;
+    ab = rest % nab;
+    ii = (int)(rest / nab);
+  }
+  const int64_t ia = ab / P.nb, ib = ab % P.nb;
+  uint64_t* row = P.data + ia * P.sa + ib * P.sb + ((int64_t)ii << P.logN);
+  const uint64_t* cs = CONV ? P.X.csrc + ia * P.X.csrc_sa + ib * P.X.csrc_sb : nullptr;
   const int p = P.pidx[ii];
   if (P.pc[p].k <= FP_MAX_BITS)
-    cols_body<LOGS, FWD, true>(P, row, p, tile, lds);
+    cols_body<LOGS, FWD, CONV, true>(P, row, cs, p, tile, lds);
   else
-    cols_body<LOGS, FWD, false>(P, row, p, tile, lds);
+    cols_body<LOGS, FWD, CONV, false>(P, row, cs, p, tile, lds);
 }
 
 // ------------------------------------------------------------------ pass B (rows)
@@ -235,14 +354,20 @@ __device__ __forceinline__ int swz(int l) { return l ^ ((l >> 4) & 15); }
 // from P.group limbs that share one prime (so they share all twiddles), times R/group
 // consecutive b.  COAL: accesses in the {16*j + r} layout go through an extra LDS
 // transpose so that every global load/store is coalesced.
-template <int LOGS, bool FWD, bool COAL, bool FP>
-__device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, int p, int b, uint64_t* l) {
+// FUSE: inverse - read the row out of place from inrow (through the automorphism);
+// forward - key-switch combine epilogue for row (ab, ii) instead of a store.
+template <int LOGS, bool FWD, bool COAL, bool FUSE, bool FP>
+__device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, const uint64_t* inrow, int64_t ab,
+                                          int ii, int p, int b, uint64_t* l) {
   constexpr int S = 1 << LOGS, T = S / 16;
   const int j = threadIdx.x % T;
   const PrimeConst pc = P.pc[p];
   const int N1 = 1 << (P.logN - LOGS);
   const int64_t base = N1 + b;
+  const int64_t pos0 = (int64_t)b * S;
+  const uint64_t gal = P.X.galois;
   if (FP) {
+#pragma clang fp contract(off)
     const double q = pc.qd, qi = pc.qinv;
     const double* tw = P.twf + ((int64_t)p << P.logN);
     auto bf = [&](double& X, double& Y, double w) {
@@ -267,8 +392,17 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, int
 #pragma unroll
         for (int r = 0; r < 16; ++r) l[swz(16 * j + r)] = y[r];
         __syncthreads();
+        if (FUSE) {
+          uint64_t v[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) src[j + T * r] = l[swz(j + T * r)];
+          for (int r = 0; r < 16; ++r) v[r] = l[swz(j + T * r)];
+          ks_epi16(P.X.epi, ab, ii, p, pc.q, P.logN, pos0 + j, T, v);
+        } else {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) src[j + T * r] = l[swz(j + T * r)];
+        }
+      } else if (FUSE) {
+        ks_epi16(P.X.epi, ab, ii, p, pc.q, P.logN, pos0 + 16 * j, 1, y);
       } else {
         U2* dst = reinterpret_cast<U2*>(src + 16 * j);
 #pragma unroll
@@ -276,12 +410,20 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, int
       }
     } else {
       if (COAL) {
+        if (FUSE) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) l[swz(j + T * r)] = src[j + T * r];
+          for (int r = 0; r < 16; ++r) l[swz(j + T * r)] = ld_in(inrow, pos0 + j + T * r, gal, P.logN);
+        } else {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) l[swz(j + T * r)] = src[j + T * r];
+        }
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < 16; ++r) x[r] = u64_to_f(l[swz(16 * j + r)]);
         __syncthreads();
+      } else if (FUSE) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[r] = u64_to_f(ld_in(inrow, pos0 + 16 * j + r, gal, P.logN));
       } else {
         const U2* s2 = reinterpret_cast<const U2*>(src + 16 * j);
 #pragma unroll
@@ -328,8 +470,17 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, int
 #pragma unroll
         for (int r = 0; r < 16; ++r) l[swz(16 * j + r)] = x[r];
         __syncthreads();
+        if (FUSE) {
+          uint64_t v[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) src[j + T * r] = l[swz(j + T * r)];
+          for (int r = 0; r < 16; ++r) v[r] = l[swz(j + T * r)];
+          ks_epi16(P.X.epi, ab, ii, p, q, P.logN, pos0 + j, T, v);
+        } else {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) src[j + T * r] = l[swz(j + T * r)];
+        }
+      } else if (FUSE) {
+        ks_epi16(P.X.epi, ab, ii, p, q, P.logN, pos0 + 16 * j, 1, x);
       } else {
         U2* dst = reinterpret_cast<U2*>(src + 16 * j);
 #pragma unroll
@@ -337,12 +488,20 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, int
       }
     } else {
       if (COAL) {
+        if (FUSE) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) l[swz(j + T * r)] = src[j + T * r];
+          for (int r = 0; r < 16; ++r) l[swz(j + T * r)] = ld_in(inrow, pos0 + j + T * r, gal, P.logN);
+        } else {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) l[swz(j + T * r)] = src[j + T * r];
+        }
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < 16; ++r) x[r] = l[swz(16 * j + r)];
         __syncthreads();
+      } else if (FUSE) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[r] = ld_in(inrow, pos0 + 16 * j + r, gal, P.logN);
       } else {
         const U2* s2 = reinterpret_cast<const U2*>(src + 16 * j);
 #pragma unroll
@@ -365,28 +524,42 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, int
   }
 }
 
-template <int LOGS, bool FWD, bool COAL>
+template <int LOGS, bool FWD, bool COAL, bool FUSE>
 __global__ void __launch_bounds__(256) k_ntt_rows(NttParams P) {
   constexpr int S = 1 << LOGS, T = S / 16, R = 256 / T;
   __shared__ uint64_t lds[4096];
   const int tid = threadIdx.x;
   const int G = P.group;
-  const int tile = (int)(blockIdx.x % P.tiles);
-  const int64_t rest = blockIdx.x / P.tiles;
   const int64_t nab = P.na * P.nb, ngrp = nab / G;
-  const int64_t lg = rest % ngrp;
-  const int ii = (int)(rest / ngrp);
+  int64_t lg;
+  int ii, tile;
+  if (FUSE) {
+    // all tiles of one limb group on one XCD: the automorphism gathers from the whole limb
+    int64_t unit, sub;
+    xcd_map(blockIdx.x, P.tiles, ngrp * P.ni, unit, sub);
+    tile = (int)sub;
+    lg = unit % ngrp;
+    ii = (int)(unit / ngrp);
+  } else {
+    tile = (int)(blockIdx.x % P.tiles);
+    const int64_t rest = blockIdx.x / P.tiles;
+    lg = rest % ngrp;
+    ii = (int)(rest / ngrp);
+  }
   const int rl = tid / T;
   const int64_t ab = lg * G + rl % G;
   const int b = tile * (R / G) + rl / G;
-  uint64_t* row = P.data + (ab / P.nb) * P.sa + (ab % P.nb) * P.sb + ((int64_t)ii << P.logN);
+  const int64_t ia = ab / P.nb, ib = ab % P.nb;
+  uint64_t* row = P.data + ia * P.sa + ib * P.sb + ((int64_t)ii << P.logN);
+  const uint64_t* inrow =
+      !FWD && FUSE ? P.X.in + ia * P.X.in_sa + ib * P.X.in_sb + ((int64_t)ii << P.logN) : nullptr;
   const int p = P.pidx[ii];
   uint64_t* src = row + (int64_t)b * S;
   uint64_t* l = lds + rl * S;
   if (P.pc[p].k <= FP_MAX_BITS)
-    rows_body<LOGS, FWD, COAL, true>(P, src, p, b, l);
+    rows_body<LOGS, FWD, COAL, FUSE, true>(P, src, inrow, ab, ii, p, b, l);
   else
-    rows_body<LOGS, FWD, COAL, false>(P, src, p, b, l);
+    rows_body<LOGS, FWD, COAL, FUSE, false>(P, src, inrow, ab, ii, p, b, l);
 }
 
 // ------------------------------------------------------------------ launch
@@ -412,10 +585,17 @@ int g_rows_variant[2] = {1, 1};
 
 template <int LB, bool FWD>
 void launch_rows(const NttParams& P, unsigned blocks, hipStream_t s) {
-  if (g_rows_variant[FWD ? 0 : 1])
-    hipLaunchKernelGGL((k_ntt_rows<LB, FWD, true>), dim3(blocks), dim3(256), 0, s, P);
-  else
-    hipLaunchKernelGGL((k_ntt_rows<LB, FWD, false>), dim3(blocks), dim3(256), 0, s, P);
+  const bool fuse = FWD ? P.X.has_epi != 0 : P.X.in != nullptr;
+  if (fuse) {
+    if (g_rows_variant[FWD ? 0 : 1])
+      hipLaunchKernelGGL((k_ntt_rows<LB, FWD, true, true>), dim3(blocks), dim3(256), 0, s, P);
+    else
+      hipLaunchKernelGGL((k_ntt_rows<LB, FWD, false, true>), dim3(blocks), dim3(256), 0, s, P);
+  } else if (g_rows_variant[FWD ? 0 : 1]) {
+    hipLaunchKernelGGL((k_ntt_rows<LB, FWD, true, false>), dim3(blocks), dim3(256), 0, s, P);
+  } else {
+    hipLaunchKernelGGL((k_ntt_rows<LB, FWD, false, false>), dim3(blocks), dim3(256), 0, s, P);
+  }
 }
 
 template <int LA, int LB>
@@ -435,12 +615,15 @@ void run_ntt(NttParams P, int64_t rows, bool inverse, const U2* twf, const U2* t
     P.tw = twf;
     P.twf = twff;
     P.tiles = tilesA;
-    hipLaunchKernelGGL((k_ntt_cols<LA, true>), dim3((unsigned)(rows * tilesA)), dim3(256), 0, s, P);
+    if (P.X.csrc)
+      hipLaunchKernelGGL((k_ntt_cols<LA, true, true>), dim3((unsigned)(rows * tilesA)), dim3(256), 0, s, P);
+    else
+      hipLaunchKernelGGL((k_ntt_cols<LA, true, false>), dim3((unsigned)(rows * tilesA)), dim3(256), 0, s, P);
     P.tiles = tilesB;
     ProfState& ps = prof();
     bool sample = false;
     hipEvent_t ea = nullptr, eb = nullptr;
-    if (ps.every > 0) {
+    if (ps.every > 0 && !P.X.has_epi) {  // the plain forward row pass only
       std::lock_guard<std::mutex> g(ps.mu);
       if (ps.every > 0 && (ps.seen++ % ps.every) == 0 && hipEventCreate(&ea) == hipSuccess &&
           hipEventCreate(&eb) == hipSuccess)
@@ -459,7 +642,7 @@ void run_ntt(NttParams P, int64_t rows, bool inverse, const U2* twf, const U2* t
     P.tiles = tilesB;
     launch_rows<LB, false>(P, blocksB, s);
     P.tiles = tilesA;
-    hipLaunchKernelGGL((k_ntt_cols<LA, false>), dim3((unsigned)(rows * tilesA)), dim3(256), 0, s, P);
+    hipLaunchKernelGGL((k_ntt_cols<LA, false, false>), dim3((unsigned)(rows * tilesA)), dim3(256), 0, s, P);
   }
 }
 
@@ -513,7 +696,13 @@ extern "C" int heqg_prof_stop(double* avg_us, int64_t* launches, double* avg_row
 }
 
 int launch_ntt(const DevTables& t, int log2N, const RowSet& rs, bool inverse, hipStream_t s) {
+  NttExtra x{};
+  return launch_ntt_ex(t, log2N, rs, inverse, x, s);
+}
+
+int launch_ntt_ex(const DevTables& t, int log2N, const RowSet& rs, bool inverse, const NttExtra& x, hipStream_t s) {
   NttParams P;
+  P.X = x;
   P.data = rs.data;
   P.na = rs.na;
   P.nb = rs.nb;

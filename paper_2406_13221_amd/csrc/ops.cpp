@@ -164,37 +164,78 @@ size_t mul_const_ws_words(const heqg_ctx* c, int64_t count, int n_poly, int leve
 
 void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, CtV base0, CtV base1, bool has_base1,
              CtV out, uint64_t* ws, hipStream_t s, uint64_t galois, const CtV* addend) {
-  const int N = c->g.N, nl = level + 1, np = c->g.n_p, nq = c->g.n_q, nx = nl + np, alpha = c->g.alpha;
+  const Geo& g = c->g;
+  const int N = g.N, nl = level + 1, np = g.n_p, nq = g.n_q, nx = nl + np, alpha = g.alpha;
   const int nd = (nl + alpha - 1) / alpha;
-  uint64_t* dcoef = ws;
-  uint64_t* ext = dcoef + (size_t)count * nl * N;
+  uint64_t* ycoef = ws;
+  uint64_t* ext = ycoef + (size_t)count * nl * N;
   uint64_t* acc = ext + (size_t)count * nd * nx * N;
   uint64_t* conv = acc + (size_t)count * 2 * nx * N;
   const int64_t ext_cs = (int64_t)nd * nx * N;
-  // 1. d (after the automorphism, if any) to coefficient form
-  if (galois == 1)
-    k_copy_launch(c->g, d, CtV{dcoef, (int64_t)nl * N, 0}, count, 1, nl, s);
-  else
-    k_automorph_launch(c->g, d, CtV{dcoef, (int64_t)nl * N, 0}, count, 1, nl, galois, s);
-  ntt(c, rows_q(dcoef, count, (int64_t)nl * N, 1, 0, nl), true, s);
-  // 2. ModUp per digit, then NTT of the new rows
+  const uint64_t* scale = c->t.ks_scale + 2 * (size_t)level * g.nqp;
+  const double* scalef = c->t.ks_scale_f + (size_t)level * g.nqp;
+  // 1. y = INTT(d) * (D/s)^-1 mod s per limb s of digit D, read from d through the automorphism
+  {
+    NttExtra x{};
+    x.in = d.d;
+    x.in_sa = d.cs;
+    x.galois = galois;
+    x.scale = scale;
+    x.scalef = scalef;
+    launch_ntt_ex(c->t, g.logN, rows_q(ycoef, count, (int64_t)nl * N, 1, 0, nl, 0), true, x, s);
+  }
+  // 2. ModUp per digit fused into the forward NTT of its target rows
   for (int j = 0; j < nd; ++j) {
     int lo = j * alpha, sz = std::min(alpha, nl - lo);
     std::vector<int> tgt;
-    for (int g = 0; g < nl; ++g)
-      if (g < lo || g >= lo + sz) tgt.push_back(g);
+    for (int q = 0; q < nl; ++q)
+      if (q < lo || q >= lo + sz) tgt.push_back(q);
     for (int kk = 0; kk < np; ++kk) tgt.push_back(nq + kk);
-    uint64_t* e = ext + (size_t)j * nx * N;
-    k_modup_launch(c->g, c->t, dcoef, count, level, j, e, ext_cs, s);
-    ntt(c, rows(e, count, ext_cs, 1, 0, (int)tgt.size(), tgt.data()), false, s);
+    NttExtra x{};
+    x.csrc = ycoef + (size_t)lo * N;
+    x.csrc_sa = (int64_t)nl * N;
+    x.ns = sz;
+    x.cstride = alpha;
+    x.chat = c->t.modup + 2 * (size_t)((level * g.dnum + j) * g.mu_stride) + 2 * alpha;
+    x.chatf = c->t.modup_f + 2 * (size_t)((level * g.dnum + j) * g.nqp) * alpha;
+    for (int k = 0; k < sz; ++k) x.csplit |= (c->primes[lo + k] >> FP_MAX_BITS ? 1 : 0) << k;
+    launch_ntt_ex(c->t, g.logN, rows(ext + (size_t)j * nx * N, count, ext_cs, 1, 0, (int)tgt.size(), tgt.data()),
+                  false, x, s);
   }
   // 3. inner product with the key over Q_l and P
-  k_ks_inner_launch(c->g, c->t, d, ext, ext_cs, (int64_t)nx * N, key, acc, count, level, galois, s);
-  // 4. ModDown of both parts
-  ntt(c, rows_q(acc + (size_t)nl * N, count, (int64_t)2 * nx * N, 2, (int64_t)nx * N, np, nq), true, s);
-  k_moddown_conv_launch(c->g, c->t, acc, conv, count, level, s);
-  ntt(c, rows_q(conv, count * 2, (int64_t)nl * N, 1, 0, nl), false, s);
-  k_ks_combine_launch(c->g, c->t, acc, conv, base0, base1, has_base1, out, count, level, galois, addend, s);
+  k_ks_inner_launch(g, c->t, d, ext, ext_cs, (int64_t)nx * N, key, acc, count, level, galois, s);
+  // 4. ModDown: INTT of the P rows of both parts, scaled by (P/p)^-1 ...
+  {
+    NttExtra x{};
+    x.scale = scale;
+    x.scalef = scalef;
+    launch_ntt_ex(c->t, g.logN, rows_q(acc + (size_t)nl * N, count, (int64_t)2 * nx * N, 2, (int64_t)nx * N, np, nq),
+                  true, x, s);
+  }
+  // ... then conversion P -> Q, forward NTT and (acc_Q - conv) * P^-1 + base in one launch
+  {
+    NttExtra x{};
+    x.csrc = acc + (size_t)nl * N;
+    x.csrc_sa = (int64_t)nx * N;
+    x.ns = np;
+    x.cstride = np;
+    x.chat = c->t.moddown + 2 * np;
+    x.chatf = c->t.moddown_f;
+    for (int k = 0; k < np; ++k) x.csplit |= (c->primes[nq + k] >> FP_MAX_BITS ? 1 : 0) << k;
+    x.has_epi = 1;
+    KsEpi& e = x.epi;
+    e.acc = acc;
+    e.acc_s = (int64_t)nx * N;
+    e.pinv = c->t.moddown + 2 * np + 2 * (size_t)nq * np;
+    e.base0 = base0;
+    e.base1 = base1;
+    e.has_base1 = has_base1 ? 1 : 0;
+    if (addend) e.addend = *addend;
+    e.has_addend = addend ? 1 : 0;
+    e.out = out;
+    e.galois = galois;
+    launch_ntt_ex(c->t, g.logN, rows_q(conv, count * 2, (int64_t)nl * N, 1, 0, nl, 0), false, x, s);
+  }
 }
 
 int relin(heqg_ctx* c, const heqg_keys* k, CtV in3, CtV out, int64_t count, int level, uint64_t* ws, hipStream_t s) {
