@@ -209,8 +209,8 @@ int heqg_decrypt(heqg_ctx* ctx, const heqg_keys* keys, const heqg_ct_batch* in, 
  * Key-holder refresh (stand-in for the paper's bootstrap, section 4.3 step 7):
  * decrypts, lifts each coefficient to the integer centred in q_0*q_1 (q_0 at
  * level 0), and encrypts it afresh at target_level with stream
- * (seed, object_first + b).  The scale is kept.  out may equal in only when
- * target_level == in->level.
+ * (seed, object_first + b).  The scale is kept.  out may share storage with
+ * in at any level: in is read completely (decryption) before out is written.
  */
 int heqg_refresh(heqg_ctx* ctx, const heqg_keys* keys, const heqg_ct_batch* in, int target_level, uint64_t seed,
                  uint64_t object_first, const heqg_ct_batch* out, void* ws, size_t ws_bytes, hipStream_t stream);
@@ -384,6 +384,25 @@ size_t heqg_nag_ws_bytes(const heqg_ctx* ctx, int batch, int degree);
 int heqg_nag_qg_step(heqg_ctx* ctx, const heqg_keys* keys, const heqg_ct_batch* Z, const heqg_ct* Bbar,
                      heqg_ct* W, heqg_ct* V, const heqg_sigmoid* sig, heqg_nag_state* st, int batch, void* ws,
                      size_t ws_bytes, hipStream_t stream);
+
+/*
+ * The same iteration as heqg_nag_qg_step, submitted as one HIP graph.  The
+ * first call for a given set of buffers (keys, Z, Bbar, W, V, masks, ws and
+ * their levels/scales, batch) captures the iteration's launches on `stream`
+ * and instantiates the graph; later calls with the same set replay it.  The
+ * per-iteration constants (lr_t, eta_t products) are written to the workspace
+ * by an ordinary launch before the replay, so one graph serves every t.
+ * Results are identical to heqg_nag_qg_step.  An iteration that refreshes the
+ * gradient mid-way (chains too short) draws fresh randomness per t and is
+ * launched without a graph.  stream must not be the null stream
+ * (HEQG_ERR_ARG).  The graphs belong to the context (heqg_graph_clear, or
+ * heqg_ctx_destroy, releases them); a graph must not outlive the buffers it
+ * was captured with.
+ */
+int heqg_nag_qg_graph(heqg_ctx* ctx, const heqg_keys* keys, const heqg_ct_batch* Z, const heqg_ct* Bbar,
+                      heqg_ct* W, heqg_ct* V, const heqg_sigmoid* sig, heqg_nag_state* st, int batch, void* ws,
+                      size_t ws_bytes, hipStream_t stream);
+int heqg_graph_clear(heqg_ctx* ctx);
 
 #ifdef __cplusplus
 }

@@ -222,10 +222,6 @@ extern "C" int heqg_refresh(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch
     set_err("refresh: output shape mismatch");
     return HEQG_ERR_ARG;
   }
-  if (out->data == in->data && target_level != in->level) {
-    set_err("refresh: in-place refresh must keep the level");
-    return HEQG_ERR_ARG;
-  }
   if (!ws || ws_bytes < heqg_enc_ws_bytes(c, in->count) + 8 * (size_t)in->count * (in->level + 1) * c->g.N) {
     set_err("refresh: workspace too small");
     return HEQG_ERR_ARG;

@@ -1,6 +1,7 @@
 // Host-side context and helpers of the library (not part of the C ABI).
 #pragma once
 #include <complex>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -28,6 +29,11 @@ struct heqg_ctx {
   // encode/decode support
   std::vector<std::complex<double>> fft_roots;  // exp(-2 pi i k / N), k < N/2
   std::vector<uint32_t> slot_pos;               // (5^k mod 2N - 1)/2 for k < N/2
+  // instantiated HIP graphs of NAG iterations, keyed by everything their launches depend on
+  std::map<std::string, hipGraphExec_t> graphs;
+  ~heqg_ctx() {
+    for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
+  }
 };
 
 struct heqg_keys {

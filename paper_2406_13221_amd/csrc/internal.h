@@ -85,6 +85,8 @@ struct Geo {
 
 // ---- launchers (kernels.hip / ntt.hip) ----
 int launch_ntt(const DevTables& t, int log2N, const RowSet& rows, bool inverse, hipStream_t s);
+// bumped whenever a tuning choice changes, so graphs captured before it are not reused
+int tune_epoch();
 int launch_ntt_ex(const DevTables& t, int log2N, const RowSet& rows, bool inverse, const NttExtra& x, hipStream_t s);
 
 void k_add_launch(const Geo& g, const DevTables& t, CtV a, CtV b, CtV out, int64_t count, int n_poly, int nl, bool sub,
@@ -98,7 +100,11 @@ void k_mul_pt_launch(const Geo& g, const DevTables& t, CtV a, const uint64_t* pt
 void k_add_pt_launch(const Geo& g, const DevTables& t, CtV a, const uint64_t* pt, CtV out, int64_t count, int nl,
                      hipStream_t s);
 void k_mul_scalar_launch(const Geo& g, const DevTables& t, CtV a, CtV out, int64_t count, int n_poly, int nl,
-                         const uint64_t* k_res /* host [nl][2] */, hipStream_t s);
+                         const uint64_t* k_res /* host [nl][2] */, hipStream_t s,
+                         const uint64_t* k_dev = nullptr /* device [nl][2], replaces k_res */);
+// host words -> device, through kernel arguments (usable where a copy from host memory is not)
+constexpr int kWriteWords = 240;
+void k_write_words_launch(uint64_t* dst, const uint64_t* src, size_t n, hipStream_t s);
 void k_copy_launch(const Geo& g, CtV a, CtV out, int64_t count, int n_poly, int nl, hipStream_t s);
 void k_automorph_launch(const Geo& g, CtV a, CtV out, int64_t count, int n_poly, int nl, uint64_t galois,
                         hipStream_t s);

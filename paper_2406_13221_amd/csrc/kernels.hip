@@ -5,6 +5,8 @@
 // operand) and each workgroup of 256 threads a 512-coefficient chunk of one
 // row; the grid enumerates (ciphertext, part, limb, chunk) with the chunk
 // fastest, so consecutive workgroups stream consecutive memory.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace {
@@ -196,8 +198,10 @@ __global__ void __launch_bounds__(EW_THREADS) k_add_pt(const PrimeConst* pc, CtV
   st2(out.d + ct * out.cs + out.ps + off, y.a, y.b);
 }
 
+// kdev (device, [nl] pairs) replaces k when given: the constant is then read at run time,
+// so a captured launch can be replayed with new constants
 __global__ void __launch_bounds__(EW_THREADS) k_mul_scalar(const PrimeConst* pc, CtV a, CtV out, int logN, int nl,
-                                                            int n_poly, K64 k) {
+                                                            int n_poly, K64 k, const U2* kdev) {
   const int chunks = (1 << logN) / EW_CHUNK;
   int64_t bid = blockIdx.x;
   int ch = (int)(bid % chunks);
@@ -209,7 +213,7 @@ __global__ void __launch_bounds__(EW_THREADS) k_mul_scalar(const PrimeConst* pc,
   int64_t off = ((int64_t)i << logN) + ch * EW_CHUNK + threadIdx.x * 2;
   const uint64_t q = pc[i].q;
   U2 x = ld2(a.d + ct * a.cs + p * a.ps + off);
-  U2 w = k.v[i];
+  U2 w = kdev ? kdev[i] : k.v[i];
   st2(out.d + ct * out.cs + p * out.ps + off, mul_shoup(x.a, w.a, w.b, q), mul_shoup(x.b, w.a, w.b, q));
 }
 
@@ -827,11 +831,27 @@ void k_add_pt_launch(const Geo& g, const DevTables& t, CtV a, const uint64_t* pt
   if (n) LAUNCH(k_add_pt, n, s, t.pc, a, pt, out, g.logN, nl);
 }
 void k_mul_scalar_launch(const Geo& g, const DevTables& t, CtV a, CtV out, int64_t count, int n_poly, int nl,
-                         const uint64_t* k_res, hipStream_t s) {
-  K64 k;
-  for (int i = 0; i < nl; ++i) k.v[i] = U2{k_res[2 * i], k_res[2 * i + 1]};
+                         const uint64_t* k_res, hipStream_t s, const uint64_t* k_dev) {
+  K64 k{};
+  if (!k_dev)
+    for (int i = 0; i < nl; ++i) k.v[i] = U2{k_res[2 * i], k_res[2 * i + 1]};
   int64_t n = count * n_poly * nl * CHUNKS(g);
-  if (n) LAUNCH(k_mul_scalar, n, s, t.pc, a, out, g.logN, nl, n_poly, k);
+  if (n) LAUNCH(k_mul_scalar, n, s, t.pc, a, out, g.logN, nl, n_poly, k, reinterpret_cast<const U2*>(k_dev));
+}
+
+struct Words {
+  uint64_t v[kWriteWords];
+};
+__global__ void k_write_words(uint64_t* dst, int n, Words w) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = w.v[i];
+}
+void k_write_words_launch(uint64_t* dst, const uint64_t* src, size_t n, hipStream_t s) {
+  for (size_t o = 0; o < n; o += kWriteWords) {
+    Words w{};
+    const int m = (int)std::min<size_t>(kWriteWords, n - o);
+    for (int i = 0; i < m; ++i) w.v[i] = src[o + i];
+    hipLaunchKernelGGL(k_write_words, dim3(1), dim3(256), 0, s, dst + o, m, w);
+  }
 }
 void k_copy_launch(const Geo& g, CtV a, CtV out, int64_t count, int n_poly, int nl, hipStream_t s) {
   int64_t n = count * n_poly * nl * CHUNKS(g);

@@ -14,6 +14,8 @@
 
 namespace {
 
+constexpr size_t kConstWords = 1024;  // device words for the constant products of one iteration
+
 struct Ct {
   uint64_t* d;
   int64_t cs, ps;
@@ -38,6 +40,8 @@ struct Exec {
   size_t next = 0;
   uint64_t* ks_ws;
   uint64_t* rs_ws;
+  std::vector<uint64_t> consts;   // residue tables of this run's constant products, in call order
+  uint64_t* consts_dev = nullptr; // their device copy (graph replays read them at run time)
 
   int N() const { return c->g.N; }
   double q(int l) const { return (double)c->primes[l]; }
@@ -133,8 +137,13 @@ struct Exec {
     if (a.level < 1) fail(HEQG_ERR_LEVEL, "level exhausted");
     int64_t kint;
     if (ops::const_int(c, cst, target, a.level, a.scale, &kint)) fail(HEQG_ERR_OVERFLOW, "constant overflow");
+    const size_t off = consts.size();
+    ops::const_residues(c, kint, a.level, consts);
+    if (consts.size() > kConstWords) fail(HEQG_ERR_ARG, "internal: constant table full");
     Ct o = slot(a.n_poly, a.level - 1, target, a.count);
-    if (!dry) ops::mul_const(c, a.v(), a.count, a.n_poly, a.level, a.scale, cst, target, o.v(), rs_ws, s);
+    if (!dry)
+      ops::mul_const(c, a.v(), a.count, a.n_poly, a.level, a.scale, cst, target, o.v(), rs_ws, s,
+                     consts_dev ? consts_dev + off : nullptr);
     return o;
   }
   // x <- x + Rot(x, step), reusing x's slot (x must be the most recent allocation);
@@ -276,12 +285,28 @@ extern "C" size_t heqg_nag_ws_bytes(const heqg_ctx* c, int batch, int degree) {
   size_t ks = std::max(ops::rot_ws_words(c, batch, top),
                        ops::enc_ws_words(c, 1) + (size_t)c->g.n_q * c->g.N);
   size_t rs = 2 * slot_words(c, batch);
-  return 8 * (kSlots * slot_words(c, batch) + ks + rs);
+  return 8 * (kSlots * slot_words(c, batch) + ks + rs + kConstWords);
 }
 
-extern "C" int heqg_nag_qg_step(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch* Z, const heqg_ct* Bbar,
-                                heqg_ct* W, heqg_ct* V, const heqg_sigmoid* sg, heqg_nag_state* st, int batch,
-                                void* ws, size_t ws_bytes, hipStream_t s) {
+static std::string graph_key(const heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch* Z, const heqg_ct* Bbar,
+                             const heqg_ct* W, const heqg_ct* V, const heqg_sigmoid* sg, const heqg_nag_state* st,
+                             int batch, const void* ws, size_t ws_bytes) {
+  std::string key;
+  auto put = [&](const void* p, size_t n) { key.append(static_cast<const char*>(p), n); };
+  auto val = [&](auto v) { put(&v, sizeof(v)); };
+  val(k);
+  val(Z->data), val(Z->count), val(Z->stride), val(Z->level), val(Z->scale);
+  for (const heqg_ct* x : {Bbar, W, V}) val(x->data), val(x->level), val(x->scale);
+  val(sg->masks), val(sg->degree), val(sg->mask_level);
+  for (int i = 0; i <= n_terms(sg->degree); ++i) val(sg->mask_scales[i]);
+  val(st->m_rows), val(st->g_cols), val(batch), val(ws), val(ws_bytes), val(tune_epoch());
+  (void)c;
+  return key;
+}
+
+static int nag_step(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch* Z, const heqg_ct* Bbar, heqg_ct* W,
+                    heqg_ct* V, const heqg_sigmoid* sg, heqg_nag_state* st, int batch, void* ws, size_t ws_bytes,
+                    hipStream_t s, bool graph) {
   if (!c || !k || !Z || !Bbar || !W || !V || !sg || !st || !Z->data || !Bbar->data || !W->data || !V->data ||
       !sg->masks || !sg->mask_scales) {
     set_err("nag_qg_step: null argument");
@@ -307,6 +332,10 @@ extern "C" int heqg_nag_qg_step(heqg_ctx* c, const heqg_keys* k, const heqg_ct_b
     set_err("nag_qg_step: workspace too small");
     return HEQG_ERR_ARG;
   }
+  if (graph && !s) {
+    set_err("nag_qg_graph: a HIP graph cannot be captured on the null stream");
+    return HEQG_ERR_ARG;
+  }
   const int N = c->g.N;
   Exec X{c, k, s, true, batch, c->g.n_q};
   uint64_t* w = static_cast<uint64_t*>(ws);
@@ -314,6 +343,7 @@ extern "C" int heqg_nag_qg_step(heqg_ctx* c, const heqg_keys* k, const heqg_ct_b
   X.ks_ws = w + (size_t)kSlots * slot_words(c, batch);
   X.rs_ws = X.ks_ws + std::max(ops::rot_ws_words(c, batch, c->g.n_q - 1),
                                ops::enc_ws_words(c, 1) + (size_t)c->g.n_q * N);
+  uint64_t* consts_dev = X.rs_ws + 2 * slot_words(c, batch);
   Io io;
   io.Z = Ct{Z->data, Z->stride, (int64_t)(Z->level + 1) * N, 2, Z->level, Z->scale, Z->count};
   io.Bbar = Ct{Bbar->data, 0, (int64_t)(Bbar->level + 1) * N, 2, Bbar->level, Bbar->scale, 1};
@@ -321,24 +351,65 @@ extern "C" int heqg_nag_qg_step(heqg_ctx* c, const heqg_keys* k, const heqg_ct_b
   io.V = Ct{V->data, 0, (int64_t)(V->level + 1) * N, 2, V->level, V->scale, 1};
   heqg_nag_state st_dry = *st;
   Ct Wn{}, Vn{};
-  try {
-    circuit(X, io, sg, &st_dry, Z->count, Wn, Vn);   // plan: validates everything, launches nothing
+  auto real_run = [&]() {
     X.dry = false;
+    X.consts.clear();
     heqg_nag_state st_run = *st;
     circuit(X, io, sg, &st_run, Z->count, Wn, Vn);
     // W', V' back into the caller's buffers, compact [2][level+1][N]
     k_copy_launch(c->g, Vn.v(), CtV{V->data, 0, (int64_t)(Vn.level + 1) * N}, 1, 2, Vn.level + 1, s);
     k_copy_launch(c->g, Wn.v(), CtV{W->data, 0, (int64_t)(Wn.level + 1) * N}, 1, 2, Wn.level + 1, s);
+  };
+  try {
+    circuit(X, io, sg, &st_dry, Z->count, Wn, Vn);   // plan: validates everything, launches nothing
+    // an iteration that refreshes mid-way draws fresh randomness per t: it is not replayable
+    if (graph && !st_dry.refreshed_gr) {
+      const std::string key = graph_key(c, k, Z, Bbar, W, V, sg, st, batch, ws, ws_bytes);
+      k_write_words_launch(consts_dev, X.consts.data(), X.consts.size(), s);
+      auto it = c->graphs.find(key);
+      if (it == c->graphs.end()) {
+        X.consts_dev = consts_dev;
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+          set_err(std::string("nag_qg_graph: begin capture: ") + hipGetErrorString(e));
+          return HEQG_ERR_DEVICE;
+        }
+        hipGraph_t gr = nullptr;
+        try {
+          real_run();
+        } catch (const Fail&) {
+          hipStreamEndCapture(s, &gr);
+          if (gr) hipGraphDestroy(gr);
+          throw;
+        }
+        e = hipStreamEndCapture(s, &gr);
+        hipGraphExec_t ge = nullptr;
+        if (e == hipSuccess) e = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+        if (gr) hipGraphDestroy(gr);
+        if (e != hipSuccess) {
+          set_err(std::string("nag_qg_graph: capture: ") + hipGetErrorString(e));
+          return HEQG_ERR_DEVICE;
+        }
+        it = c->graphs.emplace(key, ge).first;
+      }
+      hipError_t e = hipGraphLaunch(it->second, s);
+      if (e != hipSuccess) {
+        set_err(std::string("nag_qg_graph: launch: ") + hipGetErrorString(e));
+        return HEQG_ERR_DEVICE;
+      }
+    } else {
+      real_run();
+    }
     W->level = Wn.level;
     W->scale = Wn.scale;
     V->level = Vn.level;
     V->scale = Vn.scale;
-    st->eta = st_run.eta;
-    st->lr = st_run.lr;
-    st->refreshed_gr = st_run.refreshed_gr;
+    st->eta = st_dry.eta;
+    st->lr = st_dry.lr;
+    st->refreshed_gr = st_dry.refreshed_gr;
     st->t += 1;
-    st->alpha0 = st_run.alpha1;
-    st->alpha1 = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * st_run.alpha1 * st_run.alpha1));
+    st->alpha0 = st_dry.alpha1;
+    st->alpha1 = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * st_dry.alpha1 * st_dry.alpha1));
   } catch (const Fail& f) {
     return f.code;
   }
@@ -347,5 +418,27 @@ extern "C" int heqg_nag_qg_step(heqg_ctx* c, const heqg_keys* k, const heqg_ct_b
     set_err(std::string("nag_qg_step: ") + hipGetErrorString(e));
     return HEQG_ERR_DEVICE;
   }
+  return HEQG_OK;
+}
+
+extern "C" int heqg_nag_qg_step(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch* Z, const heqg_ct* Bbar,
+                                heqg_ct* W, heqg_ct* V, const heqg_sigmoid* sg, heqg_nag_state* st, int batch,
+                                void* ws, size_t ws_bytes, hipStream_t s) {
+  return nag_step(c, k, Z, Bbar, W, V, sg, st, batch, ws, ws_bytes, s, false);
+}
+
+extern "C" int heqg_nag_qg_graph(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch* Z, const heqg_ct* Bbar,
+                                 heqg_ct* W, heqg_ct* V, const heqg_sigmoid* sg, heqg_nag_state* st, int batch,
+                                 void* ws, size_t ws_bytes, hipStream_t s) {
+  return nag_step(c, k, Z, Bbar, W, V, sg, st, batch, ws, ws_bytes, s, true);
+}
+
+extern "C" int heqg_graph_clear(heqg_ctx* c) {
+  if (!c) {
+    set_err("graph_clear: null ctx");
+    return HEQG_ERR_ARG;
+  }
+  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
   return HEQG_OK;
 }

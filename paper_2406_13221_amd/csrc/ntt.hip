@@ -623,7 +623,9 @@ void run_ntt(NttParams P, int64_t rows, bool inverse, const U2* twf, const U2* t
     ProfState& ps = prof();
     bool sample = false;
     hipEvent_t ea = nullptr, eb = nullptr;
-    if (ps.every > 0 && !P.X.has_epi) {  // the plain forward row pass only
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (ps.every > 0 && !P.X.has_epi && hipStreamIsCapturing(s, &cap) == hipSuccess &&
+        cap == hipStreamCaptureStatusNone) {  // the plain forward row pass of eager launches only
       std::lock_guard<std::mutex> g(ps.mu);
       if (ps.every > 0 && (ps.seen++ % ps.every) == 0 && hipEventCreate(&ea) == hipSuccess &&
           hipEventCreate(&eb) == hipSuccess)
@@ -648,8 +650,12 @@ void run_ntt(NttParams P, int64_t rows, bool inverse, const U2* twf, const U2* t
 
 }  // namespace
 
+static int g_tune_epoch = 0;
+int tune_epoch() { return g_tune_epoch; }
+
 extern "C" int heqg_tune_set(int which, int value) {
   if (which < 0 || which > 1 || value < 0 || value > 1) return -1;
+  if (g_rows_variant[which] != value) ++g_tune_epoch;
   g_rows_variant[which] = value;
   return 0;
 }

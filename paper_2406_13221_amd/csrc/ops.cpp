@@ -299,21 +299,25 @@ int const_int(const heqg_ctx* c, double cst, double target, int level, double in
   return HEQG_OK;
 }
 
+void const_residues(const heqg_ctx* c, int64_t k, int level, std::vector<uint64_t>& kr) {
+  for (int i = 0; i <= level; ++i) {
+    uint64_t q = c->primes[i];
+    uint64_t m = k < 0 ? (q - (uint64_t)(-(__int128)k % q)) % q : (uint64_t)k % q;
+    kr.push_back(m);
+    kr.push_back(h_shoup(m, q));
+  }
+}
+
 int mul_const(heqg_ctx* c, CtV in, int64_t count, int n_poly, int level, double in_scale, double cst, double target,
-              CtV out, uint64_t* ws, hipStream_t s) {
+              CtV out, uint64_t* ws, hipStream_t s, const uint64_t* kdev) {
   int64_t kint;
   int rc = const_int(c, cst, target, level, in_scale, &kint);
   if (rc) return rc;
   const int N = c->g.N, nl = level + 1;
-  std::vector<uint64_t> kr(2 * (size_t)nl);
-  for (int i = 0; i < nl; ++i) {
-    uint64_t q = c->primes[i];
-    uint64_t m = kint < 0 ? (q - (uint64_t)(-(__int128)kint % q)) % q : (uint64_t)kint % q;
-    kr[2 * i] = m;
-    kr[2 * i + 1] = h_shoup(m, q);
-  }
+  std::vector<uint64_t> kr;
+  const_residues(c, kint, level, kr);
   CtV t{ws, (int64_t)n_poly * nl * N, (int64_t)nl * N};
-  k_mul_scalar_launch(c->g, c->t, in, t, count, n_poly, nl, kr.data(), s);
+  k_mul_scalar_launch(c->g, c->t, in, t, count, n_poly, nl, kr.data(), s, kdev);
   rescale(c, t, out, count, n_poly, level, ws + (size_t)count * n_poly * nl * N, s);
   return HEQG_OK;
 }

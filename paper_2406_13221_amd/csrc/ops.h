@@ -1,5 +1,6 @@
 // Internal operations behind the C ABI (device work enqueued on a stream).
 #pragma once
+#include <vector>
 #include "ctx.h"
 
 namespace ops {
@@ -35,7 +36,10 @@ int rotate(heqg_ctx* c, const heqg_keys* k, CtV in, CtV out, int64_t count, int 
            hipStream_t s, const CtV* addend = nullptr);
 void rescale(heqg_ctx* c, CtV in, CtV out, int64_t count, int n_poly, int level, uint64_t* ws, hipStream_t s);
 int const_int(const heqg_ctx* c, double cst, double target, int level, double in_scale, int64_t* k);
+// residues of the integer k modulo q_0..q_level with Shoup companions, appended to kr
+void const_residues(const heqg_ctx* c, int64_t k, int level, std::vector<uint64_t>& kr);
+// kdev: the same residue table already on the device (read at run time) instead of a host copy
 int mul_const(heqg_ctx* c, CtV in, int64_t count, int n_poly, int level, double in_scale, double cst, double target,
-              CtV out, uint64_t* ws, hipStream_t s);
+              CtV out, uint64_t* ws, hipStream_t s, const uint64_t* kdev = nullptr);
 
 }  // namespace ops

@@ -110,6 +110,9 @@ def lib():
         "heqg_nag_ws_bytes": (sz, [vp, i32, i32]),
         "heqg_nag_qg_step": (i32, [vp, vp, P(BatchS), P(CtS), P(CtS), P(CtS), P(SigmoidS), P(NagStateS), i32, vp,
                                    sz, vp]),
+        "heqg_nag_qg_graph": (i32, [vp, vp, P(BatchS), P(CtS), P(CtS), P(CtS), P(SigmoidS), P(NagStateS), i32, vp,
+                                    sz, vp]),
+        "heqg_graph_clear": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -311,8 +314,10 @@ class Context:
         rows = self.decrypt(keys, ct)[index].cpu().numpy().view(np.uint64)
         return self.decode(self.lift(rows, ct.level), ct.scale, n)
 
-    def refresh(self, keys, ct, target_level, seed, obj_first):
-        out = self.empty(ct.count, 2, target_level, ct.scale)
+    def refresh(self, keys, ct, target_level, seed, obj_first, out=None):
+        """Fresh encryption of ct's message at target_level; out (optional) may share ct's storage."""
+        if out is None:
+            out = self.empty(ct.count, 2, target_level, ct.scale)
         L = lib()
         nb = L.heqg_enc_ws_bytes(self.h, ct.count) + 8 * ct.count * (ct.level + 1) * self.N
         ws = _ws(nb)
@@ -411,10 +416,11 @@ class Context:
         return lib().heqg_nag_ws_bytes(self.h, batch, degree)
 
     def nag_qg_step(self, keys, Z, Bbar, W, V, masks, mask_level, mask_scales, degree, state, batch, ws=None,
-                    stream=None):
+                    stream=None, graph=False):
         """One encrypted QG-NAG iteration; W and V (count-1 Cts) are updated in place.
 
-        masks: int64 tensor [n_terms + 1, mask_level + 1, N] (NTT form); state: NagStateS (updated)."""
+        masks: int64 tensor [n_terms + 1, mask_level + 1, N] (NTT form); state: NagStateS (updated).
+        graph: submit the iteration as a replayed HIP graph (heqg_nag_qg_graph); needs a non-null stream."""
         L = lib()
         if ws is None:
             ws = _ws(self.nag_ws_bytes(batch, degree))
@@ -423,14 +429,17 @@ class Context:
         zb = Z.batch()
         bb, wb, vb = Bbar.one(), W.one(), V.one()
         s = _stream() if stream is None else ctypes.c_void_p(stream)
-        _check(L.heqg_nag_qg_step(self.h, keys.handle, ctypes.byref(zb), ctypes.byref(bb), ctypes.byref(wb),
-                                  ctypes.byref(vb), ctypes.byref(sig), ctypes.byref(state), batch, ws.data_ptr(),
-                                  ws.numel(), s))
+        fn = L.heqg_nag_qg_graph if graph else L.heqg_nag_qg_step
+        _check(fn(self.h, keys.handle, ctypes.byref(zb), ctypes.byref(bb), ctypes.byref(wb), ctypes.byref(vb),
+                  ctypes.byref(sig), ctypes.byref(state), batch, ws.data_ptr(), ws.numel(), s))
         for ct, cs in ((W, wb), (V, vb)):
             n = 2 * (cs.level + 1) * self.N
             ct.data = ct.data.reshape(-1)[:n].view(1, 2, cs.level + 1, self.N)
             ct.level, ct.scale = cs.level, cs.scale
         return state
+
+    def graph_clear(self):
+        _check(lib().heqg_graph_clear(self.h))
 
     def mul_const(self, a, c, target):
         out = self.empty(a.count, a.n_poly, a.level - 1, target)

@@ -90,7 +90,8 @@ def new_state(m, g, refresh_seed=0, lr_max=2.0, lr_min=1.0, T=81.0, gamma=2.5):
 class EncryptedQGNAG:
     """Client + cloud roles of the pipeline on one GPU."""
 
-    def __init__(self, cfg, X, y, coeffs=None, batch=16, rows=None, threads=0, mini_batch=False):
+    def __init__(self, cfg, X, y, coeffs=None, batch=16, rows=None, threads=0, mini_batch=False, graph=False):
+        """graph: submit each iteration as a replayed HIP graph (on a side stream of this object)."""
         import torch
         self.cfg = cfg
         self.m, self.g = cfg["m"], cfg["g"]
@@ -133,6 +134,10 @@ class EncryptedQGNAG:
         zero = np.zeros((1, ctx.N), dtype=np.int64)
         self.W = ctx.encrypt(self.keys, zero, L, ctx.delta, cfg["enc_seed"], (1 << 40) + 1)
         self.V = ctx.encrypt(self.keys, zero, L, ctx.delta, cfg["enc_seed"], (1 << 40) + 2)
+        # W and V keep their storage for the whole run (a replayed graph is bound to it)
+        self.Wbuf, self.Vbuf = self.W.data, self.V.data
+        self.graph = graph
+        self.stream = torch.cuda.Stream() if graph else None
         self.set_sigmoid(self.coeffs)
         self.state = new_state(self.m, self.g, refresh_seed=cfg["enc_seed"] + 7)
         self.ws = heqg._ws(ctx.nag_ws_bytes(batch, self.degree))
@@ -159,20 +164,31 @@ class EncryptedQGNAG:
 
     def step(self, refresh=True):
         """One iteration: all blocks (full batch) or the blocks of batch t mod n_batches with its B-bar."""
+        if self.stream is None:
+            return self._step(refresh)
+        import torch
+        cur = torch.cuda.current_stream()
+        self.stream.wait_stream(cur)
+        with torch.cuda.stream(self.stream):
+            self._step(refresh)
+        cur.wait_stream(self.stream)
+        return self.state
+
+    def _step(self, refresh):
         ctx = self.ctx
         k = self.state.t % len(self.block_spans)
         b0, b1 = self.block_spans[k]
         Z = heqg.Cts(self.Z.data[b0:b1], self.Z.level, self.Z.scale)
         ctx.nag_qg_step(self.keys, Z, self.Bbars[k], self.W, self.V, self.masks, self.mask_level, self.mask_scales,
-                        self.degree, self.state, self.batch, self.ws)
+                        self.degree, self.state, self.batch, self.ws, graph=self.graph)
         if refresh:
             self.refresh()
         return self.state
 
     def refresh(self):
-        o = self.refresh_obj
-        self.W = self.ctx.refresh(self.keys, self.W, self.L, self.cfg["enc_seed"] + 9, o)
-        self.V = self.ctx.refresh(self.keys, self.V, self.L, self.cfg["enc_seed"] + 9, o + 1)
+        o, L, d = self.refresh_obj, self.L, self.ctx.delta
+        self.W = self.ctx.refresh(self.keys, self.W, L, self.cfg["enc_seed"] + 9, o, out=heqg.Cts(self.Wbuf, L, d))
+        self.V = self.ctx.refresh(self.keys, self.V, L, self.cfg["enc_seed"] + 9, o + 1, out=heqg.Cts(self.Vbuf, L, d))
         self.refresh_obj += 2
 
     def weights(self, f=None):
