@@ -65,6 +65,57 @@ def cpu_baseline(cfg, data, n_blocks):
                        "once-per-iteration tail is not included" % (n_blocks, dt, n_blocks))
 
 
+def iteration_model_bytes(cfg, n_blocks, degree=3):
+    """Bytes of one full-batch iteration if every primitive reads its inputs and writes its
+    outputs once (a limb = 8N bytes; an NTT reads and writes each limb once; switching keys
+    read once per iteration, so not counted per block)."""
+    N, nq, np_, dnum = 1 << cfg["log2N"], len(cfg["q_bits"]), cfg["n_p"], cfg["dnum"]
+    alpha = -(-nq // dnum)
+    g, m = cfg["g"], cfg["m"]
+    lg, lm = g.bit_length() - 1, m.bit_length() - 1
+
+    def ks(n):                     # key switch of one part with n limbs (result: 2 parts)
+        digits = [min(alpha, n - j * alpha) for j in range(-(-n // alpha))]
+        ext = n + np_
+        tgt = sum(ext - d for d in digits)
+        return (2 * n                      # INTT of the input part
+                + n + tgt                  # ModUp: read digits, write targets
+                + 2 * tgt                  # NTT of the targets
+                + len(digits) * ext + 2 * ext   # inner product: read extended digits, write 2 parts
+                + 2 * 2 * np_              # INTT of the special rows
+                + 2 * np_ + 2 * n          # ModDown conversion
+                + 2 * 2 * n                # NTT of the conversion
+                + 3 * 2 * n)               # (acc - conv) P^-1 + base: read 2, write 1
+
+    def rescale(n, parts):         # n limbs -> n-1
+        return parts * (2 + 2 * (n - 1) + 2 * n)   # INTT of the last limb, NTT of its spread, combine
+
+    def hmult_rs(n):               # tensor + relin + rescale
+        return 7 * n + ks(n) + 3 * 2 * n + rescale(n, 2)
+
+    def add_rot(n):                # x + Rot(x)
+        return ks(n) + 2 * n + 3 * 2 * n
+
+    L = nq - 1
+    per_block = 0
+    n = L + 1
+    per_block += hmult_rs(n)                       # u = Z (x) W
+    n -= 1
+    per_block += lg * add_rot(n)                   # row sums
+    per_block += 2 * (4 * n + rescale(n, 2))       # two masked plaintext products
+    per_block += hmult_rs(n)                       # u^2
+    n -= 1
+    per_block += hmult_rs(n)                       # b3 * u^2
+    if degree >= 5:
+        per_block += hmult_rs(n)
+    n -= 1
+    per_block += 2 * 3 * n + 3 * n                 # additions, + F/2
+    per_block += lg * add_rot(n)                   # replication
+    per_block += 7 * n + 3 * 2 * n                 # Z (x) p accumulated
+    tail = 3 * n + ks(n) + rescale(n, 2) + lm * add_rot(n - 1) + 2 * hmult_rs(n - 1)
+    return 8.0 * N * (per_block * n_blocks + tail)
+
+
 def pmc_traffic(avg_rows):
     """HBM bytes per launch of the row pass from committed rocprofv3 --pmc summaries, or None."""
     try:
@@ -87,6 +138,9 @@ def main():
     ap.add_argument("--batch", type=int, default=16, help="blocks per lock-step chunk")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--prof-every", type=int, default=16)
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (NTT split/variants, chunk size)")
+    ap.add_argument("--graph-steps", type=int, default=1, help="timed graph-replayed full-batch iterations")
+    ap.add_argument("--mini-steps", type=int, default=10, help="timed mini-batch steps (eager and graph)")
     ap.add_argument("--mode", default="train", choices=["train", "ntt"],
                     help="ntt: only the batched forward NTT (768 limbs) and a 1 GiB device copy, for counters")
     args = ap.parse_args()
@@ -122,6 +176,10 @@ def main():
     torch.cuda.synchronize()
     log("setup %.1f s, %d blocks, %.1f GB resident" % (time.perf_counter() - t0, run.Z.count,
                                                        torch.cuda.memory_allocated() / 1e9))
+    tuning = None
+    if not args.no_tune:
+        tuning = run.tune()
+        log("tuned: %s" % tuning)
     for i in range(args.warmup):
         run.step()
         torch.cuda.synchronize()
@@ -144,6 +202,52 @@ def main():
     upd = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps / 1000.0
     ref = sum(e[1].elapsed_time(e[2]) for e in ev) / args.steps / 1000.0
     log("timed %d steps: %.3f s/step (update %.3f s, refresh %.4f s)" % (args.steps, ms_per_step / 1e3, upd, ref))
+
+    # the same iteration submitted as a replayed HIP graph (first call captures, untimed)
+    graph_s = None
+    if args.graph_steps > 0:
+        run.graph, run.stream = True, torch.cuda.Stream()
+        run.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.graph_steps):
+            run.step()
+        torch.cuda.synchronize()
+        graph_s = (time.perf_counter() - t0) / args.graph_steps
+        run.graph, run.stream = False, None
+        run.ctx.graph_clear()
+        log("graph-replayed iteration: %.3f s" % graph_s)
+
+    # mini-batch steps (Algorithm 1, 1,024 rows = 8 blocks per batch), eager and graph-replayed
+    mini = None
+    if args.mini_steps > 0 and cfg.get("batch_rows"):
+        import copy
+        mb = run.with_batches(cfg["batch_rows"], batch=8)
+        mb.step()
+        torch.cuda.synchronize()
+        st0 = copy.copy(mb.state)
+        t0 = time.perf_counter()
+        for _ in range(args.mini_steps):
+            mb.step()
+        torch.cuda.synchronize()
+        eager_ms = (time.perf_counter() - t0) * 1e3 / args.mini_steps
+        mb.graph, mb.stream = True, torch.cuda.Stream()
+        mb.state = copy.copy(st0)
+        for _ in range(args.mini_steps):     # capture one graph per batch
+            mb.step()
+        torch.cuda.synchronize()
+        mb.state = copy.copy(st0)
+        t0 = time.perf_counter()
+        for _ in range(args.mini_steps):     # replay them
+            mb.step()
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - t0) * 1e3 / args.mini_steps
+        run.ctx.graph_clear()
+        mini = {"ms_per_step_eager": round(eager_ms, 2), "ms_per_step_graph": round(graph_ms, 2),
+                "blocks_per_step": mb.block_spans[0][1] - mb.block_spans[0][0], "steps": args.mini_steps,
+                "n_batches": len(mb.block_spans)}
+        log("mini-batch step: eager %.2f ms, graph %.2f ms" % (eager_ms, graph_ms))
+        del mb
 
     # NTT throughput: forward + inverse over a batch of 768 limbs, as read once + written once per transform
     N = run.ctx.N
@@ -177,6 +281,11 @@ def main():
                 "kernel": "k_ntt_rows<8,true> (forward NTT, second pass)",
                 "avg_launch_us": round(avg_us, 2), "sampled_launches": n_sampled, "avg_rows_per_launch": avg_rows}
 
+    model = iteration_model_bytes(cfg, run.Z.count)
+    it_roof = {"model_bytes": model, "achieved_GBps": round(model / upd / 1e9, 1), "peak": HBM_PEAK_GBS,
+               "frac": round(model / upd / 1e9 / HBM_PEAK_GBS, 4),
+               "note": "each primitive reads its inputs and writes its outputs once; keys read once per iteration"}
+
     out = {
         "metric": "sec per encrypted QG-NAG iteration (422k x 200, N=2^16)",
         "value": round(ms_per_step / 1000.0, 4),
@@ -193,12 +302,16 @@ def main():
         "config": {"workload": "%s full-batch QG-NAG iteration + W/V refresh" % cfg["name"],
                    "n_samples": cfg["n_train"], "n_features": cfg["n_features"], "log2N": cfg["log2N"],
                    "limbs": len(cfg["q_bits"]), "dnum": cfg["dnum"], "blocks": run.Z.count,
-                   "rows_per_block": cfg["m"], "cols": cfg["g"], "batch_blocks": args.batch},
+                   "rows_per_block": cfg["m"], "cols": cfg["g"], "batch_blocks": run.batch},
         "update_s": round(upd, 4),
         "refresh_s": round(ref, 5),
         "ntt_gbps": {"forward": round(fwd_gbs, 1), "inverse": round(inv_gbs, 1), "limbs_per_call": nrows,
                      "frac_of_hbm_peak": round(fwd_gbs / HBM_PEAK_GBS, 4)},
         "roofline": roofline,
+        "iteration_roofline": it_roof,
+        "graph_s_per_iter": None if graph_s is None else round(graph_s, 4),
+        "minibatch": mini,
+        "tuning": tuning,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

@@ -291,14 +291,32 @@ int heqg_prof_start(int every);
 int heqg_prof_stop(double* avg_us, int64_t* launches, double* avg_rows);
 
 /*
- * Kernel-variant switches read by the launchers (process-wide; set by the
- * autotuner in the Python package).  which = 0: forward NTT row pass,
- * 1: inverse NTT row pass; value 0 = 16-byte accesses in the per-thread
- * contiguous layout, 1 = coalesced accesses through an LDS transpose.
- * Every variant computes identical results.  Returns -1 on a bad selector.
+ * Kernel-variant switches read by the launchers (process-wide; set by
+ * heqg_tune_ntt).  which = 0: forward NTT row pass, 1: inverse NTT row pass;
+ * value 0 = 16-byte accesses in the per-thread contiguous layout, 1 =
+ * coalesced accesses through an LDS transpose.  which = 2 (forward) / 3
+ * (inverse): log2 of the first-pass size for the ring of the most recently
+ * created or tuned context (N = 2^15: 7 or 8; other rings: their one split,
+ * 2^8 x 2^8 at N = 2^16, since a pass holds at most 2^8 points).  Every choice computes
+ * identical results.  Returns -1 on a bad selector or value.
  */
 int heqg_tune_set(int which, int value);
 int heqg_tune_get(int which);
+
+/*
+ * NTT autotuner: times the forward and the inverse transform of `rows` limbs
+ * (rounded down to a multiple of n_q, at least n_q; the ctx's Q primes in
+ * turn) for every pass split and row-pass variant, each after one warm-up
+ * launch, as the mean of 3 launches, and keeps the fastest per direction for
+ * this ctx's ring degree.  Synchronous: it zeroes and uses the caller's
+ * workspace ws (heqg_tune_ws_bytes) on `stream` and waits for it.  choice
+ * (4 ints, may be NULL) receives {split_fwd, variant_fwd, split_inv,
+ * variant_inv}; best_us (2 doubles, may be NULL) the fastest mean times.
+ * Graphs captured before a changed choice are not replayed afterwards.
+ */
+size_t heqg_tune_ws_bytes(const heqg_ctx* ctx, int rows);
+int heqg_tune_ntt(heqg_ctx* ctx, int rows, void* ws, size_t ws_bytes, hipStream_t stream, int* choice,
+                  double* best_us);
 
 /* ------------------------------------------------------------------ */
 /* Learned sigmoid polynomial (replaces the fixed cubic of section 4.1)  */

@@ -19,6 +19,9 @@ extern "C" size_t heqg_ctx_tables_bytes(const heqg_params* p) {
   return n;
 }
 
+// ring degree of the most recently created or tuned context (the NTT pass splits are per ring)
+static int last_log2N = 16;
+
 extern "C" int heqg_ctx_create(const heqg_params* p, void* dev_tables, size_t bytes, heqg_ctx** out) {
   if (!p || !out) {
     set_err("ctx_create: null argument");
@@ -36,6 +39,7 @@ extern "C" int heqg_ctx_create(const heqg_params* p, void* dev_tables, size_t by
     return rc;
   }
   *out = c;
+  last_log2N = c->g.logN;
   return HEQG_OK;
 }
 
@@ -453,4 +457,87 @@ extern "C" int heqg_mul_const(heqg_ctx* c, const heqg_ct_batch* in, double cst, 
   }
   return ops::mul_const(c, view_of(c, in), in->count, in->n_poly, in->level, in->scale, cst, target, view_of(c, out),
                         static_cast<uint64_t*>(ws), s);
+}
+
+// ------------------------------------------------------------------ tuning
+
+extern "C" int heqg_tune_set(int which, int value) {
+  if (which == 0 || which == 1) return rows_variant_set(which, value);
+  if (which == 2 || which == 3) {
+    int las[8], n = 0;
+    ntt_split_options(last_log2N, las, &n);
+    for (int i = 0; i < n; ++i)
+      if (las[i] == value) {
+        ntt_split_set(which == 3, last_log2N, value);
+        return 0;
+      }
+  }
+  return -1;
+}
+
+extern "C" int heqg_tune_get(int which) {
+  if (which == 0 || which == 1) return rows_variant_get(which);
+  if (which == 2 || which == 3) return ntt_split_get(which == 3, last_log2N);
+  return -1;
+}
+
+extern "C" size_t heqg_tune_ws_bytes(const heqg_ctx* c, int rows) {
+  if (!c) return 0;
+  const int nq = c->g.n_q;
+  const int64_t na = std::max<int64_t>(1, rows / nq);
+  return 8 * (size_t)na * nq * c->g.N;
+}
+
+extern "C" int heqg_tune_ntt(heqg_ctx* c, int rows, void* ws, size_t ws_bytes, hipStream_t s, int* choice,
+                             double* best_us) {
+  if (!c || !ws || rows < 1 || ws_bytes < heqg_tune_ws_bytes(c, rows)) {
+    set_err("tune_ntt: null argument or workspace too small");
+    return HEQG_ERR_ARG;
+  }
+  last_log2N = c->g.logN;
+  const int nq = c->g.n_q, N = c->g.N;
+  const int64_t na = std::max<int64_t>(1, rows / nq);
+  uint64_t* data = static_cast<uint64_t*>(ws);
+  RowSet rs = ops::rows_q(data, na, (int64_t)nq * N, 1, 0, nq, 0);
+  if (hipMemsetAsync(data, 0, 8 * (size_t)na * nq * N, s) != hipSuccess) {
+    set_err("tune_ntt: memset failed");
+    return HEQG_ERR_DEVICE;
+  }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    set_err("tune_ntt: event creation failed");
+    return HEQG_ERR_DEVICE;
+  }
+  int las[8], nl = 0;
+  ntt_split_options(c->g.logN, las, &nl);
+  int rc = HEQG_OK;
+  for (int dir = 0; dir < 2 && rc == HEQG_OK; ++dir) {
+    const bool inv = dir == 1;
+    double best = 1e30;
+    int best_la = ntt_split_get(inv, c->g.logN), best_v = rows_variant_get(dir);
+    for (int i = 0; i < nl && rc == HEQG_OK; ++i)
+      for (int v = 0; v < 2 && rc == HEQG_OK; ++v) {
+        ntt_split_set(inv, c->g.logN, las[i]);
+        rows_variant_set(dir, v);
+        launch_ntt(c->t, c->g.logN, rs, inv, s);  // warm-up
+        hipEventRecord(e0, s);
+        for (int r = 0; r < 3; ++r) launch_ntt(c->t, c->g.logN, rs, inv, s);
+        hipEventRecord(e1, s);
+        float ms = 0.f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          set_err("tune_ntt: timing failed");
+          rc = HEQG_ERR_DEVICE;
+          break;
+        }
+        const double us = 1000.0 * ms / 3.0;
+        if (us < best) best = us, best_la = las[i], best_v = v;
+      }
+    ntt_split_set(inv, c->g.logN, best_la);
+    rows_variant_set(dir, best_v);
+    if (choice) choice[2 * dir] = best_la, choice[2 * dir + 1] = best_v;
+    if (best_us) best_us[dir] = best;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return rc;
 }

@@ -87,6 +87,12 @@ struct Geo {
 int launch_ntt(const DevTables& t, int log2N, const RowSet& rows, bool inverse, hipStream_t s);
 // bumped whenever a tuning choice changes, so graphs captured before it are not reused
 int tune_epoch();
+// NTT pass split: the first pass of a 2^log2N transform has 2^la points (la in the options)
+void ntt_split_options(int log2N, int* las, int* n);
+int ntt_split_get(bool inverse, int log2N);
+void ntt_split_set(bool inverse, int log2N, int la);
+int rows_variant_set(int which, int value);
+int rows_variant_get(int which);
 int launch_ntt_ex(const DevTables& t, int log2N, const RowSet& rows, bool inverse, const NttExtra& x, hipStream_t s);
 
 void k_add_launch(const Geo& g, const DevTables& t, CtV a, CtV b, CtV out, int64_t count, int n_poly, int nl, bool sub,

@@ -319,6 +319,7 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
 
 template <int LOGS, bool FWD, bool CONV>
 __global__ void __launch_bounds__(256) k_ntt_cols(NttParams P) {
+  static_assert(LOGS >= 6 && LOGS <= 8, "16 residues per thread cover 4 strided + 4 contiguous stages");
   __shared__ uint64_t lds[4096];
   const int64_t nab = P.na * P.nb;
   int64_t ab;
@@ -526,6 +527,7 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
 
 template <int LOGS, bool FWD, bool COAL, bool FUSE>
 __global__ void __launch_bounds__(256) k_ntt_rows(NttParams P) {
+  static_assert(LOGS >= 6 && LOGS <= 8, "16 residues per thread cover 4 strided + 4 contiguous stages");
   constexpr int S = 1 << LOGS, T = S / 16, R = 256 / T;
   __shared__ uint64_t lds[4096];
   const int tid = threadIdx.x;
@@ -578,6 +580,8 @@ ProfState& prof() {
   static ProfState p;
   return p;
 }
+
+int g_tune_epoch = 0;
 
 // Row-pass variant: 0 = 16-byte accesses in the consecutive layout, 1 = LDS-transposed
 // coalesced accesses.  Process-wide choice per direction (set by the tuner).
@@ -650,17 +654,18 @@ void run_ntt(NttParams P, int64_t rows, bool inverse, const U2* twf, const U2* t
 
 }  // namespace
 
-static int g_tune_epoch = 0;
+
 int tune_epoch() { return g_tune_epoch; }
 
-extern "C" int heqg_tune_set(int which, int value) {
+// rows-pass variants (which 0, 1); the pass splits (which 2, 3) are per ring and set in api.cpp
+int rows_variant_set(int which, int value) {
   if (which < 0 || which > 1 || value < 0 || value > 1) return -1;
   if (g_rows_variant[which] != value) ++g_tune_epoch;
   g_rows_variant[which] = value;
   return 0;
 }
 
-extern "C" int heqg_tune_get(int which) {
+int rows_variant_get(int which) {
   if (which < 0 || which > 1) return -1;
   return g_rows_variant[which];
 }
@@ -726,13 +731,48 @@ int launch_ntt_ex(const DevTables& t, int log2N, const RowSet& rs, bool inverse,
   if (rows <= 0) return 0;
   const U2* twf = reinterpret_cast<const U2*>(t.tw_fwd);
   const U2* twi = reinterpret_cast<const U2*>(t.tw_inv);
-  switch (log2N) {
-    case 12: run_ntt<6, 6>(P, rows, inverse, twf, twi, t.tw_fwd_f, t.tw_inv_f, s); break;
-    case 13: run_ntt<6, 7>(P, rows, inverse, twf, twi, t.tw_fwd_f, t.tw_inv_f, s); break;
-    case 14: run_ntt<7, 7>(P, rows, inverse, twf, twi, t.tw_fwd_f, t.tw_inv_f, s); break;
-    case 15: run_ntt<7, 8>(P, rows, inverse, twf, twi, t.tw_fwd_f, t.tw_inv_f, s); break;
-    case 16: run_ntt<8, 8>(P, rows, inverse, twf, twi, t.tw_fwd_f, t.tw_inv_f, s); break;
+  const int la = ntt_split_get(inverse, log2N);
+#define HEQG_RUN(A, B) run_ntt<A, B>(P, rows, inverse, twf, twi, t.tw_fwd_f, t.tw_inv_f, s)
+  switch (log2N * 16 + la) {
+    case 12 * 16 + 6: HEQG_RUN(6, 6); break;
+    case 13 * 16 + 6: HEQG_RUN(6, 7); break;
+    case 14 * 16 + 7: HEQG_RUN(7, 7); break;
+    case 15 * 16 + 7: HEQG_RUN(7, 8); break;
+    case 15 * 16 + 8: HEQG_RUN(8, 7); break;
+    case 16 * 16 + 8: HEQG_RUN(8, 8); break;
     default: return -1;
   }
+#undef HEQG_RUN
   return 0;
+}
+
+// ------------------------------------------------------------------ pass split choice
+static int g_split[2][17] = {};
+
+void ntt_split_options(int log2N, int* las, int* n) {
+  // a pass holds at most 2^8 points (4 strided + 4 contiguous register stages)
+  static const int o12[] = {6}, o13[] = {6}, o14[] = {7}, o15[] = {7, 8}, o16[] = {8};
+  const int* o = nullptr;
+  int k = 0;
+  switch (log2N) {
+    case 12: o = o12, k = 1; break;
+    case 13: o = o13, k = 1; break;
+    case 14: o = o14, k = 1; break;
+    case 15: o = o15, k = 2; break;
+    case 16: o = o16, k = 1; break;
+  }
+  for (int i = 0; i < k; ++i) las[i] = o[i];
+  *n = k;
+}
+
+int ntt_split_get(bool inverse, int log2N) {
+  if (log2N < 12 || log2N > 16) return 0;
+  const int v = g_split[inverse ? 1 : 0][log2N];
+  return v ? v : log2N / 2;
+}
+
+void ntt_split_set(bool inverse, int log2N, int la) {
+  if (log2N < 12 || log2N > 16) return;
+  if (ntt_split_get(inverse, log2N) != la) ++g_tune_epoch;
+  g_split[inverse ? 1 : 0][log2N] = la;
 }

@@ -105,6 +105,8 @@ def lib():
                                     ctypes.c_float, vp, vp, sz, vp]),
         "heqg_tune_set": (i32, [i32, i32]),
         "heqg_tune_get": (i32, [i32]),
+        "heqg_tune_ws_bytes": (sz, [vp, i32]),
+        "heqg_tune_ntt": (i32, [vp, i32, vp, sz, vp, P(i32), P(dbl)]),
         "heqg_prof_start": (i32, [i32]),
         "heqg_prof_stop": (i32, [P(dbl), P(i64), P(dbl)]),
         "heqg_nag_ws_bytes": (sz, [vp, i32, i32]),
@@ -437,6 +439,16 @@ class Context:
             ct.data = ct.data.reshape(-1)[:n].view(1, 2, cs.level + 1, self.N)
             ct.level, ct.scale = cs.level, cs.scale
         return state
+
+    def tune_ntt(self, rows=384):
+        """Time every NTT pass split and row-pass variant on `rows` limbs; keep the fastest per direction."""
+        L = lib()
+        ws = _ws(L.heqg_tune_ws_bytes(self.h, rows))
+        ch = (ctypes.c_int * 4)()
+        us = (ctypes.c_double * 2)()
+        _check(L.heqg_tune_ntt(self.h, rows, ws.data_ptr(), ws.numel(), _stream(), ch, us))
+        return {"split_fwd": ch[0], "variant_fwd": ch[1], "split_inv": ch[2], "variant_inv": ch[3],
+                "fwd_us": round(us[0], 2), "inv_us": round(us[1], 2)}
 
     def graph_clear(self):
         _check(lib().heqg_graph_clear(self.h))

@@ -103,6 +103,7 @@ class EncryptedQGNAG:
         L = ctx.top_level
         self.L = L
         Xs, ys = (X, y) if rows is None else (X[rows[0]:rows[1]], y[rows[0]:rows[1]])
+        self._X, self._n_rows = Xs, Xs.shape[0]
         # step 1-2: Z blocks, B-bar, W = V = 0 (client side)
         blocks = pack_rows(z_matrix(Xs, ys, self.g), self.m, self.g)
         nb = blocks.shape[0]
@@ -142,6 +143,70 @@ class EncryptedQGNAG:
         self.state = new_state(self.m, self.g, refresh_seed=cfg["enc_seed"] + 7)
         self.ws = heqg._ws(ctx.nag_ws_bytes(batch, self.degree))
         self.refresh_obj = 1 << 41
+
+    def tune(self, candidates=(8, 16, 24), blocks=48, rows=384):
+        """Autotune: NTT pass split and row-pass variants (heqg_tune_ntt), then the number of
+        blocks per lock-step chunk, timed on one iteration over the first `blocks` blocks."""
+        import copy
+        import torch
+        ctx = self.ctx
+        res = {"ntt": ctx.tune_ntt(rows)}
+        nb = min(blocks, self.Z.count)
+        Z = heqg.Cts(self.Z.data[:nb], self.Z.level, self.Z.scale)
+        times = {}
+        for B in candidates:
+            B = min(B, nb)
+            ws = heqg._ws(ctx.nag_ws_bytes(B, self.degree))
+            best = None
+            for _ in range(2):
+                W = heqg.Cts(self.W.data.clone(), self.W.level, self.W.scale)
+                V = heqg.Cts(self.V.data.clone(), self.V.level, self.V.scale)
+                st = copy.copy(self.state)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                ctx.nag_qg_step(self.keys, Z, self.Bbars[0], W, V, self.masks, self.mask_level, self.mask_scales,
+                                self.degree, st, B, ws)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1)
+                best = ms if best is None else min(best, ms)
+            times[B] = round(best, 2)
+            del ws
+        self.batch = min(times, key=times.get)
+        self.ws = heqg._ws(ctx.nag_ws_bytes(self.batch, self.degree))
+        res["batch_ms"] = times
+        res["batch"] = self.batch
+        return res
+
+    def with_batches(self, batch_rows, batch=8, graph=False):
+        """A mini-batch run (Algorithm 1: one B-bar per batch of rows) over the same encrypted blocks and keys."""
+        import copy
+        import torch
+        if batch_rows % self.m:
+            raise ValueError("batch_rows must be a multiple of m")
+        ctx, L = self.ctx, self.L
+        mb = copy.copy(self)
+        n = self._n_rows
+        spans = [(s, min(s + batch_rows, n)) for s in range(0, n, batch_rows)]
+        mb.block_spans = [(s // self.m, -(-e // self.m)) for s, e in spans]
+        mb.Bbars = []
+        for i, (s, e) in enumerate(spans):
+            B = bbar_diag(self._X[s:e], self.g)
+            sB = 2.0 ** 50 / B.max()
+            mb.Bbars.append(ctx.encrypt(self.keys, ctx.encode(tile_row(B, self.m, self.g), sB)[None], L, sB,
+                                        self.cfg["enc_seed"], (1 << 40) + (1 << 20) + i))
+        mb.Bbar = mb.Bbars[0]
+        zero = np.zeros((1, ctx.N), dtype=np.int64)
+        mb.W = ctx.encrypt(self.keys, zero, L, ctx.delta, self.cfg["enc_seed"], (1 << 40) + 3)
+        mb.V = ctx.encrypt(self.keys, zero, L, ctx.delta, self.cfg["enc_seed"], (1 << 40) + 4)
+        mb.Wbuf, mb.Vbuf = mb.W.data, mb.V.data
+        mb.state = new_state(self.m, self.g, refresh_seed=self.cfg["enc_seed"] + 7)
+        mb.batch = batch
+        mb.ws = heqg._ws(ctx.nag_ws_bytes(batch, self.degree))
+        mb.graph = graph
+        mb.stream = torch.cuda.Stream() if graph else None
+        mb.refresh_obj = 1 << 42
+        return mb
 
     def set_sigmoid(self, coeffs):
         """Encode -c_k F for each odd power (ascending) and F/2 at the planned scales, NTT form at level L-1."""
