@@ -1,9 +1,10 @@
 // One encrypted quadratic-gradient NAG iteration (paper: Algorithm 1, the
 // full-batch form of section 3.3, and steps 4-6 of the pipeline in section 4.3).
 //
-// The blocks are processed in lock-step chunks of `batch` ciphertexts, so
-// every launch covers batch x parts x limbs rows; each switching key is read
-// once per chunk instead of once per block.  The circuit is first run "dry"
+// The blocks are processed in lock-step chunks of at most `batch` ciphertexts
+// (balanced sizes, so the iteration does not end on a short, under-filled
+// chunk); every launch covers chunk x parts x limbs rows and each switching key
+// is read once per chunk instead of once per block.  The circuit is first run "dry"
 // on the host (levels, scales, key availability, constants) and only then
 // enqueued, so every error is reported before any device work starts.
 #include <cmath>
@@ -225,8 +226,12 @@ void circuit(Exec& X, const Io& io, const heqg_sigmoid* sg, heqg_nag_state* st, 
   X.reset(0);
   Ct accs = X.slot(3, 0, 0.0, 1);
   size_t base = X.next;
-  for (int64_t b0 = 0; b0 < n_blocks; b0 += X.B) {
-    const int64_t cnt = std::min<int64_t>(X.B, n_blocks - b0);
+  // balanced chunks of at most B blocks: the remainder of n_blocks / B is spread over the
+  // chunks instead of ending the iteration with one short, under-filled chunk
+  const int64_t n_chunks = (n_blocks + X.B - 1) / X.B;
+  const int64_t q_chunk = n_blocks / n_chunks, r_chunk = n_blocks % n_chunks;
+  for (int64_t ci = 0, b0 = 0; ci < n_chunks; ++ci) {
+    const int64_t cnt = q_chunk + (ci < r_chunk ? 1 : 0);
     X.reset(base);
     Ct Zc = io.Z;
     Zc.d = io.Z.d + b0 * io.Z.cs;
@@ -248,6 +253,7 @@ void circuit(Exec& X, const Io& io, const heqg_sigmoid* sg, heqg_nag_state* st, 
     }
     if (!X.dry) k_tensor_reduce_launch(X.c->g, X.c->t, Zd.v(), p.v(), cnt, acc.v(), p.level + 1, have_acc, X.s);
     have_acc = true;
+    b0 += cnt;
   }
   X.reset(base);
   Ct gr = X.rescale(X.relin(acc));

@@ -1,0 +1,91 @@
+"""Parity at the paper's full size (N = 2^16, 24 limbs, dnum 4, 422,108 x 200):
+batched key-switching operations in the chunk geometry the benchmark launches
+(24 ciphertexts per launch), compared with the oracle on sampled members of
+the batch; and one full-batch iteration over all 3,298 blocks, decrypted and
+compared with the FP64 plaintext trainer."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import trainer
+from tests.gpu_common import assert_same_ct, make_pair
+
+pytestmark = pytest.mark.gpu
+
+CHUNK = 24               # blocks per launch in the benchmark's tuned configuration
+PICKS = (0, 11, 23)      # members of the batch the oracle recomputes
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _pick(ct, i):
+    from paper_2406_13221_amd import heqg
+    return heqg.Cts(ct.data[i:i + 1], ct.level, ct.scale)
+
+
+@pytest.fixture(scope="module")
+def c3(torch_cuda):
+    steps = [1, -8, 256]
+    cfg, ora, ctx = make_pair("c3")
+    ora.keygen(cfg["key_seed"], steps)
+    keys = ctx.keygen(cfg["key_seed"], steps)
+    L = ora.top_level
+    rng = np.random.default_rng(33)
+    m1 = rng.integers(-2 ** 45, 2 ** 45, (CHUNK, ora.N))
+    m2 = rng.integers(-2 ** 45, 2 ** 45, (CHUNK, ora.N))
+    g1 = ctx.encrypt(keys, m1, L, ora.delta, cfg["enc_seed"], 1000)
+    g2 = ctx.encrypt(keys, m2, L, ora.delta, cfg["enc_seed"], 2000)
+    o1 = {i: ora.encrypt(m1[i], L, ora.delta, cfg["enc_seed"], 1000 + i) for i in PICKS}
+    o2 = {i: ora.encrypt(m2[i], L, ora.delta, cfg["enc_seed"], 2000 + i) for i in PICKS}
+    return dict(cfg=cfg, ora=ora, ctx=ctx, keys=keys, g1=g1, g2=g2, o1=o1, o2=o2)
+
+
+def test_c3_encrypt_sampled(c3):
+    for i in PICKS:
+        assert_same_ct(_pick(c3["g1"], i), c3["o1"][i], "enc[%d]" % i)
+
+
+def test_c3_rotations_sampled(c3):
+    ctx, ora, keys = c3["ctx"], c3["ora"], c3["keys"]
+    for st in (1, -8, 256):
+        r = ctx.rotate(keys, c3["g1"], st)
+        for i in PICKS:
+            assert_same_ct(_pick(r, i), ora.rotate(c3["o1"][i], st), "rot%d[%d]" % (st, i))
+
+
+def test_c3_relin_rescale_sampled(c3):
+    ctx, ora, keys = c3["ctx"], c3["ora"], c3["keys"]
+    t = ctx.tensor(c3["g1"], c3["g2"])
+    r = ctx.relin(keys, t)
+    s = ctx.rescale(r)
+    for i in PICKS:
+        to = ora.tensor(c3["o1"][i], c3["o2"][i])
+        ro = ora.relin(to)
+        assert_same_ct(_pick(r, i), ro, "relin[%d]" % i)
+        assert_same_ct(_pick(s, i), ora.rescale(ro), "rescale[%d]" % i)
+
+
+def test_c3_low_level_rotation_sampled(c3):
+    # the last digit shrinks as levels drop: level 19 has digits of 6, 6, 6, 2 limbs
+    ctx, ora, keys = c3["ctx"], c3["ora"], c3["keys"]
+    r = ctx.rotate(keys, ctx.drop(c3["g1"], 19), -8)
+    for i in PICKS[:2]:
+        assert_same_ct(_pick(r, i), ora.rotate(ora.drop(c3["o1"][i], 19), -8), "rot-low[%d]" % i)
+
+
+def test_c3_full_batch_iteration_matches_fp64(torch_cuda):
+    from paper_2406_13221_amd.train import EncryptedQGNAG
+    cfg = synth.get_config("c3")
+    d = synth.make_dataset(cfg)
+    run = EncryptedQGNAG(cfg, d["X"], d["y"], batch=CHUNK)
+    assert run.Z.count == 3298
+    run.step()
+    w = run.weights(cfg["g"])
+    ref = trainer.train(d["X"], d["y"], cfg["g"], 1)
+    assert np.abs(w - ref["history"][0]["W"]).max() < 1e-3

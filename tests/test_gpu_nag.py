@@ -92,8 +92,8 @@ def test_c1_steps_bit_exact(torch_cuda):
 
 
 def test_c2_minibatch_step_bit_exact_ragged_chunks(torch_cuda):
-    # batch 0 of 1,024 rows = 4 blocks of 256 rows with its own B-bar; chunks of 3 + 1 blocks
-    run_parity("c2", 1, batch=3, rows=(0, 1024))
+    # 1,280 rows = 5 blocks of 256 rows with their own B-bar; at most 3 per chunk: chunks of 3 + 2
+    run_parity("c2", 1, batch=3, rows=(0, 1280))
 
 
 @pytest.mark.parametrize("degree", [5, 7])
