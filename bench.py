@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PMC_FILE = os.path.join(ROOT, "profiles", "ntt_rows_fwd_c3_pmc.json")
+PMC_FILE = os.path.join(ROOT, "profiles", "conv_cols_c3_pmc.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2406_13221_amd", "csrc", "ntt.hip")
 
 
@@ -117,7 +117,9 @@ def iteration_model_bytes(cfg, n_blocks, degree=3):
 
 
 def pmc_traffic(avg_rows):
-    """HBM bytes per launch of the row pass from committed rocprofv3 --pmc summaries, or None."""
+    """HBM bytes (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy) per launch of the fused conversion
+    column pass, from the committed rocprofv3 --pmc summary: bytes per output row x rows per launch.
+    None when the summary is missing or the NTT source has changed since it was taken."""
     try:
         with open(PMC_FILE) as f:
             pm = json.load(f)
@@ -143,6 +145,8 @@ def main():
     ap.add_argument("--mini-steps", type=int, default=10, help="timed mini-batch steps (eager and graph)")
     ap.add_argument("--mode", default="train", choices=["train", "ntt"],
                     help="ntt: only the batched forward NTT (768 limbs) and a 1 GiB device copy, for counters")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="end with a 1 GiB device copy (the scale of HBM byte counters in a profiled run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path (see DESIGN.md for how "
@@ -197,7 +201,8 @@ def main():
         ev[k][2].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    avg_us, n_sampled, avg_rows = heqg.prof_stop()
+    conv_us, conv_n, conv_rows, conv_src = heqg.prof_stop(1)
+    avg_us, n_sampled, avg_rows, _ = heqg.prof_stop(0)
     ms_per_step = (t1 - t0) * 1000.0 / args.steps
     upd = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps / 1000.0
     ref = sum(e[1].elapsed_time(e[2]) for e in ev) / args.steps / 1000.0
@@ -275,11 +280,23 @@ def main():
         print("decrypted weights out of range", file=sys.stderr)
         sys.exit(1)
 
-    achieved = 16.0 * N * avg_rows / (avg_us * 1e-6) / 1e9 if avg_us > 0 else 0.0
+    # dominant kernel: the fused base-conversion column pass; algorithmic bytes per launch = every
+    # output row written once + every distinct source row read once (8N bytes a row)
+    conv_bytes = 8.0 * N * (conv_rows + conv_src)
+    achieved = conv_bytes / (conv_us * 1e-6) / 1e9 if conv_us > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": pmc_traffic(avg_rows),
-                "kernel": "k_ntt_rows<8,true> (forward NTT, second pass)",
-                "avg_launch_us": round(avg_us, 2), "sampled_launches": n_sampled, "avg_rows_per_launch": avg_rows}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": pmc_traffic(conv_rows),
+                "kernel": "k_ntt_cols<8,true,true> (ModUp / ModDown base conversion fused into the first "
+                          "forward NTT pass)",
+                "algorithmic_bytes_per_launch": conv_bytes,
+                "avg_launch_us": round(conv_us, 2), "sampled_launches": conv_n,
+                "avg_rows_per_launch": round(conv_rows, 2), "avg_source_rows_per_launch": round(conv_src, 2)}
+    row_pass = 16.0 * N * avg_rows / (avg_us * 1e-6) / 1e9 if avg_us > 0 else 0.0
+    ntt_row_roofline = {"bound": "hbm", "achieved": round(row_pass, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(row_pass / HBM_PEAK_GBS, 4),
+                        "kernel": "k_ntt_rows<8,true,*,false> (plain forward NTT, second pass)",
+                        "avg_launch_us": round(avg_us, 2), "sampled_launches": n_sampled,
+                        "avg_rows_per_launch": round(avg_rows, 2)}
 
     model = iteration_model_bytes(cfg, run.Z.count)
     it_roof = {"model_bytes": model, "achieved_GBps": round(model / upd / 1e9, 1), "peak": HBM_PEAK_GBS,
@@ -308,11 +325,18 @@ def main():
         "ntt_gbps": {"forward": round(fwd_gbs, 1), "inverse": round(inv_gbs, 1), "limbs_per_call": nrows,
                      "frac_of_hbm_peak": round(fwd_gbs / HBM_PEAK_GBS, 4)},
         "roofline": roofline,
+        "ntt_row_pass_roofline": ntt_row_roofline,
         "iteration_roofline": it_roof,
         "graph_s_per_iter": None if graph_s is None else round(graph_s, 4),
         "minibatch": mini,
         "tuning": tuning,
     }
+    if args.copy_probe:
+        src = torch.ones(1 << 27, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(cfg, data, run.Z.count)

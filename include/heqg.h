@@ -279,16 +279,21 @@ int heqg_ntt(heqg_ctx* ctx, uint64_t* dev_rows, int64_t n_rows, int first_prime,
              hipStream_t s);
 
 /*
- * Launch-duration sampling of the forward NTT row pass (the second of the two
- * passes, the most time-consuming kernel of an iteration): after
- * heqg_prof_start(every), every `every`-th launch of that kernel, on whatever
- * stream it is enqueued, is bracketed by two hipEvents recorded on the same
- * stream.  heqg_prof_stop synchronises those events and returns the mean
- * duration in microseconds, the number of sampled launches and the mean
- * number of N-word rows per sampled launch; it disables sampling.  Process-wide.
+ * Launch-duration sampling of two kernel classes: kernel 0 = the plain
+ * forward NTT row pass (second pass), kernel 1 = the fused base-conversion
+ * column pass (ModUp or ModDown conversion + first forward NTT pass, the most
+ * time-consuming kernel of an iteration).  After heqg_prof_start(every),
+ * every `every`-th eager launch of each class, on whatever stream it is
+ * enqueued, is bracketed by two hipEvents recorded on the same stream (launches
+ * inside a captured graph are not sampled).  heqg_prof_stop(kernel, ...)
+ * disables sampling, synchronises that class's events and returns the mean
+ * duration in microseconds, the number of sampled launches, the mean number of
+ * N-word rows written per launch and (kernel 1) the mean number of distinct
+ * source rows read per launch; it releases that class's samples.  Process-wide.
+ * Returns -1 for a bad class, HEQG_ERR_DEVICE (-6) if an event failed.
  */
 int heqg_prof_start(int every);
-int heqg_prof_stop(double* avg_us, int64_t* launches, double* avg_rows);
+int heqg_prof_stop(int kernel, double* avg_us, int64_t* launches, double* avg_rows, double* avg_src_rows);
 
 /*
  * Kernel-variant switches read by the launchers (process-wide; set by

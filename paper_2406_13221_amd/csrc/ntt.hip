@@ -348,7 +348,9 @@ __global__ void __launch_bounds__(256) k_ntt_cols(NttParams P) {
 }
 
 // ------------------------------------------------------------------ pass B (rows)
-// LDS position of element l of a row (XOR swizzle of the low 4 bits).
+// LDS position of element l of a row (XOR swizzle of the low 4 bits).  Sub-rows are
+// 2^LOGS words apart, a multiple of the bank period, so odd sub-rows also flip bit 4
+// (fl): the two sub-rows that share a half-wave then use complementary banks.
 __device__ __forceinline__ int swz(int l) { return l ^ ((l >> 4) & 15); }
 
 // A workgroup transforms R = 256/T sub-rows: P.group rows of the same index b taken
@@ -359,7 +361,7 @@ __device__ __forceinline__ int swz(int l) { return l ^ ((l >> 4) & 15); }
 // forward - key-switch combine epilogue for row (ab, ii) instead of a store.
 template <int LOGS, bool FWD, bool COAL, bool FUSE, bool FP>
 __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, const uint64_t* inrow, int64_t ab,
-                                          int ii, int p, int b, uint64_t* l) {
+                                          int ii, int p, int b, uint64_t* l, int fl) {
   constexpr int S = 1 << LOGS, T = S / 16;
   const int j = threadIdx.x % T;
   const PrimeConst pc = P.pc[p];
@@ -380,10 +382,10 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
       for (int r = 0; r < 16; ++r) x[r] = as_f(src[j + T * r]);
       stages_strided<true>(x, tw, base, bf);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) l[swz(j + T * r)] = as_u(x[r]);
+      for (int r = 0; r < 16; ++r) l[fl ^ swz(j + T * r)] = as_u(x[r]);
       __syncthreads();
 #pragma unroll
-      for (int r = 0; r < 16; ++r) x[r] = as_f(l[swz(16 * j + r)]);
+      for (int r = 0; r < 16; ++r) x[r] = as_f(l[fl ^ swz(16 * j + r)]);
       stages_contig<LOGS, true>(x, tw, base, j, bf);
       uint64_t y[16];
 #pragma unroll
@@ -391,16 +393,16 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
       if (COAL) {
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 16; ++r) l[swz(16 * j + r)] = y[r];
+        for (int r = 0; r < 16; ++r) l[fl ^ swz(16 * j + r)] = y[r];
         __syncthreads();
         if (FUSE) {
           uint64_t v[16];
 #pragma unroll
-          for (int r = 0; r < 16; ++r) v[r] = l[swz(j + T * r)];
+          for (int r = 0; r < 16; ++r) v[r] = l[fl ^ swz(j + T * r)];
           ks_epi16(P.X.epi, ab, ii, p, pc.q, P.logN, pos0 + j, T, v);
         } else {
 #pragma unroll
-          for (int r = 0; r < 16; ++r) src[j + T * r] = l[swz(j + T * r)];
+          for (int r = 0; r < 16; ++r) src[j + T * r] = l[fl ^ swz(j + T * r)];
         }
       } else if (FUSE) {
         ks_epi16(P.X.epi, ab, ii, p, pc.q, P.logN, pos0 + 16 * j, 1, y);
@@ -413,14 +415,14 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
       if (COAL) {
         if (FUSE) {
 #pragma unroll
-          for (int r = 0; r < 16; ++r) l[swz(j + T * r)] = ld_in(inrow, pos0 + j + T * r, gal, P.logN);
+          for (int r = 0; r < 16; ++r) l[fl ^ swz(j + T * r)] = ld_in(inrow, pos0 + j + T * r, gal, P.logN);
         } else {
 #pragma unroll
-          for (int r = 0; r < 16; ++r) l[swz(j + T * r)] = src[j + T * r];
+          for (int r = 0; r < 16; ++r) l[fl ^ swz(j + T * r)] = src[j + T * r];
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 16; ++r) x[r] = u64_to_f(l[swz(16 * j + r)]);
+        for (int r = 0; r < 16; ++r) x[r] = u64_to_f(l[fl ^ swz(16 * j + r)]);
         __syncthreads();
       } else if (FUSE) {
 #pragma unroll
@@ -436,10 +438,10 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
       }
       stages_contig<LOGS, false>(x, tw, base, j, bf);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) l[swz(16 * j + r)] = as_u(x[r]);
+      for (int r = 0; r < 16; ++r) l[fl ^ swz(16 * j + r)] = as_u(x[r]);
       __syncthreads();
 #pragma unroll
-      for (int r = 0; r < 16; ++r) x[r] = as_f(l[swz(j + T * r)]);
+      for (int r = 0; r < 16; ++r) x[r] = as_f(l[fl ^ swz(j + T * r)]);
       stages_strided<false>(x, tw, base, bf);
 #pragma unroll
       for (int r = 0; r < 16; ++r) src[j + T * r] = as_u(x[r]);
@@ -456,10 +458,10 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
       for (int r = 0; r < 16; ++r) x[r] = src[j + T * r];
       stages_strided<true>(x, tw, base, bf);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) l[swz(j + T * r)] = x[r];
+      for (int r = 0; r < 16; ++r) l[fl ^ swz(j + T * r)] = x[r];
       __syncthreads();
 #pragma unroll
-      for (int r = 0; r < 16; ++r) x[r] = l[swz(16 * j + r)];
+      for (int r = 0; r < 16; ++r) x[r] = l[fl ^ swz(16 * j + r)];
       stages_contig<LOGS, true>(x, tw, base, j, bf);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
@@ -469,16 +471,16 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
       if (COAL) {
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 16; ++r) l[swz(16 * j + r)] = x[r];
+        for (int r = 0; r < 16; ++r) l[fl ^ swz(16 * j + r)] = x[r];
         __syncthreads();
         if (FUSE) {
           uint64_t v[16];
 #pragma unroll
-          for (int r = 0; r < 16; ++r) v[r] = l[swz(j + T * r)];
+          for (int r = 0; r < 16; ++r) v[r] = l[fl ^ swz(j + T * r)];
           ks_epi16(P.X.epi, ab, ii, p, q, P.logN, pos0 + j, T, v);
         } else {
 #pragma unroll
-          for (int r = 0; r < 16; ++r) src[j + T * r] = l[swz(j + T * r)];
+          for (int r = 0; r < 16; ++r) src[j + T * r] = l[fl ^ swz(j + T * r)];
         }
       } else if (FUSE) {
         ks_epi16(P.X.epi, ab, ii, p, q, P.logN, pos0 + 16 * j, 1, x);
@@ -491,14 +493,14 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
       if (COAL) {
         if (FUSE) {
 #pragma unroll
-          for (int r = 0; r < 16; ++r) l[swz(j + T * r)] = ld_in(inrow, pos0 + j + T * r, gal, P.logN);
+          for (int r = 0; r < 16; ++r) l[fl ^ swz(j + T * r)] = ld_in(inrow, pos0 + j + T * r, gal, P.logN);
         } else {
 #pragma unroll
-          for (int r = 0; r < 16; ++r) l[swz(j + T * r)] = src[j + T * r];
+          for (int r = 0; r < 16; ++r) l[fl ^ swz(j + T * r)] = src[j + T * r];
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 16; ++r) x[r] = l[swz(16 * j + r)];
+        for (int r = 0; r < 16; ++r) x[r] = l[fl ^ swz(16 * j + r)];
         __syncthreads();
       } else if (FUSE) {
 #pragma unroll
@@ -514,10 +516,10 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
       }
       stages_contig<LOGS, false>(x, tw, base, j, bf);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) l[swz(16 * j + r)] = x[r];
+      for (int r = 0; r < 16; ++r) l[fl ^ swz(16 * j + r)] = x[r];
       __syncthreads();
 #pragma unroll
-      for (int r = 0; r < 16; ++r) x[r] = l[swz(j + T * r)];
+      for (int r = 0; r < 16; ++r) x[r] = l[fl ^ swz(j + T * r)];
       stages_strided<false>(x, tw, base, bf);
 #pragma unroll
       for (int r = 0; r < 16; ++r) src[j + T * r] = x[r];
@@ -558,28 +560,61 @@ __global__ void __launch_bounds__(256) k_ntt_rows(NttParams P) {
   const int p = P.pidx[ii];
   uint64_t* src = row + (int64_t)b * S;
   uint64_t* l = lds + rl * S;
+  const int fl = (rl & 1) << 4;
   if (P.pc[p].k <= FP_MAX_BITS)
-    rows_body<LOGS, FWD, COAL, FUSE, true>(P, src, inrow, ab, ii, p, b, l);
+    rows_body<LOGS, FWD, COAL, FUSE, true>(P, src, inrow, ab, ii, p, b, l, fl);
   else
-    rows_body<LOGS, FWD, COAL, FUSE, false>(P, src, inrow, ab, ii, p, b, l);
+    rows_body<LOGS, FWD, COAL, FUSE, false>(P, src, inrow, ab, ii, p, b, l, fl);
 }
 
 // ------------------------------------------------------------------ launch
-// sampled launch timing of the forward row pass
+// Sampled launch timing of two kernel classes: 0 = the plain forward row pass, 1 = the
+// fused base-conversion column pass (ModUp / ModDown conversion + first forward pass).
 struct ProfState {
   std::mutex mu;
   int every = 0;
-  int64_t seen = 0;
+  int64_t seen[2] = {0, 0};
   struct Rec {
     hipEvent_t a, b;
-    int64_t rows;
+    int64_t rows, src_rows;
   };
-  std::vector<Rec> recs;
+  std::vector<Rec> recs[2];
 };
 ProfState& prof() {
   static ProfState p;
   return p;
 }
+
+// Starts a sample of class cls on an eager (not captured) launch: returns the end event
+// to record after the launch, or null.
+struct ProfSample {
+  hipEvent_t a = nullptr, b = nullptr;
+  int cls = -1;
+  int64_t rows = 0, src_rows = 0;
+  void begin(int c, int64_t r, int64_t sr, hipStream_t s) {
+    ProfState& ps = prof();
+    if (ps.every <= 0) return;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return;
+    std::lock_guard<std::mutex> g(ps.mu);
+    if (ps.every <= 0 || (ps.seen[c]++ % ps.every) != 0) return;
+    if (hipEventCreate(&a) != hipSuccess) return;
+    if (hipEventCreate(&b) != hipSuccess) {
+      hipEventDestroy(a);
+      a = nullptr;
+      return;
+    }
+    cls = c, rows = r, src_rows = sr;
+    hipEventRecord(a, s);
+  }
+  void end(hipStream_t s) {
+    if (cls < 0) return;
+    hipEventRecord(b, s);
+    ProfState& ps = prof();
+    std::lock_guard<std::mutex> g(ps.mu);
+    ps.recs[cls].push_back({a, b, rows, src_rows});
+  }
+};
 
 int g_tune_epoch = 0;
 
@@ -619,29 +654,19 @@ void run_ntt(NttParams P, int64_t rows, bool inverse, const U2* twf, const U2* t
     P.tw = twf;
     P.twf = twff;
     P.tiles = tilesA;
-    if (P.X.csrc)
+    ProfSample sc;
+    if (P.X.csrc) {
+      sc.begin(1, rows, nab * P.X.ns, s);
       hipLaunchKernelGGL((k_ntt_cols<LA, true, true>), dim3((unsigned)(rows * tilesA)), dim3(256), 0, s, P);
-    else
+      sc.end(s);
+    } else {
       hipLaunchKernelGGL((k_ntt_cols<LA, true, false>), dim3((unsigned)(rows * tilesA)), dim3(256), 0, s, P);
+    }
     P.tiles = tilesB;
-    ProfState& ps = prof();
-    bool sample = false;
-    hipEvent_t ea = nullptr, eb = nullptr;
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (ps.every > 0 && !P.X.has_epi && hipStreamIsCapturing(s, &cap) == hipSuccess &&
-        cap == hipStreamCaptureStatusNone) {  // the plain forward row pass of eager launches only
-      std::lock_guard<std::mutex> g(ps.mu);
-      if (ps.every > 0 && (ps.seen++ % ps.every) == 0 && hipEventCreate(&ea) == hipSuccess &&
-          hipEventCreate(&eb) == hipSuccess)
-        sample = true;
-    }
-    if (sample) hipEventRecord(ea, s);
+    ProfSample sr;
+    if (!P.X.has_epi) sr.begin(0, rows, 0, s);
     launch_rows<LB, true>(P, blocksB, s);
-    if (sample) {
-      hipEventRecord(eb, s);
-      std::lock_guard<std::mutex> g(ps.mu);
-      ps.recs.push_back({ea, eb, rows});
-    }
+    sr.end(s);
   } else {
     P.tw = twi;
     P.twf = twif;
@@ -673,36 +698,42 @@ int rows_variant_get(int which) {
 extern "C" int heqg_prof_start(int every) {
   ProfState& ps = prof();
   std::lock_guard<std::mutex> g(ps.mu);
-  for (auto& r : ps.recs) {
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
+  for (auto& v : ps.recs) {
+    for (auto& r : v) {
+      hipEventDestroy(r.a);
+      hipEventDestroy(r.b);
+    }
+    v.clear();
   }
-  ps.recs.clear();
-  ps.seen = 0;
+  ps.seen[0] = ps.seen[1] = 0;
   ps.every = every > 0 ? every : 1;
   return 0;
 }
 
-extern "C" int heqg_prof_stop(double* avg_us, int64_t* launches, double* avg_rows) {
+extern "C" int heqg_prof_stop(int kernel, double* avg_us, int64_t* launches, double* avg_rows,
+                              double* avg_src_rows) {
+  if (kernel < 0 || kernel > 1) return -1;
   ProfState& ps = prof();
   std::lock_guard<std::mutex> g(ps.mu);
   ps.every = 0;
-  double tot = 0.0, rows = 0.0;
+  double tot = 0.0, rows = 0.0, srows = 0.0;
   int64_t n = 0;
   int rc = 0;
-  for (auto& r : ps.recs) {
+  for (auto& r : ps.recs[kernel]) {
     float ms = 0.f;
     if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) rc = -6;
     tot += ms;
     rows += (double)r.rows;
+    srows += (double)r.src_rows;
     ++n;
     hipEventDestroy(r.a);
     hipEventDestroy(r.b);
   }
-  ps.recs.clear();
+  ps.recs[kernel].clear();
   if (avg_us) *avg_us = n ? 1000.0 * tot / n : 0.0;
   if (launches) *launches = n;
   if (avg_rows) *avg_rows = n ? rows / n : 0.0;
+  if (avg_src_rows) *avg_src_rows = n ? srows / n : 0.0;
   return rc;
 }
 

@@ -19,7 +19,7 @@ _BASE = {
         sigmoid_degree=3, target_pos=None,
     ),
     "c3": dict(
-        name="c3-paper-scale", log2N=16, q_bits=[60] + [40] * 23, n_p=6, p_bits=60, dnum=4, log2_scale=40,
+        name="c3-paper-scale", log2N=16, q_bits=[60] + [40] * 23, n_p=7, p_bits=42, dnum=4, log2_scale=40,
         m=128, g=256, n_train=422108, n_features=200, n_valid=844217, seed=3, iters=10, batch_rows=1024,
         sigmoid_degree=3, target_pos=0.2, standardise=True,
     ),
