@@ -42,9 +42,12 @@ struct NttExtra {
   const uint64_t* in;
   int64_t in_sa, in_sb;
   uint64_t galois;
-  // inverse, last pass: multiply by scale[p] (pairs w, Shoup(w)) / scalef[p] instead of N^-1
+  // inverse, last pass: multiply by scale[p] (pairs w, Shoup(w)) / scalef[p] instead of N^-1;
+  // out_f64: rows of primes of at most FP_MAX_BITS bits are written as doubles (the
+  // canonical residue's value), for a base conversion that reads them (csrc_f64)
   const uint64_t* scale;
   const double* scalef;
+  int out_f64;
   // forward, first pass: the input of row (ia, ib, ii) is the base conversion
   //   sum_s csrc_s * hat[p][s]  mod q_p,  csrc_s = csrc + ia*csrc_sa + ib*csrc_sb + s*N
   // with hat pairs (w, Shoup(w)) at chat + 2*(p*cstride + s) and FP64 pairs
@@ -53,6 +56,7 @@ struct NttExtra {
   const uint64_t* csrc;
   int64_t csrc_sa, csrc_sb;
   int ns, cstride, csplit;
+  int csrc_f64;  // sources whose csplit bit is clear hold doubles (written with out_f64)
   const uint64_t* chat;
   const double* chatf;
   // forward, last pass: key-switch combine instead of a plain store

@@ -42,15 +42,25 @@ __device__ __forceinline__ double fred(double x, double q, double qi) {
   return __fma_rn(-__builtin_rint(x * qi), q, x);
 }
 
-// canonical residue of an exact integer x (|x| < 2^52) as uint64
-__device__ __forceinline__ uint64_t fcanon(double x, double q, double qi) {
+// a non-negative integer t < 2^53 held in a double, as uint64
+__device__ __forceinline__ uint64_t fint_to_u64(double t) {
 #pragma clang fp contract(off)
-  double t = fred(x, q, qi);
-  t = t < 0.0 ? t + q : t;
-  t = t >= q ? t - q : t;
   double hi = __builtin_floor(t * 2.3283064365386963e-10);   // 2^-32, exact
   double lo = __fma_rn(hi, -4294967296.0, t);
   return ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
+}
+
+// canonical residue in [0, q) of an exact integer x (|x| < 2^52), as a double
+__device__ __forceinline__ double fcanon_d(double x, double q, double qi) {
+#pragma clang fp contract(off)
+  double t = fred(x, q, qi);
+  t = t < 0.0 ? t + q : t;
+  return t >= q ? t - q : t;
+}
+
+// canonical residue of an exact integer x (|x| < 2^52) as uint64
+__device__ __forceinline__ uint64_t fcanon(double x, double q, double qi) {
+  return fint_to_u64(fcanon_d(x, q, qi));
 }
 
 __device__ __forceinline__ double u64_to_f(uint64_t v) {

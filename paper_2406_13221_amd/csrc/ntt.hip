@@ -223,15 +223,22 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
         for (int s = 0; s < P.X.ns; ++s) {
           const uint64_t* ys = cs + ((int64_t)s << P.logN) + c;
           const double h0 = h[2 * s], h1 = h[2 * s + 1];
+          // all 16 loads are issued before any use (left to itself the compiler waits on
+          // each load in turn)
+          uint64_t y[16];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) y[r] = ys[(int64_t)(kg + T * r) * N2];
+          __builtin_amdgcn_sched_barrier(0);
           if ((P.X.csplit >> s) & 1) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-              const uint64_t y = ys[(int64_t)(kg + T * r) * N2];
-              x[r] += fmulmod((double)(uint32_t)(y >> 32), h1, q, qi) + fmulmod((double)(uint32_t)y, h0, q, qi);
-            }
+            for (int r = 0; r < 16; ++r)
+              x[r] += fmulmod((double)(uint32_t)(y[r] >> 32), h1, q, qi) + fmulmod((double)(uint32_t)y[r], h0, q, qi);
+          } else if (P.X.csrc_f64) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) x[r] += fmulmod(as_f(y[r]), h0, q, qi);
           } else {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) x[r] += fmulmod(u64_to_f(ys[(int64_t)(kg + T * r) * N2]), h0, q, qi);
+            for (int r = 0; r < 16; ++r) x[r] += fmulmod(u64_to_f(y[r]), h0, q, qi);
           }
         }
 #pragma unroll
@@ -260,8 +267,14 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
       for (int r = 0; r < 16; ++r) x[r] = as_f(lds[(kg + T * r) * C + cl]);
       stages_strided<false>(x, tw, 1, bf);
       const double sd = P.X.scalef ? P.X.scalef[p] : pc.ninv_d;
+      if (P.X.out_f64) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) row[(int64_t)(kg + T * r) * N2 + c] = fcanon(fmulmod(x[r], sd, q, qi), q, qi);
+        for (int r = 0; r < 16; ++r)
+          row[(int64_t)(kg + T * r) * N2 + c] = as_u(fcanon_d(fmulmod(x[r], sd, q, qi), q, qi));
+      } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) row[(int64_t)(kg + T * r) * N2 + c] = fcanon(fmulmod(x[r], sd, q, qi), q, qi);
+      }
     }
   } else {
     const uint64_t q = pc.q, two_q = 2 * q;
@@ -280,9 +293,15 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
         for (int s = 0; s < P.X.ns; ++s) {
           const uint64_t* ys = cs + ((int64_t)s << P.logN) + c;
           const uint64_t w = h[2 * s], wsh = h[2 * s + 1];
+          const bool as_double = P.X.csrc_f64 && !((P.X.csplit >> s) & 1);
+          uint64_t y[16];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) y[r] = ys[(int64_t)(kg + T * r) * N2];
+          __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
-            const uint64_t v = x[r] + mul_shoup_lazy(ys[(int64_t)(kg + T * r) * N2], w, wsh, q);
+            const uint64_t yr = as_double ? fint_to_u64(as_f(y[r])) : y[r];
+            const uint64_t v = x[r] + mul_shoup_lazy(yr, w, wsh, q);
             x[r] = v >= two_q ? v - two_q : v;
           }
         }
@@ -414,8 +433,12 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
     } else {
       if (COAL) {
         if (FUSE) {
+          uint64_t v[16];
 #pragma unroll
-          for (int r = 0; r < 16; ++r) l[fl ^ swz(j + T * r)] = ld_in(inrow, pos0 + j + T * r, gal, P.logN);
+          for (int r = 0; r < 16; ++r) v[r] = ld_in(inrow, pos0 + j + T * r, gal, P.logN);
+          __builtin_amdgcn_sched_barrier(0);  // every gather load in flight before the first use
+#pragma unroll
+          for (int r = 0; r < 16; ++r) l[fl ^ swz(j + T * r)] = v[r];
         } else {
 #pragma unroll
           for (int r = 0; r < 16; ++r) l[fl ^ swz(j + T * r)] = src[j + T * r];
@@ -425,8 +448,12 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
         for (int r = 0; r < 16; ++r) x[r] = u64_to_f(l[fl ^ swz(16 * j + r)]);
         __syncthreads();
       } else if (FUSE) {
+        uint64_t v[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) x[r] = u64_to_f(ld_in(inrow, pos0 + 16 * j + r, gal, P.logN));
+        for (int r = 0; r < 16; ++r) v[r] = ld_in(inrow, pos0 + 16 * j + r, gal, P.logN);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[r] = u64_to_f(v[r]);
       } else {
         const U2* s2 = reinterpret_cast<const U2*>(src + 16 * j);
 #pragma unroll
@@ -492,8 +519,12 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
     } else {
       if (COAL) {
         if (FUSE) {
+          uint64_t v[16];
 #pragma unroll
-          for (int r = 0; r < 16; ++r) l[fl ^ swz(j + T * r)] = ld_in(inrow, pos0 + j + T * r, gal, P.logN);
+          for (int r = 0; r < 16; ++r) v[r] = ld_in(inrow, pos0 + j + T * r, gal, P.logN);
+          __builtin_amdgcn_sched_barrier(0);  // every gather load in flight before the first use
+#pragma unroll
+          for (int r = 0; r < 16; ++r) l[fl ^ swz(j + T * r)] = v[r];
         } else {
 #pragma unroll
           for (int r = 0; r < 16; ++r) l[fl ^ swz(j + T * r)] = src[j + T * r];
@@ -505,6 +536,7 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
       } else if (FUSE) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) x[r] = ld_in(inrow, pos0 + 16 * j + r, gal, P.logN);
+        __builtin_amdgcn_sched_barrier(0);
       } else {
         const U2* s2 = reinterpret_cast<const U2*>(src + 16 * j);
 #pragma unroll

@@ -182,6 +182,7 @@ void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, 
     x.galois = galois;
     x.scale = scale;
     x.scalef = scalef;
+    x.out_f64 = 1;
     launch_ntt_ex(c->t, g.logN, rows_q(ycoef, count, (int64_t)nl * N, 1, 0, nl, 0), true, x, s);
   }
   // 2. ModUp per digit fused into the forward NTT of its target rows
@@ -198,6 +199,7 @@ void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, 
     x.cstride = alpha;
     x.chat = c->t.modup + 2 * (size_t)((level * g.dnum + j) * g.mu_stride) + 2 * alpha;
     x.chatf = c->t.modup_f + 2 * (size_t)((level * g.dnum + j) * g.nqp) * alpha;
+    x.csrc_f64 = 1;
     for (int k = 0; k < sz; ++k) x.csplit |= (c->primes[lo + k] >> FP_MAX_BITS ? 1 : 0) << k;
     launch_ntt_ex(c->t, g.logN, rows(ext + (size_t)j * nx * N, count, ext_cs, 1, 0, (int)tgt.size(), tgt.data()),
                   false, x, s);
@@ -209,6 +211,7 @@ void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, 
     NttExtra x{};
     x.scale = scale;
     x.scalef = scalef;
+    x.out_f64 = 1;
     launch_ntt_ex(c->t, g.logN, rows_q(acc + (size_t)nl * N, count, (int64_t)2 * nx * N, 2, (int64_t)nx * N, np, nq),
                   true, x, s);
   }
@@ -221,6 +224,7 @@ void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, 
     x.cstride = np;
     x.chat = c->t.moddown + 2 * np;
     x.chatf = c->t.moddown_f;
+    x.csrc_f64 = 1;
     for (int k = 0; k < np; ++k) x.csplit |= (c->primes[nq + k] >> FP_MAX_BITS ? 1 : 0) << k;
     x.has_epi = 1;
     KsEpi& e = x.epi;

@@ -11,7 +11,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libheqg.so")
+# HEQG_LIB selects another build of the same library (side-by-side comparisons)
+LIB_PATH = os.environ.get("HEQG_LIB") or os.path.join(HERE, "libheqg.so")
 
 OK, ERR_ARG, ERR_LEVEL, ERR_SCALE, ERR_KEY, ERR_OVERFLOW, ERR_DEVICE, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 _NAMES = {-1: "ARG", -2: "LEVEL", -3: "SCALE", -4: "KEY", -5: "OVERFLOW", -6: "DEVICE", -7: "UNSUPPORTED"}
@@ -59,8 +60,8 @@ def lib():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError("libheqg.so is not built (run __graft_entry__.build() or python -m "
-                           "paper_2406_13221_amd.build); there is no non-HIP fallback")
+        raise RuntimeError("%s is not built (run __graft_entry__.build() or python -m "
+                           "paper_2406_13221_amd.build); there is no non-HIP fallback" % LIB_PATH)
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, u64, sz, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_double
     P = ctypes.POINTER
