@@ -42,20 +42,23 @@ __device__ __forceinline__ double fred(double x, double q, double qi) {
   return __fma_rn(-__builtin_rint(x * qi), q, x);
 }
 
-// a non-negative integer t < 2^53 held in a double, as uint64
+// For an integer 0 <= v < 2^52 the double 2^52 + v is exact and its 52 mantissa bits are v,
+// so integer <-> double conversions of residues need no convert instructions.
+constexpr uint64_t kTwo52Bits = 0x4330000000000000ull;  // bit pattern of 2^52
+constexpr double kTwo52 = 4503599627370496.0;
+
+// a non-negative integer t < 2^52 held in a double, as uint64
 __device__ __forceinline__ uint64_t fint_to_u64(double t) {
 #pragma clang fp contract(off)
-  double hi = __builtin_floor(t * 2.3283064365386963e-10);   // 2^-32, exact
-  double lo = __fma_rn(hi, -4294967296.0, t);
-  return ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
+  return (uint64_t)__double_as_longlong(t + kTwo52) & 0x000FFFFFFFFFFFFFull;
 }
 
-// canonical residue in [0, q) of an exact integer x (|x| < 2^52), as a double
+// canonical residue in [0, q) of an exact integer x (|x| < 2^52), as a double: fred leaves
+// |t| <= q/2 + 1, so one conditional +q suffices
 __device__ __forceinline__ double fcanon_d(double x, double q, double qi) {
 #pragma clang fp contract(off)
   double t = fred(x, q, qi);
-  t = t < 0.0 ? t + q : t;
-  return t >= q ? t - q : t;
+  return t < 0.0 ? t + q : t;
 }
 
 // canonical residue of an exact integer x (|x| < 2^52) as uint64
@@ -63,9 +66,10 @@ __device__ __forceinline__ uint64_t fcanon(double x, double q, double qi) {
   return fint_to_u64(fcanon_d(x, q, qi));
 }
 
+// an integer 0 <= v < 2^52 (a residue of a prime of at most FP_MAX_BITS bits) as a double
 __device__ __forceinline__ double u64_to_f(uint64_t v) {
 #pragma clang fp contract(off)
-  return __fma_rn((double)(uint32_t)(v >> 32), 4294967296.0, (double)(uint32_t)v);
+  return __longlong_as_double((long long)(v | kTwo52Bits)) - kTwo52;
 }
 
 __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }

@@ -75,9 +75,12 @@ __device__ __forceinline__ void ct_f(double& X, double& Y, double w, double q, d
   Y = x - t;
 }
 
+// Lazy: the sum is not reduced.  Magnitudes at most double per stage, so the callers reduce
+// every residue (fred) after each group of at most 4 stages: from |x| <= q/2 + 1 the values
+// stay below 16q < 2^46, inside fmulmod's exactness bound.
 __device__ __forceinline__ void gs_f(double& X, double& Y, double w, double q, double qi) {
 #pragma clang fp contract(off)
-  double s = fred(X + Y, q, qi);
+  double s = X + Y;
   double d = X - Y;
   X = s;
   Y = fmulmod(d, w, q, qi);
@@ -261,7 +264,7 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
       for (int r = 0; r < 16; ++r) x[r] = as_f(row[(int64_t)(16 * kg + r) * N2 + c]);
       stages_contig<LOGS, false>(x, tw, 1, kg, bf);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) lds[(16 * kg + r) * C + cl] = as_u(x[r]);
+      for (int r = 0; r < 16; ++r) lds[(16 * kg + r) * C + cl] = as_u(fred(x[r], q, qi));
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < 16; ++r) x[r] = as_f(lds[(kg + T * r) * C + cl]);
@@ -465,13 +468,13 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
       }
       stages_contig<LOGS, false>(x, tw, base, j, bf);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) l[fl ^ swz(16 * j + r)] = as_u(x[r]);
+      for (int r = 0; r < 16; ++r) l[fl ^ swz(16 * j + r)] = as_u(fred(x[r], q, qi));
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < 16; ++r) x[r] = as_f(l[fl ^ swz(j + T * r)]);
       stages_strided<false>(x, tw, base, bf);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) src[j + T * r] = as_u(x[r]);
+      for (int r = 0; r < 16; ++r) src[j + T * r] = as_u(fred(x[r], q, qi));
     }
   } else {
     const uint64_t q = pc.q, two_q = 2 * q;
