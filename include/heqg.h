@@ -274,6 +274,8 @@ int heqg_mul_const(heqg_ctx* ctx, const heqg_ct_batch* in, double c, double targ
 /*
  * In-place forward (inverse = 0) or inverse negacyclic NTT of n_rows rows of
  * N residues at dev_rows + r*N; row r uses prime index first_prime + (r mod period).
+ * Inputs must be residues in [0, q) of their row's prime; outputs are in [0, q).
+ * n_rows = 0 is a no-op; n_rows must be a multiple of period (HEQG_ERR_ARG).
  */
 int heqg_ntt(heqg_ctx* ctx, uint64_t* dev_rows, int64_t n_rows, int first_prime, int period, int inverse,
              hipStream_t s);

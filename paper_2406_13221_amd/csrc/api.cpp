@@ -377,11 +377,13 @@ extern "C" int heqg_rotate(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch*
 
 extern "C" int heqg_rescale(heqg_ctx* c, const heqg_ct_batch* in, const heqg_ct_batch* out, void* ws,
                             size_t ws_bytes, hipStream_t s) {
-  if (!c || !batch_ok(c, in, 0, "rescale") || !batch_ok(c, out, 0, "rescale")) return HEQG_ERR_ARG;
+  // the input's level is checked first: at level 0 there is no valid output shape at all
+  if (!c || !batch_ok(c, in, 0, "rescale")) return HEQG_ERR_ARG;
   if (in->level < 1) {
     set_err("rescale: level exhausted");
     return HEQG_ERR_LEVEL;
   }
+  if (!batch_ok(c, out, 0, "rescale")) return HEQG_ERR_ARG;
   if (out->level != in->level - 1 || out->count != in->count || out->n_poly != in->n_poly) {
     set_err("rescale: output shape mismatch");
     return HEQG_ERR_ARG;
@@ -441,11 +443,13 @@ extern "C" int heqg_add_pt(heqg_ctx* c, const heqg_ct_batch* in, const uint64_t*
 
 extern "C" int heqg_mul_const(heqg_ctx* c, const heqg_ct_batch* in, double cst, double target,
                               const heqg_ct_batch* out, void* ws, size_t ws_bytes, hipStream_t s) {
-  if (!c || !batch_ok(c, in, 0, "mul_const") || !batch_ok(c, out, 0, "mul_const")) return HEQG_ERR_ARG;
+  // the input's level is checked first: at level 0 there is no valid output shape at all
+  if (!c || !batch_ok(c, in, 0, "mul_const")) return HEQG_ERR_ARG;
   if (in->level < 1) {
     set_err("mul_const: level exhausted");
     return HEQG_ERR_LEVEL;
   }
+  if (!batch_ok(c, out, 0, "mul_const")) return HEQG_ERR_ARG;
   if (out->level != in->level - 1 || out->n_poly != in->n_poly || out->count != in->count) {
     set_err("mul_const: output shape mismatch");
     return HEQG_ERR_ARG;
