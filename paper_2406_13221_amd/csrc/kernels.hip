@@ -378,86 +378,112 @@ __global__ void __launch_bounds__(EW_THREADS) k_modup(const PrimeConst* pc, cons
 
 // acc[ct][part][x] = sum_j v_j[x] * key_j[part][prime(x)], x over Q rows 0..l then P rows;
 // v_j[x] = d[x] for x in digit j, else the ModUp row of digit j.  One thread owns two
-// coefficients of one extended row of one ciphertext.  The grid is XCD-aware:
-// workgroup b runs on XCD b mod 8, and the `count` workgroups that share one
-// (row, chunk) tile of the key are given consecutive slots on the same XCD, so the
-// key tile is fetched from HBM once per launch and then served by that XCD's L2.
-// With galois != 1, d is the input before the automorphism X -> X^galois and the
-// in-digit rows are gathered through it.
+// coefficients of one extended row of KS_CTP ciphertexts: the key values are loaded once
+// and used for each of them.  The grid is XCD-aware: workgroup b runs on XCD b mod 8, and
+// the workgroups that share one (row, chunk) tile of the key are given consecutive slots
+// on the same XCD, so the key tile is fetched from HBM once per launch and then served by
+// that XCD's L2.  With galois != 1, d is the input before the automorphism X -> X^galois
+// and the in-digit rows are gathered through it.
 constexpr int KS_MAX_DIGITS = 8;
+constexpr int KS_CTP = 2;
+template <int ND>  // digits at this level
 __global__ void __launch_bounds__(EW_THREADS) k_ks_inner(const PrimeConst* pc, CtV d, const uint64_t* ext, int64_t ext_cs,
                                                           int64_t ext_ds, const uint64_t* key, uint64_t* acc, int logN,
                                                           int level, int nq, int np, int alpha, int64_t count,
                                                           uint64_t galois) {
   const int chunks = (1 << logN) / EW_CHUNK;
   const int nl = level + 1, nx = nl + np, nqp = nq + np;
+  const int64_t ngrp = (count + KS_CTP - 1) / KS_CTP;
   const int64_t bid = blockIdx.x;
   const int64_t rest = bid >> 3;
-  const int64_t ct = rest % count;
-  const int64_t tile = (rest / count) * 8 + (bid & 7);
+  const int64_t grp = rest % ngrp;
+  const int64_t tile = (rest / ngrp) * 8 + (bid & 7);
   const int ch = (int)(tile % chunks);
   const int x = (int)(tile / chunks);
   const int c = ch * EW_CHUNK + threadIdx.x * 2;
   const int gp = x < nl ? x : nq + (x - nl);
   const PrimeConst P = pc[gp];
-  const int nd = (nl + alpha - 1) / alpha;
-  U2 v[KS_MAX_DIGITS], kb[KS_MAX_DIGITS], ka[KS_MAX_DIGITS];
+  U2 kb[ND], ka[ND];
 #pragma unroll
-  for (int j = 0; j < KS_MAX_DIGITS; ++j) {
-    if (j < nd) {
+  for (int j = 0; j < ND; ++j)
+    {
       const uint64_t* kp = key + (((int64_t)j * 2 * nqp + gp) << logN) + c;
       kb[j] = ld2(kp);
       ka[j] = ld2(kp + ((int64_t)nqp << logN));
-      int lo = j * alpha, hi = min(lo + alpha, nl);
-      if (x >= lo && x < hi) {
-        const uint64_t* row = d.d + ct * d.cs + ((int64_t)x << logN);
-        if (galois != 1) {
-          const uint32_t mask2n = (2u << logN) - 1;
-          uint32_t e0 = (uint32_t)(((uint64_t)(2 * brv_n(c, logN) + 1) * galois) & mask2n);
-          uint32_t e1 = (uint32_t)(((uint64_t)(2 * brv_n(c + 1, logN) + 1) * galois) & mask2n);
-          v[j].a = row[brv_n((e0 - 1) >> 1, logN)];
-          v[j].b = row[brv_n((e1 - 1) >> 1, logN)];
+    }
+  const int64_t ct0 = grp * KS_CTP;
+  const int nct = (int)min((int64_t)KS_CTP, count - ct0);
+  U2 v[KS_CTP][ND];
+#pragma unroll
+  for (int u = 0; u < KS_CTP; ++u) {
+    if (u >= nct) break;
+    const int64_t ct = ct0 + u;
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+      {
+        int lo = j * alpha, hi = min(lo + alpha, nl);
+        if (x >= lo && x < hi) {
+          const uint64_t* row = d.d + ct * d.cs + ((int64_t)x << logN);
+          if (galois != 1) {
+            v[u][j].a = row[galois_src(c, galois, logN)];
+            v[u][j].b = row[galois_src(c + 1, galois, logN)];
+          } else {
+            v[u][j] = ld2(row + c);
+          }
         } else {
-          v[j] = ld2(row + c);
+          int e = x < lo ? x : x - (hi - lo);
+          v[u][j] = ld2(ext + ct * ext_cs + j * ext_ds + ((int64_t)e << logN) + c);
         }
-      } else {
-        int e = x < lo ? x : x - (hi - lo);
-        v[j] = ld2(ext + ct * ext_cs + j * ext_ds + ((int64_t)e << logN) + c);
       }
     }
   }
-  uint64_t* o = acc + ct * ((int64_t)(2 * nx) << logN) + ((int64_t)x << logN) + c;
   if (P.k <= FP_MAX_BITS) {
 #pragma clang fp contract(off)
     const double q = P.qd, qi = P.qinv;
-    double s0a = 0, s0b = 0, s1a = 0, s1b = 0;
+    double kbf[ND][2], kaf[ND][2];
 #pragma unroll
-    for (int j = 0; j < KS_MAX_DIGITS; ++j)
-      if (j < nd) {
-        double va = u64_to_f(v[j].a), vb = u64_to_f(v[j].b);
-        s0a += fmulmod(va, u64_to_f(kb[j].a), q, qi);
-        s0b += fmulmod(vb, u64_to_f(kb[j].b), q, qi);
-        s1a += fmulmod(va, u64_to_f(ka[j].a), q, qi);
-        s1b += fmulmod(vb, u64_to_f(ka[j].b), q, qi);
+    for (int j = 0; j < ND; ++j)
+      {
+        kbf[j][0] = u64_to_f(kb[j].a), kbf[j][1] = u64_to_f(kb[j].b);
+        kaf[j][0] = u64_to_f(ka[j].a), kaf[j][1] = u64_to_f(ka[j].b);
       }
-    st2(o, fcanon(s0a, q, qi), fcanon(s0b, q, qi));
-    st2(o + ((int64_t)nx << logN), fcanon(s1a, q, qi), fcanon(s1b, q, qi));
+#pragma unroll
+    for (int u = 0; u < KS_CTP; ++u) {
+      if (u >= nct) break;
+      double s0a = 0, s0b = 0, s1a = 0, s1b = 0;
+#pragma unroll
+      for (int j = 0; j < ND; ++j)
+        {
+          double va = u64_to_f(v[u][j].a), vb = u64_to_f(v[u][j].b);
+          s0a += fmulmod(va, kbf[j][0], q, qi);
+          s0b += fmulmod(vb, kbf[j][1], q, qi);
+          s1a += fmulmod(va, kaf[j][0], q, qi);
+          s1b += fmulmod(vb, kaf[j][1], q, qi);
+        }
+      uint64_t* o = acc + (ct0 + u) * ((int64_t)(2 * nx) << logN) + ((int64_t)x << logN) + c;
+      st2(o, fcanon(s0a, q, qi), fcanon(s0b, q, qi));
+      st2(o + ((int64_t)nx << logN), fcanon(s1a, q, qi), fcanon(s1b, q, qi));
+    }
     return;
   }
-  uint64_t s0a = 0, s0b = 0, s1a = 0, s1b = 0;
 #pragma unroll
-  for (int j = 0; j < KS_MAX_DIGITS; ++j)
-    if (j < nd) {
-      s0a = addmod(s0a, mulmod(v[j].a, kb[j].a, P), P.q);
-      s0b = addmod(s0b, mulmod(v[j].b, kb[j].b, P), P.q);
-      s1a = addmod(s1a, mulmod(v[j].a, ka[j].a, P), P.q);
-      s1b = addmod(s1b, mulmod(v[j].b, ka[j].b, P), P.q);
-    }
-  st2(o, s0a, s0b);
-  st2(o + ((int64_t)nx << logN), s1a, s1b);
+  for (int u = 0; u < KS_CTP; ++u) {
+    if (u >= nct) break;
+    uint64_t s0a = 0, s0b = 0, s1a = 0, s1b = 0;
+#pragma unroll
+    for (int j = 0; j < ND; ++j)
+      {
+        s0a = addmod(s0a, mulmod(v[u][j].a, kb[j].a, P), P.q);
+        s0b = addmod(s0b, mulmod(v[u][j].b, kb[j].b, P), P.q);
+        s1a = addmod(s1a, mulmod(v[u][j].a, ka[j].a, P), P.q);
+        s1b = addmod(s1b, mulmod(v[u][j].b, ka[j].b, P), P.q);
+      }
+    uint64_t* o = acc + (ct0 + u) * ((int64_t)(2 * nx) << logN) + ((int64_t)x << logN) + c;
+    st2(o, s0a, s0b);
+    st2(o + ((int64_t)nx << logN), s1a, s1b);
+  }
 }
 
-// conv[ct][part][i] = sum_k [x_k * (P/p_k)^-1]_{p_k} * (P/p_k) mod q_i  (x = P rows of acc, coefficient form)
 __global__ void __launch_bounds__(EW_THREADS) k_moddown_conv(const PrimeConst* pc, const uint64_t* md,
                                                               const double* mdf, const uint64_t* acc, uint64_t* conv,
                                                               int logN, int level, int nq, int np) {
@@ -889,11 +915,19 @@ void k_modup_launch(const Geo& g, const DevTables& t, const uint64_t* dcoef, int
 void k_ks_inner_launch(const Geo& g, const DevTables& t, CtV d, const uint64_t* ext, int64_t ext_cs, int64_t ext_ds,
                        const uint64_t* key, uint64_t* acc, int64_t count, int level, uint64_t galois, hipStream_t s) {
   int nx = level + 1 + g.n_p;
-  // tiles (row x chunk) are a multiple of 8 because N/512 is
-  int64_t n = count * (int64_t)nx * CHUNKS(g);
-  if (n)
-    LAUNCH(k_ks_inner, n, s, t.pc, d, ext, ext_cs, ext_ds, key, acc, g.logN, level, g.n_q, g.n_p, g.alpha, count,
-           galois);
+  // tiles (row x chunk) are a multiple of 8 because N/512 is; KS_CTP ciphertexts per workgroup
+  int64_t n = (count + KS_CTP - 1) / KS_CTP * (int64_t)nx * CHUNKS(g);
+  const int nd = (level + g.alpha) / g.alpha;
+  if (!n) return;
+  switch (nd) {
+#define HEQG_KSI(D)                                                                                              \
+  case D:                                                                                                        \
+    LAUNCH(k_ks_inner<D>, n, s, t.pc, d, ext, ext_cs, ext_ds, key, acc, g.logN, level, g.n_q, g.n_p, g.alpha, count, \
+           galois);                                                                                              \
+    break;
+    HEQG_KSI(1) HEQG_KSI(2) HEQG_KSI(3) HEQG_KSI(4) HEQG_KSI(5) HEQG_KSI(6) HEQG_KSI(7) HEQG_KSI(8)
+#undef HEQG_KSI
+  }
 }
 void k_moddown_conv_launch(const Geo& g, const DevTables& t, const uint64_t* acc, uint64_t* conv, int64_t count,
                            int level, hipStream_t s) {
