@@ -143,6 +143,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (NTT split/variants, chunk size)")
     ap.add_argument("--graph-steps", type=int, default=1, help="timed graph-replayed full-batch iterations")
     ap.add_argument("--mini-steps", type=int, default=10, help="timed mini-batch steps (eager and graph)")
+    ap.add_argument("--learned-steps", type=int, default=1,
+                    help="timed iterations of the learned-sigmoid form (degree-5 polynomial, depth 3)")
     ap.add_argument("--mode", default="train", choices=["train", "ntt"],
                     help="ntt: only the batched forward NTT (768 limbs) and a 1 GiB device copy, for counters")
     ap.add_argument("--copy-probe", action="store_true",
@@ -197,6 +199,7 @@ def main():
         ev[k][0].record()
         run.step(refresh=False)
         ev[k][1].record()
+        depth_g8 = run.L - run.W.level
         run.refresh()
         ev[k][2].record()
     torch.cuda.synchronize()
@@ -222,6 +225,29 @@ def main():
         run.graph, run.stream = False, None
         run.ctx.graph_clear()
         log("graph-replayed iteration: %.3f s" % graph_s)
+
+    # the learned-sigmoid form: an odd degree-5 polynomial (here the least-squares fit of sigma on a
+    # uniform grid over [-8, 8]; the time does not depend on the coefficients) costs one more level
+    learned = None
+    if args.learned_steps > 0:
+        import numpy as np
+        grid = np.linspace(-8.0, 8.0, 4001)
+        basis = np.stack([grid ** k for k in (1, 3, 5)], axis=1)
+        c5 = np.linalg.lstsq(basis, 1.0 / (1.0 + np.exp(-grid)) - 0.5, rcond=None)[0]
+        g8 = dict(run.coeffs)
+        run.set_sigmoid({1: float(c5[0]), 3: float(c5[1]), 5: float(c5[2])})
+        run.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.learned_steps):
+            run.step(refresh=False)
+            depth = run.L - run.W.level
+            run.refresh()
+        torch.cuda.synchronize()
+        learned = {"degree": 5, "s_per_iter": round((time.perf_counter() - t0) / args.learned_steps, 4),
+                   "levels_per_iteration": depth, "levels_per_iteration_g8": depth_g8}
+        run.set_sigmoid(g8)
+        log("learned degree-5 iteration: %.3f s, %d levels (g8: %d)" % (learned["s_per_iter"], depth, depth_g8))
 
     # mini-batch steps (Algorithm 1, 1,024 rows = 8 blocks per batch), eager and graph-replayed
     mini = None
@@ -329,6 +355,7 @@ def main():
         "iteration_roofline": it_roof,
         "graph_s_per_iter": None if graph_s is None else round(graph_s, 4),
         "minibatch": mini,
+        "learned_sigmoid": learned,
         "tuning": tuning,
     }
     if args.copy_probe:

@@ -102,3 +102,32 @@ def test_learned_degree5_gain_over_g8_encrypted(torch_cuda, c2_run):
         out[name] = (trainer.loglik(d["Xv"], d["yv"], w), trainer.auroc(trainer.xhat(d["Xv"], g) @ w, d["yv"]))
     assert out["learned"][0] > out["g8"][0] + 1e-3
     assert out["learned"][1] >= out["g8"][1] - 1e-4
+
+
+@pytest.fixture(scope="module")
+def c3_margins():
+    cfg = synth.get_config("c5")
+    d = synth.make_dataset(cfg)
+    r = trainer.train(d["X"], d["y"], cfg["g"], 10, exact_sigmoid=True, log_margins=True)
+    return cfg, d, np.concatenate(r["margins"]).astype(np.float32)
+
+
+@pytest.mark.parametrize("deg", [5, 7])
+def test_paper_scale_fit_and_encrypted_iteration(torch_cuda, c3_margins, deg):
+    # the learned form at the paper's size: 4.2M trajectory margins, GPU fit at the least-squares
+    # optimum, one encrypted full-batch iteration with it tracking FP64 and one level deeper than g8
+    from paper_2406_13221_amd import sigmoid_fit
+    from paper_2406_13221_amd.train import EncryptedQGNAG
+    cfg, d, m = c3_margins
+    assert m.size == 10 * 422108
+    mo = m.astype(np.float64)
+    c, _ = sigmoid_fit.fit(m, deg)
+    assert osf.loss(c, mo, deg) <= osf.loss(osf.normal_equations(mo, deg), mo, deg) * 1.001
+    coeffs = sigmoid_fit.power_coeffs(c)
+    run = EncryptedQGNAG(cfg, d["X"], d["y"], coeffs=coeffs, batch=24)
+    top = run.L
+    run.step(refresh=False)
+    assert run.W.level == top - 6            # g8: top - 5 (the sigmoid takes depth 3 instead of 2)
+    w = run.weights(cfg["g"])
+    ref = trainer.train(d["X"], d["y"], cfg["g"], 1, coeffs=coeffs)
+    assert np.abs(w - ref["history"][0]["W"]).max() < 1e-3
