@@ -108,8 +108,9 @@ __device__ __forceinline__ uint32_t brv_n(uint32_t x, int logN) { return __brev(
 
 // Slot k of an NTT-form polynomial holds the evaluation at psi^(2 brv(k) + 1).  After
 // X -> X^galois, slot k holds what slot galois_src(k) held before.
+// The exponent is needed mod 2N = 2^(logN+1), which divides 2^32: 32-bit products suffice.
 __device__ __forceinline__ uint32_t galois_src(uint32_t k, uint64_t galois, int logN) {
-  const uint32_t e = (uint32_t)(((uint64_t)(2 * brv_n(k, logN) + 1) * galois) & ((2u << logN) - 1));
+  const uint32_t e = ((2u * brv_n(k, logN) + 1u) * (uint32_t)galois) & ((2u << logN) - 1);
   return brv_n((e - 1) >> 1, logN);
 }
 __device__ __forceinline__ uint64_t submod(uint64_t a, uint64_t b, uint64_t q) { return a >= b ? a - b : a + q - b; }

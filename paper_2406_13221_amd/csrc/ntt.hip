@@ -162,9 +162,10 @@ __device__ __forceinline__ uint64_t ld_in(const uint64_t* in, int64_t pos, uint6
 
 // Key-switch combine of the 16 output residues y[r] of row (ab, ii) at positions
 // pos0 + st*r.  All loads of a group of 8 are issued before any store, so the stores
-// (which the compiler must assume may alias the inputs) do not serialise them.
-__device__ __forceinline__ void ks_epi16(const KsEpi& E, int64_t ab, int ii, int p, uint64_t q, int logN, int64_t pos0,
-                                         int st, const uint64_t (&y)[16]) {
+// (which the compiler must assume may alias the inputs) do not serialise them.  (An FP64
+// form of this combine measured slower than the 64-bit integer one.)
+__device__ __forceinline__ void ks_epi16(const KsEpi& E, int64_t ab, int ii, int p, const PrimeConst& pc, int logN,
+                                         int64_t pos0, int st, const uint64_t (&y)[16]) {
   const int64_t ct = ab >> 1;
   const int part = (int)(ab & 1);
   const int64_t lo = (int64_t)ii << logN;
@@ -175,7 +176,7 @@ __device__ __forceinline__ void ks_epi16(const KsEpi& E, int64_t ab, int ii, int
   const bool gather = part == 0 && E.galois > 1;
   const uint64_t* ad = E.addend.d + ct * E.addend.cs + part * E.addend.ps + lo;
   uint64_t* out = E.out.d + ct * E.out.cs + part * E.out.ps + lo;
-  const uint64_t w = E.pinv[2 * p], wsh = E.pinv[2 * p + 1];
+  const uint64_t q = pc.q, w = E.pinv[2 * p], wsh = E.pinv[2 * p + 1];
 #pragma unroll
   for (int h = 0; h < 16; h += 8) {
     uint64_t a[8], z[8], v[8];
@@ -421,13 +422,13 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
           uint64_t v[16];
 #pragma unroll
           for (int r = 0; r < 16; ++r) v[r] = l[fl ^ swz(j + T * r)];
-          ks_epi16(P.X.epi, ab, ii, p, pc.q, P.logN, pos0 + j, T, v);
+          ks_epi16(P.X.epi, ab, ii, p, pc, P.logN, pos0 + j, T, v);
         } else {
 #pragma unroll
           for (int r = 0; r < 16; ++r) src[j + T * r] = l[fl ^ swz(j + T * r)];
         }
       } else if (FUSE) {
-        ks_epi16(P.X.epi, ab, ii, p, pc.q, P.logN, pos0 + 16 * j, 1, y);
+        ks_epi16(P.X.epi, ab, ii, p, pc, P.logN, pos0 + 16 * j, 1, y);
       } else {
         U2* dst = reinterpret_cast<U2*>(src + 16 * j);
 #pragma unroll
@@ -507,13 +508,13 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
           uint64_t v[16];
 #pragma unroll
           for (int r = 0; r < 16; ++r) v[r] = l[fl ^ swz(j + T * r)];
-          ks_epi16(P.X.epi, ab, ii, p, q, P.logN, pos0 + j, T, v);
+          ks_epi16(P.X.epi, ab, ii, p, pc, P.logN, pos0 + j, T, v);
         } else {
 #pragma unroll
           for (int r = 0; r < 16; ++r) src[j + T * r] = l[fl ^ swz(j + T * r)];
         }
       } else if (FUSE) {
-        ks_epi16(P.X.epi, ab, ii, p, q, P.logN, pos0 + 16 * j, 1, x);
+        ks_epi16(P.X.epi, ab, ii, p, pc, P.logN, pos0 + 16 * j, 1, x);
       } else {
         U2* dst = reinterpret_cast<U2*>(src + 16 * j);
 #pragma unroll
