@@ -122,17 +122,9 @@ void k_rescale_spread_launch(const Geo& g, const DevTables& t, const uint64_t* l
                              int level, hipStream_t s);
 void k_rescale_combine_launch(const Geo& g, const DevTables& t, CtV in, const uint64_t* spread, CtV out, int64_t count,
                               int n_poly, int level, hipStream_t s);
-void k_modup_launch(const Geo& g, const DevTables& t, const uint64_t* dcoef, int64_t count, int level, int digit,
-                    uint64_t* ext, int64_t ext_cs, hipStream_t s);
 void k_ks_inner_launch(const Geo& g, const DevTables& t, CtV d, const uint64_t* ext, int64_t ext_cs, int64_t ext_ds,
                        const uint64_t* key, uint64_t* acc, int64_t count, int level, uint64_t galois, hipStream_t s);
-void k_moddown_conv_launch(const Geo& g, const DevTables& t, const uint64_t* acc, uint64_t* conv, int64_t count,
-                           int level, hipStream_t s);
 // out = [addend +] base + KS result; with galois != 1 base0 is gathered through X -> X^galois
-void k_ks_combine_launch(const Geo& g, const DevTables& t, const uint64_t* acc, const uint64_t* conv, CtV base0,
-                         CtV base1, bool has_base1, CtV out, int64_t count, int level, uint64_t galois,
-                         const CtV* addend, hipStream_t s);
-
 // sampling / encryption
 enum { PUR_SK = 1, PUR_PK_A = 2, PUR_PK_E = 3, PUR_KSK_A = 4, PUR_KSK_E = 5, PUR_ENC_V = 6, PUR_ENC_E0 = 7, PUR_ENC_E1 = 8 };
 void k_sample_small_launch(uint64_t seed, uint64_t purpose, uint64_t obj_first, int64_t count, int N, int kind,

@@ -1,4 +1,5 @@
-// Elementwise, base-conversion, key-switching and sampling kernels (gfx950).
+// Elementwise, key inner-product, rescale, automorphism, sampling and encryption kernels
+// (gfx950).  The base conversions of key switching live in ntt.hip, fused into NTT passes.
 //
 // All data are limb-major uint64 rows of N residues.  Elementwise kernels
 // give each thread two adjacent coefficients (one 16-byte access per
@@ -282,303 +283,6 @@ __global__ void __launch_bounds__(EW_THREADS) k_rescale_spread(const PrimeConst*
     st2(spread + ((r * level + i) << logN) + c, v0, v1);
   }
 }
-
-// out_i = (in_i - spread_i) * q_l^-1 mod q_i for i < level
-__global__ void __launch_bounds__(EW_THREADS) k_rescale_combine(const PrimeConst* pc, const uint64_t* rs, CtV in,
-                                                                 const uint64_t* spread, CtV out, int logN, int level,
-                                                                 int n_poly, int nq) {
-  const int chunks = (1 << logN) / EW_CHUNK;
-  int64_t bid = blockIdx.x;
-  int ch = (int)(bid % chunks);
-  int64_t row = bid / chunks;
-  int i = (int)(row % level);
-  int64_t r2 = row / level;  // = ct * n_poly + p
-  int p = (int)(r2 % n_poly);
-  int64_t ct = r2 / n_poly;
-  int64_t off = ((int64_t)i << logN) + ch * EW_CHUNK + threadIdx.x * 2;
-  const uint64_t q = pc[i].q;
-  const uint64_t* c2 = rs + ((int64_t)level * nq + i) * 2;
-  U2 x = ld2(in.d + ct * in.cs + p * in.ps + off);
-  U2 y = ld2(spread + ((r2 * level) << logN) + off);
-  st2(out.d + ct * out.cs + p * out.ps + off, mul_shoup(submod(x.a, y.a, q), c2[0], c2[1], q),
-      mul_shoup(submod(x.b, y.b, q), c2[0], c2[1], q));
-}
-
-// ------------------------------------------------------------------ key switching
-// ModUp of digit j at level l: d (coefficient form, rows 0..l, ct stride (l+1)N) to every
-// prime outside the digit: sum_k [x_k * (D/s_k)^-1]_{s_k} * (D/s_k) mod target.
-// ext rows: targets in order (Q rows 0..l outside the digit, then P rows).
-__global__ void __launch_bounds__(EW_THREADS) k_modup(const PrimeConst* pc, const uint64_t* mu_tab,
-                                                       const double* muf, const uint64_t* dcoef, uint64_t* ext,
-                                                       int64_t ext_cs, int logN, int level, int lo, int sz, int nq,
-                                                       int np, int alpha, int tgroup, int ngroups) {
-  const int chunks = (1 << logN) / EW_CHUNK;
-  int64_t bid = blockIdx.x;
-  int ch = (int)(bid % chunks);
-  int64_t rest = bid / chunks;
-  const int e_lo = (int)(rest % ngroups) * tgroup, e_hi = e_lo + tgroup;
-  int64_t ct = rest / ngroups;
-  const int nl = level + 1;
-  int c = ch * EW_CHUNK + threadIdx.x * 2;
-  const uint64_t* src = dcoef + ((ct * nl) << logN) + c;
-  uint64_t y0[16], y1[16];
-  bool src_small = true;  // every source residue fits an exact double operand
-#pragma unroll 4
-  for (int k = 0; k < sz; ++k) {
-    const uint64_t q = pc[lo + k].q;
-    src_small = src_small && pc[lo + k].k <= FP_MAX_BITS;
-    U2 x = ld2(src + ((int64_t)(lo + k) << logN));
-    uint64_t w = mu_tab[2 * k], ws = mu_tab[2 * k + 1];
-    y0[k] = mul_shoup(x.a, w, ws, q);
-    y1[k] = mul_shoup(x.b, w, ws, q);
-  }
-  uint64_t* dst = ext + ct * ext_cs + c;
-  int e = 0;
-  for (int g = 0; g < nl + np; ++g) {
-    if (g >= lo && g < lo + sz) continue;
-    if (e < e_lo || e >= e_hi) {
-      ++e;
-      continue;
-    }
-    int gp = g < nl ? g : nq + (g - nl);
-    const PrimeConst P = pc[gp];
-    if (P.k <= FP_MAX_BITS) {
-#pragma clang fp contract(off)
-      // y * hat = y_hi * (2^32 hat) + y_lo * hat; every product exact, |sum| < 2 sz q
-      const double* h = muf + 2 * (int64_t)gp * alpha;
-      double a0 = 0.0, a1 = 0.0;
-      for (int k = 0; k < sz; ++k) {
-        if (src_small) {
-          a0 += fmulmod(u64_to_f(y0[k]), h[2 * k], P.qd, P.qinv);
-          a1 += fmulmod(u64_to_f(y1[k]), h[2 * k], P.qd, P.qinv);
-        } else {
-          a0 += fmulmod((double)(uint32_t)(y0[k] >> 32), h[2 * k + 1], P.qd, P.qinv) +
-                fmulmod((double)(uint32_t)y0[k], h[2 * k], P.qd, P.qinv);
-          a1 += fmulmod((double)(uint32_t)(y1[k] >> 32), h[2 * k + 1], P.qd, P.qinv) +
-                fmulmod((double)(uint32_t)y1[k], h[2 * k], P.qd, P.qinv);
-        }
-      }
-      st2(dst + ((int64_t)e << logN), fcanon(a0, P.qd, P.qinv), fcanon(a1, P.qd, P.qinv));
-    } else {
-      const uint64_t q = P.q, two_q = 2 * q;
-      const uint64_t* h = mu_tab + 2 * (alpha + gp * alpha);
-      uint64_t a0 = 0, a1 = 0;
-      for (int k = 0; k < sz; ++k) {
-        uint64_t w = h[2 * k], ws = h[2 * k + 1];
-        a0 += mul_shoup_lazy(y0[k], w, ws, q);
-        a1 += mul_shoup_lazy(y1[k], w, ws, q);
-        a0 = a0 >= two_q ? a0 - two_q : a0;
-        a1 = a1 >= two_q ? a1 - two_q : a1;
-      }
-      st2(dst + ((int64_t)e << logN), csub(a0, q), csub(a1, q));
-    }
-    ++e;
-  }
-}
-
-// acc[ct][part][x] = sum_j v_j[x] * key_j[part][prime(x)], x over Q rows 0..l then P rows;
-// v_j[x] = d[x] for x in digit j, else the ModUp row of digit j.  One thread owns two
-// coefficients of one extended row of KS_CTP ciphertexts: the key values are loaded once
-// and used for each of them.  The grid is XCD-aware: workgroup b runs on XCD b mod 8, and
-// the workgroups that share one (row, chunk) tile of the key are given consecutive slots
-// on the same XCD, so the key tile is fetched from HBM once per launch and then served by
-// that XCD's L2.  With galois != 1, d is the input before the automorphism X -> X^galois
-// and the in-digit rows are gathered through it.
-constexpr int KS_MAX_DIGITS = 8;
-constexpr int KS_CTP = 2;
-template <int ND>  // digits at this level
-__global__ void __launch_bounds__(EW_THREADS) k_ks_inner(const PrimeConst* pc, CtV d, const uint64_t* ext, int64_t ext_cs,
-                                                          int64_t ext_ds, const uint64_t* key, uint64_t* acc, int logN,
-                                                          int level, int nq, int np, int alpha, int64_t count,
-                                                          uint64_t galois) {
-  const int chunks = (1 << logN) / EW_CHUNK;
-  const int nl = level + 1, nx = nl + np, nqp = nq + np;
-  const int64_t ngrp = (count + KS_CTP - 1) / KS_CTP;
-  const int64_t bid = blockIdx.x;
-  const int64_t rest = bid >> 3;
-  const int64_t grp = rest % ngrp;
-  const int64_t tile = (rest / ngrp) * 8 + (bid & 7);
-  const int ch = (int)(tile % chunks);
-  const int x = (int)(tile / chunks);
-  const int c = ch * EW_CHUNK + threadIdx.x * 2;
-  const int gp = x < nl ? x : nq + (x - nl);
-  const PrimeConst P = pc[gp];
-  U2 kb[ND], ka[ND];
-#pragma unroll
-  for (int j = 0; j < ND; ++j)
-    {
-      const uint64_t* kp = key + (((int64_t)j * 2 * nqp + gp) << logN) + c;
-      kb[j] = ld2(kp);
-      ka[j] = ld2(kp + ((int64_t)nqp << logN));
-    }
-  const int64_t ct0 = grp * KS_CTP;
-  const int nct = (int)min((int64_t)KS_CTP, count - ct0);
-  U2 v[KS_CTP][ND];
-#pragma unroll
-  for (int u = 0; u < KS_CTP; ++u) {
-    if (u >= nct) break;
-    const int64_t ct = ct0 + u;
-#pragma unroll
-    for (int j = 0; j < ND; ++j) {
-      {
-        int lo = j * alpha, hi = min(lo + alpha, nl);
-        if (x >= lo && x < hi) {
-          const uint64_t* row = d.d + ct * d.cs + ((int64_t)x << logN);
-          if (galois != 1) {
-            v[u][j].a = row[galois_src(c, galois, logN)];
-            v[u][j].b = row[galois_src(c + 1, galois, logN)];
-          } else {
-            v[u][j] = ld2(row + c);
-          }
-        } else {
-          int e = x < lo ? x : x - (hi - lo);
-          v[u][j] = ld2(ext + ct * ext_cs + j * ext_ds + ((int64_t)e << logN) + c);
-        }
-      }
-    }
-  }
-  if (P.k <= FP_MAX_BITS) {
-#pragma clang fp contract(off)
-    const double q = P.qd, qi = P.qinv;
-    double kbf[ND][2], kaf[ND][2];
-#pragma unroll
-    for (int j = 0; j < ND; ++j)
-      {
-        kbf[j][0] = u64_to_f(kb[j].a), kbf[j][1] = u64_to_f(kb[j].b);
-        kaf[j][0] = u64_to_f(ka[j].a), kaf[j][1] = u64_to_f(ka[j].b);
-      }
-#pragma unroll
-    for (int u = 0; u < KS_CTP; ++u) {
-      if (u >= nct) break;
-      double s0a = 0, s0b = 0, s1a = 0, s1b = 0;
-#pragma unroll
-      for (int j = 0; j < ND; ++j)
-        {
-          double va = u64_to_f(v[u][j].a), vb = u64_to_f(v[u][j].b);
-          s0a += fmulmod(va, kbf[j][0], q, qi);
-          s0b += fmulmod(vb, kbf[j][1], q, qi);
-          s1a += fmulmod(va, kaf[j][0], q, qi);
-          s1b += fmulmod(vb, kaf[j][1], q, qi);
-        }
-      uint64_t* o = acc + (ct0 + u) * ((int64_t)(2 * nx) << logN) + ((int64_t)x << logN) + c;
-      st2(o, fcanon(s0a, q, qi), fcanon(s0b, q, qi));
-      st2(o + ((int64_t)nx << logN), fcanon(s1a, q, qi), fcanon(s1b, q, qi));
-    }
-    return;
-  }
-#pragma unroll
-  for (int u = 0; u < KS_CTP; ++u) {
-    if (u >= nct) break;
-    uint64_t s0a = 0, s0b = 0, s1a = 0, s1b = 0;
-#pragma unroll
-    for (int j = 0; j < ND; ++j)
-      {
-        s0a = addmod(s0a, mulmod(v[u][j].a, kb[j].a, P), P.q);
-        s0b = addmod(s0b, mulmod(v[u][j].b, kb[j].b, P), P.q);
-        s1a = addmod(s1a, mulmod(v[u][j].a, ka[j].a, P), P.q);
-        s1b = addmod(s1b, mulmod(v[u][j].b, ka[j].b, P), P.q);
-      }
-    uint64_t* o = acc + (ct0 + u) * ((int64_t)(2 * nx) << logN) + ((int64_t)x << logN) + c;
-    st2(o, s0a, s0b);
-    st2(o + ((int64_t)nx << logN), s1a, s1b);
-  }
-}
-
-__global__ void __launch_bounds__(EW_THREADS) k_moddown_conv(const PrimeConst* pc, const uint64_t* md,
-                                                              const double* mdf, const uint64_t* acc, uint64_t* conv,
-                                                              int logN, int level, int nq, int np) {
-  const int chunks = (1 << logN) / EW_CHUNK;
-  const int nl = level + 1, nx = nl + np;
-  int64_t bid = blockIdx.x;
-  int ch = (int)(bid % chunks);
-  int64_t r = bid / chunks;  // ct*2 + part
-  int c = ch * EW_CHUNK + threadIdx.x * 2;
-  const uint64_t* src = acc + ((r * nx + nl) << logN) + c;
-  uint64_t y0[16], y1[16];
-  for (int k = 0; k < np; ++k) {
-    const uint64_t q = pc[nq + k].q;
-    U2 x = ld2(src + ((int64_t)k << logN));
-    y0[k] = mul_shoup(x.a, md[2 * k], md[2 * k + 1], q);
-    y1[k] = mul_shoup(x.b, md[2 * k], md[2 * k + 1], q);
-  }
-  const uint64_t* hat = md + 2 * np;
-  uint64_t* dst = conv + ((r * nl) << logN) + c;
-  for (int i = 0; i < nl; ++i) {
-    const PrimeConst Pi = pc[i];
-    if (Pi.k <= FP_MAX_BITS) {
-#pragma clang fp contract(off)
-      // y * hat = y_hi * (2^32 hat) + y_lo * hat, exact products, |sum| < 2 np q
-      const double* h = mdf + 2 * (int64_t)i * np;
-      double a0 = 0.0, a1 = 0.0;
-      for (int k = 0; k < np; ++k) {
-        a0 += fmulmod((double)(uint32_t)(y0[k] >> 32), h[2 * k + 1], Pi.qd, Pi.qinv) +
-              fmulmod((double)(uint32_t)y0[k], h[2 * k], Pi.qd, Pi.qinv);
-        a1 += fmulmod((double)(uint32_t)(y1[k] >> 32), h[2 * k + 1], Pi.qd, Pi.qinv) +
-              fmulmod((double)(uint32_t)y1[k], h[2 * k], Pi.qd, Pi.qinv);
-      }
-      st2(dst + ((int64_t)i << logN), fcanon(a0, Pi.qd, Pi.qinv), fcanon(a1, Pi.qd, Pi.qinv));
-      continue;
-    }
-    const uint64_t q = Pi.q, two_q = 2 * q;
-    const uint64_t* h = hat + 2 * (int64_t)i * np;
-    uint64_t a0 = 0, a1 = 0;
-    for (int k = 0; k < np; ++k) {
-      a0 += mul_shoup_lazy(y0[k], h[2 * k], h[2 * k + 1], q);
-      a1 += mul_shoup_lazy(y1[k], h[2 * k], h[2 * k + 1], q);
-      a0 = a0 >= two_q ? a0 - two_q : a0;
-      a1 = a1 >= two_q ? a1 - two_q : a1;
-    }
-    st2(dst + ((int64_t)i << logN), csub(a0, q), csub(a1, q));
-  }
-}
-
-// out_p_i = [addend_p_i +] base_p_i + (acc_p_i - conv_p_i) * P^-1 mod q_i   (base_1 may be absent).
-// With galois != 1, base_0 is read through the automorphism X -> X^galois (NTT-domain gather).
-__global__ void __launch_bounds__(EW_THREADS) k_ks_combine(const PrimeConst* pc, const uint64_t* pinv,
-                                                            const uint64_t* acc, const uint64_t* conv, CtV base0,
-                                                            CtV base1, int has_base1, CtV out, int logN, int level,
-                                                            int np, uint64_t galois, CtV addend, int has_addend) {
-  const int chunks = (1 << logN) / EW_CHUNK;
-  const int nl = level + 1, nx = nl + np;
-  int64_t bid = blockIdx.x;
-  int ch = (int)(bid % chunks);
-  int64_t row = bid / chunks;
-  int i = (int)(row % nl);
-  int64_t r2 = row / nl;
-  int p = (int)(r2 % 2);
-  int64_t ct = r2 / 2;
-  const int k0 = ch * EW_CHUNK + threadIdx.x * 2;
-  int64_t off = ((int64_t)i << logN) + k0;
-  const uint64_t q = pc[i].q;
-  U2 x = ld2(acc + ((ct * 2 + p) * nx << logN) + off);
-  U2 y = ld2(conv + ((ct * 2 + p) * nl << logN) + off);
-  uint64_t w = pinv[2 * i], ws = pinv[2 * i + 1];
-  uint64_t r0 = mul_shoup(submod(x.a, y.a, q), w, ws, q);
-  uint64_t r1 = mul_shoup(submod(x.b, y.b, q), w, ws, q);
-  if (p == 0 || has_base1) {
-    const CtV& B = p == 0 ? base0 : base1;
-    U2 z;
-    if (p == 0 && galois != 1) {
-      const uint64_t* src = B.d + ct * B.cs + ((int64_t)i << logN);
-      const uint32_t mask2n = (2u << logN) - 1;
-      uint32_t e0 = (uint32_t)(((uint64_t)(2 * brv_n(k0, logN) + 1) * galois) & mask2n);
-      uint32_t e1 = (uint32_t)(((uint64_t)(2 * brv_n(k0 + 1, logN) + 1) * galois) & mask2n);
-      z.a = src[brv_n((e0 - 1) >> 1, logN)];
-      z.b = src[brv_n((e1 - 1) >> 1, logN)];
-    } else {
-      z = ld2(B.d + ct * B.cs + off);
-    }
-    r0 = addmod(r0, z.a, q);
-    r1 = addmod(r1, z.b, q);
-  }
-  if (has_addend) {
-    U2 z = ld2(addend.d + ct * addend.cs + p * addend.ps + off);
-    r0 = addmod(r0, z.a, q);
-    r1 = addmod(r1, z.b, q);
-  }
-  st2(out.d + ct * out.cs + p * out.ps + off, r0, r1);
-}
-
 // ------------------------------------------------------------------ ChaCha20 (RFC 8439) and samplers
 __device__ __forceinline__ uint32_t rotl(uint32_t v, int n) { return (v << n) | (v >> (32 - n)); }
 #define QRD(a, b, c, d)          \
@@ -826,124 +530,6 @@ __global__ void __launch_bounds__(EW_THREADS) k_mul_rows(const PrimeConst* pc, c
 }
 
 }  // namespace
-
-// ====================================================================== launchers
-#define CHUNKS(g) ((g).N / EW_CHUNK)
-#define LAUNCH(kern, nblk, s, ...) hipLaunchKernelGGL(kern, dim3(grid_of(nblk)), dim3(EW_THREADS), 0, s, __VA_ARGS__)
-
-void k_add_launch(const Geo& g, const DevTables& t, CtV a, CtV b, CtV out, int64_t count, int n_poly, int nl, bool sub,
-                  hipStream_t s) {
-  int64_t n = count * n_poly * nl * CHUNKS(g);
-  if (n) LAUNCH(k_add, n, s, t.pc, a, b, out, g.logN, nl, n_poly, sub ? 1 : 0);
-}
-void k_tensor_launch(const Geo& g, const DevTables& t, CtV a, CtV b, CtV out, int64_t count, int nl, bool acc,
-                     hipStream_t s) {
-  int64_t n = count * nl * CHUNKS(g);
-  if (n) LAUNCH(k_tensor, n, s, t.pc, a, b, out, g.logN, nl, acc ? 1 : 0);
-}
-void k_tensor_reduce_launch(const Geo& g, const DevTables& t, CtV a, CtV b, int64_t count, CtV acc, int nl,
-                            bool accumulate, hipStream_t s) {
-  int64_t n = (int64_t)nl * CHUNKS(g);
-  LAUNCH(k_tensor_reduce, n, s, t.pc, a, b, count, acc, g.logN, nl, accumulate ? 1 : 0);
-}
-void k_mul_pt_launch(const Geo& g, const DevTables& t, CtV a, const uint64_t* pt, CtV out, int64_t count, int n_poly,
-                     int nl, hipStream_t s) {
-  int64_t n = count * n_poly * nl * CHUNKS(g);
-  if (n) LAUNCH(k_mul_pt, n, s, t.pc, a, pt, out, g.logN, nl, n_poly);
-}
-void k_add_pt_launch(const Geo& g, const DevTables& t, CtV a, const uint64_t* pt, CtV out, int64_t count, int nl,
-                     hipStream_t s) {
-  int64_t n = count * nl * CHUNKS(g);
-  if (n) LAUNCH(k_add_pt, n, s, t.pc, a, pt, out, g.logN, nl);
-}
-void k_mul_scalar_launch(const Geo& g, const DevTables& t, CtV a, CtV out, int64_t count, int n_poly, int nl,
-                         const uint64_t* k_res, hipStream_t s, const uint64_t* k_dev) {
-  K64 k{};
-  if (!k_dev)
-    for (int i = 0; i < nl; ++i) k.v[i] = U2{k_res[2 * i], k_res[2 * i + 1]};
-  int64_t n = count * n_poly * nl * CHUNKS(g);
-  if (n) LAUNCH(k_mul_scalar, n, s, t.pc, a, out, g.logN, nl, n_poly, k, reinterpret_cast<const U2*>(k_dev));
-}
-
-struct Words {
-  uint64_t v[kWriteWords];
-};
-__global__ void k_write_words(uint64_t* dst, int n, Words w) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = w.v[i];
-}
-void k_write_words_launch(uint64_t* dst, const uint64_t* src, size_t n, hipStream_t s) {
-  for (size_t o = 0; o < n; o += kWriteWords) {
-    Words w{};
-    const int m = (int)std::min<size_t>(kWriteWords, n - o);
-    for (int i = 0; i < m; ++i) w.v[i] = src[o + i];
-    hipLaunchKernelGGL(k_write_words, dim3(1), dim3(256), 0, s, dst + o, m, w);
-  }
-}
-void k_copy_launch(const Geo& g, CtV a, CtV out, int64_t count, int n_poly, int nl, hipStream_t s) {
-  int64_t n = count * n_poly * nl * CHUNKS(g);
-  if (n) LAUNCH(k_copy, n, s, a, out, g.logN, nl, n_poly);
-}
-void k_automorph_launch(const Geo& g, CtV a, CtV out, int64_t count, int n_poly, int nl, uint64_t galois,
-                        hipStream_t s) {
-  int64_t n = count * n_poly * nl * CHUNKS(g);
-  if (n) LAUNCH(k_automorph, n, s, a, out, g.logN, nl, n_poly, galois);
-}
-void k_rescale_spread_launch(const Geo& g, const DevTables& t, const uint64_t* last, uint64_t* spread, int64_t rows,
-                             int level, hipStream_t s) {
-  int64_t n = rows * CHUNKS(g);
-  if (n) LAUNCH(k_rescale_spread, n, s, t.pc, t.rescale_q, last, spread, g.logN, level, g.n_q);
-}
-void k_rescale_combine_launch(const Geo& g, const DevTables& t, CtV in, const uint64_t* spread, CtV out, int64_t count,
-                              int n_poly, int level, hipStream_t s) {
-  int64_t n = count * n_poly * level * CHUNKS(g);
-  if (n) LAUNCH(k_rescale_combine, n, s, t.pc, t.rescale, in, spread, out, g.logN, level, n_poly, g.n_q);
-}
-void k_modup_launch(const Geo& g, const DevTables& t, const uint64_t* dcoef, int64_t count, int level, int digit,
-                    uint64_t* ext, int64_t ext_cs, hipStream_t s) {
-  int nl = level + 1;
-  int lo = digit * g.alpha;
-  int sz = nl - lo < g.alpha ? nl - lo : g.alpha;
-  const uint64_t* tab = t.modup + 2 * (int64_t)((level * g.dnum + digit) * g.mu_stride);
-  // targets are split over workgroups (8 per group) to keep every CU busy
-  const int nt = nl + g.n_p - sz, tgroup = 8, ngroups = (nt + tgroup - 1) / tgroup;
-  int64_t n = count * ngroups * CHUNKS(g);
-  const double* tabf = t.modup_f + 2 * (int64_t)((level * g.dnum + digit) * g.nqp) * g.alpha;
-  if (n)
-    LAUNCH(k_modup, n, s, t.pc, tab, tabf, dcoef, ext, ext_cs, g.logN, level, lo, sz, g.n_q, g.n_p, g.alpha, tgroup,
-           ngroups);
-}
-void k_ks_inner_launch(const Geo& g, const DevTables& t, CtV d, const uint64_t* ext, int64_t ext_cs, int64_t ext_ds,
-                       const uint64_t* key, uint64_t* acc, int64_t count, int level, uint64_t galois, hipStream_t s) {
-  int nx = level + 1 + g.n_p;
-  // tiles (row x chunk) are a multiple of 8 because N/512 is; KS_CTP ciphertexts per workgroup
-  int64_t n = (count + KS_CTP - 1) / KS_CTP * (int64_t)nx * CHUNKS(g);
-  const int nd = (level + g.alpha) / g.alpha;
-  if (!n) return;
-  switch (nd) {
-#define HEQG_KSI(D)                                                                                              \
-  case D:                                                                                                        \
-    LAUNCH(k_ks_inner<D>, n, s, t.pc, d, ext, ext_cs, ext_ds, key, acc, g.logN, level, g.n_q, g.n_p, g.alpha, count, \
-           galois);                                                                                              \
-    break;
-    HEQG_KSI(1) HEQG_KSI(2) HEQG_KSI(3) HEQG_KSI(4) HEQG_KSI(5) HEQG_KSI(6) HEQG_KSI(7) HEQG_KSI(8)
-#undef HEQG_KSI
-  }
-}
-void k_moddown_conv_launch(const Geo& g, const DevTables& t, const uint64_t* acc, uint64_t* conv, int64_t count,
-                           int level, hipStream_t s) {
-  int64_t n = count * 2 * CHUNKS(g);
-  if (n) LAUNCH(k_moddown_conv, n, s, t.pc, t.moddown, t.moddown_f, acc, conv, g.logN, level, g.n_q, g.n_p);
-}
-void k_ks_combine_launch(const Geo& g, const DevTables& t, const uint64_t* acc, const uint64_t* conv, CtV base0,
-                         CtV base1, bool has_base1, CtV out, int64_t count, int level, uint64_t galois,
-                         const CtV* addend, hipStream_t s) {
-  const uint64_t* pinv = t.moddown + 2 * g.n_p + 2 * (int64_t)g.n_q * g.n_p;
-  int64_t n = count * 2 * (level + 1) * CHUNKS(g);
-  CtV ad = addend ? *addend : CtV{nullptr, 0, 0};
-  if (n)
-    LAUNCH(k_ks_combine, n, s, t.pc, pinv, acc, conv, base0, base1, has_base1 ? 1 : 0, out, g.logN, level, g.n_p,
-           galois, ad, addend ? 1 : 0);
-}
 void k_sample_small_launch(uint64_t seed, uint64_t purpose, uint64_t obj_first, int64_t count, int N, int kind,
                            int64_t* out, hipStream_t s) {
   int64_t threads = count * (N / 8);

@@ -636,16 +636,16 @@ struct ProfSample {
     if (ps.every <= 0 || (ps.seen[c]++ % ps.every) != 0) return;
     if (hipEventCreate(&a) != hipSuccess) return;
     if (hipEventCreate(&b) != hipSuccess) {
-      hipEventDestroy(a);
+      (void)hipEventDestroy(a);
       a = nullptr;
       return;
     }
     cls = c, rows = r, src_rows = sr;
-    hipEventRecord(a, s);
+    (void)hipEventRecord(a, s);
   }
   void end(hipStream_t s) {
     if (cls < 0) return;
-    hipEventRecord(b, s);
+    (void)hipEventRecord(b, s);
     ProfState& ps = prof();
     std::lock_guard<std::mutex> g(ps.mu);
     ps.recs[cls].push_back({a, b, rows, src_rows});
@@ -736,8 +736,8 @@ extern "C" int heqg_prof_start(int every) {
   std::lock_guard<std::mutex> g(ps.mu);
   for (auto& v : ps.recs) {
     for (auto& r : v) {
-      hipEventDestroy(r.a);
-      hipEventDestroy(r.b);
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
     }
     v.clear();
   }
@@ -762,8 +762,8 @@ extern "C" int heqg_prof_stop(int kernel, double* avg_us, int64_t* launches, dou
     rows += (double)r.rows;
     srows += (double)r.src_rows;
     ++n;
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
   }
   ps.recs[kernel].clear();
   if (avg_us) *avg_us = n ? 1000.0 * tot / n : 0.0;
