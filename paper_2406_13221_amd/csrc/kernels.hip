@@ -283,6 +283,136 @@ __global__ void __launch_bounds__(EW_THREADS) k_rescale_spread(const PrimeConst*
     st2(spread + ((r * level + i) << logN) + c, v0, v1);
   }
 }
+
+// out_i = (in_i - spread_i) * q_l^-1 mod q_i for i < level
+__global__ void __launch_bounds__(EW_THREADS) k_rescale_combine(const PrimeConst* pc, const uint64_t* rs, CtV in,
+                                                                 const uint64_t* spread, CtV out, int logN, int level,
+                                                                 int n_poly, int nq) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  int64_t bid = blockIdx.x;
+  int ch = (int)(bid % chunks);
+  int64_t row = bid / chunks;
+  int i = (int)(row % level);
+  int64_t r2 = row / level;  // = ct * n_poly + p
+  int p = (int)(r2 % n_poly);
+  int64_t ct = r2 / n_poly;
+  int64_t off = ((int64_t)i << logN) + ch * EW_CHUNK + threadIdx.x * 2;
+  const uint64_t q = pc[i].q;
+  const uint64_t* c2 = rs + ((int64_t)level * nq + i) * 2;
+  U2 x = ld2(in.d + ct * in.cs + p * in.ps + off);
+  U2 y = ld2(spread + ((r2 * level) << logN) + off);
+  st2(out.d + ct * out.cs + p * out.ps + off, mul_shoup(submod(x.a, y.a, q), c2[0], c2[1], q),
+      mul_shoup(submod(x.b, y.b, q), c2[0], c2[1], q));
+}
+
+// acc[ct][part][x] = sum_j v_j[x] * key_j[part][prime(x)], x over Q rows 0..l then P rows;
+// v_j[x] = d[x] for x in digit j, else the ModUp row of digit j.  One thread owns two
+// coefficients of one extended row of KS_CTP ciphertexts: the key values are loaded once
+// and used for each of them.  The grid is XCD-aware: workgroup b runs on XCD b mod 8, and
+// the workgroups that share one (row, chunk) tile of the key are given consecutive slots
+// on the same XCD, so the key tile is fetched from HBM once per launch and then served by
+// that XCD's L2.  With galois != 1, d is the input before the automorphism X -> X^galois
+// and the in-digit rows are gathered through it.
+constexpr int KS_MAX_DIGITS = 8;
+constexpr int KS_CTP = 2;
+template <int ND>  // digits at this level
+__global__ void __launch_bounds__(EW_THREADS) k_ks_inner(const PrimeConst* pc, CtV d, const uint64_t* ext, int64_t ext_cs,
+                                                          int64_t ext_ds, const uint64_t* key, uint64_t* acc, int logN,
+                                                          int level, int nq, int np, int alpha, int64_t count,
+                                                          uint64_t galois) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  const int nl = level + 1, nx = nl + np, nqp = nq + np;
+  const int64_t ngrp = (count + KS_CTP - 1) / KS_CTP;
+  const int64_t bid = blockIdx.x;
+  const int64_t rest = bid >> 3;
+  const int64_t grp = rest % ngrp;
+  const int64_t tile = (rest / ngrp) * 8 + (bid & 7);
+  const int ch = (int)(tile % chunks);
+  const int x = (int)(tile / chunks);
+  const int c = ch * EW_CHUNK + threadIdx.x * 2;
+  const int gp = x < nl ? x : nq + (x - nl);
+  const PrimeConst P = pc[gp];
+  U2 kb[ND], ka[ND];
+#pragma unroll
+  for (int j = 0; j < ND; ++j)
+    {
+      const uint64_t* kp = key + (((int64_t)j * 2 * nqp + gp) << logN) + c;
+      kb[j] = ld2(kp);
+      ka[j] = ld2(kp + ((int64_t)nqp << logN));
+    }
+  const int64_t ct0 = grp * KS_CTP;
+  const int nct = (int)min((int64_t)KS_CTP, count - ct0);
+  U2 v[KS_CTP][ND];
+#pragma unroll
+  for (int u = 0; u < KS_CTP; ++u) {
+    if (u >= nct) break;
+    const int64_t ct = ct0 + u;
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+      {
+        int lo = j * alpha, hi = min(lo + alpha, nl);
+        if (x >= lo && x < hi) {
+          const uint64_t* row = d.d + ct * d.cs + ((int64_t)x << logN);
+          if (galois != 1) {
+            v[u][j].a = row[galois_src(c, galois, logN)];
+            v[u][j].b = row[galois_src(c + 1, galois, logN)];
+          } else {
+            v[u][j] = ld2(row + c);
+          }
+        } else {
+          int e = x < lo ? x : x - (hi - lo);
+          v[u][j] = ld2(ext + ct * ext_cs + j * ext_ds + ((int64_t)e << logN) + c);
+        }
+      }
+    }
+  }
+  if (P.k <= FP_MAX_BITS) {
+#pragma clang fp contract(off)
+    const double q = P.qd, qi = P.qinv;
+    double kbf[ND][2], kaf[ND][2];
+#pragma unroll
+    for (int j = 0; j < ND; ++j)
+      {
+        kbf[j][0] = u64_to_f(kb[j].a), kbf[j][1] = u64_to_f(kb[j].b);
+        kaf[j][0] = u64_to_f(ka[j].a), kaf[j][1] = u64_to_f(ka[j].b);
+      }
+#pragma unroll
+    for (int u = 0; u < KS_CTP; ++u) {
+      if (u >= nct) break;
+      double s0a = 0, s0b = 0, s1a = 0, s1b = 0;
+#pragma unroll
+      for (int j = 0; j < ND; ++j)
+        {
+          double va = u64_to_f(v[u][j].a), vb = u64_to_f(v[u][j].b);
+          s0a += fmulmod(va, kbf[j][0], q, qi);
+          s0b += fmulmod(vb, kbf[j][1], q, qi);
+          s1a += fmulmod(va, kaf[j][0], q, qi);
+          s1b += fmulmod(vb, kaf[j][1], q, qi);
+        }
+      uint64_t* o = acc + (ct0 + u) * ((int64_t)(2 * nx) << logN) + ((int64_t)x << logN) + c;
+      st2(o, fcanon(s0a, q, qi), fcanon(s0b, q, qi));
+      st2(o + ((int64_t)nx << logN), fcanon(s1a, q, qi), fcanon(s1b, q, qi));
+    }
+    return;
+  }
+#pragma unroll
+  for (int u = 0; u < KS_CTP; ++u) {
+    if (u >= nct) break;
+    uint64_t s0a = 0, s0b = 0, s1a = 0, s1b = 0;
+#pragma unroll
+    for (int j = 0; j < ND; ++j)
+      {
+        s0a = addmod(s0a, mulmod(v[u][j].a, kb[j].a, P), P.q);
+        s0b = addmod(s0b, mulmod(v[u][j].b, kb[j].b, P), P.q);
+        s1a = addmod(s1a, mulmod(v[u][j].a, ka[j].a, P), P.q);
+        s1b = addmod(s1b, mulmod(v[u][j].b, ka[j].b, P), P.q);
+      }
+    uint64_t* o = acc + (ct0 + u) * ((int64_t)(2 * nx) << logN) + ((int64_t)x << logN) + c;
+    st2(o, s0a, s0b);
+    st2(o + ((int64_t)nx << logN), s1a, s1b);
+  }
+}
+
 // ------------------------------------------------------------------ ChaCha20 (RFC 8439) and samplers
 __device__ __forceinline__ uint32_t rotl(uint32_t v, int n) { return (v << n) | (v >> (32 - n)); }
 #define QRD(a, b, c, d)          \
@@ -530,6 +660,95 @@ __global__ void __launch_bounds__(EW_THREADS) k_mul_rows(const PrimeConst* pc, c
 }
 
 }  // namespace
+
+// ====================================================================== launchers
+#define CHUNKS(g) ((g).N / EW_CHUNK)
+#define LAUNCH(kern, nblk, s, ...) hipLaunchKernelGGL(kern, dim3(grid_of(nblk)), dim3(EW_THREADS), 0, s, __VA_ARGS__)
+
+void k_add_launch(const Geo& g, const DevTables& t, CtV a, CtV b, CtV out, int64_t count, int n_poly, int nl, bool sub,
+                  hipStream_t s) {
+  int64_t n = count * n_poly * nl * CHUNKS(g);
+  if (n) LAUNCH(k_add, n, s, t.pc, a, b, out, g.logN, nl, n_poly, sub ? 1 : 0);
+}
+void k_tensor_launch(const Geo& g, const DevTables& t, CtV a, CtV b, CtV out, int64_t count, int nl, bool acc,
+                     hipStream_t s) {
+  int64_t n = count * nl * CHUNKS(g);
+  if (n) LAUNCH(k_tensor, n, s, t.pc, a, b, out, g.logN, nl, acc ? 1 : 0);
+}
+void k_tensor_reduce_launch(const Geo& g, const DevTables& t, CtV a, CtV b, int64_t count, CtV acc, int nl,
+                            bool accumulate, hipStream_t s) {
+  int64_t n = (int64_t)nl * CHUNKS(g);
+  LAUNCH(k_tensor_reduce, n, s, t.pc, a, b, count, acc, g.logN, nl, accumulate ? 1 : 0);
+}
+void k_mul_pt_launch(const Geo& g, const DevTables& t, CtV a, const uint64_t* pt, CtV out, int64_t count, int n_poly,
+                     int nl, hipStream_t s) {
+  int64_t n = count * n_poly * nl * CHUNKS(g);
+  if (n) LAUNCH(k_mul_pt, n, s, t.pc, a, pt, out, g.logN, nl, n_poly);
+}
+void k_add_pt_launch(const Geo& g, const DevTables& t, CtV a, const uint64_t* pt, CtV out, int64_t count, int nl,
+                     hipStream_t s) {
+  int64_t n = count * nl * CHUNKS(g);
+  if (n) LAUNCH(k_add_pt, n, s, t.pc, a, pt, out, g.logN, nl);
+}
+void k_mul_scalar_launch(const Geo& g, const DevTables& t, CtV a, CtV out, int64_t count, int n_poly, int nl,
+                         const uint64_t* k_res, hipStream_t s, const uint64_t* k_dev) {
+  K64 k{};
+  if (!k_dev)
+    for (int i = 0; i < nl; ++i) k.v[i] = U2{k_res[2 * i], k_res[2 * i + 1]};
+  int64_t n = count * n_poly * nl * CHUNKS(g);
+  if (n) LAUNCH(k_mul_scalar, n, s, t.pc, a, out, g.logN, nl, n_poly, k, reinterpret_cast<const U2*>(k_dev));
+}
+
+struct Words {
+  uint64_t v[kWriteWords];
+};
+__global__ void k_write_words(uint64_t* dst, int n, Words w) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = w.v[i];
+}
+void k_write_words_launch(uint64_t* dst, const uint64_t* src, size_t n, hipStream_t s) {
+  for (size_t o = 0; o < n; o += kWriteWords) {
+    Words w{};
+    const int m = (int)std::min<size_t>(kWriteWords, n - o);
+    for (int i = 0; i < m; ++i) w.v[i] = src[o + i];
+    hipLaunchKernelGGL(k_write_words, dim3(1), dim3(256), 0, s, dst + o, m, w);
+  }
+}
+void k_copy_launch(const Geo& g, CtV a, CtV out, int64_t count, int n_poly, int nl, hipStream_t s) {
+  int64_t n = count * n_poly * nl * CHUNKS(g);
+  if (n) LAUNCH(k_copy, n, s, a, out, g.logN, nl, n_poly);
+}
+void k_automorph_launch(const Geo& g, CtV a, CtV out, int64_t count, int n_poly, int nl, uint64_t galois,
+                        hipStream_t s) {
+  int64_t n = count * n_poly * nl * CHUNKS(g);
+  if (n) LAUNCH(k_automorph, n, s, a, out, g.logN, nl, n_poly, galois);
+}
+void k_rescale_spread_launch(const Geo& g, const DevTables& t, const uint64_t* last, uint64_t* spread, int64_t rows,
+                             int level, hipStream_t s) {
+  int64_t n = rows * CHUNKS(g);
+  if (n) LAUNCH(k_rescale_spread, n, s, t.pc, t.rescale_q, last, spread, g.logN, level, g.n_q);
+}
+void k_rescale_combine_launch(const Geo& g, const DevTables& t, CtV in, const uint64_t* spread, CtV out, int64_t count,
+                              int n_poly, int level, hipStream_t s) {
+  int64_t n = count * n_poly * level * CHUNKS(g);
+  if (n) LAUNCH(k_rescale_combine, n, s, t.pc, t.rescale, in, spread, out, g.logN, level, n_poly, g.n_q);
+}
+void k_ks_inner_launch(const Geo& g, const DevTables& t, CtV d, const uint64_t* ext, int64_t ext_cs, int64_t ext_ds,
+                       const uint64_t* key, uint64_t* acc, int64_t count, int level, uint64_t galois, hipStream_t s) {
+  int nx = level + 1 + g.n_p;
+  // tiles (row x chunk) are a multiple of 8 because N/512 is; KS_CTP ciphertexts per workgroup
+  int64_t n = (count + KS_CTP - 1) / KS_CTP * (int64_t)nx * CHUNKS(g);
+  const int nd = (level + g.alpha) / g.alpha;
+  if (!n) return;
+  switch (nd) {
+#define HEQG_KSI(D)                                                                                              \
+  case D:                                                                                                        \
+    LAUNCH(k_ks_inner<D>, n, s, t.pc, d, ext, ext_cs, ext_ds, key, acc, g.logN, level, g.n_q, g.n_p, g.alpha, count, \
+           galois);                                                                                              \
+    break;
+    HEQG_KSI(1) HEQG_KSI(2) HEQG_KSI(3) HEQG_KSI(4) HEQG_KSI(5) HEQG_KSI(6) HEQG_KSI(7) HEQG_KSI(8)
+#undef HEQG_KSI
+  }
+}
 void k_sample_small_launch(uint64_t seed, uint64_t purpose, uint64_t obj_first, int64_t count, int N, int kind,
                            int64_t* out, hipStream_t s) {
   int64_t threads = count * (N / 8);
