@@ -24,6 +24,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP64 vector issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz instructions per second (the published
+# 78.6 TFLOP/s counts each FMA as two flops)
+FP64_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 PMC_FILE = os.path.join(ROOT, "profiles", "conv_cols_c3_pmc.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2406_13221_amd", "csrc", "ntt.hip")
 
@@ -207,8 +210,8 @@ def main():
         ev[k][2].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    conv_us, conv_n, conv_rows, conv_src = heqg.prof_stop(1)
-    avg_us, n_sampled, avg_rows, _ = heqg.prof_stop(0)
+    conv_us, conv_n, conv_rows, conv_src, conv_ops = heqg.prof_stop(1)
+    avg_us, n_sampled, avg_rows, _, _ = heqg.prof_stop(0)
     ms_per_step = (t1 - t0) * 1000.0 / args.steps
     upd = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps / 1000.0
     ref = sum(e[1].elapsed_time(e[2]) for e in ev) / args.steps / 1000.0
@@ -309,15 +312,21 @@ def main():
         print("decrypted weights out of range", file=sys.stderr)
         sys.exit(1)
 
-    # dominant kernel: the fused base-conversion column pass; algorithmic bytes per launch = every
-    # output row written once + every distinct source row read once (8N bytes a row)
+    # dominant kernel: the fused base-conversion column pass.  It moves exactly its algorithmic bytes
+    # (every output row written once, every distinct source row read once) at a small fraction of the
+    # HBM peak and is bound by FP64 issue: the roofline is its algorithmic FP64 instructions per launch
+    # against the FP64 issue rate, with the HBM figures beside it
     conv_bytes = 8.0 * N * (conv_rows + conv_src)
-    achieved = conv_bytes / (conv_us * 1e-6) / 1e9 if conv_us > 0 else 0.0
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": pmc_traffic(conv_rows),
+    conv_gbs = conv_bytes / (conv_us * 1e-6) / 1e9 if conv_us > 0 else 0.0
+    conv_tops = conv_ops / (conv_us * 1e-6) / 1e12 if conv_us > 0 else 0.0
+    roofline = {"bound": "alu", "achieved": round(conv_tops, 2), "peak": round(FP64_PEAK_TOPS, 2), "unit": "TFLOP/s",
+                "frac": round(conv_tops / FP64_PEAK_TOPS, 4), "traffic": pmc_traffic(conv_rows),
                 "kernel": "k_ntt_cols<8,true,true> (ModUp / ModDown base conversion fused into the first "
                           "forward NTT pass)",
-                "algorithmic_bytes_per_launch": conv_bytes,
+                "ops": "FP64 instructions (an FMA counts once) per launch: output residues x (7 per conversion "
+                       "term + 3 + 4 per stage)",
+                "algorithmic_ops_per_launch": conv_ops, "algorithmic_bytes_per_launch": conv_bytes,
+                "hbm_achieved_GBps": round(conv_gbs, 1), "hbm_frac": round(conv_gbs / HBM_PEAK_GBS, 4),
                 "avg_launch_us": round(conv_us, 2), "sampled_launches": conv_n,
                 "avg_rows_per_launch": round(conv_rows, 2), "avg_source_rows_per_launch": round(conv_src, 2)}
     row_pass = 16.0 * N * avg_rows / (avg_us * 1e-6) / 1e9 if avg_us > 0 else 0.0

@@ -291,11 +291,15 @@ int heqg_ntt(heqg_ctx* ctx, uint64_t* dev_rows, int64_t n_rows, int first_prime,
  * disables sampling, synchronises that class's events and returns the mean
  * duration in microseconds, the number of sampled launches, the mean number of
  * N-word rows written per launch and (kernel 1) the mean number of distinct
- * source rows read per launch; it releases that class's samples.  Process-wide.
- * Returns -1 for a bad class, HEQG_ERR_DEVICE (-6) if an event failed.
+ * source rows read and of algorithmic FP64 instructions per launch (per output
+ * residue: 7 per base-conversion term, 3 for its reduction, 4 per first-pass
+ * stage); it releases that class's samples.  Out pointers may be NULL.
+ * Process-wide.  Returns -1 for a bad class, HEQG_ERR_DEVICE (-6) if an event
+ * failed.
  */
 int heqg_prof_start(int every);
-int heqg_prof_stop(int kernel, double* avg_us, int64_t* launches, double* avg_rows, double* avg_src_rows);
+int heqg_prof_stop(int kernel, double* avg_us, int64_t* launches, double* avg_rows, double* avg_src_rows,
+                   double* avg_ops);
 
 /*
  * Kernel-variant switches read by the launchers (process-wide; set by

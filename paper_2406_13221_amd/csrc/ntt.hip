@@ -613,6 +613,7 @@ struct ProfState {
   struct Rec {
     hipEvent_t a, b;
     int64_t rows, src_rows;
+    double ops;
   };
   std::vector<Rec> recs[2];
 };
@@ -627,7 +628,8 @@ struct ProfSample {
   hipEvent_t a = nullptr, b = nullptr;
   int cls = -1;
   int64_t rows = 0, src_rows = 0;
-  void begin(int c, int64_t r, int64_t sr, hipStream_t s) {
+  double ops = 0.0;
+  void begin(int c, int64_t r, int64_t sr, double op, hipStream_t s) {
     ProfState& ps = prof();
     if (ps.every <= 0) return;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -640,7 +642,7 @@ struct ProfSample {
       a = nullptr;
       return;
     }
-    cls = c, rows = r, src_rows = sr;
+    cls = c, rows = r, src_rows = sr, ops = op;
     (void)hipEventRecord(a, s);
   }
   void end(hipStream_t s) {
@@ -648,7 +650,7 @@ struct ProfSample {
     (void)hipEventRecord(b, s);
     ProfState& ps = prof();
     std::lock_guard<std::mutex> g(ps.mu);
-    ps.recs[cls].push_back({a, b, rows, src_rows});
+    ps.recs[cls].push_back({a, b, rows, src_rows, ops});
   }
 };
 
@@ -692,7 +694,10 @@ void run_ntt(NttParams P, int64_t rows, bool inverse, const U2* twf, const U2* t
     P.tiles = tilesA;
     ProfSample sc;
     if (P.X.csrc) {
-      sc.begin(1, rows, nab * P.X.ns, s);
+      // FP64 instructions per output residue: 7 per conversion term (exact product, reduction,
+      // accumulate), 3 for the final reduction, 8 per butterfly over LA stages of N/2 each
+      const double ops = (double)rows * (double)(1 << P.logN) * (7.0 * P.X.ns + 3.0 + 4.0 * LA);
+      sc.begin(1, rows, nab * P.X.ns, ops, s);
       hipLaunchKernelGGL((k_ntt_cols<LA, true, true>), dim3((unsigned)(rows * tilesA)), dim3(256), 0, s, P);
       sc.end(s);
     } else {
@@ -700,7 +705,7 @@ void run_ntt(NttParams P, int64_t rows, bool inverse, const U2* twf, const U2* t
     }
     P.tiles = tilesB;
     ProfSample sr;
-    if (!P.X.has_epi) sr.begin(0, rows, 0, s);
+    if (!P.X.has_epi) sr.begin(0, rows, 0, 0.0, s);
     launch_rows<LB, true>(P, blocksB, s);
     sr.end(s);
   } else {
@@ -747,12 +752,12 @@ extern "C" int heqg_prof_start(int every) {
 }
 
 extern "C" int heqg_prof_stop(int kernel, double* avg_us, int64_t* launches, double* avg_rows,
-                              double* avg_src_rows) {
+                              double* avg_src_rows, double* avg_ops) {
   if (kernel < 0 || kernel > 1) return -1;
   ProfState& ps = prof();
   std::lock_guard<std::mutex> g(ps.mu);
   ps.every = 0;
-  double tot = 0.0, rows = 0.0, srows = 0.0;
+  double tot = 0.0, rows = 0.0, srows = 0.0, ops = 0.0;
   int64_t n = 0;
   int rc = 0;
   for (auto& r : ps.recs[kernel]) {
@@ -761,6 +766,7 @@ extern "C" int heqg_prof_stop(int kernel, double* avg_us, int64_t* launches, dou
     tot += ms;
     rows += (double)r.rows;
     srows += (double)r.src_rows;
+    ops += r.ops;
     ++n;
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -770,6 +776,7 @@ extern "C" int heqg_prof_stop(int kernel, double* avg_us, int64_t* launches, dou
   if (launches) *launches = n;
   if (avg_rows) *avg_rows = n ? rows / n : 0.0;
   if (avg_src_rows) *avg_src_rows = n ? srows / n : 0.0;
+  if (avg_ops) *avg_ops = n ? ops / n : 0.0;
   return rc;
 }
 

@@ -109,7 +109,7 @@ def lib():
         "heqg_tune_ws_bytes": (sz, [vp, i32]),
         "heqg_tune_ntt": (i32, [vp, i32, vp, sz, vp, P(i32), P(dbl)]),
         "heqg_prof_start": (i32, [i32]),
-        "heqg_prof_stop": (i32, [i32, P(dbl), P(i64), P(dbl), P(dbl)]),
+        "heqg_prof_stop": (i32, [i32, P(dbl), P(i64), P(dbl), P(dbl), P(dbl)]),
         "heqg_nag_ws_bytes": (sz, [vp, i32, i32]),
         "heqg_nag_qg_step": (i32, [vp, vp, P(BatchS), P(CtS), P(CtS), P(CtS), P(SigmoidS), P(NagStateS), i32, vp,
                                    sz, vp]),
@@ -138,10 +138,12 @@ def prof_start(every):
 
 def prof_stop(kernel=0):
     """(mean microseconds, sampled launches, mean rows written per launch, mean source rows read per
-    launch) of kernel class 0 (plain forward NTT row pass) or 1 (fused base-conversion column pass)."""
-    a, n, r, sr = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
-    _check(lib().heqg_prof_stop(int(kernel), ctypes.byref(a), ctypes.byref(n), ctypes.byref(r), ctypes.byref(sr)))
-    return a.value, n.value, r.value, sr.value
+    launch, mean algorithmic FP64 instructions per launch) of kernel class 0 (plain forward NTT row
+    pass) or 1 (fused base-conversion column pass)."""
+    a, n, r, sr, op = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().heqg_prof_stop(int(kernel), ctypes.byref(a), ctypes.byref(n), ctypes.byref(r), ctypes.byref(sr),
+                                ctypes.byref(op)))
+    return a.value, n.value, r.value, sr.value, op.value
 
 
 def _torch():
