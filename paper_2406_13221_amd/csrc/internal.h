@@ -44,19 +44,19 @@ struct NttExtra {
   uint64_t galois;
   // inverse, last pass: multiply by scale[p] (pairs w, Shoup(w)) / scalef[p] instead of N^-1;
   // out_f64: rows of primes of at most FP_MAX_BITS bits are written as doubles (the
-  // canonical residue's value), for a base conversion that reads them (csrc_f64)
+  // canonical residue's value), the form a base conversion reads them in
   const uint64_t* scale;
   const double* scalef;
   int out_f64;
   // forward, first pass: the input of row (ia, ib, ii) is the base conversion
   //   sum_s csrc_s * hat[p][s]  mod q_p,  csrc_s = csrc + ia*csrc_sa + ib*csrc_sb + s*N
   // with hat pairs (w, Shoup(w)) at chat + 2*(p*cstride + s) and FP64 pairs
-  // (w, 2^32 w mod q_p) at chatf + 2*(p*cstride + s); bit s of csplit: source s may
-  // exceed FP_MAX_BITS bits, so FP64 products take it in 32-bit halves
+  // (w, 2^32 w mod q_p) at chatf + 2*(p*cstride + s).  Bit s of csplit: source s
+  // exceeds FP_MAX_BITS bits and holds canonical integers, so FP64 products take it in
+  // 32-bit halves; every other source holds its residues as doubles (out_f64)
   const uint64_t* csrc;
   int64_t csrc_sa, csrc_sb;
   int ns, cstride, csplit;
-  int csrc_f64;  // sources whose csplit bit is clear hold doubles (written with out_f64)
   const uint64_t* chat;
   const double* chatf;
   // forward, last pass: key-switch combine instead of a plain store

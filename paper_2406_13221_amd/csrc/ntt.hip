@@ -35,6 +35,33 @@ struct __align__(16) U2 {
   uint64_t a, b;
 };
 
+// Raw buffer view of one row region (< 2 GiB): the byte offset of an access is a
+// per-thread part (one VGPR) plus a part uniform across the workgroup (an SGPR), so a
+// strided access needs no per-access vector address arithmetic.  The third word is the
+// gfx9 descriptor format for untyped access; with stride 0 and this record count the
+// range check never triggers for the offsets used here.
+struct RowBuf {
+  __amdgpu_buffer_rsrc_t r;
+  // base must be uniform across the workgroup; reading it from the first lane puts it
+  // in SGPRs even where the compiler computed it in vector registers
+  __device__ __forceinline__ explicit RowBuf(const void* base) {
+    const uint64_t a = reinterpret_cast<uintptr_t>(base);
+    const uint64_t u = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(a >> 32)) << 32) |
+                       (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+    r = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(u), 0, 0x7fffffff, 0x00020000);
+  }
+  __device__ __forceinline__ uint64_t ld(uint32_t v, uint32_t u) const {
+    const auto x = __builtin_amdgcn_raw_buffer_load_b64(r, v, u, 0);
+    return ((uint64_t)x[1] << 32) | x[0];
+  }
+  __device__ __forceinline__ void st(uint64_t d, uint32_t v, uint32_t u) const {
+    decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)) x;
+    x[0] = (uint32_t)d;
+    x[1] = (uint32_t)(d >> 32);
+    __builtin_amdgcn_raw_buffer_store_b64(x, r, v, u, 0);
+  }
+};
+
 struct NttParams {
   uint64_t* data;
   int64_t na, nb;
@@ -209,6 +236,11 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
   const int N2 = 1 << (P.logN - LOGS);
   const int cl = tid % C, kg = tid / C;
   const int c = tile * C + cl;
+  // element (kg + T*r)*N2 + c ("strided") and (16*kg + r)*N2 + c ("contiguous") of a row:
+  // per-thread byte offsets and the uniform byte step per r
+  const uint32_t vs = (uint32_t)(kg * N2 + c) * 8, us = (uint32_t)(T * N2) * 8;
+  const uint32_t vc = (uint32_t)(16 * kg * N2 + c) * 8, uc = (uint32_t)N2 * 8;
+  const RowBuf rb(row);
   if (FP) {
 #pragma clang fp contract(off)
     const double q = pc.qd, qi = pc.qinv;
@@ -223,33 +255,43 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
         const double* h = P.X.chatf + 2 * (int64_t)p * P.X.cstride;
 #pragma unroll
         for (int r = 0; r < 16; ++r) x[r] = 0.0;
+        const uint32_t all = (1u << P.X.ns) - 1;
+        // sources wider than the FP64 path hold integers: two products (high and low
+        // 32 bits) per term.  One loop per kind, each over the set bits of its mask,
+        // so that neither carries a branch.
 #pragma unroll 1
-        for (int s = 0; s < P.X.ns; ++s) {
-          const uint64_t* ys = cs + ((int64_t)s << P.logN) + c;
+        for (uint32_t m = P.X.csplit & all; m; m &= m - 1) {
+          const int s = __builtin_ctz(m);
+          const RowBuf ys(cs + ((int64_t)s << P.logN));
           const double h0 = h[2 * s], h1 = h[2 * s + 1];
+          uint64_t y[16];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) y[r] = ys.ld(vs, r * us);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int r = 0; r < 16; ++r)
+            x[r] += fmulmod((double)(uint32_t)(y[r] >> 32), h1, q, qi) + fmulmod((double)(uint32_t)y[r], h0, q, qi);
+        }
+        // the others hold doubles
+#pragma unroll 1
+        for (uint32_t m = ~P.X.csplit & all; m; m &= m - 1) {
+          const int s = __builtin_ctz(m);
+          const RowBuf ys(cs + ((int64_t)s << P.logN));
+          const double h0 = h[2 * s];
           // all 16 loads are issued before any use (left to itself the compiler waits on
           // each load in turn)
           uint64_t y[16];
 #pragma unroll
-          for (int r = 0; r < 16; ++r) y[r] = ys[(int64_t)(kg + T * r) * N2];
+          for (int r = 0; r < 16; ++r) y[r] = ys.ld(vs, r * us);
           __builtin_amdgcn_sched_barrier(0);
-          if ((P.X.csplit >> s) & 1) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
-              x[r] += fmulmod((double)(uint32_t)(y[r] >> 32), h1, q, qi) + fmulmod((double)(uint32_t)y[r], h0, q, qi);
-          } else if (P.X.csrc_f64) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) x[r] += fmulmod(as_f(y[r]), h0, q, qi);
-          } else {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) x[r] += fmulmod(u64_to_f(y[r]), h0, q, qi);
-          }
+          for (int r = 0; r < 16; ++r) x[r] += fmulmod(as_f(y[r]), h0, q, qi);
         }
 #pragma unroll
         for (int r = 0; r < 16; ++r) x[r] = fred(x[r], q, qi);
       } else {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) x[r] = u64_to_f(row[(int64_t)(kg + T * r) * N2 + c]);
+        for (int r = 0; r < 16; ++r) x[r] = u64_to_f(rb.ld(vs, r * us));
       }
       stages_strided<true>(x, tw, 1, bf);
 #pragma unroll
@@ -259,10 +301,10 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
       for (int r = 0; r < 16; ++r) x[r] = as_f(lds[(16 * kg + r) * C + cl]);
       stages_contig<LOGS, true>(x, tw, 1, kg, bf);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) row[(int64_t)(16 * kg + r) * N2 + c] = as_u(x[r]);
+      for (int r = 0; r < 16; ++r) rb.st(as_u(x[r]), vc, r * uc);
     } else {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) x[r] = as_f(row[(int64_t)(16 * kg + r) * N2 + c]);
+      for (int r = 0; r < 16; ++r) x[r] = as_f(rb.ld(vc, r * uc));
       stages_contig<LOGS, false>(x, tw, 1, kg, bf);
 #pragma unroll
       for (int r = 0; r < 16; ++r) lds[(16 * kg + r) * C + cl] = as_u(fred(x[r], q, qi));
@@ -273,11 +315,10 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
       const double sd = P.X.scalef ? P.X.scalef[p] : pc.ninv_d;
       if (P.X.out_f64) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-          row[(int64_t)(kg + T * r) * N2 + c] = as_u(fcanon_d(fmulmod(x[r], sd, q, qi), q, qi));
+        for (int r = 0; r < 16; ++r) rb.st(as_u(fcanon_d(fmulmod(x[r], sd, q, qi), q, qi)), vs, r * us);
       } else {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) row[(int64_t)(kg + T * r) * N2 + c] = fcanon(fmulmod(x[r], sd, q, qi), q, qi);
+        for (int r = 0; r < 16; ++r) rb.st(fcanon(fmulmod(x[r], sd, q, qi), q, qi), vs, r * us);
       }
     }
   } else {
@@ -295,12 +336,12 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
         for (int r = 0; r < 16; ++r) x[r] = 0;
 #pragma unroll 1
         for (int s = 0; s < P.X.ns; ++s) {
-          const uint64_t* ys = cs + ((int64_t)s << P.logN) + c;
+          const RowBuf ys(cs + ((int64_t)s << P.logN));
           const uint64_t w = h[2 * s], wsh = h[2 * s + 1];
-          const bool as_double = P.X.csrc_f64 && !((P.X.csplit >> s) & 1);
+          const bool as_double = !((P.X.csplit >> s) & 1);
           uint64_t y[16];
 #pragma unroll
-          for (int r = 0; r < 16; ++r) y[r] = ys[(int64_t)(kg + T * r) * N2];
+          for (int r = 0; r < 16; ++r) y[r] = ys.ld(vs, r * us);
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
@@ -311,7 +352,7 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
         }
       } else {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) x[r] = row[(int64_t)(kg + T * r) * N2 + c];
+        for (int r = 0; r < 16; ++r) x[r] = rb.ld(vs, r * us);
       }
       stages_strided<true>(x, tw, 1, bf);
 #pragma unroll
@@ -321,10 +362,10 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
       for (int r = 0; r < 16; ++r) x[r] = lds[(16 * kg + r) * C + cl];
       stages_contig<LOGS, true>(x, tw, 1, kg, bf);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) row[(int64_t)(16 * kg + r) * N2 + c] = x[r];
+      for (int r = 0; r < 16; ++r) rb.st(x[r], vc, r * uc);
     } else {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) x[r] = row[(int64_t)(16 * kg + r) * N2 + c];
+      for (int r = 0; r < 16; ++r) x[r] = rb.ld(vc, r * uc);
       stages_contig<LOGS, false>(x, tw, 1, kg, bf);
 #pragma unroll
       for (int r = 0; r < 16; ++r) lds[(16 * kg + r) * C + cl] = x[r];
@@ -335,7 +376,7 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
       const uint64_t sw = P.X.scale ? P.X.scale[2 * p] : pc.ninv;
       const uint64_t ssh = P.X.scale ? P.X.scale[2 * p + 1] : pc.ninv_sh;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) row[(int64_t)(kg + T * r) * N2 + c] = mul_shoup(x[r], sw, ssh, q);
+      for (int r = 0; r < 16; ++r) rb.st(mul_shoup(x[r], sw, ssh, q), vs, r * us);
     }
   }
 }

@@ -199,7 +199,6 @@ void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, 
     x.cstride = alpha;
     x.chat = c->t.modup + 2 * (size_t)((level * g.dnum + j) * g.mu_stride) + 2 * alpha;
     x.chatf = c->t.modup_f + 2 * (size_t)((level * g.dnum + j) * g.nqp) * alpha;
-    x.csrc_f64 = 1;
     for (int k = 0; k < sz; ++k) x.csplit |= (c->primes[lo + k] >> FP_MAX_BITS ? 1 : 0) << k;
     launch_ntt_ex(c->t, g.logN, rows(ext + (size_t)j * nx * N, count, ext_cs, 1, 0, (int)tgt.size(), tgt.data()),
                   false, x, s);
@@ -224,7 +223,6 @@ void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, 
     x.cstride = np;
     x.chat = c->t.moddown + 2 * np;
     x.chatf = c->t.moddown_f;
-    x.csrc_f64 = 1;
     for (int k = 0; k < np; ++k) x.csplit |= (c->primes[nq + k] >> FP_MAX_BITS ? 1 : 0) << k;
     x.has_epi = 1;
     KsEpi& e = x.epi;
