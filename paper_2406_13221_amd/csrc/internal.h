@@ -62,6 +62,25 @@ struct NttExtra {
   // forward, last pass: key-switch combine instead of a plain store
   int has_epi;
   KsEpi epi;
+  // forward: run the column pass only; the row pass is done by launch_ks_rows
+  int cols_only;
+};
+
+// The forward row pass of every digit's ModUp extension, fused with the key inner
+// product (hybrid key switching):
+//   acc[ct][part][x] = sum_j v_j[x] * key[j][part][x]  mod p_x,  x over Q_l then P,
+// where v_j[x] is the in-digit limb x of the input (NTT form, read through X -> X^galois)
+// when x lies in digit j, else row e of digit j's extension after its column pass.
+struct KsRows {
+  const uint64_t* ext;  // row e of digit j, ciphertext ct: ext + ct*ext_cs + j*ext_ds + e*N
+  int64_t ext_cs, ext_ds;
+  CtV d;                // limb x of ciphertext ct: d.d + ct*d.cs + x*N
+  uint64_t galois;
+  const uint64_t* key;  // [digit][part: b, a][nqp][N]
+  uint64_t* acc;        // [ct][part][nl + np][N]
+  int64_t count;
+  int nl, nq, np, alpha, nd;
+  uint64_t fp_primes;   // bit i: prime i has at most FP_MAX_BITS bits (FP64 path)
 };
 
 // Device-side table pointers (inside the caller's table buffer).
@@ -98,6 +117,8 @@ void ntt_split_set(bool inverse, int log2N, int la);
 int rows_variant_set(int which, int value);
 int rows_variant_get(int which);
 int launch_ntt_ex(const DevTables& t, int log2N, const RowSet& rows, bool inverse, const NttExtra& x, hipStream_t s);
+// the fused row pass + inner product above; the pass split is the forward one in use
+int launch_ks_rows(const DevTables& t, int log2N, const KsRows& k, hipStream_t s);
 
 void k_add_launch(const Geo& g, const DevTables& t, CtV a, CtV b, CtV out, int64_t count, int n_poly, int nl, bool sub,
                   hipStream_t s);
@@ -122,8 +143,6 @@ void k_rescale_spread_launch(const Geo& g, const DevTables& t, const uint64_t* l
                              int level, hipStream_t s);
 void k_rescale_combine_launch(const Geo& g, const DevTables& t, CtV in, const uint64_t* spread, CtV out, int64_t count,
                               int n_poly, int level, hipStream_t s);
-void k_ks_inner_launch(const Geo& g, const DevTables& t, CtV d, const uint64_t* ext, int64_t ext_cs, int64_t ext_ds,
-                       const uint64_t* key, uint64_t* acc, int64_t count, int level, uint64_t galois, hipStream_t s);
 // out = [addend +] base + KS result; with galois != 1 base0 is gathered through X -> X^galois
 // sampling / encryption
 enum { PUR_SK = 1, PUR_PK_A = 2, PUR_PK_E = 3, PUR_KSK_A = 4, PUR_KSK_E = 5, PUR_ENC_V = 6, PUR_ENC_E0 = 7, PUR_ENC_E1 = 8 };

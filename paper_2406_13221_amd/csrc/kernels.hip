@@ -1,5 +1,6 @@
-// Elementwise, key inner-product, rescale, automorphism, sampling and encryption kernels
-// (gfx950).  The base conversions of key switching live in ntt.hip, fused into NTT passes.
+// Elementwise, rescale, automorphism, sampling and encryption kernels
+// (gfx950).  The base conversions and the key inner product of key switching live in
+// ntt.hip, fused into NTT passes.
 //
 // All data are limb-major uint64 rows of N residues.  Elementwise kernels
 // give each thread two adjacent coefficients (one 16-byte access per
@@ -303,114 +304,6 @@ __global__ void __launch_bounds__(EW_THREADS) k_rescale_combine(const PrimeConst
   U2 y = ld2(spread + ((r2 * level) << logN) + off);
   st2(out.d + ct * out.cs + p * out.ps + off, mul_shoup(submod(x.a, y.a, q), c2[0], c2[1], q),
       mul_shoup(submod(x.b, y.b, q), c2[0], c2[1], q));
-}
-
-// acc[ct][part][x] = sum_j v_j[x] * key_j[part][prime(x)], x over Q rows 0..l then P rows;
-// v_j[x] = d[x] for x in digit j, else the ModUp row of digit j.  One thread owns two
-// coefficients of one extended row of KS_CTP ciphertexts: the key values are loaded once
-// and used for each of them.  The grid is XCD-aware: workgroup b runs on XCD b mod 8, and
-// the workgroups that share one (row, chunk) tile of the key are given consecutive slots
-// on the same XCD, so the key tile is fetched from HBM once per launch and then served by
-// that XCD's L2.  With galois != 1, d is the input before the automorphism X -> X^galois
-// and the in-digit rows are gathered through it.
-constexpr int KS_MAX_DIGITS = 8;
-constexpr int KS_CTP = 2;
-template <int ND>  // digits at this level
-__global__ void __launch_bounds__(EW_THREADS) k_ks_inner(const PrimeConst* pc, CtV d, const uint64_t* ext, int64_t ext_cs,
-                                                          int64_t ext_ds, const uint64_t* key, uint64_t* acc, int logN,
-                                                          int level, int nq, int np, int alpha, int64_t count,
-                                                          uint64_t galois) {
-  const int chunks = (1 << logN) / EW_CHUNK;
-  const int nl = level + 1, nx = nl + np, nqp = nq + np;
-  const int64_t ngrp = (count + KS_CTP - 1) / KS_CTP;
-  const int64_t bid = blockIdx.x;
-  const int64_t rest = bid >> 3;
-  const int64_t grp = rest % ngrp;
-  const int64_t tile = (rest / ngrp) * 8 + (bid & 7);
-  const int ch = (int)(tile % chunks);
-  const int x = (int)(tile / chunks);
-  const int c = ch * EW_CHUNK + threadIdx.x * 2;
-  const int gp = x < nl ? x : nq + (x - nl);
-  const PrimeConst P = pc[gp];
-  U2 kb[ND], ka[ND];
-#pragma unroll
-  for (int j = 0; j < ND; ++j)
-    {
-      const uint64_t* kp = key + (((int64_t)j * 2 * nqp + gp) << logN) + c;
-      kb[j] = ld2(kp);
-      ka[j] = ld2(kp + ((int64_t)nqp << logN));
-    }
-  const int64_t ct0 = grp * KS_CTP;
-  const int nct = (int)min((int64_t)KS_CTP, count - ct0);
-  U2 v[KS_CTP][ND];
-#pragma unroll
-  for (int u = 0; u < KS_CTP; ++u) {
-    if (u >= nct) break;
-    const int64_t ct = ct0 + u;
-#pragma unroll
-    for (int j = 0; j < ND; ++j) {
-      {
-        int lo = j * alpha, hi = min(lo + alpha, nl);
-        if (x >= lo && x < hi) {
-          const uint64_t* row = d.d + ct * d.cs + ((int64_t)x << logN);
-          if (galois != 1) {
-            v[u][j].a = row[galois_src(c, galois, logN)];
-            v[u][j].b = row[galois_src(c + 1, galois, logN)];
-          } else {
-            v[u][j] = ld2(row + c);
-          }
-        } else {
-          int e = x < lo ? x : x - (hi - lo);
-          v[u][j] = ld2(ext + ct * ext_cs + j * ext_ds + ((int64_t)e << logN) + c);
-        }
-      }
-    }
-  }
-  if (P.k <= FP_MAX_BITS) {
-#pragma clang fp contract(off)
-    const double q = P.qd, qi = P.qinv;
-    double kbf[ND][2], kaf[ND][2];
-#pragma unroll
-    for (int j = 0; j < ND; ++j)
-      {
-        kbf[j][0] = u64_to_f(kb[j].a), kbf[j][1] = u64_to_f(kb[j].b);
-        kaf[j][0] = u64_to_f(ka[j].a), kaf[j][1] = u64_to_f(ka[j].b);
-      }
-#pragma unroll
-    for (int u = 0; u < KS_CTP; ++u) {
-      if (u >= nct) break;
-      double s0a = 0, s0b = 0, s1a = 0, s1b = 0;
-#pragma unroll
-      for (int j = 0; j < ND; ++j)
-        {
-          double va = u64_to_f(v[u][j].a), vb = u64_to_f(v[u][j].b);
-          s0a += fmulmod(va, kbf[j][0], q, qi);
-          s0b += fmulmod(vb, kbf[j][1], q, qi);
-          s1a += fmulmod(va, kaf[j][0], q, qi);
-          s1b += fmulmod(vb, kaf[j][1], q, qi);
-        }
-      uint64_t* o = acc + (ct0 + u) * ((int64_t)(2 * nx) << logN) + ((int64_t)x << logN) + c;
-      st2(o, fcanon(s0a, q, qi), fcanon(s0b, q, qi));
-      st2(o + ((int64_t)nx << logN), fcanon(s1a, q, qi), fcanon(s1b, q, qi));
-    }
-    return;
-  }
-#pragma unroll
-  for (int u = 0; u < KS_CTP; ++u) {
-    if (u >= nct) break;
-    uint64_t s0a = 0, s0b = 0, s1a = 0, s1b = 0;
-#pragma unroll
-    for (int j = 0; j < ND; ++j)
-      {
-        s0a = addmod(s0a, mulmod(v[u][j].a, kb[j].a, P), P.q);
-        s0b = addmod(s0b, mulmod(v[u][j].b, kb[j].b, P), P.q);
-        s1a = addmod(s1a, mulmod(v[u][j].a, ka[j].a, P), P.q);
-        s1b = addmod(s1b, mulmod(v[u][j].b, ka[j].b, P), P.q);
-      }
-    uint64_t* o = acc + (ct0 + u) * ((int64_t)(2 * nx) << logN) + ((int64_t)x << logN) + c;
-    st2(o, s0a, s0b);
-    st2(o + ((int64_t)nx << logN), s1a, s1b);
-  }
 }
 
 // ------------------------------------------------------------------ ChaCha20 (RFC 8439) and samplers
@@ -731,23 +624,6 @@ void k_rescale_combine_launch(const Geo& g, const DevTables& t, CtV in, const ui
                               int n_poly, int level, hipStream_t s) {
   int64_t n = count * n_poly * level * CHUNKS(g);
   if (n) LAUNCH(k_rescale_combine, n, s, t.pc, t.rescale, in, spread, out, g.logN, level, n_poly, g.n_q);
-}
-void k_ks_inner_launch(const Geo& g, const DevTables& t, CtV d, const uint64_t* ext, int64_t ext_cs, int64_t ext_ds,
-                       const uint64_t* key, uint64_t* acc, int64_t count, int level, uint64_t galois, hipStream_t s) {
-  int nx = level + 1 + g.n_p;
-  // tiles (row x chunk) are a multiple of 8 because N/512 is; KS_CTP ciphertexts per workgroup
-  int64_t n = (count + KS_CTP - 1) / KS_CTP * (int64_t)nx * CHUNKS(g);
-  const int nd = (level + g.alpha) / g.alpha;
-  if (!n) return;
-  switch (nd) {
-#define HEQG_KSI(D)                                                                                              \
-  case D:                                                                                                        \
-    LAUNCH(k_ks_inner<D>, n, s, t.pc, d, ext, ext_cs, ext_ds, key, acc, g.logN, level, g.n_q, g.n_p, g.alpha, count, \
-           galois);                                                                                              \
-    break;
-    HEQG_KSI(1) HEQG_KSI(2) HEQG_KSI(3) HEQG_KSI(4) HEQG_KSI(5) HEQG_KSI(6) HEQG_KSI(7) HEQG_KSI(8)
-#undef HEQG_KSI
-  }
 }
 void k_sample_small_launch(uint64_t seed, uint64_t purpose, uint64_t obj_first, int64_t count, int N, int kind,
                            int64_t* out, hipStream_t s) {

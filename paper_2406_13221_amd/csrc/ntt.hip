@@ -40,16 +40,21 @@ struct __align__(16) U2 {
 // strided access needs no per-access vector address arithmetic.  The third word is the
 // gfx9 descriptor format for untyped access; with stride 0 and this record count the
 // range check never triggers for the offsets used here.
+// p (uniform across the workgroup) from the first lane: in SGPRs even where the compiler
+// computed it in vector registers
+template <class W>
+__device__ __forceinline__ W* uniform_ptr(W* p) {
+  const uint64_t a = reinterpret_cast<uintptr_t>(p);
+  const uint64_t u = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(a >> 32)) << 32) |
+                     (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+  return reinterpret_cast<W*>(u);
+}
+
 struct RowBuf {
   __amdgpu_buffer_rsrc_t r;
-  // base must be uniform across the workgroup; reading it from the first lane puts it
-  // in SGPRs even where the compiler computed it in vector registers
-  __device__ __forceinline__ explicit RowBuf(const void* base) {
-    const uint64_t a = reinterpret_cast<uintptr_t>(base);
-    const uint64_t u = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(a >> 32)) << 32) |
-                       (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
-    r = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(u), 0, 0x7fffffff, 0x00020000);
-  }
+  // base must be uniform across the workgroup
+  __device__ __forceinline__ explicit RowBuf(const void* base)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(uniform_ptr(base)), 0, 0x7fffffff, 0x00020000)) {}
   __device__ __forceinline__ uint64_t ld(uint32_t v, uint32_t u) const {
     const auto x = __builtin_amdgcn_raw_buffer_load_b64(r, v, u, 0);
     return ((uint64_t)x[1] << 32) | x[0];
@@ -644,19 +649,204 @@ __global__ void __launch_bounds__(256) k_ntt_rows(NttParams P) {
     rows_body<LOGS, FWD, COAL, FUSE, false>(P, src, inrow, ab, ii, p, b, l, fl);
 }
 
+// ------------------------------------------------------------------ pass B fused with the key inner product
+// One workgroup: ciphertext ct, output limb x (prime gp), 4096 consecutive residues.  For each
+// digit it completes the forward transform of the extension row (as the plain row pass, ending
+// in the coalesced {j + T*r} layout) or gathers the in-digit input limb, and multiplies by both
+// key parts into register accumulators; only the two sums are stored.  The workgroups of one
+// (x, tile) run on one XCD, so its key tiles are fetched once per launch.
+struct KsrParams {
+  KsRows K;
+  const U2* tw;
+  const double* twf;
+  const PrimeConst* pc;
+  int logN, tiles;
+  int nxs;                     // output limbs of this launch (one arithmetic path) ...
+  int xs[HEQG_MAX_PRIMES];     // ... and their indices x
+};
+
+template <int LOGS, bool FP>
+__device__ __forceinline__ void ksr_body(const KsrParams& P, int64_t ct, int x, int gp, int b, uint64_t* l, int fl) {
+  constexpr int S = 1 << LOGS, T = S / 16;
+  const KsRows& K = P.K;
+  const int jt = threadIdx.x % T;
+  const PrimeConst pc = P.pc[gp];
+  const int N1 = 1 << (P.logN - LOGS);
+  const int64_t base = N1 + b;
+  const int64_t pos0 = (int64_t)b * S;
+  const int nx = K.nl + K.np, nqp = K.nq + K.np;
+  const uint64_t* own = K.d.d + ct * K.d.cs + ((int64_t)x << P.logN);
+  const uint64_t* ex = K.ext + ct * K.ext_cs + pos0 + jt;
+  const uint64_t* key = K.key + ((int64_t)gp << P.logN) + pos0 + jt;
+  const int64_t kpart = (int64_t)nqp << P.logN, kdig = 2 * kpart;
+  uint64_t* out = K.acc + ct * ((int64_t)(2 * nx) << P.logN) + ((int64_t)x << P.logN) + pos0 + jt;
+  // a Q limb lies in exactly one digit, whose value is the input limb itself; the other
+  // digits (all of them for a P limb) are extension rows
+  const bool inq = x < K.nl;
+  const int jo = inq ? x / K.alpha : K.nd;
+  const int next = K.nd - (inq ? 1 : 0);
+  // row of extension k (k < next): digit j = k, or k + 1 from the in-digit one on
+  auto ext_row = [&](int k) {
+    const int j = k + (k >= jo ? 1 : 0);
+    const int lo = j * K.alpha, hi = min(lo + K.alpha, K.nl);
+    const int e = x < lo ? x : x - (hi - lo);
+    return ex + j * K.ext_ds + ((int64_t)e << P.logN);
+  };
+  if (FP) {
+#pragma clang fp contract(off)
+    const double q = pc.qd, qi = pc.qinv;
+    const double* tw = uniform_ptr(P.twf + ((int64_t)gp << P.logN));
+    auto bf = [&](double& X, double& Y, double w) { ct_f(X, Y, w, q, qi); };
+    // each product |.| <= q/2 + 1, at most 8 per sum: exact
+    double s0[16], s1[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) s0[r] = s1[r] = 0.0;
+    // |v| < 9q (input of at most 16 lazy stages): inside fmulmod's range
+    // one key part at a time: 16 key words in flight instead of 32 (register pressure)
+    auto mac = [&](const double (&v)[16], int j) {
+      const uint64_t* kb = key + j * kdig;
+      uint64_t w[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) w[r] = kb[T * r];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s0[r] += fmulmod(v[r], u64_to_f(w[r]), q, qi);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) w[r] = kb[kpart + T * r];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s1[r] += fmulmod(v[r], u64_to_f(w[r]), q, qi);
+    };
+    if (inq) {
+      uint64_t u[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) u[r] = ld_in(own, pos0 + jt + T * r, K.galois, P.logN);
+      __builtin_amdgcn_sched_barrier(0);
+      double v[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = u64_to_f(u[r]);
+      mac(v, jo);
+    }
+#pragma unroll 1
+    for (int k = 0; k < next; ++k) {
+      const uint64_t* src = ext_row(k);
+      // twiddles and LDS addresses are recomputed per extension rather than held in ~50
+      // registers across the loop: the opaque copies keep the compiler from hoisting them
+      const double* twk = tw;
+      int jk = jt, flk = fl;
+      int64_t bk = base;
+      asm volatile("" : "+s"(twk), "+v"(jk), "+v"(flk), "+v"(bk));
+      double v[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = as_f(src[T * r]);
+      stages_strided<true>(v, twk, bk, bf);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) l[flk ^ swz(jk + T * r)] = as_u(v[r]);
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = as_f(l[flk ^ swz(16 * jk + r)]);
+      stages_contig<LOGS, true>(v, twk, bk, jk, bf);
+      // only this thread reads these 16 words in this exchange: no barrier before rewriting them
+#pragma unroll
+      for (int r = 0; r < 16; ++r) l[flk ^ swz(16 * jk + r)] = as_u(v[r]);
+      __syncthreads();
+      // the words read here are rewritten only by this thread (next extension's first exchange)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = as_f(l[flk ^ swz(jk + T * r)]);
+      mac(v, k + (k >= jo ? 1 : 0));
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) out[T * r] = fcanon(s0[r], q, qi);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) out[((int64_t)nx << P.logN) + T * r] = fcanon(s1[r], q, qi);
+  } else {
+    const uint64_t q = pc.q, two_q = 2 * q;
+    const U2* tw = uniform_ptr(P.tw + ((int64_t)gp << P.logN));
+    auto bf = [&](uint64_t& X, uint64_t& Y, U2 w) { ct_bfly(X, Y, w, q, two_q); };
+    uint64_t s0[16], s1[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) s0[r] = s1[r] = 0;
+    auto mac = [&](const uint64_t (&v)[16], int j) {
+      const uint64_t* kb = key + j * kdig;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        s0[r] = addmod(s0[r], mulmod(v[r], kb[T * r], pc), q);
+        s1[r] = addmod(s1[r], mulmod(v[r], kb[kpart + T * r], pc), q);
+      }
+    };
+    if (inq) {
+      uint64_t v[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = ld_in(own, pos0 + jt + T * r, K.galois, P.logN);
+      __builtin_amdgcn_sched_barrier(0);
+      mac(v, jo);
+    }
+#pragma unroll 1
+    for (int k = 0; k < next; ++k) {
+      const uint64_t* src = ext_row(k);
+      const U2* twk = tw;
+      int jk = jt, flk = fl;
+      int64_t bk = base;
+      asm volatile("" : "+s"(twk), "+v"(jk), "+v"(flk), "+v"(bk));
+      uint64_t v[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = src[T * r];
+      stages_strided<true>(v, twk, bk, bf);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) l[flk ^ swz(jk + T * r)] = v[r];
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = l[flk ^ swz(16 * jk + r)];
+      stages_contig<LOGS, true>(v, twk, bk, jk, bf);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const uint64_t w = v[r] >= two_q ? v[r] - two_q : v[r];
+        l[flk ^ swz(16 * jk + r)] = w >= q ? w - q : w;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = l[flk ^ swz(jk + T * r)];
+      mac(v, k + (k >= jo ? 1 : 0));
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) out[T * r] = s0[r];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) out[((int64_t)nx << P.logN) + T * r] = s1[r];
+  }
+}
+
+// FP: the output limbs' primes take the FP64 path; its register need (168) allows three
+// waves per SIMD.
+template <int LOGS, bool FP>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FP ? 3 : 1)))
+k_ntt_rows_ks(KsrParams P) {
+  static_assert(LOGS >= 6 && LOGS <= 8, "16 residues per thread cover 4 strided + 4 contiguous stages");
+  constexpr int S = 1 << LOGS, T = S / 16, R = 256 / T;
+  __shared__ uint64_t lds[4096];
+  const KsRows& K = P.K;
+  int64_t unit, ct;
+  xcd_map(blockIdx.x, K.count, (int64_t)P.nxs * P.tiles, unit, ct);
+  const int tile = (int)(unit % P.tiles);
+  const int x = P.xs[unit / P.tiles];
+  const int gp = x < K.nl ? x : K.nq + (x - K.nl);
+  const int rl = threadIdx.x / T;
+  ksr_body<LOGS, FP>(P, ct, x, gp, tile * R + rl, lds + rl * S, (rl & 1) << 4);
+}
+
 // ------------------------------------------------------------------ launch
-// Sampled launch timing of two kernel classes: 0 = the plain forward row pass, 1 = the
-// fused base-conversion column pass (ModUp / ModDown conversion + first forward pass).
+// Sampled launch timing of three kernel classes: 0 = the plain forward row pass, 1 = the
+// fused base-conversion column pass (ModUp / ModDown conversion + first forward pass),
+// 2 = the ModUp row pass fused with the key inner product.
 struct ProfState {
   std::mutex mu;
   int every = 0;
-  int64_t seen[2] = {0, 0};
+  int64_t seen[3] = {0, 0, 0};
   struct Rec {
     hipEvent_t a, b;
     int64_t rows, src_rows;
     double ops;
   };
-  std::vector<Rec> recs[2];
+  std::vector<Rec> recs[3];
 };
 ProfState& prof() {
   static ProfState p;
@@ -744,6 +934,7 @@ void run_ntt(NttParams P, int64_t rows, bool inverse, const U2* twf, const U2* t
     } else {
       hipLaunchKernelGGL((k_ntt_cols<LA, true, false>), dim3((unsigned)(rows * tilesA)), dim3(256), 0, s, P);
     }
+    if (P.X.cols_only) return;
     P.tiles = tilesB;
     ProfSample sr;
     if (!P.X.has_epi) sr.begin(0, rows, 0, 0.0, s);
@@ -787,14 +978,14 @@ extern "C" int heqg_prof_start(int every) {
     }
     v.clear();
   }
-  ps.seen[0] = ps.seen[1] = 0;
+  ps.seen[0] = ps.seen[1] = ps.seen[2] = 0;
   ps.every = every > 0 ? every : 1;
   return 0;
 }
 
 extern "C" int heqg_prof_stop(int kernel, double* avg_us, int64_t* launches, double* avg_rows,
                               double* avg_src_rows, double* avg_ops) {
-  if (kernel < 0 || kernel > 1) return -1;
+  if (kernel < 0 || kernel > 2) return -1;
   ProfState& ps = prof();
   std::lock_guard<std::mutex> g(ps.mu);
   ps.every = 0;
@@ -858,6 +1049,48 @@ int launch_ntt_ex(const DevTables& t, int log2N, const RowSet& rs, bool inverse,
     default: return -1;
   }
 #undef HEQG_RUN
+  return 0;
+}
+
+template <int LB>
+void run_ks_rows(KsrParams P, hipStream_t s) {
+  const KsRows& K = P.K;
+  const int nx = K.nl + K.np;
+  for (int fp = 1; fp >= 0; --fp) {
+    P.nxs = 0;
+    for (int x = 0; x < nx; ++x) {
+      const int gp = x < K.nl ? x : K.nq + (x - K.nl);
+      if ((int)((K.fp_primes >> gp) & 1) == fp) P.xs[P.nxs++] = x;
+    }
+    if (!P.nxs) continue;
+    const unsigned blocks = (unsigned)(K.count * P.nxs * P.tiles);
+    ProfSample sp;
+    // rows moved: nd inputs and 2 outputs per (ct, x); the key rows, read once
+    if (fp) sp.begin(2, K.count * P.nxs * (K.nd + 2), (int64_t)K.nd * 2 * P.nxs, 0.0, s);
+    if (fp)
+      hipLaunchKernelGGL((k_ntt_rows_ks<LB, true>), dim3(blocks), dim3(256), 0, s, P);
+    else
+      hipLaunchKernelGGL((k_ntt_rows_ks<LB, false>), dim3(blocks), dim3(256), 0, s, P);
+    sp.end(s);
+  }
+}
+
+int launch_ks_rows(const DevTables& t, int log2N, const KsRows& k, hipStream_t s) {
+  if (k.count <= 0) return 0;
+  if (k.nd < 1 || k.nd > 8 || log2N < 12 || log2N > 16) return -1;
+  KsrParams P;
+  P.K = k;
+  P.tw = reinterpret_cast<const U2*>(t.tw_fwd);
+  P.twf = t.tw_fwd_f;
+  P.pc = t.pc;
+  P.logN = log2N;
+  P.tiles = (1 << log2N) / 4096;  // a workgroup holds 4096 residues of one row
+  switch (log2N - ntt_split_get(false, log2N)) {
+    case 6: run_ks_rows<6>(P, s); break;
+    case 7: run_ks_rows<7>(P, s); break;
+    case 8: run_ks_rows<8>(P, s); break;
+    default: return -1;
+  }
   return 0;
 }
 

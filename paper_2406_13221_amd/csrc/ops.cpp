@@ -185,7 +185,7 @@ void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, 
     x.out_f64 = 1;
     launch_ntt_ex(c->t, g.logN, rows_q(ycoef, count, (int64_t)nl * N, 1, 0, nl, 0), true, x, s);
   }
-  // 2. ModUp per digit fused into the forward NTT of its target rows
+  // 2. ModUp per digit fused into the first forward pass of its target rows
   for (int j = 0; j < nd; ++j) {
     int lo = j * alpha, sz = std::min(alpha, nl - lo);
     std::vector<int> tgt;
@@ -200,11 +200,30 @@ void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, 
     x.chat = c->t.modup + 2 * (size_t)((level * g.dnum + j) * g.mu_stride) + 2 * alpha;
     x.chatf = c->t.modup_f + 2 * (size_t)((level * g.dnum + j) * g.nqp) * alpha;
     for (int k = 0; k < sz; ++k) x.csplit |= (c->primes[lo + k] >> FP_MAX_BITS ? 1 : 0) << k;
+    x.cols_only = 1;
     launch_ntt_ex(c->t, g.logN, rows(ext + (size_t)j * nx * N, count, ext_cs, 1, 0, (int)tgt.size(), tgt.data()),
                   false, x, s);
   }
-  // 3. inner product with the key over Q_l and P
-  k_ks_inner_launch(g, c->t, d, ext, ext_cs, (int64_t)nx * N, key, acc, count, level, galois, s);
+  // 3. second forward pass of every digit's extension fused with the inner product with the
+  //    key over Q_l and P
+  {
+    KsRows k{};
+    k.ext = ext;
+    k.ext_cs = ext_cs;
+    k.ext_ds = (int64_t)nx * N;
+    k.d = d;
+    k.galois = galois;
+    k.key = key;
+    k.acc = acc;
+    k.count = count;
+    k.nl = nl;
+    k.nq = nq;
+    k.np = np;
+    k.alpha = alpha;
+    k.nd = nd;
+    for (int i = 0; i < g.nqp; ++i) k.fp_primes |= (c->primes[i] >> FP_MAX_BITS ? 0ull : 1ull) << i;
+    launch_ks_rows(c->t, g.logN, k, s);
+  }
   // 4. ModDown: INTT of the P rows of both parts, scaled by (P/p)^-1 ...
   {
     NttExtra x{};
