@@ -80,7 +80,6 @@ struct KsRows {
   uint64_t* acc;        // [ct][part][nl + np][N]
   int64_t count;
   int nl, nq, np, alpha, nd;
-  uint64_t fp_primes;   // bit i: prime i has at most FP_MAX_BITS bits (FP64 path)
 };
 
 // Device-side table pointers (inside the caller's table buffer).

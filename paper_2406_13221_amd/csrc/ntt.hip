@@ -661,8 +661,6 @@ struct KsrParams {
   const double* twf;
   const PrimeConst* pc;
   int logN, tiles;
-  int nxs;                     // output limbs of this launch (one arithmetic path) ...
-  int xs[HEQG_MAX_PRIMES];     // ... and their indices x
 };
 
 template <int LOGS, bool FP>
@@ -815,22 +813,24 @@ __device__ __forceinline__ void ksr_body(const KsrParams& P, int64_t ct, int x, 
   }
 }
 
-// FP: the output limbs' primes take the FP64 path; its register need (168) allows three
-// waves per SIMD.
-template <int LOGS, bool FP>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FP ? 3 : 1)))
-k_ntt_rows_ks(KsrParams P) {
+// Each workgroup takes the arithmetic path of its output limb's prime.  Three waves per
+// SIMD (168 registers) hold both paths with one register spilled outside the digit loop.
+template <int LOGS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_ntt_rows_ks(KsrParams P) {
   static_assert(LOGS >= 6 && LOGS <= 8, "16 residues per thread cover 4 strided + 4 contiguous stages");
   constexpr int S = 1 << LOGS, T = S / 16, R = 256 / T;
   __shared__ uint64_t lds[4096];
   const KsRows& K = P.K;
   int64_t unit, ct;
-  xcd_map(blockIdx.x, K.count, (int64_t)P.nxs * P.tiles, unit, ct);
+  xcd_map(blockIdx.x, K.count, (int64_t)(K.nl + K.np) * P.tiles, unit, ct);
   const int tile = (int)(unit % P.tiles);
-  const int x = P.xs[unit / P.tiles];
+  const int x = (int)(unit / P.tiles);
   const int gp = x < K.nl ? x : K.nq + (x - K.nl);
   const int rl = threadIdx.x / T;
-  ksr_body<LOGS, FP>(P, ct, x, gp, tile * R + rl, lds + rl * S, (rl & 1) << 4);
+  if (P.pc[gp].k <= FP_MAX_BITS)
+    ksr_body<LOGS, true>(P, ct, x, gp, tile * R + rl, lds + rl * S, (rl & 1) << 4);
+  else
+    ksr_body<LOGS, false>(P, ct, x, gp, tile * R + rl, lds + rl * S, (rl & 1) << 4);
 }
 
 // ------------------------------------------------------------------ launch
@@ -1053,26 +1053,14 @@ int launch_ntt_ex(const DevTables& t, int log2N, const RowSet& rs, bool inverse,
 }
 
 template <int LB>
-void run_ks_rows(KsrParams P, hipStream_t s) {
+void run_ks_rows(const KsrParams& P, hipStream_t s) {
   const KsRows& K = P.K;
   const int nx = K.nl + K.np;
-  for (int fp = 1; fp >= 0; --fp) {
-    P.nxs = 0;
-    for (int x = 0; x < nx; ++x) {
-      const int gp = x < K.nl ? x : K.nq + (x - K.nl);
-      if ((int)((K.fp_primes >> gp) & 1) == fp) P.xs[P.nxs++] = x;
-    }
-    if (!P.nxs) continue;
-    const unsigned blocks = (unsigned)(K.count * P.nxs * P.tiles);
-    ProfSample sp;
-    // rows moved: nd inputs and 2 outputs per (ct, x); the key rows, read once
-    if (fp) sp.begin(2, K.count * P.nxs * (K.nd + 2), (int64_t)K.nd * 2 * P.nxs, 0.0, s);
-    if (fp)
-      hipLaunchKernelGGL((k_ntt_rows_ks<LB, true>), dim3(blocks), dim3(256), 0, s, P);
-    else
-      hipLaunchKernelGGL((k_ntt_rows_ks<LB, false>), dim3(blocks), dim3(256), 0, s, P);
-    sp.end(s);
-  }
+  ProfSample sp;
+  // rows moved: nd inputs and 2 outputs per (ct, x); the key rows, read once
+  sp.begin(2, K.count * nx * (K.nd + 2), (int64_t)K.nd * 2 * nx, 0.0, s);
+  hipLaunchKernelGGL((k_ntt_rows_ks<LB>), dim3((unsigned)(K.count * nx * P.tiles)), dim3(256), 0, s, P);
+  sp.end(s);
 }
 
 int launch_ks_rows(const DevTables& t, int log2N, const KsRows& k, hipStream_t s) {

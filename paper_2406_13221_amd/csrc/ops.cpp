@@ -221,7 +221,6 @@ void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, 
     k.np = np;
     k.alpha = alpha;
     k.nd = nd;
-    for (int i = 0; i < g.nqp; ++i) k.fp_primes |= (c->primes[i] >> FP_MAX_BITS ? 0ull : 1ull) << i;
     launch_ks_rows(c->t, g.logN, k, s);
   }
   // 4. ModDown: INTT of the P rows of both parts, scaled by (P/p)^-1 ...
