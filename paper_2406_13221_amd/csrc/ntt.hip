@@ -118,9 +118,20 @@ __device__ __forceinline__ void gs_f(double& X, double& Y, double w, double q, d
   Y = fmulmod(d, w, q, qi);
 }
 
+// Read-only table data through the constant address space: where the index is uniform
+// across the workgroup the compiler can use scalar loads (batched, off the vector memory
+// path).  Only for tables no kernel writes.
+template <class W>
+using cptr = const __attribute__((address_space(4))) W*;
+template <class W>
+__device__ __forceinline__ cptr<W> to_const(const W* p) {
+  return (cptr<W>)p;
+}
+
 // Stages on layout {j + T*r}: local stages 0..3 (distance 8T..T), twiddle base*2^s + (r >> (4-s)).
-template <bool FWD, typename V, typename TW, typename BF>
-__device__ __forceinline__ void stages_strided(V (&x)[16], const TW* tw, int64_t base, BF bf) {
+// TWP: pointer to the twiddles (generic, or constant address space where base is uniform).
+template <bool FWD, typename V, typename TWP, typename BF>
+__device__ __forceinline__ void stages_strided(V (&x)[16], TWP tw, int64_t base, BF bf) {
   if (FWD) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -257,7 +268,7 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
     if (FWD) {
       if (CONV) {
         // sum of at most 2*16 products, each |.| <= q/2 + 1: exact, then reduced to |x| <= q/2 + 1
-        const double* h = P.X.chatf + 2 * (int64_t)p * P.X.cstride;
+        const cptr<double> h = to_const(P.X.chatf + 2 * (int64_t)p * P.X.cstride);
 #pragma unroll
         for (int r = 0; r < 16; ++r) x[r] = 0.0;
         const uint32_t all = (1u << P.X.ns) - 1;
@@ -298,7 +309,7 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
 #pragma unroll
         for (int r = 0; r < 16; ++r) x[r] = u64_to_f(rb.ld(vs, r * us));
       }
-      stages_strided<true>(x, tw, 1, bf);
+      stages_strided<true>(x, to_const(tw), 1, bf);
 #pragma unroll
       for (int r = 0; r < 16; ++r) lds[(kg + T * r) * C + cl] = as_u(x[r]);
       __syncthreads();
@@ -316,7 +327,7 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < 16; ++r) x[r] = as_f(lds[(kg + T * r) * C + cl]);
-      stages_strided<false>(x, tw, 1, bf);
+      stages_strided<false>(x, to_const(tw), 1, bf);
       const double sd = P.X.scalef ? P.X.scalef[p] : pc.ninv_d;
       if (P.X.out_f64) {
 #pragma unroll
@@ -336,7 +347,7 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
     if (FWD) {
       if (CONV) {
         // lazy sum kept in [0, 2q)
-        const uint64_t* h = P.X.chat + 2 * (int64_t)p * P.X.cstride;
+        const cptr<uint64_t> h = to_const(P.X.chat + 2 * (int64_t)p * P.X.cstride);
 #pragma unroll
         for (int r = 0; r < 16; ++r) x[r] = 0;
 #pragma unroll 1
