@@ -212,6 +212,7 @@ def main():
     t1 = time.perf_counter()
     conv_us, conv_n, conv_rows, conv_src, conv_ops = heqg.prof_stop(1)
     avg_us, n_sampled, avg_rows, _, _ = heqg.prof_stop(0)
+    ks_us, ks_n, ks_rows, ks_keyrows, _ = heqg.prof_stop(2)
     ms_per_step = (t1 - t0) * 1000.0 / args.steps
     upd = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps / 1000.0
     ref = sum(e[1].elapsed_time(e[2]) for e in ev) / args.steps / 1000.0
@@ -336,6 +337,16 @@ def main():
                         "avg_launch_us": round(avg_us, 2), "sampled_launches": n_sampled,
                         "avg_rows_per_launch": round(avg_rows, 2)}
 
+    # the ModUp row pass fused with the key inner product: ciphertext rows read and written plus the
+    # switching-key rows, each read once per launch
+    ks_bytes = 8.0 * N * (ks_rows + ks_keyrows)
+    ks_rate = ks_bytes / (ks_us * 1e-6) / 1e9 if ks_us > 0 else 0.0
+    ks_row_roofline = {"bound": "hbm", "achieved": round(ks_rate, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(ks_rate / HBM_PEAK_GBS, 4),
+                       "kernel": "k_ntt_rows_ks<8> (ModUp second forward pass fused with the key inner product)",
+                       "algorithmic_bytes_per_launch": ks_bytes, "avg_launch_us": round(ks_us, 2),
+                       "sampled_launches": ks_n}
+
     model = iteration_model_bytes(cfg, run.Z.count)
     it_roof = {"model_bytes": model, "achieved_GBps": round(model / upd / 1e9, 1), "peak": HBM_PEAK_GBS,
                "frac": round(model / upd / 1e9 / HBM_PEAK_GBS, 4),
@@ -364,6 +375,7 @@ def main():
                      "frac_of_hbm_peak": round(fwd_gbs / HBM_PEAK_GBS, 4)},
         "roofline": roofline,
         "ntt_row_pass_roofline": ntt_row_roofline,
+        "ks_row_pass_roofline": ks_row_roofline,
         "iteration_roofline": it_roof,
         "graph_s_per_iter": None if graph_s is None else round(graph_s, 4),
         "minibatch": mini,

@@ -281,21 +281,23 @@ int heqg_ntt(heqg_ctx* ctx, uint64_t* dev_rows, int64_t n_rows, int first_prime,
              hipStream_t s);
 
 /*
- * Launch-duration sampling of two kernel classes: kernel 0 = the plain
+ * Launch-duration sampling of three kernel classes: kernel 0 = the plain
  * forward NTT row pass (second pass), kernel 1 = the fused base-conversion
  * column pass (ModUp or ModDown conversion + first forward NTT pass, the most
- * time-consuming kernel of an iteration).  After heqg_prof_start(every),
- * every `every`-th eager launch of each class, on whatever stream it is
- * enqueued, is bracketed by two hipEvents recorded on the same stream (launches
- * inside a captured graph are not sampled).  heqg_prof_stop(kernel, ...)
- * disables sampling, synchronises that class's events and returns the mean
- * duration in microseconds, the number of sampled launches, the mean number of
- * N-word rows written per launch and (kernel 1) the mean number of distinct
- * source rows read and of algorithmic FP64 instructions per launch (per output
- * residue: 7 per base-conversion term, 3 for its reduction, 4 per first-pass
- * stage); it releases that class's samples.  Out pointers may be NULL.
- * Process-wide.  Returns -1 for a bad class, HEQG_ERR_DEVICE (-6) if an event
- * failed.
+ * time-consuming kernel of an iteration), kernel 2 = the ModUp row pass fused
+ * with the key inner product.  After heqg_prof_start(every), every `every`-th
+ * eager launch of each class, on whatever stream it is enqueued, is bracketed
+ * by two hipEvents recorded on the same stream (launches inside a captured
+ * graph are not sampled).  heqg_prof_stop(kernel, ...) returns for that class
+ * the mean launch duration in microseconds, the number of sampled launches,
+ * and per launch: kernel 0 - the mean number of N-word rows written; kernel 1
+ * - rows written, distinct source rows read and algorithmic FP64 instructions
+ * (per output residue: 7 per base-conversion term, 3 for its reduction, 4 per
+ * first-pass stage); kernel 2 - rows read and written per ciphertext summed
+ * over the launch (digits + 2 per output limb) and switching-key rows read
+ * (once per launch).  It releases that class's samples.  Out pointers may be
+ * NULL.  Process-wide.  Returns -1 for a bad class, HEQG_ERR_DEVICE (-6) if an
+ * event failed.
  */
 int heqg_prof_start(int every);
 int heqg_prof_stop(int kernel, double* avg_us, int64_t* launches, double* avg_rows, double* avg_src_rows,

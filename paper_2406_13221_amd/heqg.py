@@ -137,9 +137,10 @@ def prof_start(every):
 
 
 def prof_stop(kernel=0):
-    """(mean microseconds, sampled launches, mean rows written per launch, mean source rows read per
-    launch, mean algorithmic FP64 instructions per launch) of kernel class 0 (plain forward NTT row
-    pass) or 1 (fused base-conversion column pass)."""
+    """(mean microseconds, sampled launches, then three per-launch means) of kernel class 0 (plain
+    forward NTT row pass: rows written, -, -), 1 (fused base-conversion column pass: rows written,
+    source rows read, algorithmic FP64 instructions) or 2 (ModUp row pass fused with the key inner
+    product: ciphertext rows read and written, switching-key rows read, -)."""
     a, n, r, sr, op = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     _check(lib().heqg_prof_stop(int(kernel), ctypes.byref(a), ctypes.byref(n), ctypes.byref(r), ctypes.byref(sr),
                                 ctypes.byref(op)))
