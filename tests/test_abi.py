@@ -55,3 +55,16 @@ def test_null_arguments_are_rejected(L):
     assert L.heqg_add(None, None, None, None, None) == heqg.ERR_ARG
     assert L.heqg_nag_qg_step(None, None, None, None, None, None, None, None, 1, None, 0, None) == heqg.ERR_ARG
     assert L.heqg_keys_bytes(None, 3) == 0
+
+
+def test_profiling_classes_without_device(L):
+    # nothing sampled: zeros; a class outside 0..2 is an error
+    assert L.heqg_prof_start(4) == 0
+    a, n = ctypes.c_double(1.0), ctypes.c_int64(1)
+    r, sr, op = ctypes.c_double(1.0), ctypes.c_double(1.0), ctypes.c_double(1.0)
+    for k in range(3):
+        assert L.heqg_prof_stop(k, ctypes.byref(a), ctypes.byref(n), ctypes.byref(r), ctypes.byref(sr),
+                                ctypes.byref(op)) == 0
+        assert (a.value, n.value, r.value, sr.value, op.value) == (0.0, 0, 0.0, 0.0, 0.0)
+    assert L.heqg_prof_stop(3, None, None, None, None, None) == -1
+    assert L.heqg_prof_stop(-1, None, None, None, None, None) == -1
