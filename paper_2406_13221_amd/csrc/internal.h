@@ -35,6 +35,14 @@ struct KsEpi {
   uint64_t galois;
 };
 
+// Rescale combine, applied where the forward NTT of the spread rows stores its output
+// (rows ia = ct, ib = part, limb ii = i < level):
+//   out_i = (in_i - NTT(spread)_i) * q_level^-1 mod q_i
+struct RsEpi {
+  CtV in, out;            // element (ct, part, limb i) at d + ct*cs + part*ps + i*N
+  const uint64_t* qinv;   // [limb][2]: q_level^-1 mod q_i and its Shoup companion
+};
+
 // Optional work fused into the passes of one NTT launch (everything off when zeroed).
 struct NttExtra {
   // inverse, first pass: read row (ia, ib, ii) from in + ia*in_sa + ib*in_sb + ii*N (out of
@@ -48,6 +56,9 @@ struct NttExtra {
   const uint64_t* scale;
   const double* scalef;
   int out_f64;
+  // out_centered (primes of at most FP_MAX_BITS bits): write the representative in
+  // [-(q-1)/2, (q-1)/2] as a double instead, the form the rescale's spread reads
+  int out_centered;
   // forward, first pass: the input of row (ia, ib, ii) is the base conversion
   //   sum_s csrc_s * hat[p][s]  mod q_p,  csrc_s = csrc + ia*csrc_sa + ib*csrc_sb + s*N
   // with hat pairs (w, Shoup(w)) at chat + 2*(p*cstride + s) and FP64 pairs
@@ -64,6 +75,13 @@ struct NttExtra {
   KsEpi epi;
   // forward: run the column pass only; the row pass is done by launch_ks_rows
   int cols_only;
+  // forward, first pass: the input of row (ia, ib, ii) is the centered row (out_centered)
+  // spread + ia*spread_sa + ib*spread_sb reduced mod p (the rescale's spread)
+  const uint64_t* spread;
+  int64_t spread_sa, spread_sb;
+  // forward, last pass: rescale combine instead of a plain store
+  int has_rs;
+  RsEpi rs;
 };
 
 // The forward row pass of every digit's ModUp extension, fused with the key inner

@@ -53,6 +53,14 @@ __device__ __forceinline__ uint64_t fint_to_u64(double t) {
   return (uint64_t)__double_as_longlong(t + kTwo52) & 0x000FFFFFFFFFFFFFull;
 }
 
+// a signed integer |t| < 2^51 held in a double, as int64: t + 1.5 * 2^52 is exact and its 52
+// mantissa bits are t + 2^51
+__device__ __forceinline__ int64_t fint_to_i64(double t) {
+#pragma clang fp contract(off)
+  return (int64_t)((uint64_t)__double_as_longlong(t + 6755399441055744.0) & 0x000FFFFFFFFFFFFFull) -
+         (int64_t)(1ll << 51);
+}
+
 // canonical residue in [0, q) of an exact integer x (|x| < 2^52), as a double: fred leaves
 // |t| <= q/2 + 1, so one conditional +q suffices
 __device__ __forceinline__ double fcanon_d(double x, double q, double qi) {

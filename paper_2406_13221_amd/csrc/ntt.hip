@@ -241,11 +241,30 @@ __device__ __forceinline__ void ks_epi16(const KsEpi& E, int64_t ab, int ii, int
   }
 }
 
+// Rescale combine of the 16 output residues y[r] of row (ab, ii), ab = ct * nb + part, at
+// positions pos0 + st*r: out = (in - y) * q_level^-1 mod q_p.  In place (out == in) is safe:
+// a thread reads each of its positions before writing it, and no other thread touches them.
+__device__ __forceinline__ void rs_epi16(const RsEpi& E, int64_t ab, int64_t nb, int ii, int p, const PrimeConst& pc,
+                                         int logN, int64_t pos0, int st, const uint64_t (&y)[16]) {
+  const int64_t ct = ab / nb, part = ab % nb;
+  const int64_t lo = (int64_t)ii << logN;
+  const uint64_t* in = E.in.d + ct * E.in.cs + part * E.in.ps + lo;
+  uint64_t* out = E.out.d + ct * E.out.cs + part * E.out.ps + lo;
+  const uint64_t q = pc.q, w = E.qinv[2 * p], wsh = E.qinv[2 * p + 1];
+  uint64_t a[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) a[r] = in[pos0 + st * r];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) out[pos0 + st * r] = mul_shoup(submod(a[r], y[r], q), w, wsh, q);
+}
+
 // ------------------------------------------------------------------ pass A (columns)
 // CONV (forward only): the input is the base conversion of the rows at cs.
+// sp (forward, not CONV): the rescale's centered source row, or null.
 template <int LOGS, bool FWD, bool CONV, bool FP>
-__device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, const uint64_t* cs, int p, int tile,
-                                          uint64_t* lds) {
+__device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, const uint64_t* cs, const uint64_t* sp,
+                                          int p, int tile, uint64_t* lds) {
   constexpr int S = 1 << LOGS, T = S / 16, C = 256 / T;
   const int tid = threadIdx.x;
   const PrimeConst pc = P.pc[p];
@@ -305,6 +324,11 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
         }
 #pragma unroll
         for (int r = 0; r < 16; ++r) x[r] = fred(x[r], q, qi);
+      } else if (sp) {
+        // spread: the centered residue of the rescaled-away limb, |y| <= (q_l - 1)/2, reduced
+        const RowBuf sb(sp);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[r] = fred(as_f(sb.ld(vs, r * us)), q, qi);
       } else {
 #pragma unroll
         for (int r = 0; r < 16; ++r) x[r] = u64_to_f(rb.ld(vs, r * us));
@@ -329,7 +353,14 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
       for (int r = 0; r < 16; ++r) x[r] = as_f(lds[(kg + T * r) * C + cl]);
       stages_strided<false>(x, to_const(tw), 1, bf);
       const double sd = P.X.scalef ? P.X.scalef[p] : pc.ninv_d;
-      if (P.X.out_f64) {
+      if (P.X.out_centered) {
+        const double half = (q - 1.0) * 0.5;  // q odd: exact
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const double t = fcanon_d(fmulmod(x[r], sd, q, qi), q, qi);
+          rb.st(as_u(t > half ? t - q : t), vs, r * us);
+        }
+      } else if (P.X.out_f64) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) rb.st(as_u(fcanon_d(fmulmod(x[r], sd, q, qi), q, qi)), vs, r * us);
       } else {
@@ -365,6 +396,14 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
             const uint64_t v = x[r] + mul_shoup_lazy(yr, w, wsh, q);
             x[r] = v >= two_q ? v - two_q : v;
           }
+        }
+      } else if (sp) {
+        // spread: a centered double y (|y| < 2^51), as a signed integer made canonical (|y| < q)
+        const RowBuf sb(sp);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int64_t v = fint_to_i64(as_f(sb.ld(vs, r * us)));
+          x[r] = v < 0 ? (uint64_t)(v + (int64_t)q) : (uint64_t)v;
         }
       } else {
 #pragma unroll
@@ -420,11 +459,12 @@ __global__ void __launch_bounds__(256) k_ntt_cols(NttParams P) {
   const int64_t ia = ab / P.nb, ib = ab % P.nb;
   uint64_t* row = P.data + ia * P.sa + ib * P.sb + ((int64_t)ii << P.logN);
   const uint64_t* cs = CONV ? P.X.csrc + ia * P.X.csrc_sa + ib * P.X.csrc_sb : nullptr;
+  const uint64_t* sp = !CONV && FWD && P.X.spread ? P.X.spread + ia * P.X.spread_sa + ib * P.X.spread_sb : nullptr;
   const int p = P.pidx[ii];
   if (P.pc[p].k <= FP_MAX_BITS)
-    cols_body<LOGS, FWD, CONV, true>(P, row, cs, p, tile, lds);
+    cols_body<LOGS, FWD, CONV, true>(P, row, cs, sp, p, tile, lds);
   else
-    cols_body<LOGS, FWD, CONV, false>(P, row, cs, p, tile, lds);
+    cols_body<LOGS, FWD, CONV, false>(P, row, cs, sp, p, tile, lds);
 }
 
 // ------------------------------------------------------------------ pass B (rows)
@@ -438,7 +478,8 @@ __device__ __forceinline__ int swz(int l) { return l ^ ((l >> 4) & 15); }
 // consecutive b.  COAL: accesses in the {16*j + r} layout go through an extra LDS
 // transpose so that every global load/store is coalesced.
 // FUSE: inverse - read the row out of place from inrow (through the automorphism);
-// forward - key-switch combine epilogue for row (ab, ii) instead of a store.
+// forward - key-switch combine epilogue for row (ab, ii) instead of a store.  Forward
+// without FUSE: the rescale combine epilogue when P.X.has_rs.
 template <int LOGS, bool FWD, bool COAL, bool FUSE, bool FP>
 __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, const uint64_t* inrow, int64_t ab,
                                           int ii, int p, int b, uint64_t* l, int fl) {
@@ -475,17 +516,22 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
 #pragma unroll
         for (int r = 0; r < 16; ++r) l[fl ^ swz(16 * j + r)] = y[r];
         __syncthreads();
-        if (FUSE) {
+        if (FUSE || P.X.has_rs) {
           uint64_t v[16];
 #pragma unroll
           for (int r = 0; r < 16; ++r) v[r] = l[fl ^ swz(j + T * r)];
-          ks_epi16(P.X.epi, ab, ii, p, pc, P.logN, pos0 + j, T, v);
+          if (FUSE)
+            ks_epi16(P.X.epi, ab, ii, p, pc, P.logN, pos0 + j, T, v);
+          else
+            rs_epi16(P.X.rs, ab, P.nb, ii, p, pc, P.logN, pos0 + j, T, v);
         } else {
 #pragma unroll
           for (int r = 0; r < 16; ++r) src[j + T * r] = l[fl ^ swz(j + T * r)];
         }
       } else if (FUSE) {
         ks_epi16(P.X.epi, ab, ii, p, pc, P.logN, pos0 + 16 * j, 1, y);
+      } else if (P.X.has_rs) {
+        rs_epi16(P.X.rs, ab, P.nb, ii, p, pc, P.logN, pos0 + 16 * j, 1, y);
       } else {
         U2* dst = reinterpret_cast<U2*>(src + 16 * j);
 #pragma unroll
@@ -561,17 +607,22 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
 #pragma unroll
         for (int r = 0; r < 16; ++r) l[fl ^ swz(16 * j + r)] = x[r];
         __syncthreads();
-        if (FUSE) {
+        if (FUSE || P.X.has_rs) {
           uint64_t v[16];
 #pragma unroll
           for (int r = 0; r < 16; ++r) v[r] = l[fl ^ swz(j + T * r)];
-          ks_epi16(P.X.epi, ab, ii, p, pc, P.logN, pos0 + j, T, v);
+          if (FUSE)
+            ks_epi16(P.X.epi, ab, ii, p, pc, P.logN, pos0 + j, T, v);
+          else
+            rs_epi16(P.X.rs, ab, P.nb, ii, p, pc, P.logN, pos0 + j, T, v);
         } else {
 #pragma unroll
           for (int r = 0; r < 16; ++r) src[j + T * r] = l[fl ^ swz(j + T * r)];
         }
       } else if (FUSE) {
         ks_epi16(P.X.epi, ab, ii, p, pc, P.logN, pos0 + 16 * j, 1, x);
+      } else if (P.X.has_rs) {
+        rs_epi16(P.X.rs, ab, P.nb, ii, p, pc, P.logN, pos0 + 16 * j, 1, x);
       } else {
         U2* dst = reinterpret_cast<U2*>(src + 16 * j);
 #pragma unroll
@@ -948,7 +999,7 @@ void run_ntt(NttParams P, int64_t rows, bool inverse, const U2* twf, const U2* t
     if (P.X.cols_only) return;
     P.tiles = tilesB;
     ProfSample sr;
-    if (!P.X.has_epi) sr.begin(0, rows, 0, 0.0, s);
+    if (!P.X.has_epi && !P.X.has_rs && !P.X.spread) sr.begin(0, rows, 0, 0.0, s);
     launch_rows<LB, true>(P, blocksB, s);
     sr.end(s);
   } else {

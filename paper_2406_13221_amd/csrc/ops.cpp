@@ -295,11 +295,36 @@ int rotate(heqg_ctx* c, const heqg_keys* k, CtV in, CtV out, int64_t count, int 
   return HEQG_OK;
 }
 
+// (x - [x]_{q_l, centred}) * q_l^-1 per limb below l.  When q_l takes the FP64 path: the
+// inverse NTT of limb l reads it in place in `in` and writes its centred residues as doubles;
+// the forward NTT of the other limbs forms the spread in its first pass and applies the
+// combine in its last, so neither the spread rows nor their transforms make an extra round
+// trip through memory.  Otherwise: copy, inverse NTT, spread, forward NTT, combine.
 void rescale(heqg_ctx* c, CtV in, CtV out, int64_t count, int n_poly, int level, uint64_t* ws, hipStream_t s) {
   const int N = c->g.N;
   uint64_t* last = ws;
   uint64_t* spread = ws + (size_t)count * n_poly * N;
   const int64_t rowsn = count * n_poly;
+  if (!(c->primes[level] >> FP_MAX_BITS)) {
+    int pl[1] = {level};
+    NttExtra xi{};
+    xi.in = in.d + (size_t)level * N;
+    xi.in_sa = in.cs;
+    xi.in_sb = in.ps;
+    xi.out_centered = 1;
+    launch_ntt_ex(c->t, c->g.logN, rows(last, count, (int64_t)n_poly * N, n_poly, N, 1, pl), true, xi, s);
+    NttExtra xf{};
+    xf.spread = last;
+    xf.spread_sa = (int64_t)n_poly * N;
+    xf.spread_sb = N;
+    xf.has_rs = 1;
+    xf.rs.in = in;
+    xf.rs.out = out;
+    xf.rs.qinv = c->t.rescale + 2 * (size_t)level * c->g.n_q;
+    launch_ntt_ex(c->t, c->g.logN, rows_q(spread, count, (int64_t)n_poly * level * N, n_poly, (int64_t)level * N, level, 0),
+                  false, xf, s);
+    return;
+  }
   k_copy_launch(c->g, CtV{in.d + (size_t)level * N, in.cs, in.ps}, CtV{last, (int64_t)n_poly * N, N}, count, n_poly, 1,
                 s);
   int pl[1] = {level};
