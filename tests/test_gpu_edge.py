@@ -1,6 +1,7 @@
 """Degenerate and boundary cases of the scheme operations: level 0 (a single
 digit), rotations that are the identity, empty and inconsistent inputs
-(rejected before any launch), and an empty NTT."""
+(rejected before any launch), an empty NTT, and a rescale through each of its
+two paths (dropped prime wider than the FP64 path, or not)."""
 import numpy as np
 import pytest
 
@@ -98,3 +99,32 @@ def test_empty_ntt_is_a_noop(env):
     assert heqg.lib().heqg_ntt(ctx.h, rows.data_ptr(), 3, 0, 2, 0, heqg._stream()) == heqg.ERR_ARG
     torch.cuda.synchronize()
     assert int(rows.abs().sum()) == 0
+
+
+def test_rescale_both_paths_bit_exact():
+    # a chain whose limbs 2 and 4 exceed the FP64 path (44 bits): dropping limb 4 takes the
+    # integer path (copy, spread, combine), dropping limb 3 (40 bits) the fused one, whose
+    # spread also reaches the 50-bit limb 0 and the 44-bit limb 2 on the integer path
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cfg, ora, ctx = make_pair("c1", q_bits=[50, 40, 44, 40, 44])
+    assert [int(p).bit_length() for p in ctx.primes[:5]] == [50, 40, 44, 40, 44]
+    ora.keygen(cfg["key_seed"], [])
+    keys = ctx.keygen(cfg["key_seed"], [])
+    rng = np.random.default_rng(23)
+    L = ora.top_level
+    m = rng.integers(-2 ** 44, 2 ** 44, (2, ora.N))
+    o = [ora.encrypt(m[i], L, ora.delta, cfg["enc_seed"], 40 + i) for i in range(2)]
+    g = ctx.encrypt(keys, m, L, ora.delta, cfg["enc_seed"], 40)
+    t = ctx.tensor(g, g)
+    for i in range(2):
+        o1 = ora.rescale(o[i])
+        o2 = ora.rescale(o1)
+        g1 = ctx.rescale(g)
+        g2 = ctx.rescale(g1)
+        pick = lambda x: type(x)(x.data[i:i + 1], x.level, x.scale)
+        assert_same_ct(pick(g1), o1, "rescale wide limb [%d]" % i)
+        assert_same_ct(pick(g2), o2, "rescale 40-bit limb [%d]" % i)
+        ot = ora.tensor(o[i], o[i])
+        assert_same_ct(pick(ctx.rescale(ctx.rescale(t))), ora.rescale(ora.rescale(ot)), "rescale3 [%d]" % i)
