@@ -75,6 +75,9 @@ struct NttExtra {
   KsEpi epi;
   // forward: run the column pass only; the row pass is done by launch_ks_rows
   int cols_only;
+  // inverse: the first (row) pass was done by the producer of the rows (launch_ks_rows for
+  // the special-prime limbs); run the column pass only
+  int rows_done;
   // forward, first pass: the input of row (ia, ib, ii) is the centered row (out_centered)
   // spread + ia*spread_sa + ib*spread_sb reduced mod p (the rescale's spread)
   const uint64_t* spread;
@@ -88,7 +91,9 @@ struct NttExtra {
 // product (hybrid key switching):
 //   acc[ct][part][x] = sum_j v_j[x] * key[j][part][x]  mod p_x,  x over Q_l then P,
 // where v_j[x] is the in-digit limb x of the input (NTT form, read through X -> X^galois)
-// when x lies in digit j, else row e of digit j's extension after its column pass.
+// when x lies in digit j, else row e of digit j's extension after its column pass.  The Q
+// limbs of acc are stored in NTT form; the P limbs after the first (row) pass of their
+// inverse NTT, in the form an inverse row pass leaves (launch_ntt_ex with rows_done).
 struct KsRows {
   const uint64_t* ext;  // row e of digit j, ciphertext ct: ext + ct*ext_cs + j*ext_ds + e*N
   int64_t ext_cs, ext_ds;

@@ -721,6 +721,8 @@ struct KsrParams {
   KsRows K;
   const U2* tw;
   const double* twf;
+  const U2* twi;       // inverse twiddles: the special-prime limbs continue into ModDown's
+  const double* twif;  // inverse NTT (its first pass) before they are stored
   const PrimeConst* pc;
   int logN, tiles;
 };
@@ -815,10 +817,36 @@ __device__ __forceinline__ void ksr_body(const KsrParams& P, int64_t ct, int x, 
       for (int r = 0; r < 16; ++r) v[r] = as_f(l[flk ^ swz(jk + T * r)]);
       mac(v, k + (k >= jo ? 1 : 0));
     }
+    if (inq) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) out[T * r] = fcanon(s0[r], q, qi);
+      for (int r = 0; r < 16; ++r) out[T * r] = fcanon(s0[r], q, qi);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) out[((int64_t)nx << P.logN) + T * r] = fcanon(s1[r], q, qi);
+      for (int r = 0; r < 16; ++r) out[((int64_t)nx << P.logN) + T * r] = fcanon(s1[r], q, qi);
+    } else {
+      // special-prime limb: the first (row) pass of ModDown's inverse NTT on both sums, stored
+      // between passes as the inverse row pass stores them.  LDS: each thread's first writes
+      // are to the words it read last.
+      const double* twi = uniform_ptr(P.twif + ((int64_t)gp << P.logN));
+      auto ibf = [&](double& X, double& Y, double w) { gs_f(X, Y, w, q, qi); };
+      auto inv_row = [&](double (&v)[16], uint64_t* dst) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) l[fl ^ swz(jt + T * r)] = as_u(fred(v[r], q, qi));
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = as_f(l[fl ^ swz(16 * jt + r)]);
+        stages_contig<LOGS, false>(v, twi, base, jt, ibf);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) l[fl ^ swz(16 * jt + r)] = as_u(fred(v[r], q, qi));
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = as_f(l[fl ^ swz(jt + T * r)]);
+        stages_strided<false>(v, twi, base, ibf);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) dst[T * r] = as_u(fred(v[r], q, qi));
+      };
+      inv_row(s0, out);
+      inv_row(s1, out + ((int64_t)nx << P.logN));
+    }
   } else {
     const uint64_t q = pc.q, two_q = 2 * q;
     const U2* tw = uniform_ptr(P.tw + ((int64_t)gp << P.logN));
@@ -868,15 +896,40 @@ __device__ __forceinline__ void ksr_body(const KsrParams& P, int64_t ct, int x, 
       for (int r = 0; r < 16; ++r) v[r] = l[flk ^ swz(jk + T * r)];
       mac(v, k + (k >= jo ? 1 : 0));
     }
+    if (inq) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) out[T * r] = s0[r];
+      for (int r = 0; r < 16; ++r) out[T * r] = s0[r];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) out[((int64_t)nx << P.logN) + T * r] = s1[r];
+      for (int r = 0; r < 16; ++r) out[((int64_t)nx << P.logN) + T * r] = s1[r];
+    } else {
+      // special-prime limb: first pass of ModDown's inverse NTT (as in the FP64 path)
+      const U2* twi = uniform_ptr(P.twi + ((int64_t)gp << P.logN));
+      auto ibf = [&](uint64_t& X, uint64_t& Y, U2 w) { gs_bfly(X, Y, w, q, two_q); };
+      auto inv_row = [&](uint64_t (&v)[16], uint64_t* dst) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) l[fl ^ swz(jt + T * r)] = v[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = l[fl ^ swz(16 * jt + r)];
+        stages_contig<LOGS, false>(v, twi, base, jt, ibf);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) l[fl ^ swz(16 * jt + r)] = v[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = l[fl ^ swz(jt + T * r)];
+        stages_strided<false>(v, twi, base, ibf);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) dst[T * r] = v[r];
+      };
+      inv_row(s0, out);
+      inv_row(s1, out + ((int64_t)nx << P.logN));
+    }
   }
 }
 
-// Each workgroup takes the arithmetic path of its output limb's prime.  Three waves per
-// SIMD (168 registers) hold both paths with one register spilled outside the digit loop.
+// Each workgroup takes the arithmetic path of its output limb's prime.  At three waves per
+// SIMD (168 registers) the FP64 digit loop spills nothing; the 64-bit integer path and the
+// special-prime limbs' inverse pass spill a few registers.
 template <int LOGS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_ntt_rows_ks(KsrParams P) {
   static_assert(LOGS >= 6 && LOGS <= 8, "16 residues per thread cover 4 strided + 4 contiguous stages");
@@ -1006,7 +1059,7 @@ void run_ntt(NttParams P, int64_t rows, bool inverse, const U2* twf, const U2* t
     P.tw = twi;
     P.twf = twif;
     P.tiles = tilesB;
-    launch_rows<LB, false>(P, blocksB, s);
+    if (!P.X.rows_done) launch_rows<LB, false>(P, blocksB, s);
     P.tiles = tilesA;
     hipLaunchKernelGGL((k_ntt_cols<LA, false, false>), dim3((unsigned)(rows * tilesA)), dim3(256), 0, s, P);
   }
@@ -1132,6 +1185,8 @@ int launch_ks_rows(const DevTables& t, int log2N, const KsRows& k, hipStream_t s
   P.K = k;
   P.tw = reinterpret_cast<const U2*>(t.tw_fwd);
   P.twf = t.tw_fwd_f;
+  P.twi = reinterpret_cast<const U2*>(t.tw_inv);
+  P.twif = t.tw_inv_f;
   P.pc = t.pc;
   P.logN = log2N;
   P.tiles = (1 << log2N) / 4096;  // a workgroup holds 4096 residues of one row

@@ -205,7 +205,7 @@ void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, 
                   false, x, s);
   }
   // 3. second forward pass of every digit's extension fused with the inner product with the
-  //    key over Q_l and P
+  //    key over Q_l and P (and, for the P limbs, the first pass of step 4's inverse NTT)
   {
     KsRows k{};
     k.ext = ext;
@@ -223,9 +223,11 @@ void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, 
     k.nd = nd;
     launch_ks_rows(c->t, g.logN, k, s);
   }
-  // 4. ModDown: INTT of the P rows of both parts, scaled by (P/p)^-1 ...
+  // 4. ModDown: INTT of the P rows of both parts (its first pass already done in step 3),
+  //    scaled by (P/p)^-1 ...
   {
     NttExtra x{};
+    x.rows_done = 1;
     x.scale = scale;
     x.scalef = scalef;
     x.out_f64 = 1;
