@@ -927,6 +927,283 @@ __device__ __forceinline__ void ksr_body(const KsrParams& P, int64_t ct, int x, 
   }
 }
 
+// ---- the same with 8 residues per thread, for 256-point sub-rows (128 registers: four
+// waves per SIMD instead of three).  32 threads share a sub-row; its transform runs in
+// three register phases of 3 + 3 + 2 stages with element layouts
+//   A {j + 32r},  B {a + 4r} with a = (j & 3) + 32 (j >> 2),  C {8j + r}   (r = 0..7);
+// A also gives coalesced global accesses.  sw8 permutes a sub-row's 256 LDS words so that
+// every layout reads and writes all 32 banks of 8-byte words once per half-wave.
+__device__ __forceinline__ int sw8(int e) {
+  const int b = (e >> 5) & 7;
+  return e ^ (b ^ (b << 2));
+}
+
+// stage st (0..7) pairs elements e and e + 2^(7-st) with twiddle (base << st) + (e >> (8-st))
+template <bool FWD, typename V, typename TWP, typename BF>
+__device__ __forceinline__ void st8_A(V (&x)[8], TWP tw, int64_t base, BF bf) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int st = FWD ? k : 2 - k, d = 4 >> st;
+    const int64_t m = base << st;
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+      if ((r & d) == 0) bf(x[r], x[r + d], tw[m + (r >> (3 - st))]);
+  }
+}
+template <bool FWD, typename V, typename TWP, typename BF>
+__device__ __forceinline__ void st8_B(V (&x)[8], TWP tw, int64_t base, int a, BF bf) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int st = FWD ? 3 + k : 5 - k, d = 4 >> (st - 3);
+    const int64_t m = base << st;
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+      if ((r & d) == 0) bf(x[r], x[r + d], tw[m + ((a + 4 * r) >> (8 - st))]);
+  }
+}
+template <bool FWD, typename V, typename TWP, typename BF>
+__device__ __forceinline__ void st8_C(V (&x)[8], TWP tw, int64_t base, int j, BF bf) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int st = FWD ? 6 + k : 7 - k, d = 2 >> (st - 6);
+    const int64_t m = base << st;
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+      if ((r & d) == 0) bf(x[r], x[r + d], tw[m + ((8 * j + r) >> (8 - st))]);
+  }
+}
+
+// One workgroup: ciphertext ct, output limb x, 2048 consecutive residues (8 sub-rows b).
+// LDS: a thread's first writes in each exchange are to the words it read last, so one
+// barrier per exchange suffices.
+template <bool FP>
+__device__ __forceinline__ void ksr8_body(const KsrParams& P, int64_t ct, int x, int gp, int b, uint64_t* l) {
+  const KsRows& K = P.K;
+  const int j = threadIdx.x & 31;
+  const int a = (j & 3) + 32 * (j >> 2);
+  const PrimeConst pc = P.pc[gp];
+  const int N1 = 1 << (P.logN - 8);
+  const int64_t base = N1 + b;
+  const int64_t pos0 = (int64_t)b * 256;
+  const int nx = K.nl + K.np, nqp = K.nq + K.np;
+  const uint64_t* own = K.d.d + ct * K.d.cs + ((int64_t)x << P.logN);
+  const uint64_t* ex = K.ext + ct * K.ext_cs + pos0 + j;
+  const uint64_t* key = K.key + ((int64_t)gp << P.logN) + pos0 + j;
+  const int64_t kpart = (int64_t)nqp << P.logN, kdig = 2 * kpart;
+  uint64_t* out = K.acc + ct * ((int64_t)(2 * nx) << P.logN) + ((int64_t)x << P.logN) + pos0 + j;
+  const bool inq = x < K.nl;
+  const int jo = inq ? x / K.alpha : K.nd;
+  const int next = K.nd - (inq ? 1 : 0);
+  auto ext_row = [&](int k) {
+    const int jd = k + (k >= jo ? 1 : 0);
+    const int lo = jd * K.alpha, hi = min(lo + K.alpha, K.nl);
+    const int e = x < lo ? x : x - (hi - lo);
+    return ex + jd * K.ext_ds + ((int64_t)e << P.logN);
+  };
+  if (FP) {
+#pragma clang fp contract(off)
+    const double q = pc.qd, qi = pc.qinv;
+    const double* tw = uniform_ptr(P.twf + ((int64_t)gp << P.logN));
+    auto bf = [&](double& X, double& Y, double w) { ct_f(X, Y, w, q, qi); };
+    double s0[8], s1[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) s0[r] = s1[r] = 0.0;
+    // one key part at a time (8 words in flight)
+    auto mac = [&](const double (&v)[8], int jd) {
+      const uint64_t* kb = key + jd * kdig;
+      uint64_t w[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) w[r] = kb[32 * r];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) s0[r] += fmulmod(v[r], u64_to_f(w[r]), q, qi);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) w[r] = kb[kpart + 32 * r];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) s1[r] += fmulmod(v[r], u64_to_f(w[r]), q, qi);
+    };
+    if (inq) {
+      uint64_t u[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) u[r] = ld_in(own, pos0 + j + 32 * r, K.galois, P.logN);
+      __builtin_amdgcn_sched_barrier(0);
+      double v[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = u64_to_f(u[r]);
+      mac(v, jo);
+    }
+#pragma unroll 1
+    for (int k = 0; k < next; ++k) {
+      const uint64_t* src = ext_row(k);
+      const double* twk = tw;
+      int jk = j, ak = a;
+      int64_t bk = base;
+      asm volatile("" : "+s"(twk), "+v"(jk), "+v"(ak), "+v"(bk));
+      double v[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = as_f(src[32 * r]);
+      st8_A<true>(v, twk, bk, bf);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) l[sw8(jk + 32 * r)] = as_u(v[r]);
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = as_f(l[sw8(ak + 4 * r)]);
+      st8_B<true>(v, twk, bk, ak, bf);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) l[sw8(ak + 4 * r)] = as_u(v[r]);
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = as_f(l[sw8(8 * jk + r)]);
+      st8_C<true>(v, twk, bk, jk, bf);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) l[sw8(8 * jk + r)] = as_u(v[r]);
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = as_f(l[sw8(jk + 32 * r)]);
+      mac(v, k + (k >= jo ? 1 : 0));
+    }
+    if (inq) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) out[32 * r] = fcanon(s0[r], q, qi);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) out[((int64_t)nx << P.logN) + 32 * r] = fcanon(s1[r], q, qi);
+    } else {
+      // special-prime limb: first (row) pass of ModDown's inverse NTT, reduced after every
+      // phase (at most 3 lazy stages)
+      const double* twi = uniform_ptr(P.twif + ((int64_t)gp << P.logN));
+      auto ibf = [&](double& X, double& Y, double w) { gs_f(X, Y, w, q, qi); };
+      auto inv_row = [&](double (&v)[8], uint64_t* dst) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) l[sw8(j + 32 * r)] = as_u(fred(v[r], q, qi));
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r] = as_f(l[sw8(8 * j + r)]);
+        st8_C<false>(v, twi, base, j, ibf);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) l[sw8(8 * j + r)] = as_u(fred(v[r], q, qi));
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r] = as_f(l[sw8(a + 4 * r)]);
+        st8_B<false>(v, twi, base, a, ibf);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) l[sw8(a + 4 * r)] = as_u(fred(v[r], q, qi));
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r] = as_f(l[sw8(j + 32 * r)]);
+        st8_A<false>(v, twi, base, ibf);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) dst[32 * r] = as_u(fred(v[r], q, qi));
+      };
+      inv_row(s0, out);
+      inv_row(s1, out + ((int64_t)nx << P.logN));
+    }
+  } else {
+    const uint64_t q = pc.q, two_q = 2 * q;
+    const U2* tw = uniform_ptr(P.tw + ((int64_t)gp << P.logN));
+    auto bf = [&](uint64_t& X, uint64_t& Y, U2 w) { ct_bfly(X, Y, w, q, two_q); };
+    uint64_t s0[8], s1[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) s0[r] = s1[r] = 0;
+    auto mac = [&](const uint64_t (&v)[8], int jd) {
+      const uint64_t* kb = key + jd * kdig;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        s0[r] = addmod(s0[r], mulmod(v[r], kb[32 * r], pc), q);
+        s1[r] = addmod(s1[r], mulmod(v[r], kb[kpart + 32 * r], pc), q);
+      }
+    };
+    if (inq) {
+      uint64_t v[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = ld_in(own, pos0 + j + 32 * r, K.galois, P.logN);
+      __builtin_amdgcn_sched_barrier(0);
+      mac(v, jo);
+    }
+#pragma unroll 1
+    for (int k = 0; k < next; ++k) {
+      const uint64_t* src = ext_row(k);
+      const U2* twk = tw;
+      int jk = j, ak = a;
+      int64_t bk = base;
+      asm volatile("" : "+s"(twk), "+v"(jk), "+v"(ak), "+v"(bk));
+      uint64_t v[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = src[32 * r];
+      st8_A<true>(v, twk, bk, bf);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) l[sw8(jk + 32 * r)] = v[r];
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = l[sw8(ak + 4 * r)];
+      st8_B<true>(v, twk, bk, ak, bf);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) l[sw8(ak + 4 * r)] = v[r];
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = l[sw8(8 * jk + r)];
+      st8_C<true>(v, twk, bk, jk, bf);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const uint64_t w = v[r] >= two_q ? v[r] - two_q : v[r];
+        l[sw8(8 * jk + r)] = w >= q ? w - q : w;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = l[sw8(jk + 32 * r)];
+      mac(v, k + (k >= jo ? 1 : 0));
+    }
+    if (inq) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) out[32 * r] = s0[r];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) out[((int64_t)nx << P.logN) + 32 * r] = s1[r];
+    } else {
+      const U2* twi = uniform_ptr(P.twi + ((int64_t)gp << P.logN));
+      auto ibf = [&](uint64_t& X, uint64_t& Y, U2 w) { gs_bfly(X, Y, w, q, two_q); };
+      auto inv_row = [&](uint64_t (&v)[8], uint64_t* dst) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) l[sw8(j + 32 * r)] = v[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r] = l[sw8(8 * j + r)];
+        st8_C<false>(v, twi, base, j, ibf);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) l[sw8(8 * j + r)] = v[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r] = l[sw8(a + 4 * r)];
+        st8_B<false>(v, twi, base, a, ibf);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) l[sw8(a + 4 * r)] = v[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r] = l[sw8(j + 32 * r)];
+        st8_A<false>(v, twi, base, ibf);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) dst[32 * r] = v[r];
+      };
+      inv_row(s0, out);
+      inv_row(s1, out + ((int64_t)nx << P.logN));
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_ntt_rows_ks8(KsrParams P) {
+  __shared__ uint64_t lds[2048];
+  const KsRows& K = P.K;
+  int64_t unit, ct;
+  xcd_map(blockIdx.x, K.count, (int64_t)(K.nl + K.np) * P.tiles, unit, ct);
+  const int tile = (int)(unit % P.tiles);
+  const int x = (int)(unit / P.tiles);
+  const int gp = x < K.nl ? x : K.nq + (x - K.nl);
+  const int rl = threadIdx.x >> 5;
+  if (P.pc[gp].k <= FP_MAX_BITS)
+    ksr8_body<true>(P, ct, x, gp, tile * 8 + rl, lds + rl * 256);
+  else
+    ksr8_body<false>(P, ct, x, gp, tile * 8 + rl, lds + rl * 256);
+}
+
 // Each workgroup takes the arithmetic path of its output limb's prime.  At three waves per
 // SIMD (168 registers) the FP64 digit loop spills nothing; the 64-bit integer path and the
 // special-prime limbs' inverse pass spill a few registers.
@@ -1168,13 +1445,18 @@ int launch_ntt_ex(const DevTables& t, int log2N, const RowSet& rs, bool inverse,
 }
 
 template <int LB>
-void run_ks_rows(const KsrParams& P, hipStream_t s) {
+void run_ks_rows(KsrParams P, hipStream_t s) {
   const KsRows& K = P.K;
   const int nx = K.nl + K.np;
   ProfSample sp;
   // rows moved: nd inputs and 2 outputs per (ct, x); the key rows, read once
   sp.begin(2, K.count * nx * (K.nd + 2), (int64_t)K.nd * 2 * nx, 0.0, s);
-  hipLaunchKernelGGL((k_ntt_rows_ks<LB>), dim3((unsigned)(K.count * nx * P.tiles)), dim3(256), 0, s, P);
+  if (LB == 8) {
+    P.tiles = (1 << P.logN) / 2048;  // 8 residues per thread: 2048 per workgroup
+    hipLaunchKernelGGL(k_ntt_rows_ks8, dim3((unsigned)(K.count * nx * P.tiles)), dim3(256), 0, s, P);
+  } else {
+    hipLaunchKernelGGL((k_ntt_rows_ks<LB>), dim3((unsigned)(K.count * nx * P.tiles)), dim3(256), 0, s, P);
+  }
   sp.end(s);
 }
 
