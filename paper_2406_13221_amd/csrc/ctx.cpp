@@ -58,7 +58,7 @@ static uint32_t h_brv(uint32_t x, int bits) {
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Section offsets (bytes) in the device table buffer; returns the total size.
-size_t ctx_layout(const heqg_params* p, bool check, std::string* err, size_t offs[14]) {
+size_t ctx_layout(const heqg_params* p, bool check, std::string* err, size_t offs[16]) {
   if (!p || !p->q_bits) {
     if (err) *err = "null params";
     return 0;
@@ -91,7 +91,7 @@ size_t ctx_layout(const heqg_params* p, bool check, std::string* err, size_t off
   size_t N = (size_t)1 << p->log2N, nq = p->n_q, np = p->n_p, nqp = nq + np;
   size_t alpha = (nq + p->dnum - 1) / p->dnum;
   size_t mu_stride = alpha + nqp * alpha;
-  size_t sz[13] = {
+  size_t sz[15] = {
       nqp * N * 16,                    // tw_fwd
       nqp * N * 16,                    // tw_inv
       nqp * sizeof(PrimeConst),        // pc
@@ -105,13 +105,15 @@ size_t ctx_layout(const heqg_params* p, bool check, std::string* err, size_t off
       nq * np * 16,                    // moddown_f
       nq * nqp * 16,                   // ks_scale
       nq * nqp * 8,                    // ks_scale_f
+      nq * (np + 1) * 16,              // moddown_rs
+      nq * (np + 1) * 16,              // moddown_rs_f
   };
   size_t o = 0;
-  for (int i = 0; i < 13; ++i) {
+  for (int i = 0; i < 15; ++i) {
     if (offs) offs[i] = o;
     o = align256(o + sz[i]);
   }
-  if (offs) offs[13] = o;
+  if (offs) offs[15] = o;
   return o;
 }
 
@@ -133,7 +135,7 @@ static void fill_pc(PrimeConst& c, uint64_t q, int log2N) {
 
 int ctx_build(heqg_ctx* c, void* dev, size_t bytes, std::string* err) {
   const heqg_params* p = &c->p;
-  size_t offs[14];
+  size_t offs[16];
   size_t total = ctx_layout(p, true, err, offs);
   if (!total) return HEQG_ERR_UNSUPPORTED;
   if (!dev || bytes < total) {
@@ -272,6 +274,18 @@ int ctx_build(heqg_ctx* c, void* dev, size_t bytes, std::string* err) {
     e[1] = h_shoup(pinv, qi);
     c->pmod[2 * i] = P;
     c->pmod[2 * i + 1] = h_shoup(P, qi);
+    // ModDown merged with the following rescale: the np factors P/p_k above, then P itself
+    // (the factor of the rescale's spread, folded in before the division by P)
+    uint64_t* mr = reinterpret_cast<uint64_t*>(host.data() + offs[13]) + 2 * (size_t)i * (np + 1);
+    double* mrf = reinterpret_cast<double*>(host.data() + offs[14]) + 2 * (size_t)i * (np + 1);
+    const uint64_t two32 = (uint64_t)((((hu128)1) << 32) % qi);
+    for (int k = 0; k <= np; ++k) {
+      const uint64_t w = k < np ? md[2 * np + 2 * ((size_t)i * np + k)] : P;
+      mr[2 * k] = w;
+      mr[2 * k + 1] = h_shoup(w, qi);
+      mrf[2 * k] = (double)w;
+      mrf[2 * k + 1] = (double)h_mul(w, two32, qi);
+    }
   }
   // key-switch INTT output scales: N^-1 times the first factor of each base conversion
   {
@@ -333,6 +347,8 @@ int ctx_build(heqg_ctx* c, void* dev, size_t bytes, std::string* err) {
   c->t.moddown_f = reinterpret_cast<const double*>(d + offs[10]);
   c->t.ks_scale = reinterpret_cast<const uint64_t*>(d + offs[11]);
   c->t.ks_scale_f = reinterpret_cast<const double*>(d + offs[12]);
+  c->t.moddown_rs = reinterpret_cast<const uint64_t*>(d + offs[13]);
+  c->t.moddown_rs_f = reinterpret_cast<const double*>(d + offs[14]);
   return HEQG_OK;
 }
 

@@ -47,7 +47,7 @@ struct heqg_keys {
   size_t key_words;  // words of one switching key
 };
 
-size_t ctx_layout(const heqg_params* p, bool check, std::string* err, size_t offs[14]);
+size_t ctx_layout(const heqg_params* p, bool check, std::string* err, size_t offs[16]);
 int ctx_build(heqg_ctx* c, void* dev, size_t bytes, std::string* err);
 
 void set_err(const std::string& s);

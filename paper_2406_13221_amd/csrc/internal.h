@@ -26,6 +26,8 @@ struct CtV {
 // its output (rows ia = ct*2 + part, limb ii):
 //   out = (acc_Q - NTT(conv)) * P^-1 + base_part (+ addend)
 // base0 is read through X -> X^galois when galois != 1.
+// With qlinv set the result is also multiplied by qlinv[prime] (pairs w, Shoup(w)): the
+// division by q_l of a rescale merged into the ModDown.
 struct KsEpi {
   const uint64_t* acc;    // row (ia, ii) at acc + ia*acc_s + ii*N (NTT form)
   int64_t acc_s;
@@ -33,6 +35,7 @@ struct KsEpi {
   CtV base0, base1, addend, out;
   int has_base1, has_addend;
   uint64_t galois;
+  const uint64_t* qlinv;
 };
 
 // Rescale combine, applied where the forward NTT of the spread rows stores its output
@@ -70,6 +73,10 @@ struct NttExtra {
   int ns, cstride, csplit;
   const uint64_t* chat;
   const double* chatf;
+  // with cextra set, the last source (s = ns - 1) is read from cextra + ia*cextra_sa +
+  // ib*cextra_sb instead: centred residues held as doubles (out_centered)
+  const uint64_t* cextra;
+  int64_t cextra_sa, cextra_sb;
   // forward, last pass: key-switch combine instead of a plain store
   int has_epi;
   KsEpi epi;
@@ -121,6 +128,8 @@ struct DevTables {
   const uint64_t* ks_scale;  // [n_q][nqp][2]: at level l, N^-1 * (D/s)^-1 mod s for Q prime s in its
                              // digit D, N^-1 * (P/p)^-1 mod p for special prime p (+Shoup)
   const double* ks_scale_f;  // [n_q][nqp]: the same as doubles
+  const uint64_t* moddown_rs;  // [n_q][n_p + 1][2]: P/p_k mod q_i (k < n_p), then P mod q_i (+Shoup)
+  const double* moddown_rs_f;  // [n_q][n_p + 1][2]: (w, 2^32 w mod q_i) of the same as doubles
 };
 
 // Geometry the kernels need.

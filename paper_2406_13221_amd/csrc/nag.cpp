@@ -99,11 +99,18 @@ struct Exec {
     if (!dry) ops::rescale(c, a.v(), o.v(), a.count, a.n_poly, a.level, rs_ws, s);
     return o;
   }
+  // Rescale(Relin(x)): one key switch whose ModDown also divides by q_level where the
+  // dropped prime allows it (the same residues as the two steps)
+  Ct relin_rs(Ct a) {
+    if (!ops::can_merge_rescale(c, a.level)) return rescale(relin(a));  // reports level 0
+    Ct o = slot(2, a.level - 1, a.scale / q(a.level), a.count);
+    if (!dry) ops::relin(c, k, a.v(), o.v(), a.count, a.level, ks_ws, s, true);
+    return o;
+  }
   Ct hmult_rs(Ct a, Ct b) {  // Rescale(Relin(Tensor(a, b)))
     size_t m = next;
     Ct t = tensor(a, b);
-    Ct r = relin(t);
-    Ct o = rescale(r);
+    Ct o = relin_rs(t);
     // keep only the result: move it to the first freed slot
     if (!dry) std::swap(slots[m], slots[next - 1]);
     Ct res = o;
@@ -256,7 +263,7 @@ void circuit(Exec& X, const Io& io, const heqg_sigmoid* sg, heqg_nag_state* st, 
     b0 += cnt;
   }
   X.reset(base);
-  Ct gr = X.rescale(X.relin(acc));
+  Ct gr = X.relin_rs(acc);
   for (int k = 0; k < lm; ++k) gr = X.add_rot(gr, g << k);
   const int t = st->t;
   st->refreshed_gr = 0;

@@ -207,6 +207,7 @@ __device__ __forceinline__ uint64_t ld_in(const uint64_t* in, int64_t pos, uint6
 // pos0 + st*r.  All loads of a group of 8 are issued before any store, so the stores
 // (which the compiler must assume may alias the inputs) do not serialise them.  (An FP64
 // form of this combine measured slower than the 64-bit integer one.)
+template <bool QL>  // E.qlinv in use (a compile-time variant: it costs the combine 18 registers)
 __device__ __forceinline__ void ks_epi16(const KsEpi& E, int64_t ab, int ii, int p, const PrimeConst& pc, int logN,
                                          int64_t pos0, int st, const uint64_t (&y)[16]) {
   const int64_t ct = ab >> 1;
@@ -235,8 +236,8 @@ __device__ __forceinline__ void ks_epi16(const KsEpi& E, int64_t ab, int ii, int
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       uint64_t o = mul_shoup(submod(a[r], y[h + r], q), w, wsh, q);
-      o = addmod(o, z[r], q);
-      out[pos0 + st * (h + r)] = addmod(o, v[r], q);
+      o = addmod(addmod(o, z[r], q), v[r], q);
+      out[pos0 + st * (h + r)] = QL ? mul_shoup(o, E.qlinv[2 * p], E.qlinv[2 * p + 1], q) : o;
     }
   }
 }
@@ -261,7 +262,8 @@ __device__ __forceinline__ void rs_epi16(const RsEpi& E, int64_t ab, int64_t nb,
 
 // ------------------------------------------------------------------ pass A (columns)
 // CONV (forward only): the input is the base conversion of the rows at cs.
-// sp (forward, not CONV): the rescale's centered source row, or null.
+// sp: CONV - the row of the extra (last) source, centred doubles, or null; forward, not
+// CONV - the rescale's centred source row, or null.
 template <int LOGS, bool FWD, bool CONV, bool FP>
 __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, const uint64_t* cs, const uint64_t* sp,
                                           int p, int tile, uint64_t* lds) {
@@ -297,7 +299,7 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
 #pragma unroll 1
         for (uint32_t m = P.X.csplit & all; m; m &= m - 1) {
           const int s = __builtin_ctz(m);
-          const RowBuf ys(cs + ((int64_t)s << P.logN));
+          const RowBuf ys(sp && s == P.X.ns - 1 ? sp : cs + ((int64_t)s << P.logN));
           const double h0 = h[2 * s], h1 = h[2 * s + 1];
           uint64_t y[16];
 #pragma unroll
@@ -311,7 +313,7 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
 #pragma unroll 1
         for (uint32_t m = ~P.X.csplit & all; m; m &= m - 1) {
           const int s = __builtin_ctz(m);
-          const RowBuf ys(cs + ((int64_t)s << P.logN));
+          const RowBuf ys(sp && s == P.X.ns - 1 ? sp : cs + ((int64_t)s << P.logN));
           const double h0 = h[2 * s];
           // all 16 loads are issued before any use (left to itself the compiler waits on
           // each load in turn)
@@ -383,7 +385,7 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
         for (int r = 0; r < 16; ++r) x[r] = 0;
 #pragma unroll 1
         for (int s = 0; s < P.X.ns; ++s) {
-          const RowBuf ys(cs + ((int64_t)s << P.logN));
+          const RowBuf ys(sp && s == P.X.ns - 1 ? sp : cs + ((int64_t)s << P.logN));
           const uint64_t w = h[2 * s], wsh = h[2 * s + 1];
           const bool as_double = !((P.X.csplit >> s) & 1);
           uint64_t y[16];
@@ -392,7 +394,10 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
-            const uint64_t yr = as_double ? fint_to_u64(as_f(y[r])) : y[r];
+            // a double source may hold a centred (negative) residue: its canonical value
+            // mod q (|y| < 2^42 < q on this path)
+            const int64_t yi = fint_to_i64(as_f(y[r]));
+            const uint64_t yr = as_double ? (yi < 0 ? (uint64_t)(yi + (int64_t)q) : (uint64_t)yi) : y[r];
             const uint64_t v = x[r] + mul_shoup_lazy(yr, w, wsh, q);
             x[r] = v >= two_q ? v - two_q : v;
           }
@@ -459,7 +464,8 @@ __global__ void __launch_bounds__(256) k_ntt_cols(NttParams P) {
   const int64_t ia = ab / P.nb, ib = ab % P.nb;
   uint64_t* row = P.data + ia * P.sa + ib * P.sb + ((int64_t)ii << P.logN);
   const uint64_t* cs = CONV ? P.X.csrc + ia * P.X.csrc_sa + ib * P.X.csrc_sb : nullptr;
-  const uint64_t* sp = !CONV && FWD && P.X.spread ? P.X.spread + ia * P.X.spread_sa + ib * P.X.spread_sb : nullptr;
+  const uint64_t* sp = CONV ? (P.X.cextra ? P.X.cextra + ia * P.X.cextra_sa + ib * P.X.cextra_sb : nullptr)
+                            : (FWD && P.X.spread ? P.X.spread + ia * P.X.spread_sa + ib * P.X.spread_sb : nullptr);
   const int p = P.pidx[ii];
   if (P.pc[p].k <= FP_MAX_BITS)
     cols_body<LOGS, FWD, CONV, true>(P, row, cs, sp, p, tile, lds);
@@ -477,10 +483,11 @@ __device__ __forceinline__ int swz(int l) { return l ^ ((l >> 4) & 15); }
 // from P.group limbs that share one prime (so they share all twiddles), times R/group
 // consecutive b.  COAL: accesses in the {16*j + r} layout go through an extra LDS
 // transpose so that every global load/store is coalesced.
-// FUSE: inverse - read the row out of place from inrow (through the automorphism);
-// forward - key-switch combine epilogue for row (ab, ii) instead of a store.  Forward
-// without FUSE: the rescale combine epilogue when P.X.has_rs.
-template <int LOGS, bool FWD, bool COAL, bool FUSE, bool FP>
+// FUSE (0 = off): inverse - read the row out of place from inrow (through the
+// automorphism); forward - key-switch combine epilogue for row (ab, ii) instead of a store,
+// FUSE = 2 with the factor q_l^-1 of a merged rescale.  Forward without FUSE: the rescale
+// combine epilogue when P.X.has_rs.
+template <int LOGS, bool FWD, bool COAL, int FUSE, bool FP>
 __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, const uint64_t* inrow, int64_t ab,
                                           int ii, int p, int b, uint64_t* l, int fl) {
   constexpr int S = 1 << LOGS, T = S / 16;
@@ -521,7 +528,7 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
 #pragma unroll
           for (int r = 0; r < 16; ++r) v[r] = l[fl ^ swz(j + T * r)];
           if (FUSE)
-            ks_epi16(P.X.epi, ab, ii, p, pc, P.logN, pos0 + j, T, v);
+            ks_epi16<FUSE == 2>(P.X.epi, ab, ii, p, pc, P.logN, pos0 + j, T, v);
           else
             rs_epi16(P.X.rs, ab, P.nb, ii, p, pc, P.logN, pos0 + j, T, v);
         } else {
@@ -529,7 +536,7 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
           for (int r = 0; r < 16; ++r) src[j + T * r] = l[fl ^ swz(j + T * r)];
         }
       } else if (FUSE) {
-        ks_epi16(P.X.epi, ab, ii, p, pc, P.logN, pos0 + 16 * j, 1, y);
+        ks_epi16<FUSE == 2>(P.X.epi, ab, ii, p, pc, P.logN, pos0 + 16 * j, 1, y);
       } else if (P.X.has_rs) {
         rs_epi16(P.X.rs, ab, P.nb, ii, p, pc, P.logN, pos0 + 16 * j, 1, y);
       } else {
@@ -612,7 +619,7 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
 #pragma unroll
           for (int r = 0; r < 16; ++r) v[r] = l[fl ^ swz(j + T * r)];
           if (FUSE)
-            ks_epi16(P.X.epi, ab, ii, p, pc, P.logN, pos0 + j, T, v);
+            ks_epi16<FUSE == 2>(P.X.epi, ab, ii, p, pc, P.logN, pos0 + j, T, v);
           else
             rs_epi16(P.X.rs, ab, P.nb, ii, p, pc, P.logN, pos0 + j, T, v);
         } else {
@@ -620,7 +627,7 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
           for (int r = 0; r < 16; ++r) src[j + T * r] = l[fl ^ swz(j + T * r)];
         }
       } else if (FUSE) {
-        ks_epi16(P.X.epi, ab, ii, p, pc, P.logN, pos0 + 16 * j, 1, x);
+        ks_epi16<FUSE == 2>(P.X.epi, ab, ii, p, pc, P.logN, pos0 + 16 * j, 1, x);
       } else if (P.X.has_rs) {
         rs_epi16(P.X.rs, ab, P.nb, ii, p, pc, P.logN, pos0 + 16 * j, 1, x);
       } else {
@@ -671,7 +678,7 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
   }
 }
 
-template <int LOGS, bool FWD, bool COAL, bool FUSE>
+template <int LOGS, bool FWD, bool COAL, int FUSE>
 __global__ void __launch_bounds__(256) k_ntt_rows(NttParams P) {
   static_assert(LOGS >= 6 && LOGS <= 8, "16 residues per thread cover 4 strided + 4 contiguous stages");
   constexpr int S = 1 << LOGS, T = S / 16, R = 256 / T;
@@ -1286,15 +1293,22 @@ int g_rows_variant[2] = {1, 1};
 template <int LB, bool FWD>
 void launch_rows(const NttParams& P, unsigned blocks, hipStream_t s) {
   const bool fuse = FWD ? P.X.has_epi != 0 : P.X.in != nullptr;
-  if (fuse) {
-    if (g_rows_variant[FWD ? 0 : 1])
-      hipLaunchKernelGGL((k_ntt_rows<LB, FWD, true, true>), dim3(blocks), dim3(256), 0, s, P);
+  const bool ql = FWD && fuse && P.X.epi.qlinv;
+  const bool coal = g_rows_variant[FWD ? 0 : 1] != 0;
+  if (ql) {
+    if (coal)
+      hipLaunchKernelGGL((k_ntt_rows<LB, FWD, true, 2>), dim3(blocks), dim3(256), 0, s, P);
     else
-      hipLaunchKernelGGL((k_ntt_rows<LB, FWD, false, true>), dim3(blocks), dim3(256), 0, s, P);
-  } else if (g_rows_variant[FWD ? 0 : 1]) {
-    hipLaunchKernelGGL((k_ntt_rows<LB, FWD, true, false>), dim3(blocks), dim3(256), 0, s, P);
+      hipLaunchKernelGGL((k_ntt_rows<LB, FWD, false, 2>), dim3(blocks), dim3(256), 0, s, P);
+  } else if (fuse) {
+    if (coal)
+      hipLaunchKernelGGL((k_ntt_rows<LB, FWD, true, 1>), dim3(blocks), dim3(256), 0, s, P);
+    else
+      hipLaunchKernelGGL((k_ntt_rows<LB, FWD, false, 1>), dim3(blocks), dim3(256), 0, s, P);
+  } else if (coal) {
+    hipLaunchKernelGGL((k_ntt_rows<LB, FWD, true, 0>), dim3(blocks), dim3(256), 0, s, P);
   } else {
-    hipLaunchKernelGGL((k_ntt_rows<LB, FWD, false, false>), dim3(blocks), dim3(256), 0, s, P);
+    hipLaunchKernelGGL((k_ntt_rows<LB, FWD, false, 0>), dim3(blocks), dim3(256), 0, s, P);
   }
 }
 

@@ -150,7 +150,9 @@ int pt_load(heqg_ctx* c, const int64_t* coeffs, int64_t count, int level, uint64
 // ------------------------------------------------------------------ key switching
 size_t ks_ws_words(const heqg_ctx* c, int64_t count, int level) {
   const size_t nl = level + 1, nx = nl + c->g.n_p, nd = (nl + c->g.alpha - 1) / c->g.alpha;
-  return (size_t)count * (nl + nd * nx + 2 * nx + 2 * nl) * c->g.N;
+  // ycoef, the digits' extensions, acc, the conversion rows, and two rows per ciphertext
+  // part for a rescale merged into the ModDown (its last limb, then that limb centred)
+  return (size_t)count * (nl + nd * nx + 2 * nx + 2 * nl + 4) * c->g.N;
 }
 size_t rot_ws_words(const heqg_ctx* c, int64_t count, int level) {
   return (size_t)count * 2 * (level + 1) * c->g.N + ks_ws_words(c, count, level);
@@ -162,8 +164,12 @@ size_t mul_const_ws_words(const heqg_ctx* c, int64_t count, int n_poly, int leve
   return (size_t)count * n_poly * (level + 1) * c->g.N + rescale_ws_words(c, count, n_poly, level);
 }
 
+bool can_merge_rescale(const heqg_ctx* c, int level) {
+  return level >= 1 && !(c->primes[level] >> FP_MAX_BITS);
+}
+
 void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, CtV base0, CtV base1, bool has_base1,
-             CtV out, uint64_t* ws, hipStream_t s, uint64_t galois, const CtV* addend) {
+             CtV out, uint64_t* ws, hipStream_t s, uint64_t galois, const CtV* addend, bool rescale) {
   const Geo& g = c->g;
   const int N = g.N, nl = level + 1, np = g.n_p, nq = g.n_q, nx = nl + np, alpha = g.alpha;
   const int nd = (nl + alpha - 1) / alpha;
@@ -171,6 +177,8 @@ void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, 
   uint64_t* ext = ycoef + (size_t)count * nl * N;
   uint64_t* acc = ext + (size_t)count * nd * nx * N;
   uint64_t* conv = acc + (size_t)count * 2 * nx * N;
+  uint64_t* last = conv + (size_t)count * 2 * nl * N;  // [ct][part][N], merged rescale only
+  uint64_t* lastc = last + (size_t)count * 2 * N;
   const int64_t ext_cs = (int64_t)nd * nx * N;
   const uint64_t* scale = c->t.ks_scale + 2 * (size_t)level * g.nqp;
   const double* scalef = c->t.ks_scale_f + (size_t)level * g.nqp;
@@ -235,7 +243,7 @@ void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, 
                   true, x, s);
   }
   // ... then conversion P -> Q, forward NTT and (acc_Q - conv) * P^-1 + base in one launch
-  {
+  auto moddown = [&](int first, int n, CtV o, bool merged) {
     NttExtra x{};
     x.csrc = acc + (size_t)nl * N;
     x.csrc_sa = (int64_t)nx * N;
@@ -244,27 +252,58 @@ void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, 
     x.chat = c->t.moddown + 2 * np;
     x.chatf = c->t.moddown_f;
     for (int k = 0; k < np; ++k) x.csplit |= (c->primes[nq + k] >> FP_MAX_BITS ? 1 : 0) << k;
+    if (merged) {
+      // the rescale's spread of the centred last limb enters the conversion with factor P
+      x.ns = x.cstride = np + 1;
+      x.chat = c->t.moddown_rs;
+      x.chatf = c->t.moddown_rs_f;
+      x.cextra = lastc;
+      x.cextra_sa = N;
+    }
     x.has_epi = 1;
     KsEpi& e = x.epi;
-    e.acc = acc;
+    e.acc = acc + (size_t)first * N;
     e.acc_s = (int64_t)nx * N;
     e.pinv = c->t.moddown + 2 * np + 2 * (size_t)nq * np;
-    e.base0 = base0;
-    e.base1 = base1;
+    e.base0 = CtV{base0.d + (size_t)first * N, base0.cs, base0.ps};
+    e.base1 = CtV{base1.d + (size_t)first * N, base1.cs, base1.ps};
     e.has_base1 = has_base1 ? 1 : 0;
-    if (addend) e.addend = *addend;
+    if (addend) e.addend = CtV{addend->d + (size_t)first * N, addend->cs, addend->ps};
     e.has_addend = addend ? 1 : 0;
-    e.out = out;
+    e.out = o;
     e.galois = galois;
-    launch_ntt_ex(c->t, g.logN, rows_q(conv, count * 2, (int64_t)nl * N, 1, 0, nl, 0), false, x, s);
+    if (merged) e.qlinv = c->t.rescale + 2 * (size_t)level * nq;
+    launch_ntt_ex(c->t, g.logN, rows_q(conv + (size_t)first * N, count * 2, (int64_t)nl * N, 1, 0, n, first), false, x,
+                  s);
+  };
+  if (!rescale) {
+    moddown(0, nl, out, false);
+    return;
   }
+  // Rescale merged (out is at level - 1): with r = the key switch's result and l = level,
+  //   out_i = (r_i - NTT(spread_i)) * q_l^-1,  spread_i = [INTT(r_l)]_centred mod q_i
+  //         = ((acc_i - NTT(conv_i + P * spread_i)) * P^-1 + base_i) * q_l^-1   (i < l),
+  // so r is only formed for limb l, whose centred coefficients become one more conversion
+  // source; the other limbs of r are never stored.  The same residues, exactly.
+  moddown(level, 1, CtV{last, 2 * (int64_t)N, N}, false);
+  {
+    int pl[1] = {level};
+    NttExtra xi{};
+    xi.in = last;
+    xi.in_sa = 2 * (int64_t)N;
+    xi.in_sb = N;
+    xi.out_centered = 1;
+    launch_ntt_ex(c->t, g.logN, rows(lastc, count, 2 * (int64_t)N, 2, N, 1, pl), true, xi, s);
+  }
+  moddown(0, level, out, true);
 }
 
-int relin(heqg_ctx* c, const heqg_keys* k, CtV in3, CtV out, int64_t count, int level, uint64_t* ws, hipStream_t s) {
+int relin(heqg_ctx* c, const heqg_keys* k, CtV in3, CtV out, int64_t count, int level, uint64_t* ws, hipStream_t s,
+          bool rescale) {
   CtV d{in3.d + 2 * in3.ps, in3.cs, in3.ps};
   CtV b0{in3.d, in3.cs, in3.ps};
   CtV b1{in3.d + in3.ps, in3.cs, in3.ps};
-  ks_core(c, k->rlk, d, count, level, b0, b1, true, out, ws, s, 1, nullptr);
+  ks_core(c, k->rlk, d, count, level, b0, b1, true, out, ws, s, 1, nullptr, rescale);
   return HEQG_OK;
 }
 

@@ -27,9 +27,13 @@ size_t mul_const_ws_words(const heqg_ctx* c, int64_t count, int n_poly, int leve
 
 // key switch of d (NTT rows 0..level) with `key`; out_p = base_p + ks_p (base_1 optional)
 // galois != 1: d and base0 are read through X -> X^galois; addend (both parts) is added to the output
+// rescale: also divide by q_level (out at level - 1), merged into the ModDown; only where
+// can_merge_rescale(level)
+bool can_merge_rescale(const heqg_ctx* c, int level);
 void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, CtV base0, CtV base1, bool has_base1,
-             CtV out, uint64_t* ws, hipStream_t s, uint64_t galois, const CtV* addend);
-int relin(heqg_ctx* c, const heqg_keys* k, CtV in3, CtV out, int64_t count, int level, uint64_t* ws, hipStream_t s);
+             CtV out, uint64_t* ws, hipStream_t s, uint64_t galois, const CtV* addend, bool rescale = false);
+int relin(heqg_ctx* c, const heqg_keys* k, CtV in3, CtV out, int64_t count, int level, uint64_t* ws, hipStream_t s,
+          bool rescale = false);
 const uint64_t* rot_key(const heqg_keys* k, uint64_t galois);
 // out = Rot(in) [+ addend]; out must not alias in
 int rotate(heqg_ctx* c, const heqg_keys* k, CtV in, CtV out, int64_t count, int level, uint64_t galois, uint64_t* ws,
