@@ -288,7 +288,10 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
     double x[16];
     if (FWD) {
       if (CONV) {
-        // sum of at most 2*16 products, each |.| <= q/2 + 1: exact, then reduced to |x| <= q/2 + 1
+        // sum of at most 2*16 products, each |.| < 0.53 q: exact.  Up to 8 terms (every
+        // conversion of the paper's parameters) the sum (< 4.3 q) goes into the transform as
+        // it is: 16 lazy stages then keep |x| < 13 q, inside fmulmod's range; more terms are
+        // reduced to |x| <= q/2 + 1 first.
         const cptr<double> h = to_const(P.X.chatf + 2 * (int64_t)p * P.X.cstride);
 #pragma unroll
         for (int r = 0; r < 16; ++r) x[r] = 0.0;
@@ -324,8 +327,10 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
 #pragma unroll
           for (int r = 0; r < 16; ++r) x[r] += fmulmod(as_f(y[r]), h0, q, qi);
         }
+        if (P.X.ns + __builtin_popcount(P.X.csplit & all) > 8) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) x[r] = fred(x[r], q, qi);
+          for (int r = 0; r < 16; ++r) x[r] = fred(x[r], q, qi);
+        }
       } else if (sp) {
         // spread: the centered residue of the rescaled-away limb, |y| <= (q_l - 1)/2, reduced
         const RowBuf sb(sp);
