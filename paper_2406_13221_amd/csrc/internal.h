@@ -44,6 +44,7 @@ struct KsEpi {
 struct RsEpi {
   CtV in, out;            // element (ct, part, limb i) at d + ct*cs + part*ps + i*N
   const uint64_t* qinv;   // [limb][2]: q_level^-1 mod q_i and its Shoup companion
+  const uint64_t* pt;     // optional plaintext [limb][N]: in is read as in * pt (mul_pt folded in)
 };
 
 // Optional work fused into the passes of one NTT launch (everything off when zeroed).
@@ -157,8 +158,9 @@ void k_tensor_launch(const Geo& g, const DevTables& t, CtV a, CtV b, CtV out, in
                      hipStream_t s);
 void k_tensor_reduce_launch(const Geo& g, const DevTables& t, CtV a, CtV b, int64_t count, CtV acc, int nl,
                             bool accumulate, hipStream_t s);
+// limbs first .. first + nl - 1 of a times the same limbs of pt, into limbs 0 .. nl - 1 of out
 void k_mul_pt_launch(const Geo& g, const DevTables& t, CtV a, const uint64_t* pt, CtV out, int64_t count, int n_poly,
-                     int nl, hipStream_t s);
+                     int nl, hipStream_t s, int first = 0);
 void k_add_pt_launch(const Geo& g, const DevTables& t, CtV a, const uint64_t* pt, CtV out, int64_t count, int nl,
                      hipStream_t s);
 void k_mul_scalar_launch(const Geo& g, const DevTables& t, CtV a, CtV out, int64_t count, int n_poly, int nl,

@@ -574,9 +574,10 @@ void k_tensor_reduce_launch(const Geo& g, const DevTables& t, CtV a, CtV b, int6
   LAUNCH(k_tensor_reduce, n, s, t.pc, a, b, count, acc, g.logN, nl, accumulate ? 1 : 0);
 }
 void k_mul_pt_launch(const Geo& g, const DevTables& t, CtV a, const uint64_t* pt, CtV out, int64_t count, int n_poly,
-                     int nl, hipStream_t s) {
+                     int nl, hipStream_t s, int first) {
   int64_t n = count * n_poly * nl * CHUNKS(g);
-  if (n) LAUNCH(k_mul_pt, n, s, t.pc, a, pt, out, g.logN, nl, n_poly);
+  const size_t o = (size_t)first << g.logN;
+  if (n) LAUNCH(k_mul_pt, n, s, t.pc + first, CtV{a.d + o, a.cs, a.ps}, pt + o, out, g.logN, nl, n_poly);
 }
 void k_add_pt_launch(const Geo& g, const DevTables& t, CtV a, const uint64_t* pt, CtV out, int64_t count, int nl,
                      hipStream_t s) {

@@ -135,6 +135,13 @@ struct Exec {
     if (!dry) k_mul_pt_launch(c->g, c->t, a.v(), pt, o.v(), a.count, a.n_poly, a.level + 1, s);
     return o;
   }
+  // Rescale(a * pt): the product folded into the rescale where the dropped prime allows it
+  Ct mul_pt_rs(Ct a, const uint64_t* pt, double pt_scale) {
+    if (!ops::can_merge_rescale(c, a.level)) return rescale(mul_pt(a, pt, pt_scale));  // reports level 0
+    Ct o = slot(a.n_poly, a.level - 1, a.scale * pt_scale / q(a.level), a.count);
+    if (!dry) ops::rescale(c, a.v(), o.v(), a.count, a.n_poly, a.level, rs_ws, s, pt);
+    return o;
+  }
   Ct add_pt(Ct a, const uint64_t* pt, double pt_scale) {
     check_scale(a.scale, pt_scale, "add_pt");
     Ct o = slot(2, a.level, a.scale, a.count);
@@ -189,20 +196,20 @@ Ct sigmoid_block(Exec& X, const Ct& u, const heqg_sigmoid* sg) {
   auto M = [&](int i) { return sg->masks + i * plane; };
   if (u.level > sg->mask_level) X.fail(HEQG_ERR_ARG, "mask plaintexts below the margin level");
   size_t mark = X.next;
-  Ct a1 = X.rescale(X.mul_pt(u, M(0), sg->mask_scales[0]));
+  Ct a1 = X.mul_pt_rs(u, M(0), sg->mask_scales[0]);
   Ct s = X.hmult_rs(u, u);
   Ct s4{};
   if (sg->degree >= 5) s4 = X.hmult_rs(s, s);
-  Ct b3 = X.rescale(X.mul_pt(u, M(1), sg->mask_scales[1]));
+  Ct b3 = X.mul_pt_rs(u, M(1), sg->mask_scales[1]);
   Ct t3 = X.hmult_rs(b3, s);
   Ct p = X.add(a1, t3);
   if (sg->degree >= 5) {
-    Ct b5 = X.rescale(X.mul_pt(u, M(2), sg->mask_scales[2]));
+    Ct b5 = X.mul_pt_rs(u, M(2), sg->mask_scales[2]);
     Ct t5 = X.hmult_rs(b5, s4);
     p = X.add(p, t5);
   }
   if (sg->degree >= 7) {
-    Ct b7 = X.rescale(X.mul_pt(u, M(3), sg->mask_scales[3]));
+    Ct b7 = X.mul_pt_rs(u, M(3), sg->mask_scales[3]);
     Ct t7a = X.hmult_rs(b7, s);
     Ct t7 = X.hmult_rs(t7a, s4);
     p = X.add(p, t7);

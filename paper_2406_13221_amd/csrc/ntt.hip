@@ -243,7 +243,7 @@ __device__ __forceinline__ void ks_epi16(const KsEpi& E, int64_t ab, int ii, int
 }
 
 // Rescale combine of the 16 output residues y[r] of row (ab, ii), ab = ct * nb + part, at
-// positions pos0 + st*r: out = (in - y) * q_level^-1 mod q_p.  In place (out == in) is safe:
+// positions pos0 + st*r: out = (in [* pt] - y) * q_level^-1 mod q_p.  In place (out == in) is safe:
 // a thread reads each of its positions before writing it, and no other thread touches them.
 __device__ __forceinline__ void rs_epi16(const RsEpi& E, int64_t ab, int64_t nb, int ii, int p, const PrimeConst& pc,
                                          int logN, int64_t pos0, int st, const uint64_t (&y)[16]) {
@@ -252,12 +252,23 @@ __device__ __forceinline__ void rs_epi16(const RsEpi& E, int64_t ab, int64_t nb,
   const uint64_t* in = E.in.d + ct * E.in.cs + part * E.in.ps + lo;
   uint64_t* out = E.out.d + ct * E.out.cs + part * E.out.ps + lo;
   const uint64_t q = pc.q, w = E.qinv[2 * p], wsh = E.qinv[2 * p + 1];
-  uint64_t a[16];
+  const uint64_t* m = E.pt + lo;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) a[r] = in[pos0 + st * r];
-  __builtin_amdgcn_sched_barrier(0);
+  for (int h = 0; h < 16; h += 8) {  // groups of 8: all loads of a group issued before its stores
+    uint64_t a[8], b[8];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) out[pos0 + st * r] = mul_shoup(submod(a[r], y[r], q), w, wsh, q);
+    for (int r = 0; r < 8; ++r) a[r] = in[pos0 + st * (h + r)];
+    if (E.pt) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) b[r] = m[pos0 + st * (h + r)];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const uint64_t x = E.pt ? mulmod(a[r], b[r], pc) : a[r];
+      out[pos0 + st * (h + r)] = mul_shoup(submod(x, y[h + r], q), w, wsh, q);
+    }
+  }
 }
 
 // ------------------------------------------------------------------ pass A (columns)

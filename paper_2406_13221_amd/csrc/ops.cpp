@@ -341,7 +341,8 @@ int rotate(heqg_ctx* c, const heqg_keys* k, CtV in, CtV out, int64_t count, int 
 // the forward NTT of the other limbs forms the spread in its first pass and applies the
 // combine in its last, so neither the spread rows nor their transforms make an extra round
 // trip through memory.  Otherwise: copy, inverse NTT, spread, forward NTT, combine.
-void rescale(heqg_ctx* c, CtV in, CtV out, int64_t count, int n_poly, int level, uint64_t* ws, hipStream_t s) {
+void rescale(heqg_ctx* c, CtV in, CtV out, int64_t count, int n_poly, int level, uint64_t* ws, hipStream_t s,
+             const uint64_t* pt) {
   const int N = c->g.N;
   uint64_t* last = ws;
   uint64_t* spread = ws + (size_t)count * n_poly * N;
@@ -352,6 +353,14 @@ void rescale(heqg_ctx* c, CtV in, CtV out, int64_t count, int n_poly, int level,
     xi.in = in.d + (size_t)level * N;
     xi.in_sa = in.cs;
     xi.in_sb = in.ps;
+    if (pt) {
+      // in * pt: only the dropped limb is formed (in the spread rows, free until the forward
+      // NTT); the combine multiplies the other limbs as it reads them
+      k_mul_pt_launch(c->g, c->t, in, pt, CtV{spread, (int64_t)n_poly * N, N}, count, n_poly, 1, s, level);
+      xi.in = spread;
+      xi.in_sa = (int64_t)n_poly * N;
+      xi.in_sb = N;
+    }
     xi.out_centered = 1;
     launch_ntt_ex(c->t, c->g.logN, rows(last, count, (int64_t)n_poly * N, n_poly, N, 1, pl), true, xi, s);
     NttExtra xf{};
@@ -362,6 +371,7 @@ void rescale(heqg_ctx* c, CtV in, CtV out, int64_t count, int n_poly, int level,
     xf.rs.in = in;
     xf.rs.out = out;
     xf.rs.qinv = c->t.rescale + 2 * (size_t)level * c->g.n_q;
+    xf.rs.pt = pt;
     launch_ntt_ex(c->t, c->g.logN, rows_q(spread, count, (int64_t)n_poly * level * N, n_poly, (int64_t)level * N, level, 0),
                   false, xf, s);
     return;

@@ -38,7 +38,9 @@ const uint64_t* rot_key(const heqg_keys* k, uint64_t galois);
 // out = Rot(in) [+ addend]; out must not alias in
 int rotate(heqg_ctx* c, const heqg_keys* k, CtV in, CtV out, int64_t count, int level, uint64_t galois, uint64_t* ws,
            hipStream_t s, const CtV* addend = nullptr);
-void rescale(heqg_ctx* c, CtV in, CtV out, int64_t count, int n_poly, int level, uint64_t* ws, hipStream_t s);
+// pt (a plaintext [limb][N]): rescale in * pt instead; only where can_merge_rescale(level)
+void rescale(heqg_ctx* c, CtV in, CtV out, int64_t count, int n_poly, int level, uint64_t* ws, hipStream_t s,
+             const uint64_t* pt = nullptr);
 int const_int(const heqg_ctx* c, double cst, double target, int level, double in_scale, int64_t* k);
 // residues of the integer k modulo q_0..q_level with Shoup companions, appended to kr
 void const_residues(const heqg_ctx* c, int64_t k, int level, std::vector<uint64_t>& kr);
