@@ -313,21 +313,22 @@ def main():
         print("decrypted weights out of range", file=sys.stderr)
         sys.exit(1)
 
-    # dominant kernel: the fused base-conversion column pass.  It moves exactly its algorithmic bytes
-    # (every output row written once, every distinct source row read once) at a small fraction of the
-    # HBM peak and is bound by FP64 issue: the roofline is its algorithmic FP64 instructions per launch
-    # against the FP64 issue rate, with the HBM figures beside it
+    # dominant kernel: the base conversion (on the int8 matrix cores) fused into the first forward
+    # column pass.  Its algorithmic bytes: every output row written once, every distinct source row
+    # read once; the roofline is those bytes per launch against the HBM peak, with the FP64 issue
+    # figures beside it (the digit combine and the butterflies; the matrix products are a few percent
+    # of the int8 peak)
     conv_bytes = 8.0 * N * (conv_rows + conv_src)
     conv_gbs = conv_bytes / (conv_us * 1e-6) / 1e9 if conv_us > 0 else 0.0
     conv_tops = conv_ops / (conv_us * 1e-6) / 1e12 if conv_us > 0 else 0.0
-    roofline = {"bound": "alu", "achieved": round(conv_tops, 2), "peak": round(FP64_PEAK_TOPS, 2), "unit": "TFLOP/s",
-                "frac": round(conv_tops / FP64_PEAK_TOPS, 4), "traffic": pmc_traffic(conv_rows),
-                "kernel": "k_ntt_cols<8,true,true> (ModUp / ModDown base conversion fused into the first "
-                          "forward NTT pass)",
-                "ops": "FP64 instructions (an FMA counts once) per launch: output residues x (7 per conversion "
-                       "term + 3 + 4 per stage)",
-                "algorithmic_ops_per_launch": conv_ops, "algorithmic_bytes_per_launch": conv_bytes,
-                "hbm_achieved_GBps": round(conv_gbs, 1), "hbm_frac": round(conv_gbs / HBM_PEAK_GBS, 4),
+    roofline = {"bound": "hbm", "achieved": round(conv_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(conv_gbs / HBM_PEAK_GBS, 4), "traffic": pmc_traffic(conv_rows),
+                "kernel": "k_conv_cols<8,*> (ModUp / ModDown base conversion on the int8 matrix cores, fused "
+                          "into the first forward NTT pass)",
+                "bytes": "8 bytes per output residue written + 8 per source residue read, once",
+                "algorithmic_bytes_per_launch": conv_bytes, "algorithmic_fp64_ops_per_launch": conv_ops,
+                "fp64_ops": "output residues x (12 to combine the digit sums + 4 per stage)",
+                "fp64_achieved_Tops": round(conv_tops, 2), "fp64_frac": round(conv_tops / FP64_PEAK_TOPS, 4),
                 "avg_launch_us": round(conv_us, 2), "sampled_launches": conv_n,
                 "avg_rows_per_launch": round(conv_rows, 2), "avg_source_rows_per_launch": round(conv_src, 2)}
     row_pass = 16.0 * N * avg_rows / (avg_us * 1e-6) / 1e9 if avg_us > 0 else 0.0

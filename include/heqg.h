@@ -292,8 +292,8 @@ int heqg_ntt(heqg_ctx* ctx, uint64_t* dev_rows, int64_t n_rows, int first_prime,
  * the mean launch duration in microseconds, the number of sampled launches,
  * and per launch: kernel 0 - the mean number of N-word rows written; kernel 1
  * - rows written, distinct source rows read and algorithmic FP64 instructions
- * (per output residue: 7 per base-conversion term, 3 for its reduction, 4 per
- * first-pass stage); kernel 2 - rows read and written per ciphertext summed
+ * (per output residue: 12 to combine the conversion's int8 matrix-core digit
+ * sums into a residue, 4 per first-pass stage); kernel 2 - rows read and written per ciphertext summed
  * over the launch (digits + 2 per output limb) and switching-key rows read
  * (once per launch).  It releases that class's samples.  Out pointers may be
  * NULL.  Process-wide.  Returns -1 for a bad class, HEQG_ERR_DEVICE (-6) if an

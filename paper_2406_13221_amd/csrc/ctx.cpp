@@ -101,12 +101,12 @@ size_t ctx_layout(const heqg_params* p, bool check, std::string* err, size_t off
       (np + nq * np + nq) * 16,        // moddown
       nqp * N * 8,                     // tw_fwd_f
       nqp * N * 8,                     // tw_inv_f
-      nq * p->dnum * nqp * alpha * 16, // modup_f
-      nq * np * 16,                    // moddown_f
+      nq * p->dnum * nqp * alpha * 64, // modup_b
+      nq * np * 64,                    // moddown_b
       nq * nqp * 16,                   // ks_scale
       nq * nqp * 8,                    // ks_scale_f
       nq * (np + 1) * 16,              // moddown_rs
-      nq * (np + 1) * 16,              // moddown_rs_f
+      nq * (np + 1) * 64,              // moddown_rs_b
   };
   size_t o = 0;
   for (int i = 0; i < 15; ++i) {
@@ -115,6 +115,22 @@ size_t ctx_layout(const heqg_params* p, bool check, std::string* err, size_t off
   }
   if (offs) offs[15] = o;
   return o;
+}
+
+// Constants of one base-conversion term w (mod t) for the int8 matrix-core form of the
+// conversion: a source residue y enters as its eight balanced base-256 digits y_a in
+// [-128, 127] (y = sum_a y_a 256^a), and w * 256^a mod t is split the same way into digits
+// w_ab, so that  y * w = sum_b 256^b sum_a y_a w_ab  (mod t).  Word b holds w_ab in byte a.
+// Balanced digits of v < 2^63: the bytes of v + 0x80..80, each minus 128.
+static void conv_bytes(uint64_t w, uint64_t t, uint64_t out[8]) {
+  const uint64_t bias = 0x8080808080808080ull;
+  uint64_t pw = 1 % t;
+  for (int b = 0; b < 8; ++b) out[b] = 0;
+  for (int a = 0; a < 8; ++a) {
+    const uint64_t z = h_mul(w, pw, t) + bias;
+    for (int b = 0; b < 8; ++b) out[b] |= (((z >> (8 * b)) & 0xff) ^ 0x80) << (8 * a);
+    pw = h_mul(pw, 256 % t, t);
+  }
 }
 
 static void fill_pc(PrimeConst& c, uint64_t q, int log2N) {
@@ -237,10 +253,8 @@ int ctx_build(heqg_ctx* c, void* dev, size_t bytes, std::string* err) {
           uint64_t* e = tab + 2 * (alpha + gi * alpha + k);
           e[0] = hat;
           e[1] = h_shoup(hat, t);
-          double* ef = reinterpret_cast<double*>(host.data() + offs[9]) +
-                       2 * ((((size_t)l * p->dnum + j) * nqp + gi) * alpha + k);
-          ef[0] = (double)hat;
-          ef[1] = (double)h_mul(hat, (uint64_t)((((hu128)1) << 32) % t), t);
+          conv_bytes(hat, t, reinterpret_cast<uint64_t*>(host.data() + offs[9]) +
+                                 8 * ((((size_t)l * p->dnum + j) * nqp + gi) * alpha + k));
         }
       }
     }
@@ -263,9 +277,7 @@ int ctx_build(heqg_ctx* c, void* dev, size_t bytes, std::string* err) {
       uint64_t* e = md + 2 * np + 2 * ((size_t)i * np + k);
       e[0] = hat;
       e[1] = h_shoup(hat, qi);
-      double* ef = reinterpret_cast<double*>(host.data() + offs[10]) + 2 * ((size_t)i * np + k);
-      ef[0] = (double)hat;
-      ef[1] = (double)h_mul(hat, (uint64_t)((((hu128)1) << 32) % qi), qi);
+      conv_bytes(hat, qi, reinterpret_cast<uint64_t*>(host.data() + offs[10]) + 8 * ((size_t)i * np + k));
       P = h_mul(P, c->primes[nq + k] % qi, qi);
     }
     uint64_t pinv = h_inv(P, qi);
@@ -277,14 +289,12 @@ int ctx_build(heqg_ctx* c, void* dev, size_t bytes, std::string* err) {
     // ModDown merged with the following rescale: the np factors P/p_k above, then P itself
     // (the factor of the rescale's spread, folded in before the division by P)
     uint64_t* mr = reinterpret_cast<uint64_t*>(host.data() + offs[13]) + 2 * (size_t)i * (np + 1);
-    double* mrf = reinterpret_cast<double*>(host.data() + offs[14]) + 2 * (size_t)i * (np + 1);
-    const uint64_t two32 = (uint64_t)((((hu128)1) << 32) % qi);
+    uint64_t* mrb = reinterpret_cast<uint64_t*>(host.data() + offs[14]) + 8 * (size_t)i * (np + 1);
     for (int k = 0; k <= np; ++k) {
       const uint64_t w = k < np ? md[2 * np + 2 * ((size_t)i * np + k)] : P;
       mr[2 * k] = w;
       mr[2 * k + 1] = h_shoup(w, qi);
-      mrf[2 * k] = (double)w;
-      mrf[2 * k + 1] = (double)h_mul(w, two32, qi);
+      conv_bytes(w, qi, mrb + 8 * k);
     }
   }
   // key-switch INTT output scales: N^-1 times the first factor of each base conversion
@@ -343,12 +353,12 @@ int ctx_build(heqg_ctx* c, void* dev, size_t bytes, std::string* err) {
   c->t.moddown = reinterpret_cast<const uint64_t*>(d + offs[6]);
   c->t.tw_fwd_f = reinterpret_cast<const double*>(d + offs[7]);
   c->t.tw_inv_f = reinterpret_cast<const double*>(d + offs[8]);
-  c->t.modup_f = reinterpret_cast<const double*>(d + offs[9]);
-  c->t.moddown_f = reinterpret_cast<const double*>(d + offs[10]);
+  c->t.modup_b = reinterpret_cast<const uint64_t*>(d + offs[9]);
+  c->t.moddown_b = reinterpret_cast<const uint64_t*>(d + offs[10]);
   c->t.ks_scale = reinterpret_cast<const uint64_t*>(d + offs[11]);
   c->t.ks_scale_f = reinterpret_cast<const double*>(d + offs[12]);
   c->t.moddown_rs = reinterpret_cast<const uint64_t*>(d + offs[13]);
-  c->t.moddown_rs_f = reinterpret_cast<const double*>(d + offs[14]);
+  c->t.moddown_rs_b = reinterpret_cast<const uint64_t*>(d + offs[14]);
   return HEQG_OK;
 }
 

@@ -55,27 +55,29 @@ struct NttExtra {
   int64_t in_sa, in_sb;
   uint64_t galois;
   // inverse, last pass: multiply by scale[p] (pairs w, Shoup(w)) / scalef[p] instead of N^-1;
-  // out_f64: rows of primes of at most FP_MAX_BITS bits are written as doubles (the
-  // canonical residue's value), the form a base conversion reads them in
+  // out_digits: write each residue as its eight balanced base-256 digits, the form a base
+  // conversion reads (the int8 bytes of (v + 0x80..80) ^ 0x80..80, v as a signed integer)
   const uint64_t* scale;
   const double* scalef;
-  int out_f64;
-  // out_centered (primes of at most FP_MAX_BITS bits): write the representative in
-  // [-(q-1)/2, (q-1)/2] as a double instead, the form the rescale's spread reads
+  int out_digits;
+  // out_centered (primes of at most FP_MAX_BITS bits): the representative in
+  // [-(q-1)/2, (q-1)/2] instead of the canonical one; a double unless out_digits is set
+  // (the form the rescale's spread reads)
   int out_centered;
   // forward, first pass: the input of row (ia, ib, ii) is the base conversion
-  //   sum_s csrc_s * hat[p][s]  mod q_p,  csrc_s = csrc + ia*csrc_sa + ib*csrc_sb + s*N
-  // with hat pairs (w, Shoup(w)) at chat + 2*(p*cstride + s) and FP64 pairs
-  // (w, 2^32 w mod q_p) at chatf + 2*(p*cstride + s).  Bit s of csplit: source s
-  // exceeds FP_MAX_BITS bits and holds canonical integers, so FP64 products take it in
-  // 32-bit halves; every other source holds its residues as doubles (out_f64)
+  //   sum_s csrc_s * hat[p][s]  mod q_p,  csrc_s = csrc + ia*csrc_sa + ib*csrc_sb + s*N,
+  // every source row in digit form (out_digits).  Targets of at most FP_MAX_BITS bits take
+  // the sum on the int8 matrix cores from the digit-split constants at
+  // cbyte + 8*(p*cstride + s); bit ii of tint marks a wider target, which takes it from the
+  // pairs (w, Shoup(w)) at chat + 2*(p*cstride + s)
   const uint64_t* csrc;
   int64_t csrc_sa, csrc_sb;
-  int ns, cstride, csplit;
+  int ns, cstride;
   const uint64_t* chat;
-  const double* chatf;
+  const uint64_t* cbyte;
+  uint64_t tint;
   // with cextra set, the last source (s = ns - 1) is read from cextra + ia*cextra_sa +
-  // ib*cextra_sb instead: centred residues held as doubles (out_centered)
+  // ib*cextra_sb instead (digit form of centred residues)
   const uint64_t* cextra;
   int64_t cextra_sa, cextra_sb;
   // forward, last pass: key-switch combine instead of a plain store
@@ -124,13 +126,16 @@ struct DevTables {
   const uint64_t* moddown;   // inv_hatP [n_p][2], hatP [n_q][n_p][2], Pinv [n_q][2]
   const double* tw_fwd_f;    // [nqp][N]: psi^brv(k) as doubles (primes of <= FP_MAX_BITS bits)
   const double* tw_inv_f;    // [nqp][N]: psi^-brv(k) as doubles
-  const double* modup_f;     // [n_q][dnum][nqp][alpha][2]: (D/s_k mod t, 2^32 * D/s_k mod t) as doubles
-  const double* moddown_f;   // [n_q][n_p][2]: (P/p_k mod q_i, 2^32 * P/p_k mod q_i) as doubles
+  // [n_q][dnum][nqp][alpha][8], [n_q][n_p][8], [n_q][n_p + 1][8]: the conversion constants of
+  // modup, moddown (P/p_k mod q_i) and moddown_rs split into balanced base-256 digits for the
+  // int8 matrix cores: word b of entry (t, s) holds digit b of w * 256^a mod t in byte a
+  const uint64_t* modup_b;
+  const uint64_t* moddown_b;
   const uint64_t* ks_scale;  // [n_q][nqp][2]: at level l, N^-1 * (D/s)^-1 mod s for Q prime s in its
                              // digit D, N^-1 * (P/p)^-1 mod p for special prime p (+Shoup)
   const double* ks_scale_f;  // [n_q][nqp]: the same as doubles
   const uint64_t* moddown_rs;  // [n_q][n_p + 1][2]: P/p_k mod q_i (k < n_p), then P mod q_i (+Shoup)
-  const double* moddown_rs_f;  // [n_q][n_p + 1][2]: (w, 2^32 w mod q_i) of the same as doubles
+  const uint64_t* moddown_rs_b;
 };
 
 // Geometry the kernels need.

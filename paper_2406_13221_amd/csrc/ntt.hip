@@ -80,6 +80,10 @@ struct NttParams {
   int tiles;
   int group;
   NttExtra X;
+  // base conversion: the launch's target rows ii, those of at most FP_MAX_BITS bits first
+  // (nfp of them), then the wider ones (nint)
+  int nfp, nint;
+  uint8_t cmap[HEQG_MAX_PRIMES];
 };
 
 // ------------------------------------------------------------------ integer butterflies
@@ -181,6 +185,17 @@ __device__ __forceinline__ void stages_contig(V (&x)[16], const TW* tw, int64_t 
 __device__ __forceinline__ double as_f(uint64_t v) { return __longlong_as_double((long long)v); }
 __device__ __forceinline__ uint64_t as_u(double v) { return (uint64_t)__double_as_longlong(v); }
 
+// Digit form of a residue v (|v| < 2^62): its eight balanced base-256 digits v_a in
+// [-128, 127], v = sum_a v_a 256^a, as the int8 bytes of one word.  The bytes of
+// v + 0x80..80 are v_a + 128, so the word is (v + 0x80..80) ^ 0x80..80.
+constexpr uint64_t kDigitBias = 0x8080808080808080ull;
+__device__ __forceinline__ int64_t digits_value(uint64_t d) { return (int64_t)((d ^ kDigitBias) - kDigitBias); }
+// of an integer |t| < 2^51 held in a double: the bits of t + 1.5*2^52 are 0x4338..0 + t
+__device__ __forceinline__ uint64_t f_digits(double t) {
+#pragma clang fp contract(off)
+  return (as_u(t + 6755399441055744.0) + (kDigitBias - 0x4338000000000000ull)) ^ kDigitBias;
+}
+
 // ------------------------------------------------------------------ fused prologue / epilogue helpers
 // Workgroup index -> (unit, sub), sub fastest, such that the nsub workgroups of one unit
 // run on one XCD (workgroups are dispatched round-robin over the 8 XCDs), so data they
@@ -272,12 +287,14 @@ __device__ __forceinline__ void rs_epi16(const RsEpi& E, int64_t ab, int64_t nb,
 }
 
 // ------------------------------------------------------------------ pass A (columns)
-// CONV (forward only): the input is the base conversion of the rows at cs.
-// sp: CONV - the row of the extra (last) source, centred doubles, or null; forward, not
-// CONV - the rescale's centred source row, or null.
+// CONV (forward, integer path only): the input is the base conversion of the digit-form
+// rows at cs; targets of at most FP_MAX_BITS bits take it in convq_body instead.
+// sp: CONV - the row of the extra (last) source, or null; forward, not CONV - the
+// rescale's centred source row, or null.
 template <int LOGS, bool FWD, bool CONV, bool FP>
 __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, const uint64_t* cs, const uint64_t* sp,
                                           int p, int tile, uint64_t* lds) {
+  static_assert(!(CONV && FP), "FP64 targets convert on the matrix cores");
   constexpr int S = 1 << LOGS, T = S / 16, C = 256 / T;
   const int tid = threadIdx.x;
   const PrimeConst pc = P.pc[p];
@@ -298,51 +315,7 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
     };
     double x[16];
     if (FWD) {
-      if (CONV) {
-        // sum of at most 2*16 products, each |.| < 0.53 q: exact.  Up to 8 terms (every
-        // conversion of the paper's parameters) the sum (< 4.3 q) goes into the transform as
-        // it is: 16 lazy stages then keep |x| < 13 q, inside fmulmod's range; more terms are
-        // reduced to |x| <= q/2 + 1 first.
-        const cptr<double> h = to_const(P.X.chatf + 2 * (int64_t)p * P.X.cstride);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) x[r] = 0.0;
-        const uint32_t all = (1u << P.X.ns) - 1;
-        // sources wider than the FP64 path hold integers: two products (high and low
-        // 32 bits) per term.  One loop per kind, each over the set bits of its mask,
-        // so that neither carries a branch.
-#pragma unroll 1
-        for (uint32_t m = P.X.csplit & all; m; m &= m - 1) {
-          const int s = __builtin_ctz(m);
-          const RowBuf ys(sp && s == P.X.ns - 1 ? sp : cs + ((int64_t)s << P.logN));
-          const double h0 = h[2 * s], h1 = h[2 * s + 1];
-          uint64_t y[16];
-#pragma unroll
-          for (int r = 0; r < 16; ++r) y[r] = ys.ld(vs, r * us);
-          __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-          for (int r = 0; r < 16; ++r)
-            x[r] += fmulmod((double)(uint32_t)(y[r] >> 32), h1, q, qi) + fmulmod((double)(uint32_t)y[r], h0, q, qi);
-        }
-        // the others hold doubles
-#pragma unroll 1
-        for (uint32_t m = ~P.X.csplit & all; m; m &= m - 1) {
-          const int s = __builtin_ctz(m);
-          const RowBuf ys(sp && s == P.X.ns - 1 ? sp : cs + ((int64_t)s << P.logN));
-          const double h0 = h[2 * s];
-          // all 16 loads are issued before any use (left to itself the compiler waits on
-          // each load in turn)
-          uint64_t y[16];
-#pragma unroll
-          for (int r = 0; r < 16; ++r) y[r] = ys.ld(vs, r * us);
-          __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-          for (int r = 0; r < 16; ++r) x[r] += fmulmod(as_f(y[r]), h0, q, qi);
-        }
-        if (P.X.ns + __builtin_popcount(P.X.csplit & all) > 8) {
-#pragma unroll
-          for (int r = 0; r < 16; ++r) x[r] = fred(x[r], q, qi);
-        }
-      } else if (sp) {
+      if (sp) {
         // spread: the centered residue of the rescaled-away limb, |y| <= (q_l - 1)/2, reduced
         const RowBuf sb(sp);
 #pragma unroll
@@ -371,16 +344,20 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
       for (int r = 0; r < 16; ++r) x[r] = as_f(lds[(kg + T * r) * C + cl]);
       stages_strided<false>(x, to_const(tw), 1, bf);
       const double sd = P.X.scalef ? P.X.scalef[p] : pc.ninv_d;
-      if (P.X.out_centered) {
+      if (P.X.out_digits) {
+        const double half = P.X.out_centered ? (q - 1.0) * 0.5 : q;  // q odd: exact
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const double t = fcanon_d(fmulmod(x[r], sd, q, qi), q, qi);
+          rb.st(f_digits(t > half ? t - q : t), vs, r * us);
+        }
+      } else if (P.X.out_centered) {
         const double half = (q - 1.0) * 0.5;  // q odd: exact
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const double t = fcanon_d(fmulmod(x[r], sd, q, qi), q, qi);
           rb.st(as_u(t > half ? t - q : t), vs, r * us);
         }
-      } else if (P.X.out_f64) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) rb.st(as_u(fcanon_d(fmulmod(x[r], sd, q, qi), q, qi)), vs, r * us);
       } else {
 #pragma unroll
         for (int r = 0; r < 16; ++r) rb.st(fcanon(fmulmod(x[r], sd, q, qi), q, qi), vs, r * us);
@@ -403,19 +380,20 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
         for (int s = 0; s < P.X.ns; ++s) {
           const RowBuf ys(sp && s == P.X.ns - 1 ? sp : cs + ((int64_t)s << P.logN));
           const uint64_t w = h[2 * s], wsh = h[2 * s + 1];
-          const bool as_double = !((P.X.csplit >> s) & 1);
-          uint64_t y[16];
 #pragma unroll
-          for (int r = 0; r < 16; ++r) y[r] = ys.ld(vs, r * us);
-          __builtin_amdgcn_sched_barrier(0);
+          for (int g = 0; g < 16; g += 8) {  // 8 loads in flight at a time: registers for 4 waves/SIMD
+            uint64_t y[8];
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            // a double source may hold a centred (negative) residue: its canonical value
-            // mod q (|y| < 2^42 < q on this path)
-            const int64_t yi = fint_to_i64(as_f(y[r]));
-            const uint64_t yr = as_double ? (yi < 0 ? (uint64_t)(yi + (int64_t)q) : (uint64_t)yi) : y[r];
-            const uint64_t v = x[r] + mul_shoup_lazy(yr, w, wsh, q);
-            x[r] = v >= two_q ? v - two_q : v;
+            for (int r = 0; r < 8; ++r) y[r] = ys.ld(vs, (g + r) * us);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+              // the source's residue from its digits: canonical, or centred with |y| < 2^42 < q
+              const int64_t yi = digits_value(y[r]);
+              const uint64_t yr = yi < 0 ? (uint64_t)(yi + (int64_t)q) : (uint64_t)yi;
+              const uint64_t v = x[g + r] + mul_shoup_lazy(yr, w, wsh, q);
+              x[g + r] = v >= two_q ? v - two_q : v;
+            }
           }
         }
       } else if (sp) {
@@ -451,42 +429,230 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
       stages_strided<false>(x, tw, 1, bf);
       const uint64_t sw = P.X.scale ? P.X.scale[2 * p] : pc.ninv;
       const uint64_t ssh = P.X.scale ? P.X.scale[2 * p + 1] : pc.ninv_sh;
+      if (P.X.out_digits) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) rb.st(mul_shoup(x[r], sw, ssh, q), vs, r * us);
+        for (int r = 0; r < 16; ++r) rb.st((mul_shoup(x[r], sw, ssh, q) + kDigitBias) ^ kDigitBias, vs, r * us);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) rb.st(mul_shoup(x[r], sw, ssh, q), vs, r * us);
+      }
     }
   }
 }
 
-template <int LOGS, bool FWD, bool CONV>
+template <int LOGS, bool FWD>
 __global__ void __launch_bounds__(256) k_ntt_cols(NttParams P) {
   static_assert(LOGS >= 6 && LOGS <= 8, "16 residues per thread cover 4 strided + 4 contiguous stages");
   __shared__ uint64_t lds[4096];
   const int64_t nab = P.na * P.nb;
-  int64_t ab;
-  int ii, tile;
-  if (CONV) {
-    // the target rows of one (ab, tile) share their source tiles: keep them on one XCD
-    int64_t unit, sub;
-    xcd_map(blockIdx.x, P.ni, nab * P.tiles, unit, sub);
-    ii = (int)sub;
-    tile = (int)(unit % P.tiles);
-    ab = unit / P.tiles;
-  } else {
-    tile = (int)(blockIdx.x % P.tiles);
-    const int64_t rest = blockIdx.x / P.tiles;
-    ab = rest % nab;
-    ii = (int)(rest / nab);
-  }
-  const int64_t ia = ab / P.nb, ib = ab % P.nb;
+  const int tile = (int)(blockIdx.x % P.tiles);
+  const int64_t rest = blockIdx.x / P.tiles;
+  const int64_t ab = rest % nab, ia = ab / P.nb, ib = ab % P.nb;
+  const int ii = (int)(rest / nab);
   uint64_t* row = P.data + ia * P.sa + ib * P.sb + ((int64_t)ii << P.logN);
-  const uint64_t* cs = CONV ? P.X.csrc + ia * P.X.csrc_sa + ib * P.X.csrc_sb : nullptr;
-  const uint64_t* sp = CONV ? (P.X.cextra ? P.X.cextra + ia * P.X.cextra_sa + ib * P.X.cextra_sb : nullptr)
-                            : (FWD && P.X.spread ? P.X.spread + ia * P.X.spread_sa + ib * P.X.spread_sb : nullptr);
+  const uint64_t* sp = FWD && P.X.spread ? P.X.spread + ia * P.X.spread_sa + ib * P.X.spread_sb : nullptr;
   const int p = P.pidx[ii];
   if (P.pc[p].k <= FP_MAX_BITS)
-    cols_body<LOGS, FWD, CONV, true>(P, row, cs, sp, p, tile, lds);
+    cols_body<LOGS, FWD, false, true>(P, row, nullptr, sp, p, tile, lds);
   else
-    cols_body<LOGS, FWD, CONV, false>(P, row, cs, sp, p, tile, lds);
+    cols_body<LOGS, FWD, false, false>(P, row, nullptr, sp, p, tile, lds);
+}
+
+// ------------------------------------------------------------------ base conversion
+// The conversion  y_t = sum_s x_s * w[t][s] mod p_t  of one coefficient is a dot product;
+// over a tile of coefficients and four targets it is a small matrix product, run on the
+// int8 matrix cores exactly: the sources come in digit form (eight balanced base-256 digits,
+// written by the inverse NTT that produces them) and each constant w[t][s] * 256^a mod p_t
+// is split the same way into digits w_ab (conv_bytes on the host), so that
+//   y_t = sum_b 256^b R[t][b],   R[t][b] = sum_{s, a} x_sa * w_ab   (|R| < 2^21, exact in int32).
+// One v_mfma_i32_32x32x32_i8 takes four sources (32 digits) for 32 coefficients (the B
+// columns) and the 32 (target, b) rows of A; lane l holds column l % 32 and the rows
+// 8*(v/4) + 4*(l/32) + v%4, v < 16, and rows are assigned so that this is target 2*(l/32) + v/8,
+// digit b = v % 8: every lane finishes two targets of its coefficient alone.
+
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+typedef int v16i_t __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ v4i_t pack2(uint64_t a, uint64_t b) {
+  v4i_t v;
+  v[0] = (int)(uint32_t)a;
+  v[1] = (int)(uint32_t)(a >> 32);
+  v[2] = (int)(uint32_t)b;
+  v[3] = (int)(uint32_t)(b >> 32);
+  return v;
+}
+
+// sum_{b < 6} 256^b R[o + b] mod q as a double x with |x| <= q/2 + 2^10 (digits 6 and 7 of a
+// constant below 2^48 are zero): lo = R0 + 2^8 R1 + 2^16 R2 and hi = 2^24 (R3 + 2^8 R4 +
+// 2^16 R5) are exact (|lo| < 2^38, hi a multiple of 2^24 below 2^62); the quotient comes from
+// their rounded sum, and hi - qt*q (an FMA) is exact because it is an integer below 2^53.
+template <int O>
+__device__ __forceinline__ double digits_combine(const v16i_t& acc, double q, double qi) {
+#pragma clang fp contract(off)
+  const int lo32 = acc[O] + (int)((uint32_t)acc[O + 1] << 8);
+  const int mi32 = acc[O + 3] + (int)((uint32_t)acc[O + 4] << 8);
+  const double lo = __fma_rn((double)acc[O + 2], 65536.0, (double)lo32);
+  const double hi = __fma_rn((double)acc[O + 5], 0x1p40, (double)mi32 * 0x1p24);
+  const double qt = __builtin_rint((hi + lo) * qi);
+  return __fma_rn(-qt, q, hi) + lo;
+}
+
+// LDS words of one lane half's exchange region in convq_body: rows of C2 words, padded by C2
+// words every 16 rows so that the 16-row groups read together start on different banks
+template <int LOGS>
+constexpr int convq_lds_words() {
+  constexpr int T = (1 << LOGS) / 16, C2 = 128 / T;
+  return (1 << LOGS) * C2 + (C2 <= 16 ? T * C2 : 0);
+}
+
+// Conversion into up to four FP64 targets (quad) over a tile of C2 = 128/T columns, then the
+// first forward pass of each.  Thread slot sig = (wave, lane % 32) owns column cl = sig % C2
+// and the strided elements {kg + T*r} of it (kg = sig / C2), lane half h = lane / 32 the
+// targets 2h and 2h + 1; block r of the conversion is row kg + T*r of the 32 slots of a wave.
+// NM matrix products cover the ns <= 4*NM sources.
+template <int LOGS, int NM>
+__device__ __forceinline__ void convq_body(const NttParams& P, uint64_t* obase, const uint64_t* cs,
+                                           const uint64_t* sp, int quad, int ctile, uint64_t* lds) {
+#pragma clang fp contract(off)
+  constexpr int S = 1 << LOGS, T = S / 16, C2 = 128 / T, PAD = C2 <= 16 ? C2 : 0;
+  const int tid = threadIdx.x, l = tid & 63, h = l >> 5;
+  const int sig = ((tid >> 6) << 5) | (l & 31);
+  const int cl = sig % C2, kg = sig / C2;
+  const int N2 = 1 << (P.logN - LOGS);
+  const int c = ctile * C2 + cl;
+  const uint32_t vs = (uint32_t)(kg * N2 + c) * 8, us = (uint32_t)(T * N2) * 8;
+  const uint32_t vc = (uint32_t)(16 * kg * N2 + c) * 8, uc = (uint32_t)N2 * 8;
+  const int nt = min(4, P.nfp - 4 * quad);
+  int tii[4], tp[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    tii[t] = P.cmap[4 * quad + (t < nt ? t : 0)];
+    tp[t] = P.pidx[tii[t]];
+  }
+  const int ns = P.X.ns;
+  // A: row i = lane % 32 is (target ta, digit ba); lane half h brings sources 4m + 2h, +1
+  v4i_t A[NM];
+  {
+    const int i = l & 31;
+    const int ta = 2 * ((i >> 2) & 1) + (i >> 4), ba = 4 * ((i >> 3) & 1) + (i & 3);
+    const int pa = ta == 0 ? tp[0] : ta == 1 ? tp[1] : ta == 2 ? tp[2] : tp[3];
+    const uint64_t* cb = P.X.cbyte + 8 * ((int64_t)pa * P.X.cstride) + ba;
+    const bool act = ta < nt;
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      const int s0 = 4 * m + 2 * h, s1 = s0 + 1;
+      A[m] = pack2(act && s0 < ns ? cb[8 * s0] : 0, act && s1 < ns ? cb[8 * s1] : 0);
+    }
+  }
+  // this lane's two targets
+  const int t0 = 2 * h, t1 = t0 + 1;
+  const int p0 = h ? tp[2] : tp[0], p1 = h ? tp[3] : tp[1];
+  const int i0 = h ? tii[2] : tii[0], i1 = h ? tii[3] : tii[1];
+  const double q0 = P.pc[p0].qd, qi0 = P.pc[p0].qinv, q1 = P.pc[p1].qd, qi1 = P.pc[p1].qinv;
+  // sources: rows of cs (nsc of them), the last one from sp when given; a slot past the
+  // sources reads a valid row and is multiplied by zero constants
+  const RowBuf csb(cs), spb(sp ? sp : cs);
+  const int nsc = sp ? ns - 1 : ns;
+  const int se = sp ? ns - 1 : 4 * NM;
+  const uint32_t rowb = (uint32_t)8 << P.logN;
+  uint32_t soff[NM][2];
+#pragma unroll
+  for (int m = 0; m < NM; ++m)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) soff[m][j] = vs + (uint32_t)min(4 * m + 2 * h + j, nsc - 1) * rowb;
+  double x0[16], x1[16];
+  // software pipeline over the 16 blocks: while block r is combined (VALU), block r + 1's
+  // products run on the matrix cores and block r + 2's sources are loaded
+  uint64_t y[2][NM][2], ye[2];
+  v16i_t acc[2];
+  auto load = [&](int r, int k) {
+#pragma unroll
+    for (int m = 0; m < NM; ++m)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) y[k][m][j] = csb.ld(soff[m][j], r * us);
+    ye[k] = sp ? spb.ld(vs, r * us) : 0;
+  };
+  auto mult = [&](int k) {
+    v16i_t a = {};
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      const int s0 = 4 * m + 2 * h;
+      a = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+          A[m], pack2(s0 == se ? ye[k] : y[k][m][0], s0 + 1 == se ? ye[k] : y[k][m][1]), a, 0, 0, 0);
+    }
+    acc[k] = a;
+  };
+  load(0, 0);
+  load(1, 1);
+  mult(0);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int k = r & 1;
+    if (r + 2 < 16) load(r + 2, k);
+    if (r + 1 < 16) mult(k ^ 1);
+    __builtin_amdgcn_sched_barrier(0);
+    x0[r] = digits_combine<0>(acc[k], q0, qi0);
+    x1[r] = digits_combine<8>(acc[k], q1, qi1);
+    // in this order (left alone, the compiler sinks every block's combine below all the
+    // products, with all sixteen accumulators live)
+    asm volatile("" : "+v"(x0[r]), "+v"(x1[r]));
+  }
+  // first forward pass of each target in turn (the second waits in registers): strided
+  // stages, exchange through LDS (lane half h in its own half of it), contiguous stages, store
+  const RowBuf ob(obase);
+  uint64_t* L = lds + h * convq_lds_words<LOGS>();
+  auto pass = [&](double (&x)[16], int p, double q, double qi, bool act, int ii) {
+    const double* tw = P.twf + ((int64_t)p << P.logN);
+    auto bf = [&](double& X, double& Y, double w) { ct_f(X, Y, w, q, qi); };
+    stages_strided<true>(x, tw, 1, bf);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = kg + T * r;
+      L[row * C2 + cl + (row >> 4) * PAD] = as_u(x[r]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = 16 * kg + r;
+      x[r] = as_f(L[row * C2 + cl + (row >> 4) * PAD]);
+    }
+    stages_contig<LOGS, true>(x, tw, 1, kg, bf);
+    if (act) {
+      const uint32_t o = ((uint32_t)ii << P.logN) * 8 + vc;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) ob.st(as_u(x[r]), o, r * uc);
+    }
+  };
+  pass(x0, p0, q0, qi0, t0 < nt, i0);
+  // keep the second target's loads and arithmetic after the first's stores
+  asm volatile("" ::: "memory");
+  __syncthreads();  // the exchange region is reused
+  pass(x1, p1, q1, qi1, t1 < nt, i1);
+}
+
+// Base conversion fused into the first forward pass.  Unit = (ab, tile of C = 256/T
+// columns); its nint wider targets each take one workgroup (integer path, cols_body), its
+// FP64 targets a workgroup per quad and half tile.  All sub-blocks of a unit share the
+// source tiles: xcd_map keeps them on one XCD.
+template <int LOGS, int NM>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_conv_cols(NttParams P) {
+  static_assert(LOGS >= 6 && LOGS <= 8, "16 residues per thread cover 4 strided + 4 contiguous stages");
+  __shared__ uint64_t lds[2 * convq_lds_words<LOGS>()];
+  const int64_t nab = P.na * P.nb;
+  int64_t unit, sub;
+  xcd_map(blockIdx.x, P.nint + 2 * ((P.nfp + 3) >> 2), nab * P.tiles, unit, sub);
+  const int tile = (int)(unit % P.tiles);
+  const int64_t ab = unit / P.tiles, ia = ab / P.nb, ib = ab % P.nb;
+  uint64_t* base = P.data + ia * P.sa + ib * P.sb;
+  const uint64_t* cs = P.X.csrc + ia * P.X.csrc_sa + ib * P.X.csrc_sb;
+  const uint64_t* sp = P.X.cextra ? P.X.cextra + ia * P.X.cextra_sa + ib * P.X.cextra_sb : nullptr;
+  if (sub < P.nint) {
+    const int ii = P.cmap[P.nfp + (int)sub];
+    cols_body<LOGS, true, true, false>(P, base + ((int64_t)ii << P.logN), cs, sp, P.pidx[ii], tile, lds);
+  } else {
+    const int qh = (int)(sub - P.nint);
+    convq_body<LOGS, NM>(P, base, cs, sp, qh >> 1, 2 * tile + (qh & 1), lds);
+  }
 }
 
 // ------------------------------------------------------------------ pass B (rows)
@@ -1347,14 +1513,27 @@ void run_ntt(NttParams P, int64_t rows, bool inverse, const U2* twf, const U2* t
     P.tiles = tilesA;
     ProfSample sc;
     if (P.X.csrc) {
-      // FP64 instructions per output residue: 7 per conversion term (exact product, reduction,
-      // accumulate), 3 for the final reduction, 8 per butterfly over LA stages of N/2 each
-      const double ops = (double)rows * (double)(1 << P.logN) * (7.0 * P.X.ns + 3.0 + 4.0 * LA);
+      int nfp = 0, nint = 0;
+      for (int i = 0; i < P.ni; ++i)
+        if (!((P.X.tint >> i) & 1)) P.cmap[nfp++] = (uint8_t)i;
+      for (int i = 0; i < P.ni; ++i)
+        if ((P.X.tint >> i) & 1) P.cmap[nfp + nint++] = (uint8_t)i;
+      P.nfp = nfp;
+      P.nint = nint;
+      const unsigned blocks = (unsigned)(nab * tilesA * (nint + 2 * ((nfp + 3) / 4)));
+      // FP64 instructions per output residue: 12 to combine the digit sums into a residue,
+      // 8 per butterfly over LA stages of N/2 each
+      const double ops = (double)rows * (double)(1 << P.logN) * (12.0 + 4.0 * LA);
       sc.begin(1, rows, nab * P.X.ns, ops, s);
-      hipLaunchKernelGGL((k_ntt_cols<LA, true, true>), dim3((unsigned)(rows * tilesA)), dim3(256), 0, s, P);
+      switch ((P.X.ns + 3) / 4) {
+        case 1: hipLaunchKernelGGL((k_conv_cols<LA, 1>), dim3(blocks), dim3(256), 0, s, P); break;
+        case 2: hipLaunchKernelGGL((k_conv_cols<LA, 2>), dim3(blocks), dim3(256), 0, s, P); break;
+        case 3: hipLaunchKernelGGL((k_conv_cols<LA, 3>), dim3(blocks), dim3(256), 0, s, P); break;
+        default: hipLaunchKernelGGL((k_conv_cols<LA, 4>), dim3(blocks), dim3(256), 0, s, P); break;
+      }
       sc.end(s);
     } else {
-      hipLaunchKernelGGL((k_ntt_cols<LA, true, false>), dim3((unsigned)(rows * tilesA)), dim3(256), 0, s, P);
+      hipLaunchKernelGGL((k_ntt_cols<LA, true>), dim3((unsigned)(rows * tilesA)), dim3(256), 0, s, P);
     }
     if (P.X.cols_only) return;
     P.tiles = tilesB;
@@ -1368,7 +1547,7 @@ void run_ntt(NttParams P, int64_t rows, bool inverse, const U2* twf, const U2* t
     P.tiles = tilesB;
     if (!P.X.rows_done) launch_rows<LB, false>(P, blocksB, s);
     P.tiles = tilesA;
-    hipLaunchKernelGGL((k_ntt_cols<LA, false, false>), dim3((unsigned)(rows * tilesA)), dim3(256), 0, s, P);
+    hipLaunchKernelGGL((k_ntt_cols<LA, false>), dim3((unsigned)(rows * tilesA)), dim3(256), 0, s, P);
   }
 }
 
@@ -1455,8 +1634,11 @@ int launch_ntt_ex(const DevTables& t, int log2N, const RowSet& rs, bool inverse,
   P.twf = nullptr;
   P.tiles = 1;
   P.group = 1;
+  P.nfp = P.nint = 0;
   int64_t rows = rs.na * rs.nb * rs.ni;
   if (rows <= 0) return 0;
+  // the matrix-core conversion takes at most 16 sources
+  if (x.csrc && (x.ns < 1 || x.ns > 16 || rs.ni > HEQG_MAX_PRIMES)) return -1;
   const U2* twf = reinterpret_cast<const U2*>(t.tw_fwd);
   const U2* twi = reinterpret_cast<const U2*>(t.tw_inv);
   const int la = ntt_split_get(inverse, log2N);

@@ -165,7 +165,8 @@ size_t mul_const_ws_words(const heqg_ctx* c, int64_t count, int n_poly, int leve
 }
 
 bool can_merge_rescale(const heqg_ctx* c, int level) {
-  return level >= 1 && !(c->primes[level] >> FP_MAX_BITS);
+  // the merged ModDown has n_p + 1 conversion sources, at most 16
+  return level >= 1 && !(c->primes[level] >> FP_MAX_BITS) && c->g.n_p < 16;
 }
 
 void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, CtV base0, CtV base1, bool has_base1,
@@ -190,7 +191,7 @@ void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, 
     x.galois = galois;
     x.scale = scale;
     x.scalef = scalef;
-    x.out_f64 = 1;
+    x.out_digits = 1;
     launch_ntt_ex(c->t, g.logN, rows_q(ycoef, count, (int64_t)nl * N, 1, 0, nl, 0), true, x, s);
   }
   // 2. ModUp per digit fused into the first forward pass of its target rows
@@ -206,8 +207,8 @@ void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, 
     x.ns = sz;
     x.cstride = alpha;
     x.chat = c->t.modup + 2 * (size_t)((level * g.dnum + j) * g.mu_stride) + 2 * alpha;
-    x.chatf = c->t.modup_f + 2 * (size_t)((level * g.dnum + j) * g.nqp) * alpha;
-    for (int k = 0; k < sz; ++k) x.csplit |= (c->primes[lo + k] >> FP_MAX_BITS ? 1 : 0) << k;
+    x.cbyte = c->t.modup_b + 8 * (size_t)((level * g.dnum + j) * g.nqp) * alpha;
+    for (size_t k = 0; k < tgt.size(); ++k) x.tint |= (uint64_t)(c->primes[tgt[k]] >> FP_MAX_BITS ? 1 : 0) << k;
     x.cols_only = 1;
     launch_ntt_ex(c->t, g.logN, rows(ext + (size_t)j * nx * N, count, ext_cs, 1, 0, (int)tgt.size(), tgt.data()),
                   false, x, s);
@@ -238,7 +239,7 @@ void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, 
     x.rows_done = 1;
     x.scale = scale;
     x.scalef = scalef;
-    x.out_f64 = 1;
+    x.out_digits = 1;
     launch_ntt_ex(c->t, g.logN, rows_q(acc + (size_t)nl * N, count, (int64_t)2 * nx * N, 2, (int64_t)nx * N, np, nq),
                   true, x, s);
   }
@@ -250,13 +251,13 @@ void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, 
     x.ns = np;
     x.cstride = np;
     x.chat = c->t.moddown + 2 * np;
-    x.chatf = c->t.moddown_f;
-    for (int k = 0; k < np; ++k) x.csplit |= (c->primes[nq + k] >> FP_MAX_BITS ? 1 : 0) << k;
+    x.cbyte = c->t.moddown_b;
+    for (int k = 0; k < n; ++k) x.tint |= (uint64_t)(c->primes[first + k] >> FP_MAX_BITS ? 1 : 0) << k;
     if (merged) {
       // the rescale's spread of the centred last limb enters the conversion with factor P
       x.ns = x.cstride = np + 1;
       x.chat = c->t.moddown_rs;
-      x.chatf = c->t.moddown_rs_f;
+      x.cbyte = c->t.moddown_rs_b;
       x.cextra = lastc;
       x.cextra_sa = N;
     }
@@ -293,6 +294,7 @@ void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, 
     xi.in_sa = 2 * (int64_t)N;
     xi.in_sb = N;
     xi.out_centered = 1;
+    xi.out_digits = 1;
     launch_ntt_ex(c->t, g.logN, rows(lastc, count, 2 * (int64_t)N, 2, N, 1, pl), true, xi, s);
   }
   moddown(0, level, out, true);
