@@ -530,6 +530,13 @@ __device__ __forceinline__ void convq_body(const NttParams& P, uint64_t* obase, 
     tp[t] = P.pidx[tii[t]];
   }
   const int ns = P.X.ns;
+  // the first pass's twiddles of the four targets (S per target, one per thread), loaded now and
+  // put in LDS after the conversion
+  static_assert(S <= 256, "one twiddle per thread and target");
+  double* TW = reinterpret_cast<double*>(lds + 2 * convq_lds_words<LOGS>());
+  double twv[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) twv[t] = tid < S ? P.twf[((int64_t)tp[t] << P.logN) + tid] : 0.0;
   // A: row i = lane % 32 is (target ta, digit ba); lane half h brings sources 4m + 2h, +1
   v4i_t A[NM];
   {
@@ -601,8 +608,13 @@ __device__ __forceinline__ void convq_body(const NttParams& P, uint64_t* obase, 
   // stages, exchange through LDS (lane half h in its own half of it), contiguous stages, store
   const RowBuf ob(obase);
   uint64_t* L = lds + h * convq_lds_words<LOGS>();
-  auto pass = [&](double (&x)[16], int p, double q, double qi, bool act, int ii) {
-    const double* tw = P.twf + ((int64_t)p << P.logN);
+  if (tid < S) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) TW[t * S + tid] = twv[t];
+  }
+  __syncthreads();  // the twiddles are in LDS
+  auto pass = [&](double (&x)[16], int t, double q, double qi, bool act, int ii) {
+    const double* tw = TW + t * S;
     auto bf = [&](double& X, double& Y, double w) { ct_f(X, Y, w, q, qi); };
     stages_strided<true>(x, tw, 1, bf);
 #pragma unroll
@@ -623,11 +635,11 @@ __device__ __forceinline__ void convq_body(const NttParams& P, uint64_t* obase, 
       for (int r = 0; r < 16; ++r) ob.st(as_u(x[r]), o, r * uc);
     }
   };
-  pass(x0, p0, q0, qi0, t0 < nt, i0);
+  pass(x0, t0, q0, qi0, t0 < nt, i0);
   // keep the second target's loads and arithmetic after the first's stores
   asm volatile("" ::: "memory");
   __syncthreads();  // the exchange region is reused
-  pass(x1, p1, q1, qi1, t1 < nt, i1);
+  pass(x1, t1, q1, qi1, t1 < nt, i1);
 }
 
 // Base conversion fused into the first forward pass.  Unit = (ab, tile of C = 256/T
@@ -637,7 +649,7 @@ __device__ __forceinline__ void convq_body(const NttParams& P, uint64_t* obase, 
 template <int LOGS, int NM>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_conv_cols(NttParams P) {
   static_assert(LOGS >= 6 && LOGS <= 8, "16 residues per thread cover 4 strided + 4 contiguous stages");
-  __shared__ uint64_t lds[2 * convq_lds_words<LOGS>()];
+  __shared__ uint64_t lds[2 * convq_lds_words<LOGS>() + 4 * (1 << LOGS)];
   const int64_t nab = P.na * P.nb;
   int64_t unit, sub;
   xcd_map(blockIdx.x, P.nint + 2 * ((P.nfp + 3) >> 2), nab * P.tiles, unit, sub);
