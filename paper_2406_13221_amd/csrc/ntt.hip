@@ -569,8 +569,8 @@ __device__ __forceinline__ void convq_body(const NttParams& P, uint64_t* obase, 
     for (int j = 0; j < 2; ++j) soff[m][j] = vs + (uint32_t)min(4 * m + 2 * h + j, nsc - 1) * rowb;
   double x0[16], x1[16];
   // software pipeline over the 16 blocks: while block r is combined (VALU), block r + 1's
-  // products run on the matrix cores and block r + 2's sources are loaded
-  uint64_t y[2][NM][2], ye[2];
+  // products run on the matrix cores and block r + 3's sources are loaded
+  uint64_t y[3][NM][2], ye[3];
   v16i_t acc[2];
   auto load = [&](int r, int k) {
 #pragma unroll
@@ -579,7 +579,7 @@ __device__ __forceinline__ void convq_body(const NttParams& P, uint64_t* obase, 
       for (int j = 0; j < 2; ++j) y[k][m][j] = csb.ld(soff[m][j], r * us);
     ye[k] = sp ? spb.ld(vs, r * us) : 0;
   };
-  auto mult = [&](int k) {
+  auto mult = [&](int k, int ka) {
     v16i_t a = {};
 #pragma unroll
     for (int m = 0; m < NM; ++m) {
@@ -587,16 +587,17 @@ __device__ __forceinline__ void convq_body(const NttParams& P, uint64_t* obase, 
       a = __builtin_amdgcn_mfma_i32_32x32x32_i8(
           A[m], pack2(s0 == se ? ye[k] : y[k][m][0], s0 + 1 == se ? ye[k] : y[k][m][1]), a, 0, 0, 0);
     }
-    acc[k] = a;
+    acc[ka] = a;
   };
   load(0, 0);
   load(1, 1);
-  mult(0);
+  load(2, 2);
+  mult(0, 0);
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int k = r & 1;
-    if (r + 2 < 16) load(r + 2, k);
-    if (r + 1 < 16) mult(k ^ 1);
+    if (r + 3 < 16) load(r + 3, r % 3);
+    if (r + 1 < 16) mult((r + 1) % 3, k ^ 1);
     __builtin_amdgcn_sched_barrier(0);
     x0[r] = digits_combine<0>(acc[k], q0, qi0);
     x1[r] = digits_combine<8>(acc[k], q1, qi1);
