@@ -24,6 +24,10 @@
 //  * larger primes: 64-bit Shoup multiplication with lazy reduction (Harvey);
 //    forward values live in [0, 4q), inverse in [0, 2q).
 // Both paths produce the canonical residues of the same transform.
+//
+// A base conversion into the first forward pass (k_conv_cols) computes its sums of
+// products on the int8 matrix cores from sources and constants split into balanced
+// base-256 digits, exactly (see the base conversion section below).
 #include <mutex>
 #include <vector>
 
