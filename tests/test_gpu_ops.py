@@ -111,6 +111,20 @@ def test_relin_hmult_bit_exact(env):
                    "hmult-low")
 
 
+def test_key_switch_every_level_bit_exact(env):
+    """Relinearisation and rotation at every level from the top down to 1: every digit count and
+    last-digit size (1..alpha conversion sources, one or two matrix products), target quads that
+    are full or partial, and targets above 42 bits (the integer path of the same launch)."""
+    ctx, ora, keys = env["ctx"], env["ora"], env["keys"]
+    L = ora.top_level
+    st = env["steps"][0]
+    for lv in range(L, 0, -1):
+        g = ctx.drop(env["g1"], lv) if lv < L else env["g1"]
+        o = ora.drop(env["o1"], lv) if lv < L else env["o1"]
+        assert_same_ct(ctx.relin(keys, ctx.tensor(g, g)), ora.relin(ora.tensor(o, o)), "relin@%d" % lv)
+        assert_same_ct(ctx.rotate(keys, g, st), ora.rotate(o, st), "rot@%d" % lv)
+
+
 def test_rescale_bit_exact(env):
     ctx, ora = env["ctx"], env["ora"]
     assert_same_ct(ctx.rescale(env["g1"]), ora.rescale(env["o1"]), "rescale")
