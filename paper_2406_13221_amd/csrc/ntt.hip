@@ -69,6 +69,13 @@ struct RowBuf {
     x[1] = (uint32_t)(d >> 32);
     __builtin_amdgcn_raw_buffer_store_b64(x, r, v, u, 0);
   }
+  // the same with the non-temporal hint (streamed to memory rather than kept in the caches)
+  __device__ __forceinline__ void st_nt(uint64_t d, uint32_t v, uint32_t u) const {
+    decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)) x;
+    x[0] = (uint32_t)d;
+    x[1] = (uint32_t)(d >> 32);
+    __builtin_amdgcn_raw_buffer_store_b64(x, r, v, u, 2);
+  }
 };
 
 struct NttParams {
@@ -420,7 +427,12 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
       for (int r = 0; r < 16; ++r) x[r] = lds[(16 * kg + r) * C + cl];
       stages_contig<LOGS, true>(x, tw, 1, kg, bf);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) rb.st(x[r], vc, r * uc);
+      for (int r = 0; r < 16; ++r) {
+        if (CONV)
+          rb.st_nt(x[r], vc, r * uc);
+        else
+          rb.st(x[r], vc, r * uc);
+      }
     } else {
 #pragma unroll
       for (int r = 0; r < 16; ++r) x[r] = rb.ld(vc, r * uc);
@@ -637,7 +649,7 @@ __device__ __forceinline__ void convq_body(const NttParams& P, uint64_t* obase, 
     if (act) {
       const uint32_t o = ((uint32_t)ii << P.logN) * 8 + vc;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) ob.st(as_u(x[r]), o, r * uc);
+      for (int r = 0; r < 16; ++r) ob.st_nt(as_u(x[r]), o, r * uc);
     }
   };
   pass(x0, t0, q0, qi0, t0 < nt, i0);
