@@ -313,15 +313,14 @@ def main():
         print("decrypted weights out of range", file=sys.stderr)
         sys.exit(1)
 
-    # dominant kernel: the base conversion (on the int8 matrix cores) fused into the first forward
-    # column pass.  Its algorithmic bytes: every output row written once, every distinct source row
+    # the base conversion (on the int8 matrix cores) fused into the first forward column pass.  Its algorithmic bytes: every output row written once, every distinct source row
     # read once; the roofline is those bytes per launch against the HBM peak, with the FP64 issue
     # figures beside it (the digit combine and the butterflies; the matrix products are a few percent
     # of the int8 peak)
     conv_bytes = 8.0 * N * (conv_rows + conv_src)
     conv_gbs = conv_bytes / (conv_us * 1e-6) / 1e9 if conv_us > 0 else 0.0
     conv_tops = conv_ops / (conv_us * 1e-6) / 1e12 if conv_us > 0 else 0.0
-    roofline = {"bound": "hbm", "achieved": round(conv_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+    conv_roofline = {"bound": "hbm", "achieved": round(conv_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(conv_gbs / HBM_PEAK_GBS, 4), "traffic": pmc_traffic(conv_rows),
                 "kernel": "k_conv_cols<8,*> (ModUp / ModDown base conversion on the int8 matrix cores, fused "
                           "into the first forward NTT pass)",
@@ -338,15 +337,19 @@ def main():
                         "avg_launch_us": round(avg_us, 2), "sampled_launches": n_sampled,
                         "avg_rows_per_launch": round(avg_rows, 2)}
 
-    # the ModUp row pass fused with the key inner product: ciphertext rows read and written plus the
-    # switching-key rows, each read once per launch
+    # dominant kernel: the ModUp row pass fused with the key inner product.  Its algorithmic bytes:
+    # ciphertext rows read and written plus the switching-key rows, each read once per launch.  Its
+    # rocprofv3 FETCH_SIZE / WRITE_SIZE (profiles/hbm_bytes_c3.md) were taken at 16 blocks per chunk
+    # only, so no per-launch traffic figure is claimed for the launch size timed here
     ks_bytes = 8.0 * N * (ks_rows + ks_keyrows)
     ks_rate = ks_bytes / (ks_us * 1e-6) / 1e9 if ks_us > 0 else 0.0
-    ks_row_roofline = {"bound": "hbm", "achieved": round(ks_rate, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": round(ks_rate / HBM_PEAK_GBS, 4),
-                       "kernel": "k_ntt_rows_ks<8> (ModUp second forward pass fused with the key inner product)",
-                       "algorithmic_bytes_per_launch": ks_bytes, "avg_launch_us": round(ks_us, 2),
-                       "sampled_launches": ks_n}
+    roofline = {"bound": "hbm", "achieved": round(ks_rate, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ks_rate / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_ntt_rows_ks8 (ModUp second forward pass of every digit fused with the key inner "
+                          "product; the P limbs' first inverse pass)",
+                "bytes": "8 bytes per ciphertext residue read (digits) and written (2 parts), key rows once",
+                "algorithmic_bytes_per_launch": ks_bytes, "avg_launch_us": round(ks_us, 2),
+                "sampled_launches": ks_n}
 
     model = iteration_model_bytes(cfg, run.Z.count)
     it_roof = {"model_bytes": model, "achieved_GBps": round(model / upd / 1e9, 1), "peak": HBM_PEAK_GBS,
@@ -375,8 +378,8 @@ def main():
         "ntt_gbps": {"forward": round(fwd_gbs, 1), "inverse": round(inv_gbs, 1), "limbs_per_call": nrows,
                      "frac_of_hbm_peak": round(fwd_gbs / HBM_PEAK_GBS, 4)},
         "roofline": roofline,
+        "conv_pass_roofline": conv_roofline,
         "ntt_row_pass_roofline": ntt_row_roofline,
-        "ks_row_pass_roofline": ks_row_roofline,
         "iteration_roofline": it_roof,
         "graph_s_per_iter": None if graph_s is None else round(graph_s, 4),
         "minibatch": mini,
