@@ -55,7 +55,7 @@ enum {
 /* ------------------------------------------------------------------ */
 
 /*
- * RNS-CKKS parameters.  N = 2^log2N (10 <= log2N <= 16).  The ciphertext
+ * RNS-CKKS parameters.  N = 2^log2N (12 <= log2N <= 16).  The ciphertext
  * modulus chain has n_q primes of q_bits[i] bits (q_0 first, q_{n_q-1} is
  * rescaled away first); n_p special primes of p_bits bits extend it for key
  * switching; dnum digits of alpha = ceil(n_q/dnum) primes (n_p >= alpha is
@@ -145,6 +145,7 @@ size_t heqg_keygen_ws_bytes(const heqg_ctx* ctx);
  */
 int heqg_keygen(heqg_ctx* ctx, uint64_t seed, const int* rot_steps, int n_rot, void* dev_keys, size_t bytes,
                 void* ws, size_t ws_bytes, heqg_keys** out, hipStream_t stream);
+/* Releases the handle and every graph of the context captured with it; call before heqg_ctx_destroy. */
 void heqg_keys_destroy(heqg_keys* keys);
 /* Number of rotation keys held and their Galois elements (host array of that length, may be NULL). */
 int heqg_keys_galois(const heqg_keys* keys, uint64_t* out);
@@ -209,11 +210,11 @@ int heqg_decrypt(heqg_ctx* ctx, const heqg_keys* keys, const heqg_ct_batch* in, 
  * Key-holder refresh (stand-in for the paper's bootstrap, section 4.3 step 7):
  * decrypts, lifts each coefficient to the integer centred in q_0*q_1 (q_0 at
  * level 0), and encrypts it afresh at target_level with stream
- * (seed, object_first + b).  The scale is kept.  out may share storage with
+ * (seed, object_first + b).  The scale is kept (written to out->scale).  out may share storage with
  * in at any level: in is read completely (decryption) before out is written.
  */
 int heqg_refresh(heqg_ctx* ctx, const heqg_keys* keys, const heqg_ct_batch* in, int target_level, uint64_t seed,
-                 uint64_t object_first, const heqg_ct_batch* out, void* ws, size_t ws_bytes, hipStream_t stream);
+                 uint64_t object_first, heqg_ct_batch* out, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Signed coefficients (device int64 [count][N]) -> NTT-form plaintexts [count][level+1][N]. */
 int heqg_pt_load(heqg_ctx* ctx, const int64_t* dev_coeffs, int64_t count, int level, uint64_t* dev_pt,
@@ -222,50 +223,77 @@ int heqg_pt_load(heqg_ctx* ctx, const int64_t* dev_coeffs, int64_t count, int le
 /* ------------------------------------------------------------------ */
 /* Arithmetic (section 2.1).  Batched: one call processes every          */
 /* ciphertext of the batch.  Binary operations drop the higher-level     */
-/* operand to the lower level; outputs take that level.                  */
+/* operand to the lower level; outputs take that level.  The caller      */
+/* sets out->level to the documented output level (it sizes the buffer); */
+/* on success each call writes out->scale by the CKKS rules: a + b keeps  */
+/* a's scale, a (x) b gives s_a*s_b, a rescale s/q_l, a plaintext product */
+/* s*s_pt, a constant product its target, the rest keep the input's.     */
 /* ------------------------------------------------------------------ */
 
 /* Device workspace bytes for hmult/rotate/relin on a batch of `count` at the context's top level. */
 size_t heqg_ks_ws_bytes(const heqg_ctx* ctx, int64_t count);
 
 /* out = a + b / a - b (scales must agree to 2^-20; out keeps a's scale). */
-int heqg_add(heqg_ctx* ctx, const heqg_ct_batch* a, const heqg_ct_batch* b, const heqg_ct_batch* out, hipStream_t s);
-int heqg_sub(heqg_ctx* ctx, const heqg_ct_batch* a, const heqg_ct_batch* b, const heqg_ct_batch* out, hipStream_t s);
+int heqg_add(heqg_ctx* ctx, const heqg_ct_batch* a, const heqg_ct_batch* b, heqg_ct_batch* out, hipStream_t s);
+int heqg_sub(heqg_ctx* ctx, const heqg_ct_batch* a, const heqg_ct_batch* b, heqg_ct_batch* out, hipStream_t s);
 /* Tensor product (a0 b0, a0 b1 + a1 b0, a1 b1); out->n_poly = 3, scale s_a*s_b. */
-int heqg_tensor(heqg_ctx* ctx, const heqg_ct_batch* a, const heqg_ct_batch* b, const heqg_ct_batch* out, hipStream_t s);
+int heqg_tensor(heqg_ctx* ctx, const heqg_ct_batch* a, const heqg_ct_batch* b, heqg_ct_batch* out, hipStream_t s);
 /* Relinearise a 3-part ciphertext with the s^2 -> s key (hybrid key switching). */
-int heqg_relin(heqg_ctx* ctx, const heqg_keys* keys, const heqg_ct_batch* in, const heqg_ct_batch* out, void* ws,
+int heqg_relin(heqg_ctx* ctx, const heqg_keys* keys, const heqg_ct_batch* in, heqg_ct_batch* out, void* ws,
                size_t ws_bytes, hipStream_t s);
 /* Mul: tensor + relinearise (no rescale). */
 int heqg_hmult(heqg_ctx* ctx, const heqg_keys* keys, const heqg_ct_batch* a, const heqg_ct_batch* b,
-               const heqg_ct_batch* out, void* ws, size_t ws_bytes, hipStream_t s);
+               heqg_ct_batch* out, void* ws, size_t ws_bytes, hipStream_t s);
 /*
  * Rotation of every slot vector left by `step`: X -> X^(5^step), then key
  * switch back to s.  HEQG_ERR_KEY if no key for that Galois element.
  */
-int heqg_rotate(heqg_ctx* ctx, const heqg_keys* keys, const heqg_ct_batch* in, int step, const heqg_ct_batch* out,
+int heqg_rotate(heqg_ctx* ctx, const heqg_keys* keys, const heqg_ct_batch* in, int step, heqg_ct_batch* out,
                 void* ws, size_t ws_bytes, hipStream_t s);
 /*
  * Rescale by the last prime q_l: x_i <- (x_i - [x_l]_centred) * q_l^-1 mod q_i,
  * level l -> l-1, scale / q_l.  HEQG_ERR_LEVEL at level 0.
  */
-int heqg_rescale(heqg_ctx* ctx, const heqg_ct_batch* in, const heqg_ct_batch* out, void* ws, size_t ws_bytes,
+int heqg_rescale(heqg_ctx* ctx, const heqg_ct_batch* in, heqg_ct_batch* out, void* ws, size_t ws_bytes,
                  hipStream_t s);
-/* Keep limbs 0..level (out may alias in; no data moves when it does and strides match). */
-int heqg_drop(heqg_ctx* ctx, const heqg_ct_batch* in, int level, const heqg_ct_batch* out, hipStream_t s);
+/* Keep limbs 0..level (out may alias in with the same stride; then no data moves). */
+int heqg_drop(heqg_ctx* ctx, const heqg_ct_batch* in, int level, heqg_ct_batch* out, hipStream_t s);
 /* Every part times an NTT-form plaintext (device rows, >= level+1 limbs); scale s*pt_scale. */
 int heqg_mul_pt(heqg_ctx* ctx, const heqg_ct_batch* in, const uint64_t* dev_pt, double pt_scale,
-                const heqg_ct_batch* out, hipStream_t s);
+                heqg_ct_batch* out, hipStream_t s);
 /* c0 += plaintext (scales must agree). */
 int heqg_add_pt(heqg_ctx* ctx, const heqg_ct_batch* in, const uint64_t* dev_pt, double pt_scale,
-                const heqg_ct_batch* out, hipStream_t s);
+                heqg_ct_batch* out, hipStream_t s);
 /*
  * cMul with exact target scale: k = round(c * target * q_l / scale) (FP64,
  * left to right, ties away from zero), multiply by k, rescale; the result is
  * labelled with `target`.  HEQG_ERR_OVERFLOW if |k| >= 2^62.
  */
-int heqg_mul_const(heqg_ctx* ctx, const heqg_ct_batch* in, double c, double target, const heqg_ct_batch* out,
+int heqg_mul_const(heqg_ctx* ctx, const heqg_ct_batch* in, double c, double target, heqg_ct_batch* out,
                    void* ws, size_t ws_bytes, hipStream_t s);
+
+/*
+ * cAdd (section 2.1): adds the real constant c to every slot.  The constant
+ * encodes exactly to the polynomial k = round(c * scale) (ties away from zero),
+ * whose every NTT evaluation is k, so part 0 gains k mod q_i in every residue
+ * of limb i; other parts are copied.  out may alias in.  HEQG_ERR_OVERFLOW if
+ * |c * scale| >= 2^62.
+ */
+int heqg_add_const(heqg_ctx* ctx, const heqg_ct_batch* in, double c, heqg_ct_batch* out, hipStream_t s);
+
+/*
+ * Parity I/O in the canonical coefficient form (for comparison with a CPU
+ * implementation).  heqg_export writes the batch to host_out as
+ * [count][n_poly][level+1][N] residues of the coefficients (inverse NTT of
+ * every row), using the caller's device workspace (heqg_export_ws_bytes) and
+ * synchronising the stream.  heqg_import reads host_in in that layout
+ * (HEQG_ERR_ARG if a residue is not below its row's prime, checked before
+ * any copy), transforms it to NTT form into out (out->level, n_poly, count,
+ * stride as given; out->scale untouched) and synchronises the stream.
+ */
+size_t heqg_export_ws_bytes(const heqg_ctx* ctx, const heqg_ct_batch* b);
+int heqg_export(heqg_ctx* ctx, const heqg_ct_batch* in, uint64_t* host_out, void* ws, size_t ws_bytes, hipStream_t s);
+int heqg_import(heqg_ctx* ctx, const uint64_t* host_in, const heqg_ct_batch* out, hipStream_t s);
 
 /* ------------------------------------------------------------------ */
 /* Limb NTT (exposed for parity and throughput measurement)             */
@@ -304,27 +332,32 @@ int heqg_prof_stop(int kernel, double* avg_us, int64_t* launches, double* avg_ro
                    double* avg_ops);
 
 /*
- * Kernel-variant switches read by the launchers (process-wide; set by
- * heqg_tune_ntt).  which = 0: forward NTT row pass, 1: inverse NTT row pass;
- * value 0 = 16-byte accesses in the per-thread contiguous layout, 1 =
- * coalesced accesses through an LDS transpose.  which = 2 (forward) / 3
- * (inverse): log2 of the first-pass size for the ring of the most recently
- * created or tuned context (N = 2^15: 7 or 8; other rings: their one split,
- * 2^8 x 2^8 at N = 2^16, since a pass holds at most 2^8 points).  Every choice computes
- * identical results.  Returns -1 on a bad selector or value.
+ * Tuning choices of one context (every choice computes identical residues).
+ * which = 0 / 1: row-pass access variant of the forward / inverse NTT, value
+ * 0 = 16-byte accesses in the per-thread contiguous layout, 1 = coalesced
+ * accesses through an LDS transpose.  which = 2: log2 of the first pass of the
+ * two-pass NTT, shared by both directions (the key switch runs part of an
+ * inverse transform inside a forward row pass); N = 2^15 has 7 and 8, every
+ * other ring its one split (2^8 x 2^8 at N = 2^16: a pass holds at most 2^8
+ * points).  Each context keeps its own choices.  heqg_tune_set returns -1 on a
+ * bad selector or value, heqg_tune_get -1 on a bad selector.  A choice must not
+ * change while work of the same context is being enqueued on another thread.
  */
-int heqg_tune_set(int which, int value);
-int heqg_tune_get(int which);
+int heqg_tune_set(heqg_ctx* ctx, int which, int value);
+int heqg_tune_get(const heqg_ctx* ctx, int which);
 
 /*
  * NTT autotuner: times the forward and the inverse transform of `rows` limbs
  * (rounded down to a multiple of n_q, at least n_q; the ctx's Q primes in
  * turn) for every pass split and row-pass variant, each after one warm-up
- * launch, as the mean of 3 launches, and keeps the fastest per direction for
- * this ctx's ring degree.  Synchronous: it zeroes and uses the caller's
- * workspace ws (heqg_tune_ws_bytes) on `stream` and waits for it.  choice
- * (4 ints, may be NULL) receives {split_fwd, variant_fwd, split_inv,
- * variant_inv}; best_us (2 doubles, may be NULL) the fastest mean times.
+ * launch, as the mean of 3 launches; keeps, per split, the fastest variant of
+ * each direction and then the split with the smallest forward + inverse time.
+ * Synchronous: it zeroes and uses the caller's workspace ws
+ * (heqg_tune_ws_bytes) on `stream` and waits for it.  Pass rows large enough
+ * that the limbs do not fit in the caches (>= 2048 limbs of 2^16 words,
+ * 1 GiB) to time the transform as the training step runs it.  choice (4 ints,
+ * may be NULL) receives {split, variant_fwd, split, variant_inv}; best_us (2
+ * doubles, may be NULL) the forward and inverse mean times of that choice.
  * Graphs captured before a changed choice are not replayed afterwards.
  */
 size_t heqg_tune_ws_bytes(const heqg_ctx* ctx, int rows);
@@ -361,6 +394,41 @@ int heqg_sigfit_grad(const float* dev_m, int64_t n, const float* dev_c, int n_te
                      float* dev_loss, void* ws, size_t ws_bytes, hipStream_t stream);
 int heqg_sigfit_train(const float* dev_m, int64_t n, int n_terms, float* dev_c, int steps, float lr, float beta1,
                       float beta2, float eps, float* dev_loss_trace, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------ */
+/* Client-side inputs of the training step (host, synchronous)          */
+/* ------------------------------------------------------------------ */
+
+/*
+ * The diagonal of B-bar (section 3.1; section 4.3 builds it from -1/4 X^T X):
+ * with Xh = [1 | X] (X row-major n x f, double), H = 1/4 Xh^T Xh and
+ * out[j] = 1 / (eps + sum_l |H_jl|) for j <= f, out[j] = 0 for f < j < g
+ * (padding columns: no 1/eps amplification of noise there).  out has g
+ * entries.  Work is split over `threads` host threads (<= 0: hardware
+ * concurrency) in fixed row slices; the result does not depend on the thread
+ * count.  HEQG_ERR_ARG unless n >= 1 and f + 1 <= g.
+ */
+int heqg_bbar(const double* X, int64_t n, int f, int g, double eps, double* out, int threads);
+
+/*
+ * Scale plan of the masked sigmoid: level is the level of the tensor
+ * Z (x) W (the blocks' level), s_z and s_w their scales, s_c the scale every
+ * term must reach.  Writes (degree+1)/2 + 1 scales: one per odd power k
+ * ascending (the mask encode(-c_k F) at that scale, multiplied into the
+ * rescaled margin u and then into the rescaled even powers of u, lands at
+ * s_c), then s_c for encode(F/2).  HEQG_ERR_ARG for a degree other than 3, 5,
+ * 7 or a level too low for its depth.
+ */
+int heqg_sigmoid_plan(const heqg_ctx* ctx, int level, double s_z, double s_w, double s_c, int degree, double* scales);
+/*
+ * The mask plaintexts of heqg_sigmoid in coefficient form (host int64
+ * [n_terms+1][N]) with their scales (n_terms+1 doubles): encode(-c_k F) for
+ * coeffs[i] = c_(2i+1), i < n_terms, then encode(F/2), where F is 1 in column 0
+ * of every row of the m x g block layout (m*g <= N/2).  Load them at level-1
+ * with heqg_pt_load.
+ */
+int heqg_sigmoid_masks(const heqg_ctx* ctx, const double* coeffs, int degree, int m, int g, int level, double s_z,
+                       double s_w, double s_c, int64_t* coeffs_out, double* scales);
 
 /* ------------------------------------------------------------------ */
 /* Training step (section 3.2 Algorithm 1; section 3.3; section 4.3)    */
@@ -434,6 +502,8 @@ int heqg_nag_qg_graph(heqg_ctx* ctx, const heqg_keys* keys, const heqg_ct_batch*
                       heqg_ct* W, heqg_ct* V, const heqg_sigmoid* sig, heqg_nag_state* st, int batch, void* ws,
                       size_t ws_bytes, hipStream_t stream);
 int heqg_graph_clear(heqg_ctx* ctx);
+/* Number of instantiated graphs the context holds (a key set's graphs go with heqg_keys_destroy). */
+int heqg_graph_count(const heqg_ctx* ctx);
 
 #ifdef __cplusplus
 }

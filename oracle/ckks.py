@@ -12,6 +12,7 @@ Scale rules (FP64):
   mul_pt:       s * s_pt;   add_pt: the plaintext scale must agree with s
   mul_const:    multiply by the integer k = round(c * s_t * q_l / s) and rescale;
                 the result is labelled with the target scale s_t exactly
+  add_const:    adds k = round(c * s) to the constant coefficient; scale kept
 Binary operations first drop the higher-level operand to the lower level.
 """
 import ctypes
@@ -266,6 +267,21 @@ class Oracle:
         pt = np.ascontiguousarray(pt_ntt[: ct.level + 1])
         out = np.zeros_like(ct.data)
         lib().oracle_add_pt(self.ctx, _p(ct.data), _p(pt), ct.level, _p(out))
+        return Ct(out, ct.level, ct.scale)
+
+    def add_const(self, ct, c):
+        """cAdd (section 2.1): c in every slot is the constant polynomial k = round(c * scale)
+        (ties away from zero); it is transformed like any plaintext and added to part 0."""
+        k = round_half_away(c * ct.scale)
+        if not abs(k) < 2 ** 62:
+            raise OracleError("constant overflow")
+        m = np.zeros(self.N, dtype=np.int64)
+        m[0] = k
+        pt = self.pt_from_int(m, ct.level)
+        out = ct.data.copy()
+        p0 = np.zeros((2, ct.level + 1, self.N), dtype=np.uint64)
+        lib().oracle_add_pt(self.ctx, _p(np.ascontiguousarray(ct.data[:2])), _p(pt), ct.level, _p(p0))
+        out[0] = p0[0]
         return Ct(out, ct.level, ct.scale)
 
     def mul_int(self, ct, k):

@@ -1,5 +1,6 @@
 // C ABI: context, keys, encryption, arithmetic (see include/heqg.h).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -19,9 +20,6 @@ extern "C" size_t heqg_ctx_tables_bytes(const heqg_params* p) {
   return n;
 }
 
-// ring degree of the most recently created or tuned context (the NTT pass splits are per ring)
-static int last_log2N = 16;
-
 extern "C" int heqg_ctx_create(const heqg_params* p, void* dev_tables, size_t bytes, heqg_ctx** out) {
   if (!p || !out) {
     set_err("ctx_create: null argument");
@@ -39,7 +37,6 @@ extern "C" int heqg_ctx_create(const heqg_params* p, void* dev_tables, size_t by
     return rc;
   }
   *out = c;
-  last_log2N = c->g.logN;
   return HEQG_OK;
 }
 
@@ -114,6 +111,8 @@ extern "C" int heqg_keygen(heqg_ctx* c, uint64_t seed, const int* rot_steps, int
   k->rot = k->rlk + key_words(c);
   k->galois = gal;
   k->key_words = key_words(c);
+  static std::atomic<uint64_t> next_gen{0};
+  k->gen = ++next_gen;
   int rc = ops::keygen(c, k, seed, static_cast<uint8_t*>(ws), s);
   if (rc != HEQG_OK) {
     delete k;
@@ -123,7 +122,22 @@ extern "C" int heqg_keygen(heqg_ctx* c, uint64_t seed, const int* rot_steps, int
   return HEQG_OK;
 }
 
-extern "C" void heqg_keys_destroy(heqg_keys* k) { delete k; }
+extern "C" void heqg_keys_destroy(heqg_keys* k) {
+  if (!k) return;
+  // graphs captured with these keys read their device buffers: drop them
+  auto& gr = k->ctx->graphs;
+  for (auto it = gr.begin(); it != gr.end();) {
+    uint64_t g;
+    std::memcpy(&g, it->first.data(), sizeof(g));
+    if (g == k->gen) {
+      hipGraphExecDestroy(it->second);
+      it = gr.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  delete k;
+}
 
 extern "C" int heqg_keys_galois(const heqg_keys* k, uint64_t* out) {
   if (!k) {
@@ -219,7 +233,7 @@ extern "C" int heqg_decrypt(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch
 }
 
 extern "C" int heqg_refresh(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch* in, int target_level,
-                            uint64_t seed, uint64_t object_first, const heqg_ct_batch* out, void* ws, size_t ws_bytes,
+                            uint64_t seed, uint64_t object_first, heqg_ct_batch* out, void* ws, size_t ws_bytes,
                             hipStream_t s) {
   if (!c || !k || !batch_ok(c, in, 2, "refresh") || !batch_ok(c, out, 2, "refresh")) return HEQG_ERR_ARG;
   if (out->level != target_level || out->count != in->count) {
@@ -230,8 +244,11 @@ extern "C" int heqg_refresh(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch
     set_err("refresh: workspace too small");
     return HEQG_ERR_ARG;
   }
-  return ops::refresh(c, k, view_of(c, in), in->count, in->level, target_level, seed, object_first, view_of(c, out),
-                      static_cast<uint64_t*>(ws), s);
+  const double sc = in->scale;
+  int rc = ops::refresh(c, k, view_of(c, in), in->count, in->level, target_level, seed, object_first,
+                        view_of(c, out), static_cast<uint64_t*>(ws), s);
+  if (rc == HEQG_OK) out->scale = sc;
+  return rc;
 }
 
 extern "C" int heqg_pt_load(heqg_ctx* c, const int64_t* dev_coeffs, int64_t count, int level, uint64_t* dev_pt,
@@ -241,6 +258,69 @@ extern "C" int heqg_pt_load(heqg_ctx* c, const int64_t* dev_coeffs, int64_t coun
     return HEQG_ERR_ARG;
   }
   return ops::pt_load(c, dev_coeffs, count, level, dev_pt, s);
+}
+
+// ------------------------------------------------------------------ parity I/O
+extern "C" size_t heqg_export_ws_bytes(const heqg_ctx* c, const heqg_ct_batch* b) {
+  if (!c || !b || b->count < 1 || b->n_poly < 2 || b->n_poly > 3 || b->level < 0 || b->level >= c->g.n_q) return 0;
+  return 8 * (size_t)b->count * b->n_poly * (b->level + 1) * c->g.N;
+}
+
+extern "C" int heqg_export(heqg_ctx* c, const heqg_ct_batch* in, uint64_t* host_out, void* ws, size_t ws_bytes,
+                           hipStream_t s) {
+  if (!c || !host_out || !batch_ok(c, in, 0, "export")) {
+    if (!host_out) set_err("export: null output");
+    return HEQG_ERR_ARG;
+  }
+  const size_t N = c->g.N, nl = in->level + 1, per = (size_t)in->n_poly * nl * N;
+  if (!ws || ws_bytes < heqg_export_ws_bytes(c, in)) {
+    set_err("export: workspace too small");
+    return HEQG_ERR_ARG;
+  }
+  uint64_t* w = static_cast<uint64_t*>(ws);
+  k_copy_launch(c->g, view_of(c, in), CtV{w, (int64_t)per, (int64_t)(nl * N)}, in->count, in->n_poly, (int)nl, s);
+  int rc = ops::ntt(c, ops::rows_q(w, in->count * in->n_poly, (int64_t)(nl * N), 1, 0, (int)nl, 0), true, s);
+  if (rc) return rc;
+  if (hipMemcpyAsync(host_out, w, 8 * per * in->count, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    set_err("export: copy to the host failed");
+    return HEQG_ERR_DEVICE;
+  }
+  return HEQG_OK;
+}
+
+extern "C" int heqg_import(heqg_ctx* c, const uint64_t* host_in, const heqg_ct_batch* out, hipStream_t s) {
+  if (!c || !host_in || !batch_ok(c, out, 0, "import")) {
+    if (!host_in) set_err("import: null input");
+    return HEQG_ERR_ARG;
+  }
+  const size_t N = c->g.N, nl = out->level + 1, per = (size_t)out->n_poly * nl * N;
+  for (int64_t b = 0; b < out->count; ++b)
+    for (int p = 0; p < out->n_poly; ++p)
+      for (size_t i = 0; i < nl; ++i) {
+        const uint64_t q = c->primes[i];
+        const uint64_t* r = host_in + b * per + (p * nl + i) * N;
+        for (size_t j = 0; j < N; ++j)
+          if (r[j] >= q) {
+            set_err("import: residue not below its prime");
+            return HEQG_ERR_ARG;
+          }
+      }
+  const int64_t cs = out->count > 1 ? out->stride : (int64_t)per;
+  if (hipMemcpy2DAsync(out->data, 8 * (size_t)cs, host_in, 8 * per, 8 * per, (size_t)out->count,
+                       hipMemcpyHostToDevice, s) != hipSuccess) {
+    set_err("import: copy to the device failed");
+    return HEQG_ERR_DEVICE;
+  }
+  RowSet rs = ops::rows_q(out->data, out->count, cs, out->n_poly, (int64_t)(nl * N), (int)nl, 0);
+  int rc = ops::ntt(c, rs, false, s);
+  if (rc) return rc;
+  // the host buffer may be released once the call returns
+  if (hipStreamSynchronize(s) != hipSuccess) {
+    set_err("import: synchronisation failed");
+    return HEQG_ERR_DEVICE;
+  }
+  return HEQG_OK;
 }
 
 extern "C" int heqg_ntt(heqg_ctx* c, uint64_t* dev_rows, int64_t n_rows, int first_prime, int period, int inverse,
@@ -267,7 +347,7 @@ extern "C" size_t heqg_ks_ws_bytes(const heqg_ctx* c, int64_t count) {
   return ops::ks_ws_words(c, count, c->g.n_q - 1) * 8;
 }
 
-static int binary_check(heqg_ctx* c, const heqg_ct_batch* a, const heqg_ct_batch* b, const heqg_ct_batch* out,
+static int binary_check(heqg_ctx* c, const heqg_ct_batch* a, const heqg_ct_batch* b, heqg_ct_batch* out,
                         const char* what, int& lv) {
   if (!c || !batch_ok(c, a, 0, what) || !batch_ok(c, b, 0, what) || !batch_ok(c, out, 0, what)) return HEQG_ERR_ARG;
   if (!(b->count == a->count || b->count == 1) || out->count != a->count) {
@@ -282,7 +362,7 @@ static int binary_check(heqg_ctx* c, const heqg_ct_batch* a, const heqg_ct_batch
   return HEQG_OK;
 }
 
-static int addsub(heqg_ctx* c, const heqg_ct_batch* a, const heqg_ct_batch* b, const heqg_ct_batch* out, bool sub,
+static int addsub(heqg_ctx* c, const heqg_ct_batch* a, const heqg_ct_batch* b, heqg_ct_batch* out, bool sub,
                   hipStream_t s) {
   int lv;
   int rc = binary_check(c, a, b, out, sub ? "sub" : "add", lv);
@@ -296,19 +376,20 @@ static int addsub(heqg_ctx* c, const heqg_ct_batch* a, const heqg_ct_batch* b, c
     return HEQG_ERR_SCALE;
   }
   k_add_launch(c->g, c->t, view_of(c, a), view_of(c, b), view_of(c, out), a->count, a->n_poly, lv + 1, sub, s);
+  out->scale = a->scale;
   return HEQG_OK;
 }
 
-extern "C" int heqg_add(heqg_ctx* c, const heqg_ct_batch* a, const heqg_ct_batch* b, const heqg_ct_batch* out,
+extern "C" int heqg_add(heqg_ctx* c, const heqg_ct_batch* a, const heqg_ct_batch* b, heqg_ct_batch* out,
                         hipStream_t s) {
   return addsub(c, a, b, out, false, s);
 }
-extern "C" int heqg_sub(heqg_ctx* c, const heqg_ct_batch* a, const heqg_ct_batch* b, const heqg_ct_batch* out,
+extern "C" int heqg_sub(heqg_ctx* c, const heqg_ct_batch* a, const heqg_ct_batch* b, heqg_ct_batch* out,
                         hipStream_t s) {
   return addsub(c, a, b, out, true, s);
 }
 
-extern "C" int heqg_tensor(heqg_ctx* c, const heqg_ct_batch* a, const heqg_ct_batch* b, const heqg_ct_batch* out,
+extern "C" int heqg_tensor(heqg_ctx* c, const heqg_ct_batch* a, const heqg_ct_batch* b, heqg_ct_batch* out,
                            hipStream_t s) {
   int lv;
   int rc = binary_check(c, a, b, out, "tensor", lv);
@@ -318,10 +399,11 @@ extern "C" int heqg_tensor(heqg_ctx* c, const heqg_ct_batch* a, const heqg_ct_ba
     return HEQG_ERR_ARG;
   }
   k_tensor_launch(c->g, c->t, view_of(c, a), view_of(c, b), view_of(c, out), a->count, lv + 1, false, s);
+  out->scale = a->scale * b->scale;
   return HEQG_OK;
 }
 
-extern "C" int heqg_relin(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch* in, const heqg_ct_batch* out,
+extern "C" int heqg_relin(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch* in, heqg_ct_batch* out,
                           void* ws, size_t ws_bytes, hipStream_t s) {
   if (!c || !k || !batch_ok(c, in, 3, "relin") || !batch_ok(c, out, 2, "relin")) return HEQG_ERR_ARG;
   if (out->level != in->level || out->count != in->count) {
@@ -332,11 +414,13 @@ extern "C" int heqg_relin(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch* 
     set_err("relin: workspace too small");
     return HEQG_ERR_ARG;
   }
-  return ops::relin(c, k, view_of(c, in), view_of(c, out), in->count, in->level, static_cast<uint64_t*>(ws), s);
+  int rc = ops::relin(c, k, view_of(c, in), view_of(c, out), in->count, in->level, static_cast<uint64_t*>(ws), s);
+  if (rc == HEQG_OK) out->scale = in->scale;
+  return rc;
 }
 
 extern "C" int heqg_hmult(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch* a, const heqg_ct_batch* b,
-                          const heqg_ct_batch* out, void* ws, size_t ws_bytes, hipStream_t s) {
+                          heqg_ct_batch* out, void* ws, size_t ws_bytes, hipStream_t s) {
   int lv;
   int rc = binary_check(c, a, b, out, "hmult", lv);
   if (rc) return rc;
@@ -352,11 +436,13 @@ extern "C" int heqg_hmult(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch* 
   uint64_t* w = static_cast<uint64_t*>(ws);
   CtV t3{w, (int64_t)3 * (lv + 1) * c->g.N, (int64_t)(lv + 1) * c->g.N};
   k_tensor_launch(c->g, c->t, view_of(c, a), view_of(c, b), t3, a->count, lv + 1, false, s);
-  return ops::relin(c, k, t3, view_of(c, out), a->count, lv, w + tmp, s);
+  int rc2 = ops::relin(c, k, t3, view_of(c, out), a->count, lv, w + tmp, s);
+  if (rc2 == HEQG_OK) out->scale = a->scale * b->scale;
+  return rc2;
 }
 
 extern "C" int heqg_rotate(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch* in, int step,
-                           const heqg_ct_batch* out, void* ws, size_t ws_bytes, hipStream_t s) {
+                           heqg_ct_batch* out, void* ws, size_t ws_bytes, hipStream_t s) {
   if (!c || !k || !batch_ok(c, in, 2, "rotate") || !batch_ok(c, out, 2, "rotate")) return HEQG_ERR_ARG;
   if (out->level != in->level || out->count != in->count) {
     set_err("rotate: output shape mismatch");
@@ -372,10 +458,12 @@ extern "C" int heqg_rotate(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch*
     set_err("rotate: workspace too small");
     return HEQG_ERR_ARG;
   }
-  return ops::rotate(c, k, view_of(c, in), view_of(c, out), in->count, in->level, t, static_cast<uint64_t*>(ws), s);
+  int rc = ops::rotate(c, k, view_of(c, in), view_of(c, out), in->count, in->level, t, static_cast<uint64_t*>(ws), s);
+  if (rc == HEQG_OK) out->scale = in->scale;
+  return rc;
 }
 
-extern "C" int heqg_rescale(heqg_ctx* c, const heqg_ct_batch* in, const heqg_ct_batch* out, void* ws,
+extern "C" int heqg_rescale(heqg_ctx* c, const heqg_ct_batch* in, heqg_ct_batch* out, void* ws,
                             size_t ws_bytes, hipStream_t s) {
   // the input's level is checked first: at level 0 there is no valid output shape at all
   if (!c || !batch_ok(c, in, 0, "rescale")) return HEQG_ERR_ARG;
@@ -397,10 +485,11 @@ extern "C" int heqg_rescale(heqg_ctx* c, const heqg_ct_batch* in, const heqg_ct_
     return HEQG_ERR_ARG;
   }
   ops::rescale(c, view_of(c, in), view_of(c, out), in->count, in->n_poly, in->level, static_cast<uint64_t*>(ws), s);
+  out->scale = in->scale / (double)c->primes[in->level];
   return HEQG_OK;
 }
 
-extern "C" int heqg_drop(heqg_ctx* c, const heqg_ct_batch* in, int level, const heqg_ct_batch* out, hipStream_t s) {
+extern "C" int heqg_drop(heqg_ctx* c, const heqg_ct_batch* in, int level, heqg_ct_batch* out, hipStream_t s) {
   if (!c || !batch_ok(c, in, 0, "drop") || !batch_ok(c, out, 0, "drop")) return HEQG_ERR_ARG;
   if (level > in->level || out->level != level || out->count != in->count || out->n_poly != in->n_poly) {
     set_err("drop: bad level or output shape");
@@ -410,24 +499,29 @@ extern "C" int heqg_drop(heqg_ctx* c, const heqg_ct_batch* in, int level, const 
     set_err("drop: an in-place drop must keep the level (use a separate output)");
     return HEQG_ERR_ARG;
   }
-  k_copy_launch(c->g, view_of(c, in), view_of(c, out), in->count, in->n_poly, level + 1, s);
+  if (out->data == in->data && in->count > 1 && out->stride != in->stride) {
+    set_err("drop: an in-place drop must keep the stride");
+    return HEQG_ERR_ARG;
+  }
+  if (out->data != in->data) k_copy_launch(c->g, view_of(c, in), view_of(c, out), in->count, in->n_poly, level + 1, s);
+  out->scale = in->scale;
   return HEQG_OK;
 }
 
 extern "C" int heqg_mul_pt(heqg_ctx* c, const heqg_ct_batch* in, const uint64_t* dev_pt, double pt_scale,
-                           const heqg_ct_batch* out, hipStream_t s) {
-  (void)pt_scale;
+                           heqg_ct_batch* out, hipStream_t s) {
   if (!c || !dev_pt || !batch_ok(c, in, 0, "mul_pt") || !batch_ok(c, out, 0, "mul_pt")) return HEQG_ERR_ARG;
   if (out->level != in->level || out->n_poly != in->n_poly || out->count != in->count) {
     set_err("mul_pt: output shape mismatch");
     return HEQG_ERR_ARG;
   }
   k_mul_pt_launch(c->g, c->t, view_of(c, in), dev_pt, view_of(c, out), in->count, in->n_poly, in->level + 1, s);
+  out->scale = in->scale * pt_scale;
   return HEQG_OK;
 }
 
 extern "C" int heqg_add_pt(heqg_ctx* c, const heqg_ct_batch* in, const uint64_t* dev_pt, double pt_scale,
-                           const heqg_ct_batch* out, hipStream_t s) {
+                           heqg_ct_batch* out, hipStream_t s) {
   if (!c || !dev_pt || !batch_ok(c, in, 2, "add_pt") || !batch_ok(c, out, 2, "add_pt")) return HEQG_ERR_ARG;
   if (out->level != in->level || out->count != in->count) {
     set_err("add_pt: output shape mismatch");
@@ -438,11 +532,12 @@ extern "C" int heqg_add_pt(heqg_ctx* c, const heqg_ct_batch* in, const uint64_t*
     return HEQG_ERR_SCALE;
   }
   k_add_pt_launch(c->g, c->t, view_of(c, in), dev_pt, view_of(c, out), in->count, in->level + 1, s);
+  out->scale = in->scale;
   return HEQG_OK;
 }
 
 extern "C" int heqg_mul_const(heqg_ctx* c, const heqg_ct_batch* in, double cst, double target,
-                              const heqg_ct_batch* out, void* ws, size_t ws_bytes, hipStream_t s) {
+                              heqg_ct_batch* out, void* ws, size_t ws_bytes, hipStream_t s) {
   // the input's level is checked first: at level 0 there is no valid output shape at all
   if (!c || !batch_ok(c, in, 0, "mul_const")) return HEQG_ERR_ARG;
   if (in->level < 1) {
@@ -459,29 +554,59 @@ extern "C" int heqg_mul_const(heqg_ctx* c, const heqg_ct_batch* in, double cst, 
     set_err("mul_const: workspace too small");
     return HEQG_ERR_ARG;
   }
-  return ops::mul_const(c, view_of(c, in), in->count, in->n_poly, in->level, in->scale, cst, target, view_of(c, out),
-                        static_cast<uint64_t*>(ws), s);
+  int rc = ops::mul_const(c, view_of(c, in), in->count, in->n_poly, in->level, in->scale, cst, target,
+                          view_of(c, out), static_cast<uint64_t*>(ws), s);
+  if (rc == HEQG_OK) out->scale = target;
+  return rc;
+}
+
+extern "C" int heqg_add_const(heqg_ctx* c, const heqg_ct_batch* in, double cst, heqg_ct_batch* out, hipStream_t s) {
+  if (!c || !batch_ok(c, in, 0, "add_const") || !batch_ok(c, out, 0, "add_const")) return HEQG_ERR_ARG;
+  if (out->level != in->level || out->n_poly != in->n_poly || out->count != in->count) {
+    set_err("add_const: output shape mismatch");
+    return HEQG_ERR_ARG;
+  }
+  const double v = cst * in->scale;
+  if (!(std::fabs(v) < 4611686018427387904.0)) {
+    set_err("add_const: constant times scale reaches 2^62");
+    return HEQG_ERR_OVERFLOW;
+  }
+  const int64_t kint = std::llround(v);  // ties away from zero
+  std::vector<uint64_t> kr(in->level + 1);
+  for (int i = 0; i <= in->level; ++i) {
+    const uint64_t q = c->primes[i];
+    kr[i] = kint < 0 ? (q - (uint64_t)((unsigned __int128)(-(__int128)kint) % q)) % q : (uint64_t)kint % q;
+  }
+  k_add_scalar_launch(c->g, c->t, view_of(c, in), view_of(c, out), in->count, in->n_poly, in->level + 1, kr.data(), s);
+  out->scale = in->scale;
+  return HEQG_OK;
 }
 
 // ------------------------------------------------------------------ tuning
 
-extern "C" int heqg_tune_set(int which, int value) {
-  if (which == 0 || which == 1) return rows_variant_set(which, value);
-  if (which == 2 || which == 3) {
+extern "C" int heqg_tune_set(heqg_ctx* c, int which, int value) {
+  if (!c) return -1;
+  if (which == 0 || which == 1) {
+    if (value != 0 && value != 1) return -1;
+    c->t.rows_var[which] = value;
+    return 0;
+  }
+  if (which == 2) {
     int las[8], n = 0;
-    ntt_split_options(last_log2N, las, &n);
+    ntt_split_options(c->g.logN, las, &n);
     for (int i = 0; i < n; ++i)
       if (las[i] == value) {
-        ntt_split_set(which == 3, last_log2N, value);
+        c->t.split = value;
         return 0;
       }
   }
   return -1;
 }
 
-extern "C" int heqg_tune_get(int which) {
-  if (which == 0 || which == 1) return rows_variant_get(which);
-  if (which == 2 || which == 3) return ntt_split_get(which == 3, last_log2N);
+extern "C" int heqg_tune_get(const heqg_ctx* c, int which) {
+  if (!c) return -1;
+  if (which == 0 || which == 1) return c->t.rows_var[which];
+  if (which == 2) return c->t.split;
   return -1;
 }
 
@@ -498,7 +623,6 @@ extern "C" int heqg_tune_ntt(heqg_ctx* c, int rows, void* ws, size_t ws_bytes, h
     set_err("tune_ntt: null argument or workspace too small");
     return HEQG_ERR_ARG;
   }
-  last_log2N = c->g.logN;
   const int nq = c->g.n_q, N = c->g.N;
   const int64_t na = std::max<int64_t>(1, rows / nq);
   uint64_t* data = static_cast<uint64_t*>(ws);
@@ -514,15 +638,21 @@ extern "C" int heqg_tune_ntt(heqg_ctx* c, int rows, void* ws, size_t ws_bytes, h
   }
   int las[8], nl = 0;
   ntt_split_options(c->g.logN, las, &nl);
+  const DevTables saved = c->t;
+  // one split serves both directions (the fused key switch runs part of an inverse transform
+  // with the forward row pass): per split, the fastest variant of each direction, then the
+  // split with the smallest forward + inverse time
+  double best_total = 1e30, best[2] = {0.0, 0.0};
+  int best_la = saved.split, best_v[2] = {saved.rows_var[0], saved.rows_var[1]};
   int rc = HEQG_OK;
-  for (int dir = 0; dir < 2 && rc == HEQG_OK; ++dir) {
-    const bool inv = dir == 1;
-    double best = 1e30;
-    int best_la = ntt_split_get(inv, c->g.logN), best_v = rows_variant_get(dir);
-    for (int i = 0; i < nl && rc == HEQG_OK; ++i)
+  for (int i = 0; i < nl && rc == HEQG_OK; ++i) {
+    double dir_best[2] = {1e30, 1e30};
+    int dir_v[2] = {0, 0};
+    for (int dir = 0; dir < 2 && rc == HEQG_OK; ++dir)
       for (int v = 0; v < 2 && rc == HEQG_OK; ++v) {
-        ntt_split_set(inv, c->g.logN, las[i]);
-        rows_variant_set(dir, v);
+        c->t.split = las[i];
+        c->t.rows_var[dir] = v;
+        const bool inv = dir == 1;
         launch_ntt(c->t, c->g.logN, rs, inv, s);  // warm-up
         hipEventRecord(e0, s);
         for (int r = 0; r < 3; ++r) launch_ntt(c->t, c->g.logN, rs, inv, s);
@@ -534,12 +664,22 @@ extern "C" int heqg_tune_ntt(heqg_ctx* c, int rows, void* ws, size_t ws_bytes, h
           break;
         }
         const double us = 1000.0 * ms / 3.0;
-        if (us < best) best = us, best_la = las[i], best_v = v;
+        if (us < dir_best[dir]) dir_best[dir] = us, dir_v[dir] = v;
       }
-    ntt_split_set(inv, c->g.logN, best_la);
-    rows_variant_set(dir, best_v);
-    if (choice) choice[2 * dir] = best_la, choice[2 * dir + 1] = best_v;
-    if (best_us) best_us[dir] = best;
+    if (rc == HEQG_OK && dir_best[0] + dir_best[1] < best_total) {
+      best_total = dir_best[0] + dir_best[1];
+      best_la = las[i];
+      best_v[0] = dir_v[0], best_v[1] = dir_v[1];
+      best[0] = dir_best[0], best[1] = dir_best[1];
+    }
+  }
+  c->t = saved;
+  if (rc == HEQG_OK) {
+    c->t.split = best_la;
+    c->t.rows_var[0] = best_v[0];
+    c->t.rows_var[1] = best_v[1];
+    if (choice) choice[0] = choice[2] = best_la, choice[1] = best_v[0], choice[3] = best_v[1];
+    if (best_us) best_us[0] = best[0], best_us[1] = best[1];
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);

@@ -359,6 +359,8 @@ int ctx_build(heqg_ctx* c, void* dev, size_t bytes, std::string* err) {
   c->t.ks_scale_f = reinterpret_cast<const double*>(d + offs[12]);
   c->t.moddown_rs = reinterpret_cast<const uint64_t*>(d + offs[13]);
   c->t.moddown_rs_b = reinterpret_cast<const uint64_t*>(d + offs[14]);
+  c->t.split = ntt_split_default(c->g.logN);
+  c->t.rows_var[0] = c->t.rows_var[1] = 1;
   return HEQG_OK;
 }
 

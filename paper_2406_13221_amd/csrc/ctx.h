@@ -45,6 +45,8 @@ struct heqg_keys {
   uint64_t* rot;     // [n_rot][dnum][2][nqp][N]
   std::vector<uint64_t> galois;
   size_t key_words;  // words of one switching key
+  uint64_t gen;      // unique per key set in the process (graph cache keys; a freed handle's
+                     // address may be reused by the next key set)
 };
 
 size_t ctx_layout(const heqg_params* p, bool check, std::string* err, size_t offs[16]);

@@ -136,6 +136,11 @@ struct DevTables {
   const double* ks_scale_f;  // [n_q][nqp]: the same as doubles
   const uint64_t* moddown_rs;  // [n_q][n_p + 1][2]: P/p_k mod q_i (k < n_p), then P mod q_i (+Shoup)
   const uint64_t* moddown_rs_b;
+  // tuning choices of this context (every choice computes identical residues):
+  // log2 of the first NTT pass (both directions share it), row-pass access variant per
+  // direction (0 = 16-byte accesses, 1 = coalesced through an LDS transpose)
+  int split;
+  int rows_var[2];
 };
 
 // Geometry the kernels need.
@@ -146,13 +151,9 @@ struct Geo {
 // ---- launchers (kernels.hip / ntt.hip) ----
 int launch_ntt(const DevTables& t, int log2N, const RowSet& rows, bool inverse, hipStream_t s);
 // bumped whenever a tuning choice changes, so graphs captured before it are not reused
-int tune_epoch();
 // NTT pass split: the first pass of a 2^log2N transform has 2^la points (la in the options)
 void ntt_split_options(int log2N, int* las, int* n);
-int ntt_split_get(bool inverse, int log2N);
-void ntt_split_set(bool inverse, int log2N, int la);
-int rows_variant_set(int which, int value);
-int rows_variant_get(int which);
+int ntt_split_default(int log2N);
 int launch_ntt_ex(const DevTables& t, int log2N, const RowSet& rows, bool inverse, const NttExtra& x, hipStream_t s);
 // the fused row pass + inner product above; the pass split is the forward one in use
 int launch_ks_rows(const DevTables& t, int log2N, const KsRows& k, hipStream_t s);
@@ -172,6 +173,9 @@ void k_mul_scalar_launch(const Geo& g, const DevTables& t, CtV a, CtV out, int64
                          const uint64_t* k_res /* host [nl][2] */, hipStream_t s,
                          const uint64_t* k_dev = nullptr /* device [nl][2], replaces k_res */);
 // host words -> device, through kernel arguments (usable where a copy from host memory is not)
+// part 0 + k (k_res: host [nl], k mod q_i), other parts copied
+void k_add_scalar_launch(const Geo& g, const DevTables& t, CtV a, CtV out, int64_t count, int n_poly, int nl,
+                         const uint64_t* k_res, hipStream_t s);
 constexpr int kWriteWords = 240;
 void k_write_words_launch(uint64_t* dst, const uint64_t* src, size_t n, hipStream_t s);
 void k_copy_launch(const Geo& g, CtV a, CtV out, int64_t count, int n_poly, int nl, hipStream_t s);

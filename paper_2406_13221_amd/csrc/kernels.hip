@@ -219,6 +219,28 @@ __global__ void __launch_bounds__(EW_THREADS) k_mul_scalar(const PrimeConst* pc,
   st2(out.d + ct * out.cs + p * out.ps + off, mul_shoup(x.a, w.a, w.b, q), mul_shoup(x.b, w.a, w.b, q));
 }
 
+// cAdd: part 0 plus the constant polynomial k (each of its NTT evaluations is k itself, so
+// limb i adds k mod q_i to every residue); the other parts are copied
+__global__ void __launch_bounds__(EW_THREADS) k_add_scalar(const PrimeConst* pc, CtV a, CtV out, int logN, int nl,
+                                                            int n_poly, K64 k) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  int64_t bid = blockIdx.x;
+  int ch = (int)(bid % chunks);
+  int64_t row = bid / chunks;
+  int i = (int)(row % nl);
+  int64_t r2 = row / nl;
+  int p = (int)(r2 % n_poly);
+  int64_t ct = r2 / n_poly;
+  int64_t off = ((int64_t)i << logN) + ch * EW_CHUNK + threadIdx.x * 2;
+  U2 x = ld2(a.d + ct * a.cs + p * a.ps + off);
+  if (p == 0) {
+    const uint64_t q = pc[i].q, w = k.v[i].a;
+    x.a = addmod(x.a, w, q);
+    x.b = addmod(x.b, w, q);
+  }
+  st2(out.d + ct * out.cs + p * out.ps + off, x.a, x.b);
+}
+
 __global__ void __launch_bounds__(EW_THREADS) k_copy(CtV a, CtV out, int logN, int nl, int n_poly) {
   const int chunks = (1 << logN) / EW_CHUNK;
   int64_t bid = blockIdx.x;
@@ -591,6 +613,14 @@ void k_mul_scalar_launch(const Geo& g, const DevTables& t, CtV a, CtV out, int64
     for (int i = 0; i < nl; ++i) k.v[i] = U2{k_res[2 * i], k_res[2 * i + 1]};
   int64_t n = count * n_poly * nl * CHUNKS(g);
   if (n) LAUNCH(k_mul_scalar, n, s, t.pc, a, out, g.logN, nl, n_poly, k, reinterpret_cast<const U2*>(k_dev));
+}
+
+void k_add_scalar_launch(const Geo& g, const DevTables& t, CtV a, CtV out, int64_t count, int n_poly, int nl,
+                         const uint64_t* k_res, hipStream_t s) {
+  K64 k{};
+  for (int i = 0; i < nl; ++i) k.v[i] = U2{k_res[i], 0};
+  int64_t n = count * n_poly * nl * CHUNKS(g);
+  if (n) LAUNCH(k_add_scalar, n, s, t.pc, a, out, g.logN, nl, n_poly, k);
 }
 
 struct Words {

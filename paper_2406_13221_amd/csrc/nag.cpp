@@ -314,13 +314,13 @@ static std::string graph_key(const heqg_ctx* c, const heqg_keys* k, const heqg_c
   std::string key;
   auto put = [&](const void* p, size_t n) { key.append(static_cast<const char*>(p), n); };
   auto val = [&](auto v) { put(&v, sizeof(v)); };
-  val(k);
+  val(k->gen);  // first: heqg_keys_destroy drops the graphs of its key set by this prefix
   val(Z->data), val(Z->count), val(Z->stride), val(Z->level), val(Z->scale);
   for (const heqg_ct* x : {Bbar, W, V}) val(x->data), val(x->level), val(x->scale);
   val(sg->masks), val(sg->degree), val(sg->mask_level);
   for (int i = 0; i <= n_terms(sg->degree); ++i) val(sg->mask_scales[i]);
-  val(st->m_rows), val(st->g_cols), val(batch), val(ws), val(ws_bytes), val(tune_epoch());
-  (void)c;
+  val(st->m_rows), val(st->g_cols), val(batch), val(ws), val(ws_bytes);
+  val(c->t.split), val(c->t.rows_var[0]), val(c->t.rows_var[1]);
   return key;
 }
 
@@ -451,6 +451,14 @@ extern "C" int heqg_nag_qg_graph(heqg_ctx* c, const heqg_keys* k, const heqg_ct_
                                  heqg_ct* W, heqg_ct* V, const heqg_sigmoid* sg, heqg_nag_state* st, int batch,
                                  void* ws, size_t ws_bytes, hipStream_t s) {
   return nag_step(c, k, Z, Bbar, W, V, sg, st, batch, ws, ws_bytes, s, true);
+}
+
+extern "C" int heqg_graph_count(const heqg_ctx* c) {
+  if (!c) {
+    set_err("graph_count: null ctx");
+    return HEQG_ERR_ARG;
+  }
+  return (int)c->graphs.size();
 }
 
 extern "C" int heqg_graph_clear(heqg_ctx* c) {

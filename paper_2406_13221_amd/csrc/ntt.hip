@@ -1495,17 +1495,12 @@ struct ProfSample {
   }
 };
 
-int g_tune_epoch = 0;
-
-// Row-pass variant: 0 = 16-byte accesses in the consecutive layout, 1 = LDS-transposed
-// coalesced accesses.  Process-wide choice per direction (set by the tuner).
-int g_rows_variant[2] = {1, 1};
-
+// Row-pass variant (coal): 0 = 16-byte accesses in the consecutive layout, 1 = LDS-transposed
+// coalesced accesses; a per-context choice per direction (DevTables::rows_var, set by the tuner).
 template <int LB, bool FWD>
-void launch_rows(const NttParams& P, unsigned blocks, hipStream_t s) {
+void launch_rows(const NttParams& P, bool coal, unsigned blocks, hipStream_t s) {
   const bool fuse = FWD ? P.X.has_epi != 0 : P.X.in != nullptr;
   const bool ql = FWD && fuse && P.X.epi.qlinv;
-  const bool coal = g_rows_variant[FWD ? 0 : 1] != 0;
   if (ql) {
     if (coal)
       hipLaunchKernelGGL((k_ntt_rows<LB, FWD, true, 2>), dim3(blocks), dim3(256), 0, s, P);
@@ -1525,7 +1520,7 @@ void launch_rows(const NttParams& P, unsigned blocks, hipStream_t s) {
 
 template <int LA, int LB>
 void run_ntt(NttParams P, int64_t rows, bool inverse, const U2* twf, const U2* twi, const double* twff,
-             const double* twif, hipStream_t s) {
+             const double* twif, const int* rows_var, hipStream_t s) {
   const int N1 = 1 << LA, N2 = 1 << LB;
   const int tilesA = N2 / (256 / ((1 << LA) / 16));
   const int RB = 256 / ((1 << LB) / 16);
@@ -1568,13 +1563,13 @@ void run_ntt(NttParams P, int64_t rows, bool inverse, const U2* twf, const U2* t
     P.tiles = tilesB;
     ProfSample sr;
     if (!P.X.has_epi && !P.X.has_rs && !P.X.spread) sr.begin(0, rows, 0, 0.0, s);
-    launch_rows<LB, true>(P, blocksB, s);
+    launch_rows<LB, true>(P, rows_var[0] != 0, blocksB, s);
     sr.end(s);
   } else {
     P.tw = twi;
     P.twf = twif;
     P.tiles = tilesB;
-    if (!P.X.rows_done) launch_rows<LB, false>(P, blocksB, s);
+    if (!P.X.rows_done) launch_rows<LB, false>(P, rows_var[1] != 0, blocksB, s);
     P.tiles = tilesA;
     hipLaunchKernelGGL((k_ntt_cols<LA, false>), dim3((unsigned)(rows * tilesA)), dim3(256), 0, s, P);
   }
@@ -1582,21 +1577,6 @@ void run_ntt(NttParams P, int64_t rows, bool inverse, const U2* twf, const U2* t
 
 }  // namespace
 
-
-int tune_epoch() { return g_tune_epoch; }
-
-// rows-pass variants (which 0, 1); the pass splits (which 2, 3) are per ring and set in api.cpp
-int rows_variant_set(int which, int value) {
-  if (which < 0 || which > 1 || value < 0 || value > 1) return -1;
-  if (g_rows_variant[which] != value) ++g_tune_epoch;
-  g_rows_variant[which] = value;
-  return 0;
-}
-
-int rows_variant_get(int which) {
-  if (which < 0 || which > 1) return -1;
-  return g_rows_variant[which];
-}
 
 extern "C" int heqg_prof_start(int every) {
   ProfState& ps = prof();
@@ -1670,8 +1650,10 @@ int launch_ntt_ex(const DevTables& t, int log2N, const RowSet& rs, bool inverse,
   if (x.csrc && (x.ns < 1 || x.ns > 16 || rs.ni > HEQG_MAX_PRIMES)) return -1;
   const U2* twf = reinterpret_cast<const U2*>(t.tw_fwd);
   const U2* twi = reinterpret_cast<const U2*>(t.tw_inv);
-  const int la = ntt_split_get(inverse, log2N);
-#define HEQG_RUN(A, B) run_ntt<A, B>(P, rows, inverse, twf, twi, t.tw_fwd_f, t.tw_inv_f, s)
+  // one split for both directions: the fused key switch finishes the special-prime limbs'
+  // inverse transform with the column pass of the split whose row pass it ran (rows_done)
+  const int la = t.split;
+#define HEQG_RUN(A, B) run_ntt<A, B>(P, rows, inverse, twf, twi, t.tw_fwd_f, t.tw_inv_f, t.rows_var, s)
   switch (log2N * 16 + la) {
     case 12 * 16 + 6: HEQG_RUN(6, 6); break;
     case 13 * 16 + 6: HEQG_RUN(6, 7); break;
@@ -1713,7 +1695,7 @@ int launch_ks_rows(const DevTables& t, int log2N, const KsRows& k, hipStream_t s
   P.pc = t.pc;
   P.logN = log2N;
   P.tiles = (1 << log2N) / 4096;  // a workgroup holds 4096 residues of one row
-  switch (log2N - ntt_split_get(false, log2N)) {
+  switch (log2N - t.split) {
     case 6: run_ks_rows<6>(P, s); break;
     case 7: run_ks_rows<7>(P, s); break;
     case 8: run_ks_rows<8>(P, s); break;
@@ -1723,8 +1705,6 @@ int launch_ks_rows(const DevTables& t, int log2N, const KsRows& k, hipStream_t s
 }
 
 // ------------------------------------------------------------------ pass split choice
-static int g_split[2][17] = {};
-
 void ntt_split_options(int log2N, int* las, int* n) {
   // a pass holds at most 2^8 points (4 strided + 4 contiguous register stages)
   static const int o12[] = {6}, o13[] = {6}, o14[] = {7}, o15[] = {7, 8}, o16[] = {8};
@@ -1741,14 +1721,4 @@ void ntt_split_options(int log2N, int* las, int* n) {
   *n = k;
 }
 
-int ntt_split_get(bool inverse, int log2N) {
-  if (log2N < 12 || log2N > 16) return 0;
-  const int v = g_split[inverse ? 1 : 0][log2N];
-  return v ? v : log2N / 2;
-}
-
-void ntt_split_set(bool inverse, int log2N, int la) {
-  if (log2N < 12 || log2N > 16) return;
-  if (ntt_split_get(inverse, log2N) != la) ++g_tune_epoch;
-  g_split[inverse ? 1 : 0][log2N] = la;
-}
+int ntt_split_default(int log2N) { return (log2N < 12 || log2N > 16) ? 0 : log2N / 2; }

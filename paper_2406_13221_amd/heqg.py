@@ -104,8 +104,8 @@ def lib():
         "heqg_sigfit_grad": (i32, [vp, i64, vp, i32, vp, vp, vp, sz, vp]),
         "heqg_sigfit_train": (i32, [vp, i64, i32, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                     ctypes.c_float, vp, vp, sz, vp]),
-        "heqg_tune_set": (i32, [i32, i32]),
-        "heqg_tune_get": (i32, [i32]),
+        "heqg_tune_set": (i32, [vp, i32, i32]),
+        "heqg_tune_get": (i32, [vp, i32]),
         "heqg_tune_ws_bytes": (sz, [vp, i32]),
         "heqg_tune_ntt": (i32, [vp, i32, vp, sz, vp, P(i32), P(dbl)]),
         "heqg_prof_start": (i32, [i32]),
@@ -116,6 +116,14 @@ def lib():
         "heqg_nag_qg_graph": (i32, [vp, vp, P(BatchS), P(CtS), P(CtS), P(CtS), P(SigmoidS), P(NagStateS), i32, vp,
                                     sz, vp]),
         "heqg_graph_clear": (i32, [vp]),
+        "heqg_graph_count": (i32, [vp]),
+        "heqg_add_const": (i32, [vp, P(BatchS), dbl, P(BatchS), vp]),
+        "heqg_export_ws_bytes": (sz, [vp, P(BatchS)]),
+        "heqg_export": (i32, [vp, P(BatchS), vp, vp, sz, vp]),
+        "heqg_import": (i32, [vp, vp, P(BatchS), vp]),
+        "heqg_bbar": (i32, [vp, i64, i32, i32, dbl, vp, i32]),
+        "heqg_sigmoid_plan": (i32, [vp, i32, dbl, dbl, dbl, i32, vp]),
+        "heqg_sigmoid_masks": (i32, [vp, vp, i32, i32, i32, i32, dbl, dbl, dbl, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -145,6 +153,15 @@ def prof_stop(kernel=0):
     _check(lib().heqg_prof_stop(int(kernel), ctypes.byref(a), ctypes.byref(n), ctypes.byref(r), ctypes.byref(sr),
                                 ctypes.byref(op)))
     return a.value, n.value, r.value, sr.value, op.value
+
+
+def bbar(X, g, eps=1e-8, threads=0):
+    """Diagonal of B-bar (heqg_bbar): 1 / (eps + sum_l |H_jl|), H = 1/4 [1|X]^T [1|X]; 0 on padding."""
+    Xc = np.ascontiguousarray(X, dtype=np.float64)
+    n, f = Xc.shape
+    out = np.zeros(g, dtype=np.float64)
+    _check(lib().heqg_bbar(Xc.ctypes.data, n, f, g, float(eps), out.ctypes.data, int(threads)))
+    return out
 
 
 def _torch():
@@ -331,6 +348,7 @@ class Context:
         bi, bo = ct.batch(), out.batch()
         _check(L.heqg_refresh(self.h, keys.handle, ctypes.byref(bi), target_level, seed, obj_first, ctypes.byref(bo),
                               ws.data_ptr(), ws.numel(), _stream()))
+        out.scale = bo.scale
         return out
 
     def pt_load(self, coeffs, level):
@@ -349,74 +367,137 @@ class Context:
         return rows
 
     # ---------------------------------------------------------------- arithmetic
-    def _bin(self, fn, a, b, n_poly, scale):
-        lv = min(a.level, b.level)
-        out = self.empty(a.count, n_poly, lv, scale)
-        ba, bb, bo = a.batch(), b.batch(), out.batch()
-        _check(fn(self.h, ctypes.byref(ba), ctypes.byref(bb), ctypes.byref(bo), _stream()))
+    # Output levels are shape bookkeeping (they size the buffers); output scales are written by
+    # the library (heqg.h: the CKKS scale rules) and read back from the output batch.
+    def _out(self, count, n_poly, level):
+        return self.empty(count, n_poly, level, 0.0)
+
+    @staticmethod
+    def _done(out, bo):
+        out.scale = bo.scale
         return out
 
+    def _bin(self, fn, a, b, n_poly):
+        lv = min(a.level, b.level)
+        out = self._out(a.count, n_poly, lv)
+        ba, bb, bo = a.batch(), b.batch(), out.batch()
+        _check(fn(self.h, ctypes.byref(ba), ctypes.byref(bb), ctypes.byref(bo), _stream()))
+        return self._done(out, bo)
+
     def add(self, a, b):
-        return self._bin(lib().heqg_add, a, b, a.n_poly, a.scale)
+        return self._bin(lib().heqg_add, a, b, a.n_poly)
 
     def sub(self, a, b):
-        return self._bin(lib().heqg_sub, a, b, a.n_poly, a.scale)
+        return self._bin(lib().heqg_sub, a, b, a.n_poly)
 
     def tensor(self, a, b):
-        return self._bin(lib().heqg_tensor, a, b, 3, a.scale * b.scale)
+        return self._bin(lib().heqg_tensor, a, b, 3)
 
     def relin(self, keys, a):
-        out = self.empty(a.count, 2, a.level, a.scale)
+        out = self._out(a.count, 2, a.level)
         L = lib()
         ws = _ws(L.heqg_ks_ws_bytes(self.h, a.count))
         ba, bo = a.batch(), out.batch()
         _check(L.heqg_relin(self.h, keys.handle, ctypes.byref(ba), ctypes.byref(bo), ws.data_ptr(), ws.numel(),
                             _stream()))
-        return out
+        return self._done(out, bo)
 
     def hmult(self, keys, a, b):
         lv = min(a.level, b.level)
-        out = self.empty(a.count, 2, lv, a.scale * b.scale)
+        out = self._out(a.count, 2, lv)
         L = lib()
         ws = _ws(L.heqg_ks_ws_bytes(self.h, a.count) + 8 * a.count * 3 * (lv + 1) * self.N)
         ba, bb, bo = a.batch(), b.batch(), out.batch()
         _check(L.heqg_hmult(self.h, keys.handle, ctypes.byref(ba), ctypes.byref(bb), ctypes.byref(bo), ws.data_ptr(),
                             ws.numel(), _stream()))
-        return out
+        return self._done(out, bo)
 
     def rotate(self, keys, a, step):
-        out = self.empty(a.count, 2, a.level, a.scale)
+        out = self._out(a.count, 2, a.level)
         L = lib()
         ws = _ws(L.heqg_ks_ws_bytes(self.h, a.count) + 8 * a.count * 2 * (a.level + 1) * self.N)
         ba, bo = a.batch(), out.batch()
         _check(L.heqg_rotate(self.h, keys.handle, ctypes.byref(ba), step, ctypes.byref(bo), ws.data_ptr(), ws.numel(),
                              _stream()))
-        return out
+        return self._done(out, bo)
 
     def rescale(self, a):
-        out = self.empty(a.count, a.n_poly, a.level - 1, a.scale / float(int(self.primes[a.level])))
+        out = self._out(a.count, a.n_poly, a.level - 1)
         ws = _ws(8 * a.count * a.n_poly * (a.level + 1) * self.N)
         ba, bo = a.batch(), out.batch()
         _check(lib().heqg_rescale(self.h, ctypes.byref(ba), ctypes.byref(bo), ws.data_ptr(), ws.numel(), _stream()))
-        return out
+        return self._done(out, bo)
 
     def drop(self, a, level):
-        out = self.empty(a.count, a.n_poly, level, a.scale)
+        out = self._out(a.count, a.n_poly, level)
         ba, bo = a.batch(), out.batch()
         _check(lib().heqg_drop(self.h, ctypes.byref(ba), level, ctypes.byref(bo), _stream()))
-        return out
+        return self._done(out, bo)
 
     def mul_pt(self, a, pt, pt_scale):
-        out = self.empty(a.count, a.n_poly, a.level, a.scale * pt_scale)
+        out = self._out(a.count, a.n_poly, a.level)
         ba, bo = a.batch(), out.batch()
         _check(lib().heqg_mul_pt(self.h, ctypes.byref(ba), pt.data_ptr(), float(pt_scale), ctypes.byref(bo), _stream()))
-        return out
+        return self._done(out, bo)
 
     def add_pt(self, a, pt, pt_scale):
-        out = self.empty(a.count, 2, a.level, a.scale)
+        out = self._out(a.count, 2, a.level)
         ba, bo = a.batch(), out.batch()
         _check(lib().heqg_add_pt(self.h, ctypes.byref(ba), pt.data_ptr(), float(pt_scale), ctypes.byref(bo), _stream()))
+        return self._done(out, bo)
+
+    def add_const(self, a, c, out=None):
+        """cAdd: c added to every slot; out may be a (in place)."""
+        if out is None:
+            out = self._out(a.count, a.n_poly, a.level)
+        ba, bo = a.batch(), out.batch()
+        _check(lib().heqg_add_const(self.h, ctypes.byref(ba), float(c), ctypes.byref(bo), _stream()))
+        return self._done(out, bo)
+
+    def mul_const(self, a, c, target):
+        out = self._out(a.count, a.n_poly, a.level - 1)
+        ws = _ws(16 * a.count * a.n_poly * (a.level + 1) * self.N)
+        ba, bo = a.batch(), out.batch()
+        _check(lib().heqg_mul_const(self.h, ctypes.byref(ba), float(c), float(target), ctypes.byref(bo), ws.data_ptr(),
+                                    ws.numel(), _stream()))
+        return self._done(out, bo)
+
+    # ---------------------------------------------------------------- parity I/O
+    def export(self, a):
+        """Coefficient-form residues, numpy uint64 [count][n_poly][level+1][N]."""
+        L = lib()
+        ba = a.batch()
+        ws = _ws(L.heqg_export_ws_bytes(self.h, ctypes.byref(ba)))
+        out = np.zeros((a.count, a.n_poly, a.level + 1, self.N), dtype=np.uint64)
+        _check(L.heqg_export(self.h, ctypes.byref(ba), out.ctypes.data, ws.data_ptr(), ws.numel(), _stream()))
         return out
+
+    def import_(self, coeffs, level, scale):
+        """Coefficient-form residues [count][n_poly][level+1][N] -> NTT-form Cts on the GPU."""
+        c = np.ascontiguousarray(coeffs, dtype=np.uint64)
+        if c.ndim == 3:
+            c = c[None]
+        out = self.empty(c.shape[0], c.shape[1], level, scale)
+        bo = out.batch()
+        _check(lib().heqg_import(self.h, c.ctypes.data, ctypes.byref(bo), _stream()))
+        return out
+
+    # ---------------------------------------------------------------- client-side inputs
+    def sigmoid_masks(self, coeffs, m, g, level, s_z, s_w, s_c):
+        """{odd k: c_k} -> (int64 [n_terms+1][N] coefficient-form masks, their scales) (heqg_sigmoid_masks)."""
+        deg = max(coeffs)
+        cs = np.array([coeffs.get(k, 0.0) for k in range(1, deg + 1, 2)], dtype=np.float64)
+        nt = len(cs)
+        out = np.zeros((nt + 1, self.N), dtype=np.int64)
+        sc = np.zeros(nt + 1, dtype=np.float64)
+        _check(lib().heqg_sigmoid_masks(self.h, cs.ctypes.data, deg, m, g, level, float(s_z), float(s_w), float(s_c),
+                                        out.ctypes.data, sc.ctypes.data))
+        return out, [float(x) for x in sc]
+
+    def sigmoid_plan(self, level, s_z, s_w, s_c, degree):
+        sc = np.zeros((degree + 1) // 2 + 1, dtype=np.float64)
+        _check(lib().heqg_sigmoid_plan(self.h, level, float(s_z), float(s_w), float(s_c), degree, sc.ctypes.data))
+        return [float(x) for x in sc]
 
     # ---------------------------------------------------------------- training step
     def nag_ws_bytes(self, batch, degree=3):
@@ -445,8 +526,20 @@ class Context:
             ct.level, ct.scale = cs.level, cs.scale
         return state
 
-    def tune_ntt(self, rows=384):
-        """Time every NTT pass split and row-pass variant on `rows` limbs; keep the fastest per direction."""
+    def tune_set(self, which, value):
+        """Tuning choice of this context: 0/1 row-pass variant fwd/inv, 2 NTT pass split (False if refused)."""
+        return lib().heqg_tune_set(self.h, int(which), int(value)) == 0
+
+    def tune_get(self, which):
+        return lib().heqg_tune_get(self.h, int(which))
+
+    def graph_count(self):
+        return _check(lib().heqg_graph_count(self.h))
+
+    def tune_ntt(self, rows=2048):
+        """Time every NTT pass split and row-pass variant on `rows` limbs (default 2,048: 1 GiB at
+        N = 2^16, past the caches); keep the split with the fastest forward + inverse time and the
+        fastest variant of each direction."""
         L = lib()
         ws = _ws(L.heqg_tune_ws_bytes(self.h, rows))
         ch = (ctypes.c_int * 4)()

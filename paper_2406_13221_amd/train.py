@@ -46,39 +46,14 @@ def pack_rows(Z, m, g):
 
 
 def bbar_diag(X, g, eps=1e-8):
-    """1 / (eps + sum_l |H_jl|), H = 1/4 [1|X]^T [1|X] (sections 3.1, 4.3); 0 on padding columns."""
-    n, f = X.shape
-    A = np.hstack([np.ones((n, 1)), X])
-    H = 0.25 * (A.T @ A)
-    out = np.zeros(g)
-    out[:f + 1] = 1.0 / (eps + np.abs(H).sum(axis=1))
-    return out
+    """B-bar of rows X (sections 3.1, 4.3), computed by the library (heqg_bbar)."""
+    return heqg.bbar(X, g, eps)
 
 
 def tile_row(vec, m, g):
     row = np.zeros(g)
     row[:len(vec)] = vec
     return np.tile(row, m)
-
-
-def first_column(m, g):
-    F = np.zeros((m, g))
-    F[:, 0] = 1.0
-    return F.reshape(-1)
-
-
-def sigmoid_scales(primes, level, s_z, s_w, s_c, degree):
-    """Plaintext scales for the masked odd terms so every term reaches scale s_c."""
-    q = [float(int(p)) for p in primes]
-    s_u = s_z * s_w / q[level]
-    s_s = s_u * s_u / q[level - 1]
-    sc = {1: s_c * q[level - 1] / s_u, 3: s_c * q[level - 2] * q[level - 1] / (s_u * s_s)}
-    if degree >= 5:
-        s_s4 = s_s * s_s / q[level - 2]
-        sc[5] = s_c * q[level - 3] * q[level - 1] / (s_u * s_s4)
-        if degree >= 7:
-            sc[7] = s_c * q[level - 3] * q[level - 2] * q[level - 1] / (s_u * s_s * s_s4)
-    return sc
 
 
 def new_state(m, g, refresh_seed=0, lr_max=2.0, lr_min=1.0, T=81.0, gamma=2.5):
@@ -144,7 +119,7 @@ class EncryptedQGNAG:
         self.ws = heqg._ws(ctx.nag_ws_bytes(batch, self.degree))
         self.refresh_obj = 1 << 41
 
-    def tune(self, candidates=(8, 16, 24), blocks=48, rows=384):
+    def tune(self, candidates=(8, 16, 24), blocks=48, rows=2048):
         """Autotune: NTT pass split and row-pass variants (heqg_tune_ntt), then the number of
         blocks per lock-step chunk, timed on one iteration over the first `blocks` blocks."""
         import copy
@@ -209,22 +184,15 @@ class EncryptedQGNAG:
         return mb
 
     def set_sigmoid(self, coeffs):
-        """Encode -c_k F for each odd power (ascending) and F/2 at the planned scales, NTT form at level L-1."""
+        """Masks -c_k F for each odd power (ascending) and F/2 at the planned scales (heqg_sigmoid_masks),
+        loaded in NTT form at level L-1."""
         ctx = self.ctx
         self.coeffs = dict(coeffs)
         self.degree = max(self.coeffs)
         lv = self.L
-        s_c = ctx.delta
-        sc = sigmoid_scales(ctx.primes, lv, ctx.delta, ctx.delta, s_c, self.degree)
-        F = first_column(self.m, self.g)
-        vals, scales = [], []
-        for k in sorted(self.coeffs):
-            vals.append(ctx.encode(-self.coeffs[k] * F, sc[k]))
-            scales.append(sc[k])
-        vals.append(ctx.encode(0.5 * F, s_c))
-        scales.append(s_c)
+        vals, scales = ctx.sigmoid_masks(self.coeffs, self.m, self.g, lv, ctx.delta, ctx.delta, ctx.delta)
         self.mask_level = lv - 1
-        self.masks = ctx.pt_load(np.stack(vals), self.mask_level)
+        self.masks = ctx.pt_load(vals, self.mask_level)
         self.mask_scales = scales
 
     def step(self, refresh=True):

@@ -1,19 +1,26 @@
-"""Parity at the paper's full size (N = 2^16, 24 limbs, dnum 4, 422,108 x 200):
-batched key-switching operations in the chunk geometry the benchmark launches
-(24 ciphertexts per launch), compared with the oracle on sampled members of
-the batch; and one full-batch iteration over all 3,298 blocks, decrypted and
-compared with the FP64 plaintext trainer."""
+"""Parity at the paper's full size (N = 2^16, 24 limbs of 60/40 bits, seven
+42-bit special primes, dnum 4, 422,108 x 200):
+ - batched key-switching operations in the chunk geometry the benchmark tunes
+   to (16 ciphertexts per launch), compared with the oracle on sampled members;
+ - the whole iteration (heqg_nag_qg_step) residue by residue against the
+   oracle's circuit on the first blocks (a ragged 2 + 1 chunk), with the
+   learned degree-5 and degree-7 sigmoids, and as the mini-batch step over the
+   220-row tail of the data (422,108 mod 1,024) with its own B-bar;
+ - one full-batch iteration over all 3,298 blocks, decrypted and compared with
+   the FP64 plaintext trainer."""
 import numpy as np
 import pytest
 
 import synth
 from oracle import trainer
 from tests.gpu_common import assert_same_ct, make_pair
+from tests.nag_parity import run_parity
 
 pytestmark = pytest.mark.gpu
 
-CHUNK = 24               # blocks per launch in the benchmark's tuned configuration
-PICKS = (0, 11, 23)      # members of the batch the oracle recomputes
+CHUNK = 16               # blocks per launch the benchmark's chunk tuner settles on
+PICKS = (0, 7, 15)       # members of the batch the oracle recomputes
+TAIL = (421888, 422108)  # the last, short mini-batch: 422,108 mod 1,024 = 220 rows (2 blocks)
 
 
 @pytest.fixture(scope="module")
@@ -89,3 +96,19 @@ def test_c3_full_batch_iteration_matches_fp64(torch_cuda):
     w = run.weights(cfg["g"])
     ref = trainer.train(d["X"], d["y"], cfg["g"], 1)
     assert np.abs(w - ref["history"][0]["W"]).max() < 1e-3
+
+
+def test_c3_step_bit_exact_ragged_chunks(torch_cuda):
+    # 3 blocks, at most 2 per launch: chunks of 2 + 1
+    run_parity("c3", 1, batch=2, rows=(0, 384))
+
+
+@pytest.mark.parametrize("degree", [5, 7])
+def test_c3_learned_degree_step_bit_exact(torch_cuda, degree):
+    base = {5: [0.19129, -4.5951e-3, 4.2214e-5], 7: [0.21689, -8.1934e-3, 1.6588e-4, -1.1959e-6]}[degree]
+    run_parity("c3", 1, batch=1, coeffs={2 * i + 1: c for i, c in enumerate(base)}, rows=(0, 128))
+
+
+def test_c3_minibatch_tail_step_bit_exact(torch_cuda):
+    # the tail batch's own B-bar, its 92-row last block zero-padded
+    run_parity("c3", 1, batch=2, rows=TAIL)

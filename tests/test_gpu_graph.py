@@ -76,3 +76,27 @@ def test_graph_needs_a_stream(torch_cuda):
                             run.degree, run.state, run.batch, run.ws, stream=0, graph=True)
     assert e.value.code == heqg.ERR_ARG
     assert run.state.t == 0
+
+
+def test_destroyed_keys_drop_their_graphs(torch_cuda):
+    # a graph reads the switching keys it was captured with: destroying the key set drops its
+    # graphs, and a new key set (whose handle and buffers may reuse the old addresses) is captured
+    # afresh and gives the eager results
+    import gc
+    from paper_2406_13221_amd.train import rot_steps
+    torch = torch_cuda
+    cfg, d, eager, graph = _pair("c2", False, batch=3, rows=(0, 1024))
+    graph.step()
+    eager.step()
+    torch.cuda.synchronize()
+    assert graph.ctx.graph_count() == 1
+    graph.keys = None
+    gc.collect()
+    assert graph.ctx.graph_count() == 0
+    graph.keys = graph.ctx.keygen(cfg["key_seed"], rot_steps(cfg["m"], cfg["g"]))
+    graph.step()
+    eager.step()
+    torch.cuda.synchronize()
+    assert graph.ctx.graph_count() == 1
+    _same(torch, graph.W, eager.W, "W after a new key set")
+    _same(torch, graph.V, eager.V, "V after a new key set")

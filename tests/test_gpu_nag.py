@@ -6,9 +6,7 @@ import pytest
 
 import synth
 from oracle import circuit, trainer
-from oracle.ckks import Oracle
-from oracle.encode import encode
-from tests.gpu_common import assert_same_ct, gpu_ct
+from tests.nag_parity import gpu_side, gpu_state, oracle_setup, run_parity
 
 pytestmark = pytest.mark.gpu
 TOL_W = 1e-3
@@ -22,78 +20,15 @@ def torch_cuda():
     return torch
 
 
-def oracle_setup(cfgkey, coeffs=trainer.G8, rows=None, bbar_rows=None, **over):
-    cfg = synth.get_config(cfgkey)
-    cfg.update(over)
-    d = synth.make_dataset(cfg)
-    X, y = d["X"], d["y"]
-    if rows:
-        X, y = X[rows[0]:rows[1]], y[rows[0]:rows[1]]
-    o = Oracle.from_config(cfg)
-    N, m, g = o.N, cfg["m"], cfg["g"]
-    o.keygen(cfg["key_seed"], circuit.rot_steps(m, g))
-    Z = trainer.build_Z(X, y, g)
-    blocks = circuit.pack_blocks(Z, m, g, N)
-    L = o.top_level
-    Zc = [o.encrypt(encode(blocks[b], N, o.delta), L, o.delta, cfg["enc_seed"], b) for b in range(len(blocks))]
-    XB = X if bbar_rows is None else X[bbar_rows[0]:bbar_rows[1]]
-    B = trainer.bbar(XB, g)
-    sB = 2.0 ** 50 / B.max()
-    Bc = o.encrypt(encode(circuit.replicate_row(B, m, g), N, sB), L, sB, cfg["enc_seed"], 1 << 20)
-    W = o.encrypt(np.zeros(N, np.int64), L, o.delta, cfg["enc_seed"], (1 << 20) + 1)
-    V = o.encrypt(np.zeros(N, np.int64), L, o.delta, cfg["enc_seed"], (1 << 20) + 2)
-    masks = circuit.make_masks(o, m, g, coeffs, L, o.delta)
-    return cfg, o, X, y, Zc, Bc, W, V, masks
-
-
-def gpu_side(cfg, o, Zc, Bc, W, V, masks, coeffs):
-    import torch
-    from paper_2406_13221_amd import heqg
-    ctx = heqg.Context.from_config(cfg)
-    keys = ctx.keygen(cfg["key_seed"], circuit.rot_steps(cfg["m"], cfg["g"]))
-    Z = heqg.Cts(torch.from_numpy(np.stack([z.data for z in Zc]).view(np.int64).copy()).cuda(), Zc[0].level,
-                 Zc[0].scale)
-    order = sorted(coeffs) + ["half"]
-    mk = torch.from_numpy(np.stack([masks[k][0] for k in order]).view(np.int64).copy()).cuda()
-    scales = [masks[k][1] for k in order]
-    return ctx, keys, Z, gpu_ct(ctx, Bc), gpu_ct(ctx, W), gpu_ct(ctx, V), mk, scales
-
-
-def gpu_state(ost, m, g):
-    from paper_2406_13221_amd import heqg
-    return heqg.NagStateS(ost["t"], ost["alpha0"], ost["alpha1"], 2.0, 1.0, 81.0, 2.5, m, g, ost["refresh_seed"],
-                          0.0, 0.0, 0)
-
-
-def run_parity(cfgkey, iters, batch, coeffs=trainer.G8, rows=None, bbar_rows=None, **over):
-    cfg, o, X, y, Zc, Bc, W, V, masks = oracle_setup(cfgkey, coeffs, rows, bbar_rows, **over)
-    m, g, L = cfg["m"], cfg["g"], o.top_level
-    ctx, keys, gZ, gB, gW, gV, mk, scales = gpu_side(cfg, o, Zc, Bc, W, V, masks, coeffs)
-    deg = max(coeffs)
-    ost = circuit.new_state(refresh_seed=7)
-    gst = gpu_state(ost, m, g)
-    for it in range(iters):
-        W, V, ost = circuit.nag_qg_step(o, Zc, Bc, W, V, ost, masks, m, g, degree=deg)
-        ctx.nag_qg_step(keys, gZ, gB, gW, gV, mk, L - 1, scales, deg, gst, batch)
-        assert_same_ct(gW, W, "W%d" % it)
-        assert_same_ct(gV, V, "V%d" % it)
-        assert gst.t == ost["t"] and gst.alpha1 == ost["alpha1"] and gst.eta == ost["eta"]
-        assert bool(gst.refreshed_gr) == ost["refreshed_gr"]
-        W = o.refresh(W, L, 99, 2 * it)
-        V = o.refresh(V, L, 99, 2 * it + 1)
-        gW = ctx.refresh(keys, gW, L, 99, 2 * it)
-        gV = ctx.refresh(keys, gV, L, 99, 2 * it + 1)
-        assert_same_ct(gW, W, "W%d-refreshed" % it)
-    return o, W
-
-
 def test_c1_steps_bit_exact(torch_cuda):
     run_parity("c1", 3, batch=1)
 
 
-def test_c2_minibatch_step_bit_exact_ragged_chunks(torch_cuda):
-    # 1,280 rows = 5 blocks of 256 rows with their own B-bar; at most 3 per chunk: chunks of 3 + 2
-    run_parity("c2", 1, batch=3, rows=(0, 1280))
+@pytest.mark.parametrize("split", [7, 8])
+def test_c2_minibatch_step_bit_exact_ragged_chunks(torch_cuda, split):
+    # 1,280 rows = 5 blocks of 256 rows with their own B-bar; at most 3 per chunk: chunks of 3 + 2;
+    # N = 2^15 has two NTT pass splits, each runs the whole iteration
+    run_parity("c2", 1, batch=3, rows=(0, 1280), split=split)
 
 
 @pytest.mark.parametrize("degree", [5, 7])

@@ -1,9 +1,10 @@
-"""Every NTT choice the autotuner can make computes the oracle's transform bit
-for bit, and the tuner's pick is one of them."""
+"""Every NTT choice the autotuner can make computes the oracle's transform and
+key switches bit for bit, the choices belong to one context, and the tuner's
+pick is one of them."""
 import numpy as np
 import pytest
 
-from tests.gpu_common import cpu_u64, make_pair
+from tests.gpu_common import assert_same_ct, cpu_u64, gpu_ct, make_pair
 
 pytestmark = pytest.mark.gpu
 
@@ -29,50 +30,64 @@ def _check_ntt(torch, ora, ctx, reps, seed):
     assert np.array_equal(cpu_u64(g2), ora.ntt(a, pidx, inverse=True))
 
 
-@pytest.fixture
-def restore_tuning(torch_cuda):
-    from paper_2406_13221_amd import heqg
-    L = heqg.lib()
-    saved = [L.heqg_tune_get(w) for w in range(4)]
-    yield
-    for w, v in enumerate(saved):
-        L.heqg_tune_set(w, v)
-
-
-def test_every_split_and_variant_bit_exact(torch_cuda, restore_tuning):
-    from paper_2406_13221_amd import heqg
-    L = heqg.lib()
-    cfg, ora, ctx = make_pair("c2")               # N = 2^15: first pass 2^7 or 2^8
-    for la in (7, 8):
-        for v in (0, 1):
-            assert L.heqg_tune_set(2, la) == 0 and L.heqg_tune_set(3, la) == 0
-            assert L.heqg_tune_set(0, v) == 0 and L.heqg_tune_set(1, v) == 0
-            assert L.heqg_tune_get(2) == la and L.heqg_tune_get(1) == v
-            _check_ntt(torch_cuda, ora, ctx, 2, 10 * la + v)
-    assert L.heqg_tune_set(2, 9) == -1            # a pass holds at most 2^8 points
-    assert L.heqg_tune_set(4, 0) == -1
-
-
-def test_tuner_pick_is_valid_and_exact(torch_cuda, restore_tuning):
+@pytest.fixture(scope="module")
+def c2_ks(torch_cuda):
+    """c2 (N = 2^15, the ring with two pass splits): oracle relinearisation, rotations and
+    relinearisation + rescale at the top level and at level 6, computed once."""
+    steps = [1, -4, 64]
     cfg, ora, ctx = make_pair("c2")
+    ora.keygen(cfg["key_seed"], steps)
+    keys = ctx.keygen(cfg["key_seed"], steps)
+    rng = np.random.default_rng(71)
+    L = ora.top_level
+    cts = [ora.encrypt(rng.integers(-2 ** 40, 2 ** 40, ora.N), L, ora.delta, cfg["enc_seed"], i) for i in range(2)]
+    exp = {}
+    for lv in (L, 6):
+        a, b = (ora.drop(c, lv) for c in cts)
+        t = ora.tensor(a, b)
+        r = ora.relin(t)
+        exp[lv] = dict(a=a, b=b, t=t, relin=r, rs=ora.rescale(r), rot={s: ora.rotate(a, s) for s in steps})
+    return cfg, ora, ctx, keys, exp, steps
+
+
+@pytest.mark.parametrize("split", [7, 8])
+@pytest.mark.parametrize("variants", [(0, 0), (1, 1), (0, 1)])
+def test_every_split_and_variant_bit_exact(torch_cuda, c2_ks, split, variants):
+    cfg, ora, ctx, keys, exp, steps = c2_ks
+    assert ctx.tune_set(2, split) and ctx.tune_set(0, variants[0]) and ctx.tune_set(1, variants[1])
+    assert ctx.tune_get(2) == split and ctx.tune_get(0) == variants[0] and ctx.tune_get(1) == variants[1]
+    _check_ntt(torch_cuda, ora, ctx, 2, 10 * split + variants[0])
+    # key switching runs part of ModDown's inverse transform inside the forward row pass:
+    # relinearisation, the merged relinearisation + rescale and rotations at this split
+    for lv, e in exp.items():
+        a, b = gpu_ct(ctx, e["a"]), gpu_ct(ctx, e["b"])
+        r = ctx.relin(keys, gpu_ct(ctx, e["t"]))
+        assert_same_ct(r, e["relin"], "relin L%d split %d" % (lv, split))
+        assert_same_ct(ctx.rescale(r), e["rs"], "rescale L%d split %d" % (lv, split))
+        for s in steps:
+            assert_same_ct(ctx.rotate(keys, a, s), e["rot"][s], "rot%d L%d split %d" % (s, lv, split))
+        assert_same_ct(ctx.hmult(keys, a, b), e["relin"], "hmult L%d split %d" % (lv, split))
+
+
+def test_choices_are_per_context(torch_cuda):
+    cfg, ora, ctx = make_pair("c2")
+    cfg2, ora2, ctx2 = make_pair("c1")
+    assert ctx.tune_set(2, 8) and ctx.tune_get(2) == 8
+    assert ctx2.tune_get(2) == 6                   # N = 2^12 keeps its one split
+    assert ctx.tune_set(2, 7) and ctx2.tune_get(2) == 6 and ctx.tune_get(2) == 7
+    assert not ctx2.tune_set(2, 7)                 # not a split of N = 2^12
+    assert not ctx.tune_set(2, 9)                  # a pass holds at most 2^8 points
+    assert not ctx.tune_set(3, 7) and not ctx.tune_set(0, 2)
+    _check_ntt(torch_cuda, ora2, ctx2, 1, 3)
+
+
+def test_tuner_pick_is_valid_and_exact(torch_cuda, c2_ks):
+    cfg, ora, ctx, keys, exp, steps = c2_ks
     ch = ctx.tune_ntt(rows=2 * ctx.n_q)
-    assert ch["split_fwd"] in (7, 8) and ch["split_inv"] in (7, 8)
+    assert ch["split_fwd"] in (7, 8) and ch["split_inv"] == ch["split_fwd"]
     assert ch["variant_fwd"] in (0, 1) and ch["variant_inv"] in (0, 1)
     assert ch["fwd_us"] > 0 and ch["inv_us"] > 0
+    assert ctx.tune_get(2) == ch["split_fwd"]
     _check_ntt(torch_cuda, ora, ctx, 2, 5)
-
-
-def test_tuned_batch_gives_the_same_iteration(torch_cuda, restore_tuning):
-    # the chunk-size tuner only changes how many blocks share a launch
-    import synth
-    from paper_2406_13221_amd.train import EncryptedQGNAG
-    cfg = synth.get_config("c2")
-    d = synth.make_dataset(cfg)
-    a = EncryptedQGNAG(cfg, d["X"], d["y"], batch=16)
-    b = EncryptedQGNAG(cfg, d["X"], d["y"], batch=16)
-    res = b.tune(candidates=(4, 16), blocks=16)
-    assert res["batch"] in (4, 16) and set(res["batch_ms"]) == {4, 16}
-    a.step()
-    b.step()
-    torch_cuda.cuda.synchronize()
-    assert torch_cuda.equal(a.W.data, b.W.data) and torch_cuda.equal(a.V.data, b.V.data)
+    L = ora.top_level
+    assert_same_ct(ctx.relin(keys, gpu_ct(ctx, exp[L]["t"])), exp[L]["relin"], "relin after tuning")

@@ -167,3 +167,33 @@ def test_homomorphic_slot_product_and_sum():
     assert np.abs(o.decrypt_values(rot).real - np.roll(x, -7)).max() < 1e-6
     k = o.mul_const(cx, -0.3, d)
     assert np.abs(o.decrypt_values(k).real + 0.3 * x).max() < 1e-6
+
+
+@pytest.mark.parametrize("c", [0.75, -1.5, 1e-9, 0.0])
+def test_add_const_adds_round_c_scale_at_x0(c):
+    # cAdd (section 2.1): the decryption changes by exactly round(c * scale) in the constant
+    # coefficient and nowhere else (coefficient form, every limb), so every slot gains c
+    o = small_oracle()
+    rng = np.random.default_rng(9)
+    ct = o.encrypt(rng.integers(-2 ** 20, 2 ** 20, o.N), 3, 2.0 ** 30, SEED_ENC, 4)
+    r = o.add_const(ct, c)
+    assert r.level == ct.level and r.scale == ct.scale
+    assert np.array_equal(r.data[1], ct.data[1])
+    d0, d1 = o.decrypt(ct), o.decrypt(r)
+    k = int(np.round(abs(c) * 2 ** 30)) * (1 if c >= 0 else -1)
+    for i in range(ct.level + 1):
+        q = o.q(i)
+        diff = [(int(b) - int(a)) % q for a, b in zip(d0[i], d1[i])]
+        assert diff[0] == k % q and not any(diff[1:])
+    z0, z1 = o.decrypt_values(ct), o.decrypt_values(r)
+    assert np.allclose(z1 - z0, c, atol=1e-6)
+
+
+def test_add_const_three_parts_and_overflow():
+    o = small_oracle()
+    a = o.encrypt(np.arange(o.N), 3, 2.0 ** 30, SEED_ENC, 5)
+    t = o.tensor(a, a)
+    r = o.add_const(t, 2.0)
+    assert np.array_equal(r.data[1:], t.data[1:]) and not np.array_equal(r.data[0], t.data[0])
+    with pytest.raises(Exception):
+        o.add_const(a, 2.0 ** 40)
