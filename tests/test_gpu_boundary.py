@@ -32,8 +32,11 @@ def test_add_const_bit_exact(c1, c):
     for lv in (ora.top_level, 1):
         a = ora.drop(cts[0], lv)
         assert_same_ct(ctx.add_const(gpu_ct(ctx, a), c), ora.add_const(a, c), "add_const L%d" % lv)
+    # a tensor product carries scale 2^80: the constant is taken 2^-30 times smaller so
+    # that round(c * scale) stays below 2^62 on both sides
     t = ora.tensor(cts[0], cts[1])
-    assert_same_ct(ctx.add_const(gpu_ct(ctx, t), c), ora.add_const(t, c), "add_const 3 parts")
+    c3 = c * 2.0 ** -30
+    assert_same_ct(ctx.add_const(gpu_ct(ctx, t), c3), ora.add_const(t, c3), "add_const 3 parts")
 
 
 def test_add_const_in_place_and_overflow(c1):
