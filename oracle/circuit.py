@@ -23,6 +23,11 @@ After the blocks:
   G_v = Rescale(Relin(B_v (x) gr)),  G_w = Rescale(Relin(B_w (x) gr))
   V' = cMul(W, 1) + G_v;   W' = cMul(W, 1 - eta) + cMul(V, eta) + G_w
 Every cMul targets the working scale Delta, so W' and V' come out at Delta.
+
+With several column blocks (section 2.2: Z cut into m x g sub-matrices Z_ij, the
+model into g-column pieces W_j), nag_qg_step_grid sums the tensor products
+Z_ij (x) W_j of a row block before its one relinearisation, and column block j
+accumulates sum_i Z_ij (x) p_i; the rest runs per column block as above.
 """
 import math
 
@@ -45,6 +50,22 @@ def pack_blocks(Z, m, g, N):
     for b in range(nb):
         rows = Z[b * m: (b + 1) * m]
         out[b, : rows.size] = rows.reshape(-1)
+    return out
+
+
+def pack_grid(Z, m, g, N):
+    """The partition of section 2.2: Z (n x G, G a multiple of g) into ceil(n/m) x G/g
+    sub-matrices of m rows and g columns (zero rows pad the last row block), each packed
+    row by row into one slot vector of N/2 entries: out[i][j]."""
+    n, G = Z.shape
+    if G % g:
+        raise ValueError("the padded width must be a multiple of g")
+    nr, nc = (n + m - 1) // m, G // g
+    out = np.zeros((nr, nc, N // 2))
+    for i in range(nr):
+        for j in range(nc):
+            blk = Z[i * m: (i + 1) * m, j * g: (j + 1) * g]
+            out[i, j, : blk.size] = blk.reshape(-1)
     return out
 
 
@@ -122,42 +143,78 @@ def sigmoid_block(ora, u, masks, degree):
 
 
 def nag_qg_step(ora, Z_cts, B_ct, W, V, state, masks, m, g, degree=3, lr_fn=f2_lr, trace=None):
-    """One iteration; returns (W', V', new_state).  trace (list) collects intermediates."""
+    """One iteration with one column block (g >= f + 1); returns (W', V', new_state).
+    trace (list) collects intermediates."""
+    Wn, Vn, st = nag_qg_step_grid(ora, [[z] for z in Z_cts], [B_ct], [W], [V], state, masks, m, g, degree,
+                                  lr_fn, trace)
+    return Wn[0], Vn[0], st
+
+
+# Objects of the mid-iteration refresh of the gradient ciphertexts: (t << 4) | 2, plus j for
+# column block j, so at most this many column blocks may take it.
+MAX_REFRESH_COL_BLOCKS = 14
+
+
+def nag_qg_step_grid(ora, Z_grid, B_cts, Ws, Vs, state, masks, m, g, degree=3, lr_fn=f2_lr, trace=None):
+    """One iteration over the m x g sub-matrix partition of section 2.2: Z_grid[i][j] is row
+    block i, column block j (columns j*g .. j*g + g - 1 of Z); B_cts, Ws and Vs hold one
+    ciphertext per column block.  The margins of row block i are the row sums of
+    sum_j Z_ij (x) W_j (the tensor products added in three-part form, relinearised once);
+    the sigmoid, replicated across the row, then multiplies every Z_ij, and column block j
+    accumulates its own gradient sum_i Z_ij (x) p_i, whose column sums, B-bar product and NAG
+    update stay within that block.  Returns (W'_j list, V'_j list, new_state)."""
     lg, lm = int(math.log2(g)), int(math.log2(m))
-    acc = None
-    for b, Zb in enumerate(Z_cts):
-        u = ora.rescale(ora.hmult(Zb, W))
+    nc = len(Ws)
+    if not (len(Vs) == len(B_cts) == nc and all(len(row) == nc for row in Z_grid)):
+        raise ValueError("every row block needs one ciphertext per column block")
+    acc = [None] * nc
+    for i, row in enumerate(Z_grid):
+        t3 = None
+        for j in range(nc):
+            prod = ora.tensor(row[j], Ws[j])
+            t3 = prod if t3 is None else ora.add(t3, prod)
+        u = ora.rescale(ora.relin(t3))
         for k in range(lg):
             u = ora.add(u, ora.rotate(u, 1 << k))
         p = sigmoid_block(ora, u, masks, degree)
         for k in range(lg):
             p = ora.add(p, ora.rotate(p, -(1 << k)))
-        prod = ora.tensor(Zb, p)
-        acc = prod if acc is None else ora.add(acc, prod)
-        if trace is not None and b == 0:
+        for j in range(nc):
+            prod = ora.tensor(row[j], p)
+            acc[j] = prod if acc[j] is None else ora.add(acc[j], prod)
+        if trace is not None and i == 0:
             trace.append(("u0", u))
             trace.append(("p0", p))
-    gr = ora.rescale(ora.relin(acc))
-    for k in range(lm):
-        gr = ora.add(gr, ora.rotate(gr, g << k))
+    grs = []
+    for j in range(nc):
+        gr = ora.rescale(ora.relin(acc[j]))
+        for k in range(lm):
+            gr = ora.add(gr, ora.rotate(gr, g << k))
+        grs.append(gr)
     if trace is not None:
-        trace.append(("gr", gr))
+        trace.append(("gr", grs[0]))
     st = dict(state)
     t = st["t"]
-    if min(B_ct.level - 1, gr.level) < 1:
-        gr = ora.refresh(gr, ora.top_level, st["refresh_seed"], (t << 4) | 2)
+    B0 = B_cts[0]
+    if min(B0.level - 1, grs[0].level) < 1:
+        if nc > MAX_REFRESH_COL_BLOCKS:
+            raise ValueError("too many column blocks for a mid-iteration refresh")
+        grs = [ora.refresh(gr, ora.top_level, st["refresh_seed"], ((t << 4) | 2) + j) for j, gr in enumerate(grs)]
         st["refreshed_gr"] = True
     eta = (1.0 - st["alpha0"]) / st["alpha1"]
     lr = lr_fn(t)
     s_g = ora.delta
-    lt = min(B_ct.level - 1, gr.level)
-    s_bv = s_g * float(ora.q(lt)) / gr.scale
-    Bv = ora.mul_const(B_ct, lr, s_bv)
-    Bw = ora.mul_const(B_ct, lr * (1.0 - eta), s_bv)
-    Gv = ora.rescale(ora.hmult(Bv, gr))
-    Gw = ora.rescale(ora.hmult(Bw, gr))
-    Vn = ora.add(ora.mul_const(W, 1.0, s_g), Gv)
-    Wn = ora.add(ora.add(ora.mul_const(W, 1.0 - eta, s_g), ora.mul_const(V, eta, s_g)), Gw)
+    Wn, Vn = [], []
+    for j in range(nc):
+        gr = grs[j]
+        lt = min(B_cts[j].level - 1, gr.level)
+        s_bv = s_g * float(ora.q(lt)) / gr.scale
+        Bv = ora.mul_const(B_cts[j], lr, s_bv)
+        Bw = ora.mul_const(B_cts[j], lr * (1.0 - eta), s_bv)
+        Gv = ora.rescale(ora.hmult(Bv, gr))
+        Gw = ora.rescale(ora.hmult(Bw, gr))
+        Vn.append(ora.add(ora.mul_const(Ws[j], 1.0, s_g), Gv))
+        Wn.append(ora.add(ora.add(ora.mul_const(Ws[j], 1.0 - eta, s_g), ora.mul_const(Vs[j], eta, s_g)), Gw))
     st["t"] = t + 1
     st["alpha0"], st["alpha1"] = st["alpha1"], alpha_next(st["alpha1"])
     st["eta"], st["lr"] = eta, lr

@@ -7,5 +7,5 @@ training.  The paper's two datasets are not available, so workloads are drawn
 to the shapes of its experiments (section 5.1: 422,108 x 200 training rows,
 844,217 validation rows; mini-batch 1,024).
 """
-from .configs import CONFIGS, get_config  # noqa: F401
+from .configs import CONFIGS, col_blocks, get_config, padded_width  # noqa: F401
 from .data import make_dataset  # noqa: F401

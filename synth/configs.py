@@ -27,7 +27,23 @@ _BASE = {
 _BASE["c4"] = dict(_BASE["c3"], name="c4-batching-form")
 _BASE["c5"] = dict(_BASE["c3"], name="c5-learned-sigmoid", sigmoid_degree=(5, 7))
 
+# The m x g partition of section 2.2 with several column blocks (the padded width [1 | X | 0] is
+# cut into blocks of g columns): a tiny case (3 row blocks, the last ragged, x 2 column blocks),
+# the mid data as 16 x 4 blocks, and the paper-scale data as 413 x 7 blocks of 1,024 x 32.
+_BASE["c1g"] = dict(_BASE["c1"], name="c1-grid-m512-g4", m=512, g=4, n_train=1200, n_valid=2400)
+_BASE["c2g"] = dict(_BASE["c2"], name="c2-grid-m1024-g16", m=1024, g=16)
+_BASE["c3g"] = dict(_BASE["c3"], name="c3-grid-m1024-g32", m=1024, g=32)
+
 CONFIGS = _BASE
+
+
+def col_blocks(cfg):
+    """Column blocks of g columns covering the bias column and the features."""
+    return -(-(cfg["n_features"] + 1) // cfg["g"])
+
+
+def padded_width(cfg):
+    return col_blocks(cfg) * cfg["g"]
 
 
 def get_config(key):

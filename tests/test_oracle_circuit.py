@@ -104,3 +104,88 @@ def test_scale_mismatch_is_an_error():
     bad.scale *= 1.001
     with pytest.raises(ValueError):
         o.add(W, bad)
+
+
+# ---------------------------------------------------------------- m x g partition (section 2.2)
+def setup_grid(cfgkey, **over):
+    """Row blocks i x column blocks j of Z, and B-bar, W, V as one ciphertext per column block."""
+    cfg = synth.get_config(cfgkey)
+    cfg.update(over)
+    d = synth.make_dataset(cfg)
+    X, y = d["X"], d["y"]
+    o = Oracle.from_config(cfg)
+    N, m, g = o.N, cfg["m"], cfg["g"]
+    G, nc = synth.padded_width(cfg), synth.col_blocks(cfg)
+    o.keygen(cfg["key_seed"], circuit.rot_steps(m, g))
+    grid = circuit.pack_grid(trainer.build_Z(X, y, G), m, g, N)
+    L = o.top_level
+    Zg = [[o.encrypt(encode(grid[i, j], N, o.delta), L, o.delta, cfg["enc_seed"], i * nc + j) for j in range(nc)]
+          for i in range(grid.shape[0])]
+    B = trainer.bbar(X, G)
+    sB = 2.0 ** 50 / B.max()
+    Bc = [o.encrypt(encode(circuit.replicate_row(B[j * g:(j + 1) * g], m, g), N, sB), L, sB, cfg["enc_seed"],
+                    (1 << 20) + j) for j in range(nc)]
+    zero = np.zeros(N, np.int64)
+    W = [o.encrypt(zero, L, o.delta, cfg["enc_seed"], (1 << 21) + j) for j in range(nc)]
+    V = [o.encrypt(zero, L, o.delta, cfg["enc_seed"], (1 << 22) + j) for j in range(nc)]
+    masks = circuit.make_masks(o, m, g, trainer.G8, L, o.delta)
+    return cfg, o, X, y, Zg, Bc, W, V, masks
+
+
+def test_pack_grid_layout():
+    Z = np.arange(5 * 6, dtype=float).reshape(5, 6)
+    out = circuit.pack_grid(Z, 2, 3, 12)          # m = 2 rows, g = 3 columns, 6 slots
+    assert out.shape == (3, 2, 6)
+    assert np.array_equal(out[0, 1], [3, 4, 5, 9, 10, 11])
+    assert np.array_equal(out[2, 0], [24, 25, 26, 0, 0, 0])   # last row block zero-padded
+    # the single-column-block packing is the grid's j = 0
+    assert np.array_equal(circuit.pack_grid(Z[:, :3], 2, 3, 12)[:, 0], circuit.pack_blocks(Z[:, :3], 2, 3, 12))
+
+
+def test_grid_iterations_match_fp64():
+    """2 iterations over 3 row blocks (the last ragged) x 2 column blocks follow the FP64 trainer on the
+    padded width; the split of the model over column blocks does not change the method (section 2.2)."""
+    cfg, o, X, y, Zg, Bc, W, V, masks = setup_grid("c1g")
+    m, g, L, nc = cfg["m"], cfg["g"], o.top_level, len(W)
+    assert (len(Zg), nc) == (3, 2)
+    G = nc * g
+    ref = trainer.train(X, y, G, 2)
+    st = circuit.new_state(refresh_seed=7)
+    for it in range(2):
+        W, V, st = circuit.nag_qg_step_grid(o, Zg, Bc, W, V, st, masks, m, g)
+        assert st["refreshed_gr"]
+        W = [o.refresh(w, L, 99, 4 * it + j) for j, w in enumerate(W)]
+        V = [o.refresh(v, L, 99, 4 * it + 2 + j) for j, v in enumerate(V)]
+        w = np.concatenate([o.decrypt_values(c, g).real for c in W])
+        assert np.abs(w - ref["history"][it]["W"]).max() < TOL_W
+    v = np.concatenate([o.decrypt_values(c, g).real for c in V])
+    assert np.abs(v - ref["V"]).max() < TOL_W
+
+
+def test_grid_intermediates_are_the_plaintext_quantities():
+    """From a nonzero W: row block 0's margins sum the products of both column blocks; the
+    sigmoid column is replicated; column block 0's gradient sums every row block."""
+    cfg, o, X, y, Zg, Bc, W, V, masks = setup_grid("c1g")
+    m, g, nc = cfg["m"], cfg["g"], len(W)
+    G = nc * g
+    rng = np.random.default_rng(3)
+    w = np.zeros(G)
+    w[: X.shape[1] + 1] = rng.normal(size=X.shape[1] + 1) * 0.5
+    Wc = [o.encrypt(encode(circuit.replicate_row(w[j * g:(j + 1) * g], m, g), o.N, o.delta), o.top_level,
+                    o.delta, 9, 9 + j) for j in range(nc)]
+    trace = []
+    circuit.nag_qg_step_grid(o, Zg, Bc, Wc, Wc, circuit.new_state(7), masks, m, g, trace=trace)
+    tr = dict(trace)
+    Z = trainer.build_Z(X, y, G)
+    Zp = np.zeros((len(Zg) * m, G))
+    Zp[: Z.shape[0]] = Z
+    margins = Zp @ w
+    u = o.decrypt_values(tr["u0"]).real.reshape(m, g)
+    assert np.abs(u[:, 0] - margins[:m]).max() < 1e-6
+    p_ref = 1 - trainer.sigma_tilde(margins, trainer.G8)
+    p = o.decrypt_values(tr["p0"]).real.reshape(m, g)
+    assert np.abs(p - p_ref[:m, None]).max() < 1e-6
+    # padding rows of the last row block have zero Z, so they add nothing to the gradient
+    gr = o.decrypt_values(tr["gr"]).real.reshape(m, g)
+    assert np.abs(gr - (Zp[:, :g].T @ p_ref)[None, :]).max() < 1e-5
+
