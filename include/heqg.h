@@ -250,6 +250,28 @@ int heqg_hmult(heqg_ctx* ctx, const heqg_keys* keys, const heqg_ct_batch* a, con
  */
 int heqg_rotate(heqg_ctx* ctx, const heqg_keys* keys, const heqg_ct_batch* in, int step, heqg_ct_batch* out,
                 void* ws, size_t ws_bytes, hipStream_t s);
+
+/*
+ * heqg_rotate without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  The key switch's workspace is a device array of
+ * HEQG_SCRATCH_MIB MiB inside the library: every device the library runs on
+ * holds its own copy from the code object's load until the process ends (the
+ * one exception to "the library never allocates").  The call allocates
+ * nothing; inputs, outputs and keys are the caller's as for heqg_rotate, and
+ * the result is identical to heqg_rotate's.  A batch is rotated in chunks of
+ * as many ciphertexts as fit the array, one after another on `s`.
+ * HEQG_ERR_UNSUPPORTED if one ciphertext at in->level needs more (it does
+ * not at the paper-scale parameters: 155 MiB at N = 2^16, 24 + 7 limbs);
+ * HEQG_ERR_DEVICE if the array's address cannot be obtained on the current
+ * device (looked up once per device, by heqg_ctx_create there, so that the
+ * first call allocates nothing either).  All calls on
+ * one device share its array: calls that overlap in time on one device (other
+ * streams, other threads) race and give wrong results; serialise them.
+ */
+#define HEQG_SCRATCH_MIB 160
+int heqg_rotate_noalloc(heqg_ctx* ctx, const heqg_keys* keys, const heqg_ct_batch* in, int step,
+                        heqg_ct_batch* out, hipStream_t s);
 /*
  * Rescale by the last prime q_l: x_i <- (x_i - [x_l]_centred) * q_l^-1 mod q_i,
  * level l -> l-1, scale / q_l.  HEQG_ERR_LEVEL at level 0.

@@ -36,6 +36,7 @@ extern "C" int heqg_ctx_create(const heqg_params* p, void* dev_tables, size_t by
     delete c;
     return rc;
   }
+  noalloc_setup_current_device();
   *out = c;
   return HEQG_OK;
 }

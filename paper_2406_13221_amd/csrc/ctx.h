@@ -53,3 +53,5 @@ size_t ctx_layout(const heqg_params* p, bool check, std::string* err, size_t off
 int ctx_build(heqg_ctx* c, void* dev, size_t bytes, std::string* err);
 
 void set_err(const std::string& s);
+// Looks up the allocation-free entry point's device array on the current device (noalloc.cpp).
+void noalloc_setup_current_device();

@@ -94,6 +94,7 @@ def lib():
         "heqg_relin": (i32, [vp, vp, P(BatchS), P(BatchS), vp, sz, vp]),
         "heqg_hmult": (i32, [vp, vp, P(BatchS), P(BatchS), P(BatchS), vp, sz, vp]),
         "heqg_rotate": (i32, [vp, vp, P(BatchS), i32, P(BatchS), vp, sz, vp]),
+        "heqg_rotate_noalloc": (i32, [vp, vp, P(BatchS), i32, P(BatchS), vp]),
         "heqg_rescale": (i32, [vp, P(BatchS), P(BatchS), vp, sz, vp]),
         "heqg_drop": (i32, [vp, P(BatchS), i32, P(BatchS), vp]),
         "heqg_mul_pt": (i32, [vp, P(BatchS), vp, dbl, P(BatchS), vp]),
@@ -419,6 +420,14 @@ class Context:
         ba, bo = a.batch(), out.batch()
         _check(L.heqg_rotate(self.h, keys.handle, ctypes.byref(ba), step, ctypes.byref(bo), ws.data_ptr(), ws.numel(),
                              _stream()))
+        return self._done(out, bo)
+
+    def rotate_noalloc(self, keys, a, step, out=None):
+        """heqg_rotate_noalloc: the workspace is the library's own device array."""
+        if out is None:
+            out = self._out(a.count, 2, a.level)
+        ba, bo = a.batch(), out.batch()
+        _check(lib().heqg_rotate_noalloc(self.h, keys.handle, ctypes.byref(ba), step, ctypes.byref(bo), _stream()))
         return self._done(out, bo)
 
     def rescale(self, a):
