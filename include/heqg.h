@@ -474,8 +474,11 @@ typedef struct {
  * NAG state (Algorithm 1): iteration index t (0-based), alpha0, alpha1; the
  * learning-rate multiplier on G is F2(t) = lr_max - (lr_max - lr_min)*(t/T)^gamma.
  * On return t is incremented and (alpha0, alpha1) advanced; eta and lr hold
- * the values used; refreshed_gr is 1 when the gradient ciphertext had to be
+ * the values used; refreshed_gr is 1 when the gradient ciphertexts had to be
  * refreshed mid-iteration (chains too short for the whole iteration).
+ * col_blocks: the number of column blocks of the m_rows x g_cols partition
+ * of section 2.2 (0 is taken as 1): the padded width [1 | X | 0] is
+ * col_blocks * g_cols columns.
  */
 typedef struct {
   int t;
@@ -485,22 +488,28 @@ typedef struct {
   uint64_t refresh_seed;
   double eta, lr;
   int refreshed_gr;
+  int col_blocks;
 } heqg_nag_state;
 
-/* Device workspace bytes for heqg_nag_qg_step with `batch` blocks in flight. */
+/* Device workspace bytes for heqg_nag_qg_step with `batch` row blocks in flight. */
 size_t heqg_nag_ws_bytes(const heqg_ctx* ctx, int batch, int degree);
 
 /*
  * One encrypted QG-NAG iteration over the blocks Z (all blocks: full-batch,
  * section 3.3; the blocks of one mini-batch with that batch's B-bar:
  * Algorithm 1).  Z, Bbar, W, V at one level with W, V at the working scale.
- * Per block: margins u = Rescale(Relin(Z_b (x) W)), row sums by rotations,
- * masked sigmoid p = 1 - sigma~(u) in column 0, replication across the row,
- * accumulation of Z_b (x) p.  Then relinearise + rescale, column sums,
- * G_v = (lr B-bar) g, G_w = (lr (1-eta) B-bar) g, and
- * V' = W + G_v,  W' = (1-eta) W + eta V + G_w  (section 3.2, Algorithm 1).
- * W and V are overwritten with W', V' (level lower by the depth used, scale
- * Delta).  `batch` blocks are processed per launch (1 <= batch).
+ * With C = st->col_blocks column blocks (section 2.2), Z holds row block i,
+ * column block j as ciphertext i*C + j, and Bbar, W and V each point to C
+ * ciphertexts stored back to back ([C][2][level+1][N], for W and V at their
+ * level on input and on output).  Per row block i: margins
+ * u = Rescale(Relin(sum_j Z_ij (x) W_j)), row sums by rotations, masked
+ * sigmoid p = 1 - sigma~(u) in column 0, replication across the row, and
+ * accumulation of Z_ij (x) p into column block j's gradient.  Then per
+ * column block: relinearise + rescale, column sums, G_v = (lr B-bar) g,
+ * G_w = (lr (1-eta) B-bar) g, V' = W + G_v,  W' = (1-eta) W + eta V + G_w
+ * (section 3.2, Algorithm 1).  W and V are overwritten with W', V' (level
+ * lower by the depth used, scale Delta).  `batch` row blocks are processed
+ * per launch (C <= batch, else HEQG_ERR_ARG).
  */
 int heqg_nag_qg_step(heqg_ctx* ctx, const heqg_keys* keys, const heqg_ct_batch* Z, const heqg_ct* Bbar,
                      heqg_ct* W, heqg_ct* V, const heqg_sigmoid* sig, heqg_nag_state* st, int batch, void* ws,

@@ -162,8 +162,11 @@ void k_add_launch(const Geo& g, const DevTables& t, CtV a, CtV b, CtV out, int64
                   hipStream_t s);
 void k_tensor_launch(const Geo& g, const DevTables& t, CtV a, CtV b, CtV out, int64_t count, int nl, bool acc,
                      hipStream_t s);
+// groups independent reductions in one launch: group r reads a, b and writes acc offset by
+// r*a_gs, r*b_gs, r*acc_gs words
 void k_tensor_reduce_launch(const Geo& g, const DevTables& t, CtV a, CtV b, int64_t count, CtV acc, int nl,
-                            bool accumulate, hipStream_t s);
+                            bool accumulate, hipStream_t s, int64_t groups = 1, int64_t a_gs = 0, int64_t b_gs = 0,
+                            int64_t acc_gs = 0);
 // limbs first .. first + nl - 1 of a times the same limbs of pt, into limbs 0 .. nl - 1 of out
 void k_mul_pt_launch(const Geo& g, const DevTables& t, CtV a, const uint64_t* pt, CtV out, int64_t count, int n_poly,
                      int nl, hipStream_t s, int first = 0);

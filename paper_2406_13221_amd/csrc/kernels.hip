@@ -110,17 +110,25 @@ __global__ void __launch_bounds__(EW_THREADS) k_tensor(const PrimeConst* pc, CtV
   st2(po + 2 * out.ps, d2a, d2b);
 }
 
-// acc (3 parts, one ciphertext) (+)= sum_b a_b (x) b_b
+// For each group r < groups: acc_r (3 parts) (+)= sum_b a_{r,b} (x) b_{r,b}, where operand x of
+// group r, term b starts at x.d + r*gs.x + b*x.cs (gs: the groups' strides; acc_r at acc.d + r*gs.o).
+struct GroupStrides {
+  int64_t a, b, o;
+};
 __global__ void __launch_bounds__(EW_THREADS) k_tensor_reduce(const PrimeConst* pc, CtV a, CtV b, int64_t count, CtV acc,
-                                                               int logN, int nl, int accumulate) {
+                                                               int logN, int nl, int accumulate, GroupStrides gs) {
   const int chunks = (1 << logN) / EW_CHUNK;
   int64_t bid = blockIdx.x;
   int ch = (int)(bid % chunks);
-  int i = (int)(bid / chunks);
+  int64_t row = bid / chunks;
+  int i = (int)(row % nl);
+  const int64_t grp = row / nl;
+  a.d += grp * gs.a;
+  b.d += grp * gs.b;
   int64_t off = ((int64_t)i << logN) + ch * EW_CHUNK + threadIdx.x * 2;
   const PrimeConst P = pc[i];
   uint64_t s0a = 0, s1a = 0, s2a = 0, s0b = 0, s1b = 0, s2b = 0;
-  uint64_t* po = acc.d + off;
+  uint64_t* po = acc.d + grp * gs.o + off;
   if (accumulate) {
     U2 o0 = ld2(po), o1 = ld2(po + acc.ps), o2 = ld2(po + 2 * acc.ps);
     s0a = o0.a; s0b = o0.b; s1a = o1.a; s1b = o1.b; s2a = o2.a; s2b = o2.b;
@@ -591,9 +599,11 @@ void k_tensor_launch(const Geo& g, const DevTables& t, CtV a, CtV b, CtV out, in
   if (n) LAUNCH(k_tensor, n, s, t.pc, a, b, out, g.logN, nl, acc ? 1 : 0);
 }
 void k_tensor_reduce_launch(const Geo& g, const DevTables& t, CtV a, CtV b, int64_t count, CtV acc, int nl,
-                            bool accumulate, hipStream_t s) {
-  int64_t n = (int64_t)nl * CHUNKS(g);
-  LAUNCH(k_tensor_reduce, n, s, t.pc, a, b, count, acc, g.logN, nl, accumulate ? 1 : 0);
+                            bool accumulate, hipStream_t s, int64_t groups, int64_t a_gs, int64_t b_gs,
+                            int64_t acc_gs) {
+  int64_t n = groups * nl * CHUNKS(g);
+  if (n) LAUNCH(k_tensor_reduce, n, s, t.pc, a, b, count, acc, g.logN, nl, accumulate ? 1 : 0,
+                GroupStrides{a_gs, b_gs, acc_gs});
 }
 void k_mul_pt_launch(const Geo& g, const DevTables& t, CtV a, const uint64_t* pt, CtV out, int64_t count, int n_poly,
                      int nl, hipStream_t s, int first) {

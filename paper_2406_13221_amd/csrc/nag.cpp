@@ -224,9 +224,13 @@ Ct sigmoid_block(Exec& X, const Ct& u, const heqg_sigmoid* sg) {
 }
 
 struct Io {
-  Ct Z;  // all blocks
-  Ct Bbar, W, V;
+  Ct Z;            // all blocks, row block i and column block j at i * nc + j
+  Ct Bbar, W, V;   // nc ciphertexts each
+  int nc;          // column blocks (section 2.2)
 };
+
+// max refresh objects per iteration: (t << 4) | 2 + j, j < nc
+constexpr int kMaxRefreshColBlocks = 14;
 
 // the whole iteration; returns (W', V') in slots, updates st
 void circuit(Exec& X, const Io& io, const heqg_sigmoid* sg, heqg_nag_state* st, int64_t n_blocks, Ct& Wn, Ct& Vn) {
@@ -234,13 +238,14 @@ void circuit(Exec& X, const Io& io, const heqg_sigmoid* sg, heqg_nag_state* st, 
   int lg = 0, lm = 0;
   while ((1 << lg) < g) ++lg;
   while ((1 << lm) < m) ++lm;
-  // acc lives in slot 0 for the whole iteration
+  const int nc = io.nc;
+  // the column blocks' gradient accumulators live in slot 0 for the whole iteration
   Ct acc{};
   bool have_acc = false;
   X.reset(0);
-  Ct accs = X.slot(3, 0, 0.0, 1);
+  Ct accs = X.slot(3, 0, 0.0, nc);
   size_t base = X.next;
-  // balanced chunks of at most B blocks: the remainder of n_blocks / B is spread over the
+  // balanced chunks of at most B row blocks: the remainder of n_blocks / B is spread over the
   // chunks instead of ending the iteration with one short, under-filled chunk
   const int64_t n_chunks = (n_blocks + X.B - 1) / X.B;
   const int64_t q_chunk = n_blocks / n_chunks, r_chunk = n_blocks % n_chunks;
@@ -248,9 +253,27 @@ void circuit(Exec& X, const Io& io, const heqg_sigmoid* sg, heqg_nag_state* st, 
     const int64_t cnt = q_chunk + (ci < r_chunk ? 1 : 0);
     X.reset(base);
     Ct Zc = io.Z;
-    Zc.d = io.Z.d + b0 * io.Z.cs;
-    Zc.count = cnt;
-    Ct u = X.hmult_rs(Zc, io.W);
+    Zc.d = io.Z.d + b0 * nc * io.Z.cs;
+    Zc.count = cnt * nc;
+    Ct u{};
+    if (nc == 1) {
+      u = X.hmult_rs(Zc, io.W);
+    } else {
+      // sum_j Z_ij (x) W_j for every row block i of the chunk (one three-part ciphertext each),
+      // then one relinearisation + rescale per row block
+      Ct Zl = Zc, Wl = io.W;
+      X.align(Zl, Wl);
+      const size_t mark = X.next;
+      Ct u3 = X.slot(3, Zl.level, Zl.scale * Wl.scale, cnt);
+      if (!X.dry)
+        k_tensor_reduce_launch(X.c->g, X.c->t, CtV{Zl.d, Zl.cs, Zl.ps}, CtV{Wl.d, Wl.cs, Wl.ps}, nc,
+                               u3.v(), Zl.level + 1, false, X.s, cnt, nc * Zl.cs, 0, u3.cs);
+      u = X.relin_rs(u3);
+      // keep u only: move it to the first slot of this step
+      if (!X.dry) std::swap(X.slots[mark], X.slots[X.next - 1]);
+      u.d = X.slots[mark];
+      X.reset(mark + 1);
+    }
     for (int k = 0; k < lg; ++k) u = X.add_rot(u, 1 << k);
     Ct p = sigmoid_block(X, u, sg);
     for (int k = 0; k < lg; ++k) p = X.add_rot(p, -(1 << k));
@@ -265,7 +288,10 @@ void circuit(Exec& X, const Io& io, const heqg_sigmoid* sg, heqg_nag_state* st, 
       acc.scale = sc;
       acc.n_poly = 3;
     }
-    if (!X.dry) k_tensor_reduce_launch(X.c->g, X.c->t, Zd.v(), p.v(), cnt, acc.v(), p.level + 1, have_acc, X.s);
+    // column block j: acc_j (+)= sum_i Z_ij (x) p_i over the chunk's row blocks
+    if (!X.dry)
+      k_tensor_reduce_launch(X.c->g, X.c->t, CtV{Zd.d, nc * Zd.cs, Zd.ps}, p.v(), cnt, CtV{acc.d, acc.cs, acc.ps},
+                             p.level + 1, have_acc, X.s, nc, Zd.cs, 0, acc.cs);
     have_acc = true;
     b0 += cnt;
   }
@@ -275,6 +301,7 @@ void circuit(Exec& X, const Io& io, const heqg_sigmoid* sg, heqg_nag_state* st, 
   const int t = st->t;
   st->refreshed_gr = 0;
   if (std::min(io.Bbar.level - 1, gr.level) < 1) {
+    if (nc > kMaxRefreshColBlocks) X.fail(HEQG_ERR_UNSUPPORTED, "too many column blocks for a mid-iteration refresh");
     gr = X.refresh(gr, X.c->g.n_q - 1, st->refresh_seed, ((uint64_t)t << 4) | 2);
     st->refreshed_gr = 1;
   }
@@ -302,8 +329,9 @@ extern "C" size_t heqg_nag_ws_bytes(const heqg_ctx* c, int batch, int degree) {
   (void)degree;
   if (!c || batch < 1) return 0;
   const int top = c->g.n_q - 1;
+  // key switches of `batch` ciphertexts; a mid-iteration refresh of up to `batch` gradients
   size_t ks = std::max(ops::rot_ws_words(c, batch, top),
-                       ops::enc_ws_words(c, 1) + (size_t)c->g.n_q * c->g.N);
+                       ops::enc_ws_words(c, batch) + (size_t)batch * c->g.n_q * c->g.N);
   size_t rs = 2 * slot_words(c, batch);
   return 8 * (kSlots * slot_words(c, batch) + ks + rs + kConstWords);
 }
@@ -319,7 +347,7 @@ static std::string graph_key(const heqg_ctx* c, const heqg_keys* k, const heqg_c
   for (const heqg_ct* x : {Bbar, W, V}) val(x->data), val(x->level), val(x->scale);
   val(sg->masks), val(sg->degree), val(sg->mask_level);
   for (int i = 0; i <= n_terms(sg->degree); ++i) val(sg->mask_scales[i]);
-  val(st->m_rows), val(st->g_cols), val(batch), val(ws), val(ws_bytes);
+  val(st->m_rows), val(st->g_cols), val(st->col_blocks), val(batch), val(ws), val(ws_bytes);
   val(c->t.split), val(c->t.rows_var[0]), val(c->t.rows_var[1]);
   return key;
 }
@@ -332,6 +360,7 @@ static int nag_step(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch* Z, con
     set_err("nag_qg_step: null argument");
     return HEQG_ERR_ARG;
   }
+  const int nc = st ? std::max(1, st->col_blocks) : 1;
   if (batch < 1 || Z->count < 1 || Z->n_poly != 2 || Bbar->n_poly != 2 || W->n_poly != 2 || V->n_poly != 2 ||
       (sg->degree != 3 && sg->degree != 5 && sg->degree != 7) || st->m_rows < 1 || st->g_cols < 1 ||
       (int64_t)st->m_rows * st->g_cols != c->g.N / 2 || (st->g_cols & (st->g_cols - 1)) ||
@@ -348,6 +377,10 @@ static int nag_step(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch* Z, con
     set_err("nag_qg_step: Z stride too small");
     return HEQG_ERR_ARG;
   }
+  if (Z->count % nc || nc > batch || st->col_blocks < 0) {
+    set_err("nag_qg_step: Z must hold whole row blocks of col_blocks ciphertexts, and col_blocks <= batch");
+    return HEQG_ERR_ARG;
+  }
   if (!ws || ws_bytes < heqg_nag_ws_bytes(c, batch, sg->degree)) {
     set_err("nag_qg_step: workspace too small");
     return HEQG_ERR_ARG;
@@ -362,26 +395,30 @@ static int nag_step(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch* Z, con
   for (int i = 0; i < kSlots; ++i) X.slots.push_back(w + (size_t)i * slot_words(c, batch));
   X.ks_ws = w + (size_t)kSlots * slot_words(c, batch);
   X.rs_ws = X.ks_ws + std::max(ops::rot_ws_words(c, batch, c->g.n_q - 1),
-                               ops::enc_ws_words(c, 1) + (size_t)c->g.n_q * N);
+                               ops::enc_ws_words(c, batch) + (size_t)batch * c->g.n_q * N);
   uint64_t* consts_dev = X.rs_ws + 2 * slot_words(c, batch);
   Io io;
   io.Z = Ct{Z->data, Z->stride, (int64_t)(Z->level + 1) * N, 2, Z->level, Z->scale, Z->count};
-  io.Bbar = Ct{Bbar->data, 0, (int64_t)(Bbar->level + 1) * N, 2, Bbar->level, Bbar->scale, 1};
-  io.W = Ct{W->data, 0, (int64_t)(W->level + 1) * N, 2, W->level, W->scale, 1};
-  io.V = Ct{V->data, 0, (int64_t)(V->level + 1) * N, 2, V->level, V->scale, 1};
+  // B-bar, W and V: nc ciphertexts back to back at their level
+  io.Bbar = Ct{Bbar->data, 2 * (int64_t)(Bbar->level + 1) * N, (int64_t)(Bbar->level + 1) * N, 2, Bbar->level,
+               Bbar->scale, nc};
+  io.W = Ct{W->data, 2 * (int64_t)(W->level + 1) * N, (int64_t)(W->level + 1) * N, 2, W->level, W->scale, nc};
+  io.V = Ct{V->data, 2 * (int64_t)(V->level + 1) * N, (int64_t)(V->level + 1) * N, 2, V->level, V->scale, nc};
+  io.nc = nc;
   heqg_nag_state st_dry = *st;
   Ct Wn{}, Vn{};
   auto real_run = [&]() {
     X.dry = false;
     X.consts.clear();
     heqg_nag_state st_run = *st;
-    circuit(X, io, sg, &st_run, Z->count, Wn, Vn);
-    // W', V' back into the caller's buffers, compact [2][level+1][N]
-    k_copy_launch(c->g, Vn.v(), CtV{V->data, 0, (int64_t)(Vn.level + 1) * N}, 1, 2, Vn.level + 1, s);
-    k_copy_launch(c->g, Wn.v(), CtV{W->data, 0, (int64_t)(Wn.level + 1) * N}, 1, 2, Wn.level + 1, s);
+    circuit(X, io, sg, &st_run, Z->count / nc, Wn, Vn);
+    // W', V' back into the caller's buffers, compact [nc][2][level+1][N]
+    const int64_t vps = (int64_t)(Vn.level + 1) * N, wps = (int64_t)(Wn.level + 1) * N;
+    k_copy_launch(c->g, Vn.v(), CtV{V->data, 2 * vps, vps}, nc, 2, Vn.level + 1, s);
+    k_copy_launch(c->g, Wn.v(), CtV{W->data, 2 * wps, wps}, nc, 2, Wn.level + 1, s);
   };
   try {
-    circuit(X, io, sg, &st_dry, Z->count, Wn, Vn);   // plan: validates everything, launches nothing
+    circuit(X, io, sg, &st_dry, Z->count / nc, Wn, Vn);   // plan: validates everything, launches nothing
     // an iteration that refreshes mid-way draws fresh randomness per t: it is not replayable
     if (graph && !st_dry.refreshed_gr) {
       const std::string key = graph_key(c, k, Z, Bbar, W, V, sg, st, batch, ws, ws_bytes);

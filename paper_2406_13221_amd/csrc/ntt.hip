@@ -1149,11 +1149,14 @@ __device__ __forceinline__ void ksr_body(const KsrParams& P, int64_t ct, int x, 
 // waves per SIMD instead of three).  32 threads share a sub-row; its transform runs in
 // three register phases of 3 + 3 + 2 stages with element layouts
 //   A {j + 32r},  B {a + 4r} with a = (j & 3) + 32 (j >> 2),  C {8j + r}   (r = 0..7);
-// A also gives coalesced global accesses.  sw8 permutes a sub-row's 256 LDS words so that
-// every layout reads and writes all 32 banks of 8-byte words once per half-wave.
+// A also gives coalesced global accesses.  sw8 permutes a sub-row's 256 LDS words (an XOR of
+// the low five address bits with the high ones: bit 4 into bit 0, bits 5, 6, 7 into bits 2, 3, 4,
+// bit 6 also into bit 1) so that in every layout the 32 lanes of a sub-row hit 32 distinct
+// 8-byte bank slots and each 16-lane quarter-wave 16 distinct slots modulo 16: conflict-free
+// whether a 64-bit access is served 32 or 16 lanes per cycle.  (The earlier form, which only
+// kept half-waves distinct, left layout C with two lanes per slot in each quarter-wave.)
 __device__ __forceinline__ int sw8(int e) {
-  const int b = (e >> 5) & 7;
-  return e ^ (b ^ (b << 2));
+  return e ^ ((e >> 4) & 1) ^ ((e >> 3) & 28) ^ ((e >> 5) & 2);
 }
 
 // stage st (0..7) pairs elements e and e + 2^(7-st) with twiddle (base << st) + (e >> (8-st))

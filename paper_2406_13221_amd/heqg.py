@@ -48,7 +48,7 @@ class NagStateS(ctypes.Structure):
                 ("lr_max", ctypes.c_double), ("lr_min", ctypes.c_double), ("T", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("m_rows", ctypes.c_int), ("g_cols", ctypes.c_int),
                 ("refresh_seed", ctypes.c_uint64), ("eta", ctypes.c_double), ("lr", ctypes.c_double),
-                ("refreshed_gr", ctypes.c_int)]
+                ("refreshed_gr", ctypes.c_int), ("col_blocks", ctypes.c_int)]
 
 
 EXPORTS = None  # filled on load: every heqg_* function name the header declares
@@ -514,10 +514,12 @@ class Context:
 
     def nag_qg_step(self, keys, Z, Bbar, W, V, masks, mask_level, mask_scales, degree, state, batch, ws=None,
                     stream=None, graph=False):
-        """One encrypted QG-NAG iteration; W and V (count-1 Cts) are updated in place.
+        """One encrypted QG-NAG iteration; W and V are updated in place.
 
-        masks: int64 tensor [n_terms + 1, mask_level + 1, N] (NTT form); state: NagStateS (updated).
-        graph: submit the iteration as a replayed HIP graph (heqg_nag_qg_graph); needs a non-null stream."""
+        Z: row block i, column block j at i * C + j with C = state.col_blocks (0 means 1); Bbar, W
+        and V: Cts of C contiguous ciphertexts.  masks: int64 tensor [n_terms + 1, mask_level + 1, N]
+        (NTT form); state: NagStateS (updated).  graph: submit the iteration as a replayed HIP graph
+        (heqg_nag_qg_graph); needs a non-null stream."""
         L = lib()
         if ws is None:
             ws = _ws(self.nag_ws_bytes(batch, degree))
@@ -530,8 +532,8 @@ class Context:
         _check(fn(self.h, keys.handle, ctypes.byref(zb), ctypes.byref(bb), ctypes.byref(wb), ctypes.byref(vb),
                   ctypes.byref(sig), ctypes.byref(state), batch, ws.data_ptr(), ws.numel(), s))
         for ct, cs in ((W, wb), (V, vb)):
-            n = 2 * (cs.level + 1) * self.N
-            ct.data = ct.data.reshape(-1)[:n].view(1, 2, cs.level + 1, self.N)
+            n = ct.count * 2 * (cs.level + 1) * self.N
+            ct.data = ct.data.reshape(-1)[:n].view(ct.count, 2, cs.level + 1, self.N)
             ct.level, ct.scale = cs.level, cs.scale
         return state
 

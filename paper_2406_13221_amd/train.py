@@ -45,6 +45,28 @@ def pack_rows(Z, m, g):
     return out
 
 
+def pack_grid(Z, m, g):
+    """The m x g partition of section 2.2: Z (n x C*g) as row block i, column block j at i*C + j,
+    each sub-matrix flattened row-major into m*g slots (zero rows pad the last row block)."""
+    n, G = Z.shape
+    C = G // g
+    if C == 1:
+        return pack_rows(Z, m, g)
+    nb = -(-n // m)
+    out = np.zeros((nb * C, m * g))
+    for i in range(nb):
+        rows = Z[i * m:(i + 1) * m]
+        for j in range(C):
+            blk = rows[:, j * g:(j + 1) * g]
+            out[i * C + j, :blk.size] = blk.reshape(-1)
+    return out
+
+
+def col_blocks(f, g):
+    """Column blocks of g columns that hold the bias column and f features."""
+    return -(-(f + 1) // g)
+
+
 def bbar_diag(X, g, eps=1e-8):
     """B-bar of rows X (sections 3.1, 4.3), computed by the library (heqg_bbar)."""
     return heqg.bbar(X, g, eps)
@@ -56,10 +78,10 @@ def tile_row(vec, m, g):
     return np.tile(row, m)
 
 
-def new_state(m, g, refresh_seed=0, lr_max=2.0, lr_min=1.0, T=81.0, gamma=2.5):
+def new_state(m, g, refresh_seed=0, lr_max=2.0, lr_min=1.0, T=81.0, gamma=2.5, col_blocks=1):
     a0 = 0.01
     a1 = 0.5 * (1.0 + math.sqrt(1.0 + 4.0 * a0 * a0))
-    return heqg.NagStateS(0, a0, a1, lr_max, lr_min, T, gamma, m, g, refresh_seed, 0.0, 0.0, 0)
+    return heqg.NagStateS(0, a0, a1, lr_max, lr_min, T, gamma, m, g, refresh_seed, 0.0, 0.0, 0, col_blocks)
 
 
 class EncryptedQGNAG:
@@ -79,8 +101,11 @@ class EncryptedQGNAG:
         self.L = L
         Xs, ys = (X, y) if rows is None else (X[rows[0]:rows[1]], y[rows[0]:rows[1]])
         self._X, self._n_rows = Xs, Xs.shape[0]
+        # column blocks of the partition (section 2.2); W, V and each B-bar are one ciphertext per block
+        self.nc = nc = col_blocks(Xs.shape[1], self.g)
+        self.width = nc * self.g
         # step 1-2: Z blocks, B-bar, W = V = 0 (client side)
-        blocks = pack_rows(z_matrix(Xs, ys, self.g), self.m, self.g)
+        blocks = pack_grid(z_matrix(Xs, ys, self.width), self.m, self.g)
         nb = blocks.shape[0]
         self.Z = heqg.Cts(torch.empty((nb, 2, L + 1, ctx.N), dtype=torch.int64, device="cuda"), L, ctx.delta)
         chunk = 64
@@ -100,24 +125,27 @@ class EncryptedQGNAG:
             raise ValueError("batch_rows must be a multiple of m")
         spans = [(0, n)] if not br else [(s, min(s + br, n)) for s in range(0, n, br)]
         self.block_spans = [(s // self.m, -(-e // self.m)) for s, e in spans]
-        self.Bbars = []
-        for i, (s, e) in enumerate(spans):
-            B = bbar_diag(Xs[s:e], self.g)
-            sB = 2.0 ** 50 / B.max()
-            self.Bbars.append(ctx.encrypt(self.keys, ctx.encode(tile_row(B, self.m, self.g), sB)[None], L, sB,
-                                          cfg["enc_seed"], (1 << 40) + 16 + i))
+        self.Bbars = [self._bbar_cts(Xs[s:e], (1 << 40) + 16 + i * nc) for i, (s, e) in enumerate(spans)]
         self.Bbar = self.Bbars[0]
-        zero = np.zeros((1, ctx.N), dtype=np.int64)
+        zero = np.zeros((nc, ctx.N), dtype=np.int64)
         self.W = ctx.encrypt(self.keys, zero, L, ctx.delta, cfg["enc_seed"], (1 << 40) + 1)
-        self.V = ctx.encrypt(self.keys, zero, L, ctx.delta, cfg["enc_seed"], (1 << 40) + 2)
+        self.V = ctx.encrypt(self.keys, zero, L, ctx.delta, cfg["enc_seed"], (1 << 40) + 1 + nc)
         # W and V keep their storage for the whole run (a replayed graph is bound to it)
         self.Wbuf, self.Vbuf = self.W.data, self.V.data
         self.graph = graph
         self.stream = torch.cuda.Stream() if graph else None
         self.set_sigmoid(self.coeffs)
-        self.state = new_state(self.m, self.g, refresh_seed=cfg["enc_seed"] + 7)
+        self.state = new_state(self.m, self.g, refresh_seed=cfg["enc_seed"] + 7, col_blocks=nc)
         self.ws = heqg._ws(ctx.nag_ws_bytes(batch, self.degree))
         self.refresh_obj = 1 << 41
+
+    def _bbar_cts(self, Xr, obj_first):
+        """B-bar of the rows Xr (width C*g), one ciphertext per column block (objects obj_first + j)."""
+        ctx, g = self.ctx, self.g
+        B = bbar_diag(Xr, self.width)
+        sB = 2.0 ** 50 / B.max()
+        pts = np.stack([ctx.encode(tile_row(B[j * g:(j + 1) * g], self.m, g), sB) for j in range(self.nc)])
+        return ctx.encrypt(self.keys, pts, self.L, sB, self.cfg["enc_seed"], obj_first)
 
     def tune(self, candidates=(8, 16, 24), blocks=48, rows=2048):
         """Autotune: NTT pass split and row-pass variants (heqg_tune_ntt), then the number of
@@ -126,11 +154,11 @@ class EncryptedQGNAG:
         import torch
         ctx = self.ctx
         res = {"ntt": ctx.tune_ntt(rows)}
-        nb = min(blocks, self.Z.count)
-        Z = heqg.Cts(self.Z.data[:nb], self.Z.level, self.Z.scale)
+        nb = min(blocks, self.Z.count // self.nc)
+        Z = heqg.Cts(self.Z.data[:nb * self.nc], self.Z.level, self.Z.scale)
         times = {}
         for B in candidates:
-            B = min(B, nb)
+            B = max(min(B, nb), self.nc)
             ws = heqg._ws(ctx.nag_ws_bytes(B, self.degree))
             best = None
             for _ in range(2):
@@ -164,18 +192,14 @@ class EncryptedQGNAG:
         n = self._n_rows
         spans = [(s, min(s + batch_rows, n)) for s in range(0, n, batch_rows)]
         mb.block_spans = [(s // self.m, -(-e // self.m)) for s, e in spans]
-        mb.Bbars = []
-        for i, (s, e) in enumerate(spans):
-            B = bbar_diag(self._X[s:e], self.g)
-            sB = 2.0 ** 50 / B.max()
-            mb.Bbars.append(ctx.encrypt(self.keys, ctx.encode(tile_row(B, self.m, self.g), sB)[None], L, sB,
-                                        self.cfg["enc_seed"], (1 << 40) + (1 << 20) + i))
+        nc = self.nc
+        mb.Bbars = [self._bbar_cts(self._X[s:e], (1 << 40) + (1 << 20) + i * nc) for i, (s, e) in enumerate(spans)]
         mb.Bbar = mb.Bbars[0]
-        zero = np.zeros((1, ctx.N), dtype=np.int64)
-        mb.W = ctx.encrypt(self.keys, zero, L, ctx.delta, self.cfg["enc_seed"], (1 << 40) + 3)
-        mb.V = ctx.encrypt(self.keys, zero, L, ctx.delta, self.cfg["enc_seed"], (1 << 40) + 4)
+        zero = np.zeros((nc, ctx.N), dtype=np.int64)
+        mb.W = ctx.encrypt(self.keys, zero, L, ctx.delta, self.cfg["enc_seed"], (1 << 40) + 3 * nc)
+        mb.V = ctx.encrypt(self.keys, zero, L, ctx.delta, self.cfg["enc_seed"], (1 << 40) + 4 * nc)
         mb.Wbuf, mb.Vbuf = mb.W.data, mb.V.data
-        mb.state = new_state(self.m, self.g, refresh_seed=self.cfg["enc_seed"] + 7)
+        mb.state = new_state(self.m, self.g, refresh_seed=self.cfg["enc_seed"] + 7, col_blocks=nc)
         mb.batch = batch
         mb.ws = heqg._ws(ctx.nag_ws_bytes(batch, self.degree))
         mb.graph = graph
@@ -211,7 +235,7 @@ class EncryptedQGNAG:
         ctx = self.ctx
         k = self.state.t % len(self.block_spans)
         b0, b1 = self.block_spans[k]
-        Z = heqg.Cts(self.Z.data[b0:b1], self.Z.level, self.Z.scale)
+        Z = heqg.Cts(self.Z.data[b0 * self.nc:b1 * self.nc], self.Z.level, self.Z.scale)
         ctx.nag_qg_step(self.keys, Z, self.Bbars[k], self.W, self.V, self.masks, self.mask_level, self.mask_scales,
                         self.degree, self.state, self.batch, self.ws, graph=self.graph)
         if refresh:
@@ -220,13 +244,16 @@ class EncryptedQGNAG:
 
     def refresh(self):
         o, L, d = self.refresh_obj, self.L, self.ctx.delta
+        nc = self.nc
         self.W = self.ctx.refresh(self.keys, self.W, L, self.cfg["enc_seed"] + 9, o, out=heqg.Cts(self.Wbuf, L, d))
-        self.V = self.ctx.refresh(self.keys, self.V, L, self.cfg["enc_seed"] + 9, o + 1, out=heqg.Cts(self.Vbuf, L, d))
-        self.refresh_obj += 2
+        self.V = self.ctx.refresh(self.keys, self.V, L, self.cfg["enc_seed"] + 9, o + nc,
+                                  out=heqg.Cts(self.Vbuf, L, d))
+        self.refresh_obj += 2 * nc
 
     def weights(self, f=None):
-        n = self.g if f is None else f
-        return self.ctx.decrypt_values(self.keys, self.W, n)
+        """Row 0 of W: the model over the padded width (its first f entries when f is given)."""
+        w = np.concatenate([self.ctx.decrypt_values(self.keys, self.W, self.g, index=j) for j in range(self.nc)])
+        return w if f is None else w[:f]
 
 
 def ctypes_byref(x):

@@ -142,3 +142,79 @@ def run_parity(cfgkey, iters, batch, coeffs=trainer.G8, rows=None, bbar_rows=Non
     finally:
         ctx.tune_set(2, saved)
     return o, W
+
+
+# ---------------------------------------------------------------- the m x g partition (section 2.2)
+def grid_oracle_setup(cfgkey, rows=None, **over):
+    """Row blocks x column blocks of Z and one B-bar, W, V ciphertext per column block, encrypted by the
+    oracle (object ids: i * C + j for Z; 2^20 + j, 2^21 + j, 2^22 + j for B-bar, W, V)."""
+    cfg = config(cfgkey, **over)
+    d = dataset(cfgkey, **over)
+    X, y = d["X"], d["y"]
+    if rows:
+        X, y = X[rows[0]:rows[1]], y[rows[0]:rows[1]]
+    o = oracle_with_keys(cfgkey, **over)
+    N, m, g = o.N, cfg["m"], cfg["g"]
+    G, nc = synth.padded_width(cfg), synth.col_blocks(cfg)
+    grid = circuit.pack_grid(trainer.build_Z(X, y, G), m, g, N)
+    L = o.top_level
+    Zg = [[o.encrypt(encode(grid[i, j], N, o.delta), L, o.delta, cfg["enc_seed"], i * nc + j) for j in range(nc)]
+          for i in range(grid.shape[0])]
+    B = trainer.bbar(X, G)
+    sB = 2.0 ** 50 / B.max()
+    Bc = [o.encrypt(encode(circuit.replicate_row(B[j * g:(j + 1) * g], m, g), N, sB), L, sB, cfg["enc_seed"],
+                    (1 << 20) + j) for j in range(nc)]
+    zero = np.zeros(N, np.int64)
+    W = [o.encrypt(zero, L, o.delta, cfg["enc_seed"], (1 << 21) + j) for j in range(nc)]
+    V = [o.encrypt(zero, L, o.delta, cfg["enc_seed"], (1 << 22) + j) for j in range(nc)]
+    masks = circuit.make_masks(o, m, g, trainer.G8, L, o.delta)
+    return cfg, o, X, y, Zg, Bc, W, V, masks
+
+
+def stack_cts(cts):
+    """Oracle ciphertexts of one level and scale -> one GPU Cts batch (upload of oracle output)."""
+    import torch
+    from paper_2406_13221_amd import heqg
+    return heqg.Cts(torch.from_numpy(np.stack([c.data for c in cts]).view(np.int64).copy()).cuda(), cts[0].level,
+                    cts[0].scale)
+
+
+def assert_same_cts(g, cts, what):
+    """A GPU batch against a list of oracle ciphertexts, residue by residue."""
+    got = g.data.cpu().numpy().view(np.uint64)
+    assert g.level == cts[0].level and g.scale == cts[0].scale, (what, g.level, cts[0].level)
+    for j, c in enumerate(cts):
+        if not np.array_equal(got[j], c.data):
+            bad = np.argwhere(got[j] != c.data)
+            raise AssertionError("%s[%d]: %d of %d residues differ, first at %s" % (what, j, len(bad), c.data.size,
+                                                                                  bad[0]))
+
+
+def run_grid_parity(cfgkey, iters, batch, rows=None, **over):
+    """iters iterations over the partition on both sides (W, V refreshed after each), compared residue
+    by residue; returns the oracle and its last W list."""
+    print("grid parity: %s iters=%d batch=%d rows=%s" % (cfgkey, iters, batch, rows), flush=True)
+    cfg, o, X, y, Zg, Bc, W, V, masks = grid_oracle_setup(cfgkey, rows, **over)
+    m, g, L, nc = cfg["m"], cfg["g"], o.top_level, len(W)
+    ctx, keys = gpu_with_keys(cfgkey, **over)
+    import torch
+    gZ = stack_cts([c for row in Zg for c in row])
+    gB, gW, gV = stack_cts(Bc), stack_cts(W), stack_cts(V)
+    order = [1, 3, "half"]
+    mk = torch.from_numpy(np.stack([masks[k][0] for k in order]).view(np.int64).copy()).cuda()
+    scales = [masks[k][1] for k in order]
+    ost = circuit.new_state(refresh_seed=7)
+    gst = gpu_state(ost, m, g)
+    gst.col_blocks = nc
+    for it in range(iters):
+        W, V, ost = circuit.nag_qg_step_grid(o, Zg, Bc, W, V, ost, masks, m, g)
+        ctx.nag_qg_step(keys, gZ, gB, gW, gV, mk, L - 1, scales, 3, gst, batch)
+        assert_same_cts(gW, W, "W%d" % it)
+        assert_same_cts(gV, V, "V%d" % it)
+        assert gst.t == ost["t"] and gst.eta == ost["eta"] and bool(gst.refreshed_gr) == ost["refreshed_gr"]
+        W = [o.refresh(w, L, 99, 4 * it + j) for j, w in enumerate(W)]
+        V = [o.refresh(v, L, 99, 4 * it + 2 + j) for j, v in enumerate(V)]
+        gW = ctx.refresh(keys, gW, L, 99, 4 * it)
+        gV = ctx.refresh(keys, gV, L, 99, 4 * it + 2)
+        assert_same_cts(gW, W, "W%d-refreshed" % it)
+    return o, W, X, y
