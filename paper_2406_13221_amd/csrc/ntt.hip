@@ -1194,11 +1194,73 @@ __device__ __forceinline__ void st8_C(V (&x)[8], TWP tw, int64_t base, int j, BF
   }
 }
 
+// Twiddles of one 256-point sub-row (stage st pairs with psi^brv((base << st) + k), k < 2^st) held
+// in LDS: stage st's 2^st values at [2^st - 1, 2^(st+1) - 1), stages 6 and 7 stored transposed
+// (k -> (k >> s) + 32 (k & (2^s - 1)), s = st - 5), so that in layout C the 32 lanes of a sub-row
+// read 32 consecutive words, in layout B 8 words in distinct banks and in layout A one word.
+// Read through LDS they leave the vector-memory queue to the row and key loads.
+__device__ __forceinline__ int tw8_pos(int st, int k) {
+  return st == 6 ? 63 + (k >> 1) + 32 * (k & 1) : st == 7 ? 127 + (k >> 2) + 32 * (k & 3) : (1 << st) - 1 + k;
+}
+// the 255 twiddles of each of the workgroup's 8 sub-rows (bases N1 + b0 .. N1 + b0 + 7) from the
+// table tw (one prime) into T[8][256]; every thread loads 8 (threads 32 rl .. 32 rl + 31 for sub-row rl)
+__device__ __forceinline__ void tw8_load(double* T, const double* tw, int64_t base0) {
+  const int rl = threadIdx.x >> 5, j = threadIdx.x & 31;
+  const int64_t base = base0 + rl;
+  double v[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int e = j + 32 * i;
+    const int st = 31 - __clz(e + 1), k = e + 1 - (1 << st);
+    v[i] = e < 255 ? tw[(base << st) + k] : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int e = j + 32 * i;
+    const int st = 31 - __clz(e + 1), k = e + 1 - (1 << st);
+    if (e < 255) T[rl * 256 + tw8_pos(st, k)] = v[i];
+  }
+}
+// the three register phases with the twiddles from the sub-row's LDS table T (j = lane in the
+// sub-row, jq = j >> 2; see st8_A, st8_B, st8_C for the pairs)
+template <bool FWD, typename BF>
+__device__ __forceinline__ void st8T_A(double (&x)[8], const double* T, BF bf) {
+#pragma unroll
+  for (int kk = 0; kk < 3; ++kk) {
+    const int st = FWD ? kk : 2 - kk, d = 4 >> st;
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+      if ((r & d) == 0) bf(x[r], x[r + d], T[(1 << st) - 1 + (r >> (3 - st))]);
+  }
+}
+template <bool FWD, typename BF>
+__device__ __forceinline__ void st8T_B(double (&x)[8], const double* T, int jq, BF bf) {
+#pragma unroll
+  for (int kk = 0; kk < 3; ++kk) {
+    const int st = FWD ? 3 + kk : 5 - kk, d = 4 >> (st - 3);
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+      if ((r & d) == 0) bf(x[r], x[r + d], T[(1 << st) - 1 + (jq << (st - 3)) + (r >> (6 - st))]);
+  }
+}
+template <bool FWD, typename BF>
+__device__ __forceinline__ void st8T_C(double (&x)[8], const double* T, int j, BF bf) {
+#pragma unroll
+  for (int kk = 0; kk < 2; ++kk) {
+    const int st = FWD ? 6 + kk : 7 - kk, d = 2 >> (st - 6);
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+      if ((r & d) == 0) bf(x[r], x[r + d], T[(1 << st) - 1 + j + 32 * (r >> (8 - st))]);
+  }
+}
+
 // One workgroup: ciphertext ct, output limb x, 2048 consecutive residues (8 sub-rows b).
 // LDS: a thread's first writes in each exchange are to the words it read last, so one
 // barrier per exchange suffices.
+// twl: the workgroup's LDS twiddle tables (8 sub-rows x 256 doubles; FP64 path only).
 template <bool FP>
-__device__ __forceinline__ void ksr8_body(const KsrParams& P, int64_t ct, int x, int gp, int b, uint64_t* l) {
+__device__ __forceinline__ void ksr8_body(const KsrParams& P, int64_t ct, int x, int gp, int b, uint64_t* l,
+                                          double* twl) {
   const KsRows& K = P.K;
   const int j = threadIdx.x & 31;
   const int a = (j & 3) + 32 * (j >> 2);
@@ -1224,7 +1286,9 @@ __device__ __forceinline__ void ksr8_body(const KsrParams& P, int64_t ct, int x,
   if (FP) {
 #pragma clang fp contract(off)
     const double q = pc.qd, qi = pc.qinv;
-    const double* tw = uniform_ptr(P.twf + ((int64_t)gp << P.logN));
+    const int rl = threadIdx.x >> 5;
+    const double* T = twl + rl * 256;
+    tw8_load(twl, uniform_ptr(P.twf + ((int64_t)gp << P.logN)), base - rl);
     auto bf = [&](double& X, double& Y, double w) { ct_f(X, Y, w, q, qi); };
     double s0[8], s1[8];
 #pragma unroll
@@ -1254,29 +1318,28 @@ __device__ __forceinline__ void ksr8_body(const KsrParams& P, int64_t ct, int x,
       for (int r = 0; r < 8; ++r) v[r] = u64_to_f(u[r]);
       mac(v, jo);
     }
+    __syncthreads();  // the twiddle tables are in LDS
 #pragma unroll 1
     for (int k = 0; k < next; ++k) {
       const uint64_t* src = ext_row(k);
-      const double* twk = tw;
-      int jk = j, ak = a;
-      int64_t bk = base;
-      asm volatile("" : "+s"(twk), "+v"(jk), "+v"(ak), "+v"(bk));
+      int jk = j, ak = a, jqk = j >> 2;
+      asm volatile("" : "+v"(jk), "+v"(ak), "+v"(jqk));
       double v[8];
 #pragma unroll
       for (int r = 0; r < 8; ++r) v[r] = as_f(src[32 * r]);
-      st8_A<true>(v, twk, bk, bf);
+      st8T_A<true>(v, T, bf);
 #pragma unroll
       for (int r = 0; r < 8; ++r) l[sw8(jk + 32 * r)] = as_u(v[r]);
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < 8; ++r) v[r] = as_f(l[sw8(ak + 4 * r)]);
-      st8_B<true>(v, twk, bk, ak, bf);
+      st8T_B<true>(v, T, jqk, bf);
 #pragma unroll
       for (int r = 0; r < 8; ++r) l[sw8(ak + 4 * r)] = as_u(v[r]);
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < 8; ++r) v[r] = as_f(l[sw8(8 * jk + r)]);
-      st8_C<true>(v, twk, bk, jk, bf);
+      st8T_C<true>(v, T, jk, bf);
 #pragma unroll
       for (int r = 0; r < 8; ++r) l[sw8(8 * jk + r)] = as_u(v[r]);
       __syncthreads();
@@ -1291,28 +1354,29 @@ __device__ __forceinline__ void ksr8_body(const KsrParams& P, int64_t ct, int x,
       for (int r = 0; r < 8; ++r) out[((int64_t)nx << P.logN) + 32 * r] = fcanon(s1[r], q, qi);
     } else {
       // special-prime limb: first (row) pass of ModDown's inverse NTT, reduced after every
-      // phase (at most 3 lazy stages)
-      const double* twi = uniform_ptr(P.twif + ((int64_t)gp << P.logN));
+      // phase (at most 3 lazy stages), with the inverse twiddles in place of the forward ones
+      __syncthreads();  // every wave is done with the forward tables
+      tw8_load(twl, uniform_ptr(P.twif + ((int64_t)gp << P.logN)), base - rl);
       auto ibf = [&](double& X, double& Y, double w) { gs_f(X, Y, w, q, qi); };
       auto inv_row = [&](double (&v)[8], uint64_t* dst) {
 #pragma unroll
         for (int r = 0; r < 8; ++r) l[sw8(j + 32 * r)] = as_u(fred(v[r], q, qi));
-        __syncthreads();
+        __syncthreads();  // (the first time: the inverse tables are in LDS too)
 #pragma unroll
         for (int r = 0; r < 8; ++r) v[r] = as_f(l[sw8(8 * j + r)]);
-        st8_C<false>(v, twi, base, j, ibf);
+        st8T_C<false>(v, T, j, ibf);
 #pragma unroll
         for (int r = 0; r < 8; ++r) l[sw8(8 * j + r)] = as_u(fred(v[r], q, qi));
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < 8; ++r) v[r] = as_f(l[sw8(a + 4 * r)]);
-        st8_B<false>(v, twi, base, a, ibf);
+        st8T_B<false>(v, T, j >> 2, ibf);
 #pragma unroll
         for (int r = 0; r < 8; ++r) l[sw8(a + 4 * r)] = as_u(fred(v[r], q, qi));
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < 8; ++r) v[r] = as_f(l[sw8(j + 32 * r)]);
-        st8_A<false>(v, twi, base, ibf);
+        st8T_A<false>(v, T, ibf);
 #pragma unroll
         for (int r = 0; r < 8; ++r) dst[32 * r] = as_u(fred(v[r], q, qi));
       };
@@ -1412,6 +1476,7 @@ __device__ __forceinline__ void ksr8_body(const KsrParams& P, int64_t ct, int x,
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_ntt_rows_ks8(KsrParams P) {
   __shared__ uint64_t lds[2048];
+  __shared__ double twl[2048];
   const KsRows& K = P.K;
   int64_t unit, ct;
   xcd_map(blockIdx.x, K.count, (int64_t)(K.nl + K.np) * P.tiles, unit, ct);
@@ -1420,9 +1485,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   const int gp = x < K.nl ? x : K.nq + (x - K.nl);
   const int rl = threadIdx.x >> 5;
   if (P.pc[gp].k <= FP_MAX_BITS)
-    ksr8_body<true>(P, ct, x, gp, tile * 8 + rl, lds + rl * 256);
+    ksr8_body<true>(P, ct, x, gp, tile * 8 + rl, lds + rl * 256, twl);
   else
-    ksr8_body<false>(P, ct, x, gp, tile * 8 + rl, lds + rl * 256);
+    ksr8_body<false>(P, ct, x, gp, tile * 8 + rl, lds + rl * 256, twl);
 }
 
 // Each workgroup takes the arithmetic path of its output limb's prime.  At three waves per
