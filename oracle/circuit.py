@@ -142,11 +142,11 @@ def sigmoid_block(ora, u, masks, degree):
     return ora.add_pt(p, *masks["half"])
 
 
-def nag_qg_step(ora, Z_cts, B_ct, W, V, state, masks, m, g, degree=3, lr_fn=f2_lr, trace=None):
+def nag_qg_step(ora, Z_cts, B_ct, W, V, state, masks, m, g, degree=3, lr_fn=f2_lr, trace=None, fo_gamma=None):
     """One iteration with one column block (g >= f + 1); returns (W', V', new_state).
     trace (list) collects intermediates."""
     Wn, Vn, st = nag_qg_step_grid(ora, [[z] for z in Z_cts], [B_ct], [W], [V], state, masks, m, g, degree,
-                                  lr_fn, trace)
+                                  lr_fn, trace, fo_gamma)
     return Wn[0], Vn[0], st
 
 
@@ -155,16 +155,23 @@ def nag_qg_step(ora, Z_cts, B_ct, W, V, state, masks, m, g, degree=3, lr_fn=f2_l
 MAX_REFRESH_COL_BLOCKS = 14
 
 
-def nag_qg_step_grid(ora, Z_grid, B_cts, Ws, Vs, state, masks, m, g, degree=3, lr_fn=f2_lr, trace=None):
+def nag_qg_step_grid(ora, Z_grid, B_cts, Ws, Vs, state, masks, m, g, degree=3, lr_fn=f2_lr, trace=None,
+                     fo_gamma=None):
     """One iteration over the m x g sub-matrix partition of section 2.2: Z_grid[i][j] is row
     block i, column block j (columns j*g .. j*g + g - 1 of Z); B_cts, Ws and Vs hold one
     ciphertext per column block.  The margins of row block i are the row sums of
     sum_j Z_ij (x) W_j (the tensor products added in three-part form, relinearised once);
     the sigmoid, replicated across the row, then multiplies every Z_ij, and column block j
     accumulates its own gradient sum_i Z_ij (x) p_i, whose column sums, B-bar product and NAG
-    update stay within that block.  Returns (W'_j list, V'_j list, new_state)."""
+    update stay within that block.  Returns (W'_j list, V'_j list, new_state).
+
+    fo_gamma: the first-order NAG the paper compares against (section 3.2, Fig. 1): the gradient
+    ciphertexts are multiplied by the constants fo_gamma and fo_gamma (1 - eta) instead of the
+    B-bar products (B_cts unused), with lr = 1; the rest of the update is unchanged."""
     lg, lm = int(math.log2(g)), int(math.log2(m))
     nc = len(Ws)
+    if fo_gamma is not None:
+        B_cts = [None] * nc
     if not (len(Vs) == len(B_cts) == nc and all(len(row) == nc for row in Z_grid)):
         raise ValueError("every row block needs one ciphertext per column block")
     acc = [None] * nc
@@ -196,23 +203,27 @@ def nag_qg_step_grid(ora, Z_grid, B_cts, Ws, Vs, state, masks, m, g, degree=3, l
     st = dict(state)
     t = st["t"]
     B0 = B_cts[0]
-    if min(B0.level - 1, grs[0].level) < 1:
+    if min(grs[0].level if fo_gamma is not None else B0.level - 1, grs[0].level) < 1:
         if nc > MAX_REFRESH_COL_BLOCKS:
             raise ValueError("too many column blocks for a mid-iteration refresh")
         grs = [ora.refresh(gr, ora.top_level, st["refresh_seed"], ((t << 4) | 2) + j) for j, gr in enumerate(grs)]
         st["refreshed_gr"] = True
     eta = (1.0 - st["alpha0"]) / st["alpha1"]
-    lr = lr_fn(t)
+    lr = lr_fn(t) if fo_gamma is None else 1.0
     s_g = ora.delta
     Wn, Vn = [], []
     for j in range(nc):
         gr = grs[j]
-        lt = min(B_cts[j].level - 1, gr.level)
-        s_bv = s_g * float(ora.q(lt)) / gr.scale
-        Bv = ora.mul_const(B_cts[j], lr, s_bv)
-        Bw = ora.mul_const(B_cts[j], lr * (1.0 - eta), s_bv)
-        Gv = ora.rescale(ora.hmult(Bv, gr))
-        Gw = ora.rescale(ora.hmult(Bw, gr))
+        if fo_gamma is None:
+            lt = min(B_cts[j].level - 1, gr.level)
+            s_bv = s_g * float(ora.q(lt)) / gr.scale
+            Bv = ora.mul_const(B_cts[j], lr, s_bv)
+            Bw = ora.mul_const(B_cts[j], lr * (1.0 - eta), s_bv)
+            Gv = ora.rescale(ora.hmult(Bv, gr))
+            Gw = ora.rescale(ora.hmult(Bw, gr))
+        else:
+            Gv = ora.mul_const(gr, fo_gamma, s_g)
+            Gw = ora.mul_const(gr, fo_gamma * (1.0 - eta), s_g)
         Vn.append(ora.add(ora.mul_const(Ws[j], 1.0, s_g), Gv))
         Wn.append(ora.add(ora.add(ora.mul_const(Ws[j], 1.0 - eta, s_g), ora.mul_const(Vs[j], eta, s_g)), Gw))
     st["t"] = t + 1

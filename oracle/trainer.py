@@ -96,11 +96,17 @@ def batches(n, batch_rows):
     return [(s, min(s + batch_rows, n)) for s in range(0, n, batch_rows)]
 
 
-def train(X, y, g, iters, coeffs=G8, batch_rows=None, exact_sigmoid=False, eps=EPS, lr_fn=f2_lr, log_margins=False):
-    """Run QG-NAG; returns dict(W, V, history, margins)."""
+def train(X, y, g, iters, coeffs=G8, batch_rows=None, exact_sigmoid=False, eps=EPS, lr_fn=f2_lr, log_margins=False,
+          first_order=None):
+    """Run QG-NAG; returns dict(W, V, history, margins).
+
+    first_order: None for the quadratic gradient G = B-bar g with multiplier lr_fn(t); a number lr0 for
+    the first-order NAG the paper compares against (section 3.2, Fig. 1; Tables 1 and 2: learning rate
+    0.01/n on the Financial data, 1.0/n on MNIST): G = (lr0 / n_k) g with n_k the rows of the batch and
+    no B-bar, the rest of the update unchanged."""
     Z = build_Z(X, y, g)
     bl = batches(X.shape[0], batch_rows)
-    Bs = [bbar(X[s:e], g, eps) for (s, e) in bl]
+    Bs = [bbar(X[s:e], g, eps) if first_order is None else np.full(g, first_order / (e - s)) for (s, e) in bl]
     W = np.zeros(g)
     V = np.zeros(g)
     a0 = 0.01
@@ -116,7 +122,7 @@ def train(X, y, g, iters, coeffs=G8, batch_rows=None, exact_sigmoid=False, eps=E
         gr = Zk.T @ p
         G = B * gr
         eta = (1.0 - a0) / a1
-        lr = lr_fn(t)
+        lr = lr_fn(t) if first_order is None else 1.0
         Vt = W + lr * G
         W = (1.0 - eta) * Vt + eta * V
         V = Vt

@@ -1,9 +1,11 @@
 """Seeded synthetic logistic-regression data.
 
-Features are i.i.d. uniform on [-1, 1].  Labels are Bernoulli(sigmoid(x.w* + b))
-with w* ~ N(0, I) rescaled so that std(x.w*) = 1.5 (unscaled N(0, I) weights put
-margins far outside the interval a degree-3 sigmoid approximation is fitted
-on), and b = 0 or found by bisection to give a target positive rate.
+Features are i.i.d. uniform on [-1, 1] (or the workload's x_range, each entry kept
+with probability x_density when the workload sets one, else 0).  Labels are
+Bernoulli(sigmoid(x.w* + b)) with w* ~ N(0, I) rescaled so that std(x.w*) = 1.5
+(or the workload's signal; unscaled N(0, I) weights put margins far outside the
+interval a degree-3 sigmoid approximation is fitted on), and b = 0 or found by
+bisection to give a target positive rate.
 """
 import numpy as np
 
@@ -17,8 +19,15 @@ def make_dataset(cfg, rng_seed=None):
     seed = cfg["seed"] if rng_seed is None else rng_seed
     rng = np.random.default_rng(seed)
     n, f, nv = cfg["n_train"], cfg["n_features"], cfg["n_valid"]
-    X = rng.uniform(-1.0, 1.0, size=(n, f))
-    Xv = rng.uniform(-1.0, 1.0, size=(nv, f))
+    lo, hi = cfg.get("x_range", (-1.0, 1.0))
+    X = rng.uniform(lo, hi, size=(n, f))
+    Xv = rng.uniform(lo, hi, size=(nv, f))
+    dens = cfg.get("x_density")
+    if dens is not None:
+        # sparse features (most pixels of a digit image are background): each entry is kept
+        # with probability dens, else 0
+        X *= rng.uniform(size=(n, f)) < dens
+        Xv *= rng.uniform(size=(nv, f)) < dens
     if cfg.get("standardise"):
         mu, sd = X.mean(axis=0), X.std(axis=0)
         X = (X - mu) / sd
@@ -27,7 +36,7 @@ def make_dataset(cfg, rng_seed=None):
         X = X / mx
         Xv = np.clip(Xv / mx, -1.0, 1.0)
     w = rng.standard_normal(f)
-    w *= 1.5 / np.std(X @ w)
+    w *= cfg.get("signal", 1.5) / np.std(X @ w)
     m = X @ w
     b = 0.0
     if cfg.get("target_pos"):

@@ -189,3 +189,29 @@ def test_grid_intermediates_are_the_plaintext_quantities():
     gr = o.decrypt_values(tr["gr"]).real.reshape(m, g)
     assert np.abs(gr - (Zp[:, :g].T @ p_ref)[None, :]).max() < 1e-5
 
+
+
+@pytest.mark.parametrize("cfgkey", ["c1", "c1g"])
+def test_first_order_nag_matches_fp64(cfgkey):
+    """The first-order NAG baseline (no B-bar; the gradient times lr0 / n) follows the FP64 trainer's
+    first-order run, on one column block and on the grid."""
+    lr0 = 1.0
+    if cfgkey == "c1":
+        cfg, o, X, y, Zc, Bc, W, V, masks = setup_run("c1")
+        Zg, W, V = [[z] for z in Zc], [W], [V]
+    else:
+        cfg, o, X, y, Zg, Bc, W, V, masks = setup_grid("c1g")
+    m, g, L, nc = cfg["m"], cfg["g"], o.top_level, len(W)
+    G = nc * g
+    gamma = lr0 / X.shape[0]
+    ref = trainer.train(X, y, G, 2, first_order=lr0)
+    st = circuit.new_state(refresh_seed=7)
+    for it in range(2):
+        W, V, st = circuit.nag_qg_step_grid(o, Zg, None, W, V, st, masks, m, g, fo_gamma=gamma)
+        W = [o.refresh(w, L, 99, 4 * it + j) for j, w in enumerate(W)]
+        V = [o.refresh(v, L, 99, 4 * it + 2 + j) for j, v in enumerate(V)]
+        w = np.concatenate([o.decrypt_values(c, g).real for c in W])
+        assert np.abs(w - ref["history"][it]["W"]).max() < TOL_W
+    # the first-order run moves differently from the quadratic-gradient one
+    assert np.abs(ref["W"] - trainer.train(X, y, G, 2)["W"]).max() > 10 * TOL_W
+

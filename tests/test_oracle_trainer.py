@@ -122,6 +122,25 @@ def test_qgnag_with_exact_sigmoid_reaches_mle():
     assert np.abs(res["W"][:7] - mle).max() < 1e-4
 
 
+def test_first_order_nag_reaches_mle_slower_than_qgnag():
+    """The first-order baseline (G = (lr0/n) g, section 3.2 / Fig. 1) also converges to the MLE,
+    and needs more iterations than the quadratic gradient for the same accuracy."""
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(4)
+    X = rng.uniform(-1, 1, (2000, 6))
+    w_true = rng.normal(size=6)
+    y = (rng.uniform(size=2000) < trainer.sigmoid(X @ w_true)).astype(int)
+    g = 8
+    f = lambda w: -trainer.loglik(X, y, np.concatenate([w, np.zeros(g - 7)]))
+    mle = minimize(f, np.zeros(7), method="BFGS", options=dict(gtol=1e-10)).x
+    fo = trainer.train(X, y, g, 400, exact_sigmoid=True, first_order=4.0)
+    assert np.abs(fo["W"][:7] - mle).max() < 1e-4
+    err = lambda r: np.abs(r["W"][:7] - mle).max()
+    qg20 = trainer.train(X, y, g, 20, exact_sigmoid=True, lr_fn=lambda t: 1.0)
+    fo20 = trainer.train(X, y, g, 20, exact_sigmoid=True, first_order=4.0)
+    assert err(qg20) < err(fo20)
+
+
 def test_minibatch_schedule_cycles_batches():
     rng = np.random.default_rng(5)
     X = rng.uniform(-1, 1, (250, 3))
