@@ -137,6 +137,50 @@ def pmc_traffic(avg_rows):
         return None
 
 
+def loglik_auroc(Xv, yv, w):
+    """Mean log-likelihood (section 2.3) and AUROC (rank statistic, ties at mid-rank) of the decrypted
+    model w (bias first) on validation rows."""
+    import numpy as np
+    score = w[0] + Xv @ w[1:Xv.shape[1] + 1]
+    ypm = 2.0 * yv - 1.0
+    ll = -float(np.mean(np.logaddexp(0.0, -ypm * score)))
+    from scipy.stats import rankdata
+    ranks = rankdata(score)
+    npos = int(yv.sum())
+    nneg = len(yv) - npos
+    auc = (ranks[yv == 1].sum() - npos * (npos + 1) / 2.0) / (npos * nneg)
+    return ll, float(auc)
+
+
+def mnist_leg(steps, batch):
+    import torch
+    import synth
+    from paper_2406_13221_amd.train import EncryptedQGNAG
+    cfg = synth.get_config("c6")
+    d = synth.make_dataset(cfg)
+    g16 = {1: 0.0843, 3: -0.0002}   # least-squares cubic on [-16, 16] (section 4.1)
+    res = {"workload": cfg["name"], "n_samples": cfg["n_train"], "n_features": cfg["n_features"],
+           "n_valid": cfg["n_valid"], "rows_per_block": cfg["m"], "cols": cfg["g"], "sigmoid": "g16",
+           "iterations": steps}
+    for name, fo in (("quadratic_gradient", False), ("first_order_nag", True)):
+        run = EncryptedQGNAG(cfg, d["X"], d["y"], coeffs=g16, batch=min(batch, 12), first_order=fo)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            run.step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        w = run.weights(cfg["n_features"] + 1)
+        ll_tr, _ = loglik_auroc(d["X"], d["y"], w)
+        ll_v, auc = loglik_auroc(d["Xv"], d["yv"], w)
+        res[name] = {"s_per_iter": round(dt, 4), "train_loglik": round(ll_tr, 5), "valid_loglik": round(ll_v, 5),
+                     "valid_auroc": round(auc, 5)}
+        log("mnist-shaped %s: %.3f s/iter, train loglik %.4f, valid AUROC %.4f" % (name, dt, ll_tr, auc))
+        del run
+        torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,8 +193,12 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (NTT split/variants, chunk size)")
     ap.add_argument("--graph-steps", type=int, default=1, help="timed graph-replayed full-batch iterations")
     ap.add_argument("--mini-steps", type=int, default=10, help="timed mini-batch steps (eager and graph)")
-    ap.add_argument("--learned-steps", type=int, default=1,
-                    help="timed iterations of the learned-sigmoid form (degree-5 polynomial, depth 3)")
+    ap.add_argument("--learned-steps", type=int, default=3,
+                    help="iterations of g8 and of the learned degree-5 and degree-7 forms, each from W = V = 0")
+    ap.add_argument("--grid-steps", type=int, default=1,
+                    help="timed iterations of the same task over 1,024 x 32 blocks (7 column blocks, section 2.2)")
+    ap.add_argument("--mnist-steps", type=int, default=3,
+                    help="iterations of the MNIST-shaped task (section 5.2), quadratic gradient and first-order NAG")
     ap.add_argument("--mode", default="train", choices=["train", "ntt"],
                     help="ntt: only the batched forward NTT (768 limbs) and a 1 GiB device copy, for counters")
     ap.add_argument("--copy-probe", action="store_true",
@@ -217,6 +265,8 @@ def main():
     upd = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps / 1000.0
     ref = sum(e[1].elapsed_time(e[2]) for e in ev) / args.steps / 1000.0
     log("timed %d steps: %.3f s/step (update %.3f s, refresh %.4f s)" % (args.steps, ms_per_step / 1e3, upd, ref))
+    # the model after these iterations (g8 only so far), for the comparison with the 1,024 x 32 layout
+    w_cmp, t_cmp = run.weights(cfg["n_features"] + 1), int(run.state.t)
 
     # the same iteration submitted as a replayed HIP graph (first call captures, untimed)
     graph_s = None
@@ -233,28 +283,47 @@ def main():
         run.ctx.graph_clear()
         log("graph-replayed iteration: %.3f s" % graph_s)
 
-    # the learned-sigmoid form: an odd degree-5 polynomial (here the least-squares fit of sigma on a
-    # uniform grid over [-8, 8]; the time does not depend on the coefficients) costs one more level
+    # the learned-sigmoid form (odd degree 5 and 7 polynomials in m/8, fitted by FP32 Adam on the GPU
+    # to sigma on the margins of the data owner's FP64 plaintext run with the exact sigmoid, 10
+    # iterations x 422,108 rows) beside g8: each trained from W = V = 0 for the same iterations;
+    # decrypted validation log-likelihood and AUROC, levels consumed per iteration, time per iteration
     learned = None
     if args.learned_steps > 0:
         import numpy as np
-        grid = np.linspace(-8.0, 8.0, 4001)
-        basis = np.stack([grid ** k for k in (1, 3, 5)], axis=1)
-        c5 = np.linalg.lstsq(basis, 1.0 / (1.0 + np.exp(-grid)) - 0.5, rcond=None)[0]
-        g8 = dict(run.coeffs)
-        run.set_sigmoid({1: float(c5[0]), 3: float(c5[1]), 5: float(c5[2])})
-        run.step()
-        torch.cuda.synchronize()
+        from paper_2406_13221_amd import sigmoid_fit
         t0 = time.perf_counter()
-        for _ in range(args.learned_steps):
-            run.step(refresh=False)
-            depth = run.L - run.W.level
-            run.refresh()
-        torch.cuda.synchronize()
-        learned = {"degree": 5, "s_per_iter": round((time.perf_counter() - t0) / args.learned_steps, 4),
-                   "levels_per_iteration": depth, "levels_per_iteration_g8": depth_g8}
+        _, margins = heqg.plain_qgnag(data["X"], data["y"], 10)
+        t_traj = time.perf_counter() - t0
+        forms = {"g8": dict(run.coeffs)}
+        fit_info = {}
+        for deg in (5, 7):
+            t0 = time.perf_counter()
+            c, trace = sigmoid_fit.fit(margins, deg, steps=2000)
+            torch.cuda.synchronize()
+            forms["degree%d" % deg] = sigmoid_fit.power_coeffs(c)
+            fit_info["degree%d" % deg] = {"coeffs_of_m_over_8": [float(v) for v in c], "fit_s":
+                                          round(time.perf_counter() - t0, 3), "final_mse": float(trace[-1])}
+        g8 = dict(run.coeffs)
+        learned = {"margins": int(margins.size), "trajectory_s": round(t_traj, 2), "fits": fit_info,
+                   "iterations": args.learned_steps}
+        for name, co in forms.items():
+            run.set_sigmoid(co)
+            run.reset()
+            times, depth = [], None
+            for _ in range(args.learned_steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                run.step(refresh=False)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+                depth = run.L - run.W.level
+                run.refresh()
+            wl = run.weights(cfg["n_features"] + 1)
+            ll, auc = loglik_auroc(data["Xv"], data["yv"], wl)
+            learned[name] = {"s_per_iter": round(float(np.mean(times)), 4), "levels_per_iteration": depth,
+                             "valid_loglik": round(ll, 6), "valid_auroc": round(auc, 6)}
+            log("%s: %.3f s/iter, %d levels, valid loglik %.5f, AUROC %.5f" % (name, np.mean(times), depth, ll, auc))
         run.set_sigmoid(g8)
-        log("learned degree-5 iteration: %.3f s, %d levels (g8: %d)" % (learned["s_per_iter"], depth, depth_g8))
 
     # mini-batch steps (Algorithm 1, 1,024 rows = 8 blocks per batch), eager and graph-replayed
     mini = None
@@ -287,28 +356,40 @@ def main():
         log("mini-batch step: eager %.2f ms, graph %.2f ms" % (eager_ms, graph_ms))
         del mb
 
-    # NTT throughput: forward + inverse over a batch of 768 limbs, as read once + written once per transform
+    # NTT throughput over the full batch of the iteration: every limb of every part of the 3,298 Z
+    # ciphertexts (3,298 x 2 x 24 rows, 40- and 60-bit primes, 83 GB: far past the caches), transformed
+    # in place forward and then back, which restores Z exactly; bytes = read once + written once per limb
     N = run.ctx.N
-    rows = torch.randint(0, 2 ** 39, (16 * 2, run.ctx.n_q, N), dtype=torch.int64, device="cuda")
-    nrows = rows.shape[0] * rows.shape[1]
-    for _ in range(2):
-        run.ctx.ntt(rows, 0, run.ctx.n_q)
-        run.ctx.ntt(rows, 0, run.ctx.n_q, inverse=True)
+    zrows = run.Z.data.view(-1, N)
+    nrows = zrows.shape[0]
+    for _ in range(1):
+        run.ctx.ntt(zrows, 0, run.ctx.n_q)
+        run.ctx.ntt(zrows, 0, run.ctx.n_q, inverse=True)
     e0, e1, e2 = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    reps = 5
+    reps = 2
     e0.record()
     for _ in range(reps):
-        run.ctx.ntt(rows, 0, run.ctx.n_q)
+        run.ctx.ntt(zrows, 0, run.ctx.n_q)
+        run.ctx.ntt(zrows, 0, run.ctx.n_q, inverse=True)
     e1.record()
+    torch.cuda.synchronize()
+    e1b, e2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e1b.record()
     for _ in range(reps):
-        run.ctx.ntt(rows, 0, run.ctx.n_q, inverse=True)
+        run.ctx.ntt(zrows, 0, run.ctx.n_q)
     e2.record()
     torch.cuda.synchronize()
+    for _ in range(reps):
+        run.ctx.ntt(zrows, 0, run.ctx.n_q, inverse=True)
+    torch.cuda.synchronize()
     ntt_bytes = 16.0 * N * nrows
-    fwd_gbs = ntt_bytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    inv_gbs = ntt_bytes * reps / (e1.elapsed_time(e2) * 1e-3) / 1e9
+    fwd_s = e1b.elapsed_time(e2) * 1e-3 / reps
+    both_s = e0.elapsed_time(e1) * 1e-3 / reps
+    fwd_gbs = ntt_bytes / fwd_s / 1e9
+    inv_gbs = ntt_bytes / max(both_s - fwd_s, 1e-9) / 1e9
 
     w = run.weights(cfg["n_features"] + 1)
+    n_blocks = run.Z.count
     if not (abs(w).max() < 1e3):
         print("decrypted weights out of range", file=sys.stderr)
         sys.exit(1)
@@ -376,7 +457,8 @@ def main():
         "update_s": round(upd, 4),
         "refresh_s": round(ref, 5),
         "ntt_gbps": {"forward": round(fwd_gbs, 1), "inverse": round(inv_gbs, 1), "limbs_per_call": nrows,
-                     "frac_of_hbm_peak": round(fwd_gbs / HBM_PEAK_GBS, 4)},
+                     "bytes_per_call": ntt_bytes, "frac_of_hbm_peak": round(fwd_gbs / HBM_PEAK_GBS, 4),
+                     "batch": "every limb of the iteration's ciphertexts (blocks x 2 parts x limbs), in place"},
         "roofline": roofline,
         "conv_pass_roofline": conv_roofline,
         "ntt_row_pass_roofline": ntt_row_roofline,
@@ -386,6 +468,42 @@ def main():
         "learned_sigmoid": learned,
         "tuning": tuning,
     }
+    # the same task over the 1,024 x 32 partition of section 2.2 (7 column blocks; 10x fewer key
+    # switches per iteration), trained for as many iterations as the run above from the same start:
+    # its decrypted model against the 128 x 256 run's
+    grid = None
+    if args.grid_steps > 0:
+        import numpy as np
+        del run
+        torch.cuda.empty_cache()
+        gcfg = synth.get_config("c3g")
+        gr = EncryptedQGNAG(gcfg, data["X"], data["y"], batch=args.batch)
+        for _ in range(max(t_cmp - args.grid_steps, 0)):
+            gr.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.grid_steps):
+            gr.step()
+        torch.cuda.synchronize()
+        gs = (time.perf_counter() - t0) / args.grid_steps
+        wg = gr.weights(cfg["n_features"] + 1)
+        grid = {"workload": gcfg["name"], "rows_per_block": gcfg["m"], "cols": gcfg["g"], "col_blocks": gr.nc,
+                "ciphertexts": gr.Z.count, "s_per_iter": round(gs, 4), "iterations": int(gr.state.t),
+                "max_abs_dw_vs_128x256": float(np.abs(wg - w_cmp).max()) if gr.state.t == t_cmp else None}
+        log("grid 1024x32 iteration: %.3f s, max|dw| vs 128x256 after %d iterations: %.2e" %
+            (gs, gr.state.t, grid["max_abs_dw_vs_128x256"]))
+        del gr
+        torch.cuda.empty_cache()
+    out["grid_1024x32"] = grid
+
+    # the paper's second workload (section 5.2, Table 2): MNIST-shaped, g16, 12 x 7 blocks; the quadratic
+    # gradient beside the first-order NAG baseline (section 3.2, Fig. 1), decrypted log-likelihood and
+    # validation AUROC after the same number of iterations
+    mnist = None
+    if args.mnist_steps > 0:
+        mnist = mnist_leg(args.mnist_steps, args.batch)
+    out["mnist_shaped"] = mnist
+
     if args.copy_probe:
         src = torch.ones(1 << 27, dtype=torch.int64, device="cuda")
         dst = torch.empty_like(src)
@@ -394,7 +512,7 @@ def main():
         del src, dst
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(cfg, data, run.Z.count)
+        out["cpu_baseline"] = cpu_baseline(cfg, data, n_blocks)
     print(json.dumps(out), flush=True)
 
 

@@ -433,6 +433,24 @@ int heqg_sigfit_train(const float* dev_m, int64_t n, int n_terms, float* dev_c, 
 int heqg_bbar(const double* X, int64_t n, int f, int g, double eps, double* out, int threads);
 
 /*
+ * The data owner's plaintext run of the method in FP64 (Algorithm 1; the
+ * full-batch form of section 3.3 when batch_rows = 0), whose margins the
+ * learned sigmoid is fitted on.  X row-major n x f, y in {0, 1}; Z = y+- [1|X];
+ * B-bar of each batch of batch_rows rows (heqg_bbar with this eps); per
+ * iteration t over batch t mod n_batches: m = Z_k W, p = 1 - s(m),
+ * g = Z_k^T p, V_tmp = W + F2(t) B-bar g, W = (1-eta) V_tmp + eta V,
+ * V = V_tmp, F2(t) = lr_max - (lr_max - lr_min)(t/T)^gamma (section 3.2).
+ * s: the exact sigmoid (degree 0) or 1/2 + sum c_k m^k over odd k <= degree
+ * (coeffs: c_1, c_3, ...).  margins (may be NULL): every iteration's margins
+ * m, iteration after iteration (FP32, sum over t of the batch rows);
+ * w_out: the f + 1 weights W after `iters` iterations.  Host threads as for
+ * heqg_bbar; the result does not depend on their number.
+ */
+int heqg_plain_qgnag(const double* X, const int* y, int64_t n, int f, int iters, int64_t batch_rows,
+                     const double* coeffs, int degree, double lr_max, double lr_min, double T, double gamma,
+                     double eps, float* margins, double* w_out, int threads);
+
+/*
  * Scale plan of the masked sigmoid: level is the level of the tensor
  * Z (x) W (the blocks' level), s_z and s_w their scales, s_c the scale every
  * term must reach.  Writes (degree+1)/2 + 1 scales: one per odd power k
@@ -479,6 +497,10 @@ typedef struct {
  * col_blocks: the number of column blocks of the m_rows x g_cols partition
  * of section 2.2 (0 is taken as 1): the padded width [1 | X | 0] is
  * col_blocks * g_cols columns.
+ * first_order: 0 for the quadratic gradient G = B-bar g; 1 for the
+ * first-order NAG the paper compares against (section 3.2, Fig. 1), whose
+ * step multiplies the gradient by the constant fo_gamma (e.g. lr0 / n) in
+ * place of lr * B-bar, with lr = 1; Bbar may then be null.
  */
 typedef struct {
   int t;
@@ -489,6 +511,8 @@ typedef struct {
   double eta, lr;
   int refreshed_gr;
   int col_blocks;
+  int first_order;
+  double fo_gamma;
 } heqg_nag_state;
 
 /* Device workspace bytes for heqg_nag_qg_step with `batch` row blocks in flight. */

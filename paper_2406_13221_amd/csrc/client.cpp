@@ -110,3 +110,81 @@ extern "C" int heqg_sigmoid_masks(const heqg_ctx* c, const double* coeffs, int d
   }
   return HEQG_OK;
 }
+
+// The data owner's plaintext run of the method in FP64 (Algorithm 1; the full-batch form of
+// section 3.3 when batch_rows = 0): Z = y+- [1 | X] (labels {0,1} -> -1/+1), B-bar of each batch
+// from heqg_bbar, and for t = 0 .. iters-1 over batch k = t mod n_batches:
+//   m = Z_k W,  p = 1 - s(m),  g = Z_k^T p,  G = B-bar_k g,  eta = (1 - a0)/a1,  lr = F2(t),
+//   V_tmp = W + lr G,  W = (1 - eta) V_tmp + eta V,  V = V_tmp,  a0 = a1,  a1 = (1 + sqrt(1 + 4 a0^2))/2,
+// with s the exact sigmoid (degree 0) or 1/2 + sum_k c_k m^k over the odd k <= degree.  Row slices
+// are summed in a fixed order, so the result does not depend on the thread count.
+extern "C" int heqg_plain_qgnag(const double* X, const int* y, int64_t n, int f, int iters, int64_t batch_rows,
+                                const double* coeffs, int degree, double lr_max, double lr_min, double T,
+                                double gamma, double eps, float* margins, double* w_out, int threads) {
+  if (!X || !y || !w_out || n < 1 || f < 0 || iters < 0 || batch_rows < 0 ||
+      (degree != 0 && degree != 3 && degree != 5 && degree != 7) || (degree && !coeffs) || !(T > 0.0)) {
+    set_err("plain_qgnag: bad argument (degree 0 = exact sigmoid, or 3, 5, 7 with coefficients)");
+    return HEQG_ERR_ARG;
+  }
+  const int d = f + 1;
+  const int64_t br = batch_rows ? batch_rows : n;
+  const int64_t n_batches = (n + br - 1) / br;
+  std::vector<double> B((size_t)n_batches * d);
+  for (int64_t k = 0; k < n_batches; ++k) {
+    const int64_t r0 = k * br, r1 = std::min(n, r0 + br);
+    int rc = heqg_bbar(X + r0 * f, r1 - r0, f, d, eps, B.data() + (size_t)k * d, threads);
+    if (rc) return rc;
+  }
+  std::vector<double> W(d, 0.0), V(d, 0.0), grad(d);
+  double a0 = 0.01, a1 = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * a0 * a0));
+  constexpr int64_t kSlice = 4096;
+  int nt = threads > 0 ? threads : (int)std::max(1u, std::thread::hardware_concurrency());
+  auto sig = [&](double m) {
+    if (degree == 0) return 0.5 * (1.0 + std::tanh(0.5 * m));
+    double s = 0.5, mk = m, m2 = m * m;
+    for (int i = 0; i < (degree + 1) / 2; ++i, mk *= m2) s += coeffs[i] * mk;
+    return s;
+  };
+  float* mout = margins;
+  for (int t = 0; t < iters; ++t) {
+    const int64_t k = t % n_batches, r0 = k * br, r1 = std::min(n, r0 + br), rows = r1 - r0;
+    const int64_t n_slices = (rows + kSlice - 1) / kSlice;
+    std::vector<double> part((size_t)n_slices * d, 0.0);
+    auto work = [&](int64_t s0, int64_t s1) {
+      for (int64_t sl = s0; sl < s1; ++sl) {
+        double* gp = part.data() + (size_t)sl * d;
+        const int64_t e1 = std::min(rows, (sl + 1) * kSlice);
+        for (int64_t i = sl * kSlice; i < e1; ++i) {
+          const double* xr = X + (r0 + i) * f;
+          const double yp = y[r0 + i] ? 1.0 : -1.0;
+          double m = W[0];
+          for (int j = 0; j < f; ++j) m += xr[j] * W[j + 1];
+          m *= yp;
+          if (mout) mout[i] = (float)m;
+          const double c = (1.0 - sig(m)) * yp;
+          gp[0] += c;
+          for (int j = 0; j < f; ++j) gp[j + 1] += c * xr[j];
+        }
+      }
+    };
+    const int nth = (int)std::min<int64_t>(nt, n_slices);
+    std::vector<std::thread> pool;
+    for (int th = 0; th < nth; ++th) pool.emplace_back(work, n_slices * th / nth, n_slices * (th + 1) / nth);
+    for (auto& th : pool) th.join();
+    std::fill(grad.begin(), grad.end(), 0.0);
+    for (int64_t sl = 0; sl < n_slices; ++sl)
+      for (int j = 0; j < d; ++j) grad[j] += part[(size_t)sl * d + j];
+    const double eta = (1.0 - a0) / a1;
+    const double lr = lr_max - (lr_max - lr_min) * std::pow((double)t / T, gamma);
+    for (int j = 0; j < d; ++j) {
+      const double vt = W[j] + lr * B[(size_t)k * d + j] * grad[j];
+      W[j] = (1.0 - eta) * vt + eta * V[j];
+      V[j] = vt;
+    }
+    a0 = a1;
+    a1 = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * a0 * a0));
+    if (mout) mout += rows;
+  }
+  std::copy(W.begin(), W.end(), w_out);
+  return HEQG_OK;
+}

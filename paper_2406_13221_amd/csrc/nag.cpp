@@ -299,21 +299,29 @@ void circuit(Exec& X, const Io& io, const heqg_sigmoid* sg, heqg_nag_state* st, 
   Ct gr = X.relin_rs(acc);
   for (int k = 0; k < lm; ++k) gr = X.add_rot(gr, g << k);
   const int t = st->t;
+  const bool fo = st->first_order != 0;
   st->refreshed_gr = 0;
-  if (std::min(io.Bbar.level - 1, gr.level) < 1) {
+  if (std::min(fo ? gr.level : io.Bbar.level - 1, gr.level) < 1) {
     if (nc > kMaxRefreshColBlocks) X.fail(HEQG_ERR_UNSUPPORTED, "too many column blocks for a mid-iteration refresh");
     gr = X.refresh(gr, X.c->g.n_q - 1, st->refresh_seed, ((uint64_t)t << 4) | 2);
     st->refreshed_gr = 1;
   }
   const double eta = (1.0 - st->alpha0) / st->alpha1;
-  const double lr = st->lr_max - (st->lr_max - st->lr_min) * std::pow((double)t / st->T, st->gamma);
+  const double lr = fo ? 1.0 : st->lr_max - (st->lr_max - st->lr_min) * std::pow((double)t / st->T, st->gamma);
   const double s_g = X.c->delta;
-  const int lt = std::min(io.Bbar.level - 1, gr.level);
-  const double s_bv = s_g * X.q(lt) / gr.scale;
-  Ct Bv = X.mul_const(io.Bbar, lr, s_bv);
-  Ct Bw = X.mul_const(io.Bbar, lr * (1.0 - eta), s_bv);
-  Ct Gv = X.hmult_rs(Bv, gr);
-  Ct Gw = X.hmult_rs(Bw, gr);
+  Ct Gv{}, Gw{};
+  if (fo) {
+    // first-order NAG: the gradient times the constants fo_gamma and fo_gamma (1 - eta)
+    Gv = X.mul_const(gr, st->fo_gamma, s_g);
+    Gw = X.mul_const(gr, st->fo_gamma * (1.0 - eta), s_g);
+  } else {
+    const int lt = std::min(io.Bbar.level - 1, gr.level);
+    const double s_bv = s_g * X.q(lt) / gr.scale;
+    Ct Bv = X.mul_const(io.Bbar, lr, s_bv);
+    Ct Bw = X.mul_const(io.Bbar, lr * (1.0 - eta), s_bv);
+    Gv = X.hmult_rs(Bv, gr);
+    Gw = X.hmult_rs(Bw, gr);
+  }
   Vn = X.add(X.mul_const(io.W, 1.0, s_g), Gv);
   Wn = X.add(X.add(X.mul_const(io.W, 1.0 - eta, s_g), X.mul_const(io.V, eta, s_g)), Gw);
   st->eta = eta;
@@ -344,7 +352,9 @@ static std::string graph_key(const heqg_ctx* c, const heqg_keys* k, const heqg_c
   auto val = [&](auto v) { put(&v, sizeof(v)); };
   val(k->gen);  // first: heqg_keys_destroy drops the graphs of its key set by this prefix
   val(Z->data), val(Z->count), val(Z->stride), val(Z->level), val(Z->scale);
-  for (const heqg_ct* x : {Bbar, W, V}) val(x->data), val(x->level), val(x->scale);
+  for (const heqg_ct* x : {Bbar, W, V})
+    if (x) val(x->data), val(x->level), val(x->scale);
+  val(st->first_order);
   val(sg->masks), val(sg->degree), val(sg->mask_level);
   for (int i = 0; i <= n_terms(sg->degree); ++i) val(sg->mask_scales[i]);
   val(st->m_rows), val(st->g_cols), val(st->col_blocks), val(batch), val(ws), val(ws_bytes);
@@ -355,20 +365,23 @@ static std::string graph_key(const heqg_ctx* c, const heqg_keys* k, const heqg_c
 static int nag_step(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch* Z, const heqg_ct* Bbar, heqg_ct* W,
                     heqg_ct* V, const heqg_sigmoid* sg, heqg_nag_state* st, int batch, void* ws, size_t ws_bytes,
                     hipStream_t s, bool graph) {
-  if (!c || !k || !Z || !Bbar || !W || !V || !sg || !st || !Z->data || !Bbar->data || !W->data || !V->data ||
-      !sg->masks || !sg->mask_scales) {
+  const bool fo = st && st->first_order != 0;
+  if (!c || !k || !Z || (!Bbar && !fo) || !W || !V || !sg || !st || !Z->data || (Bbar && !Bbar->data) ||
+      !W->data || !V->data || !sg->masks || !sg->mask_scales) {
     set_err("nag_qg_step: null argument");
     return HEQG_ERR_ARG;
   }
   const int nc = st ? std::max(1, st->col_blocks) : 1;
-  if (batch < 1 || Z->count < 1 || Z->n_poly != 2 || Bbar->n_poly != 2 || W->n_poly != 2 || V->n_poly != 2 ||
+  if (fo) Bbar = nullptr;  // unused by the first-order step
+  if (batch < 1 || Z->count < 1 || Z->n_poly != 2 || (Bbar && Bbar->n_poly != 2) || W->n_poly != 2 ||
+      V->n_poly != 2 ||
       (sg->degree != 3 && sg->degree != 5 && sg->degree != 7) || st->m_rows < 1 || st->g_cols < 1 ||
       (int64_t)st->m_rows * st->g_cols != c->g.N / 2 || (st->g_cols & (st->g_cols - 1)) ||
       (st->m_rows & (st->m_rows - 1)) || sg->mask_level < 0 || sg->mask_level >= c->g.n_q) {
     set_err("nag_qg_step: bad shapes (m_rows*g_cols must equal N/2, powers of two; degree 3, 5 or 7)");
     return HEQG_ERR_ARG;
   }
-  for (int lv : {Z->level, Bbar->level, W->level, V->level})
+  for (int lv : {Z->level, Bbar ? Bbar->level : Z->level, W->level, V->level})
     if (lv < 0 || lv >= c->g.n_q) {
       set_err("nag_qg_step: level out of range");
       return HEQG_ERR_ARG;
@@ -400,8 +413,9 @@ static int nag_step(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch* Z, con
   Io io;
   io.Z = Ct{Z->data, Z->stride, (int64_t)(Z->level + 1) * N, 2, Z->level, Z->scale, Z->count};
   // B-bar, W and V: nc ciphertexts back to back at their level
-  io.Bbar = Ct{Bbar->data, 2 * (int64_t)(Bbar->level + 1) * N, (int64_t)(Bbar->level + 1) * N, 2, Bbar->level,
-               Bbar->scale, nc};
+  if (Bbar)
+    io.Bbar = Ct{Bbar->data, 2 * (int64_t)(Bbar->level + 1) * N, (int64_t)(Bbar->level + 1) * N, 2, Bbar->level,
+                 Bbar->scale, nc};
   io.W = Ct{W->data, 2 * (int64_t)(W->level + 1) * N, (int64_t)(W->level + 1) * N, 2, W->level, W->scale, nc};
   io.V = Ct{V->data, 2 * (int64_t)(V->level + 1) * N, (int64_t)(V->level + 1) * N, 2, V->level, V->scale, nc};
   io.nc = nc;

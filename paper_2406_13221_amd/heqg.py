@@ -48,7 +48,8 @@ class NagStateS(ctypes.Structure):
                 ("lr_max", ctypes.c_double), ("lr_min", ctypes.c_double), ("T", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("m_rows", ctypes.c_int), ("g_cols", ctypes.c_int),
                 ("refresh_seed", ctypes.c_uint64), ("eta", ctypes.c_double), ("lr", ctypes.c_double),
-                ("refreshed_gr", ctypes.c_int), ("col_blocks", ctypes.c_int)]
+                ("refreshed_gr", ctypes.c_int), ("col_blocks", ctypes.c_int), ("first_order", ctypes.c_int),
+                ("fo_gamma", ctypes.c_double)]
 
 
 EXPORTS = None  # filled on load: every heqg_* function name the header declares
@@ -123,6 +124,7 @@ def lib():
         "heqg_export": (i32, [vp, P(BatchS), vp, vp, sz, vp]),
         "heqg_import": (i32, [vp, vp, P(BatchS), vp]),
         "heqg_bbar": (i32, [vp, i64, i32, i32, dbl, vp, i32]),
+        "heqg_plain_qgnag": (i32, [vp, vp, i64, i32, i32, i64, vp, i32, dbl, dbl, dbl, dbl, dbl, vp, vp, i32]),
         "heqg_sigmoid_plan": (i32, [vp, i32, dbl, dbl, dbl, i32, vp]),
         "heqg_sigmoid_masks": (i32, [vp, vp, i32, i32, i32, i32, dbl, dbl, dbl, vp, vp]),
     }
@@ -163,6 +165,26 @@ def bbar(X, g, eps=1e-8, threads=0):
     out = np.zeros(g, dtype=np.float64)
     _check(lib().heqg_bbar(Xc.ctypes.data, n, f, g, float(eps), out.ctypes.data, int(threads)))
     return out
+
+
+def plain_qgnag(X, y, iters, batch_rows=0, coeffs=None, lr=(2.0, 1.0, 81.0, 2.5), eps=1e-8, margins=True,
+                threads=0):
+    """The data owner's FP64 plaintext run (heqg_plain_qgnag): returns (W over 1 + f columns, margins of
+    every iteration as one float32 array, or None).  coeffs: {odd k: c_k}, or None for the exact sigmoid."""
+    Xc = np.ascontiguousarray(X, dtype=np.float64)
+    yc = np.ascontiguousarray(y, dtype=np.int32)
+    n, f = Xc.shape
+    deg = max(coeffs) if coeffs else 0
+    cs = np.array([coeffs.get(k, 0.0) for k in range(1, deg + 1, 2)], dtype=np.float64) if coeffs else None
+    br = int(batch_rows or n)
+    total = sum(min(br, n - (t % -(-n // br)) * br) for t in range(iters))
+    m = np.zeros(total, dtype=np.float32) if margins else None
+    w = np.zeros(f + 1, dtype=np.float64)
+    _check(lib().heqg_plain_qgnag(Xc.ctypes.data, yc.ctypes.data, n, f, iters, int(batch_rows or 0),
+                                  cs.ctypes.data if cs is not None else None, deg, float(lr[0]), float(lr[1]),
+                                  float(lr[2]), float(lr[3]), float(eps), m.ctypes.data if m is not None else None,
+                                  w.ctypes.data, int(threads)))
+    return w, m
 
 
 def _torch():
@@ -526,10 +548,12 @@ class Context:
         sc = (ctypes.c_double * len(mask_scales))(*mask_scales)
         sig = SigmoidS(degree, masks.data_ptr(), mask_level, sc)
         zb = Z.batch()
-        bb, wb, vb = Bbar.one(), W.one(), V.one()
+        bb = Bbar.one() if Bbar is not None else None
+        wb, vb = W.one(), V.one()
         s = _stream() if stream is None else ctypes.c_void_p(stream)
         fn = L.heqg_nag_qg_graph if graph else L.heqg_nag_qg_step
-        _check(fn(self.h, keys.handle, ctypes.byref(zb), ctypes.byref(bb), ctypes.byref(wb), ctypes.byref(vb),
+        _check(fn(self.h, keys.handle, ctypes.byref(zb), ctypes.byref(bb) if bb is not None else None,
+                  ctypes.byref(wb), ctypes.byref(vb),
                   ctypes.byref(sig), ctypes.byref(state), batch, ws.data_ptr(), ws.numel(), s))
         for ct, cs in ((W, wb), (V, vb)):
             n = ct.count * 2 * (cs.level + 1) * self.N

@@ -87,8 +87,11 @@ def new_state(m, g, refresh_seed=0, lr_max=2.0, lr_min=1.0, T=81.0, gamma=2.5, c
 class EncryptedQGNAG:
     """Client + cloud roles of the pipeline on one GPU."""
 
-    def __init__(self, cfg, X, y, coeffs=None, batch=16, rows=None, threads=0, mini_batch=False, graph=False):
-        """graph: submit each iteration as a replayed HIP graph (on a side stream of this object)."""
+    def __init__(self, cfg, X, y, coeffs=None, batch=16, rows=None, threads=0, mini_batch=False, graph=False,
+                 first_order=False):
+        """graph: submit each iteration as a replayed HIP graph (on a side stream of this object).
+        first_order: train with the first-order NAG the paper compares against (step cfg["fo_lr"] / n on
+        the gradient, no B-bar) instead of the quadratic gradient."""
         import torch
         self.cfg = cfg
         self.m, self.g = cfg["m"], cfg["g"]
@@ -125,6 +128,8 @@ class EncryptedQGNAG:
             raise ValueError("batch_rows must be a multiple of m")
         spans = [(0, n)] if not br else [(s, min(s + br, n)) for s in range(0, n, br)]
         self.block_spans = [(s // self.m, -(-e // self.m)) for s, e in spans]
+        self.span_rows = [e - s for s, e in spans]
+        self.first_order = first_order
         self.Bbars = [self._bbar_cts(Xs[s:e], (1 << 40) + 16 + i * nc) for i, (s, e) in enumerate(spans)]
         self.Bbar = self.Bbars[0]
         zero = np.zeros((nc, ctx.N), dtype=np.int64)
@@ -135,9 +140,23 @@ class EncryptedQGNAG:
         self.graph = graph
         self.stream = torch.cuda.Stream() if graph else None
         self.set_sigmoid(self.coeffs)
-        self.state = new_state(self.m, self.g, refresh_seed=cfg["enc_seed"] + 7, col_blocks=nc)
+        self.state = new_state(self.m, self.g, refresh_seed=cfg["enc_seed"] + 7, col_blocks=nc,
+                               T=cfg.get("lr_T", 81.0))
         self.ws = heqg._ws(ctx.nag_ws_bytes(batch, self.degree))
         self.refresh_obj = 1 << 41
+
+    def reset(self, obj=(1 << 40) + (1 << 30)):
+        """W = V = 0 again (fresh encryptions into the same storage, objects obj + j) and t = 0."""
+        ctx, nc, L = self.ctx, self.nc, self.L
+        zero = np.zeros((nc, ctx.N), dtype=np.int64)
+        self.W = heqg.Cts(self.Wbuf, L, ctx.delta)
+        self.V = heqg.Cts(self.Vbuf, L, ctx.delta)
+        for ct, o in ((self.W, obj), (self.V, obj + nc)):
+            fresh = ctx.encrypt(self.keys, zero, L, ctx.delta, self.cfg["enc_seed"], o)
+            ct.data.copy_(fresh.data)
+        st = self.state
+        self.state = new_state(self.m, self.g, refresh_seed=st.refresh_seed, lr_max=st.lr_max, lr_min=st.lr_min,
+                               T=st.T, gamma=st.gamma, col_blocks=nc)
 
     def _bbar_cts(self, Xr, obj_first):
         """B-bar of the rows Xr (width C*g), one ciphertext per column block (objects obj_first + j)."""
@@ -199,7 +218,9 @@ class EncryptedQGNAG:
         mb.W = ctx.encrypt(self.keys, zero, L, ctx.delta, self.cfg["enc_seed"], (1 << 40) + 3 * nc)
         mb.V = ctx.encrypt(self.keys, zero, L, ctx.delta, self.cfg["enc_seed"], (1 << 40) + 4 * nc)
         mb.Wbuf, mb.Vbuf = mb.W.data, mb.V.data
-        mb.state = new_state(self.m, self.g, refresh_seed=self.cfg["enc_seed"] + 7, col_blocks=nc)
+        mb.state = new_state(self.m, self.g, refresh_seed=self.cfg["enc_seed"] + 7, col_blocks=nc,
+                             T=self.cfg.get("lr_T", 81.0))
+        mb.span_rows = [e - s for s, e in spans]
         mb.batch = batch
         mb.ws = heqg._ws(ctx.nag_ws_bytes(batch, self.degree))
         mb.graph = graph
@@ -236,8 +257,12 @@ class EncryptedQGNAG:
         k = self.state.t % len(self.block_spans)
         b0, b1 = self.block_spans[k]
         Z = heqg.Cts(self.Z.data[b0 * self.nc:b1 * self.nc], self.Z.level, self.Z.scale)
-        ctx.nag_qg_step(self.keys, Z, self.Bbars[k], self.W, self.V, self.masks, self.mask_level, self.mask_scales,
-                        self.degree, self.state, self.batch, self.ws, graph=self.graph)
+        if self.first_order:
+            self.state.first_order = 1
+            self.state.fo_gamma = self.cfg["fo_lr"] / self.span_rows[k]
+        ctx.nag_qg_step(self.keys, Z, None if self.first_order else self.Bbars[k], self.W, self.V, self.masks,
+                        self.mask_level, self.mask_scales, self.degree, self.state, self.batch, self.ws,
+                        graph=self.graph)
         if refresh:
             self.refresh()
         return self.state

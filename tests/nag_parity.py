@@ -145,7 +145,7 @@ def run_parity(cfgkey, iters, batch, coeffs=trainer.G8, rows=None, bbar_rows=Non
 
 
 # ---------------------------------------------------------------- the m x g partition (section 2.2)
-def grid_oracle_setup(cfgkey, rows=None, **over):
+def grid_oracle_setup(cfgkey, rows=None, coeffs=trainer.G8, **over):
     """Row blocks x column blocks of Z and one B-bar, W, V ciphertext per column block, encrypted by the
     oracle (object ids: i * C + j for Z; 2^20 + j, 2^21 + j, 2^22 + j for B-bar, W, V)."""
     cfg = config(cfgkey, **over)
@@ -167,7 +167,7 @@ def grid_oracle_setup(cfgkey, rows=None, **over):
     zero = np.zeros(N, np.int64)
     W = [o.encrypt(zero, L, o.delta, cfg["enc_seed"], (1 << 21) + j) for j in range(nc)]
     V = [o.encrypt(zero, L, o.delta, cfg["enc_seed"], (1 << 22) + j) for j in range(nc)]
-    masks = circuit.make_masks(o, m, g, trainer.G8, L, o.delta)
+    masks = circuit.make_masks(o, m, g, coeffs, L, o.delta)
     return cfg, o, X, y, Zg, Bc, W, V, masks
 
 
@@ -190,12 +190,20 @@ def assert_same_cts(g, cts, what):
                                                                                   bad[0]))
 
 
-def run_grid_parity(cfgkey, iters, batch, rows=None, **over):
+def run_grid_parity(cfgkey, iters, batch, rows=None, first_order=False, **over):
     """iters iterations over the partition on both sides (W, V refreshed after each), compared residue
-    by residue; returns the oracle and its last W list."""
-    print("grid parity: %s iters=%d batch=%d rows=%s" % (cfgkey, iters, batch, rows), flush=True)
-    cfg, o, X, y, Zg, Bc, W, V, masks = grid_oracle_setup(cfgkey, rows, **over)
+    by residue; the workload's sigmoid (g8 or g16) and learning-rate horizon; first_order: the
+    first-order NAG baseline with step lr0 / n (the workload's fo_lr).  Returns the oracle, its last W
+    list and the rows."""
+    import functools
+    print("grid parity: %s iters=%d batch=%d rows=%s first_order=%s" % (cfgkey, iters, batch, rows, first_order),
+          flush=True)
+    cfg0 = config(cfgkey, **over)
+    coeffs = trainer.G16 if cfg0.get("sigmoid") == "g16" else trainer.G8
+    cfg, o, X, y, Zg, Bc, W, V, masks = grid_oracle_setup(cfgkey, rows, coeffs=coeffs, **over)
     m, g, L, nc = cfg["m"], cfg["g"], o.top_level, len(W)
+    lr_fn = functools.partial(trainer.f2_lr, T=cfg["lr_T"])
+    fo_gamma = cfg["fo_lr"] / X.shape[0] if first_order else None
     ctx, keys = gpu_with_keys(cfgkey, **over)
     import torch
     gZ = stack_cts([c for row in Zg for c in row])
@@ -206,9 +214,12 @@ def run_grid_parity(cfgkey, iters, batch, rows=None, **over):
     ost = circuit.new_state(refresh_seed=7)
     gst = gpu_state(ost, m, g)
     gst.col_blocks = nc
+    gst.T = cfg["lr_T"]
+    if first_order:
+        gst.first_order, gst.fo_gamma = 1, fo_gamma
     for it in range(iters):
-        W, V, ost = circuit.nag_qg_step_grid(o, Zg, Bc, W, V, ost, masks, m, g)
-        ctx.nag_qg_step(keys, gZ, gB, gW, gV, mk, L - 1, scales, 3, gst, batch)
+        W, V, ost = circuit.nag_qg_step_grid(o, Zg, Bc, W, V, ost, masks, m, g, lr_fn=lr_fn, fo_gamma=fo_gamma)
+        ctx.nag_qg_step(keys, gZ, None if first_order else gB, gW, gV, mk, L - 1, scales, 3, gst, batch)
         assert_same_cts(gW, W, "W%d" % it)
         assert_same_cts(gV, V, "V%d" % it)
         assert gst.t == ost["t"] and gst.eta == ost["eta"] and bool(gst.refreshed_gr) == ost["refreshed_gr"]

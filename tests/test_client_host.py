@@ -40,3 +40,28 @@ def test_bbar_rejects_bad_shapes(heqg):
     assert e.value.code == heqg.ERR_ARG
     with pytest.raises(heqg.HeqgError):
         heqg.bbar(np.zeros((0, 3)), 4)
+
+
+@pytest.mark.parametrize("exact,batch_rows", [(True, 0), (False, 0), (False, 700)])
+def test_plain_qgnag_matches_oracle_trainer(heqg, exact, batch_rows):
+    """The data owner's FP64 run (heqg_plain_qgnag) against the oracle's trainer: weights and every
+    iteration's margins (full batch and ragged mini-batches, exact sigmoid and g8)."""
+    rng = np.random.default_rng(11)
+    X = rng.uniform(-1, 1, (3000, 9))
+    y = (rng.uniform(size=3000) < 0.3).astype(np.int64)
+    coeffs = None if exact else trainer.G8
+    w, m = heqg.plain_qgnag(X, y, 6, batch_rows=batch_rows, coeffs=coeffs, threads=3)
+    ref = trainer.train(X, y, 10, 6, exact_sigmoid=exact, batch_rows=batch_rows or None, log_margins=True)
+    assert np.allclose(w, ref["W"][:10], rtol=1e-10, atol=1e-13)
+    rm = np.concatenate(ref["margins"])
+    assert m.shape == rm.shape
+    assert np.allclose(m, rm.astype(np.float32), rtol=1e-6, atol=1e-6)
+
+
+def test_plain_qgnag_independent_of_threads(heqg):
+    rng = np.random.default_rng(12)
+    X = rng.uniform(-1, 1, (10000, 5))
+    y = (rng.uniform(size=10000) < 0.5).astype(np.int64)
+    a = heqg.plain_qgnag(X, y, 3, threads=1)
+    b = heqg.plain_qgnag(X, y, 3, threads=8)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
