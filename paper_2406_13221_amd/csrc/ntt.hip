@@ -1155,8 +1155,18 @@ __device__ __forceinline__ void ksr_body(const KsrParams& P, int64_t ct, int x, 
 // 8-byte bank slots and each 16-lane quarter-wave 16 distinct slots modulo 16: conflict-free
 // whether a 64-bit access is served 32 or 16 lanes per cycle.  (The earlier form, which only
 // kept half-waves distinct, left layout C with two lanes per slot in each quarter-wave.)
-__device__ __forceinline__ int sw8(int e) {
+__host__ __device__ constexpr int sw8(int e) {
   return e ^ ((e >> 4) & 1) ^ ((e >> 3) & 28) ^ ((e >> 5) & 2);
+}
+// sw8 is linear over GF(2) (an XOR of shifted bit fields), and in each layout an element index
+// is the XOR of a lane part and an r part (A: j ^ 32r, B: a ^ 4r, C: 8j ^ r), so an LDS byte
+// address is a per-lane base XOR a compile-time constant: one VALU instruction per access.
+__host__ __device__ constexpr uint32_t sw8A(int r) { return 8u * (uint32_t)sw8(32 * r); }
+__host__ __device__ constexpr uint32_t sw8B(int r) { return 8u * (uint32_t)sw8(4 * r); }
+__host__ __device__ constexpr uint32_t sw8C(int r) { return 8u * (uint32_t)sw8(r); }
+// the LDS word at byte offset off of the workgroup's exchange array
+__device__ __forceinline__ uint64_t& lds_word(uint64_t* lds, uint32_t off) {
+  return *reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(lds) + off);
 }
 
 // stage st (0..7) pairs elements e and e + 2^(7-st) with twiddle (base << st) + (e >> (8-st))
@@ -1259,11 +1269,17 @@ __device__ __forceinline__ void st8T_C(double (&x)[8], const double* T, int j, B
 // barrier per exchange suffices.
 // twl: the workgroup's LDS twiddle tables (8 sub-rows x 256 doubles; FP64 path only).
 template <bool FP>
-__device__ __forceinline__ void ksr8_body(const KsrParams& P, int64_t ct, int x, int gp, int b, uint64_t* l,
+__device__ __forceinline__ void ksr8_body(const KsrParams& P, int64_t ct, int x, int gp, int b, uint64_t* lds,
                                           double* twl) {
   const KsRows& K = P.K;
   const int j = threadIdx.x & 31;
   const int a = (j & 3) + 32 * (j >> 2);
+  // byte offsets in the exchange array of this lane's elements in layouts A, B, C (r = 0); the
+  // sub-row's 256 words start at a multiple of 2048 bytes, so the XOR with a constant below 2048
+  // stays inside it
+  const uint32_t rbase = (uint32_t)(threadIdx.x >> 5) * 2048u;
+  const uint32_t oA = rbase + 8u * (uint32_t)sw8(j), oB = rbase + 8u * (uint32_t)sw8(a),
+                 oC = rbase + 8u * (uint32_t)sw8(8 * j);
   const PrimeConst pc = P.pc[gp];
   const int N1 = 1 << (P.logN - 8);
   const int64_t base = N1 + b;
@@ -1322,29 +1338,30 @@ __device__ __forceinline__ void ksr8_body(const KsrParams& P, int64_t ct, int x,
 #pragma unroll 1
     for (int k = 0; k < next; ++k) {
       const uint64_t* src = ext_row(k);
-      int jk = j, ak = a, jqk = j >> 2;
-      asm volatile("" : "+v"(jk), "+v"(ak), "+v"(jqk));
+      int jk = j, jqk = j >> 2;
+      uint32_t oAk = oA, oBk = oB, oCk = oC;
+      asm volatile("" : "+v"(jk), "+v"(jqk), "+v"(oAk), "+v"(oBk), "+v"(oCk));
       double v[8];
 #pragma unroll
       for (int r = 0; r < 8; ++r) v[r] = as_f(src[32 * r]);
       st8T_A<true>(v, T, bf);
 #pragma unroll
-      for (int r = 0; r < 8; ++r) l[sw8(jk + 32 * r)] = as_u(v[r]);
+      for (int r = 0; r < 8; ++r) lds_word(lds, oAk ^ sw8A(r)) = as_u(v[r]);
       __syncthreads();
 #pragma unroll
-      for (int r = 0; r < 8; ++r) v[r] = as_f(l[sw8(ak + 4 * r)]);
+      for (int r = 0; r < 8; ++r) v[r] = as_f(lds_word(lds, oBk ^ sw8B(r)));
       st8T_B<true>(v, T, jqk, bf);
 #pragma unroll
-      for (int r = 0; r < 8; ++r) l[sw8(ak + 4 * r)] = as_u(v[r]);
+      for (int r = 0; r < 8; ++r) lds_word(lds, oBk ^ sw8B(r)) = as_u(v[r]);
       __syncthreads();
 #pragma unroll
-      for (int r = 0; r < 8; ++r) v[r] = as_f(l[sw8(8 * jk + r)]);
+      for (int r = 0; r < 8; ++r) v[r] = as_f(lds_word(lds, oCk ^ sw8C(r)));
       st8T_C<true>(v, T, jk, bf);
 #pragma unroll
-      for (int r = 0; r < 8; ++r) l[sw8(8 * jk + r)] = as_u(v[r]);
+      for (int r = 0; r < 8; ++r) lds_word(lds, oCk ^ sw8C(r)) = as_u(v[r]);
       __syncthreads();
 #pragma unroll
-      for (int r = 0; r < 8; ++r) v[r] = as_f(l[sw8(jk + 32 * r)]);
+      for (int r = 0; r < 8; ++r) v[r] = as_f(lds_word(lds, oAk ^ sw8A(r)));
       mac(v, k + (k >= jo ? 1 : 0));
     }
     if (inq) {
@@ -1360,22 +1377,22 @@ __device__ __forceinline__ void ksr8_body(const KsrParams& P, int64_t ct, int x,
       auto ibf = [&](double& X, double& Y, double w) { gs_f(X, Y, w, q, qi); };
       auto inv_row = [&](double (&v)[8], uint64_t* dst) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) l[sw8(j + 32 * r)] = as_u(fred(v[r], q, qi));
+        for (int r = 0; r < 8; ++r) lds_word(lds, oA ^ sw8A(r)) = as_u(fred(v[r], q, qi));
         __syncthreads();  // (the first time: the inverse tables are in LDS too)
 #pragma unroll
-        for (int r = 0; r < 8; ++r) v[r] = as_f(l[sw8(8 * j + r)]);
+        for (int r = 0; r < 8; ++r) v[r] = as_f(lds_word(lds, oC ^ sw8C(r)));
         st8T_C<false>(v, T, j, ibf);
 #pragma unroll
-        for (int r = 0; r < 8; ++r) l[sw8(8 * j + r)] = as_u(fred(v[r], q, qi));
+        for (int r = 0; r < 8; ++r) lds_word(lds, oC ^ sw8C(r)) = as_u(fred(v[r], q, qi));
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 8; ++r) v[r] = as_f(l[sw8(a + 4 * r)]);
+        for (int r = 0; r < 8; ++r) v[r] = as_f(lds_word(lds, oB ^ sw8B(r)));
         st8T_B<false>(v, T, j >> 2, ibf);
 #pragma unroll
-        for (int r = 0; r < 8; ++r) l[sw8(a + 4 * r)] = as_u(fred(v[r], q, qi));
+        for (int r = 0; r < 8; ++r) lds_word(lds, oB ^ sw8B(r)) = as_u(fred(v[r], q, qi));
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 8; ++r) v[r] = as_f(l[sw8(j + 32 * r)]);
+        for (int r = 0; r < 8; ++r) v[r] = as_f(lds_word(lds, oA ^ sw8A(r)));
         st8T_A<false>(v, T, ibf);
 #pragma unroll
         for (int r = 0; r < 8; ++r) dst[32 * r] = as_u(fred(v[r], q, qi));
@@ -1411,31 +1428,32 @@ __device__ __forceinline__ void ksr8_body(const KsrParams& P, int64_t ct, int x,
       const U2* twk = tw;
       int jk = j, ak = a;
       int64_t bk = base;
-      asm volatile("" : "+s"(twk), "+v"(jk), "+v"(ak), "+v"(bk));
+      uint32_t oAk = oA, oBk = oB, oCk = oC;
+      asm volatile("" : "+s"(twk), "+v"(jk), "+v"(ak), "+v"(bk), "+v"(oAk), "+v"(oBk), "+v"(oCk));
       uint64_t v[8];
 #pragma unroll
       for (int r = 0; r < 8; ++r) v[r] = src[32 * r];
       st8_A<true>(v, twk, bk, bf);
 #pragma unroll
-      for (int r = 0; r < 8; ++r) l[sw8(jk + 32 * r)] = v[r];
+      for (int r = 0; r < 8; ++r) lds_word(lds, oAk ^ sw8A(r)) = v[r];
       __syncthreads();
 #pragma unroll
-      for (int r = 0; r < 8; ++r) v[r] = l[sw8(ak + 4 * r)];
+      for (int r = 0; r < 8; ++r) v[r] = lds_word(lds, oBk ^ sw8B(r));
       st8_B<true>(v, twk, bk, ak, bf);
 #pragma unroll
-      for (int r = 0; r < 8; ++r) l[sw8(ak + 4 * r)] = v[r];
+      for (int r = 0; r < 8; ++r) lds_word(lds, oBk ^ sw8B(r)) = v[r];
       __syncthreads();
 #pragma unroll
-      for (int r = 0; r < 8; ++r) v[r] = l[sw8(8 * jk + r)];
+      for (int r = 0; r < 8; ++r) v[r] = lds_word(lds, oCk ^ sw8C(r));
       st8_C<true>(v, twk, bk, jk, bf);
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         const uint64_t w = v[r] >= two_q ? v[r] - two_q : v[r];
-        l[sw8(8 * jk + r)] = w >= q ? w - q : w;
+        lds_word(lds, oCk ^ sw8C(r)) = w >= q ? w - q : w;
       }
       __syncthreads();
 #pragma unroll
-      for (int r = 0; r < 8; ++r) v[r] = l[sw8(jk + 32 * r)];
+      for (int r = 0; r < 8; ++r) v[r] = lds_word(lds, oAk ^ sw8A(r));
       mac(v, k + (k >= jo ? 1 : 0));
     }
     if (inq) {
@@ -1448,22 +1466,22 @@ __device__ __forceinline__ void ksr8_body(const KsrParams& P, int64_t ct, int x,
       auto ibf = [&](uint64_t& X, uint64_t& Y, U2 w) { gs_bfly(X, Y, w, q, two_q); };
       auto inv_row = [&](uint64_t (&v)[8], uint64_t* dst) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) l[sw8(j + 32 * r)] = v[r];
+        for (int r = 0; r < 8; ++r) lds_word(lds, oA ^ sw8A(r)) = v[r];
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 8; ++r) v[r] = l[sw8(8 * j + r)];
+        for (int r = 0; r < 8; ++r) v[r] = lds_word(lds, oC ^ sw8C(r));
         st8_C<false>(v, twi, base, j, ibf);
 #pragma unroll
-        for (int r = 0; r < 8; ++r) l[sw8(8 * j + r)] = v[r];
+        for (int r = 0; r < 8; ++r) lds_word(lds, oC ^ sw8C(r)) = v[r];
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 8; ++r) v[r] = l[sw8(a + 4 * r)];
+        for (int r = 0; r < 8; ++r) v[r] = lds_word(lds, oB ^ sw8B(r));
         st8_B<false>(v, twi, base, a, ibf);
 #pragma unroll
-        for (int r = 0; r < 8; ++r) l[sw8(a + 4 * r)] = v[r];
+        for (int r = 0; r < 8; ++r) lds_word(lds, oB ^ sw8B(r)) = v[r];
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 8; ++r) v[r] = l[sw8(j + 32 * r)];
+        for (int r = 0; r < 8; ++r) v[r] = lds_word(lds, oA ^ sw8A(r));
         st8_A<false>(v, twi, base, ibf);
 #pragma unroll
         for (int r = 0; r < 8; ++r) dst[32 * r] = v[r];
@@ -1485,9 +1503,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   const int gp = x < K.nl ? x : K.nq + (x - K.nl);
   const int rl = threadIdx.x >> 5;
   if (P.pc[gp].k <= FP_MAX_BITS)
-    ksr8_body<true>(P, ct, x, gp, tile * 8 + rl, lds + rl * 256, twl);
+    ksr8_body<true>(P, ct, x, gp, tile * 8 + rl, lds, twl);
   else
-    ksr8_body<false>(P, ct, x, gp, tile * 8 + rl, lds + rl * 256, twl);
+    ksr8_body<false>(P, ct, x, gp, tile * 8 + rl, lds, twl);
 }
 
 // Each workgroup takes the arithmetic path of its output limb's prime.  At three waves per
