@@ -1,0 +1,257 @@
+"""TEST INFRASTRUCTURE: CKKS bootstrapping on the oracle, step by step.
+
+The paper refreshes the weight ciphertexts by bootstrapping once per iteration (section 2.1
+lists bootstrap among the operations; section 4.3, step 7; Table 1: one iteration per
+bootstrapping); it runs inside HEAAN and is not described further.  This follows the
+published method of Cheon, Han, Kim, Kim and Song (bootstrapping for approximate homomorphic
+encryption, 2018) in the full-RNS setting, with the baby-step giant-step linear transforms of
+Halevi and Shoup and a cosine approximation with double-angle steps:
+
+  ModRaise     a level-0 ciphertext (c0, c1) mod q0 is read with centred coefficients mod the
+               whole chain: it decrypts to t = m + q0 I, I a small integer polynomial;
+  CoeffToSlot  slots z = sigma(t)/s become w = (2/N) U0^H z = (t_lo + i t_hi)/s, the low and
+               high halves of t's coefficients as real and imaginary parts
+               (U0[j][k] = zeta_j^k, zeta_j = exp(i pi 5^j / N), j, k < N/2; zeta_j^(N/2) = i);
+  EvalMod      on real slots x = t_k/s: with u = x s / q0, t_k mod q0 ~ (q0 / 2 pi) sin(2 pi u),
+               sin(2 pi u) = cos(2 pi (u - 1/4)); cos on the small argument
+               v = (u - 1/4) / 2^r by its Taylor series, then r steps c <- 2 c^2 - 1;
+  SlotToCoeff  w' = (m_lo + i m_hi)/s back to slots U0 w' = sigma(m)/s.
+
+The real and imaginary parts are split with the conjugation X -> X^(2N-1) and recombined with
+the monomial X^(N/2) (multiplication by i in every slot, exact).  A dense linear map A of the
+N/2 slots is sum_d diag_d(A) * Rot(x, d) with diag_d[j] = A[j][(j + d) mod n], evaluated as
+sum_g Rot(sum_b Rot(diag_(n1 g + b), -n1 g) * Rot(x, b), n1 g).
+
+Requires a sparse ternary secret (Hamming weight h) so that |I| stays below the interval bound
+K the cosine approximation covers (the dense secret of the training parameters gives |I| in the
+tens at N = 2^12).
+"""
+import math
+
+import numpy as np
+
+from ._lib import lib
+from .ckks import Ct, OracleError, _p, galois_elt
+from .encode import encode, slot_exponents
+
+PUR_SPARSE = 0x5350415253450000  # purpose tag of the sparse-secret stream
+
+
+def sparse_secret(seed, N, h):
+    """h distinct positions (each word of the ChaCha20 stream, taken mod N, accepted when new and
+    below the largest multiple of N in 2^64) with signs from bit 63 of a second word."""
+    L = lib()
+    out = np.zeros(N, dtype=np.int64)
+    chosen = 0
+    w = 0
+    limit = (1 << 64) - ((1 << 64) % N)
+    buf = np.zeros(2, dtype=np.uint64)
+    while chosen < h:
+        L.oracle_stream_words(seed, PUR_SPARSE, 0, 0, w, 2, _p(buf))
+        w += 2
+        a, b = int(buf[0]), int(buf[1])
+        if a >= limit:
+            continue
+        pos = a % N
+        if out[pos] != 0:
+            continue
+        out[pos] = -1 if (b >> 63) else 1
+        chosen += 1
+    return out
+
+
+def bsgs_split(n):
+    n1 = 1 << ((int(math.log2(n)) + 1) // 2)
+    return n1, n // n1
+
+
+def boot_steps(N):
+    """Rotation steps of the two slot transforms (baby steps 1..n1-1, giant steps n1 g)."""
+    n = N // 2
+    n1, n2 = bsgs_split(n)
+    return list(range(1, n1)) + [n1 * g for g in range(1, n2)]
+
+
+def keygen_sparse(ora, seed, h, rot_steps):
+    """The oracle's keys (pk, relinearisation, rotations for rot_steps and the bootstrapping
+    transforms, conjugation) for a sparse ternary secret of weight h."""
+    L, N, nq, nqp = lib(), ora.N, ora.n_q, ora.n_q + ora.n_p
+    s = sparse_secret(seed, N, h)
+    s_ntt = np.zeros((nqp, N), dtype=np.uint64)
+    L.oracle_secret_ntt(ora.ctx, _p(s), _p(s_ntt))
+    pk = np.zeros((2, nq, N), dtype=np.uint64)
+    L.oracle_pk(ora.ctx, seed, _p(s_ntt), _p(pk))
+    s2 = np.zeros((nq, N), dtype=np.uint64)
+    sq = np.ascontiguousarray(s_ntt[:nq])
+    L.oracle_mul_pt(ora.ctx, _p(sq), _p(sq), 1, nq - 1, _p(s2))
+    rlk = ora._ksk(seed, 0, s_ntt, s2)
+    rot = {}
+    gal = [galois_elt(r, N) for r in list(rot_steps) + boot_steps(N)] + [2 * N - 1]
+    for t in gal:
+        if t in rot or t == 1:
+            continue
+        sr = np.zeros(N, dtype=np.int64)
+        L.oracle_automorph_int(N, _p(s), t, _p(sr))
+        sr_ntt = np.zeros((nq, N), dtype=np.uint64)
+        L.oracle_pt_from_int(ora.ctx, _p(sr), nq - 1, _p(sr_ntt))
+        rot[t] = ora._ksk(seed, t, s_ntt, sr_ntt)
+    ora.keys = dict(s=s, s_ntt=s_ntt, pk=pk, rlk=rlk, rot=rot, seed=seed)
+    return ora.keys
+
+
+def conjugate(ora, ct):
+    """X -> X^(2N-1): every slot to its complex conjugate, then key switching back to s."""
+    t = 2 * ora.N - 1
+    key = ora.keys["rot"].get(t)
+    if key is None:
+        raise OracleError("no conjugation key")
+    out = np.zeros((2, ct.level + 1, ora.N), dtype=np.uint64)
+    lib().oracle_rotate(ora.ctx, _p(ct.data), ct.level, t, _p(key), _p(out))
+    return Ct(out, ct.level, ct.scale)
+
+
+def times_i(ora, ct):
+    """Multiply every slot by i: the monomial X^(N/2) (zeta_j^(N/2) = i), exact, scale kept."""
+    mono = np.zeros(ora.N, dtype=np.int64)
+    mono[ora.N // 2] = 1
+    pt = ora.pt_from_int(mono, ct.level)
+    r = ora.mul_pt(ct, pt, 1.0)
+    r.scale = ct.scale
+    return r
+
+
+def mod_raise(ora, ct):
+    """A level-0 ciphertext read with centred coefficients (mod q0) at the top level."""
+    if ct.level != 0 or ct.n_poly != 2:
+        raise OracleError("mod_raise takes a two-part ciphertext at level 0")
+    q0 = ora.q(0)
+    coef = ora.ntt(ct.data[:, 0, :], [0, 0], inverse=True)
+    parts = []
+    for p in range(2):
+        c = coef[p].astype(np.int64)
+        c = np.where(coef[p] > (q0 - 1) // 2, c - np.int64(q0), c)
+        parts.append(ora.pt_from_int(c, ora.top_level))
+    return Ct(np.stack(parts), ora.top_level, ct.scale)
+
+
+def u0_matrix(N):
+    """U0[j][k] = zeta_j^k for the N/2 slots j and the first N/2 coefficient positions k."""
+    e = slot_exponents(N).astype(np.float64)
+    k = np.arange(N // 2, dtype=np.float64)
+    return np.exp(1j * np.pi * np.outer(e, k) / N)
+
+
+def linear(ora, ct, A):
+    """Slots x -> A x (A an N/2 x N/2 complex matrix), one level: diagonal plaintexts encoded at
+    scale q_level, products summed at scale s q_level, one rescale at the end."""
+    n = ora.N // 2
+    n1, n2 = bsgs_split(n)
+    lv = ct.level
+    if lv < 1:
+        raise OracleError("level exhausted")
+    ql = float(ora.q(lv))
+    idx = np.arange(n)
+    xb = [ct] + [ora.rotate(ct, b) for b in range(1, n1)]
+    total = None
+    for g in range(n2):
+        inner = None
+        for b in range(n1):
+            d = n1 * g + b
+            diag = A[idx, (idx + d) % n]
+            shifted = np.roll(diag, n1 * g)          # Rot(diag_d, -n1 g)
+            pt = ora.pt_from_int(encode(shifted, ora.N, ql), lv)
+            prod = ora.mul_pt(xb[b], pt, ql)
+            inner = prod if inner is None else ora.add(inner, prod)
+        if g:
+            inner = ora.rotate(inner, n1 * g)
+        total = inner if total is None else ora.add(total, inner)
+    out = ora.rescale(total)
+    out.scale = ct.scale   # the diagonals carry exactly the factor q_lv the rescale divides by
+    return out
+
+
+def coeff_to_slot(ora, ct):
+    U0 = u0_matrix(ora.N)
+    return linear(ora, ct, (2.0 / ora.N) * U0.conj().T)
+
+
+def slot_to_coeff(ora, ct):
+    return linear(ora, ct, u0_matrix(ora.N))
+
+
+class EvalMod:
+    """t mod q0 on real slots x = t/s, |t| < K q0: see the module docstring.  taylor: degree of
+    the cosine's Taylor polynomial (even, at most 22), r: double-angle steps.  The Taylor
+    polynomial in y = v^2 is evaluated as B0(y) + y^4 B1(y) + y^8 B2(y), each B_i of degree at
+    most 3 (baby steps y, y^2, y^3; giant steps y^4, y^8)."""
+
+    def __init__(self, K=16, r=5, taylor=20):
+        if taylor % 2 or taylor > 22:
+            raise ValueError("even Taylor degree up to 22")
+        self.K, self.r, self.taylor = K, r, taylor
+
+    def levels(self):
+        """Levels consumed: the affine map (1), the powers of y and the blocks (5), the double
+        angles (r), the final constant (1)."""
+        return 1 + 5 + self.r + 1
+
+    def __call__(self, ora, ct, q0, half=1.0):
+        """ct: real slots x (times `half`, the factor of the real/imaginary split, folded in here);
+        returns slots ~ (t mod q0)/s at scale ct.scale."""
+        s_in, delta = ct.scale, ora.delta
+        r = self.r
+        # v = (u - 1/4) / 2^r with u = x s_in / q0 (one constant product, one constant addition)
+        v = ora.mul_const(ct, half * s_in / (q0 * 2.0 ** r), delta)
+        v = ora.add_const(v, -0.25 / 2.0 ** r)
+        # cos(2 pi v) = sum_k (-1)^k (2 pi)^(2k) / (2k)! y^k, y = v^2, k <= taylor / 2
+        kmax = self.taylor // 2
+        c = [(-1) ** k * (2 * math.pi) ** (2 * k) / math.factorial(2 * k) for k in range(kmax + 1)]
+        y1 = ora.rescale(ora.hmult(v, v))
+        y2 = ora.rescale(ora.hmult(y1, y1))
+        y3 = ora.rescale(ora.hmult(y2, y1))
+        y4 = ora.rescale(ora.hmult(y2, y2))
+        y8 = ora.rescale(ora.hmult(y4, y4)) if kmax >= 8 else None
+        pw = {1: y1, 2: y2, 3: y3}
+
+        def block(k0, target):
+            acc = None
+            for k in range(1, 4):
+                if k0 + k > kmax:
+                    break
+                t = ora.mul_const(pw[k], c[k0 + k], target)
+                acc = t if acc is None else ora.add(acc, t)
+            if acc is None:
+                raise OracleError("a block needs a power of y")
+            return ora.add_const(acc, c[k0])
+
+        # a block multiplied by y^4 or y^8 is rescaled by the prime of the level the product is
+        # taken at: its constants target delta q / scale(giant power), so the sum lands at delta
+        blk_level = y3.level - 1
+        cosv = block(0, delta)
+        for k0, giant in ((4, y4), (8, y8)):
+            if k0 > kmax:
+                break
+            lv = min(blk_level, giant.level)
+            b = block(k0, delta * float(ora.q(lv)) / giant.scale)
+            cosv = ora.add(cosv, ora.rescale(ora.hmult(b, giant)))
+        # r double-angle steps: cos(2 theta) = 2 cos^2 theta - 1
+        for _ in range(r):
+            sq = ora.rescale(ora.hmult(cosv, cosv))
+            cosv = ora.add_const(ora.add(sq, sq), -1.0)
+        # (q0 / 2 pi) sin(2 pi u) / s_in at the input's scale
+        return ora.mul_const(cosv, q0 / (2.0 * math.pi * s_in), s_in)
+
+
+def bootstrap(ora, ct, evalmod=None):
+    """A level-0 ciphertext -> the same message at level top - (transforms + EvalMod)."""
+    em = evalmod or EvalMod()
+    q0 = float(ora.q(0))
+    t = mod_raise(ora, ct)
+    w = coeff_to_slot(ora, t)
+    wc = conjugate(ora, w)
+    re2 = ora.add(w, wc)                                   # 2 Re(w)
+    im2 = times_i(ora, ora.add(wc, w, sub=True))           # i (conj(w) - w) = 2 Im(w)
+    re = em(ora, re2, q0, half=0.5)
+    im = em(ora, im2, q0, half=0.5)
+    wp = ora.add(re, times_i(ora, im))
+    return slot_to_coeff(ora, wp)

@@ -1,0 +1,109 @@
+"""Pins for the oracle's CKKS bootstrapping (oracle/boot.py), each step against what its
+definition fixes: the sparse secret's weight; ModRaise decrypting to m + q0 I with I a small
+integer polynomial; the baby-step giant-step transform against a plain matrix product;
+CoeffToSlot putting the raised plaintext's coefficients into the slots; SlotToCoeff inverting it;
+EvalMod reducing x mod q0 within its approximation bound; and the whole bootstrap returning the
+message at a lower level.  Test-only parameters: N = 2^12, scale 2^50 with fifteen 50-bit primes
+and a 60-bit q0 (q0 / Delta = 2^10), a secret of Hamming weight 64.  The slot transform spreads
+each coefficient's error over all N/2 slots (about sqrt(N/2) = 45 times), so EvalMod works at
+the 50-bit scale."""
+import numpy as np
+import pytest
+
+from oracle import boot
+from oracle.ckks import Oracle
+from oracle.encode import decode, encode
+
+H, K = 64, 16
+CFG = dict(log2N=12, q_bits=[60] + [50] * 15, n_p=6, p_bits=60, dnum=3, log2_scale=50)
+
+
+@pytest.fixture(scope="module")
+def ora():
+    o = Oracle.from_config(CFG)
+    boot.keygen_sparse(o, 31, H, [])
+    return o
+
+
+def _coeffs(o, ct):
+    """Centred integer coefficients of the decryption (exact: lifted from two limbs)."""
+    return np.array(o.lift(o.decrypt(ct), ct.level), dtype=np.float64)
+
+
+def _fresh(o, z, level, obj):
+    return o.encrypt(encode(z, o.N, o.delta), level, o.delta, 77, obj)
+
+
+def test_sparse_secret_has_weight_h():
+    s = boot.sparse_secret(31, 4096, H)
+    assert int(np.count_nonzero(s)) == H and set(np.unique(s)) <= {-1, 0, 1}
+    assert np.array_equal(s, boot.sparse_secret(31, 4096, H))
+    assert not np.array_equal(s, boot.sparse_secret(32, 4096, H))
+
+
+def test_mod_raise_decrypts_to_m_plus_q0_I(ora):
+    o = ora
+    rng = np.random.default_rng(1)
+    z = rng.uniform(-1, 1, o.N // 2)
+    ct = _fresh(o, z, 0, 1)
+    m = o.lift(o.decrypt(ct), 0)                         # centred mod q0 (Python integers)
+    t = o.lift(o.decrypt(boot.mod_raise(o, ct)), 1)      # centred mod q0 q1
+    q0 = o.q(0)
+    assert all((a - b) % q0 == 0 for a, b in zip(t, m))  # t = m + q0 I exactly
+    I = [(a - b) // q0 for a, b in zip(t, m)]
+    assert max(abs(v) for v in I) <= K and max(abs(v) for v in I) >= 1
+
+
+def test_bsgs_transform_is_the_matrix_product(ora):
+    o = ora
+    rng = np.random.default_rng(2)
+    n = o.N // 2
+    A = (rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))) / np.sqrt(n)
+    z = rng.uniform(-1, 1, n) + 1j * rng.uniform(-1, 1, n)
+    ct = _fresh(o, z, 3, 2)
+    got = o.decrypt_values(boot.linear(o, ct, A))
+    assert np.abs(got - A @ z).max() < 1e-6
+
+
+def test_coeff_to_slot_then_slot_to_coeff(ora):
+    o = ora
+    rng = np.random.default_rng(3)
+    z = rng.uniform(-1, 1, o.N // 2)
+    ct0 = _fresh(o, z, 0, 3)
+    raised = boot.mod_raise(o, ct0)
+    t = _coeffs(o, raised)
+    w = boot.coeff_to_slot(o, raised)
+    got = o.decrypt_values(w)
+    h = o.N // 2
+    ref = (t[:h] + 1j * t[h:]) / raised.scale
+    assert np.abs(got - ref).max() < 1e-3              # |t| / scale reaches K q0 / Delta = 2^11
+    back = o.decrypt_values(boot.slot_to_coeff(o, w))
+    assert np.abs(back - decode(t, o.N, raised.scale)).max() < 1e-2
+
+
+def test_eval_mod_reduces_mod_q0(ora):
+    o = ora
+    rng = np.random.default_rng(4)
+    n = o.N // 2
+    q0 = float(o.q(0))
+    m = rng.uniform(-1, 1, n)                            # message values, |m| Delta << q0
+    I = rng.integers(-K + 1, K, n)
+    x = m + I * q0 / o.delta
+    ct = _fresh(o, x, o.top_level, 4)
+    em = boot.EvalMod(K=K)
+    out = em(o, ct, q0)
+    assert out.level == o.top_level - em.levels()
+    got = o.decrypt_values(out).real
+    # the sine linearisation costs (2 pi m Delta / q0)^2 / 6 relatively: below 7e-6 here
+    assert np.abs(got - m).max() < 2e-5
+
+
+def test_bootstrap_returns_the_message(ora):
+    o = ora
+    rng = np.random.default_rng(5)
+    z = rng.uniform(-1, 1, o.N // 2) + 1j * rng.uniform(-1, 1, o.N // 2)
+    ct0 = _fresh(o, z, 0, 5)
+    em = boot.EvalMod(K=K)
+    out = boot.bootstrap(o, ct0, em)
+    assert out.level == o.top_level - 2 - em.levels()
+    assert np.abs(o.decrypt_values(out) - z).max() < 1e-3
