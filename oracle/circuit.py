@@ -230,3 +230,23 @@ def nag_qg_step_grid(ora, Z_grid, B_cts, Ws, Vs, state, masks, m, g, degree=3, l
     st["alpha0"], st["alpha1"] = st["alpha1"], alpha_next(st["alpha1"])
     st["eta"], st["lr"] = eta, lr
     return Wn, Vn, st
+
+
+def score_grid(ora, X_grid, Ws, m, g):
+    """Encrypted scoring of validation rows with an encrypted model (the accuracy and AUROC of
+    sections 5.1 and 5.2 taken from encrypted scores): X_grid[i][j] holds rows of [1 | X | 0]
+    (no labels) in the m x g partition of section 2.2, Ws the model's column blocks.  For row
+    block i: u = Rescale(Relin(sum_j X_ij (x) W_j)), then u += Rot(u, 2^k) for k < log2 g, which
+    leaves each row's score x-hat . w in its column 0.  Returns the list of u."""
+    lg = int(math.log2(g))
+    out = []
+    for row in X_grid:
+        t3 = None
+        for j, x in enumerate(row):
+            prod = ora.tensor(x, Ws[j])
+            t3 = prod if t3 is None else ora.add(t3, prod)
+        u = ora.rescale(ora.relin(t3))
+        for k in range(lg):
+            u = ora.add(u, ora.rotate(u, 1 << k))
+        out.append(u)
+    return out

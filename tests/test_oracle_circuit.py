@@ -215,3 +215,31 @@ def test_first_order_nag_matches_fp64(cfgkey):
     # the first-order run moves differently from the quadratic-gradient one
     assert np.abs(ref["W"] - trainer.train(X, y, G, 2)["W"]).max() > 10 * TOL_W
 
+
+
+@pytest.mark.parametrize("cfgkey", ["c1", "c1g"])
+def test_encrypted_scores_are_the_plaintext_scores(cfgkey):
+    """Encrypted scoring: column 0 of every row decrypts to x-hat . w of that row (validation rows,
+    no labels), on one column block and on the grid; the AUROC of the decrypted scores is the
+    plaintext one."""
+    cfg = synth.get_config(cfgkey)
+    d = synth.make_dataset(cfg)
+    o = Oracle.from_config(cfg)
+    m, g = cfg["m"], cfg["g"]
+    G, nc = synth.padded_width(cfg), synth.col_blocks(cfg)
+    o.keygen(cfg["key_seed"], circuit.rot_steps(m, g))
+    Xv, yv = d["Xv"][:700], d["yv"][:700]
+    grid = circuit.pack_grid(trainer.xhat(Xv, G), m, g, o.N)
+    L = o.top_level
+    Xg = [[o.encrypt(encode(grid[i, j], o.N, o.delta), L, o.delta, 5, i * nc + j) for j in range(nc)]
+          for i in range(grid.shape[0])]
+    rng = np.random.default_rng(8)
+    w = np.zeros(G)
+    w[: Xv.shape[1] + 1] = rng.normal(size=Xv.shape[1] + 1) * 0.5
+    Wc = [o.encrypt(encode(circuit.replicate_row(w[j * g:(j + 1) * g], m, g), o.N, o.delta), L, o.delta, 6, j)
+          for j in range(nc)]
+    us = circuit.score_grid(o, Xg, Wc, m, g)
+    got = np.concatenate([o.decrypt_values(u).real.reshape(m, g)[:, 0] for u in us])[: len(yv)]
+    ref = trainer.xhat(Xv, G) @ w
+    assert np.abs(got - ref).max() < 1e-6
+    assert abs(trainer.auroc(got, yv) - trainer.auroc(ref, yv)) < 1e-9
