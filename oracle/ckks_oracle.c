@@ -673,14 +673,20 @@ void oracle_rescale(void* vc, const uint64_t* a, int n_poly, int level, uint64_t
  * Approximate fast base conversion of coefficient-form residues x over the
  * source primes src[0..ns) to one target prime qt:
  *   sum_i [x_i * (S/s_i)^-1]_{s_i} * (S/s_i)  mod qt,   S = prod src.
- * The integer this represents is x + u*S with 0 <= u < ns.
+ * With the canonical representatives of the bracket the integer this
+ * represents is x + u*S with 0 <= u < ns; with the centred ones (centred != 0,
+ * each in (-s_i/2, s_i/2)) it is x_c + u*S with x_c the centred residue of x
+ * mod S and |u| <= ns/2, symmetric about zero.
  */
 static uint64_t conv_one(const octx* c, const uint64_t* xs, const int* src, int ns, const uint64_t* inv_hat,
-                         const uint64_t* hat_t, uint64_t qt) {
+                         const uint64_t* hat_t, uint64_t qt, int centred) {
   uint64_t acc = 0;
   for (int k = 0; k < ns; ++k) {
-    uint64_t y = mulmod(xs[k], inv_hat[k], c->primes[src[k]]);
-    acc = addmod(acc, mulmod(y % qt, hat_t[k], qt), qt);
+    uint64_t p = c->primes[src[k]];
+    uint64_t y = mulmod(xs[k], inv_hat[k], p);
+    uint64_t term = mulmod(y % qt, hat_t[k], qt);
+    if (centred && y > (p - 1) / 2) term = submod(term, mulmod(p % qt, hat_t[k], qt), qt);
+    acc = addmod(acc, term, qt);
   }
   return acc;
 }
@@ -689,8 +695,8 @@ static uint64_t conv_one(const octx* c, const uint64_t* xs, const int* src, int 
  * Base conversion of whole coefficient-form polynomials:
  * in: ns limbs (primes src[]), out: nt limbs (primes dst[]).
  */
-void oracle_base_conv(void* vc, const uint64_t* in, const int* src, int ns, const int* dst, int nt, uint64_t* out) {
-  octx* c = (octx*)vc;
+static void base_conv(octx* c, const uint64_t* in, const int* src, int ns, const int* dst, int nt, uint64_t* out,
+                      int centred) {
   int N = c->N;
   uint64_t* inv_hat = (uint64_t*)malloc(sizeof(uint64_t) * ns);
   for (int k = 0; k < ns; ++k) {
@@ -705,11 +711,16 @@ void oracle_base_conv(void* vc, const uint64_t* in, const int* src, int ns, cons
     for (int k = 0; k < ns; ++k) hat_t[k] = prod_mod(c, src, ns, src[k], qt);
     for (int j = 0; j < N; ++j) {
       for (int k = 0; k < ns; ++k) xs[k] = in[(size_t)k * N + j];
-      out[(size_t)t * N + j] = conv_one(c, xs, src, ns, inv_hat, hat_t, qt);
+      out[(size_t)t * N + j] = conv_one(c, xs, src, ns, inv_hat, hat_t, qt, centred);
     }
     free(hat_t); free(xs);
   }
   free(inv_hat);
+}
+
+/* The canonical-representative conversion (ModUp's). */
+void oracle_base_conv(void* vc, const uint64_t* in, const int* src, int ns, const int* dst, int nt, uint64_t* out) {
+  base_conv((octx*)vc, in, src, ns, dst, nt, out, 0);
 }
 
 /*
@@ -721,7 +732,13 @@ void oracle_base_conv(void* vc, const uint64_t* in, const int* src, int ns, cons
  *      ModUp: extend [d]_{D_j} to every other active Q prime and every P prime
  *      by fast base conversion; limbs of D_j are d itself;
  *   3. NTT the extended limbs; inner product with (b_j, a_j) over Q_l and P;
- *   4. ModDown each of the two sums: (x - Conv_{P->Q_l}([x]_P)) * P^-1.
+ *   4. ModDown each of the two sums: (x - Conv_{P->Q_l}([x]_P)) * P^-1, the
+ *      conversion with centred terms, so that the division by P rounds to a
+ *      nearest integer up to a symmetric error |u| <= n_p/2.  (Canonical terms
+ *      would make it a floor minus u in [0, n_p): a bias of about -(n_p+1)/2
+ *      per coefficient, which the product of the second part with s turns into
+ *      a slowly varying error that piles up in the low slots over many key
+ *      switches.)
  */
 void oracle_keyswitch(void* vc, const uint64_t* d, int level, const uint64_t* ksk, uint64_t* out) {
   octx* c = (octx*)vc;
@@ -752,7 +769,7 @@ void oracle_keyswitch(void* vc, const uint64_t* d, int level, const uint64_t* ks
       ++nt;
     }
     uint64_t* conv = (uint64_t*)malloc(sizeof(uint64_t) * nt * N);
-    oracle_base_conv(c, dc + (size_t)lo * N, src, ns, dst, nt, conv);
+    base_conv(c, dc + (size_t)lo * N, src, ns, dst, nt, conv, 0);
     oracle_ntt(c, conv, nt, dst, 0);
     for (int t = 0; t < nt; ++t) memcpy(ext + (size_t)dpos[t] * N, conv + (size_t)t * N, sizeof(uint64_t) * N);
     for (int x = lo; x < hi; ++x) memcpy(ext + (size_t)x * N, d + (size_t)x * N, sizeof(uint64_t) * N);
@@ -779,7 +796,7 @@ void oracle_keyswitch(void* vc, const uint64_t* d, int level, const uint64_t* ks
     uint64_t* a = acc + (size_t)part * nx * N;
     memcpy(xp, a + (size_t)nl * N, sizeof(uint64_t) * np * N);
     oracle_ntt(c, xp, np, pidx, 1);
-    oracle_base_conv(c, xp, pidx, np, ext_idx, nl, conv);
+    base_conv(c, xp, pidx, np, ext_idx, nl, conv, 1);
     oracle_ntt(c, conv, nl, ext_idx, 0);
     uint64_t* o = out + (size_t)part * nl * N;
     for (int i = 0; i < nl; ++i) {

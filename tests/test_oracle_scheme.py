@@ -197,3 +197,48 @@ def test_add_const_three_parts_and_overflow():
     assert np.array_equal(r.data[1:], t.data[1:]) and not np.array_equal(r.data[0], t.data[0])
     with pytest.raises(Exception):
         o.add_const(a, 2.0 ** 40)
+
+
+def _ones_times(s):
+    """(1 + X + ... + X^(N-1)) s(X) mod X^N + 1: coefficient k is sum_{j<=k} s_j - sum_{j>k} s_j."""
+    s = np.asarray(s, dtype=np.float64)
+    c = np.cumsum(s)
+    return 2.0 * c - c[-1]
+
+
+@pytest.mark.parametrize("op", ["rotate", "relin"])
+def test_key_switch_error_has_no_bias(op):
+    """The division by P in ModDown rounds to nearest: a one-sided remainder (a floor, plus the
+    fast conversion's u P with 0 <= u < n_p) would give every coefficient of both key-switch
+    outputs a bias of about -(n_p + 1)/2, which the second output's product with s turns into
+    b (1 + X + ... + X^(N-1)) s, a slowly varying error.  The error of a key switch, regressed on
+    that polynomial, must have no such component (N = 2^12 gives 4,096 samples; the slope's
+    standard error is about 0.01, a biased ModDown gives about -1)."""
+    import synth
+    cfg = synth.get_config("c1")
+    o = Oracle.from_config(cfg)
+    o.keygen(cfg["key_seed"], [1])
+    rng = np.random.default_rng(11)
+    lv = o.top_level
+    a = rng.integers(-2 ** 30, 2 ** 30, o.N)
+    ca = o.encrypt(a, lv, 1.0, SEED_ENC, 21)
+    if op == "rotate":
+        da = [int(x) for x in _dec_int(o, ca)]
+        t = galois_elt(1, o.N)
+        exp = np.zeros(o.N)
+        for j in range(o.N):
+            e = (j * t) % (2 * o.N)
+            if e < o.N:
+                exp[e] += da[j]
+            else:
+                exp[e - o.N] -= da[j]
+        err = np.array([float(x) for x in _dec_int(o, o.rotate(ca, 1))]) - exp
+    else:
+        cb = o.encrypt(rng.integers(-2 ** 30, 2 ** 30, o.N), lv, 1.0, SEED_ENC, 22)
+        t3 = o.tensor(ca, cb)
+        err = np.array([float(int(x) - int(y)) for x, y in zip(_dec_int(o, o.relin(t3)), _dec_int(o, t3))])
+    w = _ones_times(o.keys["s"])
+    A = np.stack([np.ones(o.N), w], axis=1)
+    (b0, b1), *_ = np.linalg.lstsq(A, err, rcond=None)
+    assert abs(b1) < 0.1, (op, b0, b1)
+    assert abs(b0) < 2.0, (op, b0, b1)
