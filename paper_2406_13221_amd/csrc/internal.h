@@ -60,7 +60,7 @@ struct NttExtra {
   const uint64_t* scale;
   const double* scalef;
   int out_digits;
-  // out_centered (primes of at most FP_MAX_BITS bits): the representative in
+  // out_centered: the representative in
   // [-(q-1)/2, (q-1)/2] instead of the canonical one; a double unless out_digits is set
   // (the form the rescale's spread reads)
   int out_centered;

@@ -399,9 +399,9 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
-              // the source's residue from its digits: canonical, or centred with |y| < 2^42 < q
+              // the source's residue from its digits: canonical, or centred (|y| < 2^63)
               const int64_t yi = digits_value(y[r]);
-              const uint64_t yr = yi < 0 ? (uint64_t)(yi + (int64_t)q) : (uint64_t)yi;
+              const uint64_t yr = yi >= 0 ? (uint64_t)yi : negmod(reduce64((uint64_t)(-yi), pc), q);
               const uint64_t v = x[g + r] + mul_shoup_lazy(yr, w, wsh, q);
               x[g + r] = v >= two_q ? v - two_q : v;
             }
@@ -446,8 +446,12 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
       const uint64_t sw = P.X.scale ? P.X.scale[2 * p] : pc.ninv;
       const uint64_t ssh = P.X.scale ? P.X.scale[2 * p + 1] : pc.ninv_sh;
       if (P.X.out_digits) {
+        const uint64_t half = P.X.out_centered ? (q - 1) / 2 : q;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) rb.st((mul_shoup(x[r], sw, ssh, q) + kDigitBias) ^ kDigitBias, vs, r * us);
+        for (int r = 0; r < 16; ++r) {
+          const uint64_t y = mul_shoup(x[r], sw, ssh, q);
+          rb.st(((y > half ? y - q : y) + kDigitBias) ^ kDigitBias, vs, r * us);  // y - q: two's complement
+        }
       } else {
 #pragma unroll
         for (int r = 0; r < 16; ++r) rb.st(mul_shoup(x[r], sw, ssh, q), vs, r * us);

@@ -233,13 +233,15 @@ void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, 
     launch_ks_rows(c->t, g.logN, k, s);
   }
   // 4. ModDown: INTT of the P rows of both parts (its first pass already done in step 3),
-  //    scaled by (P/p)^-1 ...
+  //    scaled by (P/p)^-1 and centred, so that the conversion's error u P has |u| <= n_p/2
+  //    about zero and the division by P rounds to nearest without a bias ...
   {
     NttExtra x{};
     x.rows_done = 1;
     x.scale = scale;
     x.scalef = scalef;
     x.out_digits = 1;
+    x.out_centered = 1;
     launch_ntt_ex(c->t, g.logN, rows_q(acc + (size_t)nl * N, count, (int64_t)2 * nx * N, 2, (int64_t)nx * N, np, nq),
                   true, x, s);
   }
