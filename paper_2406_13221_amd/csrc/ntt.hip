@@ -207,6 +207,17 @@ __device__ __forceinline__ uint64_t f_digits(double t) {
   return (as_u(t + 6755399441055744.0) + (kDigitBias - 0x4338000000000000ull)) ^ kDigitBias;
 }
 
+// Rows written by the base-conversion pass (k_conv_cols) are consumed only by the row pass that
+// follows it (the key-switch row pass, or the ModDown combine), so they use their own layout:
+// in the N1 x N2 view (N1 rows of N2 = 2^LOGS_row elements), element (b, c) sits at word
+//   tm(b, c) = ((c >> 3) * N1 + b) * 8 + (c & 7),
+// i.e. column tiles of 8 stored row after row.  A conversion workgroup (8 columns, all N1 rows)
+// then writes one contiguous block of whole cache lines, and a row-pass workgroup (8
+// consecutive rows) reads 512 contiguous bytes per column tile.
+__device__ __forceinline__ int64_t tm_word(int64_t b, int c, int n1) {
+  return (((int64_t)(c >> 3) * n1 + b) << 3) + (c & 7);
+}
+
 // ------------------------------------------------------------------ fused prologue / epilogue helpers
 // Workgroup index -> (unit, sub), sub fastest, such that the nsub workgroups of one unit
 // run on one XCD (workgroups are dispatched round-robin over the 8 XCDs), so data they
@@ -426,12 +437,14 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
 #pragma unroll
       for (int r = 0; r < 16; ++r) x[r] = lds[(16 * kg + r) * C + cl];
       stages_contig<LOGS, true>(x, tw, 1, kg, bf);
+      if (CONV) {
+        // tile-major output (tm_word): rows 16 kg + r of column c, 64 bytes apart
+        const uint32_t vt = (uint32_t)tm_word(16 * kg, c, S) * 8;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        if (CONV)
-          rb.st_nt(x[r], vc, r * uc);
-        else
-          rb.st(x[r], vc, r * uc);
+        for (int r = 0; r < 16; ++r) rb.st_nt(x[r], vt, r * 64);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) rb.st(x[r], vc, r * uc);
       }
     } else {
 #pragma unroll
@@ -651,9 +664,10 @@ __device__ __forceinline__ void convq_body(const NttParams& P, uint64_t* obase, 
     }
     stages_contig<LOGS, true>(x, tw, 1, kg, bf);
     if (act) {
-      const uint32_t o = ((uint32_t)ii << P.logN) * 8 + vc;
+      // tile-major output (tm_word): rows 16 kg + r of column c, 64 bytes apart
+      const uint32_t o = ((uint32_t)ii << P.logN) * 8 + (uint32_t)tm_word(16 * kg, c, S) * 8;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) ob.st_nt(as_u(x[r]), o, r * uc);
+      for (int r = 0; r < 16; ++r) ob.st_nt(as_u(x[r]), o, r * 64);
     }
   };
   pass(x0, t0, q0, qi0, t0 < nt, i0);
@@ -721,8 +735,15 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
     };
     double x[16];
     if (FWD) {
+      if (FUSE) {
+        // the conversion pass's tile-major rows (tm_word)
+        const uint64_t* t = src - (int64_t)b * S + (int64_t)b * 8;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) x[r] = as_f(src[j + T * r]);
+        for (int r = 0; r < 16; ++r) x[r] = as_f(t[tm_word(0, j + T * r, N1)]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[r] = as_f(src[j + T * r]);
+      }
       stages_strided<true>(x, tw, base, bf);
 #pragma unroll
       for (int r = 0; r < 16; ++r) l[fl ^ swz(j + T * r)] = as_u(x[r]);
@@ -810,8 +831,14 @@ __device__ __forceinline__ void rows_body(const NttParams& P, uint64_t* src, con
     };
     uint64_t x[16];
     if (FWD) {
+      if (FUSE) {
+        const uint64_t* t = src - (int64_t)b * S + (int64_t)b * 8;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) x[r] = src[j + T * r];
+        for (int r = 0; r < 16; ++r) x[r] = t[tm_word(0, j + T * r, N1)];
+      } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[r] = src[j + T * r];
+      }
       stages_strided<true>(x, tw, base, bf);
 #pragma unroll
       for (int r = 0; r < 16; ++r) l[fl ^ swz(j + T * r)] = x[r];
@@ -960,7 +987,8 @@ __device__ __forceinline__ void ksr_body(const KsrParams& P, int64_t ct, int x, 
   const int64_t pos0 = (int64_t)b * S;
   const int nx = K.nl + K.np, nqp = K.nq + K.np;
   const uint64_t* own = K.d.d + ct * K.d.cs + ((int64_t)x << P.logN);
-  const uint64_t* ex = K.ext + ct * K.ext_cs + pos0 + jt;
+  // extension rows in the conversion pass's tile-major layout (tm_word, N1 rows)
+  const uint64_t* ex = K.ext + ct * K.ext_cs + (int64_t)b * 8;
   const uint64_t* key = K.key + ((int64_t)gp << P.logN) + pos0 + jt;
   const int64_t kpart = (int64_t)nqp << P.logN, kdig = 2 * kpart;
   uint64_t* out = K.acc + ct * ((int64_t)(2 * nx) << P.logN) + ((int64_t)x << P.logN) + pos0 + jt;
@@ -1022,7 +1050,7 @@ __device__ __forceinline__ void ksr_body(const KsrParams& P, int64_t ct, int x, 
       asm volatile("" : "+s"(twk), "+v"(jk), "+v"(flk), "+v"(bk));
       double v[16];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) v[r] = as_f(src[T * r]);
+      for (int r = 0; r < 16; ++r) v[r] = as_f(src[tm_word(0, jk + T * r, N1)]);
       stages_strided<true>(v, twk, bk, bf);
 #pragma unroll
       for (int r = 0; r < 16; ++r) l[flk ^ swz(jk + T * r)] = as_u(v[r]);
@@ -1100,7 +1128,7 @@ __device__ __forceinline__ void ksr_body(const KsrParams& P, int64_t ct, int x, 
       asm volatile("" : "+s"(twk), "+v"(jk), "+v"(flk), "+v"(bk));
       uint64_t v[16];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) v[r] = src[T * r];
+      for (int r = 0; r < 16; ++r) v[r] = src[tm_word(0, jk + T * r, N1)];
       stages_strided<true>(v, twk, bk, bf);
 #pragma unroll
       for (int r = 0; r < 16; ++r) l[flk ^ swz(jk + T * r)] = v[r];
@@ -1290,7 +1318,12 @@ __device__ __forceinline__ void ksr8_body(const KsrParams& P, int64_t ct, int x,
   const int64_t pos0 = (int64_t)b * 256;
   const int nx = K.nl + K.np, nqp = K.nq + K.np;
   const uint64_t* own = K.d.d + ct * K.d.cs + ((int64_t)x << P.logN);
-  const uint64_t* ex = K.ext + ct * K.ext_cs + pos0 + j;
+  // extension rows in the conversion pass's tile-major layout (tm_word): element (b, j + 32 r) at
+  // word b*8 + (j >> 3)*8*N1 + (j & 7) + r * 32 N1 of its row; read as raw buffer loads with the
+  // lane part in a VGPR and the row and r parts uniform
+  const uint64_t* ex = K.ext + ct * K.ext_cs;
+  const uint32_t vex = (uint32_t)tm_word(b, j, N1) * 8u;
+  const uint32_t rstep = (uint32_t)N1 * 256u;  // bytes per r: 32 N1 words
   const uint64_t* key = K.key + ((int64_t)gp << P.logN) + pos0 + j;
   const int64_t kpart = (int64_t)nqp << P.logN, kdig = 2 * kpart;
   uint64_t* out = K.acc + ct * ((int64_t)(2 * nx) << P.logN) + ((int64_t)x << P.logN) + pos0 + j;
@@ -1341,13 +1374,13 @@ __device__ __forceinline__ void ksr8_body(const KsrParams& P, int64_t ct, int x,
     __syncthreads();  // the twiddle tables are in LDS
 #pragma unroll 1
     for (int k = 0; k < next; ++k) {
-      const uint64_t* src = ext_row(k);
+      const RowBuf src(ext_row(k));
       int jk = j, jqk = j >> 2;
       uint32_t oAk = oA, oBk = oB, oCk = oC;
       asm volatile("" : "+v"(jk), "+v"(jqk), "+v"(oAk), "+v"(oBk), "+v"(oCk));
       double v[8];
 #pragma unroll
-      for (int r = 0; r < 8; ++r) v[r] = as_f(src[32 * r]);
+      for (int r = 0; r < 8; ++r) v[r] = as_f(src.ld(vex, r * rstep));
       st8T_A<true>(v, T, bf);
 #pragma unroll
       for (int r = 0; r < 8; ++r) lds_word(lds, oAk ^ sw8A(r)) = as_u(v[r]);
@@ -1428,7 +1461,7 @@ __device__ __forceinline__ void ksr8_body(const KsrParams& P, int64_t ct, int x,
     }
 #pragma unroll 1
     for (int k = 0; k < next; ++k) {
-      const uint64_t* src = ext_row(k);
+      const RowBuf src(ext_row(k));
       const U2* twk = tw;
       int jk = j, ak = a;
       int64_t bk = base;
@@ -1436,7 +1469,7 @@ __device__ __forceinline__ void ksr8_body(const KsrParams& P, int64_t ct, int x,
       asm volatile("" : "+s"(twk), "+v"(jk), "+v"(ak), "+v"(bk), "+v"(oAk), "+v"(oBk), "+v"(oCk));
       uint64_t v[8];
 #pragma unroll
-      for (int r = 0; r < 8; ++r) v[r] = src[32 * r];
+      for (int r = 0; r < 8; ++r) v[r] = src.ld(vex, r * rstep);
       st8_A<true>(v, twk, bk, bf);
 #pragma unroll
       for (int r = 0; r < 8; ++r) lds_word(lds, oAk ^ sw8A(r)) = v[r];
