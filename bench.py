@@ -14,6 +14,7 @@ row-pass roofline measured live with sampled HIP events, and the CPU oracle
 timed on a bounded sample of the same workload).
 """
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -137,19 +138,74 @@ def pmc_traffic(avg_rows):
         return None
 
 
+def auroc(score, y):
+    """Area under the ROC curve as the rank statistic (ties at mid-rank)."""
+    from scipy.stats import rankdata
+    r = rankdata(score)
+    npos = int(y.sum())
+    return float((r[y == 1].sum() - npos * (npos + 1) / 2.0) / (npos * (len(y) - npos)))
+
+
 def loglik_auroc(Xv, yv, w):
-    """Mean log-likelihood (section 2.3) and AUROC (rank statistic, ties at mid-rank) of the decrypted
-    model w (bias first) on validation rows."""
+    """Mean log-likelihood (section 2.3) and AUROC of the decrypted model w (bias first) on validation rows."""
     import numpy as np
     score = w[0] + Xv @ w[1:Xv.shape[1] + 1]
     ypm = 2.0 * yv - 1.0
     ll = -float(np.mean(np.logaddexp(0.0, -ypm * score)))
-    from scipy.stats import rankdata
-    ranks = rankdata(score)
-    npos = int(yv.sum())
-    nneg = len(yv) - npos
-    auc = (ranks[yv == 1].sum() - npos * (npos + 1) / 2.0) / (npos * nneg)
-    return ll, float(auc)
+    return ll, auroc(score, yv)
+
+
+def scoring_leg(run, cfg, data, level=2, sample_blocks=64):
+    """Encrypted validation scoring: the client encrypts the validation rows [1 | X | 0] (no labels) at
+    `level` (one product and the row-sum rotations need no more), the cloud computes every row's score
+    x-hat . w under the encrypted model (heqg_score); timed over all rows; a sample of row blocks is
+    decrypted and compared with the plaintext scores of the decrypted model."""
+    import numpy as np
+    import torch
+    from paper_2406_13221_amd import heqg
+    from paper_2406_13221_amd.train import pack_grid
+    ctx, keys, m, g = run.ctx, run.keys, run.m, run.g
+    Xv, yv = data["Xv"], data["yv"]
+    n, f = Xv.shape
+    Xh = np.zeros((n, run.width))
+    Xh[:, 0] = 1.0
+    Xh[:, 1:f + 1] = Xv
+    blocks = pack_grid(Xh, m, g)
+    nb = blocks.shape[0]
+    t0 = time.perf_counter()
+    cts = heqg.Cts(torch.empty((nb, 2, level + 1, ctx.N), dtype=torch.int64, device="cuda"), level, ctx.delta)
+    ws = heqg._ws(heqg.lib().heqg_enc_ws_bytes(ctx.h, 256))
+    for b0 in range(0, nb, 256):
+        b1 = min(nb, b0 + 256)
+        dev = torch.from_numpy(ctx.encode_batch(blocks[b0:b1], ctx.delta)).cuda()
+        ob = heqg.Cts(cts.data[b0:b1], level, ctx.delta).batch()
+        heqg._check(heqg.lib().heqg_encrypt(ctx.h, keys.handle, dev.data_ptr(), cfg["enc_seed"] + 300, b0,
+                                            ctypes.byref(ob), ws.data_ptr(), ws.numel(), heqg._stream()))
+    del ws
+    torch.cuda.synchronize()
+    t_enc = time.perf_counter() - t0
+    W2 = ctx.drop(run.W, level)
+    ctx.score(keys, heqg.Cts(cts.data[:run.batch * run.nc], level, ctx.delta), W2, g, col_blocks=run.nc,
+              batch=run.batch, ws=run.ws)     # warm-up on one chunk
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sc = ctx.score(keys, cts, W2, g, col_blocks=run.nc, batch=run.batch, ws=run.ws)
+    torch.cuda.synchronize()
+    t_score = time.perf_counter() - t0
+    w = run.weights(f + 1)
+    nsb = min(sample_blocks, sc.count)
+    got = np.concatenate([ctx.decrypt_values(keys, sc, index=i).reshape(m, g)[:, 0] for i in range(nsb)])
+    rows = min(n, nsb * m)
+    ref = Xh[:rows, :f + 1] @ w
+    res = {"rows": n, "row_blocks": sc.count, "ciphertexts_in": int(cts.count), "level": level,
+           "encrypt_s": round(t_enc, 3), "score_s": round(t_score, 4),
+           "rows_per_s": round(n / t_score, 1), "sample_rows": rows,
+           "sample_max_abs_err": float(np.abs(got[:rows] - ref).max()),
+           "sample_auroc_encrypted": round(auroc(got[:rows], yv[:rows]), 6),
+           "sample_auroc_plain": round(auroc(ref, yv[:rows]), 6)}
+    del cts, sc
+    torch.cuda.empty_cache()
+    return res
 
 
 def mnist_leg(steps, batch):
@@ -200,8 +256,12 @@ def main():
                     help="timed iterations of the same task over 1,024 x 32 blocks (7 column blocks, section 2.2)")
     ap.add_argument("--mnist-steps", type=int, default=3,
                     help="iterations of the MNIST-shaped task (section 5.2), quadratic gradient and first-order NAG")
+    ap.add_argument("--no-score", dest="score", action="store_false",
+                    help="skip encrypted scoring of the validation rows")
     ap.add_argument("--mode", default="train", choices=["train", "ntt"],
                     help="ntt: only the batched forward NTT (768 limbs) and a 1 GiB device copy, for counters")
+    ap.add_argument("--no-ntt-probe", dest="ntt_probe", action="store_false",
+                    help="skip the full-batch NTT throughput leg (keeps per-kernel profiles to the iteration)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with a 1 GiB device copy (the scale of HBM byte counters in a profiled run)")
     args = ap.parse_args()
@@ -355,33 +415,38 @@ def main():
     # ciphertexts (3,298 x 2 x 24 rows, 40- and 60-bit primes, 83 GB: far past the caches), transformed
     # in place forward and then back, which restores Z exactly; bytes = read once + written once per limb
     N = run.ctx.N
-    zrows = run.Z.data.view(-1, N)
-    nrows = zrows.shape[0]
-    for _ in range(1):
-        run.ctx.ntt(zrows, 0, run.ctx.n_q)
-        run.ctx.ntt(zrows, 0, run.ctx.n_q, inverse=True)
-    e0, e1, e2 = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    reps = 2
-    e0.record()
-    for _ in range(reps):
-        run.ctx.ntt(zrows, 0, run.ctx.n_q)
-        run.ctx.ntt(zrows, 0, run.ctx.n_q, inverse=True)
-    e1.record()
-    torch.cuda.synchronize()
-    e1b, e2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e1b.record()
-    for _ in range(reps):
-        run.ctx.ntt(zrows, 0, run.ctx.n_q)
-    e2.record()
-    torch.cuda.synchronize()
-    for _ in range(reps):
-        run.ctx.ntt(zrows, 0, run.ctx.n_q, inverse=True)
-    torch.cuda.synchronize()
-    ntt_bytes = 16.0 * N * nrows
-    fwd_s = e1b.elapsed_time(e2) * 1e-3 / reps
-    both_s = e0.elapsed_time(e1) * 1e-3 / reps
-    fwd_gbs = ntt_bytes / fwd_s / 1e9
-    inv_gbs = ntt_bytes / max(both_s - fwd_s, 1e-9) / 1e9
+    ntt_gbps = None
+    if args.ntt_probe:
+        zrows = run.Z.data.view(-1, N)
+        nrows = zrows.shape[0]
+        for _ in range(1):
+            run.ctx.ntt(zrows, 0, run.ctx.n_q)
+            run.ctx.ntt(zrows, 0, run.ctx.n_q, inverse=True)
+        e0, e1, e2 = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        reps = 2
+        e0.record()
+        for _ in range(reps):
+            run.ctx.ntt(zrows, 0, run.ctx.n_q)
+            run.ctx.ntt(zrows, 0, run.ctx.n_q, inverse=True)
+        e1.record()
+        torch.cuda.synchronize()
+        e1b, e2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e1b.record()
+        for _ in range(reps):
+            run.ctx.ntt(zrows, 0, run.ctx.n_q)
+        e2.record()
+        torch.cuda.synchronize()
+        for _ in range(reps):
+            run.ctx.ntt(zrows, 0, run.ctx.n_q, inverse=True)
+        torch.cuda.synchronize()
+        ntt_bytes = 16.0 * N * nrows
+        fwd_s = e1b.elapsed_time(e2) * 1e-3 / reps
+        both_s = e0.elapsed_time(e1) * 1e-3 / reps
+        fwd_gbs = ntt_bytes / fwd_s / 1e9
+        inv_gbs = ntt_bytes / max(both_s - fwd_s, 1e-9) / 1e9
+        ntt_gbps = {"forward": round(fwd_gbs, 1), "inverse": round(inv_gbs, 1), "limbs_per_call": nrows,
+                    "bytes_per_call": ntt_bytes, "frac_of_hbm_peak": round(fwd_gbs / HBM_PEAK_GBS, 4),
+                    "batch": "every limb of the iteration's ciphertexts (blocks x 2 parts x limbs), in place"}
 
     w = run.weights(cfg["n_features"] + 1)
     n_blocks = run.Z.count
@@ -451,9 +516,7 @@ def main():
                    "rows_per_block": cfg["m"], "cols": cfg["g"], "batch_blocks": run.batch},
         "update_s": round(upd, 4),
         "refresh_s": round(ref, 5),
-        "ntt_gbps": {"forward": round(fwd_gbs, 1), "inverse": round(inv_gbs, 1), "limbs_per_call": nrows,
-                     "bytes_per_call": ntt_bytes, "frac_of_hbm_peak": round(fwd_gbs / HBM_PEAK_GBS, 4),
-                     "batch": "every limb of the iteration's ciphertexts (blocks x 2 parts x limbs), in place"},
+        "ntt_gbps": ntt_gbps,
         "roofline": roofline,
         "conv_pass_roofline": conv_roofline,
         "ntt_row_pass_roofline": ntt_row_roofline,
@@ -463,6 +526,14 @@ def main():
         "learned_sigmoid": learned,
         "tuning": tuning,
     }
+    # encrypted validation scoring (844,217 rows) with the trained model
+    scoring = None
+    if args.score:
+        scoring = scoring_leg(run, cfg, data)
+        log("encrypted scoring of %d validation rows: %.3f s; sample AUROC %.5f (plain %.5f)" %
+            (scoring["rows"], scoring["score_s"], scoring["sample_auroc_encrypted"], scoring["sample_auroc_plain"]))
+    out["validation_scoring"] = scoring
+
     # the same task over the 1,024 x 32 partition of section 2.2 (7 column blocks; 10x fewer key
     # switches per iteration), trained for as many iterations as the run above from the same start:
     # its decrypted model against the 128 x 256 run's

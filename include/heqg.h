@@ -145,6 +145,19 @@ size_t heqg_keygen_ws_bytes(const heqg_ctx* ctx);
  */
 int heqg_keygen(heqg_ctx* ctx, uint64_t seed, const int* rot_steps, int n_rot, void* dev_keys, size_t bytes,
                 void* ws, size_t ws_bytes, heqg_keys** out, hipStream_t stream);
+/*
+ * heqg_keygen with a choice of secret and the conjugation key (bootstrapping):
+ * hamming = 0 gives the uniform ternary secret of heqg_keygen; hamming = h > 0
+ * a sparse ternary secret of exactly h nonzero coefficients (positions from
+ * word pairs (2i, 2i+1) of the stream (seed, 0x5350415253450000, 0, lane 0):
+ * a mod N when a lies below the largest multiple of N in 2^64 and the position
+ * is free; sign -1 when bit 63 of the second word is set).  conj != 0 adds the
+ * switching key of X -> X^(2N-1) (complex conjugation of the slots) after the
+ * rotation keys; size the key buffer with heqg_keys_bytes(ctx, n_rot + 1).
+ * Synchronises the stream while sampling a sparse secret.
+ */
+int heqg_keygen_ex(heqg_ctx* ctx, uint64_t seed, int hamming, int conj, const int* rot_steps, int n_rot,
+                   void* dev_keys, size_t bytes, void* ws, size_t ws_bytes, heqg_keys** out, hipStream_t stream);
 /* Releases the handle and every graph of the context captured with it; call before heqg_ctx_destroy. */
 void heqg_keys_destroy(heqg_keys* keys);
 /* Number of rotation keys held and their Galois elements (host array of that length, may be NULL). */
@@ -557,8 +570,100 @@ int heqg_nag_qg_graph(heqg_ctx* ctx, const heqg_keys* keys, const heqg_ct_batch*
                       heqg_ct* W, heqg_ct* V, const heqg_sigmoid* sig, heqg_nag_state* st, int batch, void* ws,
                       size_t ws_bytes, hipStream_t stream);
 int heqg_graph_clear(heqg_ctx* ctx);
+
+/*
+ * Encrypted scoring of validation rows with the encrypted model (the
+ * accuracy and AUROC of sections 5.1 and 5.2, here from encrypted scores):
+ * X holds rows of [1 | X | 0] (no labels) in the m x g_cols partition of
+ * section 2.2, row block i and column block j at ciphertext i*col_blocks + j;
+ * W holds col_blocks ciphertexts back to back.  For every row block,
+ * u = Rescale(Relin(sum_j X_ij (x) W_j)) and u += Rot(u, 2^k) for
+ * k < log2 g_cols, which leaves each row's score x-hat . w in its column 0;
+ * out (one ciphertext per row block, out->level = min(X, W level) - 1, set by
+ * the caller) receives u and out->scale is written.  `batch` row blocks per
+ * launch (col_blocks <= batch); workspace: heqg_nag_ws_bytes(ctx, batch, 3).
+ */
+int heqg_score(heqg_ctx* ctx, const heqg_keys* keys, const heqg_ct_batch* X, const heqg_ct* W, int col_blocks,
+               int g_cols, heqg_ct_batch* out, int batch, void* ws, size_t ws_bytes, hipStream_t stream);
 /* Number of instantiated graphs the context holds (a key set's graphs go with heqg_keys_destroy). */
 int heqg_graph_count(const heqg_ctx* ctx);
+
+/* ------------------------------------------------------------------ */
+/* Bootstrapping (section 2.1's bootstrap; the refresh of section 4.3,  */
+/* step 7; Table 1: one iteration per bootstrapping)                    */
+/* ------------------------------------------------------------------ */
+
+/*
+ * The scheme's bootstrap in the full-RNS form of Cheon, Han, Kim, Kim and
+ * Song, which the paper takes from HEAAN: a level-0 two-part ciphertext ->
+ * the same message at level stc_level - 1 (heqg_boot_shape), without the
+ * secret key.  Its steps, each also an entry point:
+ *   ModRaise     the centred coefficients mod q0 read at the top level
+ *                (decrypts to t = m + q0 I, I a small integer polynomial);
+ *   CoeffToSlot  slots -> (2/N) U0^H slots, U0[j][k] = zeta_j^k,
+ *                zeta_j = exp(i pi 5^j / N): t's low and high coefficient
+ *                halves over the scale become the real and imaginary parts;
+ *   split        2 Re = w + conj(w), 2 Im = i (conj(w) - w) (the conjugation
+ *                key; i is the monomial X^(N/2)), inside heqg_bootstrap;
+ *   EvalMod      x -> (t mod q0) / s for real slots x = t / s:
+ *                v = (half x s / q0 - 1/4) / 2^r, the cosine's Taylor
+ *                polynomial of the given degree in y = v^2 evaluated as
+ *                B0(y) + y^4 B1(y) + y^8 B2(y), r double angles
+ *                c <- 2 c^2 - 1 (giving sin(2 pi t / q0)), times q0 / (2 pi s);
+ *                level cost 7 + r;
+ *   SlotToCoeff  slots -> U0 slots.
+ * The slot transforms are baby-step giant-step products
+ * sum_g Rot(sum_b P[g][b] (.) Rot(x, b), n1 g), n1 n2 = N/2, with the
+ * plaintext P[g][b] = diagonal n1 g + b of the matrix rotated right by n1 g,
+ * encoded at scale q_level of the transform's input level so that the one
+ * rescale returns the input scale.  The keys need the rotations
+ * heqg_boot_steps lists and the conjugation (heqg_keygen_ex with conj); a
+ * sparse secret (weight 64 with r = 5 and degree 20) keeps |I| within the
+ * interval of 16 that EvalMod covers.  Every step is the scheme's operation on
+ * exact residues with the oracle's level and scale bookkeeping (the same
+ * sequence of FP64 operations), so results are reproducible residue for
+ * residue.  The dense diagonals take (n1 n2) plaintexts per transform: meant
+ * for ring degrees up to 2^13 or so.
+ *
+ * heqg_boot_steps: writes the rotation steps to steps (may be NULL) and
+ * returns their number.
+ * heqg_boot_shape: n1, n2 and the input levels of CoeffToSlot (the top) and
+ * SlotToCoeff for r double angles; HEQG_ERR_LEVEL when the chain is too short.
+ * heqg_boot_encode (host): the transforms' plaintexts in coefficient form into
+ * coeffs[2 n1 n2 + 1][N]: CoeffToSlot's P[g][b] (index n1 g + b), then
+ * SlotToCoeff's, then X^(N/2); over `threads` host threads (<= 0: all).
+ * heqg_boot_setup: loads such coefficients (device int64, same layout) into
+ * dev (>= heqg_boot_bytes) in NTT form; the handle refers to dev, which the
+ * caller owns; heqg_boot_destroy frees the handle only.
+ * Each evaluation call takes a workspace of heqg_boot_ws_bytes(ctx, count)
+ * and a batch of count two-part ciphertexts; out->scale is written:
+ *   heqg_mod_raise      in level 0 -> out at the top level (no keys);
+ *   heqg_coeff_to_slot  in at the top level -> out one level lower;
+ *   heqg_eval_mod       in at level l >= 7 + r -> out at l - 7 - r, scale kept;
+ *   heqg_slot_to_coeff  in at stc_level -> out at stc_level - 1;
+ *   heqg_bootstrap      in level 0 -> out at stc_level - 1.
+ * HEQG_ERR_ARG for a wrong level, shape or workspace; HEQG_ERR_KEY when a
+ * rotation or the conjugation key is missing.
+ */
+typedef struct heqg_boot heqg_boot;
+int heqg_boot_steps(const heqg_ctx* ctx, int* steps);
+int heqg_boot_shape(const heqg_ctx* ctx, int r, int* n1, int* n2, int* cts_level, int* stc_level);
+int heqg_boot_encode(const heqg_ctx* ctx, int r, int64_t* coeffs, int threads);
+size_t heqg_boot_bytes(const heqg_ctx* ctx, int r);
+int heqg_boot_setup(heqg_ctx* ctx, const int64_t* dev_coeffs, int r, int taylor, void* dev, size_t bytes,
+                    heqg_boot** out, hipStream_t stream);
+void heqg_boot_destroy(heqg_boot* boot);
+size_t heqg_boot_ws_bytes(const heqg_ctx* ctx, int64_t count);
+int heqg_mod_raise(heqg_ctx* ctx, const heqg_ct_batch* in, heqg_ct_batch* out, void* ws, size_t ws_bytes,
+                   hipStream_t stream);
+int heqg_coeff_to_slot(heqg_ctx* ctx, const heqg_keys* keys, const heqg_boot* boot, const heqg_ct_batch* in,
+                       heqg_ct_batch* out, void* ws, size_t ws_bytes, hipStream_t stream);
+int heqg_eval_mod(heqg_ctx* ctx, const heqg_keys* keys, const heqg_boot* boot, const heqg_ct_batch* in, double half,
+                  heqg_ct_batch* out, void* ws, size_t ws_bytes, hipStream_t stream);
+int heqg_slot_to_coeff(heqg_ctx* ctx, const heqg_keys* keys, const heqg_boot* boot, const heqg_ct_batch* in,
+                       heqg_ct_batch* out, void* ws, size_t ws_bytes, hipStream_t stream);
+int heqg_bootstrap(heqg_ctx* ctx, const heqg_keys* keys, const heqg_boot* boot, const heqg_ct_batch* in,
+                   heqg_ct_batch* out, void* ws, size_t ws_bytes, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -141,6 +141,22 @@ def u0_matrix(N):
     return np.exp(1j * np.pi * np.outer(e, k) / N)
 
 
+def diagonal_plaintexts(ora, A, lv):
+    """The coefficient forms of the baby-step giant-step plaintexts of A for input level lv:
+    entry n1 g + b is diagonal d = n1 g + b of A (diag_d[j] = A[j][(j + d) mod n]) rotated right by
+    n1 g, encoded at scale q_lv."""
+    n = ora.N // 2
+    n1, n2 = bsgs_split(n)
+    ql = float(ora.q(lv))
+    idx = np.arange(n)
+    out = np.zeros((n1 * n2, ora.N), dtype=np.int64)
+    for d in range(n1 * n2):
+        g = d // n1
+        diag = A[idx, (idx + d) % n]
+        out[d] = encode(np.roll(diag, n1 * g), ora.N, ql)   # Rot(diag_d, -n1 g)
+    return out
+
+
 def linear(ora, ct, A):
     """Slots x -> A x (A an N/2 x N/2 complex matrix), one level: diagonal plaintexts encoded at
     scale q_level, products summed at scale s q_level, one rescale at the end."""
@@ -150,16 +166,13 @@ def linear(ora, ct, A):
     if lv < 1:
         raise OracleError("level exhausted")
     ql = float(ora.q(lv))
-    idx = np.arange(n)
+    pts = diagonal_plaintexts(ora, A, lv)
     xb = [ct] + [ora.rotate(ct, b) for b in range(1, n1)]
     total = None
     for g in range(n2):
         inner = None
         for b in range(n1):
-            d = n1 * g + b
-            diag = A[idx, (idx + d) % n]
-            shifted = np.roll(diag, n1 * g)          # Rot(diag_d, -n1 g)
-            pt = ora.pt_from_int(encode(shifted, ora.N, ql), lv)
+            pt = ora.pt_from_int(pts[n1 * g + b], lv)
             prod = ora.mul_pt(xb[b], pt, ql)
             inner = prod if inner is None else ora.add(inner, prod)
         if g:
@@ -170,13 +183,29 @@ def linear(ora, ct, A):
     return out
 
 
+def cts_matrix(N):
+    """CoeffToSlot's map (2/N) U0^H."""
+    return (2.0 / N) * u0_matrix(N).conj().T
+
+
 def coeff_to_slot(ora, ct):
-    U0 = u0_matrix(ora.N)
-    return linear(ora, ct, (2.0 / ora.N) * U0.conj().T)
+    return linear(ora, ct, cts_matrix(ora.N))
 
 
 def slot_to_coeff(ora, ct):
     return linear(ora, ct, u0_matrix(ora.N))
+
+
+def transform_plaintexts(ora, evalmod=None):
+    """Every plaintext the slot transforms of bootstrap() use, [2 n1 n2 + 1][N] int64: CoeffToSlot's
+    at the top level, SlotToCoeff's at the level EvalMod leaves, then X^(N/2)."""
+    em = evalmod or EvalMod()
+    top = ora.top_level
+    stc = top - 1 - em.levels()
+    mono = np.zeros((1, ora.N), dtype=np.int64)
+    mono[0, ora.N // 2] = 1
+    return np.concatenate([diagonal_plaintexts(ora, cts_matrix(ora.N), top),
+                           diagonal_plaintexts(ora, u0_matrix(ora.N), stc), mono])
 
 
 class EvalMod:

@@ -7,7 +7,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libheqg.so")
-SOURCES = ["ntt.hip", "kernels.hip", "sigfit.hip", "nag.cpp", "ops.cpp", "ctx.cpp", "api.cpp", "client.cpp", "noalloc.cpp"]
+SOURCES = ["ntt.hip", "kernels.hip", "sigfit.hip", "nag.cpp", "ops.cpp", "ctx.cpp", "api.cpp", "client.cpp", "noalloc.cpp",
+           "boot.cpp"]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
     # packed FP32 instructions are kept out of every kernel

@@ -88,16 +88,23 @@ static uint64_t galois_of(const heqg_ctx* c, int step) {
 
 extern "C" int heqg_keygen(heqg_ctx* c, uint64_t seed, const int* rot_steps, int n_rot, void* dev_keys, size_t bytes,
                            void* ws, size_t ws_bytes, heqg_keys** out, hipStream_t s) {
-  if (!c || !dev_keys || !out || (n_rot > 0 && !rot_steps) || n_rot < 0) {
+  return heqg_keygen_ex(c, seed, 0, 0, rot_steps, n_rot, dev_keys, bytes, ws, ws_bytes, out, s);
+}
+
+extern "C" int heqg_keygen_ex(heqg_ctx* c, uint64_t seed, int hamming, int conj, const int* rot_steps, int n_rot,
+                              void* dev_keys, size_t bytes, void* ws, size_t ws_bytes, heqg_keys** out,
+                              hipStream_t s) {
+  if (!c || !dev_keys || !out || (n_rot > 0 && !rot_steps) || n_rot < 0 || hamming < 0 || hamming > c->g.N) {
     set_err("keygen: bad argument");
     return HEQG_ERR_ARG;
   }
-  // distinct Galois elements, in order of first appearance
+  // distinct Galois elements, in order of first appearance (then the conjugation X -> X^(2N-1))
   std::vector<uint64_t> gal;
   for (int i = 0; i < n_rot; ++i) {
     uint64_t t = galois_of(c, rot_steps[i]);
     if (t != 1 && std::find(gal.begin(), gal.end(), t) == gal.end()) gal.push_back(t);
   }
+  if (conj) gal.push_back(2 * (uint64_t)c->g.N - 1);
   if (bytes < heqg_keys_bytes(c, (int)gal.size()) || !ws || ws_bytes < heqg_keygen_ws_bytes(c)) {
     set_err("keygen: key or workspace buffer too small");
     return HEQG_ERR_ARG;
@@ -114,7 +121,7 @@ extern "C" int heqg_keygen(heqg_ctx* c, uint64_t seed, const int* rot_steps, int
   k->key_words = key_words(c);
   static std::atomic<uint64_t> next_gen{0};
   k->gen = ++next_gen;
-  int rc = ops::keygen(c, k, seed, static_cast<uint8_t*>(ws), s);
+  int rc = ops::keygen(c, k, seed, static_cast<uint8_t*>(ws), s, hamming);
   if (rc != HEQG_OK) {
     delete k;
     return rc;
@@ -567,18 +574,8 @@ extern "C" int heqg_add_const(heqg_ctx* c, const heqg_ct_batch* in, double cst, 
     set_err("add_const: output shape mismatch");
     return HEQG_ERR_ARG;
   }
-  const double v = cst * in->scale;
-  if (!(std::fabs(v) < 4611686018427387904.0)) {
-    set_err("add_const: constant times scale reaches 2^62");
-    return HEQG_ERR_OVERFLOW;
-  }
-  const int64_t kint = std::llround(v);  // ties away from zero
-  std::vector<uint64_t> kr(in->level + 1);
-  for (int i = 0; i <= in->level; ++i) {
-    const uint64_t q = c->primes[i];
-    kr[i] = kint < 0 ? (q - (uint64_t)((unsigned __int128)(-(__int128)kint) % q)) % q : (uint64_t)kint % q;
-  }
-  k_add_scalar_launch(c->g, c->t, view_of(c, in), view_of(c, out), in->count, in->n_poly, in->level + 1, kr.data(), s);
+  int rc = ops::add_const(c, view_of(c, in), in->count, in->n_poly, in->level, in->scale, cst, view_of(c, out), s);
+  if (rc) return rc;
   out->scale = in->scale;
   return HEQG_OK;
 }

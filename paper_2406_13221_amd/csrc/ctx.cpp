@@ -387,11 +387,8 @@ static void fft(std::vector<std::complex<double>>& a, const std::vector<std::com
   }
 }
 
-extern "C" int heqg_encode(const heqg_ctx* c, const double* v, size_t n, double scale, int64_t* coeffs) {
-  if (!c || (!v && n) || !coeffs) {
-    set_err("encode: null argument");
-    return HEQG_ERR_ARG;
-  }
+// complex slot values z[0..n) -> coeffs[j] = round(scale * tau^-1(z)_j), ties away from zero
+int encode_slots(const heqg_ctx* c, const std::complex<double>* z, size_t n, double scale, int64_t* coeffs) {
   const size_t N = (size_t)c->g.N;
   if (n > N / 2) {
     set_err("encode: more values than slots");
@@ -400,8 +397,8 @@ extern "C" int heqg_encode(const heqg_ctx* c, const double* v, size_t n, double 
   // values at the odd powers zeta^(2u+1): slot k sits at u = (5^k - 1)/2, its conjugate at N-1-u
   std::vector<std::complex<double>> P(N, 0.0);
   for (size_t k = 0; k < n; ++k) {
-    P[c->slot_pos[k]] = v[k];
-    P[N - 1 - c->slot_pos[k]] = v[k];
+    P[c->slot_pos[k]] = z[k];
+    P[N - 1 - c->slot_pos[k]] = std::conj(z[k]);
   }
   fft(P, c->fft_roots, false);
   std::vector<int64_t> out(N);
@@ -416,6 +413,15 @@ extern "C" int heqg_encode(const heqg_ctx* c, const double* v, size_t n, double 
   }
   std::memcpy(coeffs, out.data(), N * sizeof(int64_t));
   return HEQG_OK;
+}
+
+extern "C" int heqg_encode(const heqg_ctx* c, const double* v, size_t n, double scale, int64_t* coeffs) {
+  if (!c || (!v && n) || !coeffs) {
+    set_err("encode: null argument");
+    return HEQG_ERR_ARG;
+  }
+  std::vector<std::complex<double>> z(v, v + n);
+  return encode_slots(c, z.data(), n, scale, coeffs);
 }
 
 extern "C" int heqg_encode_batch(const heqg_ctx* c, const double* v, size_t n, int64_t count, double scale,

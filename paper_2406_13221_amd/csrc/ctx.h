@@ -55,3 +55,6 @@ int ctx_build(heqg_ctx* c, void* dev, size_t bytes, std::string* err);
 void set_err(const std::string& s);
 // Looks up the allocation-free entry point's device array on the current device (noalloc.cpp).
 void noalloc_setup_current_device();
+// Complex slot values -> N integer coefficients (the canonical embedding's inverse times scale,
+// rounded ties away from zero); heqg_encode is the real case (ctx.cpp).
+int encode_slots(const heqg_ctx* c, const std::complex<double>* z, size_t n, double scale, int64_t* coeffs);

@@ -182,6 +182,11 @@ void k_add_scalar_launch(const Geo& g, const DevTables& t, CtV a, CtV out, int64
 constexpr int kWriteWords = 240;
 void k_write_words_launch(uint64_t* dst, const uint64_t* src, size_t n, hipStream_t s);
 void k_copy_launch(const Geo& g, CtV a, CtV out, int64_t count, int n_poly, int nl, hipStream_t s);
+void k_mul_pt_sum_launch(const Geo& g, const DevTables& t, CtV x, int64_t xs, const uint64_t* pt, int64_t pts,
+                         int nterms, CtV out, int64_t count, int nl, hipStream_t s);
+void k_center0_launch(const DevTables& t, const uint64_t* in, int64_t n, int64_t* out, hipStream_t s);
+void k_stream_words_launch(uint64_t seed, uint64_t purpose, uint64_t obj, uint32_t lane, uint64_t first_block,
+                           int64_t n_blocks, uint64_t* out, hipStream_t s);
 void k_automorph_launch(const Geo& g, CtV a, CtV out, int64_t count, int n_poly, int nl, uint64_t galois,
                         hipStream_t s);
 void k_rescale_spread_launch(const Geo& g, const DevTables& t, const uint64_t* last, uint64_t* spread, int64_t rows,
@@ -191,6 +196,7 @@ void k_rescale_combine_launch(const Geo& g, const DevTables& t, CtV in, const ui
 // out = [addend +] base + KS result; with galois != 1 base0 is gathered through X -> X^galois
 // sampling / encryption
 enum { PUR_SK = 1, PUR_PK_A = 2, PUR_PK_E = 3, PUR_KSK_A = 4, PUR_KSK_E = 5, PUR_ENC_V = 6, PUR_ENC_E0 = 7, PUR_ENC_E1 = 8 };
+constexpr uint64_t PUR_SPARSE = 0x5350415253450000ull;  // the sparse secret's positions and signs
 void k_sample_small_launch(uint64_t seed, uint64_t purpose, uint64_t obj_first, int64_t count, int N, int kind,
                            int64_t* out, hipStream_t s);  // kind 0 ternary, 1 CBD(21)
 void k_small_to_rows_launch(const Geo& g, const DevTables& t, const int64_t* in, int64_t in_stride, int64_t count,

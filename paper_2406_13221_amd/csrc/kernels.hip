@@ -174,6 +174,39 @@ __global__ void __launch_bounds__(EW_THREADS) k_tensor_reduce(const PrimeConst* 
 }
 
 // ------------------------------------------------------------------ plaintext / scalar products
+// out = sum_{b < nterms} x_b (.) pt_b over the two parts of `count` ciphertexts; x_b at x.d + b * xs
+// (ciphertext stride x.cs), pt_b (rows 0..nl-1 of N words) at pt + b * pts
+__global__ void __launch_bounds__(EW_THREADS) k_mul_pt_sum(const PrimeConst* pc, CtV x, int64_t xs,
+                                                            const uint64_t* pt, int64_t pts, int nterms, CtV out,
+                                                            int logN, int nl) {
+  const int chunks = (1 << logN) / EW_CHUNK;
+  int64_t bid = blockIdx.x;
+  int ch = (int)(bid % chunks);
+  int64_t row = bid / chunks;
+  int i = (int)(row % nl);
+  int64_t r2 = row / nl;
+  int part = (int)(r2 % 2);
+  int64_t ct = r2 / 2;
+  int64_t off = ((int64_t)i << logN) + ch * EW_CHUNK + threadIdx.x * 2;
+  const PrimeConst P = pc[i];
+  uint64_t sa = 0, sb = 0;
+  for (int b = 0; b < nterms; ++b) {
+    U2 v = ld2(x.d + b * xs + ct * x.cs + part * x.ps + off);
+    U2 w = ld2(pt + b * pts + off);
+    sa = addmod(sa, mulmod(v.a, w.a, P), P.q);
+    sb = addmod(sb, mulmod(v.b, w.b, P), P.q);
+  }
+  st2(out.d + ct * out.cs + part * out.ps + off, sa, sb);
+}
+
+// centred lift of residues mod prime 0 (rows of N words) to signed integers
+__global__ void __launch_bounds__(EW_THREADS) k_center0(const PrimeConst* pc, const uint64_t* in, int64_t n,
+                                                         int64_t* out) {
+  int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n) return;
+  const uint64_t q = pc[0].q, v = in[gid];
+  out[gid] = v > (q - 1) / 2 ? (int64_t)v - (int64_t)q : (int64_t)v;
+}
 __global__ void __launch_bounds__(EW_THREADS) k_mul_pt(const PrimeConst* pc, CtV a, const uint64_t* pt, CtV out,
                                                         int logN, int nl, int n_poly) {
   const int chunks = (1 << logN) / EW_CHUNK;
@@ -397,6 +430,19 @@ __global__ void __launch_bounds__(EW_THREADS) k_sample_small(uint64_t seed, uint
   }
 }
 
+// raw stream words: word w of stream (seed, purpose, object, lane) is block w / 8, words
+// (2 (w % 8), 2 (w % 8) + 1); one thread per block
+__global__ void __launch_bounds__(EW_THREADS) k_stream_words(uint64_t seed, uint64_t purpose, uint64_t obj,
+                                                              uint32_t lane, uint64_t first_block, int64_t n_blocks,
+                                                              uint64_t* out) {
+  int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n_blocks) return;
+  uint32_t w[16];
+  chacha_block(seed, purpose, obj, lane, (uint32_t)(first_block + (uint64_t)gid), w);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) out[gid * 8 + k] = (uint64_t)w[2 * k] | ((uint64_t)w[2 * k + 1] << 32);
+}
+
 // uniform rows: row r uses prime pidx[r] and lane pidx[r]; coefficient c from words 2c, 2c+1
 struct I64 {
   int v[HEQG_MAX_PRIMES];
@@ -593,6 +639,14 @@ void k_add_launch(const Geo& g, const DevTables& t, CtV a, CtV b, CtV out, int64
   int64_t n = count * n_poly * nl * CHUNKS(g);
   if (n) LAUNCH(k_add, n, s, t.pc, a, b, out, g.logN, nl, n_poly, sub ? 1 : 0);
 }
+void k_mul_pt_sum_launch(const Geo& g, const DevTables& t, CtV x, int64_t xs, const uint64_t* pt, int64_t pts,
+                         int nterms, CtV out, int64_t count, int nl, hipStream_t s) {
+  int64_t n = count * 2 * nl * CHUNKS(g);
+  if (n) LAUNCH(k_mul_pt_sum, n, s, t.pc, x, xs, pt, pts, nterms, out, g.logN, nl);
+}
+void k_center0_launch(const DevTables& t, const uint64_t* in, int64_t n, int64_t* out, hipStream_t s) {
+  if (n > 0) LAUNCH(k_center0, (n + EW_THREADS - 1) / EW_THREADS, s, t.pc, in, n, out);
+}
 void k_tensor_launch(const Geo& g, const DevTables& t, CtV a, CtV b, CtV out, int64_t count, int nl, bool acc,
                      hipStream_t s) {
   int64_t n = count * nl * CHUNKS(g);
@@ -676,6 +730,10 @@ void k_small_to_rows_launch(const Geo& g, const DevTables& t, const int64_t* in,
                             uint64_t* rows, int64_t row_cs, int nrows, int, int, hipStream_t s) {
   int64_t n = count * nrows * CHUNKS(g);
   if (n) LAUNCH(k_small_to_rows, n, s, t.pc, in, in_stride, rows, row_cs, g.logN, nrows);
+}
+void k_stream_words_launch(uint64_t seed, uint64_t purpose, uint64_t obj, uint32_t lane, uint64_t first_block,
+                           int64_t n_blocks, uint64_t* out, hipStream_t s) {
+  if (n_blocks > 0) LAUNCH(k_stream_words, n_blocks, s, seed, purpose, obj, lane, first_block, n_blocks, out);
 }
 void k_sample_uniform_launch(const Geo& g, const DevTables& t, uint64_t seed, uint64_t purpose, uint64_t obj,
                              uint64_t* rows, int nrows, const int* pidx_host, hipStream_t s) {

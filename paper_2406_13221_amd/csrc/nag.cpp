@@ -223,6 +223,32 @@ Ct sigmoid_block(Exec& X, const Ct& u, const heqg_sigmoid* sg) {
   return r;
 }
 
+// Margins of cnt row blocks (Zc: cnt * nc ciphertexts, row block i's column blocks at i * nc + j):
+// u = Rescale(Relin(sum_j Z_ij (x) W_j)), then u += Rot(u, 2^k) for k < lg (row sums into column 0).
+Ct row_margins(Exec& X, const Ct& Zc, const Ct& W, int nc, int64_t cnt, int lg) {
+  Ct u{};
+  if (nc == 1) {
+    u = X.hmult_rs(Zc, W);
+  } else {
+    // sum_j Z_ij (x) W_j for every row block i of the chunk (one three-part ciphertext each),
+    // then one relinearisation + rescale per row block
+    Ct Zl = Zc, Wl = W;
+    X.align(Zl, Wl);
+    const size_t mark = X.next;
+    Ct u3 = X.slot(3, Zl.level, Zl.scale * Wl.scale, cnt);
+    if (!X.dry)
+      k_tensor_reduce_launch(X.c->g, X.c->t, CtV{Zl.d, Zl.cs, Zl.ps}, CtV{Wl.d, Wl.cs, Wl.ps}, nc, u3.v(),
+                             Zl.level + 1, false, X.s, cnt, nc * Zl.cs, 0, u3.cs);
+    u = X.relin_rs(u3);
+    // keep u only: move it to the first slot of this step
+    if (!X.dry) std::swap(X.slots[mark], X.slots[X.next - 1]);
+    u.d = X.slots[mark];
+    X.reset(mark + 1);
+  }
+  for (int k = 0; k < lg; ++k) u = X.add_rot(u, 1 << k);
+  return u;
+}
+
 struct Io {
   Ct Z;            // all blocks, row block i and column block j at i * nc + j
   Ct Bbar, W, V;   // nc ciphertexts each
@@ -255,26 +281,7 @@ void circuit(Exec& X, const Io& io, const heqg_sigmoid* sg, heqg_nag_state* st, 
     Ct Zc = io.Z;
     Zc.d = io.Z.d + b0 * nc * io.Z.cs;
     Zc.count = cnt * nc;
-    Ct u{};
-    if (nc == 1) {
-      u = X.hmult_rs(Zc, io.W);
-    } else {
-      // sum_j Z_ij (x) W_j for every row block i of the chunk (one three-part ciphertext each),
-      // then one relinearisation + rescale per row block
-      Ct Zl = Zc, Wl = io.W;
-      X.align(Zl, Wl);
-      const size_t mark = X.next;
-      Ct u3 = X.slot(3, Zl.level, Zl.scale * Wl.scale, cnt);
-      if (!X.dry)
-        k_tensor_reduce_launch(X.c->g, X.c->t, CtV{Zl.d, Zl.cs, Zl.ps}, CtV{Wl.d, Wl.cs, Wl.ps}, nc,
-                               u3.v(), Zl.level + 1, false, X.s, cnt, nc * Zl.cs, 0, u3.cs);
-      u = X.relin_rs(u3);
-      // keep u only: move it to the first slot of this step
-      if (!X.dry) std::swap(X.slots[mark], X.slots[X.next - 1]);
-      u.d = X.slots[mark];
-      X.reset(mark + 1);
-    }
-    for (int k = 0; k < lg; ++k) u = X.add_rot(u, 1 << k);
+    Ct u = row_margins(X, Zc, io.W, nc, cnt, lg);
     Ct p = sigmoid_block(X, u, sg);
     for (int k = 0; k < lg; ++k) p = X.add_rot(p, -(1 << k));
     Ct Zd = Exec::drop(Zc, p.level);
@@ -502,6 +509,82 @@ extern "C" int heqg_nag_qg_graph(heqg_ctx* c, const heqg_keys* k, const heqg_ct_
                                  heqg_ct* W, heqg_ct* V, const heqg_sigmoid* sg, heqg_nag_state* st, int batch,
                                  void* ws, size_t ws_bytes, hipStream_t s) {
   return nag_step(c, k, Z, Bbar, W, V, sg, st, batch, ws, ws_bytes, s, true);
+}
+
+// Encrypted scoring (validation rows against the encrypted model): the margins of every row block,
+// in chunks of `batch` row blocks through the training step's workspace layout.
+extern "C" int heqg_score(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch* Xv, const heqg_ct* W, int col_blocks,
+                          int g_cols, heqg_ct_batch* out, int batch, void* ws, size_t ws_bytes, hipStream_t s) {
+  if (!c || !k || !Xv || !W || !out || !Xv->data || !W->data || !out->data) {
+    set_err("score: null argument");
+    return HEQG_ERR_ARG;
+  }
+  const int nc = std::max(1, col_blocks);
+  const int N = c->g.N;
+  if (batch < 1 || nc > batch || Xv->count < 1 || Xv->count % nc || Xv->n_poly != 2 || W->n_poly != 2 ||
+      out->n_poly != 2 || g_cols < 1 || (g_cols & (g_cols - 1)) || g_cols > N / 2 || Xv->level < 0 ||
+      Xv->level >= c->g.n_q || W->level < 0 || W->level >= c->g.n_q ||
+      (Xv->count > 1 && Xv->stride < (int64_t)2 * (Xv->level + 1) * N)) {
+    set_err("score: bad shapes (whole row blocks of col_blocks ciphertexts, col_blocks <= batch, g a power of two)");
+    return HEQG_ERR_ARG;
+  }
+  const int64_t n_rows = Xv->count / nc;
+  const int lv = std::min(Xv->level, W->level) - 1;
+  if (lv < 0) {
+    set_err("score: level exhausted");
+    return HEQG_ERR_LEVEL;
+  }
+  if (out->count != n_rows || out->level != lv || (out->count > 1 && out->stride < (int64_t)2 * (lv + 1) * N)) {
+    set_err("score: out must hold one ciphertext per row block at level min(X, W) - 1");
+    return HEQG_ERR_ARG;
+  }
+  if (!ws || ws_bytes < heqg_nag_ws_bytes(c, batch, 3)) {
+    set_err("score: workspace too small");
+    return HEQG_ERR_ARG;
+  }
+  int lg = 0;
+  while ((1 << lg) < g_cols) ++lg;
+  Exec X{c, k, s, true, batch, c->g.n_q};
+  uint64_t* w = static_cast<uint64_t*>(ws);
+  for (int i = 0; i < kSlots; ++i) X.slots.push_back(w + (size_t)i * slot_words(c, batch));
+  X.ks_ws = w + (size_t)kSlots * slot_words(c, batch);
+  X.rs_ws = X.ks_ws + std::max(ops::rot_ws_words(c, batch, c->g.n_q - 1),
+                               ops::enc_ws_words(c, batch) + (size_t)batch * c->g.n_q * N);
+  const Ct Zall{Xv->data, Xv->stride, (int64_t)(Xv->level + 1) * N, 2, Xv->level, Xv->scale, Xv->count};
+  const Ct Wc{W->data, 2 * (int64_t)(W->level + 1) * N, (int64_t)(W->level + 1) * N, 2, W->level, W->scale, nc};
+  double scale = 0.0;
+  auto run = [&](bool dry) {
+    X.dry = dry;
+    const int64_t n_chunks = (n_rows + batch - 1) / batch;
+    const int64_t q_chunk = n_rows / n_chunks, r_chunk = n_rows % n_chunks;
+    for (int64_t ci = 0, b0 = 0; ci < n_chunks; ++ci) {
+      const int64_t cnt = q_chunk + (ci < r_chunk ? 1 : 0);
+      X.reset(0);
+      Ct Zc = Zall;
+      Zc.d = Zall.d + b0 * nc * Zall.cs;
+      Zc.count = cnt * nc;
+      Ct u = row_margins(X, Zc, Wc, nc, cnt, lg);
+      if (u.level != lv) X.fail(HEQG_ERR_ARG, "internal: score level");
+      scale = u.scale;
+      if (!dry)
+        k_copy_launch(c->g, u.v(), CtV{out->data + b0 * out->stride, out->stride, (int64_t)(lv + 1) * N}, cnt, 2,
+                      lv + 1, s);
+      b0 += cnt;
+    }
+  };
+  try {
+    run(true);
+    run(false);
+  } catch (const Fail& f) {
+    return f.code;
+  }
+  out->scale = scale;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_err(std::string("score: ") + hipGetErrorString(e));
+    return HEQG_ERR_DEVICE;
+  }
+  return HEQG_OK;
 }
 
 extern "C" int heqg_graph_count(const heqg_ctx* c) {

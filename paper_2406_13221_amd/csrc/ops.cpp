@@ -57,13 +57,56 @@ static void make_ksk(heqg_ctx* c, heqg_keys* k, uint64_t seed, uint64_t tag, con
   }
 }
 
-int keygen(heqg_ctx* c, heqg_keys* k, uint64_t seed, uint8_t* ws, hipStream_t s) {
+// Sparse ternary secret of Hamming weight h: word pairs (2i, 2i + 1) of the stream (seed, SPARSE, 0,
+// lane 0); position a mod N, accepted when a is below the largest multiple of N in 2^64 and the
+// position is still free, sign -1 when bit 63 of the second word is set.
+static int sparse_secret(heqg_ctx* c, uint64_t seed, int h, int64_t* small, uint64_t* dev_words, hipStream_t s) {
+  const int N = c->g.N;
+  if (h < 1 || h > N) {
+    set_err("keygen: Hamming weight outside 1..N");
+    return HEQG_ERR_ARG;
+  }
+  const uint64_t rem = (~0ull % (uint64_t)N + 1) % (uint64_t)N;  // 2^64 mod N
+  std::vector<int64_t> sv(N, 0);
+  constexpr int64_t kBlocks = 64;  // 512 stream words per round trip
+  std::vector<uint64_t> w(kBlocks * 8);
+  int chosen = 0;
+  for (uint64_t blk = 0; chosen < h; blk += kBlocks) {
+    k_stream_words_launch(seed, PUR_SPARSE, 0, 0, blk, kBlocks, dev_words, s);
+    if (hipMemcpyAsync(w.data(), dev_words, w.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      set_err("keygen: reading the secret's stream failed");
+      return HEQG_ERR_DEVICE;
+    }
+    for (size_t i = 0; i + 1 < w.size() && chosen < h; i += 2) {
+      const uint64_t a = w[i], b = w[i + 1];
+      if (rem && a >= 0ull - rem) continue;
+      const int pos = (int)(a % (uint64_t)N);
+      if (sv[pos]) continue;
+      sv[pos] = (b >> 63) ? -1 : 1;
+      ++chosen;
+    }
+  }
+  if (hipMemcpyAsync(small, sv.data(), (size_t)N * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    set_err("keygen: uploading the secret failed");
+    return HEQG_ERR_DEVICE;
+  }
+  return HEQG_OK;
+}
+
+int keygen(heqg_ctx* c, heqg_keys* k, uint64_t seed, uint8_t* ws, hipStream_t s, int hamming) {
   const int N = c->g.N, nq = c->g.n_q, nqp = c->g.nqp;
   int64_t* small = reinterpret_cast<int64_t*>(ws);
   uint64_t* erows = reinterpret_cast<uint64_t*>(ws) + N;
   uint64_t* sp = erows + (size_t)nqp * N;
-  // s: ternary, stream (seed, SK, 0), NTT over every prime
-  k_sample_small_launch(seed, PUR_SK, 0, 1, N, 0, small, s);
+  // s: ternary, stream (seed, SK, 0) (or sparse of weight `hamming`), NTT over every prime
+  if (hamming > 0) {
+    int rc = sparse_secret(c, seed, hamming, small, erows, s);
+    if (rc) return rc;
+  } else {
+    k_sample_small_launch(seed, PUR_SK, 0, 1, N, 0, small, s);
+  }
   k_small_to_rows_launch(c->g, c->t, small, N, 1, k->sk, 0, nqp, 0, 0, s);
   ntt(c, rows_q(k->sk, 1, 0, 1, 0, nqp), false, s);
   // pk = (-a s + e, a) over Q
@@ -419,6 +462,23 @@ int mul_const(heqg_ctx* c, CtV in, int64_t count, int n_poly, int level, double 
   CtV t{ws, (int64_t)n_poly * nl * N, (int64_t)nl * N};
   k_mul_scalar_launch(c->g, c->t, in, t, count, n_poly, nl, kr.data(), s, kdev);
   rescale(c, t, out, count, n_poly, level, ws + (size_t)count * n_poly * nl * N, s);
+  return HEQG_OK;
+}
+
+int add_const(heqg_ctx* c, CtV in, int64_t count, int n_poly, int level, double scale, double cst, CtV out,
+              hipStream_t s) {
+  const double v = cst * scale;
+  if (!(std::fabs(v) < 4611686018427387904.0)) {
+    set_err("add_const: constant times scale reaches 2^62");
+    return HEQG_ERR_OVERFLOW;
+  }
+  const int64_t kint = std::llround(v);  // ties away from zero
+  std::vector<uint64_t> kr(level + 1);
+  for (int i = 0; i <= level; ++i) {
+    const uint64_t q = c->primes[i];
+    kr[i] = kint < 0 ? (q - (uint64_t)((unsigned __int128)(-(__int128)kint) % q)) % q : (uint64_t)kint % q;
+  }
+  k_add_scalar_launch(c->g, c->t, in, out, count, n_poly, level + 1, kr.data(), s);
   return HEQG_OK;
 }
 

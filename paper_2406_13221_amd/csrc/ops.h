@@ -9,7 +9,7 @@ int ntt(const heqg_ctx* c, const RowSet& rs, bool inverse, hipStream_t s);
 RowSet rows(uint64_t* data, int64_t na, int64_t sa, int64_t nb, int64_t sb, int ni, const int* pidx);
 RowSet rows_q(uint64_t* data, int64_t na, int64_t sa, int64_t nb, int64_t sb, int ni, int first = 0);
 
-int keygen(heqg_ctx* c, heqg_keys* k, uint64_t seed, uint8_t* ws, hipStream_t s);
+int keygen(heqg_ctx* c, heqg_keys* k, uint64_t seed, uint8_t* ws, hipStream_t s, int hamming = 0);
 
 size_t enc_ws_words(const heqg_ctx* c, int64_t count);
 int encrypt(heqg_ctx* c, const heqg_keys* k, const int64_t* coeffs, const uint64_t*, int, uint64_t seed,
@@ -47,5 +47,8 @@ void const_residues(const heqg_ctx* c, int64_t k, int level, std::vector<uint64_
 // kdev: the same residue table already on the device (read at run time) instead of a host copy
 int mul_const(heqg_ctx* c, CtV in, int64_t count, int n_poly, int level, double in_scale, double cst, double target,
               CtV out, uint64_t* ws, hipStream_t s, const uint64_t* kdev = nullptr);
+// out = in + cst in every slot: the constant polynomial round(cst * scale) (ties away from zero) on part 0
+int add_const(heqg_ctx* c, CtV in, int64_t count, int n_poly, int level, double scale, double cst, CtV out,
+              hipStream_t s);
 
 }  // namespace ops

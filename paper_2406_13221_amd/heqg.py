@@ -76,6 +76,19 @@ def lib():
         "heqg_keys_bytes": (sz, [vp, i32]),
         "heqg_keygen_ws_bytes": (sz, [vp]),
         "heqg_keygen": (i32, [vp, u64, vp, i32, vp, sz, vp, sz, P(vp), vp]),
+        "heqg_keygen_ex": (i32, [vp, u64, i32, i32, vp, i32, vp, sz, vp, sz, P(vp), vp]),
+        "heqg_boot_steps": (i32, [vp, vp]),
+        "heqg_boot_shape": (i32, [vp, i32, vp, vp, vp, vp]),
+        "heqg_boot_encode": (i32, [vp, i32, vp, i32]),
+        "heqg_boot_bytes": (sz, [vp, i32]),
+        "heqg_boot_setup": (i32, [vp, vp, i32, i32, vp, sz, P(vp), vp]),
+        "heqg_boot_destroy": (None, [vp]),
+        "heqg_boot_ws_bytes": (sz, [vp, i64]),
+        "heqg_mod_raise": (i32, [vp, P(BatchS), P(BatchS), vp, sz, vp]),
+        "heqg_coeff_to_slot": (i32, [vp, vp, vp, P(BatchS), P(BatchS), vp, sz, vp]),
+        "heqg_eval_mod": (i32, [vp, vp, vp, P(BatchS), dbl, P(BatchS), vp, sz, vp]),
+        "heqg_slot_to_coeff": (i32, [vp, vp, vp, P(BatchS), P(BatchS), vp, sz, vp]),
+        "heqg_bootstrap": (i32, [vp, vp, vp, P(BatchS), P(BatchS), vp, sz, vp]),
         "heqg_keys_destroy": (None, [vp]),
         "heqg_keys_galois": (i32, [vp, vp]),
         "heqg_keys_export": (i32, [vp, i32, i32, vp, vp]),
@@ -118,6 +131,7 @@ def lib():
         "heqg_nag_qg_graph": (i32, [vp, vp, P(BatchS), P(CtS), P(CtS), P(CtS), P(SigmoidS), P(NagStateS), i32, vp,
                                     sz, vp]),
         "heqg_graph_clear": (i32, [vp]),
+        "heqg_score": (i32, [vp, vp, P(BatchS), P(CtS), i32, i32, P(BatchS), i32, vp, sz, vp]),
         "heqg_graph_count": (i32, [vp]),
         "heqg_add_const": (i32, [vp, P(BatchS), dbl, P(BatchS), vp]),
         "heqg_export_ws_bytes": (sz, [vp, P(BatchS)]),
@@ -249,6 +263,17 @@ class Keys:
             pass
 
 
+class Boot:
+    def __init__(self, handle, buf, shape, r):
+        self.handle, self.buf, self.shape, self.r = handle, buf, shape, r
+
+    def __del__(self):
+        try:
+            lib().heqg_boot_destroy(self.handle)
+        except Exception:
+            pass
+
+
 class Context:
     def __init__(self, log2N, q_bits, n_p, p_bits, dnum, log2_scale):
         torch = _torch()
@@ -285,15 +310,21 @@ class Context:
         return self.n_q - 1
 
     # ---------------------------------------------------------------- keys
-    def keygen(self, seed, rot_steps):
+    def keygen(self, seed, rot_steps, hamming=0, conj=False):
+        """heqg_keygen (hamming = 0, no conjugation key) or heqg_keygen_ex (sparse secret of weight
+        hamming, conjugation key X -> X^(2N-1))."""
         L = lib()
         steps = (ctypes.c_int * max(1, len(rot_steps)))(*rot_steps)
-        nb = L.heqg_keys_bytes(self.h, len(rot_steps))
+        nb = L.heqg_keys_bytes(self.h, len(rot_steps) + (1 if conj else 0))
         buf = _ws(nb)
         ws = _ws(L.heqg_keygen_ws_bytes(self.h))
         h = ctypes.c_void_p()
-        _check(L.heqg_keygen(self.h, seed, steps, len(rot_steps), buf.data_ptr(), nb, ws.data_ptr(), ws.numel(),
-                             ctypes.byref(h), _stream()))
+        if hamming or conj:
+            _check(L.heqg_keygen_ex(self.h, seed, int(hamming), 1 if conj else 0, steps, len(rot_steps),
+                                    buf.data_ptr(), nb, ws.data_ptr(), ws.numel(), ctypes.byref(h), _stream()))
+        else:
+            _check(L.heqg_keygen(self.h, seed, steps, len(rot_steps), buf.data_ptr(), nb, ws.data_ptr(), ws.numel(),
+                                 ctypes.byref(h), _stream()))
         n = _check(L.heqg_keys_galois(h, None))
         gal = np.zeros(max(n, 1), dtype=np.uint64)
         L.heqg_keys_galois(h, gal.ctypes.data)
@@ -561,6 +592,20 @@ class Context:
             ct.level, ct.scale = cs.level, cs.scale
         return state
 
+    def score(self, keys, X, W, g, col_blocks=1, batch=16, ws=None):
+        """heqg_score: per row block of X (rows of [1 | X | 0] in the m x g partition), a ciphertext whose
+        column 0 holds every row's score x-hat . w under the encrypted model W (col_blocks ciphertexts)."""
+        n = X.count // max(1, col_blocks)
+        lv = min(X.level, W.level) - 1
+        out = self.empty(n, 2, lv, 0.0)
+        if ws is None:
+            ws = _ws(self.nag_ws_bytes(batch))
+        xb, wb, ob = X.batch(), W.one(), out.batch()
+        _check(lib().heqg_score(self.h, keys.handle, ctypes.byref(xb), ctypes.byref(wb), int(col_blocks), int(g),
+                                ctypes.byref(ob), int(batch), ws.data_ptr(), ws.numel(), _stream()))
+        out.scale = ob.scale
+        return out
+
     def tune_set(self, which, value):
         """Tuning choice of this context: 0/1 row-pass variant fwd/inv, 2 NTT pass split (False if refused)."""
         return lib().heqg_tune_set(self.h, int(which), int(value)) == 0
@@ -586,10 +631,76 @@ class Context:
     def graph_clear(self):
         _check(lib().heqg_graph_clear(self.h))
 
-    def mul_const(self, a, c, target):
-        out = self.empty(a.count, a.n_poly, a.level - 1, target)
-        ws = _ws(16 * a.count * a.n_poly * (a.level + 1) * self.N)
-        ba, bo = a.batch(), out.batch()
-        _check(lib().heqg_mul_const(self.h, ctypes.byref(ba), float(c), float(target), ctypes.byref(bo), ws.data_ptr(),
-                                    ws.numel(), _stream()))
+    # ---------------------------------------------------------------- bootstrapping
+    def boot_steps(self):
+        """The rotation steps the slot transforms of heqg_bootstrap use."""
+        L = lib()
+        n = _check(L.heqg_boot_steps(self.h, None))
+        out = (ctypes.c_int * max(1, n))()
+        L.heqg_boot_steps(self.h, out)
+        return list(out[:n])
+
+    def boot_shape(self, r):
+        """(n1, n2, CoeffToSlot level, SlotToCoeff level) for r double angles."""
+        v = [ctypes.c_int() for _ in range(4)]
+        _check(lib().heqg_boot_shape(self.h, int(r), *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
+
+    def boot_encode(self, r, threads=0):
+        """heqg_boot_encode: the slot transforms' plaintexts, numpy int64 [2 n1 n2 + 1][N]."""
+        n1, n2, _, _ = self.boot_shape(r)
+        out = np.zeros((2 * n1 * n2 + 1, self.N), dtype=np.int64)
+        _check(lib().heqg_boot_encode(self.h, int(r), out.ctypes.data, int(threads)))
         return out
+
+    def boot_setup(self, coeffs, r, taylor):
+        """coeffs: int64 [2 n1 n2 + 1][N] (numpy or a device tensor; CoeffToSlot diagonals, SlotToCoeff
+        diagonals, X^(N/2)).  Returns a Boot holding the NTT-form plaintexts."""
+        torch = _torch()
+        L = lib()
+        nb = L.heqg_boot_bytes(self.h, int(r))
+        if nb == 0:
+            raise HeqgError(-1, L.heqg_last_error().decode())
+        if isinstance(coeffs, np.ndarray):
+            coeffs = torch.from_numpy(np.ascontiguousarray(coeffs, dtype=np.int64)).cuda()
+        buf = _ws(nb)
+        h = ctypes.c_void_p()
+        _check(L.heqg_boot_setup(self.h, coeffs.data_ptr(), int(r), int(taylor), buf.data_ptr(), nb, ctypes.byref(h),
+                                 _stream()))
+        _torch().cuda.current_stream().synchronize()
+        return Boot(h, buf, self.boot_shape(r), int(r))
+
+    def _boot_call(self, fn, pre, ct, out_level, ws):
+        """fn(ctx, *pre, in, out, ws, ws_bytes, stream) for the bootstrapping steps."""
+        out = self._out(ct.count, 2, out_level)
+        need = lib().heqg_boot_ws_bytes(self.h, ct.count)
+        if ws is None or ws.numel() < need:
+            ws = _ws(need)
+        bi, bo = ct.batch(), out.batch()
+        _check(fn(self.h, *pre, ctypes.byref(bi), ctypes.byref(bo), ws.data_ptr(), ws.numel(), _stream()))
+        return self._done(out, bo)
+
+    def mod_raise(self, ct, ws=None):
+        """heqg_mod_raise: level 0 -> the top level (decrypts to m + q0 I)."""
+        return self._boot_call(lib().heqg_mod_raise, (), ct, self.top_level, ws)
+
+    def coeff_to_slot(self, keys, boot, ct, ws=None):
+        return self._boot_call(lib().heqg_coeff_to_slot, (keys.handle, boot.handle), ct, ct.level - 1, ws)
+
+    def slot_to_coeff(self, keys, boot, ct, ws=None):
+        return self._boot_call(lib().heqg_slot_to_coeff, (keys.handle, boot.handle), ct, ct.level - 1, ws)
+
+    def eval_mod(self, keys, boot, ct, half=1.0, ws=None):
+        out = self._out(ct.count, 2, ct.level - 7 - boot.r)
+        need = lib().heqg_boot_ws_bytes(self.h, ct.count)
+        if ws is None or ws.numel() < need:
+            ws = _ws(need)
+        bi, bo = ct.batch(), out.batch()
+        _check(lib().heqg_eval_mod(self.h, keys.handle, boot.handle, ctypes.byref(bi), float(half), ctypes.byref(bo),
+                                   ws.data_ptr(), ws.numel(), _stream()))
+        return self._done(out, bo)
+
+    def bootstrap(self, keys, boot, ct, ws=None):
+        """heqg_bootstrap: level-0 ciphertexts -> the same messages at level stc_level - 1."""
+        return self._boot_call(lib().heqg_bootstrap, (keys.handle, boot.handle), ct, boot.shape[3] - 1, ws)
+
