@@ -1245,23 +1245,31 @@ __device__ __forceinline__ int tw8_pos(int st, int k) {
   return st == 6 ? 63 + (k >> 1) + 32 * (k & 1) : st == 7 ? 127 + (k >> 2) + 32 * (k & 3) : (1 << st) - 1 + k;
 }
 // the 255 twiddles of each of the workgroup's 8 sub-rows (bases N1 + b0 .. N1 + b0 + 7) from the
-// table tw (one prime) into T[8][256]; every thread loads 8 (threads 32 rl .. 32 rl + 31 for sub-row rl)
+// table tw (one prime) into T[8][256]; thread j of sub-row rl fills table positions j + 32 i, so
+// each store instruction writes 32 consecutive words (no bank conflicts), and gathers the
+// twiddle of each position (the inverse of tw8_pos) from the global table
 __device__ __forceinline__ void tw8_load(double* T, const double* tw, int64_t base0) {
   const int rl = threadIdx.x >> 5, j = threadIdx.x & 31;
   const int64_t base = base0 + rl;
   double v[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    const int e = j + 32 * i;
-    const int st = 31 - __clz(e + 1), k = e + 1 - (1 << st);
-    v[i] = e < 255 ? tw[(base << st) + k] : 0.0;
+    const int p = j + 32 * i;
+    int st, k;
+    if (p < 63) {
+      st = 31 - __clz(p + 1);
+      k = p + 1 - (1 << st);
+    } else if (p < 127) {
+      st = 6;
+      k = 2 * ((p - 63) & 31) + ((p - 63) >> 5);
+    } else {
+      st = 7;
+      k = 4 * ((p - 127) & 31) + ((p - 127) >> 5);
+    }
+    v[i] = p < 255 ? tw[(base << st) + k] : 0.0;
   }
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int e = j + 32 * i;
-    const int st = 31 - __clz(e + 1), k = e + 1 - (1 << st);
-    if (e < 255) T[rl * 256 + tw8_pos(st, k)] = v[i];
-  }
+  for (int i = 0; i < 8; ++i) T[rl * 256 + j + 32 * i] = v[i];
 }
 // the three register phases with the twiddles from the sub-row's LDS table T (j = lane in the
 // sub-row, jq = j >> 2; see st8_A, st8_B, st8_C for the pairs)
