@@ -78,6 +78,14 @@ def tile_row(vec, m, g):
     return np.tile(row, m)
 
 
+# Scale of the sigmoid output p (the F/2 mask's encoding scale; every term of the polynomial lands on it).
+# The gradient Z^T p then carries Delta * 2^30 / q ~ 2^30, so the B-bar product's constant
+# round(lr * s * q / scale(B-bar)) gets about 2^20 instead of 2^10: with 2^40 here its rounding alone
+# put a relative error of up to 5e-4 on the step at 422,108 rows, where B-bar is ~1e-6 (the paper
+# scales ciphertexts by 2^30 too).  Lower scales cost precision in the masks' encodings instead.
+SIGMOID_SCALE = 2.0 ** 30
+
+
 def new_state(m, g, refresh_seed=0, lr_max=2.0, lr_min=1.0, T=81.0, gamma=2.5, col_blocks=1):
     a0 = 0.01
     a1 = 0.5 * (1.0 + math.sqrt(1.0 + 4.0 * a0 * a0))
@@ -235,7 +243,7 @@ class EncryptedQGNAG:
         self.coeffs = dict(coeffs)
         self.degree = max(self.coeffs)
         lv = self.L
-        vals, scales = ctx.sigmoid_masks(self.coeffs, self.m, self.g, lv, ctx.delta, ctx.delta, ctx.delta)
+        vals, scales = ctx.sigmoid_masks(self.coeffs, self.m, self.g, lv, ctx.delta, ctx.delta, SIGMOID_SCALE)
         self.mask_level = lv - 1
         self.masks = ctx.pt_load(vals, self.mask_level)
         self.mask_scales = scales

@@ -11,6 +11,7 @@ import synth
 from oracle import circuit, trainer
 from oracle.ckks import Oracle
 from oracle.encode import encode
+from paper_2406_13221_amd.train import SIGMOID_SCALE
 from tests.gpu_common import assert_same_ct, gpu_ct
 
 _DATA, _ORA, _GPU = {}, {}, {}
@@ -71,7 +72,7 @@ def oracle_setup(cfgkey, coeffs=trainer.G8, rows=None, bbar_rows=None, **over):
     Bc = o.encrypt(encode(circuit.replicate_row(B, m, g), N, sB), L, sB, cfg["enc_seed"], 1 << 20)
     W = o.encrypt(np.zeros(N, np.int64), L, o.delta, cfg["enc_seed"], (1 << 20) + 1)
     V = o.encrypt(np.zeros(N, np.int64), L, o.delta, cfg["enc_seed"], (1 << 20) + 2)
-    masks = circuit.make_masks(o, m, g, coeffs, L, o.delta)
+    masks = circuit.make_masks(o, m, g, coeffs, L, SIGMOID_SCALE)
     return cfg, o, X, y, Zc, Bc, W, V, masks
 
 
@@ -167,7 +168,7 @@ def grid_oracle_setup(cfgkey, rows=None, coeffs=trainer.G8, **over):
     zero = np.zeros(N, np.int64)
     W = [o.encrypt(zero, L, o.delta, cfg["enc_seed"], (1 << 21) + j) for j in range(nc)]
     V = [o.encrypt(zero, L, o.delta, cfg["enc_seed"], (1 << 22) + j) for j in range(nc)]
-    masks = circuit.make_masks(o, m, g, coeffs, L, o.delta)
+    masks = circuit.make_masks(o, m, g, coeffs, L, SIGMOID_SCALE)
     return cfg, o, X, y, Zg, Bc, W, V, masks
 
 
