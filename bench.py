@@ -25,10 +25,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# double-angle steps of the bootstrap whose output level the iteration works at (EvalMod with a
+# degree-20 Taylor cosine covers |I| < 16 with r = 5)
+BOOT_R = 5
 # FP64 vector issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz instructions per second (the published
 # 78.6 TFLOP/s counts each FMA as two flops)
 FP64_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-PMC_FILE = os.path.join(ROOT, "profiles", "conv_cols_c3_pmc.json")
+PMC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c3.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2406_13221_amd", "csrc", "ntt.hip")
 
 
@@ -72,10 +75,10 @@ def cpu_baseline(cfg, data, n_blocks):
                                                                           tail, n_blocks))
 
 
-def iteration_model_bytes(cfg, n_blocks, degree=3):
+def iteration_model_bytes(cfg, n_blocks, degree=3, level=None):
     """Bytes of one full-batch iteration if every primitive reads its inputs and writes its
     outputs once (a limb = 8N bytes; an NTT reads and writes each limb once; switching keys
-    read once per iteration, so not counted per block)."""
+    read once per iteration, so not counted per block), starting at `level` (default: the top)."""
     N, nq, np_, dnum = 1 << cfg["log2N"], len(cfg["q_bits"]), cfg["n_p"], cfg["dnum"]
     alpha = -(-nq // dnum)
     g, m = cfg["g"], cfg["m"]
@@ -103,7 +106,7 @@ def iteration_model_bytes(cfg, n_blocks, degree=3):
     def add_rot(n):                # x + Rot(x)
         return ks(n) + 2 * n + 3 * 2 * n
 
-    L = nq - 1
+    L = nq - 1 if level is None else level
     per_block = 0
     n = L + 1
     per_block += hmult_rs(n)                       # u = Z (x) W
@@ -123,18 +126,25 @@ def iteration_model_bytes(cfg, n_blocks, degree=3):
     return 8.0 * N * (per_block * n_blocks + tail)
 
 
-def pmc_traffic(avg_rows):
-    """HBM bytes (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy) per launch of the fused conversion
-    column pass, from the committed rocprofv3 --pmc summary: bytes per output row x rows per launch.
-    None when the summary is missing or the NTT source has changed since it was taken."""
+def pmc_traffic(kernel, batch, level, rows=None):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc summary (FETCH_SIZE and
+    WRITE_SIZE per dispatch, scaled by what the counters read for a plain device copy): for the
+    conversion pass bytes per output row x `rows`, for the others bytes per dispatch.  None when
+    the summary is missing, the NTT source has changed since it was taken, or it was taken at
+    another chunk size or working level."""
     try:
         with open(PMC_FILE) as f:
             pm = json.load(f)
         with open(KERNEL_SRC, "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != pm["kernel_source_sha256"]:
                 return None
-        return pm["bytes_per_row"] * avg_rows
-    except (OSError, KeyError, ValueError):
+        if pm["batch_blocks"] != batch or pm["work_level"] != level:
+            return None
+        k = pm["kernels"][kernel]
+        if rows is not None:
+            return k["bytes_per_output_row"] * rows
+        return k["fetch_bytes_per_dispatch"] + k["write_bytes_per_dispatch"]
+    except (OSError, KeyError, ValueError, TypeError):
         return None
 
 
@@ -260,6 +270,13 @@ def main():
                     help="skip encrypted scoring of the validation rows")
     ap.add_argument("--mode", default="train", choices=["train", "ntt"],
                     help="ntt: only the batched forward NTT (768 limbs) and a 1 GiB device copy, for counters")
+    ap.add_argument("--work-level", default="boot",
+                    help="level of W and V, the level they are refreshed to: 'boot' (the level heqg_bootstrap "
+                         "returns with 5 double angles), 'top', or a number")
+    ap.add_argument("--top-steps", type=int, default=1,
+                    help="timed iterations with W and V at the top level")
+    ap.add_argument("--paper-q-steps", type=int, default=1,
+                    help="timed iterations at the paper's working modulus (Table 1: Q = 2^275)")
     ap.add_argument("--no-ntt-probe", dest="ntt_probe", action="store_false",
                     help="skip the full-batch NTT throughput leg (keeps per-kernel profiles to the iteration)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -294,9 +311,14 @@ def main():
     data = synth.make_dataset(cfg)
     t0 = time.perf_counter()
     run = EncryptedQGNAG(cfg, data["X"], data["y"], batch=args.batch)
+    top = run.ctx.top_level
+    work = {"top": top, "boot": run.ctx.boot_shape(BOOT_R)[3] - 1}.get(args.work_level)
+    work = int(args.work_level) if work is None else work
+    if work != top:
+        run.reset(obj=(1 << 40) + 1, level=work)
     torch.cuda.synchronize()
-    log("setup %.1f s, %d blocks, %.1f GB resident" % (time.perf_counter() - t0, run.Z.count,
-                                                       torch.cuda.memory_allocated() / 1e9))
+    log("setup %.1f s, %d blocks, %.1f GB resident; Z at level %d, W and V at level %d" %
+        (time.perf_counter() - t0, run.Z.count, torch.cuda.memory_allocated() / 1e9, top, work))
     tuning = None
     if not args.no_tune:
         tuning = run.tune()
@@ -328,6 +350,12 @@ def main():
     log("timed %d steps: %.3f s/step (update %.3f s, refresh %.4f s)" % (args.steps, ms_per_step / 1e3, upd, ref))
     # the model after these iterations (g8 only so far), for the comparison with the 1,024 x 32 layout
     w_cmp, t_cmp = run.weights(cfg["n_features"] + 1), int(run.state.t)
+    batch_used = run.batch
+    # the data owner's FP64 run of the same iterations (the decrypted weights must follow it within 1e-3)
+    w_fp64 = {t: heqg.plain_qgnag(data["X"], data["y"], t, coeffs=dict(run.coeffs), margins=False)[0]
+              for t in (1, t_cmp)}
+    fp64_check = {"iterations": t_cmp, "max_abs_dw": float(abs(w_cmp - w_fp64[t_cmp]).max())}
+    log("decrypted weights after %d iterations: max|dw| vs FP64 %.2e" % (t_cmp, fp64_check["max_abs_dw"]))
 
     # the same iteration submitted as a replayed HIP graph (first call captures, untimed)
     graph_s = None
@@ -462,7 +490,7 @@ def main():
     conv_gbs = conv_bytes / (conv_us * 1e-6) / 1e9 if conv_us > 0 else 0.0
     conv_tops = conv_ops / (conv_us * 1e-6) / 1e12 if conv_us > 0 else 0.0
     conv_roofline = {"bound": "hbm", "achieved": round(conv_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(conv_gbs / HBM_PEAK_GBS, 4), "traffic": pmc_traffic(conv_rows),
+                "frac": round(conv_gbs / HBM_PEAK_GBS, 4), "traffic": pmc_traffic("k_conv_cols", run.batch, work, rows=conv_rows),
                 "kernel": "k_conv_cols<8,*> (ModUp / ModDown base conversion on the int8 matrix cores, fused "
                           "into the first forward NTT pass)",
                 "bytes": "8 bytes per output residue written + 8 per source residue read, once",
@@ -480,19 +508,19 @@ def main():
 
     # dominant kernel: the ModUp row pass fused with the key inner product.  Its algorithmic bytes:
     # ciphertext rows read and written plus the switching-key rows, each read once per launch.  Its
-    # rocprofv3 FETCH_SIZE / WRITE_SIZE (profiles/hbm_bytes_c3.md) were taken at 16 blocks per chunk
-    # only, so no per-launch traffic figure is claimed for the launch size timed here
+    # HBM traffic per launch comes from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, valid
+    # for the chunk size and working level it was taken at
     ks_bytes = 8.0 * N * (ks_rows + ks_keyrows)
     ks_rate = ks_bytes / (ks_us * 1e-6) / 1e9 if ks_us > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": round(ks_rate, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ks_rate / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(ks_rate / HBM_PEAK_GBS, 4), "traffic": pmc_traffic("k_ntt_rows_ks8", run.batch, work),
                 "kernel": "k_ntt_rows_ks8 (ModUp second forward pass of every digit fused with the key inner "
                           "product; the P limbs' first inverse pass)",
                 "bytes": "8 bytes per ciphertext residue read (digits) and written (2 parts), key rows once",
                 "algorithmic_bytes_per_launch": ks_bytes, "avg_launch_us": round(ks_us, 2),
                 "sampled_launches": ks_n}
 
-    model = iteration_model_bytes(cfg, run.Z.count)
+    model = iteration_model_bytes(cfg, run.Z.count, level=work)
     it_roof = {"model_bytes": model, "achieved_GBps": round(model / upd / 1e9, 1), "peak": HBM_PEAK_GBS,
                "frac": round(model / upd / 1e9 / HBM_PEAK_GBS, 4),
                "note": "each primitive reads its inputs and writes its outputs once; keys read once per iteration"}
@@ -510,10 +538,13 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic (seeded; shapes of the paper's 422,108 x 200 workload)",
-        "config": {"workload": "%s full-batch QG-NAG iteration + W/V refresh" % cfg["name"],
+        "config": {"workload": "%s full-batch QG-NAG iteration + W/V refresh (Z at level %d, W and V at level %d)"
+                               % (cfg["name"], top, work),
                    "n_samples": cfg["n_train"], "n_features": cfg["n_features"], "log2N": cfg["log2N"],
                    "limbs": len(cfg["q_bits"]), "dnum": cfg["dnum"], "blocks": run.Z.count,
+                   "z_level": top, "work_level": work,
                    "rows_per_block": cfg["m"], "cols": cfg["g"], "batch_blocks": run.batch},
+        "fp64_check": fp64_check,
         "update_s": round(upd, 4),
         "refresh_s": round(ref, 5),
         "ntt_gbps": ntt_gbps,
@@ -534,13 +565,59 @@ def main():
             (scoring["rows"], scoring["score_s"], scoring["sample_auroc_encrypted"], scoring["sample_auroc_plain"]))
     out["validation_scoring"] = scoring
 
+    # the same iteration with W and V at the top of the chain (as a refresh that returned them there
+    # would leave them; no bootstrap can): seconds per iteration from W = V = 0
+    top_it = None
+    if args.top_steps > 0 and work != top:
+        run.reset(level=top)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.top_steps):
+            run.step()
+        torch.cuda.synchronize()
+        top_it = {"level": top, "limbs": top + 1, "s_per_iter": round((time.perf_counter() - t0) / args.top_steps, 4),
+                  "iterations": args.top_steps}
+        if args.top_steps == 1:
+            top_it["max_abs_dw_vs_fp64"] = float(abs(run.weights(cfg["n_features"] + 1) - w_fp64[1]).max())
+        log("iteration with W and V at the top level %d: %.3f s" % (top, top_it["s_per_iter"]))
+    out["top_level_iteration"] = top_it
+
+    # the same iteration at the paper's working modulus: Table 1 gives Q = 2^275 for its ciphertexts
+    # (4.6 MB encrypted blocks at N = 2^16), the modulus its weights and data carry through an
+    # iteration; W and V at the lowest level of the chain whose modulus covers 2^275, trained for as
+    # many iterations as the run above from W = V = 0: time per iteration and the decrypted model
+    # against the main run's
+    paper_q = None
+    if args.paper_q_steps > 0:
+        import numpy as np
+        bits = np.cumsum(cfg["q_bits"])
+        lq = int(np.argmax(bits >= 275))
+        run.reset(level=lq)
+        for _ in range(max(t_cmp - args.paper_q_steps, 0)):
+            run.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.paper_q_steps):
+            run.step()
+        torch.cuda.synchronize()
+        ps = (time.perf_counter() - t0) / args.paper_q_steps
+        wq = run.weights(cfg["n_features"] + 1)
+        paper_q = {"level": lq, "limbs": lq + 1, "log2_modulus": int(bits[lq]), "s_per_iter": round(ps, 4),
+                   "iterations": int(run.state.t),
+                   "max_abs_dw_vs_main_run": float(np.abs(wq - w_cmp).max()) if run.state.t == t_cmp else None,
+                   "max_abs_dw_vs_fp64": float(np.abs(wq - w_fp64[t_cmp]).max()) if run.state.t == t_cmp else None,
+                   "note": "Table 1's Q = 2^275: the working modulus of the paper's iteration"}
+        log("iteration at level %d (2^%d): %.3f s, max|dw| vs the main run after %d iterations: %.2e" %
+            (lq, bits[lq], ps, run.state.t, paper_q["max_abs_dw_vs_main_run"] or -1.0))
+    out["paper_modulus_iteration"] = paper_q
+
     # the same task over the 1,024 x 32 partition of section 2.2 (7 column blocks; 10x fewer key
     # switches per iteration), trained for as many iterations as the run above from the same start:
     # its decrypted model against the 128 x 256 run's
     grid = None
     if args.grid_steps > 0:
         import numpy as np
-        del run
+        run = None
         torch.cuda.empty_cache()
         gcfg = synth.get_config("c3g")
         gr = EncryptedQGNAG(gcfg, data["X"], data["y"], batch=args.batch)
@@ -579,6 +656,7 @@ def main():
         del gr
         torch.cuda.empty_cache()
     out["grid_1024x32"] = grid
+
 
     # the paper's second workload (section 5.2, Table 2): MNIST-shaped, g16, 12 x 7 blocks; the quadratic
     # gradient beside the first-order NAG baseline (section 3.2, Fig. 1), decrypted log-likelihood and

@@ -96,10 +96,13 @@ class EncryptedQGNAG:
     """Client + cloud roles of the pipeline on one GPU."""
 
     def __init__(self, cfg, X, y, coeffs=None, batch=16, rows=None, threads=0, mini_batch=False, graph=False,
-                 first_order=False):
+                 first_order=False, level=None):
         """graph: submit each iteration as a replayed HIP graph (on a side stream of this object).
         first_order: train with the first-order NAG the paper compares against (step cfg["fo_lr"] / n on
-        the gradient, no B-bar) instead of the quadratic gradient."""
+        the gradient, no B-bar) instead of the quadratic gradient.
+        level: the level W and V are encrypted at and refreshed to (default: the top of the chain).  Z and
+        B-bar are always encrypted at the top, and every product with them runs at the level of W, V:
+        a bootstrapped run works at the level bootstrapping returns (heqg_boot_shape)."""
         import torch
         self.cfg = cfg
         self.m, self.g = cfg["m"], cfg["g"]
@@ -109,7 +112,6 @@ class EncryptedQGNAG:
         self.ctx = ctx = heqg.Context.from_config(cfg)
         self.keys = ctx.keygen(cfg["key_seed"], rot_steps(self.m, self.g))
         L = ctx.top_level
-        self.L = L
         Xs, ys = (X, y) if rows is None else (X[rows[0]:rows[1]], y[rows[0]:rows[1]])
         self._X, self._n_rows = Xs, Xs.shape[0]
         # column blocks of the partition (section 2.2); W, V and each B-bar are one ciphertext per block
@@ -140,28 +142,37 @@ class EncryptedQGNAG:
         self.first_order = first_order
         self.Bbars = [self._bbar_cts(Xs[s:e], (1 << 40) + 16 + i * nc) for i, (s, e) in enumerate(spans)]
         self.Bbar = self.Bbars[0]
-        zero = np.zeros((nc, ctx.N), dtype=np.int64)
-        self.W = ctx.encrypt(self.keys, zero, L, ctx.delta, cfg["enc_seed"], (1 << 40) + 1)
-        self.V = ctx.encrypt(self.keys, zero, L, ctx.delta, cfg["enc_seed"], (1 << 40) + 1 + nc)
-        # W and V keep their storage for the whole run (a replayed graph is bound to it)
-        self.Wbuf, self.Vbuf = self.W.data, self.V.data
+        # W and V keep their storage for the whole run (a replayed graph is bound to it), sized for
+        # the top level; they are encrypted at the working level
+        words = nc * 2 * (ctx.top_level + 1) * ctx.N
+        self.Wflat = torch.empty(words, dtype=torch.int64, device="cuda")
+        self.Vflat = torch.empty(words, dtype=torch.int64, device="cuda")
         self.graph = graph
         self.stream = torch.cuda.Stream() if graph else None
-        self.set_sigmoid(self.coeffs)
         self.state = new_state(self.m, self.g, refresh_seed=cfg["enc_seed"] + 7, col_blocks=nc,
                                T=cfg.get("lr_T", 81.0))
+        self.reset(obj=(1 << 40) + 1, level=L if level is None else level)
         self.ws = heqg._ws(ctx.nag_ws_bytes(batch, self.degree))
         self.refresh_obj = 1 << 41
 
-    def reset(self, obj=(1 << 40) + (1 << 30)):
-        """W = V = 0 again (fresh encryptions into the same storage, objects obj + j) and t = 0."""
-        ctx, nc, L = self.ctx, self.nc, self.L
+    def reset(self, obj=(1 << 40) + (1 << 30), level=None):
+        """W = V = 0 again (fresh encryptions into the same storage, objects obj + j) and t = 0, at
+        `level` (default: the current working level); the sigmoid masks are planned for it."""
+        ctx, nc = self.ctx, self.nc
+        L = self.L if level is None else int(level)
+        if not 1 <= L <= ctx.top_level:
+            raise ValueError("level must be in 1..%d" % ctx.top_level)
+        self.L = L
+        shape = (nc, 2, L + 1, ctx.N)
+        self.Wbuf = self.Wflat[:nc * 2 * (L + 1) * ctx.N].view(shape)
+        self.Vbuf = self.Vflat[:nc * 2 * (L + 1) * ctx.N].view(shape)
         zero = np.zeros((nc, ctx.N), dtype=np.int64)
         self.W = heqg.Cts(self.Wbuf, L, ctx.delta)
         self.V = heqg.Cts(self.Vbuf, L, ctx.delta)
         for ct, o in ((self.W, obj), (self.V, obj + nc)):
             fresh = ctx.encrypt(self.keys, zero, L, ctx.delta, self.cfg["enc_seed"], o)
             ct.data.copy_(fresh.data)
+        self.set_sigmoid(self.coeffs)
         st = self.state
         self.state = new_state(self.m, self.g, refresh_seed=st.refresh_seed, lr_max=st.lr_max, lr_min=st.lr_min,
                                T=st.T, gamma=st.gamma, col_blocks=nc)
@@ -172,7 +183,7 @@ class EncryptedQGNAG:
         B = bbar_diag(Xr, self.width)
         sB = 2.0 ** 50 / B.max()
         pts = np.stack([ctx.encode(tile_row(B[j * g:(j + 1) * g], self.m, g), sB) for j in range(self.nc)])
-        return ctx.encrypt(self.keys, pts, self.L, sB, self.cfg["enc_seed"], obj_first)
+        return ctx.encrypt(self.keys, pts, ctx.top_level, sB, self.cfg["enc_seed"], obj_first)
 
     def tune(self, candidates=(8, 16, 24), blocks=48, rows=2048):
         """Autotune: NTT pass split and row-pass variants (heqg_tune_ntt), then the number of
@@ -222,12 +233,11 @@ class EncryptedQGNAG:
         nc = self.nc
         mb.Bbars = [self._bbar_cts(self._X[s:e], (1 << 40) + (1 << 20) + i * nc) for i, (s, e) in enumerate(spans)]
         mb.Bbar = mb.Bbars[0]
-        zero = np.zeros((nc, ctx.N), dtype=np.int64)
-        mb.W = ctx.encrypt(self.keys, zero, L, ctx.delta, self.cfg["enc_seed"], (1 << 40) + 3 * nc)
-        mb.V = ctx.encrypt(self.keys, zero, L, ctx.delta, self.cfg["enc_seed"], (1 << 40) + 4 * nc)
-        mb.Wbuf, mb.Vbuf = mb.W.data, mb.V.data
+        # its own W and V storage, W = V = 0 at the same working level
+        mb.Wflat, mb.Vflat = torch.empty_like(self.Wflat), torch.empty_like(self.Vflat)
         mb.state = new_state(self.m, self.g, refresh_seed=self.cfg["enc_seed"] + 7, col_blocks=nc,
                              T=self.cfg.get("lr_T", 81.0))
+        mb.reset(obj=(1 << 40) + 3 * nc, level=L)
         mb.span_rows = [e - s for s, e in spans]
         mb.batch = batch
         mb.ws = heqg._ws(ctx.nag_ws_bytes(batch, self.degree))

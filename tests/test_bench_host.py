@@ -26,26 +26,42 @@ def test_pmc_traffic_only_for_the_measured_source(tmp_path, monkeypatch):
     src = tmp_path / "kernel.hip"
     src.write_bytes(b"// kernel source A\n")
     pmc = tmp_path / "pmc.json"
-    pmc.write_text(json.dumps({"bytes_per_row": 1000.0,
-                               "kernel_source_sha256": hashlib.sha256(src.read_bytes()).hexdigest()}))
+    pmc.write_text(json.dumps({
+        "kernel_source_sha256": hashlib.sha256(src.read_bytes()).hexdigest(), "batch_blocks": 16, "work_level": 9,
+        "kernels": {"k_conv_cols": {"bytes_per_output_row": 1000.0},
+                    "k_ntt_rows_ks8": {"fetch_bytes_per_dispatch": 300.0, "write_bytes_per_dispatch": 200.0}}}))
     monkeypatch.setattr(bench, "PMC_FILE", str(pmc))
     monkeypatch.setattr(bench, "KERNEL_SRC", str(src))
-    assert bench.pmc_traffic(3.5) == pytest.approx(3500.0)
+    assert bench.pmc_traffic("k_conv_cols", 16, 9, rows=3.5) == pytest.approx(3500.0)
+    assert bench.pmc_traffic("k_ntt_rows_ks8", 16, 9) == pytest.approx(500.0)
+    assert bench.pmc_traffic("k_ntt_rows_ks8", 24, 9) is None    # another chunk size
+    assert bench.pmc_traffic("k_ntt_rows_ks8", 16, 23) is None   # another working level
+    assert bench.pmc_traffic("k_tensor", 16, 9) is None          # not measured
     src.write_bytes(b"// kernel source B\n")       # the kernel changed since the counters were taken
-    assert bench.pmc_traffic(3.5) is None
+    assert bench.pmc_traffic("k_ntt_rows_ks8", 16, 9) is None
     monkeypatch.setattr(bench, "PMC_FILE", str(tmp_path / "missing.json"))
-    assert bench.pmc_traffic(3.5) is None
+    assert bench.pmc_traffic("k_ntt_rows_ks8", 16, 9) is None
 
 
 def test_committed_pmc_summary_is_well_formed():
     with open(bench.PMC_FILE) as f:
         pm = json.load(f)
-    assert pm["bytes_per_row"] > pm["algorithmic_write_bytes_per_row"] > 0
     assert len(pm["kernel_source_sha256"]) == 64
     assert pm["copy_probe"]["write_factor"] == pytest.approx(1.0, abs=0.05)
+    conv = pm["kernels"]["k_conv_cols"]
+    assert conv["bytes_per_output_row"] >= conv["algorithmic_write_bytes_per_row"] > 0
+    ks = pm["kernels"]["k_ntt_rows_ks8"]
+    assert ks["fetch_bytes_per_dispatch"] > 0 and ks["write_bytes_per_dispatch"] > 0
 
 
 def test_iteration_model_bytes_grows_with_the_blocks():
     cfg = synth.get_config("c3")
     one, two = bench.iteration_model_bytes(cfg, 1000), bench.iteration_model_bytes(cfg, 2000)
     assert 0 < one < two < 2 * one   # per-block work plus a once-per-iteration tail
+
+
+def test_iteration_model_bytes_shrink_with_the_working_level():
+    cfg = synth.get_config("c3")
+    top = bench.iteration_model_bytes(cfg, 1000)
+    assert bench.iteration_model_bytes(cfg, 1000, level=len(cfg["q_bits"]) - 1) == top
+    assert bench.iteration_model_bytes(cfg, 1000, level=9) < 0.6 * top

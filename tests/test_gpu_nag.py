@@ -57,11 +57,11 @@ def test_step_errors_before_launch(torch_cuda):
     assert e.value.code == heqg.ERR_KEY
 
 
-def _train_gpu(cfgkey, iters, mini, batch):
+def _train_gpu(cfgkey, iters, mini, batch, level=None):
     from paper_2406_13221_amd.train import EncryptedQGNAG
     cfg = synth.get_config(cfgkey)
     d = synth.make_dataset(cfg)
-    run = EncryptedQGNAG(cfg, d["X"], d["y"], batch=batch, mini_batch=mini)
+    run = EncryptedQGNAG(cfg, d["X"], d["y"], batch=batch, mini_batch=mini, level=level)
     ws = []
     for _ in range(iters):
         run.step()
@@ -84,5 +84,13 @@ def test_c2_minibatch_training_matches_fp64(torch_cuda):
 
 def test_c2_fullbatch_training_matches_fp64(torch_cuda):
     ws, ref, d = _train_gpu("c2", 3, False, 16)
+    for it, w in enumerate(ws):
+        assert np.abs(w - ref["history"][it]["W"]).max() < TOL_W, it
+
+
+def test_c2_training_below_the_top_level_matches_fp64(torch_cuda):
+    """The iteration at a working level below the top (Z, B-bar, W and V at level 6 of 13, refreshed
+    back to it): the circuit's five levels fit, and the decrypted weights follow FP64."""
+    ws, ref, d = _train_gpu("c2", 3, False, 16, level=6)
     for it, w in enumerate(ws):
         assert np.abs(w - ref["history"][it]["W"]).max() < TOL_W, it
