@@ -72,9 +72,9 @@ def boot_steps(N):
     return list(range(1, n1)) + [n1 * g for g in range(1, n2)]
 
 
-def keygen_sparse(ora, seed, h, rot_steps):
-    """The oracle's keys (pk, relinearisation, rotations for rot_steps and the bootstrapping
-    transforms, conjugation) for a sparse ternary secret of weight h."""
+def keygen_sparse(ora, seed, h, rot_steps, dense_steps=True):
+    """The oracle's keys (pk, relinearisation, rotations for rot_steps and, with dense_steps, the
+    dense bootstrapping transforms', conjugation) for a sparse ternary secret of weight h."""
     L, N, nq, nqp = lib(), ora.N, ora.n_q, ora.n_q + ora.n_p
     s = sparse_secret(seed, N, h)
     s_ntt = np.zeros((nqp, N), dtype=np.uint64)
@@ -86,7 +86,7 @@ def keygen_sparse(ora, seed, h, rot_steps):
     L.oracle_mul_pt(ora.ctx, _p(sq), _p(sq), 1, nq - 1, _p(s2))
     rlk = ora._ksk(seed, 0, s_ntt, s2)
     rot = {}
-    gal = [galois_elt(r, N) for r in list(rot_steps) + boot_steps(N)] + [2 * N - 1]
+    gal = [galois_elt(r, N) for r in list(rot_steps) + (boot_steps(N) if dense_steps else [])] + [2 * N - 1]
     for t in gal:
         if t in rot or t == 1:
             continue
@@ -208,6 +208,184 @@ def transform_plaintexts(ora, evalmod=None):
                            diagonal_plaintexts(ora, u0_matrix(ora.N), stc), mono])
 
 
+# ------------------------------------------------------------------ factored slot transforms
+# U0 factors like an FFT.  With w' split as even and odd positions, z_j = E_j + zeta^(e_j) O_j and
+# z_(j+n/2) = E_j - zeta^(e_j) O_j for j < n/2 (n = N/2 slots, e_j = 5^j mod 2N, and
+# e_(j+n/2) = e_j + N mod 2N), where E and O are the same transform of half the size over
+# zeta^2.  Unrolled: U0 = S_0 S_1 ... S_(t-1) R, t = log2 n, R the bit-reversal permutation of the
+# slots, and stage s acting on blocks of 2h slots, h = n / 2^(s+1): for j < h,
+#   (x[b+j], x[b+j+h]) -> (x[b+j] + c_j x[b+j+h], x[b+j] - c_j x[b+j+h]),  c_j = zeta^(2^s (5^j mod 2N/2^s)).
+# Bootstrapping keeps the slots in bit-reversed order between the transforms (EvalMod works slot
+# by slot): CoeffToSlot applies R U0^-1 = S_(t-1)^-1 ... S_0^-1, SlotToCoeff U0 R = S_0 ... S_(t-1),
+# each as a few levels of grouped stages.  A grouped level is a sparse matrix whose nonzero
+# diagonals sit at multiples of its smallest h, evaluated baby-step giant-step over those offsets.
+
+def fft_stage_twiddles(N, s):
+    """c_j for stage s (j < h = N / 2^(s+2))."""
+    h = N >> (s + 2)
+    mod = (2 * N) >> s
+    e = np.array([pow(5, j, mod) for j in range(h)], dtype=np.int64)
+    return np.exp(1j * np.pi * ((e << s) % (2 * N)) / N)
+
+
+def stage_diagonals(N, s, inverse=False):
+    """Stage s (or its inverse, each output halved) as cyclic diagonals {offset: vector},
+    diag_d[x] = M[x][(x + d) mod n]."""
+    n = N // 2
+    h = n >> (s + 1)
+    c = fft_stage_twiddles(N, s)
+    x = np.arange(n)
+    j = x % (2 * h)
+    first = j < h
+    cj = c[np.where(first, j, j - h)]
+    if not inverse:
+        d0 = np.where(first, 1.0 + 0j, -cj)
+        dp = np.where(first, cj, 0j)
+        dm = np.where(first, 0j, 1.0 + 0j)
+    else:
+        # (a, b) -> ((a + b) / 2, (a - b) conj(c) / 2)
+        d0 = np.where(first, 0.5 + 0j, -np.conj(cj) / 2)
+        dp = np.where(first, 0.5 + 0j, 0j)
+        dm = np.where(first, 0j, np.conj(cj) / 2)
+    out = {}
+    for off, v in ((0, d0), (h % n, dp), ((-h) % n, dm)):
+        out[off] = out.get(off, 0) + v
+    return out
+
+
+def diag_product(A, B, n):
+    """Diagonals of A B (B applied first)."""
+    out = {}
+    for d1, a in A.items():
+        for d2, b in B.items():
+            d = (d1 + d2) % n
+            out[d] = out.get(d, 0) + a * np.roll(b, -d1)
+    return out
+
+
+def fft_groups(N, levels):
+    """The t = log2(N/2) stages split into `levels` contiguous groups, as lists of stage indices in
+    the order SlotToCoeff applies them (innermost, h = 1, first); sizes as even as possible, the
+    larger groups first."""
+    t = (N // 2).bit_length() - 1
+    if not 1 <= levels <= t:
+        raise ValueError("levels must be in 1..log2(N/2)")
+    order = list(range(t - 1, -1, -1))
+    sizes = [t // levels + (1 if k < t % levels else 0) for k in range(levels)]
+    out, k = [], 0
+    for sz in sizes:
+        out.append(order[k:k + sz])
+        k += sz
+    return out
+
+
+def transform_levels(N, levels, inverse):
+    """The grouped levels of SlotToCoeff (inverse=False) or CoeffToSlot (inverse=True) in the order
+    they are applied: each a dict(diags={offset: vector}, step=smallest h, d0, K) with the offsets
+    d0 + c step (mod n), c < K."""
+    n = N // 2
+    groups = fft_groups(N, levels)
+    if inverse:
+        groups = [list(reversed(g)) for g in reversed(groups)]
+    out = []
+    for g in groups:
+        M = None
+        for s in g:
+            S = stage_diagonals(N, s, inverse)
+            M = S if M is None else diag_product(S, M, n)
+        step = n >> (max(g) + 1)
+        r = len(g)
+        K = (1 << (r + 1)) - 1
+        if K * step < n:
+            d0 = -((1 << r) - 1) * step
+        else:
+            K, d0 = n // step, 0
+        out.append(dict(diags=M, step=step, d0=d0, K=K))
+    return out
+
+
+def bsgs_shape(K):
+    """n1 (a power of two near sqrt(K)) and n2 = ceil(K / n1)."""
+    n1 = 1
+    while n1 * n1 < K:
+        n1 *= 2
+    return n1, -(-K // n1)
+
+
+def level_plaintexts(ora, lv_spec, lv):
+    """The baby-step giant-step plaintexts of one grouped level for input level lv: entry n1 g + b is
+    the diagonal at offset d0 + (n1 g + b) step rotated right by n1 g step, encoded at scale q_lv."""
+    n = ora.N // 2
+    n1, n2 = bsgs_shape(lv_spec["K"])
+    ql = float(ora.q(lv))
+    out = np.zeros((n1 * n2, ora.N), dtype=np.int64)
+    for c in range(lv_spec["K"]):
+        g = c // n1
+        off = (lv_spec["d0"] + c * lv_spec["step"]) % n
+        v = lv_spec["diags"].get(off)
+        if v is None:
+            continue
+        out[c] = encode(np.roll(v, g * n1 * lv_spec["step"]), ora.N, ql)
+    return out
+
+
+def linear_level(ora, ct, lv_spec, pts=None):
+    """One grouped level: sum_c diag_(d0 + c step) (.) Rot(x, d0 + c step) as
+    sum_g Rot(sum_b P[g][b] (.) Rot(x, d0 + b step), n1 g step), one rescale."""
+    lv = ct.level
+    if lv < 1:
+        raise OracleError("level exhausted")
+    n1, n2 = bsgs_shape(lv_spec["K"])
+    st, d0 = lv_spec["step"], lv_spec["d0"]
+    ql = float(ora.q(lv))
+    if pts is None:
+        pts = level_plaintexts(ora, lv_spec, lv)
+    xb = [ora.rotate(ct, d0 + b * st) if (d0 + b * st) % (ora.N // 2) else ct for b in range(n1)]
+    total = None
+    for g in range(n2):
+        inner = None
+        for b in range(n1):
+            if g * n1 + b >= lv_spec["K"]:
+                break
+            prod = ora.mul_pt(xb[b], ora.pt_from_int(pts[g * n1 + b], lv), ql)
+            inner = prod if inner is None else ora.add(inner, prod)
+        if g:
+            inner = ora.rotate(inner, g * n1 * st)
+        total = inner if total is None else ora.add(total, inner)
+    out = ora.rescale(total)
+    out.scale = ct.scale
+    return out
+
+
+def fft_steps(N, levels):
+    """Rotation steps of the factored transforms (both directions use the same offsets)."""
+    n = N // 2
+    steps = set()
+    for spec in transform_levels(N, levels, False) + transform_levels(N, levels, True):
+        n1, n2 = bsgs_shape(spec["K"])
+        for b in range(n1):
+            o = (spec["d0"] + b * spec["step"]) % n
+            if o:
+                steps.add(o)
+        for g in range(1, n2):
+            steps.add((g * n1 * spec["step"]) % n)
+    return sorted(steps)
+
+
+def coeff_to_slot_fft(ora, ct, levels):
+    """R (2/N) U0^H in `levels` levels: the slots of CoeffToSlot in bit-reversed order."""
+    for spec in transform_levels(ora.N, levels, True):
+        ct = linear_level(ora, ct, spec)
+    return ct
+
+
+def slot_to_coeff_fft(ora, ct, levels):
+    """U0 R in `levels` levels: slots in bit-reversed order back to coefficients."""
+    for spec in transform_levels(ora.N, levels, False):
+        ct = linear_level(ora, ct, spec)
+    return ct
+
+
 class EvalMod:
     """t mod q0 on real slots x = t/s, |t| < K q0: see the module docstring.  taylor: degree of
     the cosine's Taylor polynomial (even, at most 22), r: double-angle steps.  The Taylor
@@ -271,16 +449,17 @@ class EvalMod:
         return ora.mul_const(cosv, q0 / (2.0 * math.pi * s_in), s_in)
 
 
-def bootstrap(ora, ct, evalmod=None):
-    """A level-0 ciphertext -> the same message at level top - (transforms + EvalMod)."""
+def bootstrap(ora, ct, evalmod=None, fft_levels=None):
+    """A level-0 ciphertext -> the same message at level top - (transforms + EvalMod); fft_levels:
+    the factored transforms in that many levels each (slots bit-reversed in between), else dense."""
     em = evalmod or EvalMod()
     q0 = float(ora.q(0))
     t = mod_raise(ora, ct)
-    w = coeff_to_slot(ora, t)
+    w = coeff_to_slot(ora, t) if fft_levels is None else coeff_to_slot_fft(ora, t, fft_levels)
     wc = conjugate(ora, w)
     re2 = ora.add(w, wc)                                   # 2 Re(w)
     im2 = times_i(ora, ora.add(wc, w, sub=True))           # i (conj(w) - w) = 2 Im(w)
     re = em(ora, re2, q0, half=0.5)
     im = em(ora, im2, q0, half=0.5)
     wp = ora.add(re, times_i(ora, im))
-    return slot_to_coeff(ora, wp)
+    return slot_to_coeff(ora, wp) if fft_levels is None else slot_to_coeff_fft(ora, wp, fft_levels)

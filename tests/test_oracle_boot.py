@@ -21,7 +21,7 @@ CFG = dict(log2N=12, q_bits=[60] + [50] * 15, n_p=6, p_bits=60, dnum=3, log2_sca
 @pytest.fixture(scope="module")
 def ora():
     o = Oracle.from_config(CFG)
-    boot.keygen_sparse(o, 31, H, [])
+    boot.keygen_sparse(o, 31, H, sorted(set(boot.fft_steps(o.N, 2)) | set(boot.fft_steps(o.N, 3))))
     return o
 
 
@@ -106,4 +106,82 @@ def test_bootstrap_returns_the_message(ora):
     em = boot.EvalMod(K=K)
     out = boot.bootstrap(o, ct0, em)
     assert out.level == o.top_level - 2 - em.levels()
+    assert np.abs(o.decrypt_values(out) - z).max() < 1e-3
+
+
+def _dense(diags, n):
+    M = np.zeros((n, n), complex)
+    x = np.arange(n)
+    for d, v in diags.items():
+        M[x, (x + d) % n] += v
+    return M
+
+
+def _bitrev(n):
+    t = n.bit_length() - 1
+    return np.array([int(format(i, "0%db" % t)[::-1], 2) for i in range(n)])
+
+
+@pytest.mark.parametrize("N", [16, 64, 256])
+def test_fft_factorisation_of_u0(N):
+    """The stages multiply out to U0 R (R: bit reversal of the slots) and their halved inverses to
+    R (2/N) U0^H, against the plain matrices; every grouping into levels gives the same product and
+    puts each level's nonzero diagonals on its baby-step giant-step offsets."""
+    n = N // 2
+    t = n.bit_length() - 1
+    U0 = boot.u0_matrix(N)
+    R = np.eye(n)[_bitrev(n)]
+    fwd, inv = U0 @ R, R @ ((2.0 / N) * U0.conj().T)
+    P = np.eye(n, dtype=complex)
+    for s in range(t - 1, -1, -1):
+        P = _dense(boot.stage_diagonals(N, s), n) @ P
+    assert np.abs(P - fwd).max() < 1e-12
+    Q = np.eye(n, dtype=complex)
+    for s in range(t):
+        Q = _dense(boot.stage_diagonals(N, s, inverse=True), n) @ Q
+    assert np.abs(Q - inv).max() < 1e-12
+    for levels in range(1, t + 1):
+        for inverse, ref in ((False, fwd), (True, inv)):
+            T = np.eye(n, dtype=complex)
+            for spec in boot.transform_levels(N, levels, inverse):
+                offs = {(spec["d0"] + c * spec["step"]) % n for c in range(spec["K"])}
+                assert {d for d, v in spec["diags"].items() if np.abs(v).max() > 0} <= offs
+                T = _dense(spec["diags"], n) @ T
+            assert np.abs(T - ref).max() < 1e-12, (levels, inverse)
+
+
+@pytest.mark.parametrize("levels", [2, 3])
+def test_factored_coeff_to_slot_is_the_bit_reversed_dense_one(ora, levels):
+    o = ora
+    rng = np.random.default_rng(8)
+    raised = boot.mod_raise(o, _fresh(o, rng.uniform(-1, 1, o.N // 2), 0, 8))
+    dense = o.decrypt_values(boot.coeff_to_slot(o, raised))
+    w = boot.coeff_to_slot_fft(o, raised, levels)
+    assert w.level == raised.level - levels
+    got = o.decrypt_values(w)
+    assert np.abs(got - dense[_bitrev(o.N // 2)]).max() < 1e-3
+    back = boot.slot_to_coeff_fft(o, w, levels)
+    t = _coeffs(o, raised)
+    assert np.abs(o.decrypt_values(back) - decode(t, o.N, raised.scale)).max() < 1e-2
+
+
+# a chain long enough for three levels per factored transform (3 + 12 + 3 levels below the top)
+CFG_LONG = dict(log2N=12, q_bits=[60] + [50] * 19, n_p=7, p_bits=60, dnum=3, log2_scale=50)
+
+
+@pytest.fixture(scope="module")
+def ora_long():
+    o = Oracle.from_config(CFG_LONG)
+    boot.keygen_sparse(o, 33, H, boot.fft_steps(o.N, 3), dense_steps=False)
+    return o
+
+
+def test_factored_bootstrap_returns_the_message(ora_long):
+    o = ora_long
+    rng = np.random.default_rng(9)
+    z = rng.uniform(-1, 1, o.N // 2) + 1j * rng.uniform(-1, 1, o.N // 2)
+    ct0 = _fresh(o, z, 0, 9)
+    em = boot.EvalMod(K=K)
+    out = boot.bootstrap(o, ct0, em, fft_levels=3)
+    assert out.level == o.top_level - 6 - em.levels()
     assert np.abs(o.decrypt_values(out) - z).max() < 1e-3
