@@ -31,7 +31,7 @@ import math
 import numpy as np
 
 from ._lib import lib
-from .ckks import Ct, OracleError, _p, galois_elt
+from .ckks import Ct, OracleError, _p, galois_elt, round_half_away
 from .encode import encode, slot_exponents
 
 PUR_SPARSE = 0x5350415253450000  # purpose tag of the sparse-secret stream
@@ -201,7 +201,7 @@ def transform_plaintexts(ora, evalmod=None):
     at the top level, SlotToCoeff's at the level EvalMod leaves, then X^(N/2)."""
     em = evalmod or EvalMod()
     top = ora.top_level
-    stc = top - 1 - em.levels()
+    stc = top - 1 - em.levels(ora, top - 1)
     mono = np.zeros((1, ora.N), dtype=np.int64)
     mono[0, ora.N // 2] = 1
     return np.concatenate([diagonal_plaintexts(ora, cts_matrix(ora.N), top),
@@ -372,6 +372,25 @@ def fft_steps(N, levels):
     return sorted(steps)
 
 
+def transform_plaintexts_fft(ora, levels, evalmod=None):
+    """Every plaintext the factored transforms of bootstrap(..., fft_levels=levels) use, in the
+    order they are applied: CoeffToSlot's levels from the top, SlotToCoeff's from the level EvalMod
+    leaves, each n1 n2 rows (zero where n1 g + b >= K), then X^(N/2)."""
+    em = evalmod or EvalMod()
+    rows = []
+    lv = ora.top_level
+    for spec in transform_levels(ora.N, levels, True):
+        rows.append(level_plaintexts(ora, spec, lv))
+        lv -= 1
+    lv = ora.top_level - levels - em.levels(ora, ora.top_level - levels)
+    for spec in transform_levels(ora.N, levels, False):
+        rows.append(level_plaintexts(ora, spec, lv))
+        lv -= 1
+    mono = np.zeros((1, ora.N), dtype=np.int64)
+    mono[0, ora.N // 2] = 1
+    return np.concatenate(rows + [mono])
+
+
 def coeff_to_slot_fft(ora, ct, levels):
     """R (2/N) U0^H in `levels` levels: the slots of CoeffToSlot in bit-reversed order."""
     for spec in transform_levels(ora.N, levels, True):
@@ -397,10 +416,24 @@ class EvalMod:
             raise ValueError("even Taylor degree up to 22")
         self.K, self.r, self.taylor = K, r, taylor
 
-    def levels(self):
-        """Levels consumed: the affine map (1), the powers of y and the blocks (5), the double
-        angles (r), the final constant (1)."""
-        return 1 + 5 + self.r + 1
+    @staticmethod
+    def affine_primes(ora, level, s_in, q0, half=1.0, r=5):
+        """Primes the affine map divides by: its constant c = half s_in / (q0 2^r) is small when q0
+        is far above the scale (2^-26 with q0 = 2^60, s = 2^40, r = 5), and one prime leaves the
+        integer k = round(c Delta q_l / s_in) only a few bits; two (k = round(c Delta q_l q_(l-1) / s_in))
+        when one gives fewer than 2^36 and two stay below 2^62.  u is then accurate to 2^-50 or so,
+        which matters because EvalMod's result is scaled up by q0 / (2 pi Delta)."""
+        c = half * s_in / (q0 * 2.0 ** r)
+        k1 = ((c * ora.delta) * float(ora.q(level))) / s_in
+        k2 = (((c * ora.delta) * float(ora.q(level))) * float(ora.q(level - 1))) / s_in
+        return 2 if abs(k1) < 2.0 ** 36 and abs(k2) < 2.0 ** 62 else 1
+
+    def levels(self, ora=None, level=None):
+        """Levels consumed: the affine map (1, or 2 when it divides by two primes for an input at
+        `level` with the context's scale), the powers of y and the blocks (5), the double angles
+        (r), the final constant (1)."""
+        a = 1 if ora is None else self.affine_primes(ora, level, ora.delta, float(ora.q(0)), 0.5, self.r)
+        return a + 5 + self.r + 1
 
     def __call__(self, ora, ct, q0, half=1.0):
         """ct: real slots x (times `half`, the factor of the real/imaginary split, folded in here);
@@ -408,7 +441,13 @@ class EvalMod:
         s_in, delta = ct.scale, ora.delta
         r = self.r
         # v = (u - 1/4) / 2^r with u = x s_in / q0 (one constant product, one constant addition)
-        v = ora.mul_const(ct, half * s_in / (q0 * 2.0 ** r), delta)
+        c = half * s_in / (q0 * 2.0 ** r)
+        if self.affine_primes(ora, ct.level, s_in, q0, half, r) == 1:
+            v = ora.mul_const(ct, c, delta)
+        else:
+            k = round_half_away((((c * delta) * float(ora.q(ct.level))) * float(ora.q(ct.level - 1))) / s_in)
+            v = ora.rescale(ora.rescale(ora.mul_int(ct, k)))
+            v.scale = float(delta)
         v = ora.add_const(v, -0.25 / 2.0 ** r)
         # cos(2 pi v) = sum_k (-1)^k (2 pi)^(2k) / (2k)! y^k, y = v^2, k <= taylor / 2
         kmax = self.taylor // 2

@@ -185,3 +185,38 @@ def test_factored_bootstrap_returns_the_message(ora_long):
     out = boot.bootstrap(o, ct0, em, fft_levels=3)
     assert out.level == o.top_level - 6 - em.levels()
     assert np.abs(o.decrypt_values(out) - z).max() < 1e-3
+
+
+# q0 = 2^60 over a 40-bit scale, as the paper-scale chain: EvalMod's affine constant is then about
+# 2^-26 and needs two primes (an integer of ~2^54 instead of ~2^14)
+CFG40 = dict(log2N=12, q_bits=[60] + [40] * 18, n_p=7, p_bits=60, dnum=3, log2_scale=40)
+
+
+@pytest.fixture(scope="module")
+def ora40():
+    o = Oracle.from_config(CFG40)
+    boot.keygen_sparse(o, 35, H, [], dense_steps=False)
+    return o
+
+
+def test_eval_mod_affine_over_two_primes_at_a_40_bit_scale(ora40, monkeypatch):
+    o = ora40
+    rng = np.random.default_rng(10)
+    n = o.N // 2
+    q0 = float(o.q(0))
+    m = rng.uniform(-1, 1, n)
+    x = m + rng.integers(-K + 1, K, n) * q0 / o.delta
+    ct = _fresh(o, x, o.top_level, 10)
+    em = boot.EvalMod(K=K)
+    assert em.affine_primes(o, o.top_level, o.delta, q0) == 2
+    out = em(o, ct, q0)
+    assert out.level == o.top_level - (2 + 5 + em.r + 1)
+    err = np.abs(o.decrypt_values(out).real - m).max()
+    # with the affine constant on one prime (k ~ 2^14) the same inputs come out about 41 off; on two
+    # about 5.5: what is left is EvalMod's own 40-bit arithmetic (the cosine to ~1e-7 after the
+    # Taylor blocks, x4 per double angle) scaled up by q0 / (2 pi Delta) = 2^17.3, so a q0 this far
+    # above the scale is not bootstrappable with a 40-bit EvalMod
+    monkeypatch.setattr(boot.EvalMod, "affine_primes", staticmethod(lambda *a, **k: 1))
+    bad = np.abs(o.decrypt_values(em(o, ct, q0)).real - m).max()
+    assert bad > 4 * err, (bad, err)
+    assert err < 20, err
