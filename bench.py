@@ -25,9 +25,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# double-angle steps of the bootstrap whose output level the iteration works at (EvalMod with a
-# degree-20 Taylor cosine covers |I| < 16 with r = 5)
-BOOT_R = 5
+# the bootstrap whose output level the iteration works at: EvalMod with r = 5 double angles and a
+# degree-20 Taylor cosine (|I| < 16 with a weight-64 sparse secret), slot transforms factored into 2
+# levels each (the dense form needs N/2 plaintexts per transform)
+BOOT_R, BOOT_LEVELS, BOOT_TAYLOR, BOOT_WEIGHT = 5, 2, 20, 64
 # FP64 vector issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz instructions per second (the published
 # 78.6 TFLOP/s counts each FMA as two flops)
 FP64_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -39,10 +40,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cfg, data, n_blocks):
+def cpu_baseline(cfg, data, n_blocks, work=None):
     """The oracle timed on a bounded sample of the same iteration: the whole iteration (per-block
     pipeline and the once-per-iteration tail) over 1 and over 3 blocks; the difference gives the
-    per-block cost, the rest is the tail; the iteration over all blocks is extrapolated from both."""
+    per-block cost, the rest is the tail; the iteration over all blocks is extrapolated from both.
+    Z and B-bar sit at the top level, W and V at `work` (default: the top), as on the GPU."""
     import numpy as np
     from oracle import circuit, trainer
     from oracle.ckks import Oracle
@@ -53,14 +55,16 @@ def cpu_baseline(cfg, data, n_blocks):
     o.keygen(cfg["key_seed"], circuit.rot_steps(m, g))
     X, y = data["X"][:3 * m], data["y"][:3 * m]
     blocks = circuit.pack_blocks(trainer.build_Z(X, y, g), m, g, o.N)
+    from paper_2406_13221_amd.train import SIGMOID_SCALE
     L = o.top_level
+    work = L if work is None else work
     Zc = [o.encrypt(encode(blocks[b], o.N, o.delta), L, o.delta, cfg["enc_seed"], b) for b in range(3)]
     B = trainer.bbar(X, g)
     sB = 2.0 ** 50 / B.max()
     Bc = o.encrypt(encode(circuit.replicate_row(B, m, g), o.N, sB), L, sB, cfg["enc_seed"], 10)
-    W = o.encrypt(np.zeros(o.N, np.int64), L, o.delta, cfg["enc_seed"], 11)
-    V = o.encrypt(np.zeros(o.N, np.int64), L, o.delta, cfg["enc_seed"], 12)
-    masks = circuit.make_masks(o, m, g, trainer.G8, L, o.delta)
+    W = o.encrypt(np.zeros(o.N, np.int64), work, o.delta, cfg["enc_seed"], 11)
+    V = o.encrypt(np.zeros(o.N, np.int64), work, o.delta, cfg["enc_seed"], 12)
+    masks = circuit.make_masks(o, m, g, trainer.G8, work, SIGMOID_SCALE)
     times = {}
     for nb in (1, 3):
         t0 = time.perf_counter()
@@ -70,9 +74,9 @@ def cpu_baseline(cfg, data, n_blocks):
     tail = max(times[1] - per_block, 0.0)
     return dict(value=tail + per_block * n_blocks, unit="s/iter", cores=threads, kind="oracle",
                 sample="the full iteration (per-block pipeline + once-per-iteration tail) over 1 and over 3 "
-                       "of the %d blocks at the same parameters: %.1f s and %.1f s, i.e. %.2f s per block and "
-                       "%.2f s for the tail, extrapolated to %d blocks" % (n_blocks, times[1], times[3], per_block,
-                                                                          tail, n_blocks))
+                       "of the %d blocks at the same parameters and levels (W and V at level %d): %.1f s and %.1f s, "
+                       "i.e. %.2f s per block and %.2f s for the tail, extrapolated to %d blocks"
+                       % (n_blocks, work, times[1], times[3], per_block, tail, n_blocks))
 
 
 def iteration_model_bytes(cfg, n_blocks, degree=3, level=None):
@@ -273,9 +277,11 @@ def main():
     ap.add_argument("--work-level", default="boot",
                     help="level of W and V, the level they are refreshed to: 'boot' (the level heqg_bootstrap "
                          "returns with 5 double angles), 'top', or a number")
+    ap.add_argument("--boot-reps", type=int, default=2,
+                    help="timed bootstraps of W and V at these parameters (0: skip)")
     ap.add_argument("--top-steps", type=int, default=1,
                     help="timed iterations with W and V at the top level")
-    ap.add_argument("--paper-q-steps", type=int, default=1,
+    ap.add_argument("--paper-q-steps", type=int, default=0,
                     help="timed iterations at the paper's working modulus (Table 1: Q = 2^275)")
     ap.add_argument("--no-ntt-probe", dest="ntt_probe", action="store_false",
                     help="skip the full-batch NTT throughput leg (keeps per-kernel profiles to the iteration)")
@@ -312,7 +318,7 @@ def main():
     t0 = time.perf_counter()
     run = EncryptedQGNAG(cfg, data["X"], data["y"], batch=args.batch)
     top = run.ctx.top_level
-    work = {"top": top, "boot": run.ctx.boot_shape(BOOT_R)[3] - 1}.get(args.work_level)
+    work = {"top": top, "boot": run.ctx.boot_shape(BOOT_R, BOOT_LEVELS)[2]}.get(args.work_level)
     work = int(args.work_level) if work is None else work
     if work != top:
         run.reset(obj=(1 << 40) + 1, level=work)
@@ -542,7 +548,7 @@ def main():
                                % (cfg["name"], top, work),
                    "n_samples": cfg["n_train"], "n_features": cfg["n_features"], "log2N": cfg["log2N"],
                    "limbs": len(cfg["q_bits"]), "dnum": cfg["dnum"], "blocks": run.Z.count,
-                   "z_level": top, "work_level": work,
+                   "z_level": top, "work_level": work, "work_log2_modulus": int(sum(cfg["q_bits"][:work + 1])),
                    "rows_per_block": cfg["m"], "cols": cfg["g"], "batch_blocks": run.batch},
         "fp64_check": fp64_check,
         "update_s": round(upd, 4),
@@ -564,6 +570,52 @@ def main():
         log("encrypted scoring of %d validation rows: %.3f s; sample AUROC %.5f (plain %.5f)" %
             (scoring["rows"], scoring["score_s"], scoring["sample_auroc_encrypted"], scoring["sample_auroc_plain"]))
     out["validation_scoring"] = scoring
+
+    # CKKS bootstrapping at these parameters, the refresh the paper runs once per iteration (Table 1):
+    # a key set on a sparse secret (weight 64) with the factored transforms' rotations and the
+    # conjugation; W and V of the run above, decrypted and encrypted again at level 0 under it, are
+    # bootstrapped together; time per bootstrap of the pair and the error of the decrypted result
+    boot_leg = None
+    if args.boot_reps > 0:
+        import numpy as np
+        ctx = run.ctx
+        t0 = time.perf_counter()
+        kb = ctx.keygen(cfg["key_seed"] + 1, ctx.boot_steps(BOOT_LEVELS), hamming=BOOT_WEIGHT, conj=True)
+        torch.cuda.synchronize()
+        t_keys = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        pts = ctx.boot_encode(BOOT_R, BOOT_LEVELS)
+        t_enc = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        bt = ctx.boot_setup(pts, BOOT_R, BOOT_TAYLOR, levels=BOOT_LEVELS)
+        t_setup = time.perf_counter() - t0
+        del pts
+        zs = [ctx.decrypt_values(run.keys, c) for c in (run.W, run.V)]
+        ct = ctx.encrypt(kb, np.stack([ctx.encode(z, ctx.delta) for z in zs]), 0, ctx.delta, cfg["enc_seed"] + 11,
+                         1 << 43)
+        ws = heqg._ws(heqg.lib().heqg_boot_ws_bytes(ctx.h, BOOT_LEVELS, ct.count))
+        out_b = ctx.bootstrap(kb, bt, ct, ws=ws)      # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.boot_reps):
+            out_b = ctx.bootstrap(kb, bt, ct, ws=ws)
+        torch.cuda.synchronize()
+        t_boot = (time.perf_counter() - t0) / args.boot_reps
+        err = max(float(np.abs(ctx.decrypt_values(kb, out_b, index=i) - zs[i]).max()) for i in range(2))
+        cl, sl, ol, npts = ctx.boot_shape(BOOT_R, BOOT_LEVELS)
+        boot_leg = {"ciphertexts": 2, "s_per_bootstrap": round(t_boot, 4), "levels_per_transform": BOOT_LEVELS,
+                    "double_angles": BOOT_R, "taylor_degree": BOOT_TAYLOR, "secret_weight": BOOT_WEIGHT,
+                    "input_level": 0, "output_level": ol, "rotation_keys": len(kb.galois), "plaintexts": npts,
+                    "keygen_s": round(t_keys, 3), "encode_s": round(t_enc, 3), "setup_s": round(t_setup, 3),
+                    "max_abs_err": err,
+                    "note": "real bootstrapping of W and V; at a 40-bit scale with q0 = 2^60, EvalMod's error "
+                            "is scaled up by q0 / (2 pi Delta) = 2^17.3, so the result is not usable as a refresh "
+                            "and the iteration keeps the key holder's"}
+        log("bootstrap of W and V at N=2^16 (%d levels per transform): %.3f s, output level %d, max|err| %.2e"
+            % (BOOT_LEVELS, t_boot, ol, err))
+        del kb, bt, ct, out_b, ws
+        torch.cuda.empty_cache()
+    out["bootstrap"] = boot_leg
 
     # the same iteration with W and V at the top of the chain (as a refresh that returned them there
     # would leave them; no bootstrap can): seconds per iteration from W = V = 0
@@ -674,7 +726,7 @@ def main():
         del src, dst
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(cfg, data, n_blocks)
+        out["cpu_baseline"] = cpu_baseline(cfg, data, n_blocks, work)
     print(json.dumps(out), flush=True)
 
 

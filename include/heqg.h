@@ -596,13 +596,14 @@ int heqg_graph_count(const heqg_ctx* ctx);
 /*
  * The scheme's bootstrap in the full-RNS form of Cheon, Han, Kim, Kim and
  * Song, which the paper takes from HEAAN: a level-0 two-part ciphertext ->
- * the same message at level stc_level - 1 (heqg_boot_shape), without the
+ * the same message at the output level of heqg_boot_shape, without the
  * secret key.  Its steps, each also an entry point:
  *   ModRaise     the centred coefficients mod q0 read at the top level
  *                (decrypts to t = m + q0 I, I a small integer polynomial);
  *   CoeffToSlot  slots -> (2/N) U0^H slots, U0[j][k] = zeta_j^k,
  *                zeta_j = exp(i pi 5^j / N): t's low and high coefficient
- *                halves over the scale become the real and imaginary parts;
+ *                halves over the scale become the real and imaginary parts
+ *                (in bit-reversed slot order with the factored transforms);
  *   split        2 Re = w + conj(w), 2 Im = i (conj(w) - w) (the conjugation
  *                key; i is the monomial X^(N/2)), inside heqg_bootstrap;
  *   EvalMod      x -> (t mod q0) / s for real slots x = t / s:
@@ -610,50 +611,71 @@ int heqg_graph_count(const heqg_ctx* ctx);
  *                polynomial of the given degree in y = v^2 evaluated as
  *                B0(y) + y^4 B1(y) + y^8 B2(y), r double angles
  *                c <- 2 c^2 - 1 (giving sin(2 pi t / q0)), times q0 / (2 pi s);
- *                level cost 7 + r;
+ *                level cost 7 + r, or 8 + r when the affine map's constant
+ *                c = half s / (q0 2^r) would get fewer than 36 bits on one
+ *                prime (round(c Delta q_l / s) < 2^36) and fits on two: then
+ *                it multiplies by round(c Delta q_l q_(l-1) / s) and rescales
+ *                twice (q0 = 2^60 over a 40-bit scale needs it);
  *   SlotToCoeff  slots -> U0 slots.
- * The slot transforms are baby-step giant-step products
- * sum_g Rot(sum_b P[g][b] (.) Rot(x, b), n1 g), n1 n2 = N/2, with the
- * plaintext P[g][b] = diagonal n1 g + b of the matrix rotated right by n1 g,
- * encoded at scale q_level of the transform's input level so that the one
- * rescale returns the input scale.  The keys need the rotations
- * heqg_boot_steps lists and the conjugation (heqg_keygen_ex with conj); a
- * sparse secret (weight 64 with r = 5 and degree 20) keeps |I| within the
- * interval of 16 that EvalMod covers.  Every step is the scheme's operation on
- * exact residues with the oracle's level and scale bookkeeping (the same
- * sequence of FP64 operations), so results are reproducible residue for
- * residue.  The dense diagonals take (n1 n2) plaintexts per transform: meant
- * for ring degrees up to 2^13 or so.
+ * The slot transforms come in two forms, chosen by `levels` (per transform):
+ *   levels = 0, dense: one level, slots -> A slots with all N/2 diagonals of A,
+ *     CoeffToSlot A = (2/N) U0^H, SlotToCoeff A = U0 (meant for ring degrees up
+ *     to about 2^13: (N/2) plaintexts per transform);
+ *   levels >= 1, factored: U0 = S_0 ... S_(t-1) R, t = log2(N/2), R the bit
+ *     reversal of the slots and S_s a radix-2 butterfly over blocks of 2h
+ *     slots, h = (N/2) / 2^(s+1), (a, b) -> (a + c_j b, a - c_j b) with
+ *     c_j = zeta^(2^s (5^j mod 2N/2^s)); CoeffToSlot applies R U0^-1 (stages
+ *     halved and inverted), SlotToCoeff U0 R, so the slots are bit-reversed
+ *     between them (EvalMod works slot by slot).  The t stages are split into
+ *     `levels` contiguous groups (sizes as even as possible, larger first,
+ *     SlotToCoeff's innermost group, h = 1, first); a group of r stages with
+ *     smallest half-width `step` has its nonzero diagonals at offsets
+ *     d0 + c step, c < K, with K = 2^(r+1) - 1 and d0 = -(2^r - 1) step, or
+ *     K = (N/2)/step and d0 = 0 when those would wrap.
+ * Each level costs one level of the chain: sum_g Rot(sum_b P[g][b] (.)
+ * Rot(x, d0 + b step), n1 g step) with n1 the power of two nearest above
+ * sqrt(K), n2 = ceil(K / n1), and P[g][b] the diagonal at offset
+ * d0 + (n1 g + b) step rotated right by n1 g step, encoded at scale q_level of
+ * the level's input level so that its rescale returns the input scale.  The
+ * keys need the rotations heqg_boot_steps lists and the conjugation
+ * (heqg_keygen_ex with conj); a sparse secret (weight 64 with r = 5 and degree
+ * 20) keeps |I| within the interval of 16 that EvalMod covers.  The level and
+ * scale bookkeeping follows the oracle's FP64 operations, so the residues are
+ * reproducible.
  *
- * heqg_boot_steps: writes the rotation steps to steps (may be NULL) and
- * returns their number.
- * heqg_boot_shape: n1, n2 and the input levels of CoeffToSlot (the top) and
- * SlotToCoeff for r double angles; HEQG_ERR_LEVEL when the chain is too short.
- * heqg_boot_encode (host): the transforms' plaintexts in coefficient form into
- * coeffs[2 n1 n2 + 1][N]: CoeffToSlot's P[g][b] (index n1 g + b), then
- * SlotToCoeff's, then X^(N/2); over `threads` host threads (<= 0: all).
+ * heqg_boot_steps: writes the rotation steps to steps (may be NULL; distinct,
+ * ascending, in 1..N/2-1) and returns their number.
+ * heqg_boot_shape: the input levels of CoeffToSlot (the top) and SlotToCoeff,
+ * the output level of heqg_bootstrap and the number of plaintexts
+ * (sum over levels of n1 n2, plus 1); HEQG_ERR_LEVEL when the chain is too
+ * short for r double angles and these levels.
+ * heqg_boot_encode (host): every plaintext in coefficient form into
+ * coeffs[n_pts][N]: CoeffToSlot's levels in the order applied, each n1 n2
+ * plaintexts (index n1 g + b; zero for n1 g + b >= K), then SlotToCoeff's,
+ * then X^(N/2); over `threads` host threads (<= 0: all).
  * heqg_boot_setup: loads such coefficients (device int64, same layout) into
  * dev (>= heqg_boot_bytes) in NTT form; the handle refers to dev, which the
  * caller owns; heqg_boot_destroy frees the handle only.
- * Each evaluation call takes a workspace of heqg_boot_ws_bytes(ctx, count)
- * and a batch of count two-part ciphertexts; out->scale is written:
+ * Each evaluation call takes a workspace of heqg_boot_ws_bytes(ctx, levels,
+ * count) and a batch of count two-part ciphertexts; out->scale is written:
  *   heqg_mod_raise      in level 0 -> out at the top level (no keys);
- *   heqg_coeff_to_slot  in at the top level -> out one level lower;
- *   heqg_eval_mod       in at level l >= 7 + r -> out at l - 7 - r, scale kept;
- *   heqg_slot_to_coeff  in at stc_level -> out at stc_level - 1;
- *   heqg_bootstrap      in level 0 -> out at stc_level - 1.
+ *   heqg_coeff_to_slot  in at the top level -> out max(levels, 1) lower;
+ *   heqg_eval_mod       in at level l -> out at l - (7 or 8) - r, scale kept;
+ *   heqg_slot_to_coeff  in at the SlotToCoeff level -> out at the output level;
+ *   heqg_bootstrap      in level 0 -> out at the output level.
  * HEQG_ERR_ARG for a wrong level, shape or workspace; HEQG_ERR_KEY when a
  * rotation or the conjugation key is missing.
  */
 typedef struct heqg_boot heqg_boot;
-int heqg_boot_steps(const heqg_ctx* ctx, int* steps);
-int heqg_boot_shape(const heqg_ctx* ctx, int r, int* n1, int* n2, int* cts_level, int* stc_level);
-int heqg_boot_encode(const heqg_ctx* ctx, int r, int64_t* coeffs, int threads);
-size_t heqg_boot_bytes(const heqg_ctx* ctx, int r);
-int heqg_boot_setup(heqg_ctx* ctx, const int64_t* dev_coeffs, int r, int taylor, void* dev, size_t bytes,
+int heqg_boot_steps(const heqg_ctx* ctx, int levels, int* steps);
+int heqg_boot_shape(const heqg_ctx* ctx, int r, int levels, int* cts_level, int* stc_level, int* out_level,
+                    int64_t* n_pts);
+int heqg_boot_encode(const heqg_ctx* ctx, int r, int levels, int64_t* coeffs, int threads);
+size_t heqg_boot_bytes(const heqg_ctx* ctx, int r, int levels);
+int heqg_boot_setup(heqg_ctx* ctx, const int64_t* dev_coeffs, int r, int levels, int taylor, void* dev, size_t bytes,
                     heqg_boot** out, hipStream_t stream);
 void heqg_boot_destroy(heqg_boot* boot);
-size_t heqg_boot_ws_bytes(const heqg_ctx* ctx, int64_t count);
+size_t heqg_boot_ws_bytes(const heqg_ctx* ctx, int levels, int64_t count);
 int heqg_mod_raise(heqg_ctx* ctx, const heqg_ct_batch* in, heqg_ct_batch* out, void* ws, size_t ws_bytes,
                    hipStream_t stream);
 int heqg_coeff_to_slot(heqg_ctx* ctx, const heqg_keys* keys, const heqg_boot* boot, const heqg_ct_batch* in,

@@ -11,11 +11,15 @@
 //                Taylor series in y = v^2 as B0(y) + y^4 B1(y) + y^8 B2(y), r double angles
 //                c <- 2 c^2 - 1, times q0 / (2 pi s): t mod q0 as (q0 / 2 pi) sin(2 pi t / q0);
 //   SlotToCoeff  w' = Re' + i Im' -> U0 w'.
-// The slot transforms are sum_g Rot(sum_b P[g][b] * Rot(x, b), n1 g) with the caller's encoded
-// diagonal plaintexts P (one launch per g for the inner sum), one rescale each.  Every step is
-// the operation of the scheme on exact residues, and the level and scale bookkeeping is the
-// same sequence of FP64 operations as the CPU implementation's, so the results match it residue
-// for residue.
+// The slot transforms are either dense (one level: the N/2 diagonals of the whole matrix) or
+// factored (the FFT of the embedding, U0 = S_0 ... S_(t-1) R with radix-2 stages and R the bit
+// reversal of the slots, grouped into a few levels; CoeffToSlot applies R U0^-1, SlotToCoeff U0 R,
+// so the slots stay bit-reversed through EvalMod, which works slot by slot).  Each level is
+// sum_g Rot(sum_b P[g][b] (.) Rot(x, d0 + b step), n1 g step) over its nonzero diagonals at offsets
+// d0 + c step, with the caller's encoded plaintexts P (one launch per g for the inner sum) and one
+// rescale.  Every step is the operation of the scheme on exact residues, and the level and scale
+// bookkeeping is the same sequence of FP64 operations as the CPU implementation's, so the results
+// match it residue for residue.
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -27,29 +31,101 @@
 
 #include "ops.h"
 
+// one level of a slot transform: offsets d0 + c step (mod N/2), c < K, baby-step giant-step n1 x n2,
+// plaintexts [n1 n2][in_level + 1][N] in NTT form
+struct BootLevel {
+  int step, d0, K, n1, n2, in_level;
+  uint64_t* pts;
+};
+
 struct heqg_boot {
-  int n1, n2;            // baby and giant steps of the slot transforms (n1 n2 = N/2)
-  int top, stc_level;    // levels of the two transforms
-  int r, taylor;         // EvalMod: double angles, Taylor degree of the cosine
-  uint64_t* cts;         // [n2][n1][top + 1][N]       CoeffToSlot diagonals, NTT form
-  uint64_t* stc;         // [n2][n1][stc_level + 1][N] SlotToCoeff diagonals
-  uint64_t* mono;        // X^(N/2) at the top level, NTT form
+  int top, levels;           // levels per transform (0: dense)
+  int stc_level, out_level;  // input level of SlotToCoeff, output level of the bootstrap
+  int r, taylor;             // EvalMod: double angles, Taylor degree of the cosine
+  std::vector<BootLevel> cts, stc;
+  uint64_t* mono;            // X^(N/2) at the top level, NTT form
 };
 
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
-void bsgs(int N, int* n1, int* n2) {
-  int lg = 0;
-  while ((1 << lg) < N / 2) ++lg;
-  *n1 = 1 << ((lg + 1) / 2);
-  *n2 = (N / 2) / *n1;
+int log2i(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
 }
 
-// levels EvalMod consumes: the affine map, the powers of y and the blocks, r double angles, the
-// final constant
-int evalmod_levels(int r) { return 1 + 5 + r + 1; }
+// n1: the power of two nearest above sqrt(K); n2 = ceil(K / n1)
+void bsgs_shape(int K, int* n1, int* n2) {
+  int a = 1;
+  while ((int64_t)a * a < K) a *= 2;
+  *n1 = a;
+  *n2 = (K + a - 1) / a;
+}
+
+// The levels of a transform in the order they are applied (levels == 0: one dense level).
+// Factored: the t = log2(N/2) stages split into `levels` contiguous groups (sizes as even as
+// possible, larger first), in SlotToCoeff's order (innermost stage, h = 1, first); CoeffToSlot
+// applies the inverse groups in reverse order.  A group with stages s of half-width
+// h = (N/2) / 2^(s+1) has its nonzero diagonals at multiples of its smallest h: K = 2^(r+1) - 1
+// offsets from -(2^r - 1) step, or all (N/2) / step of them when those wrap around.
+struct Spec {
+  int step, d0, K;
+  std::vector<int> stages;  // in the order they are applied
+};
+std::vector<Spec> level_specs(int N, int levels, bool inverse) {
+  const int n = N / 2, t = log2i(n);
+  std::vector<Spec> out;
+  if (levels == 0) {
+    out.push_back(Spec{1, 0, n, {}});
+    return out;
+  }
+  std::vector<std::vector<int>> groups;
+  for (int k = 0, s = t - 1; k < levels; ++k) {
+    const int sz = t / levels + (k < t % levels ? 1 : 0);
+    std::vector<int> g;
+    for (int i = 0; i < sz; ++i) g.push_back(s--);
+    groups.push_back(g);
+  }
+  if (inverse) {
+    std::reverse(groups.begin(), groups.end());
+    for (auto& g : groups) std::reverse(g.begin(), g.end());
+  }
+  for (auto& g : groups) {
+    const int smax = *std::max_element(g.begin(), g.end());
+    const int step = n >> (smax + 1), r = (int)g.size();
+    int K = (1 << (r + 1)) - 1, d0 = -((1 << r) - 1) * step;
+    if ((int64_t)K * step >= n) {
+      K = n / step;
+      d0 = 0;
+    }
+    out.push_back(Spec{step, d0, K, g});
+  }
+  return out;
+}
+
+int mod_n(int64_t v, int n) { return (int)(((v % n) + n) % n); }
+
+// Primes EvalMod's affine map divides by.  Its constant c = half s / (q0 2^r) is small when q0 is
+// far above the scale (2^-26 with q0 = 2^60, s = 2^40, r = 5), and one prime leaves the integer
+// k = round(c Delta q_l / s) only a few bits; two (k = round(c Delta q_l q_(l-1) / s)) when one gives
+// fewer than 2^36 and two stay below 2^62, so that u keeps the precision EvalMod's final scaling by
+// q0 / (2 pi Delta) needs.
+int affine_primes(const heqg_ctx* c, int level, double s_in, double half, int r) {
+  if (level < 1) return 1;
+  const double q0 = (double)c->primes[0];
+  const double cst = half * s_in / (q0 * std::ldexp(1.0, r));
+  const double k1 = ((cst * c->delta) * (double)c->primes[level]) / s_in;
+  const double k2 = (((cst * c->delta) * (double)c->primes[level]) * (double)c->primes[level - 1]) / s_in;
+  return std::fabs(k1) < std::ldexp(1.0, 36) && std::fabs(k2) < std::ldexp(1.0, 62) ? 2 : 1;
+}
+
+// levels EvalMod consumes on an input at `level` and scale s_in: the affine map (1 or 2), the
+// powers of y and the blocks (5), r double angles, the final constant
+int evalmod_levels(const heqg_ctx* c, int level, double s_in, double half, int r) {
+  return affine_primes(c, level, s_in, half, r) + 5 + r + 1;
+}
 
 struct Fail {
   int code;
@@ -165,30 +241,37 @@ struct Run {
     return o;
   }
 
-  // slots -> A slots with the diagonal plaintexts P[g][b] (rows 0..level of N words, stride pst):
-  // x and its baby-step rotations go to the region xb (term stride xs), so that one launch per
-  // giant step forms sum_b P[g][b] (.) Rot(x, b)
+  // one level of a slot transform: x and its baby-step rotations Rot(x, d0 + b step) go to the
+  // region xb (term stride xs), so that one launch per giant step forms sum_b P[g][b] (.) x_b
   uint64_t* xb = nullptr;
   int64_t xs = 0;
-  B linear(const B& x, const uint64_t* P, int64_t pst, int n1, int n2) {
-    const int l = x.level;
+  B linear(const B& x, const BootLevel& L) {
+    const int l = x.level, n = N() / 2;
     if (l < 1) fail(HEQG_ERR_LEVEL, "level exhausted");
+    if (l != L.in_level) fail(HEQG_ERR_ARG, "internal: transform level");
     const CtV xv0{xb, count > 1 ? 2 * ps() : 0, ps()};
-    k_copy_launch(c->g, v(x), xv0, count, 2, l + 1, s);
-    for (int b = 1; b < n1; ++b) {
-      const int64_t half = N() / 2;
-      const uint64_t gal = h_pow(5, (uint64_t)(b % half), 2 * (uint64_t)N());
+    for (int b = 0; b < L.n1; ++b) {
+      const int off = mod_n((int64_t)L.d0 + (int64_t)b * L.step, n);
+      const CtV dst{xb + b * xs, count > 1 ? 2 * ps() : 0, ps()};
+      if (off == 0) {
+        k_copy_launch(c->g, v(x), dst, count, 2, l + 1, s);
+        continue;
+      }
+      const uint64_t gal = h_pow(5, (uint64_t)off, 2 * (uint64_t)N());
       if (!ops::rot_key(k, gal)) fail(HEQG_ERR_KEY, "missing rotation key");
-      int rc = ops::rotate(c, k, v(x), CtV{xb + b * xs, count > 1 ? 2 * ps() : 0, ps()}, count, l, gal, ks_ws, s);
+      int rc = ops::rotate(c, k, v(x), dst, count, l, gal, ks_ws, s);
       if (rc) fail(rc, "rotate");
     }
+    const int64_t pst = (int64_t)(l + 1) * N();
     B total{};
     bool have = false;
-    for (int g = 0; g < n2; ++g) {
+    for (int g = 0; g < L.n2; ++g) {
+      const int terms = std::min(L.n1, L.K - g * L.n1);
       B inner = get(2, l, x.scale * q(l));
-      k_mul_pt_sum_launch(c->g, c->t, xv0, xs, P + (int64_t)g * n1 * pst, pst, n1, v(inner), count, l + 1, s);
+      k_mul_pt_sum_launch(c->g, c->t, xv0, xs, L.pts + (int64_t)g * L.n1 * pst, pst, terms, v(inner), count, l + 1,
+                          s);
       if (g) {
-        B r = rotate(inner, n1 * g);
+        B r = rotate(inner, g * L.n1 * L.step);
         put(inner);
         inner = r;
       }
@@ -204,8 +287,16 @@ struct Run {
     }
     B o = rescale(total);
     put(total);
-    o.scale = x.scale;  // the diagonals carry exactly the factor q_l the rescale divides by
+    o.scale = x.scale;  // the plaintexts carry exactly the factor q_l the rescale divides by
     return o;
+  }
+  B transform(B x, const std::vector<BootLevel>& levels) {
+    for (const BootLevel& L : levels) {
+      B y = linear(x, L);
+      put(x);
+      x = y;
+    }
+    return x;
   }
 
   // a batch into a workspace slot (the pool layout), and back
@@ -244,9 +335,26 @@ struct Run {
 
   B evalmod(const B& x, double q0, double half, int r, int taylor) {
     const double s_in = x.scale, delta = c->delta;
-    B v = mul_const(x, half * s_in / (q0 * std::ldexp(1.0, r)), delta);
-    B va = add_const(v, -0.25 / std::ldexp(1.0, r));
-    put(v);
+    const double ca = half * s_in / (q0 * std::ldexp(1.0, r));
+    B aff{};
+    if (affine_primes(c, x.level, s_in, half, r) == 1) {
+      aff = mul_const(x, ca, delta);
+    } else {
+      // times the integer round(ca Delta q_l q_(l-1) / s_in), then two rescales
+      const double kv = (((ca * delta) * q(x.level)) * q(x.level - 1)) / s_in;
+      if (!(std::fabs(kv) < 4611686018427387904.0)) fail(HEQG_ERR_OVERFLOW, "constant overflow");
+      std::vector<uint64_t> kr;
+      ops::const_residues(c, std::llround(kv), x.level, kr);
+      B t = get(x.n_poly, x.level, s_in);
+      k_mul_scalar_launch(c->g, c->t, v(x), v(t), count, x.n_poly, x.level + 1, kr.data(), s);
+      B r1 = rescale(t);
+      put(t);
+      aff = rescale(r1);
+      put(r1);
+      aff.scale = delta;
+    }
+    B va = add_const(aff, -0.25 / std::ldexp(1.0, r));
+    put(aff);
     const int kmax = taylor / 2;
     std::vector<double> cf(kmax + 1);
     double fact = 1.0;
@@ -330,11 +438,23 @@ bool shape_ok(const heqg_ctx* c, const heqg_ct_batch* b, int level, const char* 
   return true;
 }
 
+// the largest baby-step count of either transform
+int max_n1(int N, int levels) {
+  int m = 1;
+  for (int inv = 0; inv < 2; ++inv)
+    for (const Spec& sp : level_specs(N, levels, inv != 0)) {
+      int n1, n2;
+      bsgs_shape(sp.K, &n1, &n2);
+      m = std::max(m, n1);
+    }
+  return m;
+}
+
 // Validates the batches and the workspace, lays the workspace out and runs body(R, x) on the
 // input loaded into the pool; the result goes to out.
 template <class F>
-int run(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch* in, int in_level, heqg_ct_batch* out, int out_level,
-        void* ws, size_t ws_bytes, hipStream_t s, const char* what, F body) {
+int run(heqg_ctx* c, const heqg_keys* k, int levels, const heqg_ct_batch* in, int in_level, heqg_ct_batch* out,
+        int out_level, void* ws, size_t ws_bytes, hipStream_t s, const char* what, F body) {
   if (!c) {
     set_err(std::string(what) + ": null context");
     return HEQG_ERR_ARG;
@@ -344,7 +464,7 @@ int run(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch* in, int in_level, 
     set_err(std::string(what) + ": input and output counts differ");
     return HEQG_ERR_ARG;
   }
-  if (!ws || ws_bytes < heqg_boot_ws_bytes(c, in->count)) {
+  if (!ws || ws_bytes < heqg_boot_ws_bytes(c, levels, in->count)) {
     set_err(std::string(what) + ": workspace smaller than heqg_boot_ws_bytes");
     return HEQG_ERR_ARG;
   }
@@ -381,130 +501,275 @@ bool boot_ok(const heqg_ctx* c, const heqg_keys* k, const heqg_boot* bt, const c
   return true;
 }
 
-}  // namespace
-
-extern "C" int heqg_boot_steps(const heqg_ctx* c, int* steps) {
-  if (!c) {
-    set_err("boot_steps: null ctx");
-    return HEQG_ERR_ARG;
+bool levels_ok(const heqg_ctx* c, int levels, const char* what) {
+  if (!c || levels < 0 || levels > log2i(c->g.N / 2)) {
+    set_err(std::string(what) + ": levels per transform must be 0 (dense) .. log2(N/2)");
+    return false;
   }
-  int n1, n2;
-  bsgs(c->g.N, &n1, &n2);
-  const int n = (n1 - 1) + (n2 - 1);
-  if (steps) {
-    int i = 0;
-    for (int b = 1; b < n1; ++b) steps[i++] = b;
-    for (int g = 1; g < n2; ++g) steps[i++] = n1 * g;
-  }
-  return n;
+  return true;
 }
 
-extern "C" int heqg_boot_shape(const heqg_ctx* c, int r, int* n1, int* n2, int* cts_level, int* stc_level) {
-  if (!c || r < 1) {
-    set_err("boot_shape: bad argument");
-    return HEQG_ERR_ARG;
+// Diagonals {offset: vector of n complex} of one stage of U0 R (or of its halved inverse):
+// blocks of 2h slots, h = n / 2^(s+1); for j < h with c_j = zeta^(2^s (5^j mod 2N/2^s)):
+// forward (a, b) -> (a + c_j b, a - c_j b), inverse (a, b) -> ((a + b)/2, (a - b) conj(c_j)/2)
+using Diags = std::vector<std::pair<int, std::vector<std::complex<double>>>>;
+Diags stage_diags(int N, int s, bool inverse) {
+  const int n = N / 2, h = n >> (s + 1);
+  const uint64_t mod = (2 * (uint64_t)N) >> s;
+  std::vector<std::complex<double>> cj(h);
+  uint64_t e = 1;
+  for (int j = 0; j < h; ++j) {
+    const uint64_t ex = (e << s) % (2 * (uint64_t)N);
+    cj[j] = std::polar(1.0, kPi * (double)ex / (double)N);
+    e = e * 5 % mod;
   }
-  int a, b;
-  bsgs(c->g.N, &a, &b);
-  const int top = c->g.n_q - 1;
-  const int stc = top - 1 - evalmod_levels(r);
-  if (stc < 1) {
-    set_err("boot_shape: the chain is too short for bootstrapping");
+  std::vector<std::complex<double>> d0(n), dp(n), dm(n);
+  for (int x = 0; x < n; ++x) {
+    const int j = x % (2 * h);
+    const bool first = j < h;
+    const std::complex<double> c = cj[first ? j : j - h];
+    if (!inverse) {
+      d0[x] = first ? 1.0 : -c;
+      dp[x] = first ? c : 0.0;
+      dm[x] = first ? 0.0 : 1.0;
+    } else {
+      d0[x] = first ? std::complex<double>(0.5) : -std::conj(c) * 0.5;
+      dp[x] = first ? std::complex<double>(0.5) : 0.0;
+      dm[x] = first ? std::complex<double>(0.0) : std::conj(c) * 0.5;
+    }
+  }
+  Diags out;
+  auto put = [&](int off, std::vector<std::complex<double>>& v) {
+    for (auto& p : out)
+      if (p.first == off) {
+        for (int x = 0; x < n; ++x) p.second[x] += v[x];
+        return;
+      }
+    out.emplace_back(off, v);
+  };
+  put(0, d0);
+  put(mod_n(h, n), dp);
+  put(mod_n(-h, n), dm);
+  return out;
+}
+
+// A B (B applied first): diag_d = sum_{d1 + d2 = d} A_d1 (.) (B_d2 rotated left by d1)
+Diags diag_product(const Diags& A, const Diags& Bm, int n) {
+  Diags out;
+  for (const auto& a : A)
+    for (const auto& b : Bm) {
+      const int d = mod_n((int64_t)a.first + b.first, n);
+      std::vector<std::complex<double>>* dst = nullptr;
+      for (auto& p : out)
+        if (p.first == d) dst = &p.second;
+      if (!dst) {
+        out.emplace_back(d, std::vector<std::complex<double>>(n));
+        dst = &out.back().second;
+      }
+      for (int x = 0; x < n; ++x) (*dst)[x] += a.second[x] * b.second[(x + a.first) % n];
+    }
+  return out;
+}
+
+// the level's diagonals: dense (levels == 0) from zeta_j^k directly, factored as stage products
+Diags level_diags(const heqg_ctx* c, const Spec& sp, bool inverse) {
+  const int N = c->g.N, n = N / 2;
+  Diags M;
+  if (sp.stages.empty()) {
+    // dense: CoeffToSlot (2/N) U0^H (A[j][k] = (2/N) conj(zeta_k^j)), SlotToCoeff U0 (zeta_j^k), with
+    // zeta_j^k = exp(i pi e_j k / N), e_j = 5^j mod 2N, the exponent product reduced exactly first
+    std::vector<uint64_t> e(n);
+    for (int j = 0; j < n; ++j) e[j] = 2 * (uint64_t)c->slot_pos[j] + 1;
+    auto zeta = [&](int j, int k) {
+      return std::polar(1.0, kPi * (double)((e[j] * (uint64_t)k) % (2 * (uint64_t)N)) / (double)N);
+    };
+    for (int d = 0; d < n; ++d) {
+      std::vector<std::complex<double>> v(n);
+      for (int i = 0; i < n; ++i) {
+        const int kk = (i + d) % n;
+        v[i] = inverse ? (2.0 / (double)N) * std::conj(zeta(kk, i)) : zeta(i, kk);
+      }
+      M.emplace_back(d, std::move(v));
+    }
+    return M;
+  }
+  bool first = true;
+  for (int s : sp.stages) {
+    Diags S = stage_diags(N, s, inverse);
+    M = first ? S : diag_product(S, M, n);
+    first = false;
+  }
+  return M;
+}
+
+// level specs with their baby-step giant-step shapes and input levels
+std::vector<BootLevel> plan(const heqg_ctx* c, int levels, bool inverse, int in_level) {
+  std::vector<BootLevel> out;
+  int lv = in_level;
+  for (const Spec& sp : level_specs(c->g.N, levels, inverse)) {
+    BootLevel L{sp.step, sp.d0, sp.K, 0, 0, lv--, nullptr};
+    bsgs_shape(sp.K, &L.n1, &L.n2);
+    out.push_back(L);
+  }
+  return out;
+}
+
+int shape(const heqg_ctx* c, int r, int levels, int* cts_level, int* stc_level, int* out_level) {
+  const int top = c->g.n_q - 1, L = levels == 0 ? 1 : levels;
+  const int stc = top - L - evalmod_levels(c, top - L, c->delta, 0.5, r);
+  if (r < 1 || stc - L < 0) {
+    set_err("boot_shape: the chain is too short for bootstrapping with these levels");
     return HEQG_ERR_LEVEL;
   }
-  if (n1) *n1 = a;
-  if (n2) *n2 = b;
-  if (cts_level) *cts_level = top;
-  if (stc_level) *stc_level = stc;
+  *cts_level = top;
+  *stc_level = stc;
+  *out_level = stc - L;
   return HEQG_OK;
 }
 
-extern "C" int heqg_boot_encode(const heqg_ctx* c, int r, int64_t* coeffs, int threads) {
-  int n1, n2, top, stc;
-  if (!c || !coeffs) {
-    set_err("boot_encode: null argument");
-    return HEQG_ERR_ARG;
-  }
-  int rc = heqg_boot_shape(c, r, &n1, &n2, &top, &stc);
+int64_t n_plaintexts(const heqg_ctx* c, int levels) {
+  int64_t t = 0;
+  for (int inv = 0; inv < 2; ++inv)
+    for (const Spec& sp : level_specs(c->g.N, levels, inv != 0)) {
+      int n1, n2;
+      bsgs_shape(sp.K, &n1, &n2);
+      t += (int64_t)n1 * n2;
+    }
+  return t + 1;
+}
+
+}  // namespace
+
+extern "C" int heqg_boot_steps(const heqg_ctx* c, int levels, int* steps) {
+  if (!levels_ok(c, levels, "boot_steps")) return HEQG_ERR_ARG;
+  const int n = c->g.N / 2;
+  std::vector<int> st;
+  for (int inv = 0; inv < 2; ++inv)
+    for (const Spec& sp : level_specs(c->g.N, levels, inv != 0)) {
+      int n1, n2;
+      bsgs_shape(sp.K, &n1, &n2);
+      for (int b = 0; b < n1; ++b) st.push_back(mod_n((int64_t)sp.d0 + (int64_t)b * sp.step, n));
+      for (int g = 1; g < n2; ++g) st.push_back(mod_n((int64_t)g * n1 * sp.step, n));
+    }
+  std::sort(st.begin(), st.end());
+  st.erase(std::unique(st.begin(), st.end()), st.end());
+  st.erase(std::remove(st.begin(), st.end(), 0), st.end());
+  if (steps) std::copy(st.begin(), st.end(), steps);
+  return (int)st.size();
+}
+
+extern "C" int heqg_boot_shape(const heqg_ctx* c, int r, int levels, int* cts_level, int* stc_level, int* out_level,
+                               int64_t* n_pts) {
+  if (!levels_ok(c, levels, "boot_shape") || !cts_level || !stc_level || !out_level) return HEQG_ERR_ARG;
+  int rc = shape(c, r, levels, cts_level, stc_level, out_level);
+  if (rc) return rc;
+  if (n_pts) *n_pts = n_plaintexts(c, levels);
+  return HEQG_OK;
+}
+
+extern "C" int heqg_boot_encode(const heqg_ctx* c, int r, int levels, int64_t* coeffs, int threads) {
+  int top, stc, outl;
+  if (!levels_ok(c, levels, "boot_encode") || !coeffs) return HEQG_ERR_ARG;
+  int rc = shape(c, r, levels, &top, &stc, &outl);
   if (rc) return rc;
   const int N = c->g.N, n = N / 2;
-  const int64_t terms = (int64_t)n1 * n2;
-  // zeta_j^k = exp(i pi e_j k / N) with e_j = 5^j mod 2N: the exponent product is reduced mod 2N
-  // exactly before the angle is formed
-  std::vector<uint64_t> e(n);
-  for (int j = 0; j < n; ++j) e[j] = 2 * (uint64_t)c->slot_pos[j] + 1;
-  auto zeta = [&](int j, int k) {
-    const uint64_t m = (e[j] * (uint64_t)k) % (2 * (uint64_t)N);
-    return std::polar(1.0, kPi * (double)m / (double)N);
+  // the plaintexts' (level, direction) jobs in buffer order: CoeffToSlot's levels, then SlotToCoeff's
+  struct Job {
+    Spec sp;
+    bool inverse;
+    int in_level, n1;
+    int64_t first;  // index of its first plaintext
   };
-  const double sc_cts = (double)c->primes[top], sc_stc = (double)c->primes[stc];
-  const int nt = std::max(1, std::min<int>(threads > 0 ? threads : (int)std::thread::hardware_concurrency(), 64));
-  std::atomic<int64_t> next{0};
-  std::atomic<int> err{HEQG_OK};
-  auto work = [&]() {
-    std::vector<std::complex<double>> z(n);
-    for (int64_t t; (t = next.fetch_add(1)) < 2 * terms && err.load() == HEQG_OK;) {
-      const bool stc_side = t >= terms;
-      const int64_t d = stc_side ? t - terms : t;  // d = n1 g + b
-      const int g = (int)(d / n1);
-      // diagonal d of A, rotated right by n1 g: z[i] = A[i'][(i' + d) mod n] with i' = i - n1 g mod n;
-      // CoeffToSlot A = (2/N) U0^H (A[j][k] = (2/N) conj(zeta_k^j)), SlotToCoeff A = U0
-      for (int i = 0; i < n; ++i) {
-        const int ii = (int)(((int64_t)i - (int64_t)n1 * g % n + n) % n);
-        const int kk = (int)((ii + d) % n);
-        z[i] = stc_side ? zeta(ii, kk) : (2.0 / (double)N) * std::conj(zeta(kk, ii));
-      }
-      int r2 = encode_slots(c, z.data(), n, stc_side ? sc_stc : sc_cts, coeffs + t * N);
-      if (r2) err.store(r2);
+  std::vector<Job> jobs;
+  int64_t idx = 0;
+  for (int inv = 1; inv >= 0; --inv) {
+    int lv = inv ? top : stc;
+    for (const Spec& sp : level_specs(N, levels, inv != 0)) {
+      int n1, n2;
+      bsgs_shape(sp.K, &n1, &n2);
+      jobs.push_back(Job{sp, inv != 0, lv--, n1, idx});
+      idx += (int64_t)n1 * n2;
     }
-  };
-  std::vector<std::thread> th;
-  for (int i = 1; i < nt; ++i) th.emplace_back(work);
-  work();
-  for (auto& t : th) t.join();
-  if (err.load()) return err.load();
-  // X^(N/2): i in every slot
-  int64_t* mono = coeffs + 2 * terms * N;
-  std::memset(mono, 0, (size_t)N * sizeof(int64_t));
-  mono[N / 2] = 1;
+  }
+  std::memset(coeffs, 0, (size_t)(idx + 1) * N * sizeof(int64_t));
+  coeffs[(size_t)idx * N + N / 2] = 1;  // X^(N/2): i in every slot
+  const int nt = std::max(1, std::min<int>(threads > 0 ? threads : (int)std::thread::hardware_concurrency(), 64));
+  std::atomic<int> err{HEQG_OK};
+  for (const Job& jb : jobs) {
+    const Diags M = level_diags(c, jb.sp, jb.inverse);
+    const double sc = (double)c->primes[jb.in_level];
+    std::atomic<int> next{0};
+    auto work = [&]() {
+      std::vector<std::complex<double>> z(n);
+      for (int cidx; (cidx = next.fetch_add(1)) < jb.sp.K && err.load() == HEQG_OK;) {
+        const int g = cidx / jb.n1;
+        const int off = mod_n((int64_t)jb.sp.d0 + (int64_t)cidx * jb.sp.step, n);
+        const std::vector<std::complex<double>>* v = nullptr;
+        for (const auto& p : M)
+          if (p.first == off) v = &p.second;
+        if (!v) continue;  // a zero diagonal: the plaintext stays 0
+        // rotated right by n1 g step: z[i] = v[i - n1 g step]
+        const int64_t sh = (int64_t)g * jb.n1 * jb.sp.step;
+        for (int i = 0; i < n; ++i) z[i] = (*v)[mod_n((int64_t)i - sh, n)];
+        int r2 = encode_slots(c, z.data(), n, sc, coeffs + (size_t)(jb.first + cidx) * N);
+        if (r2) err.store(r2);
+      }
+    };
+    std::vector<std::thread> th;
+    for (int i = 1; i < nt; ++i) th.emplace_back(work);
+    work();
+    for (auto& t : th) t.join();
+    if (err.load()) return err.load();
+  }
   return HEQG_OK;
 }
 
-extern "C" size_t heqg_boot_bytes(const heqg_ctx* c, int r) {
-  int n1, n2, top, stc;
-  if (heqg_boot_shape(c, r, &n1, &n2, &top, &stc)) return 0;
-  const size_t N = c->g.N;
-  return 8 * N * ((size_t)n1 * n2 * (top + 1 + stc + 1) + (top + 1));
+extern "C" size_t heqg_boot_bytes(const heqg_ctx* c, int r, int levels) {
+  int top, stc, outl;
+  if (!levels_ok(c, levels, "boot_bytes") || shape(c, r, levels, &top, &stc, &outl)) return 0;
+  size_t words = (size_t)(top + 1) * c->g.N;
+  for (int inv = 1; inv >= 0; --inv)
+    for (const BootLevel& L : plan(c, levels, inv != 0, inv ? top : stc))
+      words += (size_t)L.n1 * L.n2 * (L.in_level + 1) * c->g.N;
+  return 8 * words;
 }
 
-extern "C" int heqg_boot_setup(heqg_ctx* c, const int64_t* dev_coeffs, int r, int taylor, void* dev, size_t bytes,
-                               heqg_boot** out, hipStream_t s) {
-  int n1, n2, top, stc;
-  if (!c || !dev_coeffs || !dev || !out || taylor < 8 || taylor > 22 || (taylor & 1)) {
+extern "C" int heqg_boot_setup(heqg_ctx* c, const int64_t* dev_coeffs, int r, int levels, int taylor, void* dev,
+                               size_t bytes, heqg_boot** out, hipStream_t s) {
+  int top, stc, outl;
+  if (!c || !dev_coeffs || !dev || !out || taylor < 8 || taylor > 22 || (taylor & 1) ||
+      !levels_ok(c, levels, "boot_setup")) {
     set_err("boot_setup: bad argument (even Taylor degree 8..22)");
     return HEQG_ERR_ARG;
   }
-  int rc = heqg_boot_shape(c, r, &n1, &n2, &top, &stc);
+  int rc = shape(c, r, levels, &top, &stc, &outl);
   if (rc) return rc;
-  if (bytes < heqg_boot_bytes(c, r)) {
+  if (bytes < heqg_boot_bytes(c, r, levels)) {
     set_err("boot_setup: device buffer too small");
     return HEQG_ERR_ARG;
   }
   const int N = c->g.N;
-  const int64_t terms = (int64_t)n1 * n2;
   heqg_boot* b = new heqg_boot();
-  b->n1 = n1;
-  b->n2 = n2;
   b->top = top;
+  b->levels = levels;
   b->stc_level = stc;
+  b->out_level = outl;
   b->r = r;
   b->taylor = taylor;
-  b->cts = static_cast<uint64_t*>(dev);
-  b->stc = b->cts + (size_t)terms * (top + 1) * N;
-  b->mono = b->stc + (size_t)terms * (stc + 1) * N;
-  rc = ops::pt_load(c, dev_coeffs, terms, top, b->cts, s);
-  if (!rc) rc = ops::pt_load(c, dev_coeffs + (size_t)terms * N, terms, stc, b->stc, s);
-  if (!rc) rc = ops::pt_load(c, dev_coeffs + (size_t)2 * terms * N, 1, top, b->mono, s);
+  b->cts = plan(c, levels, true, top);
+  b->stc = plan(c, levels, false, stc);
+  uint64_t* d = static_cast<uint64_t*>(dev);
+  const int64_t* src = dev_coeffs;
+  for (auto* lv : {&b->cts, &b->stc})
+    for (BootLevel& L : *lv) {
+      const int64_t m = (int64_t)L.n1 * L.n2;
+      L.pts = d;
+      if (!rc) rc = ops::pt_load(c, src, m, L.in_level, d, s);
+      d += (size_t)m * (L.in_level + 1) * N;
+      src += (size_t)m * N;
+    }
+  b->mono = d;
+  if (!rc) rc = ops::pt_load(c, src, 1, top, b->mono, s);
   if (rc) {
     delete b;
     return rc;
@@ -515,13 +780,11 @@ extern "C" int heqg_boot_setup(heqg_ctx* c, const int64_t* dev_coeffs, int r, in
 
 extern "C" void heqg_boot_destroy(heqg_boot* b) { delete b; }
 
-extern "C" size_t heqg_boot_ws_bytes(const heqg_ctx* c, int64_t count) {
-  if (!c || count < 1) return 0;
-  int n1, n2;
-  bsgs(c->g.N, &n1, &n2);
+extern "C" size_t heqg_boot_ws_bytes(const heqg_ctx* c, int levels, int64_t count) {
+  if (!c || count < 1 || levels < 0 || levels > log2i(c->g.N / 2)) return 0;
   const int top = c->g.n_q - 1;
   const size_t ks = ops::rot_ws_words(c, count, top), rs = ops::mul_const_ws_words(c, count, 3, top);
-  const size_t xb = (size_t)n1 * count * 2 * (top + 1) * c->g.N;
+  const size_t xb = (size_t)max_n1(c->g.N, levels) * count * 2 * (top + 1) * c->g.N;
   return 8 * ((size_t)kSlots * slot_words(c, count) + ks + rs + xb);
 }
 
@@ -531,51 +794,51 @@ extern "C" int heqg_mod_raise(heqg_ctx* c, const heqg_ct_batch* in, heqg_ct_batc
     set_err("mod_raise: null context");
     return HEQG_ERR_ARG;
   }
-  return run(c, nullptr, in, 0, out, c->g.n_q - 1, ws, ws_bytes, s, "mod_raise",
+  return run(c, nullptr, 0, in, 0, out, c->g.n_q - 1, ws, ws_bytes, s, "mod_raise",
              [](Run& R, const B& x) { return R.mod_raise(x); });
 }
 
 extern "C" int heqg_coeff_to_slot(heqg_ctx* c, const heqg_keys* k, const heqg_boot* bt, const heqg_ct_batch* in,
                                   heqg_ct_batch* out, void* ws, size_t ws_bytes, hipStream_t s) {
   if (!boot_ok(c, k, bt, "coeff_to_slot")) return HEQG_ERR_ARG;
-  return run(c, k, in, bt->top, out, bt->top - 1, ws, ws_bytes, s, "coeff_to_slot", [bt](Run& R, const B& x) {
-    return R.linear(x, bt->cts, (int64_t)(bt->top + 1) * R.N(), bt->n1, bt->n2);
-  });
+  const int L = (int)bt->cts.size();
+  return run(c, k, bt->levels, in, bt->top, out, bt->top - L, ws, ws_bytes, s, "coeff_to_slot",
+             [bt](Run& R, const B& x) { return R.transform(x, bt->cts); });
 }
 
 extern "C" int heqg_slot_to_coeff(heqg_ctx* c, const heqg_keys* k, const heqg_boot* bt, const heqg_ct_batch* in,
                                   heqg_ct_batch* out, void* ws, size_t ws_bytes, hipStream_t s) {
   if (!boot_ok(c, k, bt, "slot_to_coeff")) return HEQG_ERR_ARG;
-  return run(c, k, in, bt->stc_level, out, bt->stc_level - 1, ws, ws_bytes, s, "slot_to_coeff",
-             [bt](Run& R, const B& x) {
-               return R.linear(x, bt->stc, (int64_t)(bt->stc_level + 1) * R.N(), bt->n1, bt->n2);
-             });
+  return run(c, k, bt->levels, in, bt->stc_level, out, bt->out_level, ws, ws_bytes, s, "slot_to_coeff",
+             [bt](Run& R, const B& x) { return R.transform(x, bt->stc); });
 }
 
 extern "C" int heqg_eval_mod(heqg_ctx* c, const heqg_keys* k, const heqg_boot* bt, const heqg_ct_batch* in,
                              double half, heqg_ct_batch* out, void* ws, size_t ws_bytes, hipStream_t s) {
   if (!boot_ok(c, k, bt, "eval_mod") || !in) return HEQG_ERR_ARG;
-  const int out_level = in->level - evalmod_levels(bt->r);
+  const int out_level = in->level - evalmod_levels(c, in->level, in->scale, half, bt->r);
   if (out_level < 0) {
     set_err("eval_mod: not enough levels");
     return HEQG_ERR_LEVEL;
   }
-  return run(c, k, in, in->level, out, out_level, ws, ws_bytes, s, "eval_mod", [bt, half](Run& R, const B& x) {
-    return R.evalmod(x, R.q(0), half, bt->r, bt->taylor);
-  });
+  return run(c, k, bt->levels, in, in->level, out, out_level, ws, ws_bytes, s, "eval_mod",
+             [bt, half](Run& R, const B& x) { return R.evalmod(x, R.q(0), half, bt->r, bt->taylor); });
 }
 
 extern "C" int heqg_bootstrap(heqg_ctx* c, const heqg_keys* k, const heqg_boot* bt, const heqg_ct_batch* in,
                               heqg_ct_batch* out, void* ws, size_t ws_bytes, hipStream_t s) {
   if (!boot_ok(c, k, bt, "bootstrap")) return HEQG_ERR_ARG;
-  return run(c, k, in, 0, out, bt->stc_level - 1, ws, ws_bytes, s, "bootstrap", [bt](Run& R, const B& x) {
+  if (in && std::fabs(in->scale / c->delta - 1.0) > std::ldexp(1.0, -20)) {
+    set_err("bootstrap: the input must be at the context's scale (the level plan assumes it)");
+    return HEQG_ERR_SCALE;
+  }
+  return run(c, k, bt->levels, in, 0, out, bt->out_level, ws, ws_bytes, s, "bootstrap", [bt](Run& R, const B& x) {
     const double q0 = R.q(0);
     const int N = R.N();
     B t = R.mod_raise(x);
     R.put(x);
     // CoeffToSlot, the real/imaginary split, EvalMod on both halves, recombination, SlotToCoeff
-    B w1 = R.linear(t, bt->cts, (int64_t)(bt->top + 1) * N, bt->n1, bt->n2);
-    R.put(t);
+    B w1 = R.transform(t, bt->cts);
     B wc = R.rotate_g(w1, 2 * (uint64_t)N - 1);
     B re2 = R.add(w1, wc);
     B dif = R.add(wc, w1, true);
@@ -593,6 +856,6 @@ extern "C" int heqg_bootstrap(heqg_ctx* c, const heqg_keys* k, const heqg_boot* 
     R.put(re);
     R.put(imi);
     if (wp.level != bt->stc_level) R.fail(HEQG_ERR_ARG, "internal: level before SlotToCoeff");
-    return R.linear(wp, bt->stc, (int64_t)(bt->stc_level + 1) * N, bt->n1, bt->n2);
+    return R.transform(wp, bt->stc);
   });
 }

@@ -77,13 +77,13 @@ def lib():
         "heqg_keygen_ws_bytes": (sz, [vp]),
         "heqg_keygen": (i32, [vp, u64, vp, i32, vp, sz, vp, sz, P(vp), vp]),
         "heqg_keygen_ex": (i32, [vp, u64, i32, i32, vp, i32, vp, sz, vp, sz, P(vp), vp]),
-        "heqg_boot_steps": (i32, [vp, vp]),
-        "heqg_boot_shape": (i32, [vp, i32, vp, vp, vp, vp]),
-        "heqg_boot_encode": (i32, [vp, i32, vp, i32]),
-        "heqg_boot_bytes": (sz, [vp, i32]),
-        "heqg_boot_setup": (i32, [vp, vp, i32, i32, vp, sz, P(vp), vp]),
+        "heqg_boot_steps": (i32, [vp, i32, vp]),
+        "heqg_boot_shape": (i32, [vp, i32, i32, vp, vp, vp, vp]),
+        "heqg_boot_encode": (i32, [vp, i32, i32, vp, i32]),
+        "heqg_boot_bytes": (sz, [vp, i32, i32]),
+        "heqg_boot_setup": (i32, [vp, vp, i32, i32, i32, vp, sz, P(vp), vp]),
         "heqg_boot_destroy": (None, [vp]),
-        "heqg_boot_ws_bytes": (sz, [vp, i64]),
+        "heqg_boot_ws_bytes": (sz, [vp, i32, i64]),
         "heqg_mod_raise": (i32, [vp, P(BatchS), P(BatchS), vp, sz, vp]),
         "heqg_coeff_to_slot": (i32, [vp, vp, vp, P(BatchS), P(BatchS), vp, sz, vp]),
         "heqg_eval_mod": (i32, [vp, vp, vp, P(BatchS), dbl, P(BatchS), vp, sz, vp]),
@@ -264,8 +264,8 @@ class Keys:
 
 
 class Boot:
-    def __init__(self, handle, buf, shape, r):
-        self.handle, self.buf, self.shape, self.r = handle, buf, shape, r
+    def __init__(self, handle, buf, shape, r, levels):
+        self.handle, self.buf, self.shape, self.r, self.levels = handle, buf, shape, r, levels
 
     def __del__(self):
         try:
@@ -632,48 +632,49 @@ class Context:
         _check(lib().heqg_graph_clear(self.h))
 
     # ---------------------------------------------------------------- bootstrapping
-    def boot_steps(self):
-        """The rotation steps the slot transforms of heqg_bootstrap use."""
+    def boot_steps(self, levels=0):
+        """The rotation steps the slot transforms of heqg_bootstrap use (levels per transform, 0: dense)."""
         L = lib()
-        n = _check(L.heqg_boot_steps(self.h, None))
+        n = _check(L.heqg_boot_steps(self.h, int(levels), None))
         out = (ctypes.c_int * max(1, n))()
-        L.heqg_boot_steps(self.h, out)
+        L.heqg_boot_steps(self.h, int(levels), out)
         return list(out[:n])
 
-    def boot_shape(self, r):
-        """(n1, n2, CoeffToSlot level, SlotToCoeff level) for r double angles."""
-        v = [ctypes.c_int() for _ in range(4)]
-        _check(lib().heqg_boot_shape(self.h, int(r), *[ctypes.byref(x) for x in v]))
-        return tuple(x.value for x in v)
+    def boot_shape(self, r, levels=0):
+        """(CoeffToSlot input level, SlotToCoeff input level, output level, number of plaintexts)."""
+        v = [ctypes.c_int() for _ in range(3)]
+        npts = ctypes.c_int64()
+        _check(lib().heqg_boot_shape(self.h, int(r), int(levels), *[ctypes.byref(x) for x in v], ctypes.byref(npts)))
+        return tuple(x.value for x in v) + (npts.value,)
 
-    def boot_encode(self, r, threads=0):
-        """heqg_boot_encode: the slot transforms' plaintexts, numpy int64 [2 n1 n2 + 1][N]."""
-        n1, n2, _, _ = self.boot_shape(r)
-        out = np.zeros((2 * n1 * n2 + 1, self.N), dtype=np.int64)
-        _check(lib().heqg_boot_encode(self.h, int(r), out.ctypes.data, int(threads)))
+    def boot_encode(self, r, levels=0, threads=0):
+        """heqg_boot_encode: every plaintext of the slot transforms, numpy int64 [n_pts][N]."""
+        n_pts = self.boot_shape(r, levels)[3]
+        out = np.zeros((n_pts, self.N), dtype=np.int64)
+        _check(lib().heqg_boot_encode(self.h, int(r), int(levels), out.ctypes.data, int(threads)))
         return out
 
-    def boot_setup(self, coeffs, r, taylor):
-        """coeffs: int64 [2 n1 n2 + 1][N] (numpy or a device tensor; CoeffToSlot diagonals, SlotToCoeff
-        diagonals, X^(N/2)).  Returns a Boot holding the NTT-form plaintexts."""
+    def boot_setup(self, coeffs, r, taylor, levels=0):
+        """coeffs: int64 [n_pts][N] (numpy or a device tensor, heqg_boot_encode's layout).  Returns a Boot
+        holding the NTT-form plaintexts."""
         torch = _torch()
         L = lib()
-        nb = L.heqg_boot_bytes(self.h, int(r))
+        nb = L.heqg_boot_bytes(self.h, int(r), int(levels))
         if nb == 0:
             raise HeqgError(-1, L.heqg_last_error().decode())
         if isinstance(coeffs, np.ndarray):
             coeffs = torch.from_numpy(np.ascontiguousarray(coeffs, dtype=np.int64)).cuda()
         buf = _ws(nb)
         h = ctypes.c_void_p()
-        _check(L.heqg_boot_setup(self.h, coeffs.data_ptr(), int(r), int(taylor), buf.data_ptr(), nb, ctypes.byref(h),
-                                 _stream()))
+        _check(L.heqg_boot_setup(self.h, coeffs.data_ptr(), int(r), int(levels), int(taylor), buf.data_ptr(), nb,
+                                 ctypes.byref(h), _stream()))
         _torch().cuda.current_stream().synchronize()
-        return Boot(h, buf, self.boot_shape(r), int(r))
+        return Boot(h, buf, self.boot_shape(r, levels), int(r), int(levels))
 
-    def _boot_call(self, fn, pre, ct, out_level, ws):
+    def _boot_call(self, fn, pre, ct, out_level, ws, levels=0):
         """fn(ctx, *pre, in, out, ws, ws_bytes, stream) for the bootstrapping steps."""
         out = self._out(ct.count, 2, out_level)
-        need = lib().heqg_boot_ws_bytes(self.h, ct.count)
+        need = lib().heqg_boot_ws_bytes(self.h, int(levels), ct.count)
         if ws is None or ws.numel() < need:
             ws = _ws(need)
         bi, bo = ct.batch(), out.batch()
@@ -685,14 +686,18 @@ class Context:
         return self._boot_call(lib().heqg_mod_raise, (), ct, self.top_level, ws)
 
     def coeff_to_slot(self, keys, boot, ct, ws=None):
-        return self._boot_call(lib().heqg_coeff_to_slot, (keys.handle, boot.handle), ct, ct.level - 1, ws)
+        return self._boot_call(lib().heqg_coeff_to_slot, (keys.handle, boot.handle), ct,
+                               ct.level - max(boot.levels, 1), ws, boot.levels)
 
     def slot_to_coeff(self, keys, boot, ct, ws=None):
-        return self._boot_call(lib().heqg_slot_to_coeff, (keys.handle, boot.handle), ct, ct.level - 1, ws)
+        return self._boot_call(lib().heqg_slot_to_coeff, (keys.handle, boot.handle), ct, boot.shape[2], ws,
+                               boot.levels)
 
-    def eval_mod(self, keys, boot, ct, half=1.0, ws=None):
-        out = self._out(ct.count, 2, ct.level - 7 - boot.r)
-        need = lib().heqg_boot_ws_bytes(self.h, ct.count)
+    def eval_mod(self, keys, boot, ct, half=1.0, ws=None, levels_used=None):
+        """heqg_eval_mod; levels_used: the levels it consumes (7 + r, or 8 + r with the affine map over
+        two primes; the oracle's EvalMod.levels gives it)."""
+        out = self._out(ct.count, 2, ct.level - (7 + boot.r if levels_used is None else levels_used))
+        need = lib().heqg_boot_ws_bytes(self.h, boot.levels, ct.count)
         if ws is None or ws.numel() < need:
             ws = _ws(need)
         bi, bo = ct.batch(), out.batch()
@@ -702,5 +707,5 @@ class Context:
 
     def bootstrap(self, keys, boot, ct, ws=None):
         """heqg_bootstrap: level-0 ciphertexts -> the same messages at level stc_level - 1."""
-        return self._boot_call(lib().heqg_bootstrap, (keys.handle, boot.handle), ct, boot.shape[3] - 1, ws)
+        return self._boot_call(lib().heqg_bootstrap, (keys.handle, boot.handle), ct, boot.shape[2], ws, boot.levels)
 

@@ -46,10 +46,12 @@ def _complex(rng, n):
 
 def test_shape_and_steps_match_oracle(env):
     o, ctx, em = env["o"], env["ctx"], env["em"]
-    n1, n2, cts_level, stc_level = ctx.boot_shape(R)
-    assert (n1, n2) == boot.bsgs_split(o.N // 2)
-    assert cts_level == o.top_level and stc_level == o.top_level - 1 - em.levels()
-    assert env["steps"] == boot.boot_steps(o.N)
+    cts_level, stc_level, out_level, n_pts = ctx.boot_shape(R)
+    n1, n2 = boot.bsgs_split(o.N // 2)
+    assert n_pts == 2 * n1 * n2 + 1 == len(env["pts"])
+    assert cts_level == o.top_level and stc_level == o.top_level - 1 - em.levels(o, o.top_level - 1)
+    assert out_level == stc_level - 1
+    assert env["steps"] == sorted(boot.boot_steps(o.N))
 
 
 def test_sparse_keys_bit_exact(env):
@@ -72,8 +74,8 @@ def test_library_encoder_matches_oracle_plaintexts(env):
     got = ctx.boot_encode(R, threads=8)
     ref = env["pts"]
     assert got.shape == ref.shape
-    n1, n2, top, stc = ctx.boot_shape(R)
-    t = n1 * n2
+    top, stc, _, n_pts = ctx.boot_shape(R)
+    t = (n_pts - 1) // 2
     for part, lv in ((slice(0, t), top), (slice(t, 2 * t), stc)):
         diff = np.abs(got[part] - ref[part])
         assert diff.max() <= float(o.q(lv)) * 2.0 ** -42, (lv, diff.max())
@@ -112,7 +114,7 @@ def test_eval_mod_bit_exact(env):
 
 def test_slot_to_coeff_bit_exact(env):
     o, ctx = env["o"], env["ctx"]
-    stc = ctx.boot_shape(R)[3]
+    stc = ctx.boot_shape(R)[1]
     rng = np.random.default_rng(6)
     ct = _fresh(o, _complex(rng, o.N // 2), stc, 6)
     got = ctx.slot_to_coeff(env["keys"], env["bt"], gpu_ct(ctx, ct))
@@ -145,6 +147,116 @@ def test_bootstrap_from_library_encoder(env):
     z = rng.uniform(-1, 1, o.N // 2)
     ct = ctx.encrypt(keys, ctx.encode(z, o.delta)[None], 0, o.delta, 99, 0)
     out = ctx.bootstrap(keys, bt, ct)
-    assert out.level == ctx.boot_shape(R)[3] - 1
+    assert out.level == ctx.boot_shape(R)[2]
     got = ctx.decrypt_values(keys, out, n=o.N // 2)
     assert np.abs(got - z).max() < 1e-3
+
+
+# ---------------------------------------------------------------- factored transforms
+# a chain long enough for three levels per transform (3 + 12 + 3 below the top), as the oracle's pin
+CFG_LONG = dict(log2N=12, q_bits=[60] + [50] * 19, n_p=7, p_bits=60, dnum=3, log2_scale=50)
+LEVELS = 3
+
+
+@pytest.fixture(scope="module")
+def env_fft():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_13221_amd import heqg
+    o = Oracle.from_config(CFG_LONG)
+    boot.keygen_sparse(o, 33, H, boot.fft_steps(o.N, LEVELS), dense_steps=False)
+    ctx = heqg.Context(CFG_LONG["log2N"], CFG_LONG["q_bits"], CFG_LONG["n_p"], CFG_LONG["p_bits"], CFG_LONG["dnum"],
+                       CFG_LONG["log2_scale"])
+    steps = ctx.boot_steps(LEVELS)
+    keys = ctx.keygen(33, steps, hamming=H, conj=True)
+    em = boot.EvalMod(K=K, r=R, taylor=TAYLOR)
+    pts = boot.transform_plaintexts_fft(o, LEVELS, em)
+    bt = ctx.boot_setup(pts, R, TAYLOR, levels=LEVELS)
+    return dict(o=o, ctx=ctx, keys=keys, steps=steps, em=em, pts=pts, bt=bt)
+
+
+def test_factored_shape_steps_and_keys(env_fft):
+    o, ctx, em, keys = env_fft["o"], env_fft["ctx"], env_fft["em"], env_fft["keys"]
+    assert env_fft["steps"] == boot.fft_steps(o.N, LEVELS)
+    cts_level, stc_level, out_level, n_pts = ctx.boot_shape(R, LEVELS)
+    assert n_pts == len(env_fft["pts"])
+    em_lv = em.levels(o, o.top_level - LEVELS)
+    assert (cts_level, stc_level, out_level) == (o.top_level, o.top_level - LEVELS - em_lv,
+                                                 o.top_level - 2 * LEVELS - em_lv)
+    for i, t in enumerate(keys.galois):
+        assert np.array_equal(cpu_u64(keys.export(3, i)).reshape(o.keys["rot"][t].shape), o.keys["rot"][t]), t
+
+
+def test_factored_library_encoder_matches_oracle(env_fft):
+    o, ctx = env_fft["o"], env_fft["ctx"]
+    got = ctx.boot_encode(R, LEVELS, threads=8)
+    ref = env_fft["pts"]
+    assert got.shape == ref.shape
+    # every level's plaintexts are encoded at a 50-bit q_level
+    assert np.abs(got - ref).max() <= 2.0 ** 50 * 2.0 ** -42
+    assert np.array_equal(got[-1], ref[-1])
+
+
+def test_factored_coeff_to_slot_and_slot_to_coeff_bit_exact(env_fft):
+    o, ctx, keys, bt = env_fft["o"], env_fft["ctx"], env_fft["keys"], env_fft["bt"]
+    rng = np.random.default_rng(12)
+    raised = boot.mod_raise(o, _fresh(o, _complex(rng, o.N // 2), 0, 12))
+    assert_same_ct(ctx.coeff_to_slot(keys, bt, gpu_ct(ctx, raised)), boot.coeff_to_slot_fft(o, raised, LEVELS),
+                   "coeff_to_slot (factored)")
+    stc = ctx.boot_shape(R, LEVELS)[1]
+    ct = _fresh(o, _complex(rng, o.N // 2), stc, 13)
+    assert_same_ct(ctx.slot_to_coeff(keys, bt, gpu_ct(ctx, ct)), boot.slot_to_coeff_fft(o, ct, LEVELS),
+                   "slot_to_coeff (factored)")
+
+
+def test_factored_bootstrap_bit_exact_and_from_library_encoder(env_fft):
+    """Two ciphertexts through the factored bootstrap: bit-exact against the oracle and the message
+    back within 1e-3; the same from the library's own plaintexts, decrypted on the GPU."""
+    import torch
+    from paper_2406_13221_amd import heqg
+    o, ctx, keys, em = env_fft["o"], env_fft["ctx"], env_fft["keys"], env_fft["em"]
+    rng = np.random.default_rng(14)
+    zs = [_complex(rng, o.N // 2) for _ in range(2)]
+    cts = [_fresh(o, z, 0, 20 + i) for i, z in enumerate(zs)]
+    data = torch.from_numpy(np.stack([c.data for c in cts]).view(np.int64).copy()).cuda()
+    got = ctx.bootstrap(keys, env_fft["bt"], heqg.Cts(data, 0, cts[0].scale))
+    for i, (z, c) in enumerate(zip(zs, cts)):
+        ref = boot.bootstrap(o, c, em, fft_levels=LEVELS)
+        assert_same_ct(heqg.Cts(got.data[i:i + 1], got.level, got.scale), ref, "factored bootstrap %d" % i)
+        assert np.abs(o.decrypt_values(ref) - z).max() < 1e-3
+    bt2 = ctx.boot_setup(ctx.boot_encode(R, LEVELS), R, TAYLOR, levels=LEVELS)
+    z = rng.uniform(-1, 1, o.N // 2)
+    ct = ctx.encrypt(keys, ctx.encode(z, o.delta)[None], 0, o.delta, 98, 0)
+    out = ctx.bootstrap(keys, bt2, ct)
+    assert out.level == ctx.boot_shape(R, LEVELS)[2]
+    assert np.abs(ctx.decrypt_values(keys, out, n=o.N // 2) - z).max() < 1e-3
+
+
+# q0 = 2^60 over a 40-bit scale, the ratio of the paper-scale chain: EvalMod's affine map divides by
+# two primes there (one level more)
+CFG40 = dict(log2N=12, q_bits=[60] + [40] * 22, n_p=8, p_bits=60, dnum=3, log2_scale=40)
+
+
+def test_bootstrap_at_a_40_bit_scale_bit_exact():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_13221_amd import heqg
+    o = Oracle.from_config(CFG40)
+    boot.keygen_sparse(o, 37, H, boot.fft_steps(o.N, LEVELS), dense_steps=False)
+    ctx = heqg.Context(CFG40["log2N"], CFG40["q_bits"], CFG40["n_p"], CFG40["p_bits"], CFG40["dnum"],
+                       CFG40["log2_scale"])
+    keys = ctx.keygen(37, ctx.boot_steps(LEVELS), hamming=H, conj=True)
+    em = boot.EvalMod(K=K, r=R, taylor=TAYLOR)
+    assert em.levels(o, o.top_level - LEVELS) == 2 + 5 + R + 1
+    assert ctx.boot_shape(R, LEVELS)[1] == o.top_level - LEVELS - em.levels(o, o.top_level - LEVELS)
+    bt = ctx.boot_setup(boot.transform_plaintexts_fft(o, LEVELS, em), R, TAYLOR, levels=LEVELS)
+    rng = np.random.default_rng(15)
+    z = rng.uniform(-1, 1, o.N // 2)
+    ct = _fresh(o, z, 0, 15)
+    got = ctx.bootstrap(keys, bt, gpu_ct(ctx, ct))
+    ref = boot.bootstrap(o, ct, em, fft_levels=LEVELS)
+    assert_same_ct(got, ref, "bootstrap at a 40-bit scale")
+    err = np.abs(o.decrypt_values(ref).real - z).max()
+    print("bootstrap at a 40-bit scale with q0 = 2^60: max error %.3e" % err)
