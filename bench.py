@@ -42,7 +42,7 @@ def log(*a):
 
 def cpu_baseline(cfg, data, n_blocks, work=None):
     """The oracle timed on a bounded sample of the same iteration: the whole iteration (per-block
-    pipeline and the once-per-iteration tail) over 1 and over 3 blocks; the difference gives the
+    pipeline and the once-per-iteration tail) over 1 and over 9 blocks; the difference gives the
     per-block cost, the rest is the tail; the iteration over all blocks is extrapolated from both.
     Z and B-bar sit at the top level, W and V at `work` (default: the top), as on the GPU."""
     import numpy as np
@@ -53,12 +53,13 @@ def cpu_baseline(cfg, data, n_blocks, work=None):
     o = Oracle.from_config(cfg)
     m, g = cfg["m"], cfg["g"]
     o.keygen(cfg["key_seed"], circuit.rot_steps(m, g))
-    X, y = data["X"][:3 * m], data["y"][:3 * m]
+    lo, hi = 1, 9
+    X, y = data["X"][:hi * m], data["y"][:hi * m]
     blocks = circuit.pack_blocks(trainer.build_Z(X, y, g), m, g, o.N)
     from paper_2406_13221_amd.train import SIGMOID_SCALE
     L = o.top_level
     work = L if work is None else work
-    Zc = [o.encrypt(encode(blocks[b], o.N, o.delta), L, o.delta, cfg["enc_seed"], b) for b in range(3)]
+    Zc = [o.encrypt(encode(blocks[b], o.N, o.delta), L, o.delta, cfg["enc_seed"], b) for b in range(hi)]
     B = trainer.bbar(X, g)
     sB = 2.0 ** 50 / B.max()
     Bc = o.encrypt(encode(circuit.replicate_row(B, m, g), o.N, sB), L, sB, cfg["enc_seed"], 10)
@@ -66,17 +67,17 @@ def cpu_baseline(cfg, data, n_blocks, work=None):
     V = o.encrypt(np.zeros(o.N, np.int64), work, o.delta, cfg["enc_seed"], 12)
     masks = circuit.make_masks(o, m, g, trainer.G8, work, SIGMOID_SCALE)
     times = {}
-    for nb in (1, 3):
+    for nb in (lo, hi):
         t0 = time.perf_counter()
         circuit.nag_qg_step(o, Zc[:nb], Bc, W, V, circuit.new_state(refresh_seed=7), masks, m, g, degree=3)
         times[nb] = time.perf_counter() - t0
-    per_block = (times[3] - times[1]) / 2.0
-    tail = max(times[1] - per_block, 0.0)
+    per_block = (times[hi] - times[lo]) / (hi - lo)
+    tail = max(times[lo] - lo * per_block, 0.0)
     return dict(value=tail + per_block * n_blocks, unit="s/iter", cores=threads, kind="oracle",
-                sample="the full iteration (per-block pipeline + once-per-iteration tail) over 1 and over 3 "
+                sample="the full iteration (per-block pipeline + once-per-iteration tail) over %d and over %d "
                        "of the %d blocks at the same parameters and levels (W and V at level %d): %.1f s and %.1f s, "
                        "i.e. %.2f s per block and %.2f s for the tail, extrapolated to %d blocks"
-                       % (n_blocks, work, times[1], times[3], per_block, tail, n_blocks))
+                       % (lo, hi, n_blocks, work, times[lo], times[hi], per_block, tail, n_blocks))
 
 
 def iteration_model_bytes(cfg, n_blocks, degree=3, level=None):
