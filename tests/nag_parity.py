@@ -54,7 +54,9 @@ def gpu_with_keys(cfgkey, **over):
     return _GPU[k]
 
 
-def oracle_setup(cfgkey, coeffs=trainer.G8, rows=None, bbar_rows=None, **over):
+def oracle_setup(cfgkey, coeffs=trainer.G8, rows=None, bbar_rows=None, level=None, **over):
+    """Z and B-bar encrypted at the top level, W = V = 0 at `level` (default: the top) and the
+    sigmoid masks planned for it."""
     cfg = config(cfgkey, **over)
     d = dataset(cfgkey, **over)
     X, y = d["X"], d["y"]
@@ -70,9 +72,10 @@ def oracle_setup(cfgkey, coeffs=trainer.G8, rows=None, bbar_rows=None, **over):
     B = trainer.bbar(XB, g)
     sB = 2.0 ** 50 / B.max()
     Bc = o.encrypt(encode(circuit.replicate_row(B, m, g), N, sB), L, sB, cfg["enc_seed"], 1 << 20)
-    W = o.encrypt(np.zeros(N, np.int64), L, o.delta, cfg["enc_seed"], (1 << 20) + 1)
-    V = o.encrypt(np.zeros(N, np.int64), L, o.delta, cfg["enc_seed"], (1 << 20) + 2)
-    masks = circuit.make_masks(o, m, g, coeffs, L, SIGMOID_SCALE)
+    lw = L if level is None else level
+    W = o.encrypt(np.zeros(N, np.int64), lw, o.delta, cfg["enc_seed"], (1 << 20) + 1)
+    V = o.encrypt(np.zeros(N, np.int64), lw, o.delta, cfg["enc_seed"], (1 << 20) + 2)
+    masks = circuit.make_masks(o, m, g, coeffs, lw, SIGMOID_SCALE)
     return cfg, o, X, y, Zc, Bc, W, V, masks
 
 
@@ -101,13 +104,15 @@ def gpu_state(ost, m, g):
 
 
 def run_parity(cfgkey, iters, batch, coeffs=trainer.G8, rows=None, bbar_rows=None, split=None, graph=False,
-               **over):
-    """iters iterations (each followed by a refresh of W and V) on both sides, compared
-    residue by residue; split: the NTT pass split the GPU context uses (restored after)."""
-    print("nag parity: %s iters=%d batch=%d rows=%s degree=%d split=%s graph=%s" %
-          (cfgkey, iters, batch, rows, max(coeffs), split, graph), flush=True)
-    cfg, o, X, y, Zc, Bc, W, V, masks = oracle_setup(cfgkey, coeffs, rows, bbar_rows, **over)
-    m, g, L = cfg["m"], cfg["g"], o.top_level
+               level=None, **over):
+    """iters iterations (each followed by a refresh of W and V back to their level) on both sides,
+    compared residue by residue; split: the NTT pass split the GPU context uses (restored after);
+    level: the level W and V are encrypted and refreshed at (default: the top)."""
+    print("nag parity: %s iters=%d batch=%d rows=%s degree=%d split=%s graph=%s level=%s" %
+          (cfgkey, iters, batch, rows, max(coeffs), split, graph, level), flush=True)
+    cfg, o, X, y, Zc, Bc, W, V, masks = oracle_setup(cfgkey, coeffs, rows, bbar_rows, level, **over)
+    m, g = cfg["m"], cfg["g"]
+    L = o.top_level if level is None else level
     ctx, keys, gZ, gB, gW, gV, mk, scales = gpu_side(cfg, o, Zc, Bc, W, V, masks, coeffs, cfgkey, **over)
     deg = max(coeffs)
     saved = ctx.tune_get(2)

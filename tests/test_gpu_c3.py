@@ -1,13 +1,15 @@
 """Parity at the paper's full size (N = 2^16, 24 limbs of 60/40 bits, seven
 42-bit special primes, dnum 4, 422,108 x 200):
  - batched key-switching operations in the chunk geometry the benchmark tunes
-   to (16 ciphertexts per launch), compared with the oracle on sampled members;
+   to (24 ciphertexts per launch), compared with the oracle on sampled members;
  - the whole iteration (heqg_nag_qg_step) residue by residue against the
    oracle's circuit on the first blocks (a ragged 2 + 1 chunk), with the
    learned degree-5 and degree-7 sigmoids, and as the mini-batch step over the
    220-row tail of the data (422,108 mod 1,024) with its own B-bar;
- - one full-batch iteration over all 3,298 blocks, decrypted and compared with
-   the FP64 plaintext trainer."""
+ - the iteration as the benchmark runs it (W and V at the working level 6, 24
+   blocks per launch) residue by residue on 26 blocks (a ragged 24 + 2);
+ - one full-batch iteration over all 3,298 blocks in that configuration,
+   decrypted and compared with the FP64 plaintext trainer."""
 import numpy as np
 import pytest
 
@@ -18,8 +20,10 @@ from tests.nag_parity import run_parity
 
 pytestmark = pytest.mark.gpu
 
-CHUNK = 16               # blocks per launch the benchmark's chunk tuner settles on
-PICKS = (0, 7, 15)       # members of the batch the oracle recomputes
+CHUNK = 24               # blocks per launch the benchmark's chunk tuner settles on
+PICKS = (0, 11, 23)      # members of the batch the oracle recomputes
+WORK_LEVEL = 6           # where W and V live: the level the factored bootstrap (r = 5, two levels per
+                         # transform) returns at these parameters, the lowest covering Table 1's 2^275
 TAIL = (421888, 422108)  # the last, short mini-batch: 422,108 mod 1,024 = 220 rows (2 blocks)
 
 
@@ -91,11 +95,17 @@ def test_c3_full_batch_iteration_matches_fp64(torch_cuda):
     cfg = synth.get_config("c3")
     d = synth.make_dataset(cfg)
     run = EncryptedQGNAG(cfg, d["X"], d["y"], batch=CHUNK)
-    assert run.Z.count == 3298
+    run.reset(obj=(1 << 40) + 1, level=WORK_LEVEL)
+    assert run.Z.count == 3298 and run.W.level == WORK_LEVEL
     run.step()
     w = run.weights(cfg["g"])
     ref = trainer.train(d["X"], d["y"], cfg["g"], 1)
     assert np.abs(w - ref["history"][0]["W"]).max() < 1e-3
+
+
+def test_c3_step_at_the_working_level_bit_exact(torch_cuda):
+    # 26 blocks in chunks of 24 + 2, W and V at the working level, refreshed back to it
+    run_parity("c3", 1, batch=CHUNK, rows=(0, 26 * 128), level=WORK_LEVEL)
 
 
 def test_c3_step_bit_exact_ragged_chunks(torch_cuda):
