@@ -133,19 +133,19 @@ def iteration_model_bytes(cfg, n_blocks, degree=3, level=None):
 
 def pmc_traffic(kernel, batch, level, rows=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc summary (FETCH_SIZE and
-    WRITE_SIZE per dispatch, scaled by what the counters read for a plain device copy): for the
-    conversion pass bytes per output row x `rows`, for the others bytes per dispatch.  None when
-    the summary is missing, the NTT source has changed since it was taken, or it was taken at
-    another chunk size or working level."""
+    WRITE_SIZE per dispatch, scaled by what the counters read for a plain device copy, one entry
+    per chunk size): for the conversion pass bytes per output row x `rows`, for the others bytes
+    per dispatch.  None when the summary is missing, the NTT source has changed since it was
+    taken, or it holds no entry for this chunk size or working level."""
     try:
         with open(PMC_FILE) as f:
             pm = json.load(f)
         with open(KERNEL_SRC, "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != pm["kernel_source_sha256"]:
                 return None
-        if pm["batch_blocks"] != batch or pm["work_level"] != level:
+        if pm["work_level"] != level or str(batch) not in pm["by_batch"]:
             return None
-        k = pm["kernels"][kernel]
+        k = pm["by_batch"][str(batch)]["kernels"][kernel]
         if rows is not None:
             return k["bytes_per_output_row"] * rows
         return k["fetch_bytes_per_dispatch"] + k["write_bytes_per_dispatch"]

@@ -185,9 +185,10 @@ class EncryptedQGNAG:
         pts = np.stack([ctx.encode(tile_row(B[j * g:(j + 1) * g], self.m, g), sB) for j in range(self.nc)])
         return ctx.encrypt(self.keys, pts, ctx.top_level, sB, self.cfg["enc_seed"], obj_first)
 
-    def tune(self, candidates=(8, 16, 24), blocks=48, rows=2048):
+    def tune(self, candidates=(16, 24, 32, 48), blocks=96, rows=2048, reps=3):
         """Autotune: NTT pass split and row-pass variants (heqg_tune_ntt), then the number of
-        blocks per lock-step chunk, timed on one iteration over the first `blocks` blocks."""
+        blocks per lock-step chunk, timed (best of `reps`) on one iteration over the first
+        `blocks` blocks, a multiple of every candidate."""
         import copy
         import torch
         ctx = self.ctx
@@ -199,7 +200,7 @@ class EncryptedQGNAG:
             B = max(min(B, nb), self.nc)
             ws = heqg._ws(ctx.nag_ws_bytes(B, self.degree))
             best = None
-            for _ in range(2):
+            for _ in range(reps):
                 W = heqg.Cts(self.W.data.clone(), self.W.level, self.W.scale)
                 V = heqg.Cts(self.V.data.clone(), self.V.level, self.V.scale)
                 st = copy.copy(self.state)

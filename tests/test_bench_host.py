@@ -27,14 +27,17 @@ def test_pmc_traffic_only_for_the_measured_source(tmp_path, monkeypatch):
     src.write_bytes(b"// kernel source A\n")
     pmc = tmp_path / "pmc.json"
     pmc.write_text(json.dumps({
-        "kernel_source_sha256": hashlib.sha256(src.read_bytes()).hexdigest(), "batch_blocks": 16, "work_level": 9,
-        "kernels": {"k_conv_cols": {"bytes_per_output_row": 1000.0},
-                    "k_ntt_rows_ks8": {"fetch_bytes_per_dispatch": 300.0, "write_bytes_per_dispatch": 200.0}}}))
+        "kernel_source_sha256": hashlib.sha256(src.read_bytes()).hexdigest(), "work_level": 9,
+        "by_batch": {"16": {"kernels": {
+            "k_conv_cols": {"bytes_per_output_row": 1000.0},
+            "k_ntt_rows_ks8": {"fetch_bytes_per_dispatch": 300.0, "write_bytes_per_dispatch": 200.0}}},
+            "32": {"kernels": {"k_ntt_rows_ks8": {"fetch_bytes_per_dispatch": 600.0, "write_bytes_per_dispatch": 400.0}}}}}))
     monkeypatch.setattr(bench, "PMC_FILE", str(pmc))
     monkeypatch.setattr(bench, "KERNEL_SRC", str(src))
     assert bench.pmc_traffic("k_conv_cols", 16, 9, rows=3.5) == pytest.approx(3500.0)
     assert bench.pmc_traffic("k_ntt_rows_ks8", 16, 9) == pytest.approx(500.0)
-    assert bench.pmc_traffic("k_ntt_rows_ks8", 24, 9) is None    # another chunk size
+    assert bench.pmc_traffic("k_ntt_rows_ks8", 32, 9) == pytest.approx(1000.0)
+    assert bench.pmc_traffic("k_ntt_rows_ks8", 24, 9) is None    # a chunk size not measured
     assert bench.pmc_traffic("k_ntt_rows_ks8", 16, 23) is None   # another working level
     assert bench.pmc_traffic("k_tensor", 16, 9) is None          # not measured
     src.write_bytes(b"// kernel source B\n")       # the kernel changed since the counters were taken
@@ -47,11 +50,13 @@ def test_committed_pmc_summary_is_well_formed():
     with open(bench.PMC_FILE) as f:
         pm = json.load(f)
     assert len(pm["kernel_source_sha256"]) == 64
-    assert pm["copy_probe"]["write_factor"] == pytest.approx(1.0, abs=0.05)
-    conv = pm["kernels"]["k_conv_cols"]
-    assert conv["bytes_per_output_row"] >= conv["algorithmic_write_bytes_per_row"] > 0
-    ks = pm["kernels"]["k_ntt_rows_ks8"]
-    assert ks["fetch_bytes_per_dispatch"] > 0 and ks["write_bytes_per_dispatch"] > 0
+    assert pm["by_batch"]
+    for ent in pm["by_batch"].values():
+        assert ent["copy_probe"]["write_factor"] == pytest.approx(1.0, abs=0.05)
+        conv = ent["kernels"]["k_conv_cols"]
+        assert conv["bytes_per_output_row"] >= conv["algorithmic_write_bytes_per_row"] > 0
+        ks = ent["kernels"]["k_ntt_rows_ks8"]
+        assert ks["fetch_bytes_per_dispatch"] > 0 and ks["write_bytes_per_dispatch"] > 0
 
 
 def test_iteration_model_bytes_grows_with_the_blocks():
