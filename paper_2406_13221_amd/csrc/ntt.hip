@@ -677,9 +677,126 @@ __device__ __forceinline__ void convq_body(const NttParams& P, uint64_t* obase, 
   pass(x1, t1, q1, qi1, t1 < nt, i1);
 }
 
+// Conversion into one wide target (more than FP_MAX_BITS bits, up to 62) on the matrix cores,
+// then its first forward pass on the 64-bit integer path, over a tile of C = 256/T columns.
+// Thread slot tid owns column cl = tid % C and the strided elements {kg + T*r} (kg = tid / C),
+// as in cols_body.  The 32 x 32 product shares its B columns between the two lane halves, so
+// each block takes two products: product a has as column j the coefficient of lane 32a + j
+// of the wave, lane half h bringing sources 4m + 2h, +1 of it; every A row pair holds the
+// target's digits b = 0..7 for both lane halves (the rows of output v >= 8 are zero), and lane
+// half h keeps product h.  Then y = sum_b 256^b R[b] = lo + 2^32 hi with |lo|, |hi| < 2^46: its
+// quotient by q from an FP64 estimate (error below 2^25, so the rounded quotient is within one
+// of the true one), the remainder y - qt*q exactly in 64-bit wrap-around arithmetic (it lies in
+// [-q/2 - 2^25, q/2 + 2^25]), made canonical with one conditional add.
+template <int LOGS, int NM>
+__device__ __forceinline__ void convw_body(const NttParams& P, uint64_t* row, const uint64_t* cs,
+                                           const uint64_t* sp, int p, int tile, uint64_t* lds) {
+#pragma clang fp contract(off)
+  constexpr int S = 1 << LOGS, T = S / 16, C = 256 / T;
+  const int tid = threadIdx.x, l = tid & 63, h = l >> 5;
+  const PrimeConst pc = P.pc[p];
+  const int N2 = 1 << (P.logN - LOGS);
+  const int cl = tid % C, kg = tid / C;
+  const int c = tile * C + cl;
+  // element offsets of the coefficients of lanes l & 31 and l | 32 of this wave (block 0)
+  const int t0 = tid & ~32, t1 = tid | 32;
+  const uint32_t v0 = (uint32_t)((t0 / C) * N2 + tile * C + t0 % C) * 8;
+  const uint32_t v1 = (uint32_t)((t1 / C) * N2 + tile * C + t1 % C) * 8;
+  const uint32_t us = (uint32_t)(T * N2) * 8;
+  const int ns = P.X.ns;
+  // A: row i = lane % 32 holds digit 4 ((i >> 3) & 1) + (i & 3) of the target for i < 16
+  v4i_t A[NM];
+  {
+    const int i = l & 31;
+    const int ba = 4 * ((i >> 3) & 1) + (i & 3);
+    const uint64_t* cb = P.X.cbyte + 8 * ((int64_t)p * P.X.cstride) + ba;
+    const bool act = i < 16;
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      const int s0 = 4 * m + 2 * h, s1 = s0 + 1;
+      A[m] = pack2(act && s0 < ns ? cb[8 * s0] : 0, act && s1 < ns ? cb[8 * s1] : 0);
+    }
+  }
+  // sources: rows of cs, the last one from sp when given; a slot past the sources reads a
+  // valid row and is multiplied by zero constants
+  const RowBuf csb(cs), spb(sp ? sp : cs);
+  const int nsc = sp ? ns - 1 : ns;
+  const int se = sp ? ns - 1 : 4 * NM;
+  const uint32_t rowb = (uint32_t)8 << P.logN;
+  uint32_t soff[NM][2];
+#pragma unroll
+  for (int m = 0; m < NM; ++m)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) soff[m][j] = (uint32_t)min(4 * m + 2 * h + j, nsc - 1) * rowb;
+  const uint64_t q = pc.q;
+  const double qinv = pc.qinv;
+  uint64_t x[16];
+  // one block ahead: block r + 1's sources load while block r is multiplied and combined
+  uint64_t y[2][2][NM][2], ye[2][2];
+  auto load = [&](int r, int k) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const uint32_t va = a ? v1 : v0;
+#pragma unroll
+      for (int m = 0; m < NM; ++m)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) y[k][a][m][j] = csb.ld(va + soff[m][j], r * us);
+      ye[k][a] = sp ? spb.ld(va, r * us) : 0;
+    }
+  };
+  load(0, 0);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int k = r & 1;
+    if (r + 1 < 16) load(r + 1, k ^ 1);
+    v16i_t acc[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      v16i_t z = {};
+#pragma unroll
+      for (int m = 0; m < NM; ++m) {
+        const int s0 = 4 * m + 2 * h;
+        z = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+            A[m], pack2(s0 == se ? ye[k][a] : y[k][a][m][0], s0 + 1 == se ? ye[k][a] : y[k][a][m][1]), z, 0, 0, 0);
+      }
+      acc[a] = z;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    int R[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) R[b] = h ? acc[1][b] : acc[0][b];
+    const int64_t lo = (int64_t)R[0] + (int64_t)R[1] * 256 + (int64_t)R[2] * 65536 + (int64_t)R[3] * 16777216;
+    const int64_t hi = (int64_t)R[4] + (int64_t)R[5] * 256 + (int64_t)R[6] * 65536 + (int64_t)R[7] * 16777216;
+    const double lo_d = __fma_rn((double)R[3], 16777216.0, __fma_rn((double)R[2], 65536.0,
+                                 __fma_rn((double)R[1], 256.0, (double)R[0])));
+    const double hi_d = __fma_rn((double)R[7], 16777216.0, __fma_rn((double)R[6], 65536.0,
+                                 __fma_rn((double)R[5], 256.0, (double)R[4])));
+    const int qt = (int)__builtin_rint(__fma_rn(hi_d, 4294967296.0, lo_d) * qinv);
+    const int64_t rem = (int64_t)((uint64_t)lo + ((uint64_t)hi << 32) - (uint64_t)(int64_t)qt * q);
+    x[r] = rem < 0 ? (uint64_t)(rem + (int64_t)q) : (uint64_t)rem;
+    // in this order (left alone, the compiler hoists every block's loads and products)
+    asm volatile("" : "+v"(x[r]));
+  }
+  // first forward pass (integer path), stored tile-major like the FP64 targets' rows
+  const uint64_t two_q = 2 * q;
+  const U2* tw = P.tw + ((int64_t)p << P.logN);
+  auto bf = [&](uint64_t& X, uint64_t& Y, U2 w) { ct_bfly(X, Y, w, q, two_q); };
+  stages_strided<true>(x, tw, 1, bf);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) lds[(kg + T * r) * C + cl] = x[r];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) x[r] = lds[(16 * kg + r) * C + cl];
+  stages_contig<LOGS, true>(x, tw, 1, kg, bf);
+  const RowBuf rb(row);
+  const uint32_t vt = (uint32_t)tm_word(16 * kg, c, S) * 8;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) rb.st_nt(x[r], vt, r * 64);
+}
+
 // Base conversion fused into the first forward pass.  Unit = (ab, tile of C = 256/T
-// columns); its nint wider targets each take one workgroup (integer path, cols_body), its
-// FP64 targets a workgroup per quad and half tile.  All sub-blocks of a unit share the
+// columns); its nint wider targets each take one workgroup (convw_body), its FP64 targets a
+// workgroup per quad and half tile (convq_body).  All sub-blocks of a unit share the
 // source tiles: xcd_map keeps them on one XCD.
 template <int LOGS, int NM>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_conv_cols(NttParams P) {
@@ -695,7 +812,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   const uint64_t* sp = P.X.cextra ? P.X.cextra + ia * P.X.cextra_sa + ib * P.X.cextra_sb : nullptr;
   if (sub < P.nint) {
     const int ii = P.cmap[P.nfp + (int)sub];
-    cols_body<LOGS, true, true, false>(P, base + ((int64_t)ii << P.logN), cs, sp, P.pidx[ii], tile, lds);
+    convw_body<LOGS, NM>(P, base + ((int64_t)ii << P.logN), cs, sp, P.pidx[ii], tile, lds);
   } else {
     const int qh = (int)(sub - P.nint);
     convq_body<LOGS, NM>(P, base, cs, sp, qh >> 1, 2 * tile + (qh & 1), lds);
