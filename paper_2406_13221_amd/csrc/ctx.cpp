@@ -97,6 +97,8 @@ size_t ctx_layout(const heqg_params* p, bool check, std::string* err, size_t off
       nqp * sizeof(PrimeConst),        // pc
       nq * nq * 16,                    // rescale
       nq * nq * 8,                     // rescale_q
+      // modup and moddown_rs: the conversion constants with their Shoup companions, from which
+      // the digit tables are split; no kernel reads them (moddown's P^-1 part is read)
       nq * p->dnum * mu_stride * 16,   // modup
       (np + nq * np + nq) * 16,        // moddown
       nqp * N * 8,                     // tw_fwd_f
@@ -349,7 +351,6 @@ int ctx_build(heqg_ctx* c, void* dev, size_t bytes, std::string* err) {
   c->t.pc = reinterpret_cast<const PrimeConst*>(d + offs[2]);
   c->t.rescale = reinterpret_cast<const uint64_t*>(d + offs[3]);
   c->t.rescale_q = reinterpret_cast<const uint64_t*>(d + offs[4]);
-  c->t.modup = reinterpret_cast<const uint64_t*>(d + offs[5]);
   c->t.moddown = reinterpret_cast<const uint64_t*>(d + offs[6]);
   c->t.tw_fwd_f = reinterpret_cast<const double*>(d + offs[7]);
   c->t.tw_inv_f = reinterpret_cast<const double*>(d + offs[8]);
@@ -357,7 +358,6 @@ int ctx_build(heqg_ctx* c, void* dev, size_t bytes, std::string* err) {
   c->t.moddown_b = reinterpret_cast<const uint64_t*>(d + offs[10]);
   c->t.ks_scale = reinterpret_cast<const uint64_t*>(d + offs[11]);
   c->t.ks_scale_f = reinterpret_cast<const double*>(d + offs[12]);
-  c->t.moddown_rs = reinterpret_cast<const uint64_t*>(d + offs[13]);
   c->t.moddown_rs_b = reinterpret_cast<const uint64_t*>(d + offs[14]);
   c->t.split = ntt_split_default(c->g.logN);
   c->t.rows_var[0] = c->t.rows_var[1] = 1;

@@ -66,14 +66,12 @@ struct NttExtra {
   int out_centered;
   // forward, first pass: the input of row (ia, ib, ii) is the base conversion
   //   sum_s csrc_s * hat[p][s]  mod q_p,  csrc_s = csrc + ia*csrc_sa + ib*csrc_sb + s*N,
-  // every source row in digit form (out_digits).  Targets of at most FP_MAX_BITS bits take
-  // the sum on the int8 matrix cores from the digit-split constants at
-  // cbyte + 8*(p*cstride + s); bit ii of tint marks a wider target, which takes it from the
-  // pairs (w, Shoup(w)) at chat + 2*(p*cstride + s)
+  // every source row in digit form (out_digits), taken on the int8 matrix cores from the
+  // digit-split constants at cbyte + 8*(p*cstride + s); bit ii of tint marks a target wider
+  // than FP_MAX_BITS bits, whose transform runs on the 64-bit integer path
   const uint64_t* csrc;
   int64_t csrc_sa, csrc_sb;
   int ns, cstride;
-  const uint64_t* chat;
   const uint64_t* cbyte;
   uint64_t tint;
   // with cextra set, the last source (s = ns - 1) is read from cextra + ia*cextra_sa +
@@ -122,7 +120,6 @@ struct DevTables {
   const PrimeConst* pc;      // [nqp]
   const uint64_t* rescale;   // [n_q][n_q][2]: q_l^-1 mod q_i (+Shoup) at [l][i]
   const uint64_t* rescale_q; // [n_q][n_q]: q_l mod q_i
-  const uint64_t* modup;     // [n_q][dnum][mu_stride][2]
   const uint64_t* moddown;   // inv_hatP [n_p][2], hatP [n_q][n_p][2], Pinv [n_q][2]
   const double* tw_fwd_f;    // [nqp][N]: psi^brv(k) as doubles (primes of <= FP_MAX_BITS bits)
   const double* tw_inv_f;    // [nqp][N]: psi^-brv(k) as doubles
@@ -134,7 +131,6 @@ struct DevTables {
   const uint64_t* ks_scale;  // [n_q][nqp][2]: at level l, N^-1 * (D/s)^-1 mod s for Q prime s in its
                              // digit D, N^-1 * (P/p)^-1 mod p for special prime p (+Shoup)
   const double* ks_scale_f;  // [n_q][nqp]: the same as doubles
-  const uint64_t* moddown_rs;  // [n_q][n_p + 1][2]: P/p_k mod q_i (k < n_p), then P mod q_i (+Shoup)
   const uint64_t* moddown_rs_b;
   // tuning choices of this context (every choice computes identical residues):
   // log2 of the first NTT pass (both directions share it), row-pass access variant per

@@ -309,14 +309,10 @@ __device__ __forceinline__ void rs_epi16(const RsEpi& E, int64_t ab, int64_t nb,
 }
 
 // ------------------------------------------------------------------ pass A (columns)
-// CONV (forward, integer path only): the input is the base conversion of the digit-form
-// rows at cs; targets of at most FP_MAX_BITS bits take it in convq_body instead.
-// sp: CONV - the row of the extra (last) source, or null; forward, not CONV - the
-// rescale's centred source row, or null.
-template <int LOGS, bool FWD, bool CONV, bool FP>
-__device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, const uint64_t* cs, const uint64_t* sp,
-                                          int p, int tile, uint64_t* lds) {
-  static_assert(!(CONV && FP), "FP64 targets convert on the matrix cores");
+// sp (forward): the rescale's centred source row, or null.
+template <int LOGS, bool FWD, bool FP>
+__device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, const uint64_t* sp, int p, int tile,
+                                          uint64_t* lds) {
   constexpr int S = 1 << LOGS, T = S / 16, C = 256 / T;
   const int tid = threadIdx.x;
   const PrimeConst pc = P.pc[p];
@@ -393,32 +389,7 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
     };
     uint64_t x[16];
     if (FWD) {
-      if (CONV) {
-        // lazy sum kept in [0, 2q)
-        const cptr<uint64_t> h = to_const(P.X.chat + 2 * (int64_t)p * P.X.cstride);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) x[r] = 0;
-#pragma unroll 1
-        for (int s = 0; s < P.X.ns; ++s) {
-          const RowBuf ys(sp && s == P.X.ns - 1 ? sp : cs + ((int64_t)s << P.logN));
-          const uint64_t w = h[2 * s], wsh = h[2 * s + 1];
-#pragma unroll
-          for (int g = 0; g < 16; g += 8) {  // 8 loads in flight at a time: registers for 4 waves/SIMD
-            uint64_t y[8];
-#pragma unroll
-            for (int r = 0; r < 8; ++r) y[r] = ys.ld(vs, (g + r) * us);
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int r = 0; r < 8; ++r) {
-              // the source's residue from its digits: canonical, or centred (|y| < 2^63)
-              const int64_t yi = digits_value(y[r]);
-              const uint64_t yr = yi >= 0 ? (uint64_t)yi : negmod(reduce64((uint64_t)(-yi), pc), q);
-              const uint64_t v = x[g + r] + mul_shoup_lazy(yr, w, wsh, q);
-              x[g + r] = v >= two_q ? v - two_q : v;
-            }
-          }
-        }
-      } else if (sp) {
+      if (sp) {
         // spread: a centered double y (|y| < 2^51), as a signed integer made canonical (|y| < q)
         const RowBuf sb(sp);
 #pragma unroll
@@ -437,15 +408,8 @@ __device__ __forceinline__ void cols_body(const NttParams& P, uint64_t* row, con
 #pragma unroll
       for (int r = 0; r < 16; ++r) x[r] = lds[(16 * kg + r) * C + cl];
       stages_contig<LOGS, true>(x, tw, 1, kg, bf);
-      if (CONV) {
-        // tile-major output (tm_word): rows 16 kg + r of column c, 64 bytes apart
-        const uint32_t vt = (uint32_t)tm_word(16 * kg, c, S) * 8;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) rb.st_nt(x[r], vt, r * 64);
-      } else {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) rb.st(x[r], vc, r * uc);
-      }
+      for (int r = 0; r < 16; ++r) rb.st(x[r], vc, r * uc);
     } else {
 #pragma unroll
       for (int r = 0; r < 16; ++r) x[r] = rb.ld(vc, r * uc);
@@ -486,9 +450,9 @@ __global__ void __launch_bounds__(256) k_ntt_cols(NttParams P) {
   const uint64_t* sp = FWD && P.X.spread ? P.X.spread + ia * P.X.spread_sa + ib * P.X.spread_sb : nullptr;
   const int p = P.pidx[ii];
   if (P.pc[p].k <= FP_MAX_BITS)
-    cols_body<LOGS, FWD, false, true>(P, row, nullptr, sp, p, tile, lds);
+    cols_body<LOGS, FWD, true>(P, row, sp, p, tile, lds);
   else
-    cols_body<LOGS, FWD, false, false>(P, row, nullptr, sp, p, tile, lds);
+    cols_body<LOGS, FWD, false>(P, row, sp, p, tile, lds);
 }
 
 // ------------------------------------------------------------------ base conversion

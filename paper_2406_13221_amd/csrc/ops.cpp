@@ -249,7 +249,6 @@ void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, 
     x.csrc_sa = (int64_t)nl * N;
     x.ns = sz;
     x.cstride = alpha;
-    x.chat = c->t.modup + 2 * (size_t)((level * g.dnum + j) * g.mu_stride) + 2 * alpha;
     x.cbyte = c->t.modup_b + 8 * (size_t)((level * g.dnum + j) * g.nqp) * alpha;
     for (size_t k = 0; k < tgt.size(); ++k) x.tint |= (uint64_t)(c->primes[tgt[k]] >> FP_MAX_BITS ? 1 : 0) << k;
     x.cols_only = 1;
@@ -295,13 +294,11 @@ void ks_core(heqg_ctx* c, const uint64_t* key, CtV d, int64_t count, int level, 
     x.csrc_sa = (int64_t)nx * N;
     x.ns = np;
     x.cstride = np;
-    x.chat = c->t.moddown + 2 * np;
     x.cbyte = c->t.moddown_b;
     for (int k = 0; k < n; ++k) x.tint |= (uint64_t)(c->primes[first + k] >> FP_MAX_BITS ? 1 : 0) << k;
     if (merged) {
       // the rescale's spread of the centred last limb enters the conversion with factor P
       x.ns = x.cstride = np + 1;
-      x.chat = c->t.moddown_rs;
       x.cbyte = c->t.moddown_rs_b;
       x.cextra = lastc;
       x.cextra_sa = N;
