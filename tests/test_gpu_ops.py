@@ -201,3 +201,24 @@ def test_encode_matches_oracle_encode(env):
     assert np.abs(a - b).max() <= 1
     assert np.abs(ctx.decode(a.astype(np.float64), ora.delta) - v).max() < 1e-9
     assert np.abs(odec(a.astype(np.float64), ctx.N, ora.delta).real - v).max() < 1e-9
+
+
+def test_key_switch_sixteen_source_conversions_bit_exact(torch_cuda):
+    """One digit over 14 limbs and 14 wide special primes (N = 2^12): ModUp conversions with 1..14
+    sources and ModDown conversions with 14, i.e. one to four matrix products per block, into
+    FP64 target quads and into wide targets (q0 and the 60-bit special primes), relinearisation
+    and rotation at every level."""
+    cfg, ora, ctx = make_pair("c1", q_bits=[50] + [40] * 13, n_p=14, p_bits=60, dnum=1)
+    ora.keygen(cfg["key_seed"], [1])
+    keys = ctx.keygen(cfg["key_seed"], [1])
+    rng = np.random.default_rng(17)
+    L = ora.top_level
+    m = rng.integers(-2 ** 45, 2 ** 45, ora.N)
+    o1 = ora.encrypt(m, L, ora.delta, cfg["enc_seed"], 3)
+    g1 = ctx.encrypt(keys, m[None], L, ora.delta, cfg["enc_seed"], 3)
+    assert_same_ct(g1, o1, "enc")
+    for lv in range(L, 0, -1):
+        g = ctx.drop(g1, lv) if lv < L else g1
+        o = ora.drop(o1, lv) if lv < L else o1
+        assert_same_ct(ctx.relin(keys, ctx.tensor(g, g)), ora.relin(ora.tensor(o, o)), "relin@%d" % lv)
+        assert_same_ct(ctx.rotate(keys, g, 1), ora.rotate(o, 1), "rot@%d" % lv)
