@@ -25,6 +25,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions per second (a wave64
+# instruction takes 4 cycles of a SIMD, FP64 and 32-bit integer operations alike)
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # the bootstrap whose output level the iteration works at: EvalMod with r = 5 double angles and a
 # degree-20 Taylor cosine (|I| < 16 with a weight-64 sparse secret), slot transforms factored into 2
 # levels each (the dense form needs N/2 plaintexts per transform)
@@ -149,6 +152,27 @@ def pmc_traffic(kernel, batch, level, rows=None):
         if rows is not None:
             return k["bytes_per_output_row"] * rows
         return k["fetch_bytes_per_dispatch"] + k["write_bytes_per_dispatch"]
+    except (OSError, KeyError, ValueError, TypeError):
+        return None
+
+
+def pmc_valu(kernel, batch, level, launch_us):
+    """VALU issue rate of `kernel`: its wave-level VALU instructions per dispatch from the committed
+    rocprofv3 SQ summary (SQ_INSTS_VALU), times 64 lanes, over the launch duration measured in this
+    run, against VALU_PEAK_LANE_OPS.  None under the same conditions as pmc_traffic, or where no SQ
+    pass was taken at this chunk size."""
+    try:
+        with open(PMC_FILE) as f:
+            pm = json.load(f)
+        with open(KERNEL_SRC, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != pm["kernel_source_sha256"]:
+                return None
+        if pm["work_level"] != level or str(batch) not in pm["by_batch"] or launch_us <= 0:
+            return None
+        insts = pm["by_batch"][str(batch)]["sq"][kernel]["valu_insts_per_dispatch"]
+        rate = insts * 64 / (launch_us * 1e-6)
+        return {"valu_insts_per_launch": round(insts), "lane_ops_per_s": rate, "peak_lane_ops_per_s": VALU_PEAK_LANE_OPS,
+                "frac": round(rate / VALU_PEAK_LANE_OPS, 4)}
     except (OSError, KeyError, ValueError, TypeError):
         return None
 
@@ -505,7 +529,8 @@ def main():
                 "fp64_ops": "output residues x (12 to combine the digit sums + 4 per stage)",
                 "fp64_achieved_Tops": round(conv_tops, 2), "fp64_frac": round(conv_tops / FP64_PEAK_TOPS, 4),
                 "avg_launch_us": round(conv_us, 2), "sampled_launches": conv_n,
-                "avg_rows_per_launch": round(conv_rows, 2), "avg_source_rows_per_launch": round(conv_src, 2)}
+                "avg_rows_per_launch": round(conv_rows, 2), "avg_source_rows_per_launch": round(conv_src, 2),
+                "valu": pmc_valu("k_conv_cols", run.batch, work, conv_us)}
     row_pass = 16.0 * N * avg_rows / (avg_us * 1e-6) / 1e9 if avg_us > 0 else 0.0
     ntt_row_roofline = {"bound": "hbm", "achieved": round(row_pass, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(row_pass / HBM_PEAK_GBS, 4),
@@ -525,7 +550,7 @@ def main():
                           "product; the P limbs' first inverse pass)",
                 "bytes": "8 bytes per ciphertext residue read (digits) and written (2 parts), key rows once",
                 "algorithmic_bytes_per_launch": ks_bytes, "avg_launch_us": round(ks_us, 2),
-                "sampled_launches": ks_n}
+                "sampled_launches": ks_n, "valu": pmc_valu("k_ntt_rows_ks8", run.batch, work, ks_us)}
 
     model = iteration_model_bytes(cfg, run.Z.count, level=work)
     it_roof = {"model_bytes": model, "achieved_GBps": round(model / upd / 1e9, 1), "peak": HBM_PEAK_GBS,

@@ -31,13 +31,17 @@ def test_pmc_traffic_only_for_the_measured_source(tmp_path, monkeypatch):
         "by_batch": {"16": {"kernels": {
             "k_conv_cols": {"bytes_per_output_row": 1000.0},
             "k_ntt_rows_ks8": {"fetch_bytes_per_dispatch": 300.0, "write_bytes_per_dispatch": 200.0}}},
-            "32": {"kernels": {"k_ntt_rows_ks8": {"fetch_bytes_per_dispatch": 600.0, "write_bytes_per_dispatch": 400.0}}}}}))
+            "32": {"kernels": {"k_ntt_rows_ks8": {"fetch_bytes_per_dispatch": 600.0, "write_bytes_per_dispatch": 400.0}},
+                   "sq": {"k_ntt_rows_ks8": {"valu_insts_per_dispatch": 1e6}}}}}))
     monkeypatch.setattr(bench, "PMC_FILE", str(pmc))
     monkeypatch.setattr(bench, "KERNEL_SRC", str(src))
     assert bench.pmc_traffic("k_conv_cols", 16, 9, rows=3.5) == pytest.approx(3500.0)
     assert bench.pmc_traffic("k_ntt_rows_ks8", 16, 9) == pytest.approx(500.0)
     assert bench.pmc_traffic("k_ntt_rows_ks8", 32, 9) == pytest.approx(1000.0)
     assert bench.pmc_traffic("k_ntt_rows_ks8", 24, 9) is None    # a chunk size not measured
+    v = bench.pmc_valu("k_ntt_rows_ks8", 32, 9, 100.0)            # 1e6 wave instructions in 100 us
+    assert v["lane_ops_per_s"] == pytest.approx(6.4e11) and v["frac"] == pytest.approx(6.4e11 / bench.VALU_PEAK_LANE_OPS, abs=1e-4)
+    assert bench.pmc_valu("k_ntt_rows_ks8", 16, 9, 100.0) is None  # no SQ pass at this size
     assert bench.pmc_traffic("k_ntt_rows_ks8", 16, 23) is None   # another working level
     assert bench.pmc_traffic("k_tensor", 16, 9) is None          # not measured
     src.write_bytes(b"// kernel source B\n")       # the kernel changed since the counters were taken
