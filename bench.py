@@ -76,7 +76,13 @@ def cpu_baseline(cfg, data, n_blocks, work=None):
         times[nb] = time.perf_counter() - t0
     per_block = (times[hi] - times[lo]) / (hi - lo)
     tail = max(times[lo] - lo * per_block, 0.0)
-    return dict(value=tail + per_block * n_blocks, unit="s/iter", cores=threads, kind="oracle",
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
+    return dict(value=tail + per_block * n_blocks, unit="s/iter", cores=threads, kind="oracle", cpu_model=model,
                 sample="the full iteration (per-block pipeline + once-per-iteration tail) over %d and over %d "
                        "of the %d blocks at the same parameters and levels (W and V at level %d): %.1f s and %.1f s, "
                        "i.e. %.2f s per block and %.2f s for the tail, extrapolated to %d blocks"
