@@ -32,6 +32,9 @@ VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # degree-20 Taylor cosine (|I| < 16 with a weight-64 sparse secret), slot transforms factored into 2
 # levels each (the dense form needs N/2 plaintexts per transform)
 BOOT_R, BOOT_LEVELS, BOOT_TAYLOR, BOOT_WEIGHT = 5, 2, 20, 64
+# the non-interactive pipeline (every iteration followed by bootstrapping W and V) on a chain of 50-bit
+# primes, where bootstrapping is precise: 4 double angles, 3 levels per slot transform
+NI_Q_BITS, NI_P_BITS, NI_LOG2_SCALE, NI_R, NI_LEVELS = [60] + [50] * 24, 60, 50, 4, 3
 # FP64 vector issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz instructions per second (the published
 # 78.6 TFLOP/s counts each FMA as two flops)
 FP64_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -308,6 +311,9 @@ def main():
     ap.add_argument("--work-level", default="boot",
                     help="level of W and V, the level they are refreshed to: 'boot' (the level heqg_bootstrap "
                          "returns with 5 double angles), 'top', or a number")
+    ap.add_argument("--noninteractive-steps", type=int, default=3,
+                    help="iterations of the non-interactive pipeline (iteration + bootstrapping of W and V) on "
+                         "the chain of 50-bit primes (0: skip)")
     ap.add_argument("--boot-reps", type=int, default=2,
                     help="timed bootstraps of W and V at these parameters (0: skip)")
     ap.add_argument("--top-steps", type=int, default=1,
@@ -648,6 +654,55 @@ def main():
         del kb, bt, ct, out_b, ws
         torch.cuda.empty_cache()
     out["bootstrap"] = boot_leg
+
+    # the paper's flow without the key holder (section 4.3 step 7; Table 1: one bootstrapping per
+    # iteration) at paper scale: the same data and circuit on a chain of 50-bit primes (q0 = 2^60,
+    # scale 2^50, sparse secret of weight 64), W and V at the level bootstrapping returns; each iteration
+    # is followed by bootstrapping W and V together; decrypted weights against the FP64 run
+    ni_leg = None
+    if args.noninteractive_steps > 0:
+        import numpy as np
+        ncfg = dict(cfg, q_bits=NI_Q_BITS, p_bits=NI_P_BITS, log2_scale=NI_LOG2_SCALE)
+        probe = heqg.Context.from_config(ncfg)
+        _, _, ni_level, _ = probe.boot_shape(NI_R, NI_LEVELS)
+        ni_steps = probe.boot_steps(NI_LEVELS)
+        del probe
+        nrun = EncryptedQGNAG(ncfg, data["X"], data["y"], batch=run.batch, level=ni_level,
+                              secret_weight=BOOT_WEIGHT, extra_steps=ni_steps)
+        nctx = nrun.ctx
+        pts = nctx.boot_encode(NI_R, NI_LEVELS)
+        nbt = nctx.boot_setup(pts, NI_R, BOOT_TAYLOR, levels=NI_LEVELS)
+        del pts
+        nws = heqg._ws(heqg.lib().heqg_boot_ws_bytes(nctx.h, NI_LEVELS, 2 * nrun.nc))
+        upd_s, boot_s = [], []
+        for _ in range(args.noninteractive_steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            nrun.step(refresh=False)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            nrun.bootstrap(nbt, nws)
+            torch.cuda.synchronize()
+            upd_s.append(t1 - t0)
+            boot_s.append(time.perf_counter() - t1)
+        k = args.noninteractive_steps
+        w_ni = nrun.weights(cfg["n_features"] + 1)
+        ref = heqg.plain_qgnag(data["X"], data["y"], k, coeffs=dict(nrun.coeffs), margins=False)[0]
+        tail = slice(1, None) if k > 1 else slice(None)   # the first iteration also pays first-call setup
+        ni_leg = {"iterations": k, "q_bits": "60 + 24 x 50", "special_primes": "7 x 60", "log2_scale": NI_LOG2_SCALE,
+                  "work_level": ni_level, "double_angles": NI_R, "levels_per_transform": NI_LEVELS,
+                  "taylor_degree": BOOT_TAYLOR, "secret_weight": BOOT_WEIGHT,
+                  "update_s": round(float(np.mean(upd_s[tail])), 4), "bootstrap_s": round(float(np.mean(boot_s[tail])), 4),
+                  "s_per_iter": round(float(np.mean(upd_s[tail]) + np.mean(boot_s[tail])), 4),
+                  "max_abs_dw_vs_fp64": float(abs(w_ni - ref).max()),
+                  "note": "50-bit primes take the 64-bit integer path (the FP64 path holds primes of at most 42 "
+                          "bits), hence the slower update"}
+        log("non-interactive: %d iterations with bootstrapping on the 50-bit chain (level %d): update %.3f s + "
+            "bootstrap %.4f s per iteration, max|dw| vs FP64 %.2e" % (k, ni_level, ni_leg["update_s"],
+                                                                    ni_leg["bootstrap_s"], ni_leg["max_abs_dw_vs_fp64"]))
+        del nrun, nbt, nws, nctx
+        torch.cuda.empty_cache()
+    out["noninteractive"] = ni_leg
 
     # the same iteration with W and V at the top of the chain (as a refresh that returned them there
     # would leave them; no bootstrap can): seconds per iteration from W = V = 0

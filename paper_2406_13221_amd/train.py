@@ -96,13 +96,15 @@ class EncryptedQGNAG:
     """Client + cloud roles of the pipeline on one GPU."""
 
     def __init__(self, cfg, X, y, coeffs=None, batch=16, rows=None, threads=0, mini_batch=False, graph=False,
-                 first_order=False, level=None):
+                 first_order=False, level=None, secret_weight=0, extra_steps=()):
         """graph: submit each iteration as a replayed HIP graph (on a side stream of this object).
         first_order: train with the first-order NAG the paper compares against (step cfg["fo_lr"] / n on
         the gradient, no B-bar) instead of the quadratic gradient.
         level: the level W and V are encrypted at and refreshed to (default: the top of the chain).  Z and
         B-bar are always encrypted at the top, and every product with them runs at the level of W, V:
-        a bootstrapped run works at the level bootstrapping returns (heqg_boot_shape)."""
+        a bootstrapped run works at the level bootstrapping returns (heqg_boot_shape).
+        secret_weight, extra_steps: a sparse ternary secret of that Hamming weight with the conjugation
+        key and these further rotations (heqg_boot_steps), for a run that bootstraps (bootstrap())."""
         import torch
         self.cfg = cfg
         self.m, self.g = cfg["m"], cfg["g"]
@@ -110,7 +112,8 @@ class EncryptedQGNAG:
         self.degree = max(self.coeffs)
         self.batch = batch
         self.ctx = ctx = heqg.Context.from_config(cfg)
-        self.keys = ctx.keygen(cfg["key_seed"], rot_steps(self.m, self.g))
+        steps = sorted(set(rot_steps(self.m, self.g)) | set(extra_steps))
+        self.keys = ctx.keygen(cfg["key_seed"], steps, hamming=secret_weight, conj=secret_weight > 0)
         L = ctx.top_level
         Xs, ys = (X, y) if rows is None else (X[rows[0]:rows[1]], y[rows[0]:rows[1]])
         self._X, self._n_rows = Xs, Xs.shape[0]
@@ -293,6 +296,23 @@ class EncryptedQGNAG:
         self.V = self.ctx.refresh(self.keys, self.V, L, self.cfg["enc_seed"] + 9, o + nc,
                                   out=heqg.Cts(self.Vbuf, L, d))
         self.refresh_obj += 2 * nc
+
+    def bootstrap(self, boot, ws=None):
+        """Step 7 without the key holder (section 4.3; Table 1: one bootstrapping per iteration): W and V
+        dropped to level 0 and bootstrapped together (heqg_bootstrap, keys on the sparse secret); the
+        result, at the level `boot` returns, which must be the working level, goes back into their
+        storage."""
+        import torch
+        ctx, nc, L = self.ctx, self.nc, self.L
+        if boot.shape[2] != L:
+            raise ValueError("the bootstrap returns level %d, the run works at level %d" % (boot.shape[2], L))
+        w0, v0 = ctx.drop(self.W, 0), ctx.drop(self.V, 0)
+        both = heqg.Cts(torch.cat([w0.data, v0.data]), 0, w0.scale)
+        out = ctx.bootstrap(self.keys, boot, both, ws=ws)
+        self.Wbuf.copy_(out.data[:nc])
+        self.Vbuf.copy_(out.data[nc:])
+        self.W = heqg.Cts(self.Wbuf, L, out.scale)
+        self.V = heqg.Cts(self.Vbuf, L, out.scale)
 
     def weights(self, f=None):
         """Row 0 of W: the model over the padded width (its first f entries when f is given)."""

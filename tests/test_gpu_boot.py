@@ -260,3 +260,37 @@ def test_bootstrap_at_a_40_bit_scale_bit_exact():
     assert_same_ct(got, ref, "bootstrap at a 40-bit scale")
     err = np.abs(o.decrypt_values(ref).real - z).max()
     print("bootstrap at a 40-bit scale with q0 = 2^60: max error %.3e" % err)
+
+
+def test_noninteractive_training_follows_fp64():
+    """The pipeline without the key holder (section 4.3 step 7, one bootstrapping per iteration): the
+    mid workload's data and circuit (16,384 x 63 in 64 blocks) on a chain of 50-bit primes (N = 2^15),
+    W and V at the level the bootstrap returns with 4 double angles and 3 levels per transform; three
+    iterations, each followed by EncryptedQGNAG.bootstrap instead of the refresh; the decrypted weights
+    follow the FP64 trainer."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import synth
+    from oracle import trainer
+    from paper_2406_13221_amd import heqg
+    from paper_2406_13221_amd.train import EncryptedQGNAG
+    cfg = synth.get_config("c2")
+    cfg.update(q_bits=[60] + [50] * 24, n_p=5, p_bits=60, dnum=5, log2_scale=50)
+    d = synth.make_dataset(cfg)
+    probe = heqg.Context.from_config(cfg)
+    _, _, level, _ = probe.boot_shape(4, 3)
+    steps = probe.boot_steps(3)
+    del probe
+    run = EncryptedQGNAG(cfg, d["X"], d["y"], batch=16, level=level, secret_weight=H, extra_steps=steps)
+    bt = run.ctx.boot_setup(run.ctx.boot_encode(4, 3), 4, TAYLOR, levels=3)
+    f = cfg["n_features"] + 1
+    ref = trainer.train(d["X"], d["y"], cfg["g"], 3)["history"]
+    for it in range(3):
+        run.step(refresh=False)
+        run.bootstrap(bt)
+        assert run.W.level == level and run.W.scale == run.ctx.delta
+        w = run.weights(f)
+        err = np.abs(w - ref[it]["W"][:f]).max()
+        print("iteration %d: max|dw| vs FP64 %.2e" % (it, err))
+        assert err < 2e-3
