@@ -650,7 +650,7 @@ __device__ __forceinline__ void convq_body(const NttParams& P, uint64_t* obase, 
 // target's digits b = 0..7 for both lane halves (the rows of output v >= 8 are zero), and lane
 // half h keeps product h.  Then y = sum_b 256^b R[b] = lo + 2^32 hi with |lo|, |hi| < 2^46: its
 // quotient by q from an FP64 estimate (error below 2^25, so the rounded quotient is within one
-// of the true one), the remainder y - qt*q exactly in 64-bit wrap-around arithmetic (it lies in
+// of the true one; |qt| < 2^36 for q above 2^42, an int64), the remainder y - qt*q exactly in 64-bit wrap-around arithmetic (it lies in
 // [-q/2 - 2^25, q/2 + 2^25]), made canonical with one conditional add.
 template <int LOGS, int NM>
 __device__ __forceinline__ void convw_body(const NttParams& P, uint64_t* row, const uint64_t* cs,
@@ -735,8 +735,8 @@ __device__ __forceinline__ void convw_body(const NttParams& P, uint64_t* row, co
                                  __fma_rn((double)R[1], 256.0, (double)R[0])));
     const double hi_d = __fma_rn((double)R[7], 16777216.0, __fma_rn((double)R[6], 65536.0,
                                  __fma_rn((double)R[5], 256.0, (double)R[4])));
-    const int qt = (int)__builtin_rint(__fma_rn(hi_d, 4294967296.0, lo_d) * qinv);
-    const int64_t rem = (int64_t)((uint64_t)lo + ((uint64_t)hi << 32) - (uint64_t)(int64_t)qt * q);
+    const int64_t qt = fint_to_i64(__builtin_rint(__fma_rn(hi_d, 4294967296.0, lo_d) * qinv));
+    const int64_t rem = (int64_t)((uint64_t)lo + ((uint64_t)hi << 32) - (uint64_t)qt * q);
     x[r] = rem < 0 ? (uint64_t)(rem + (int64_t)q) : (uint64_t)rem;
     // in this order (left alone, the compiler hoists every block's loads and products)
     asm volatile("" : "+v"(x[r]));

@@ -203,12 +203,13 @@ def test_encode_matches_oracle_encode(env):
     assert np.abs(odec(a.astype(np.float64), ctx.N, ora.delta).real - v).max() < 1e-9
 
 
-def test_key_switch_sixteen_source_conversions_bit_exact(torch_cuda):
+@pytest.mark.parametrize("p_bits", [60, 45])
+def test_key_switch_sixteen_source_conversions_bit_exact(torch_cuda, p_bits):
     """One digit over 14 limbs and 14 wide special primes (N = 2^12): ModUp conversions with 1..14
     sources and ModDown conversions with 14, i.e. one to four matrix products per block, into
-    FP64 target quads and into wide targets (q0 and the 60-bit special primes), relinearisation
-    and rotation at every level."""
-    cfg, ora, ctx = make_pair("c1", q_bits=[50] + [40] * 13, n_p=14, p_bits=60, dnum=1)
+    FP64 target quads and into wide targets (q0 and the special primes, 60 or 45 bits: the wide
+    combine's quotient reaches 2^36 for the narrowest), relinearisation and rotation at every level."""
+    cfg, ora, ctx = make_pair("c1", q_bits=[50] + [40] * 13, n_p=14, p_bits=p_bits, dnum=1)
     ora.keygen(cfg["key_seed"], [1])
     keys = ctx.keygen(cfg["key_seed"], [1])
     rng = np.random.default_rng(17)
