@@ -655,54 +655,6 @@ def main():
         torch.cuda.empty_cache()
     out["bootstrap"] = boot_leg
 
-    # the paper's flow without the key holder (section 4.3 step 7; Table 1: one bootstrapping per
-    # iteration) at paper scale: the same data and circuit on a chain of 50-bit primes (q0 = 2^60,
-    # scale 2^50, sparse secret of weight 64), W and V at the level bootstrapping returns; each iteration
-    # is followed by bootstrapping W and V together; decrypted weights against the FP64 run
-    ni_leg = None
-    if args.noninteractive_steps > 0:
-        import numpy as np
-        ncfg = dict(cfg, q_bits=NI_Q_BITS, p_bits=NI_P_BITS, log2_scale=NI_LOG2_SCALE)
-        probe = heqg.Context.from_config(ncfg)
-        _, _, ni_level, _ = probe.boot_shape(NI_R, NI_LEVELS)
-        ni_steps = probe.boot_steps(NI_LEVELS)
-        del probe
-        nrun = EncryptedQGNAG(ncfg, data["X"], data["y"], batch=run.batch, level=ni_level,
-                              secret_weight=BOOT_WEIGHT, extra_steps=ni_steps)
-        nctx = nrun.ctx
-        pts = nctx.boot_encode(NI_R, NI_LEVELS)
-        nbt = nctx.boot_setup(pts, NI_R, BOOT_TAYLOR, levels=NI_LEVELS)
-        del pts
-        nws = heqg._ws(heqg.lib().heqg_boot_ws_bytes(nctx.h, NI_LEVELS, 2 * nrun.nc))
-        upd_s, boot_s = [], []
-        for _ in range(args.noninteractive_steps):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            nrun.step(refresh=False)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            nrun.bootstrap(nbt, nws)
-            torch.cuda.synchronize()
-            upd_s.append(t1 - t0)
-            boot_s.append(time.perf_counter() - t1)
-        k = args.noninteractive_steps
-        w_ni = nrun.weights(cfg["n_features"] + 1)
-        ref = heqg.plain_qgnag(data["X"], data["y"], k, coeffs=dict(nrun.coeffs), margins=False)[0]
-        tail = slice(1, None) if k > 1 else slice(None)   # the first iteration also pays first-call setup
-        ni_leg = {"iterations": k, "q_bits": "60 + 24 x 50", "special_primes": "7 x 60", "log2_scale": NI_LOG2_SCALE,
-                  "work_level": ni_level, "double_angles": NI_R, "levels_per_transform": NI_LEVELS,
-                  "taylor_degree": BOOT_TAYLOR, "secret_weight": BOOT_WEIGHT,
-                  "update_s": round(float(np.mean(upd_s[tail])), 4), "bootstrap_s": round(float(np.mean(boot_s[tail])), 4),
-                  "s_per_iter": round(float(np.mean(upd_s[tail]) + np.mean(boot_s[tail])), 4),
-                  "max_abs_dw_vs_fp64": float(abs(w_ni - ref).max()),
-                  "note": "50-bit primes take the 64-bit integer path (the FP64 path holds primes of at most 42 "
-                          "bits), hence the slower update"}
-        log("non-interactive: %d iterations with bootstrapping on the 50-bit chain (level %d): update %.3f s + "
-            "bootstrap %.4f s per iteration, max|dw| vs FP64 %.2e" % (k, ni_level, ni_leg["update_s"],
-                                                                    ni_leg["bootstrap_s"], ni_leg["max_abs_dw_vs_fp64"]))
-        del nrun, nbt, nws, nctx
-        torch.cuda.empty_cache()
-    out["noninteractive"] = ni_leg
 
     # the same iteration with W and V at the top of the chain (as a refresh that returned them there
     # would leave them; no bootstrap can): seconds per iteration from W = V = 0
@@ -804,6 +756,58 @@ def main():
     if args.mnist_steps > 0:
         mnist = mnist_leg(args.mnist_steps, args.batch)
     out["mnist_shaped"] = mnist
+
+    # the paper's flow without the key holder (section 4.3 step 7; Table 1: one bootstrapping per
+    # iteration) at paper scale: the same data and circuit on a chain of 50-bit primes (q0 = 2^60,
+    # scale 2^50, sparse secret of weight 64), W and V at the level bootstrapping returns; each iteration
+    # is followed by bootstrapping W and V together; decrypted weights against the FP64 run
+    # (after every other leg: the main run's memory is released first)
+    ni_leg = None
+    if args.noninteractive_steps > 0:
+        import numpy as np
+        run = None
+        torch.cuda.empty_cache()
+        ncfg = dict(cfg, q_bits=NI_Q_BITS, p_bits=NI_P_BITS, log2_scale=NI_LOG2_SCALE)
+        probe = heqg.Context.from_config(ncfg)
+        _, _, ni_level, _ = probe.boot_shape(NI_R, NI_LEVELS)
+        ni_steps = probe.boot_steps(NI_LEVELS)
+        del probe
+        nrun = EncryptedQGNAG(ncfg, data["X"], data["y"], batch=batch_used, level=ni_level,
+                              secret_weight=BOOT_WEIGHT, extra_steps=ni_steps)
+        nctx = nrun.ctx
+        pts = nctx.boot_encode(NI_R, NI_LEVELS)
+        nbt = nctx.boot_setup(pts, NI_R, BOOT_TAYLOR, levels=NI_LEVELS)
+        del pts
+        nws = heqg._ws(heqg.lib().heqg_boot_ws_bytes(nctx.h, NI_LEVELS, 2 * nrun.nc))
+        upd_s, boot_s = [], []
+        for _ in range(args.noninteractive_steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            nrun.step(refresh=False)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            nrun.bootstrap(nbt, nws)
+            torch.cuda.synchronize()
+            upd_s.append(t1 - t0)
+            boot_s.append(time.perf_counter() - t1)
+        k = args.noninteractive_steps
+        w_ni = nrun.weights(cfg["n_features"] + 1)
+        ref = heqg.plain_qgnag(data["X"], data["y"], k, coeffs=dict(nrun.coeffs), margins=False)[0]
+        tail = slice(1, None) if k > 1 else slice(None)   # the first iteration also pays first-call setup
+        ni_leg = {"iterations": k, "q_bits": "60 + 24 x 50", "special_primes": "7 x 60", "log2_scale": NI_LOG2_SCALE,
+                  "work_level": ni_level, "double_angles": NI_R, "levels_per_transform": NI_LEVELS,
+                  "taylor_degree": BOOT_TAYLOR, "secret_weight": BOOT_WEIGHT,
+                  "update_s": round(float(np.mean(upd_s[tail])), 4), "bootstrap_s": round(float(np.mean(boot_s[tail])), 4),
+                  "s_per_iter": round(float(np.mean(upd_s[tail]) + np.mean(boot_s[tail])), 4),
+                  "max_abs_dw_vs_fp64": float(abs(w_ni - ref).max()),
+                  "note": "50-bit primes take the 64-bit integer path (the FP64 path holds primes of at most 42 "
+                          "bits), hence the slower update"}
+        log("non-interactive: %d iterations with bootstrapping on the 50-bit chain (level %d): update %.3f s + "
+            "bootstrap %.4f s per iteration, max|dw| vs FP64 %.2e" % (k, ni_level, ni_leg["update_s"],
+                                                                    ni_leg["bootstrap_s"], ni_leg["max_abs_dw_vs_fp64"]))
+        del nrun, nbt, nws, nctx
+        torch.cuda.empty_cache()
+    out["noninteractive"] = ni_leg
 
     if args.copy_probe:
         src = torch.ones(1 << 27, dtype=torch.int64, device="cuda")
