@@ -374,7 +374,10 @@ int heqg_prof_stop(int kernel, double* avg_us, int64_t* launches, double* avg_ro
  * two-pass NTT, shared by both directions (the key switch runs part of an
  * inverse transform inside a forward row pass); N = 2^15 has 7 and 8, every
  * other ring its one split (2^8 x 2^8 at N = 2^16: a pass holds at most 2^8
- * points).  Each context keeps its own choices.  heqg_tune_set returns -1 on a
+ * points).  which = 3: heqg_ntt runs both passes per slice of at most that many
+ * MiB of rows (0: each pass over the whole batch; default 256), so that a
+ * slice's rows between the passes can stay in the last-level cache; value in
+ * 0 .. 2^20.  Each context keeps its own choices.  heqg_tune_set returns -1 on a
  * bad selector or value, heqg_tune_get -1 on a bad selector.  A choice must not
  * change while work of the same context is being enqueued on another thread.
  */

@@ -339,14 +339,23 @@ extern "C" int heqg_ntt(heqg_ctx* c, uint64_t* dev_rows, int64_t n_rows, int fir
     return HEQG_ERR_ARG;
   }
   RowSet rs{};
-  rs.data = dev_rows;
-  rs.na = n_rows / period;
-  rs.sa = (int64_t)period * c->g.N;
   rs.nb = 1;
   rs.sb = 0;
   rs.ni = period;
+  rs.sa = (int64_t)period * c->g.N;
   for (int i = 0; i < period; ++i) rs.pidx[i] = first_prime + i;
-  return ops::ntt(c, rs, inverse != 0, s);
+  const int64_t na = n_rows / period;
+  // groups of `period` rows per slice (at least one)
+  const int64_t per = c->t.ntt_slice_mib > 0
+                          ? std::max<int64_t>(1, ((int64_t)c->t.ntt_slice_mib << 20) / (rs.sa * 8))
+                          : std::max<int64_t>(1, na);
+  for (int64_t a0 = 0; a0 < na; a0 += per) {
+    rs.data = dev_rows + a0 * rs.sa;
+    rs.na = std::min(per, na - a0);
+    const int rc = ops::ntt(c, rs, inverse != 0, s);
+    if (rc) return rc;
+  }
+  return 0;
 }
 
 // ------------------------------------------------------------------ arithmetic
@@ -598,6 +607,10 @@ extern "C" int heqg_tune_set(heqg_ctx* c, int which, int value) {
         return 0;
       }
   }
+  if (which == 3 && value >= 0 && value <= (1 << 20)) {
+    c->t.ntt_slice_mib = value;
+    return 0;
+  }
   return -1;
 }
 
@@ -605,6 +618,7 @@ extern "C" int heqg_tune_get(const heqg_ctx* c, int which) {
   if (!c) return -1;
   if (which == 0 || which == 1) return c->t.rows_var[which];
   if (which == 2) return c->t.split;
+  if (which == 3) return c->t.ntt_slice_mib;
   return -1;
 }
 

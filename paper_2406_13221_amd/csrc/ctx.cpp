@@ -361,6 +361,7 @@ int ctx_build(heqg_ctx* c, void* dev, size_t bytes, std::string* err) {
   c->t.moddown_rs_b = reinterpret_cast<const uint64_t*>(d + offs[14]);
   c->t.split = ntt_split_default(c->g.logN);
   c->t.rows_var[0] = c->t.rows_var[1] = 1;
+  c->t.ntt_slice_mib = 256;
   return HEQG_OK;
 }
 

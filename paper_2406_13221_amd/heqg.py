@@ -607,7 +607,8 @@ class Context:
         return out
 
     def tune_set(self, which, value):
-        """Tuning choice of this context: 0/1 row-pass variant fwd/inv, 2 NTT pass split (False if refused)."""
+        """Tuning choice of this context: 0/1 row-pass variant fwd/inv, 2 NTT pass split, 3 heqg_ntt slice
+        in MiB (False if refused)."""
         return lib().heqg_tune_set(self.h, int(which), int(value)) == 0
 
     def tune_get(self, which):

@@ -77,7 +77,7 @@ def test_choices_are_per_context(torch_cuda):
     assert ctx.tune_set(2, 7) and ctx2.tune_get(2) == 6 and ctx.tune_get(2) == 7
     assert not ctx2.tune_set(2, 7)                 # not a split of N = 2^12
     assert not ctx.tune_set(2, 9)                  # a pass holds at most 2^8 points
-    assert not ctx.tune_set(3, 7) and not ctx.tune_set(0, 2)
+    assert not ctx.tune_set(4, 7) and not ctx.tune_set(0, 2)   # no selector 4; variants are 0 / 1
     _check_ntt(torch_cuda, ora2, ctx2, 1, 3)
 
 
@@ -91,3 +91,14 @@ def test_tuner_pick_is_valid_and_exact(torch_cuda, c2_ks):
     _check_ntt(torch_cuda, ora, ctx, 2, 5)
     L = ora.top_level
     assert_same_ct(ctx.relin(keys, gpu_ct(ctx, exp[L]["t"])), exp[L]["relin"], "relin after tuning")
+
+
+@pytest.mark.parametrize("mib", [0, 1, 3, 256])
+def test_ntt_slices_bit_exact(torch_cuda, mib):
+    """heqg_ntt run slice by slice (both passes per slice of `mib` MiB: 1 MiB holds 4 groups of the
+    c1 ring's 7 limbs of 2^12 words, so 7 groups take two slices, the second ragged; 0 is one pass
+    over the whole batch) computes the oracle's transforms; the choice is read back."""
+    cfg, ora, ctx = make_pair("c1")
+    assert ctx.tune_set(3, mib) and ctx.tune_get(3) == mib
+    _check_ntt(torch_cuda, ora, ctx, 7, 5 + mib)
+    assert not ctx.tune_set(3, -1)
