@@ -47,7 +47,8 @@ enum {
   HEQG_ERR_KEY = -4,         /* no switching key for the requested rotation */
   HEQG_ERR_OVERFLOW = -5,    /* value does not fit (encode, constant, decode) */
   HEQG_ERR_DEVICE = -6,      /* a HIP runtime call failed */
-  HEQG_ERR_UNSUPPORTED = -7  /* parameter outside what the kernels implement */
+  HEQG_ERR_UNSUPPORTED = -7, /* parameter outside what the kernels implement */
+  HEQG_ERR_HOST = -8         /* host memory or threads could not be had */
 };
 
 /* ------------------------------------------------------------------ */

@@ -25,6 +25,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <exception>
 #include <string>
 #include <thread>
 #include <vector>
@@ -484,6 +485,9 @@ int run(heqg_ctx* c, const heqg_keys* k, int levels, const heqg_ct_batch* in, in
     R.store(z, out);
   } catch (const Fail& f) {
     return f.code;
+  } catch (const std::exception& x) {
+    set_err(std::string(what) + ": " + x.what());
+    return HEQG_ERR_HOST;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
@@ -667,7 +671,7 @@ extern "C" int heqg_boot_shape(const heqg_ctx* c, int r, int levels, int* cts_le
   return HEQG_OK;
 }
 
-extern "C" int heqg_boot_encode(const heqg_ctx* c, int r, int levels, int64_t* coeffs, int threads) {
+static int boot_encode(const heqg_ctx* c, int r, int levels, int64_t* coeffs, int threads) {
   int top, stc, outl;
   if (!levels_ok(c, levels, "boot_encode") || !coeffs) return HEQG_ERR_ARG;
   int rc = shape(c, r, levels, &top, &stc, &outl);
@@ -724,6 +728,15 @@ extern "C" int heqg_boot_encode(const heqg_ctx* c, int r, int levels, int64_t* c
   return HEQG_OK;
 }
 
+extern "C" int heqg_boot_encode(const heqg_ctx* c, int r, int levels, int64_t* coeffs, int threads) {
+  try {
+    return boot_encode(c, r, levels, coeffs, threads);
+  } catch (const std::exception& x) {
+    set_err(std::string("boot_encode: ") + x.what());
+    return HEQG_ERR_HOST;
+  }
+}
+
 extern "C" size_t heqg_boot_bytes(const heqg_ctx* c, int r, int levels) {
   int top, stc, outl;
   if (!levels_ok(c, levels, "boot_bytes") || shape(c, r, levels, &top, &stc, &outl)) return 0;
@@ -749,15 +762,22 @@ extern "C" int heqg_boot_setup(heqg_ctx* c, const int64_t* dev_coeffs, int r, in
     return HEQG_ERR_ARG;
   }
   const int N = c->g.N;
-  heqg_boot* b = new heqg_boot();
+  heqg_boot* b = nullptr;
+  try {
+    b = new heqg_boot();
+    b->cts = plan(c, levels, true, top);
+    b->stc = plan(c, levels, false, stc);
+  } catch (const std::exception& x) {
+    delete b;
+    set_err(std::string("boot_setup: ") + x.what());
+    return HEQG_ERR_HOST;
+  }
   b->top = top;
   b->levels = levels;
   b->stc_level = stc;
   b->out_level = outl;
   b->r = r;
   b->taylor = taylor;
-  b->cts = plan(c, levels, true, top);
-  b->stc = plan(c, levels, false, stc);
   uint64_t* d = static_cast<uint64_t*>(dev);
   const int64_t* src = dev_coeffs;
   for (auto* lv : {&b->cts, &b->stc})

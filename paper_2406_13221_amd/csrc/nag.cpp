@@ -9,6 +9,8 @@
 // enqueued, so every error is reported before any device work starts.
 #include <cmath>
 #include <cstring>
+#include <exception>
+#include <string>
 #include <vector>
 
 #include "ops.h"
@@ -490,6 +492,9 @@ static int nag_step(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch* Z, con
     st->alpha1 = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * st_dry.alpha1 * st_dry.alpha1));
   } catch (const Fail& f) {
     return f.code;
+  } catch (const std::exception& x) {
+    set_err(std::string("host: ") + x.what());
+    return HEQG_ERR_HOST;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
@@ -577,6 +582,9 @@ extern "C" int heqg_score(heqg_ctx* c, const heqg_keys* k, const heqg_ct_batch* 
     run(false);
   } catch (const Fail& f) {
     return f.code;
+  } catch (const std::exception& x) {
+    set_err(std::string("host: ") + x.what());
+    return HEQG_ERR_HOST;
   }
   out->scale = scale;
   hipError_t e = hipGetLastError();

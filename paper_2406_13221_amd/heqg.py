@@ -14,8 +14,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # HEQG_LIB selects another build of the same library (side-by-side comparisons)
 LIB_PATH = os.environ.get("HEQG_LIB") or os.path.join(HERE, "libheqg.so")
 
-OK, ERR_ARG, ERR_LEVEL, ERR_SCALE, ERR_KEY, ERR_OVERFLOW, ERR_DEVICE, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
-_NAMES = {-1: "ARG", -2: "LEVEL", -3: "SCALE", -4: "KEY", -5: "OVERFLOW", -6: "DEVICE", -7: "UNSUPPORTED"}
+OK, ERR_ARG, ERR_LEVEL, ERR_SCALE, ERR_KEY, ERR_OVERFLOW, ERR_DEVICE, ERR_UNSUPPORTED, ERR_HOST = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
+_NAMES = {-1: "ARG", -2: "LEVEL", -3: "SCALE", -4: "KEY", -5: "OVERFLOW", -6: "DEVICE", -7: "UNSUPPORTED",
+          -8: "HOST"}
 
 
 class HeqgError(RuntimeError):
