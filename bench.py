@@ -67,7 +67,7 @@ def cpu_baseline(cfg, data, n_blocks, work=None):
     work = L if work is None else work
     Zc = [o.encrypt(encode(blocks[b], o.N, o.delta), L, o.delta, cfg["enc_seed"], b) for b in range(hi)]
     B = trainer.bbar(X, g)
-    sB = 2.0 ** 50 / B.max()
+    sB = 2.0 ** (cfg["log2_scale"] + 10) / B.max()
     Bc = o.encrypt(encode(circuit.replicate_row(B, m, g), o.N, sB), L, sB, cfg["enc_seed"], 10)
     W = o.encrypt(np.zeros(o.N, np.int64), work, o.delta, cfg["enc_seed"], 11)
     V = o.encrypt(np.zeros(o.N, np.int64), work, o.delta, cfg["enc_seed"], 12)

@@ -184,7 +184,9 @@ class EncryptedQGNAG:
         """B-bar of the rows Xr (width C*g), one ciphertext per column block (objects obj_first + j)."""
         ctx, g = self.ctx, self.g
         B = bbar_diag(Xr, self.width)
-        sB = 2.0 ** 50 / B.max()
+        # largest entry at 2^(log2 scale + 10): the B-bar products' constant round(lr s q / sB) then
+        # keeps about 2^20 (below 2^62 on chains of wider primes too)
+        sB = 2.0 ** (self.cfg["log2_scale"] + 10) / B.max()
         pts = np.stack([ctx.encode(tile_row(B[j * g:(j + 1) * g], self.m, g), sB) for j in range(self.nc)])
         return ctx.encrypt(self.keys, pts, ctx.top_level, sB, self.cfg["enc_seed"], obj_first)
 

@@ -70,7 +70,7 @@ def oracle_setup(cfgkey, coeffs=trainer.G8, rows=None, bbar_rows=None, level=Non
     Zc = [o.encrypt(encode(blocks[b], N, o.delta), L, o.delta, cfg["enc_seed"], b) for b in range(len(blocks))]
     XB = X if bbar_rows is None else X[bbar_rows[0]:bbar_rows[1]]
     B = trainer.bbar(XB, g)
-    sB = 2.0 ** 50 / B.max()
+    sB = 2.0 ** (cfg["log2_scale"] + 10) / B.max()
     Bc = o.encrypt(encode(circuit.replicate_row(B, m, g), N, sB), L, sB, cfg["enc_seed"], 1 << 20)
     lw = L if level is None else level
     W = o.encrypt(np.zeros(N, np.int64), lw, o.delta, cfg["enc_seed"], (1 << 20) + 1)
@@ -167,7 +167,7 @@ def grid_oracle_setup(cfgkey, rows=None, coeffs=trainer.G8, **over):
     Zg = [[o.encrypt(encode(grid[i, j], N, o.delta), L, o.delta, cfg["enc_seed"], i * nc + j) for j in range(nc)]
           for i in range(grid.shape[0])]
     B = trainer.bbar(X, G)
-    sB = 2.0 ** 50 / B.max()
+    sB = 2.0 ** (cfg["log2_scale"] + 10) / B.max()
     Bc = [o.encrypt(encode(circuit.replicate_row(B[j * g:(j + 1) * g], m, g), N, sB), L, sB, cfg["enc_seed"],
                     (1 << 20) + j) for j in range(nc)]
     zero = np.zeros(N, np.int64)

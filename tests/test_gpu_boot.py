@@ -294,3 +294,57 @@ def test_noninteractive_training_follows_fp64():
         err = np.abs(w - ref[it]["W"][:f]).max()
         print("iteration %d: max|dw| vs FP64 %.2e" % (it, err))
         assert err < 2e-3
+
+
+def test_noninteractive_step_bit_exact():
+    """One iteration and then the bootstrap of W and V, both on the GPU, residue by residue against
+    the oracle's circuit and its bootstrap: the tiny workload's data on a chain of 50-bit primes
+    (N = 2^12), keys on a sparse secret with the circuit's and the factored transforms' rotations,
+    W and V at the level the bootstrap returns (4 double angles, 3 levels per transform), the
+    oracle's transform plaintexts loaded on the GPU."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import synth
+    from oracle import circuit, trainer
+    from paper_2406_13221_amd import heqg
+    from paper_2406_13221_amd.train import SIGMOID_SCALE
+    from tests.nag_parity import gpu_state
+    r4, lv3 = 4, 3
+    cfg = synth.get_config("c1")
+    cfg.update(q_bits=[60] + [50] * 24, n_p=5, p_bits=60, dnum=5, log2_scale=50)
+    d = synth.make_dataset(cfg)
+    m, g = cfg["m"], cfg["g"]
+    o = Oracle.from_config(cfg)
+    ctx = heqg.Context.from_config(cfg)
+    steps = sorted(set(circuit.rot_steps(m, g)) | set(ctx.boot_steps(lv3)))
+    boot.keygen_sparse(o, cfg["key_seed"], H, steps, dense_steps=False)
+    keys = ctx.keygen(cfg["key_seed"], steps, hamming=H, conj=True)
+    em = boot.EvalMod(K=K, r=r4, taylor=TAYLOR)
+    bt = ctx.boot_setup(boot.transform_plaintexts_fft(o, lv3, em), r4, TAYLOR, levels=lv3)
+    lw = ctx.boot_shape(r4, lv3)[2]
+    L, N = o.top_level, o.N
+    blocks = circuit.pack_blocks(trainer.build_Z(d["X"], d["y"], g), m, g, N)
+    Zc = [o.encrypt(encode(blocks[b], N, o.delta), L, o.delta, cfg["enc_seed"], b) for b in range(len(blocks))]
+    B = trainer.bbar(d["X"], g)
+    sB = 2.0 ** (cfg["log2_scale"] + 10) / B.max()
+    Bc = o.encrypt(encode(circuit.replicate_row(B, m, g), N, sB), L, sB, cfg["enc_seed"], 1 << 20)
+    W = o.encrypt(np.zeros(N, np.int64), lw, o.delta, cfg["enc_seed"], (1 << 20) + 1)
+    V = o.encrypt(np.zeros(N, np.int64), lw, o.delta, cfg["enc_seed"], (1 << 20) + 2)
+    masks = circuit.make_masks(o, m, g, trainer.G8, lw, SIGMOID_SCALE)
+    gZ = heqg.Cts(torch.from_numpy(np.stack([z.data for z in Zc]).view(np.int64).copy()).cuda(), L, o.delta)
+    order = sorted(trainer.G8) + ["half"]
+    mk = torch.from_numpy(np.stack([masks[k][0] for k in order]).view(np.int64).copy()).cuda()
+    gW, gV = gpu_ct(ctx, W), gpu_ct(ctx, V)
+    ost = circuit.new_state(refresh_seed=7)
+    gst = gpu_state(ost, m, g)
+    W1, V1, ost = circuit.nag_qg_step(o, Zc, Bc, W, V, ost, masks, m, g, degree=3)
+    ctx.nag_qg_step(keys, gZ, gpu_ct(ctx, Bc), gW, gV, mk, lw - 1, [masks[k][1] for k in order], 3, gst, 1)
+    assert_same_ct(gW, W1, "W after the step")
+    assert_same_ct(gV, V1, "V after the step")
+    both = heqg.Cts(torch.cat([ctx.drop(gW, 0).data, ctx.drop(gV, 0).data]), 0, gW.scale)
+    got = ctx.bootstrap(keys, bt, both)
+    for i, ref_in in enumerate((W1, V1)):
+        ref = boot.bootstrap(o, o.drop(ref_in, 0), em, fft_levels=lv3)
+        assert_same_ct(heqg.Cts(got.data[i:i + 1], got.level, got.scale), ref, "bootstrapped %s" % "WV"[i])
+        assert got.level == lw
